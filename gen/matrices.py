@@ -1,0 +1,247 @@
+"""Seeded generators for sparse lower-triangular CSR systems.
+
+Every generator follows the same conventions:
+
+* CSR with int32 ``row_ptr``/``col`` and float64 ``val``; columns strictly
+  ascending in each row, the diagonal stored last (the layout the paper's
+  serial algorithm assumes, Sec. II.A, Algorithm 1).
+* Off-diagonal values are drawn U(-1, 1) in CSR order after the sparsity
+  pattern is fixed; the diagonal is ``1 + sum(|off-diagonals|)`` so every
+  matrix is strictly diagonally dominant by rows.
+* ``rhs(m, nrhs)`` draws U(-1, 1) right-hand sides from the same generator,
+  continuing after the matrix draws; it is column-major, shape (nrhs, n).
+
+The recipes stand in for the paper's SuiteSparse workloads (Sec. IV): fat,
+parallel regions next to long runs of thin, near-serial levels.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Csr", "window_random", "stencil2d_chain", "stencil3d_tail", "powerlaw",
+    "batch_window", "rhs", "from_dense_lower", "bidiagonal", "diagonal",
+    "config_matrix",
+]
+
+
+@dataclass
+class Csr:
+    n: int
+    row_ptr: np.ndarray  # int32[n+1]
+    col: np.ndarray      # int32[nnz]
+    val: np.ndarray      # float64[nnz]
+    name: str = ""
+    rng_state: dict | None = field(default=None, repr=False)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.n, self.n))
+
+
+def _assemble(n, rows, cols, rng, name):
+    """Build the CSR from sorted, de-duplicated off-diagonal (rows, cols)
+    pairs, then draw the values with ``rng``."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    noff = np.bincount(rows, minlength=n).astype(np.int64) if rows.size else np.zeros(n, np.int64)
+    counts = noff + 1
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("matrix too large for int32 indices")
+    nnz = int(row_ptr[-1])
+    offv = rng.uniform(-1.0, 1.0, size=rows.size)
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    # position of each off-diagonal: row start + rank within its row
+    off_start = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(noff, out=off_start[1:])
+    rank = np.arange(rows.size, dtype=np.int64) - off_start[rows]
+    pos = row_ptr[rows] + rank
+    col[pos] = cols
+    val[pos] = offv
+    dpos = row_ptr[1:] - 1
+    col[dpos] = np.arange(n, dtype=np.int32)
+    absum = np.zeros(n, dtype=np.float64)
+    if rows.size:
+        np.add.at(absum, rows, np.abs(offv)) if rows.size < 4096 else None
+        if rows.size >= 4096:
+            absum = np.bincount(rows, weights=np.abs(offv), minlength=n)
+    val[dpos] = 1.0 + absum
+    return Csr(n, row_ptr.astype(np.int32), col, val, name, rng.bit_generator.state)
+
+
+def _unique_pairs(n, rows, cols):
+    key = np.unique(np.asarray(rows, np.int64) * n + np.asarray(cols, np.int64))
+    return key // n, key % n
+
+
+def window_random(n: int, seed: int, window: int = 64, draws: int = 5) -> Csr:
+    """Row i draws ``draws`` columns uniformly, with replacement, from
+    [max(0, i-window), i-1] and keeps the distinct ones ("up to 5")."""
+    rng = np.random.default_rng(seed)
+    if n > 1:
+        i = np.arange(1, n, dtype=np.int64)
+        lo = np.maximum(0, i - window)
+        c = rng.integers(lo[:, None], i[:, None], size=(n - 1, draws))
+        r = np.repeat(i, draws)
+        rows, cols = _unique_pairs(n, r, c.reshape(-1))
+    else:
+        rows = cols = np.zeros(0, np.int64)
+    return _assemble(n, rows, cols, rng, f"window{window}_n{n}_s{seed}")
+
+
+def _chain_pairs(rng, first: int, count: int):
+    """Chain rows q in [first, first+count): q-1 plus 2 distinct columns
+    uniform in [0, q-2] (fewer when q-1 < 2)."""
+    q = np.arange(first, first + count, dtype=np.int64)
+    if count == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    if first < 3:
+        raise ValueError("chain must start at row >= 3")
+    m = q - 1  # number of candidates in [0, q-2]
+    a = rng.integers(0, m)
+    c = rng.integers(0, m - 1)
+    c = c + (c >= a)
+    rows = np.concatenate([q, q, q])
+    cols = np.concatenate([a, c, q - 1])
+    return rows, cols
+
+
+def stencil2d_chain(k: int = 1000, chain: int = 20000, seed: int = 1) -> Csr:
+    """Lower triangle of the k x k 5-point stencil in natural order
+    (p = k*i + j depends on p-k and p-1), then ``chain`` near-serial rows."""
+    rng = np.random.default_rng(seed)
+    n0 = k * k
+    p = np.arange(n0, dtype=np.int64)
+    i, j = p // k, p % k
+    r_up, c_up = p[i > 0], p[i > 0] - k
+    r_lf, c_lf = p[j > 0], p[j > 0] - 1
+    cr, cc = _chain_pairs(rng, n0, chain)
+    rows = np.concatenate([r_up, r_lf, cr])
+    cols = np.concatenate([c_up, c_lf, cc])
+    rows, cols = _unique_pairs(n0 + chain, rows, cols)
+    return _assemble(n0 + chain, rows, cols, rng, f"stencil2d_k{k}_chain{chain}_s{seed}")
+
+
+def stencil3d_tail(k: int = 200, tail: int = 5000, seed: int = 4) -> Csr:
+    """Lower triangle of the k^3 7-point stencil, p = (k*i + j)*k + l, with
+    dependencies p-k^2, p-k, p-1; then a ``tail`` of chain rows."""
+    rng = np.random.default_rng(seed)
+    n0 = k * k * k
+    p = np.arange(n0, dtype=np.int64)
+    i, j, l = p // (k * k), (p // k) % k, p % k
+    parts_r = [p[i > 0], p[j > 0], p[l > 0]]
+    parts_c = [p[i > 0] - k * k, p[j > 0] - k, p[l > 0] - 1]
+    cr, cc = _chain_pairs(rng, n0, tail)
+    rows = np.concatenate(parts_r + [cr])
+    cols = np.concatenate(parts_c + [cc])
+    rows, cols = _unique_pairs(n0 + tail, rows, cols)
+    return _assemble(n0 + tail, rows, cols, rng, f"stencil3d_k{k}_tail{tail}_s{seed}")
+
+
+def powerlaw(n: int = 4_000_000, seed: int = 2, mean_deg: float = 8.0, w_loc: int = 4096,
+             nseg: int = 8, seglen: int = 250, alpha: float = 1.2) -> Csr:
+    """Power-law in-degree: column weights pi(j)^-alpha for a random
+    permutation pi. Row i takes min(Poisson(mean_deg), i) off-diagonals: one
+    local column uniform in [i-w_loc, i-1], the rest drawn by inverse CDF over
+    the weights restricted to [0, i), then de-duplicated. ``nseg`` segments of
+    ``seglen`` rows use a local window of 1, which makes them near-serial."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n).astype(np.float64) + 1.0
+    w = perm ** (-alpha)
+    cumw = np.cumsum(w)
+    deg = np.minimum(rng.poisson(mean_deg, n), np.arange(n))
+    wl = np.full(n, w_loc, dtype=np.int64)
+    for s in range(nseg):
+        st = ((s + 1) * n) // (nseg + 1)
+        wl[st:st + seglen] = 1
+    has = np.nonzero(deg >= 1)[0].astype(np.int64)
+    lo = np.maximum(0, has - wl[has])
+    loc = rng.integers(lo, has)
+    extra = (deg[has] - 1).astype(np.int64)
+    er = np.repeat(has, extra)
+    u = rng.random(er.size) * cumw[er - 1]
+    ec = np.searchsorted(cumw, u, side="right").astype(np.int64)
+    ec = np.minimum(ec, er - 1)
+    rows = np.concatenate([has, er])
+    cols = np.concatenate([loc, ec])
+    rows, cols = _unique_pairs(n, rows, cols)
+    return _assemble(n, rows, cols, rng, f"powerlaw_n{n}_s{seed}_w{w_loc}_g{nseg}")
+
+
+def batch_window(nmat: int = 512, seed: int = 3, nmin: int = 1000, nmax: int = 50000,
+                 window: int = 64) -> list[Csr]:
+    """``nmat`` independent window matrices with n ~ U{nmin..nmax}; matrix i
+    uses the window recipe with seed 1000*seed + i."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(nmin, nmax + 1, size=nmat)
+    return [window_random(int(sizes[i]), 1000 * seed + i, window) for i in range(nmat)]
+
+
+def rhs(m: Csr, nrhs: int = 1) -> np.ndarray:
+    """U(-1,1) right-hand sides continuing the matrix's generator; returned
+    column-major as an array of shape (nrhs, n) (column c is ``b[c]``)."""
+    rng = np.random.default_rng()
+    rng.bit_generator.state = m.rng_state
+    return rng.uniform(-1.0, 1.0, size=(nrhs, m.n))
+
+
+def from_dense_lower(a: np.ndarray, name: str = "dense") -> Csr:
+    """CSR of the nonzero lower triangle of a dense array (diagonal kept
+    even when zero, so validation can see it)."""
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[0]
+    rp = [0]
+    cols, vals = [], []
+    for i in range(n):
+        for j in range(i):
+            if a[i, j] != 0.0:
+                cols.append(j)
+                vals.append(a[i, j])
+        cols.append(i)
+        vals.append(a[i, i])
+        rp.append(len(cols))
+    return Csr(n, np.array(rp, np.int32), np.array(cols, np.int32), np.array(vals, np.float64), name,
+               np.random.default_rng(0).bit_generator.state)
+
+
+def diagonal(n: int, seed: int = 0) -> Csr:
+    return _assemble(n, np.zeros(0, np.int64), np.zeros(0, np.int64), np.random.default_rng(seed),
+                     f"diag_n{n}_s{seed}")
+
+
+def bidiagonal(n: int, seed: int = 0) -> Csr:
+    r = np.arange(1, n, dtype=np.int64)
+    return _assemble(n, r, r - 1, np.random.default_rng(seed), f"bidiag_n{n}_s{seed}")
+
+
+def config_matrix(idx: int, scale: str = "full"):
+    """The synthetic workload of each configuration.
+
+    ``scale="full"`` gives the benchmark sizes; ``scale="small"`` gives shapes
+    of the same structure small enough for the serial oracle in a test.
+    Returns (matrix or list of matrices, nrhs)."""
+    small = scale == "small"
+    if idx == 0:
+        return window_random(2000, 0), 1
+    if idx == 1:
+        return (stencil2d_chain(48, 600, 1) if small else stencil2d_chain(1000, 20000, 1)), 1
+    if idx == 2:
+        if small:
+            return powerlaw(60_000, 2, w_loc=512, nseg=4, seglen=60), 1
+        return powerlaw(4_000_000, 2), 1
+    if idx == 3:
+        if small:
+            return batch_window(12, 3, 500, 3000), 16
+        return batch_window(512, 3), 16
+    if idx == 4:
+        return (stencil3d_tail(16, 300, 4) if small else stencil3d_tail(200, 5000, 4)), 32
+    raise ValueError(idx)

@@ -1,0 +1,100 @@
+"""Pins for the FP64 MLP oracle (finite differences, torch autograd and
+torch's Adam in float64) and for the per-level policy features (brute force)."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from oracle import mlp
+
+
+def _batch(seed, B=37):
+    rng = np.random.default_rng(seed)
+    f = rng.normal(size=(B, 16))
+    y = (rng.random(B) < 0.4).astype(np.float64)
+    th = mlp.init(seed) + rng.normal(scale=0.05, size=mlp.NPARAM)  # nonzero biases
+    return th, f, y
+
+
+def test_param_count():
+    assert mlp.NPARAM == 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1 == 5313
+
+
+def test_gradient_finite_differences():
+    th, f, y = _batch(1)
+    g, _ = mlp.backward(th, f, y)
+    rng = np.random.default_rng(2)
+    idx = rng.choice(mlp.NPARAM, 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(th)
+        e[i] = h
+        fd = (mlp.loss(th + e, f, y) - mlp.loss(th - e, f, y)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-8
+
+
+def test_against_torch_autograd():
+    th, f, y = _batch(3)
+    g, lval = mlp.backward(th, f, y)
+    p = mlp.unpack(th)
+    t = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in p.items()}
+    x = torch.tensor(f)
+    h1 = torch.relu(x @ t["W1"].T + t["b1"])
+    h2 = torch.relu(h1 @ t["W2"].T + t["b2"])
+    z = h2 @ t["W3"] + t["b3"]
+    L = torch.nn.functional.binary_cross_entropy_with_logits(z, torch.tensor(y))
+    L.backward()
+    gt = np.concatenate([t[k].grad.numpy().reshape(-1) for k, _ in mlp.SIZES])
+    assert abs(L.item() - lval) < 1e-13
+    np.testing.assert_allclose(g, gt, rtol=1e-11, atol=1e-15)
+    prob, _ = mlp.forward(th, f)
+    np.testing.assert_allclose(prob, torch.sigmoid(z).detach().numpy(), rtol=1e-14)
+
+
+def test_adam_against_torch():
+    th, f, y = _batch(4)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    tt = torch.tensor(th.copy(), requires_grad=True)
+    opt = torch.optim.Adam([tt], lr=3e-3, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(1, 6):
+        g, _ = mlp.backward(th, f, y)
+        th, m, v = mlp.adam(th, g, m, v, step, 3e-3)
+        opt.zero_grad()
+        tt.grad = torch.tensor(mlp.backward(tt.detach().numpy(), f, y)[0])
+        opt.step()
+    np.testing.assert_allclose(th, tt.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_features_brute_force():
+    m = gen.window_random(300, 8, window=6, draws=3)
+    lv = oracle.levels(m)
+    F = oracle.level_features(m, lv)
+    c = oracle.level_costs(m, lv)
+    assert F.shape == (lv.nlev, 16)
+    nnz = np.diff(m.row_ptr)
+    for l in range(lv.nlev):
+        rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
+        R = len(rows)
+        assert F[l, 0] == pytest.approx(np.log1p(R))
+        assert F[l, 1] == pytest.approx(np.log1p(nnz[rows].sum()))
+        assert F[l, 2] == pytest.approx(np.log1p(np.sum(2 * nnz[rows] - 1)))
+        assert F[l, 3] == pytest.approx(np.sum(2 * nnz[rows] - 1) / (c.total / lv.nlev))
+        off = nnz[rows] - 1
+        bins = [off == 0, off == 1, off == 2, (off >= 3) & (off <= 4), (off >= 5) & (off <= 8), off >= 9]
+        for bi, bm in enumerate(bins):
+            assert F[l, 6 + bi] == pytest.approx(bm.mean())
+        assert F[l, 14] == pytest.approx(l / lv.nlev)
+    # features 12, 13: a single-level move toward the level before; compare with
+    # the oracle's own rewrite restricted to that one level (mask with one source)
+    for l in [1, 2, lv.nlev // 2, lv.nlev - 1]:
+        mask = np.zeros(lv.nlev, np.uint8)
+        mask[l] = 1
+        rw = oracle.rewrite(m, oracle.THIN_ROWS, 1e9, 0.0, 0, mask, lv)
+        rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
+        assert np.all(rw.target[rows] == l - 1)
+        lp = np.diff(rw.lp_ptr)[rows].sum()
+        tn = np.diff(rw.t_ptr)[rows].sum()
+        assert F[l, 12] == pytest.approx(lp / nnz[rows].sum())
+        assert F[l, 13] == pytest.approx(np.log1p(tn))

@@ -1,0 +1,313 @@
+"""Pins for the oracle's rewriting (substitution, rearrangement and the naive
+strategy's scan): the paper's Fig. 2 closed form and its cost-map example, a
+bidiagonal closed form, the unique-row characterisation by a dense solve,
+reachability by breadth-first search, and invariants on random inputs."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import gen
+import oracle
+from tests.test_oracle_solve_levels import _csr, fig2_matrix
+
+THIN_ROWS, THIN_COST = oracle.THIN_ROWS, oracle.THIN_COST
+
+
+def _row(rw_ptr, rw_col, rw_val, r):
+    s, e = rw_ptr[r], rw_ptr[r + 1]
+    return list(zip(rw_col[s:e].tolist(), rw_val[s:e].tolist()))
+
+
+# ------------------------------------------------------------- Fig. 2 example
+def test_fig2_closed_form():
+    v00, v10, v11, v22, v31, v33 = 2.0, 0.5, 3.0, 1.5, -0.75, 4.0
+    m = fig2_matrix(v00, v10, v11, v22, v31, v33)
+    lv = oracle.levels(m)
+    assert lv.nlev == 3 and list(lv.row_level) == [0, 1, 0, 2]
+    # rewrite every level toward level 0 (the two substitutions of Fig. 2)
+    rw = oracle.rewrite(m, THIN_ROWS, 100, mask=np.array([0, 1, 1], np.uint8))
+    assert list(rw.target) == [-1, 0, -1, 0]
+    l3 = _row(rw.lp_ptr, rw.lp_col, rw.lp_val, 3)
+    t3 = _row(rw.t_ptr, rw.t_col, rw.t_val, 3)
+    assert l3 == [(3, v33)]  # rewritten row keeps only its diagonal
+    assert [c for c, _ in t3] == [0, 1, 3]
+    np.testing.assert_allclose([x for _, x in t3], [v31 * v10 / (v11 * v00), -v31 / v11, 1.0], rtol=1e-15)
+    # the rewritten x[3] equals the nested expression of Sec. II.B
+    b = np.array([[0.3, -0.7, 0.2, 1.1]])
+    x = oracle.solve_rewritten(rw, b)
+    x3 = (b[0, 3] - v31 * ((b[0, 1] - v10 * (b[0, 0] / v00)) / v11)) / v33
+    assert abs(x[0, 3] - x3) <= 4e-16 * abs(x3)
+    # cost after rearrangement: row 3 costs 1 (Sec. III)
+    assert 2 * (rw.lp_ptr[4] - rw.lp_ptr[3]) - 1 == 1
+    assert oracle.levels(rw.lp).nlev == 1
+
+
+# -------------------------------------------------- cost-map worked example
+def costmap_matrix():
+    """Sec. III example shape: ancestors A..E at level 0, then levels n..n+3
+    holding rows r0..r7 (indices 5..12). Level n is kept as a target via the
+    mask; the budget is 22 as in the example."""
+    A, B, Cc, D, E = range(5)
+    r = list(range(5, 13))
+    rows = [[(i, 4.0)] for i in range(5)]
+    rows += [[(A, .1), (r[0], 4.0)], [(B, .1), (r[1], 4.0)]]              # level n
+    rows += [[(r[0], .2), (r[2], 4.0)], [(r[1], .2), (r[3], 4.0)]]        # level n+1
+    rows += [[(r[2], .3), (r[4], 4.0)],                                    # level n+2
+             [(Cc, .1), (D, .1), (E, .1), (r[3], .3), (r[5], 4.0)]]
+    rows += [[(r[5], .4), (r[6], 4.0)], [(r[4], .4), (r[7], 4.0)]]        # level n+3
+    return _csr(13, rows)
+
+
+def test_costmap_movement_pattern():
+    m = costmap_matrix()
+    lv = oracle.levels(m)
+    assert lv.nlev == 5
+    mask = np.array([0, 0, 1, 1, 1], np.uint8)
+    rw = oracle.rewrite(m, THIN_COST, 22.0, mask=mask, lv=lv)
+    r = list(range(5, 13))
+    tg = rw.target
+    # rows of level n+1 and the first row of level n+2 go to level n ...
+    assert [tg[r[2]], tg[r[3]], tg[r[4]]] == [1, 1, 1]
+    # ... the next row would push level n past the budget: it stays, and its
+    # level becomes the next target, which receives both rows of level n+3
+    assert tg[r[5]] == -1 and [tg[r[6]], tg[r[7]]] == [3, 3]
+    assert rw.rows_rewritten == 5
+    lv2 = oracle.levels(rw.lp)
+    assert lv2.nlev == lv.nlev - 2  # two levels emptied and removed
+    # level n ends with 5 rows; the next one with 3 (as in the example's result)
+    assert np.diff(lv2.level_ptr).tolist() == [5, 5, 3]
+
+
+# --------------------------------------------------- bidiagonal closed form
+def test_bidiagonal_closed_form_config1_rule():
+    n, W = 100, 32
+    m = gen.bidiagonal(n, 11)
+    d = m.val[m.row_ptr[1:] - 1]
+    e = np.zeros(n)
+    e[1:] = m.val[m.row_ptr[1:-1]]
+    rw = oracle.rewrite(m, THIN_ROWS, W, fill_cap=4.0)
+    assert oracle.levels(rw.lp).nlev == -(-n // W)
+    for r in range(n):
+        g, k = divmod(r, W)
+        if k == 0:
+            assert rw.target[r] == -1
+            continue
+        assert rw.target[r] == W * g  # targets are original level numbers
+        p = W * g - 1
+        lrow = _row(rw.lp_ptr, rw.lp_col, rw.lp_val, r)
+        if g == 0:
+            assert lrow == [(r, d[r])]
+        else:
+            val = (-1) ** k * e[r] * np.prod([e[r - q] / d[r - q] for q in range(1, k + 1)])
+            assert [c for c, _ in lrow] == [p, r]
+            assert abs(lrow[0][1] - val) <= 1e-14 * abs(val) and lrow[1][1] == d[r]
+        trow = _row(rw.t_ptr, rw.t_col, rw.t_val, r)
+        qs = range(1, (k if g > 0 else r) + 1)
+        assert [c for c, _ in trow] == sorted([r - q for q in qs]) + [r]
+        for c, tv in trow[:-1]:
+            q = r - c
+            ref = (-1) ** q * np.prod([e[r - mm] / d[r - mm - 1] for mm in range(q)])
+            assert abs(tv - ref) <= 1e-13 * abs(ref)
+        assert trow[-1] == (r, 1.0)
+
+
+# ------------------------------------------------ invariants + brute force
+def _final_cur(lv, rw):
+    cur = lv.row_level.copy()
+    mv = rw.target >= 0
+    cur[mv] = rw.target[mv]
+    return cur
+
+
+def _reach(m, r, inB):
+    """Breadth-first search from row r through rows in B: the B rows reached,
+    and the rows outside B adjacent to them (or to r)."""
+    seenB, A = set(), set()
+    stack = [int(c) for c in m.col[m.row_ptr[r]:m.row_ptr[r + 1] - 1]]
+    while stack:
+        k = stack.pop()
+        if inB[k]:
+            if k not in seenB:
+                seenB.add(k)
+                stack.extend(int(c) for c in m.col[m.row_ptr[k]:m.row_ptr[k + 1] - 1])
+        else:
+            A.add(k)
+    return seenB, A
+
+
+def check_rewrite_invariants(m, rw, lv, thin_metric, thr, fill_cap, max_distance, mask=None):
+    n = m.n
+    L = m.to_scipy()
+    Lp = rw.lp.to_scipy()
+    T = rw.t.to_scipy()
+    # L' = T L exactly in structure (values to rounding), T unit lower triangular
+    assert oracle.validate(rw.lp) == "OK"
+    assert oracle.validate(rw.t) == "OK"
+    assert np.all(rw.t_val[rw.t_ptr[1:] - 1] == 1.0)
+    prod = (T @ L).tocsr()
+    prod.sort_indices()
+    diff = abs(prod - Lp)
+    scale = abs(T) @ abs(L)
+    assert diff.max() <= 1e-12 * max(1.0, scale.max())
+    cur = _final_cur(lv, rw)
+    moved = rw.target >= 0
+    assert rw.rows_rewritten == int(moved.sum())
+    for r in range(n):
+        if not moved[r]:
+            assert _row(rw.lp_ptr, rw.lp_col, rw.lp_val, r) == list(
+                zip(m.col[m.row_ptr[r]:m.row_ptr[r + 1]].tolist(), m.val[m.row_ptr[r]:m.row_ptr[r + 1]].tolist()))
+            assert _row(rw.t_ptr, rw.t_col, rw.t_val, r) == [(r, 1.0)]
+            continue
+        t = rw.target[r]
+        assert t < lv.row_level[r]
+        if max_distance:
+            assert lv.row_level[r] - t <= max_distance
+        inB = cur >= t
+        seenB, A = _reach(m, r, inB)
+        lcols = rw.lp_col[rw.lp_ptr[r]:rw.lp_ptr[r + 1] - 1].tolist()
+        tcols = rw.t_col[rw.t_ptr[r]:rw.t_ptr[r + 1] - 1].tolist()
+        assert lcols == sorted(A)          # pattern of L'[r] = reachable A columns
+        assert tcols == sorted(seenB)      # pattern of T[r]   = reachable B rows
+        if fill_cap > 0:
+            assert len(lcols) + 1 <= fill_cap * (m.row_ptr[r + 1] - m.row_ptr[r])
+        # Appendix-style unique row: c = L[r,B] L[B,B]^{-1}, T[r,B] = -c
+        Bl = sorted(seenB)
+        if Bl:
+            LBB = L[Bl][:, Bl].toarray()
+            lrB = L[r, Bl].toarray().ravel()
+            c = np.linalg.solve(LBB.T, lrB)
+            tv = rw.t_val[rw.t_ptr[r]:rw.t_ptr[r + 1] - 1]
+            np.testing.assert_allclose(tv, -c, rtol=1e-10, atol=1e-13)
+    # re-levelled L': valid, never deeper
+    lv2 = oracle.levels(rw.lp)
+    assert lv2.nlev <= lv.nlev
+    # same x from the rewritten system
+    b = gen.rhs(m, 2)
+    assert oracle.relerr(oracle.solve_rewritten(rw, b), oracle.solve(m, b)) < 1e-10
+    return lv2
+
+
+def _scan_replay(m, lv, rw, thin_metric, thr, fill_cap, max_distance, mask):
+    """Re-derive the decisions from the per-row outcomes: every accepted row
+    respects the budget, and each run stops exactly at the first refusal."""
+    c = oracle.level_costs(m, lv)
+    W = thr if (thin_metric == THIN_ROWS or thr > 0) else c.avg
+    nnz_lp = np.diff(rw.lp_ptr)
+    nnz_l = np.diff(m.row_ptr)
+    t, size, cost = 0, c.rows[0], c.cost[0]
+    for l in range(1, lv.nlev):
+        src = bool(mask[l]) if mask is not None else (
+            c.rows[l] < W if thin_metric == THIN_ROWS else c.cost[l] < W)
+        rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
+        if not src:
+            assert np.all(rw.target[rows] == -1)
+            t, size, cost = l, c.rows[l], c.cost[l]
+            continue
+        for i, r in enumerate(rows):
+            if rw.target[r] == t:
+                size += 1
+                cost += 2 * nnz_lp[r] - 1
+                assert (size <= W) if thin_metric == THIN_ROWS else (cost <= W)
+            else:
+                assert rw.target[r] == -1 and np.all(rw.target[rows[i:]] == -1)
+                t = l
+                size = len(rows) - i
+                cost = int(np.sum(2 * nnz_l[rows[i:]] - 1))
+                break
+
+
+CASES = [
+    (THIN_ROWS, 4, 0.0, 0),
+    (THIN_ROWS, 3, 2.0, 0),
+    (THIN_ROWS, 6, 4.0, 2),
+    (THIN_COST, 0.0, 0.0, 0),
+    (THIN_COST, 0.0, 3.0, 0),
+    (THIN_COST, 40.0, 0.0, 3),
+]
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("case", CASES)
+def test_invariants_small_random(seed, case):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 40))
+    m = gen.window_random(n, seed, window=int(rng.integers(1, 8)), draws=int(rng.integers(1, 4)))
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, *case, lv=lv)
+    check_rewrite_invariants(m, rw, lv, *case)
+    _scan_replay(m, lv, rw, *case, None)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_invariants_with_mask(seed):
+    rng = np.random.default_rng(7 + seed)
+    m = gen.window_random(60, 20 + seed, window=5, draws=2)
+    lv = oracle.levels(m)
+    mask = (rng.random(lv.nlev) < 0.6).astype(np.uint8)
+    rw = oracle.rewrite(m, THIN_ROWS, 8, 4.0, 0, mask, lv)
+    check_rewrite_invariants(m, rw, lv, THIN_ROWS, 8, 4.0, 0, mask)
+    _scan_replay(m, lv, rw, THIN_ROWS, 8, 4.0, 0, mask)
+
+
+@pytest.mark.parametrize("mk", [lambda: gen.stencil2d_chain(10, 60, 1), lambda: gen.stencil3d_tail(4, 30, 4),
+                                lambda: gen.powerlaw(800, 9, w_loc=16, nseg=2, seglen=25)])
+def test_invariants_structured(mk):
+    m = mk()
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, THIN_ROWS, 32, 4.0, 0, None, lv)
+    check_rewrite_invariants(m, rw, lv, THIN_ROWS, 32, 4.0, 0)
+    _scan_replay(m, lv, rw, THIN_ROWS, 32, 4.0, 0, None)
+
+
+def test_paper_policy_thin_cost_default_budget():
+    m = gen.stencil2d_chain(12, 80, 1)
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, THIN_COST, 0.0, 0.0, 0, None, lv)
+    st = oracle.rewrite_stats(m, rw, lv)
+    assert st["nlev_after"] < st["nlev_before"]
+    # Table I relation: average level cost = total / number of levels
+    assert st["avg_level_cost_after"] == st["total_cost_after"] / st["nlev_after"]
+    check_rewrite_invariants(m, rw, lv, THIN_COST, 0.0, 0.0, 0)
+
+
+def test_config1_naive_structure():
+    m = gen.stencil2d_chain(1000, 20000, 1)
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, THIN_ROWS, 32, 4.0, 0, None, lv)
+    st = oracle.rewrite_stats(m, rw, lv)
+    assert st["nlev_before"] == 21999
+    assert st["nlev_after"] < 6000
+    # rows of the wide middle of the stencil are never touched
+    mid = lv.level_rows[lv.level_ptr[900]:lv.level_ptr[1100]]
+    assert np.all(rw.target[mid] == -1)
+
+
+# ------------------------------------------------ planted mistakes are caught
+def test_planted_sign_error_is_caught(tmp_path):
+    """Compile a copy of the oracle with one sign flipped in the substitution
+    update and check that the dense-solve pin rejects it."""
+    import ctypes as C
+    import os
+    import subprocess
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
+    bad = src.replace("s->wval[sk] = s->wval[sk] - m * v[p];", "s->wval[sk] = s->wval[sk] + m * v[p];")
+    assert bad != src
+    p = tmp_path / "bad.c"
+    p.write_text(bad)
+    so = tmp_path / "libbad.so"
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", str(p), "-o", str(so), "-lm"])
+    good_lib, good_path = oracle._lib, oracle._LIB_PATH
+    try:
+        oracle._lib = None
+        oracle._LIB_PATH = str(so)
+        oracle.build = lambda force=False: str(so)  # noqa: E731
+        m = gen.bidiagonal(70, 3)
+        lv = oracle.levels(m)
+        rw = oracle.rewrite(m, THIN_ROWS, 32, 4.0, 0, None, lv)
+        with pytest.raises(AssertionError):
+            check_rewrite_invariants(m, rw, lv, THIN_ROWS, 32, 4.0, 0)
+    finally:
+        import importlib
+        importlib.reload(oracle)
+        oracle._lib, oracle._LIB_PATH = good_lib, good_path
+    del C

@@ -1,0 +1,257 @@
+/*
+ * sptrsv.h -- C ABI of libsptrsv.so: level-scheduled sparse lower-triangular
+ * solves on MI355X (gfx950), with the equation-rewriting graph transformation of
+ * "A Graph Transformation Strategy for Optimizing SpTRSV" (Yilmaz and Yildiz,
+ * arXiv 2206.05843).
+ *
+ * Problem (Sec. II.A): given a sparse lower-triangular L in CSR and dense right-
+ * hand sides b, find x with L x = b. Rows are grouped into levels (no row depends
+ * on another row of its level) and levels are solved in order.
+ * Transformation (Sec. II.B, Sec. III): rows of thin levels are rewritten by
+ * substituting the equations of the rows they read, then rearranged back into
+ * L'x = b' form, with b' = T b; the rewritten rows move to earlier levels and
+ * the dependency graph becomes shorter and wider.
+ *
+ * Conventions for every call:
+ *   - Indices are 0-based int32. A CSR matrix has n+1 row pointers starting at 0,
+ *     column indices strictly ascending within a row, every column <= the row,
+ *     and the diagonal stored LAST in its row (the layout Algorithm 1 reads).
+ *   - Pointers named d_* are device pointers owned by the caller; h_* are host
+ *     pointers owned by the caller. Inputs are only read during the call.
+ *   - Dense right-hand sides and solutions are column-major: column c of b starts
+ *     at d_b + c*ldb (ld >= n). b and x must not overlap.
+ *   - hipStream_t may be NULL (the null stream). Calls marked ASYNC enqueue work
+ *     on the stream and return; the rest return after the stream has completed.
+ *   - Every call returns a status; nothing throws or aborts across this ABI. The
+ *     handle keeps a message for the last failure (sptrsv_last_error).
+ *   - A handle is used by one host thread at a time. All handle-owned device
+ *     memory lives until sptrsv_destroy (or the next analyze, which replaces it).
+ */
+#ifndef SPTRSV_H
+#define SPTRSV_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sptrsv_ctx *sptrsv_handle_t;
+
+typedef enum {
+  SPTRSV_OK = 0,
+  SPTRSV_ERR_ARG = 1,          /* bad argument or malformed row pointers       */
+  SPTRSV_ERR_STATE = 2,        /* call out of order (e.g. solve before analyze) */
+  SPTRSV_ERR_NOT_LOWER = 3,    /* a column index outside [0, row]              */
+  SPTRSV_ERR_UNSORTED = 4,     /* columns not strictly ascending in a row      */
+  SPTRSV_ERR_MISSING_DIAG = 5, /* empty row or last column != row              */
+  SPTRSV_ERR_ZERO_PIVOT = 6,   /* diagonal value 0                             */
+  SPTRSV_ERR_NONFINITE = 7,    /* NaN/Inf in values, or a non-finite solution  */
+  SPTRSV_ERR_OVERFLOW = 8,     /* a rewritten size exceeds int32 / a capacity  */
+  SPTRSV_ERR_ALLOC = 9,        /* device allocation failed                     */
+  SPTRSV_ERR_HIP = 10,         /* a HIP runtime call failed                    */
+  SPTRSV_ERR_TIMEOUT = 11      /* a bounded device-side wait expired           */
+} sptrsv_status_t;
+
+enum { SPTRSV_ORIGINAL = 0, SPTRSV_REWRITTEN = 1 };
+enum { SPTRSV_THIN_ROWS = 0, SPTRSV_THIN_COST = 1 };
+
+/* Handle lifetime. create: makes a handle bound to the current HIP device.
+ * destroy: frees every handle-owned buffer (NULL is accepted). */
+sptrsv_status_t sptrsv_create(sptrsv_handle_t *h);
+sptrsv_status_t sptrsv_destroy(sptrsv_handle_t h);
+/* Message of the handle's last failure ("" if none). Valid until the next call. */
+const char *sptrsv_last_error(sptrsv_handle_t h);
+/* Name of a status code, e.g. "SPTRSV_ERR_ZERO_PIVOT". */
+const char *sptrsv_status_name(sptrsv_status_t s);
+
+/* ---------------------------------------------------------------------------
+ * sptrsv_analyze -- validate L and build its level sets (Sec. II.A).
+ * The level of a row is the length of the longest dependency path that ends at
+ * it (0 for a row with no off-diagonal); the rows of a level are independent.
+ * Also builds the handle-owned level-ordered copy of L the solve streams.
+ *   n, nnz        : dimensions (nnz = d_row_ptr[n]); n >= 0
+ *   d_row_ptr     : int32[n+1], d_col: int32[nnz], d_val: double[nnz] (device)
+ *   nlevels_out   : host pointer, receives the number of levels
+ * Errors: ARG/NOT_LOWER/UNSORTED/MISSING_DIAG/ZERO_PIVOT/NONFINITE for malformed
+ * input (first in that priority order), TIMEOUT, ALLOC, HIP. The caller's arrays
+ * may be freed after the call returns (the handle keeps a copy). Synchronous.
+ * Replaces any previous analysis and rewrite held by the handle.
+ * ------------------------------------------------------------------------- */
+sptrsv_status_t sptrsv_analyze(sptrsv_handle_t h, int32_t n, int32_t nnz, const int32_t *d_row_ptr,
+                               const int32_t *d_col, const double *d_val, hipStream_t s,
+                               int32_t *nlevels_out);
+
+/* Copy the level sets of the ORIGINAL matrix or of the REWRITTEN matrix L'
+ * into caller buffers (device): level_ptr int32[nlev+1], level_rows int32[n]
+ * (rows of each level in ascending order), row_level int32[n]. Any pointer may
+ * be NULL to skip it. ERR_STATE if that matrix has not been analysed. ASYNC. */
+sptrsv_status_t sptrsv_get_levels(sptrsv_handle_t h, int which, int32_t *d_level_ptr, int32_t *d_level_rows,
+                                  int32_t *d_row_level, hipStream_t s);
+
+/* Per-level statistics of the cost model (Sec. III): rows, sum of nnz (diagonal
+ * included) and cost = 2*sum(nnz) - rows of every level, as int64[nlev] device
+ * arrays, plus (host) the total cost and avgLevelCost = total / nlev.
+ * Any pointer may be NULL. Synchronous. */
+sptrsv_status_t sptrsv_level_stats(sptrsv_handle_t h, int which, int64_t *d_rows, int64_t *d_nnz, int64_t *d_cost,
+                                   int64_t *h_total_cost, double *h_avg_level_cost, hipStream_t s);
+
+/* ---------------------------------------------------------------------------
+ * sptrsv_rewrite -- the naive strategy of Sec. III applied on the device.
+ * Sources are the thin levels (THIN_COST: level cost < thin_threshold, or
+ * < avgLevelCost when thin_threshold <= 0; THIN_ROWS: fewer than thin_threshold
+ * rows), or the levels a mask marks. Level 0 starts as the target; a non-source
+ * level becomes the target; the rows of each source level, in ascending order,
+ * are rewritten toward the current target while it stays within budget
+ * (THIN_COST: target cost, each row costing 2*nnz'-1, <= the threshold;
+ * THIN_ROWS: target rows <= thin_threshold), optionally while nnz(L'[r]) <=
+ * fill_cap * nnz(L[r]) and the distance is <= max_distance. The first refusal
+ * makes its level the next target (rows already moved stay moved).
+ * A row is rewritten by substituting, largest column first, every unknown whose
+ * row currently sits at or below the target level (Sec. II.B, Fig. 2) and
+ * rearranging (Sec. II.B): L'[r] keeps its diagonal; T[r] collects the b terms
+ * with a unit diagonal; explicit zeros from cancellation stay in the pattern.
+ * L' is then re-levelled (empty levels vanish) and prepared for solving.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t thin_metric;          /* SPTRSV_THIN_ROWS or SPTRSV_THIN_COST                         */
+  double thin_threshold;        /* ROWS: W (e.g. 32). COST: <= 0 means avgLevelCost              */
+  double fill_cap;              /* accept iff nnz(L'[r]) <= fill_cap * nnz(L[r]); <= 0 disables  */
+  int32_t max_distance;         /* 0 = unlimited                                                 */
+  const uint8_t *d_level_mask;  /* optional device uint8[nlev]: 1 = source; NULL = thin test     */
+} sptrsv_rewrite_opts_t;
+
+typedef struct {
+  int32_t nlev_before, nlev_after, rows_rewritten, max_distance, target_steps;
+  int64_t nnz_L, nnz_Lp, nnz_T, total_cost_before, total_cost_after;
+  double avg_level_cost_before, avg_level_cost_after; /* Table I metrics (Sec. IV) */
+} sptrsv_rewrite_stats_t;
+
+/* Errors: STATE (no analysis), ARG (bad opts), OVERFLOW (rewritten sizes beyond
+ * int32 or the device work capacity), TIMEOUT, ALLOC, HIP. st may be NULL.
+ * Synchronous. Replaces any previous rewrite held by the handle. */
+sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o, hipStream_t s,
+                               sptrsv_rewrite_stats_t *st);
+
+/* Copy L' and T (CSR over the ORIGINAL row numbering, both lower-triangular,
+ * diagonal last) into caller device buffers sized from the stats: row_ptr
+ * int32[n+1], col int32[nnz], val double[nnz]. Any pointer may be NULL. ASYNC.
+ * Also the per-row targets: int32[n], -1 for rows that were not rewritten. */
+sptrsv_status_t sptrsv_get_rewritten(sptrsv_handle_t h, int32_t *d_Lp_row_ptr, int32_t *d_Lp_col, double *d_Lp_val,
+                                     int32_t *d_T_row_ptr, int32_t *d_T_col, double *d_T_val, hipStream_t s);
+sptrsv_status_t sptrsv_get_targets(sptrsv_handle_t h, int32_t *d_target, hipStream_t s);
+
+/* ---------------------------------------------------------------------------
+ * sptrsv_solve -- x = L^{-1} b for nrhs >= 1 columns (Sec. II.A, Algorithm 1,
+ * level by level). which = ORIGINAL solves L; which = REWRITTEN computes
+ * b' = T b on the fly and solves L' x = b', which gives the same x.
+ *   d_b : double, column-major n x nrhs, ld ldb >= n;  d_x : same for x.
+ * ASYNC and capture-safe (no allocation, no host synchronisation) once a solve
+ * of the same (which, nrhs) has run or sptrsv_prepare has been called.
+ * A non-finite solution entry latches SPTRSV_ERR_NONFINITE on the device,
+ * reported by sptrsv_check. Errors: STATE, ARG (nrhs < 1, ld < n, overlap).
+ * ------------------------------------------------------------------------- */
+sptrsv_status_t sptrsv_solve(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
+                             double *d_x, int64_t ldx, hipStream_t s);
+
+/* Allocate the work vectors for (which, nrhs) so later solves allocate nothing. */
+sptrsv_status_t sptrsv_prepare(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s);
+
+/* Synchronise s and report (then clear) the errors latched on the device. */
+sptrsv_status_t sptrsv_check(sptrsv_handle_t h, hipStream_t s);
+
+/* Schedule knobs of the solve (see the autotuner): a level with at most
+ * thin_rows rows runs inside one workgroup of wg_threads threads, together with
+ * its thin neighbours; wider levels get one multi-workgroup launch each with
+ * wide_threads threads per workgroup. mode: 0 = automatic (tuned or default),
+ * 1 = every level as a wide launch, 2 = every level inside one workgroup. */
+typedef struct {
+  int32_t mode;
+  int32_t thin_rows;
+  int32_t wg_threads;     /* 256, 512 or 1024 */
+  int32_t wide_threads;   /* 64 .. 1024, multiple of 64 */
+  int32_t lanes_per_row;  /* wide levels, nrhs == 1: 1, 2, 4, 8, 16 or 32 lanes per row */
+} sptrsv_schedule_t;
+sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_schedule_t *sched);
+sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, sptrsv_schedule_t *sched);
+
+/* Autotuner: times candidate schedules with HIP events on s (inputs b = 1) and
+ * keeps the fastest for (which, nrhs). best_ms (host, may be NULL) receives the
+ * best solve time. Synchronous. */
+sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms);
+
+/* hipGraph capture of one solve with fixed buffers; replays are ASYNC. The graph
+ * belongs to the handle (at most 16); graph_id receives its index. */
+sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
+                                    double *d_x, int64_t ldx, hipStream_t s, int32_t *graph_id);
+sptrsv_status_t sptrsv_graph_launch(sptrsv_handle_t h, int32_t graph_id, hipStream_t s);
+
+/* Residual check: h_out[c] = max_i |(L x - b)[i,c]| for the ORIGINAL L, host
+ * double[nrhs]. Synchronous. */
+sptrsv_status_t sptrsv_residual(sptrsv_handle_t h, int32_t nrhs, const double *d_b, int64_t ldb, const double *d_x,
+                                int64_t ldx, double *h_out, hipStream_t s);
+
+/* ---------------------------------------------------------------------------
+ * Batched solves: many independent matrices, concatenated. Matrix i has n_i =
+ * h_n[i] rows starting at global row h_row_off[i] and nonzeros starting at
+ * h_nnz_off[i] of the concatenated arrays; its row pointers (d_row_ptr_cat
+ * segment of n_i+1 entries at h_row_off[i] + i) are LOCAL (start at 0) and its
+ * column indices local. Each matrix is level-scheduled as in sptrsv_analyze.
+ * batch_solve solves all matrices in one persistent launch; matrix i's b and x
+ * are n_i x nrhs column-major at offset nrhs*h_row_off[i], ld = n_i. ASYNC.
+ * ------------------------------------------------------------------------- */
+sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t nmat, const int32_t *h_n, const int64_t *h_row_off,
+                                     const int64_t *h_nnz_off, const int32_t *d_row_ptr_cat, const int32_t *d_col_cat,
+                                     const double *d_val_cat, hipStream_t s);
+sptrsv_status_t sptrsv_batch_solve(sptrsv_handle_t h, int32_t nrhs, const double *d_b_cat, double *d_x_cat,
+                                   hipStream_t s);
+/* The per-matrix solve the batched launch replaces: one plain solve per matrix,
+ * looped on the stream (ASYNC). */
+sptrsv_status_t sptrsv_batch_solve_looped(sptrsv_handle_t h, int32_t nrhs, const double *d_b_cat, double *d_x_cat,
+                                          hipStream_t s);
+/* Levels of batched matrix i (ERR_ARG if out of range). Synchronous. */
+sptrsv_status_t sptrsv_batch_levels(sptrsv_handle_t h, int32_t i, int32_t *nlev, int32_t *d_level_ptr,
+                                    int32_t *d_level_rows, hipStream_t s);
+
+/* ---------------------------------------------------------------------------
+ * Plan persistence: levels, rewritten matrix and schedules to a versioned file. */
+sptrsv_status_t sptrsv_plan_save(sptrsv_handle_t h, const char *path);
+sptrsv_status_t sptrsv_plan_load(sptrsv_handle_t h, const char *path);
+
+/* ---------------------------------------------------------------------------
+ * Learned rewrite policy (not in the paper; replaces the thin-level test of
+ * Sec. III with a small network). Parameters are float32[SPTRSV_MLP_NPARAM]:
+ * W1[64,16] b1[64] W2[64,64] b2[64] W3[64] b3[1], row-major.
+ * ------------------------------------------------------------------------- */
+#define SPTRSV_MLP_NIN 16
+#define SPTRSV_MLP_HID 64
+#define SPTRSV_MLP_NPARAM 5313
+
+/* 16 float features per level of the ORIGINAL matrix (layout float[nlev][16]):
+ * log1p(rows), log1p(sum nnz), log1p(cost), cost/avgLevelCost, rows/32,
+ * sum nnz/rows, fractions of rows with 0,1,2,3-4,5-8,>=9 off-diagonals,
+ * sum nnz(L'[r])/sum nnz(L[r]) and log1p(sum nnz(T[r])) if the level alone were
+ * rewritten into the level before it, level/nlev, log1p(rows of previous level).
+ * ASYNC. */
+sptrsv_status_t sptrsv_level_features(sptrsv_handle_t h, float *d_feat, hipStream_t s);
+/* p[i] = sigmoid(MLP(feat[i])) for batch rows (ASYNC). */
+sptrsv_status_t sptrsv_mlp_forward(const float *d_params, const float *d_feat, int32_t batch, float *d_prob,
+                                   hipStream_t s);
+/* Gradient of the mean binary cross-entropy over the batch w.r.t. every
+ * parameter (d_grad float[NPARAM], overwritten) and the loss (d_loss float[1]);
+ * d_weight (optional, float[batch]) scales each sample's loss term. ASYNC. */
+sptrsv_status_t sptrsv_mlp_backward(const float *d_params, const float *d_feat, const float *d_label,
+                                    const float *d_weight, int32_t batch, float *d_grad, float *d_loss,
+                                    hipStream_t s);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1). ASYNC. */
+sptrsv_status_t sptrsv_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t step, float lr,
+                                hipStream_t s);
+/* mask[l] = (p[l] >= threshold) for l >= 1, mask[0] = 0: the rewrite mask of
+ * the learned policy from probabilities (ASYNC). */
+sptrsv_status_t sptrsv_mlp_mask(const float *d_prob, int32_t nlev, float threshold, uint8_t *d_mask, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPTRSV_H */

@@ -1,0 +1,439 @@
+// C ABI of libsptrsv: handle, analysis, plans, schedules and the solve.
+#include <algorithm>
+#include <cstdarg>
+#include <cstring>
+
+#include "common.h"
+
+sptrsv_status_t status_from_bits(int bits) {
+  if (bits & EB_ARG) return SPTRSV_ERR_ARG;
+  if (bits & EB_NOT_LOWER) return SPTRSV_ERR_NOT_LOWER;
+  if (bits & EB_UNSORTED) return SPTRSV_ERR_UNSORTED;
+  if (bits & EB_MISSING_DIAG) return SPTRSV_ERR_MISSING_DIAG;
+  if (bits & EB_ZERO_PIVOT) return SPTRSV_ERR_ZERO_PIVOT;
+  if (bits & EB_NONFINITE) return SPTRSV_ERR_NONFINITE;
+  if (bits & EB_OVERFLOW) return SPTRSV_ERR_OVERFLOW;
+  if (bits & EB_TIMEOUT) return SPTRSV_ERR_TIMEOUT;
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t set_err(sptrsv_ctx *h, sptrsv_status_t st, const char *fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    h->last_error = std::string(sptrsv_status_name(st)) + ": " + buf;
+  }
+  return st;
+}
+
+namespace {
+
+int bit_width(int64_t v) {
+  int b = 0;
+  while (v > 0) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+sptrsv_schedule_t default_schedule() {
+  sptrsv_schedule_t s{};
+  s.mode = 0;
+  s.thin_rows = 4096;
+  s.wg_threads = 512;
+  s.wide_threads = 256;
+  s.lanes_per_row = 1;
+  return s;
+}
+
+bool same_sched(const sptrsv_schedule_t &a, const sptrsv_schedule_t &b) {
+  return a.mode == b.mode && a.thin_rows == b.thin_rows && a.wg_threads == b.wg_threads &&
+         a.wide_threads == b.wide_threads && a.lanes_per_row == b.lanes_per_row;
+}
+
+sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
+  if (s.mode < 0 || s.mode > 2) return set_err(h, SPTRSV_ERR_ARG, "schedule mode %d", s.mode);
+  if (s.wg_threads != 256 && s.wg_threads != 512 && s.wg_threads != 1024)
+    return set_err(h, SPTRSV_ERR_ARG, "wg_threads %d", s.wg_threads);
+  if (s.wide_threads < 64 || s.wide_threads > 1024 || s.wide_threads % 64)
+    return set_err(h, SPTRSV_ERR_ARG, "wide_threads %d", s.wide_threads);
+  const int g = s.lanes_per_row;
+  if (g != 1 && g != 2 && g != 4 && g != 8 && g != 16 && g != 32)
+    return set_err(h, SPTRSV_ERR_ARG, "lanes_per_row %d", g);
+  if (s.thin_rows < 0) return set_err(h, SPTRSV_ERR_ARG, "thin_rows %d", s.thin_rows);
+  return SPTRSV_OK;
+}
+
+// The schedule actually used for (P, nrhs): a tuned one if present, else the
+// handle's knobs.
+sptrsv_schedule_t effective_sched(const Plan &P, int32_t nrhs) {
+  if (P.sched.mode == 0) {
+    auto it = P.tuned.find(nrhs);
+    if (it != P.tuned.end()) return it->second;
+  }
+  return P.sched;
+}
+
+void make_runs(Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc) {
+  P.runs.clear();
+  const int32_t cap_rows = thin_lds_doubles() / nrhs;
+  int64_t thr = sc.thin_rows;
+  for (int32_t l = 0; l < P.nlev; ++l) {
+    const int32_t rows = P.h_level_ptr[l + 1] - P.h_level_ptr[l];
+    bool thin = sc.mode == 2 || (sc.mode == 0 && rows <= thr);
+    if (rows > cap_rows) thin = false;
+    if (thin && !P.runs.empty() && P.runs.back().thin && P.runs.back().l1 == l)
+      P.runs.back().l1 = l + 1;
+    else
+      P.runs.push_back(Run{l, l + 1, thin});
+  }
+  P.runs_nrhs = nrhs;
+  P.runs_sched = sc;
+}
+
+sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs) {
+  const size_t need = (size_t)P.n * (size_t)nrhs;
+  if (P.bp.n < need || !P.bp.p) HIPCHK(h, P.bp.alloc(need));
+  if (P.xp.n < need || !P.xp.p) HIPCHK(h, P.xp.alloc(need));
+  P.work_nrhs = std::max(P.work_nrhs, nrhs);
+  return SPTRSV_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan construction: levels (longest path), stable bucketing of rows by level,
+// level-ordered copy, optional T, statistics.
+sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                           const double *va, const int32_t *trp, const int32_t *tci, const double *tva,
+                           hipStream_t s) {
+  sptrsv_schedule_t keep_sched = P.ready ? P.sched : default_schedule();
+  P = Plan{};
+  P.sched = keep_sched;
+  P.n = n;
+  P.nnz = nnz;
+  HIPCHK(h, P.level_ptr.alloc((size_t)n + 1));
+  HIPCHK(h, P.perm.alloc(n));
+  HIPCHK(h, P.iperm.alloc(n));
+  HIPCHK(h, P.row_level.alloc(n));
+  HIPCHK(h, P.srp.alloc((size_t)n + 1));
+  if (n == 0) {
+    HIPCHK(h, hipMemsetAsync(P.level_ptr.p, 0, sizeof(int32_t), s));
+    HIPCHK(h, hipMemsetAsync(P.srp.p, 0, sizeof(int32_t), s));
+    HIPCHK(h, P.sci.alloc(1));
+    HIPCHK(h, P.sva.alloc(1));
+    HIPCHK(h, P.sdg.alloc(1));
+    HIPCHK(h, hipStreamSynchronize(s));
+    P.h_level_ptr.assign(1, 0);
+    P.ready = true;
+    return SPTRSV_OK;
+  }
+  DArr<int32_t> lev1, keys, ktmp, vtmp, hist;
+  DArr<long long> cnt, ex, hist64;
+  HIPCHK(h, lev1.alloc(n));
+  HIPCHK(h, keys.alloc(n));
+  HIPCHK(h, ktmp.alloc(n));
+  HIPCHK(h, vtmp.alloc(n));
+  HIPCHK(h, cnt.alloc(n));
+  HIPCHK(h, ex.alloc(n));
+  const size_t hn = radix_hist_elems(n);
+  HIPCHK(h, hist.alloc(hn));
+  HIPCHK(h, hist64.alloc(hn));
+  const size_t scr = std::max(scan_scratch_elems((int64_t)hn), scan_scratch_elems(n)) + 16;
+  if (h->scan_tmp.n < scr) HIPCHK(h, h->scan_tmp.alloc(scr));
+  int32_t *aux = h->d_aux.p;  // [0] ticket, [1] error bits, [2] max level+1, [3..4] total cost
+  HIPCHK(h, hipMemsetAsync(aux, 0, 8 * sizeof(int32_t), s));
+  HIPCHK(h, hipMemsetAsync(lev1.p, 0, sizeof(int32_t) * (size_t)n, s));
+  HIPCHK(h, launch_levels(n, rp, ci, lev1.p, reinterpret_cast<unsigned *>(aux), aux + 1, s));
+  HIPCHK(h, launch_max(lev1.p, n, aux + 2, s));
+  int32_t haux[8];
+  HIPCHK(h, hipMemcpyAsync(haux, aux, sizeof(haux), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (haux[1]) return set_err(h, status_from_bits(haux[1]), "level construction failed (bits 0x%x)", haux[1]);
+  const int32_t nlev = haux[2];
+  P.nlev = nlev;
+  // rows sorted stably by level -> level_rows (= perm), level_ptr
+  HIPCHK(h, hipMemcpyAsync(keys.p, lev1.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, launch_iota(P.perm.p, n, s));
+  HIPCHK(h, launch_radix_by_key(keys.p, P.perm.p, ktmp.p, vtmp.p, n, bit_width(nlev), hist.p, hist64.p,
+                                h->scan_tmp.p, s));
+  HIPCHK(h, launch_level_ptr_from_sorted(keys.p, n, P.level_ptr.p, nlev, s));
+  HIPCHK(h, launch_invert_perm(P.perm.p, n, P.iperm.p, s));
+  HIPCHK(h, launch_sub1(lev1.p, n, P.row_level.p, s));
+  // level-ordered copy of the off-diagonals
+  HIPCHK(h, launch_count_off(P.perm.p, rp, n, cnt.p, s));
+  HIPCHK(h, launch_scan_i64(cnt.p, ex.p, n, h->scan_tmp.p, s));
+  HIPCHK(h, launch_ptr_from_scan(ex.p, cnt.p, n, P.srp.p, aux + 1, s));
+  const int64_t noff = nnz - n;
+  HIPCHK(h, P.sci.alloc((size_t)std::max<int64_t>(noff, 1)));
+  HIPCHK(h, P.sva.alloc((size_t)std::max<int64_t>(noff, 1)));
+  HIPCHK(h, P.sdg.alloc(n));
+  HIPCHK(h, launch_fill_solve(n, P.perm.p, P.iperm.p, rp, ci, va, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, s));
+  if (trp) {
+    P.has_t = true;
+    HIPCHK(h, P.trp.alloc((size_t)n + 1));
+    HIPCHK(h, launch_count_off(P.perm.p, trp, n, cnt.p, s));
+    HIPCHK(h, launch_scan_i64(cnt.p, ex.p, n, h->scan_tmp.p, s));
+    HIPCHK(h, launch_ptr_from_scan(ex.p, cnt.p, n, P.trp.p, aux + 1, s));
+    int32_t tn = 0;
+    HIPCHK(h, hipMemcpyAsync(&tn, P.trp.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    P.nnz_t_off = tn;
+    HIPCHK(h, P.tci.alloc((size_t)std::max(tn, 1)));
+    HIPCHK(h, P.tva.alloc((size_t)std::max(tn, 1)));
+    HIPCHK(h, launch_fill_t(n, P.perm.p, P.iperm.p, trp, tci, tva, P.trp.p, P.tci.p, P.tva.p, s));
+  }
+  // statistics of the cost model
+  HIPCHK(h, P.lv_rows.alloc(nlev));
+  HIPCHK(h, P.lv_nnz.alloc(nlev));
+  HIPCHK(h, P.lv_cost.alloc(nlev));
+  HIPCHK(h, launch_level_stats(nlev, P.level_ptr.p, P.srp.p, P.lv_rows.p, P.lv_nnz.p, P.lv_cost.p,
+                               reinterpret_cast<long long *>(aux + 4), s));
+  P.h_level_ptr.resize((size_t)nlev + 1);
+  HIPCHK(h, hipMemcpyAsync(P.h_level_ptr.data(), P.level_ptr.p, sizeof(int32_t) * ((size_t)nlev + 1),
+                           hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(haux, aux, sizeof(haux), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (haux[1]) return set_err(h, status_from_bits(haux[1]), "plan construction failed (bits 0x%x)", haux[1]);
+  long long tot;
+  std::memcpy(&tot, haux + 4, sizeof(tot));
+  P.total_cost = tot;
+  P.avg_cost = nlev > 0 ? (double)tot / (double)nlev : 0.0;
+  P.ready = true;
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
+                           int64_t ldx, hipStream_t s) {
+  if (P.n == 0) return SPTRSV_OK;
+  STCHK(ensure_work(h, P, nrhs));
+  const sptrsv_schedule_t sc = effective_sched(P, nrhs);
+  if (P.runs_nrhs != nrhs || !same_sched(sc, P.runs_sched)) make_runs(P, nrhs, sc);
+  int *err = h->d_err.p;
+  HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.bp.p, s));
+  const int32_t *trp = P.has_t ? P.trp.p : nullptr;
+  for (const Run &r : P.runs) {
+    if (r.thin) {
+      HIPCHK(h, launch_thin_run(sc.wg_threads, r.l0, r.l1, P.level_ptr.p, nrhs, P.srp.p, P.sci.p, P.sva.p, P.sdg.p,
+                                trp, P.tci.p, P.tva.p, P.bp.p, P.xp.p, err, s));
+    } else {
+      HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
+                                  P.srp.p, P.sci.p, P.sva.p, P.sdg.p, trp, P.tci.p, P.tva.p, P.bp.p, P.xp.p, err,
+                                  s));
+    }
+  }
+  HIPCHK(h, launch_scatter(P.n, nrhs, P.xp.p, P.iperm.p, x, ldx, s));
+  return SPTRSV_OK;
+}
+
+// ------------------------------------------------------------------- ABI
+extern "C" {
+
+const char *sptrsv_status_name(sptrsv_status_t s) {
+  switch (s) {
+    case SPTRSV_OK: return "SPTRSV_OK";
+    case SPTRSV_ERR_ARG: return "SPTRSV_ERR_ARG";
+    case SPTRSV_ERR_STATE: return "SPTRSV_ERR_STATE";
+    case SPTRSV_ERR_NOT_LOWER: return "SPTRSV_ERR_NOT_LOWER";
+    case SPTRSV_ERR_UNSORTED: return "SPTRSV_ERR_UNSORTED";
+    case SPTRSV_ERR_MISSING_DIAG: return "SPTRSV_ERR_MISSING_DIAG";
+    case SPTRSV_ERR_ZERO_PIVOT: return "SPTRSV_ERR_ZERO_PIVOT";
+    case SPTRSV_ERR_NONFINITE: return "SPTRSV_ERR_NONFINITE";
+    case SPTRSV_ERR_OVERFLOW: return "SPTRSV_ERR_OVERFLOW";
+    case SPTRSV_ERR_ALLOC: return "SPTRSV_ERR_ALLOC";
+    case SPTRSV_ERR_HIP: return "SPTRSV_ERR_HIP";
+    case SPTRSV_ERR_TIMEOUT: return "SPTRSV_ERR_TIMEOUT";
+  }
+  return "SPTRSV_UNKNOWN";
+}
+
+sptrsv_status_t sptrsv_create(sptrsv_handle_t *out) {
+  if (!out) return SPTRSV_ERR_ARG;
+  *out = nullptr;
+  sptrsv_ctx *h = new (std::nothrow) sptrsv_ctx();
+  if (!h) return SPTRSV_ERR_ALLOC;
+  if (hipGetDevice(&h->dev) != hipSuccess || h->d_err.alloc(4) != hipSuccess || h->d_aux.alloc(512) != hipSuccess ||
+      hipMemset(h->d_err.p, 0, 4 * sizeof(int32_t)) != hipSuccess ||
+      hipMemset(h->d_aux.p, 0, 512 * sizeof(int32_t)) != hipSuccess) {
+    delete h;
+    return SPTRSV_ERR_HIP;
+  }
+  static bool inited = false;
+  if (!inited) {
+    solve_kernels_init();
+    inited = true;
+  }
+  h->orig.sched = default_schedule();
+  h->rew.sched = default_schedule();
+  *out = h;
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_destroy(sptrsv_handle_t h) {
+  if (!h) return SPTRSV_OK;
+  (void)hipDeviceSynchronize();
+  for (Graph &g : h->graphs) {
+    if (g.ge) (void)hipGraphExecDestroy(g.ge);
+    if (g.g) (void)hipGraphDestroy(g.g);
+  }
+  delete h;
+  return SPTRSV_OK;
+}
+
+const char *sptrsv_last_error(sptrsv_handle_t h) { return h ? h->last_error.c_str() : "null handle"; }
+
+sptrsv_status_t sptrsv_analyze(sptrsv_handle_t h, int32_t n, int32_t nnz, const int32_t *d_row_ptr,
+                               const int32_t *d_col, const double *d_val, hipStream_t s, int32_t *nlevels_out) {
+  if (!h) return SPTRSV_ERR_ARG;
+  h->last_error.clear();
+  if (n < 0 || nnz < 0 || !d_row_ptr || (nnz > 0 && (!d_col || !d_val)))
+    return set_err(h, SPTRSV_ERR_ARG, "analyze: n=%d nnz=%d", n, nnz);
+  if (nnz < n) return set_err(h, SPTRSV_ERR_MISSING_DIAG, "analyze: nnz %d < n %d", nnz, n);
+  h->orig.ready = false;
+  h->rew.ready = false;
+  h->has_rewrite = false;
+  int32_t *aux = h->d_aux.p;
+  HIPCHK(h, hipMemsetAsync(aux + 1, 0, sizeof(int32_t), s));
+  HIPCHK(h, launch_validate(n, nnz, d_row_ptr, d_col, d_val, aux + 1, s));
+  int32_t bits = 0;
+  HIPCHK(h, hipMemcpyAsync(&bits, aux + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (bits) return set_err(h, status_from_bits(bits), "analyze: invalid matrix (bits 0x%x)", bits);
+  h->n = n;
+  h->nnz = nnz;
+  HIPCHK(h, h->rp.alloc((size_t)n + 1));
+  HIPCHK(h, h->ci.alloc((size_t)std::max(nnz, 1)));
+  HIPCHK(h, h->va.alloc((size_t)std::max(nnz, 1)));
+  HIPCHK(h, hipMemcpyAsync(h->rp.p, d_row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+  if (nnz) {
+    HIPCHK(h, hipMemcpyAsync(h->ci.p, d_col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+    HIPCHK(h, hipMemcpyAsync(h->va.p, d_val, sizeof(double) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+  }
+  STCHK(build_plan(h, h->orig, n, nnz, h->rp.p, h->ci.p, h->va.p, nullptr, nullptr, nullptr, s));
+  if (nlevels_out) *nlevels_out = h->orig.nlev;
+  return SPTRSV_OK;
+}
+
+static Plan *plan_of(sptrsv_ctx *h, int which) {
+  if (which == SPTRSV_ORIGINAL) return &h->orig;
+  if (which == SPTRSV_REWRITTEN) return &h->rew;
+  return nullptr;
+}
+
+sptrsv_status_t sptrsv_get_levels(sptrsv_handle_t h, int which, int32_t *d_level_ptr, int32_t *d_level_rows,
+                                  int32_t *d_row_level, hipStream_t s) {
+  if (!h) return SPTRSV_ERR_ARG;
+  Plan *P = plan_of(h, which);
+  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  if (!P->ready) return set_err(h, SPTRSV_ERR_STATE, "matrix not analysed");
+  if (d_level_ptr)
+    HIPCHK(h, hipMemcpyAsync(d_level_ptr, P->level_ptr.p, sizeof(int32_t) * ((size_t)P->nlev + 1),
+                             hipMemcpyDeviceToDevice, s));
+  if (P->n && d_level_rows)
+    HIPCHK(h, hipMemcpyAsync(d_level_rows, P->perm.p, sizeof(int32_t) * (size_t)P->n, hipMemcpyDeviceToDevice, s));
+  if (P->n && d_row_level)
+    HIPCHK(h,
+           hipMemcpyAsync(d_row_level, P->row_level.p, sizeof(int32_t) * (size_t)P->n, hipMemcpyDeviceToDevice, s));
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_level_stats(sptrsv_handle_t h, int which, int64_t *d_rows, int64_t *d_nnz, int64_t *d_cost,
+                                   int64_t *h_total_cost, double *h_avg_level_cost, hipStream_t s) {
+  if (!h) return SPTRSV_ERR_ARG;
+  Plan *P = plan_of(h, which);
+  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  if (!P->ready) return set_err(h, SPTRSV_ERR_STATE, "matrix not analysed");
+  const size_t b = sizeof(int64_t) * (size_t)P->nlev;
+  if (P->nlev && d_rows) HIPCHK(h, hipMemcpyAsync(d_rows, P->lv_rows.p, b, hipMemcpyDeviceToDevice, s));
+  if (P->nlev && d_nnz) HIPCHK(h, hipMemcpyAsync(d_nnz, P->lv_nnz.p, b, hipMemcpyDeviceToDevice, s));
+  if (P->nlev && d_cost) HIPCHK(h, hipMemcpyAsync(d_cost, P->lv_cost.p, b, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (h_total_cost) *h_total_cost = P->total_cost;
+  if (h_avg_level_cost) *h_avg_level_cost = P->avg_cost;
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_prepare(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s) {
+  (void)s;
+  if (!h) return SPTRSV_ERR_ARG;
+  Plan *P = plan_of(h, which);
+  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  if (!P->ready) return set_err(h, SPTRSV_ERR_STATE, "matrix not analysed/rewritten");
+  if (nrhs < 1) return set_err(h, SPTRSV_ERR_ARG, "nrhs=%d", nrhs);
+  STCHK(ensure_work(h, *P, nrhs));
+  const sptrsv_schedule_t sc = effective_sched(*P, nrhs);
+  make_runs(*P, nrhs, sc);
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_solve(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
+                             double *d_x, int64_t ldx, hipStream_t s) {
+  if (!h) return SPTRSV_ERR_ARG;
+  Plan *P = plan_of(h, which);
+  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  if (!P->ready)
+    return set_err(h, SPTRSV_ERR_STATE, which == SPTRSV_REWRITTEN ? "no rewrite yet" : "matrix not analysed");
+  const int64_t n = P->n;
+  if (nrhs < 1 || ldb < n || ldx < n || (n > 0 && (!d_b || !d_x)))
+    return set_err(h, SPTRSV_ERR_ARG, "solve: nrhs=%d ldb=%lld ldx=%lld", nrhs, (long long)ldb, (long long)ldx);
+  if (n > 0) {
+    const char *b0 = reinterpret_cast<const char *>(d_b);
+    const char *b1 = b0 + sizeof(double) * (size_t)(ldb * (nrhs - 1) + n);
+    const char *x0 = reinterpret_cast<const char *>(d_x);
+    const char *x1 = x0 + sizeof(double) * (size_t)(ldx * (nrhs - 1) + n);
+    if (b0 < x1 && x0 < b1) return set_err(h, SPTRSV_ERR_ARG, "b and x overlap");
+  }
+  return plan_solve(h, *P, nrhs, d_b, ldb, d_x, ldx, s);
+}
+
+sptrsv_status_t sptrsv_check(sptrsv_handle_t h, hipStream_t s) {
+  if (!h) return SPTRSV_ERR_ARG;
+  int32_t bits = 0;
+  HIPCHK(h, hipMemcpyAsync(&bits, h->d_err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (bits) {
+    HIPCHK(h, hipMemsetAsync(h->d_err.p, 0, sizeof(int32_t), s));
+    HIPCHK(h, hipStreamSynchronize(s));
+    return set_err(h, status_from_bits(bits), "device reported error bits 0x%x", bits);
+  }
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_schedule_t *sched) {
+  if (!h || !sched) return SPTRSV_ERR_ARG;
+  Plan *P = plan_of(h, which);
+  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  STCHK(check_sched(h, *sched));
+  P->sched = *sched;
+  P->runs_nrhs = -1;
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, sptrsv_schedule_t *sched) {
+  if (!h || !sched) return SPTRSV_ERR_ARG;
+  Plan *P = plan_of(h, which);
+  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  *sched = P->sched;
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_residual(sptrsv_handle_t h, int32_t nrhs, const double *d_b, int64_t ldb, const double *d_x,
+                                int64_t ldx, double *h_out, hipStream_t s) {
+  if (!h || !h_out) return SPTRSV_ERR_ARG;
+  if (!h->orig.ready) return set_err(h, SPTRSV_ERR_STATE, "matrix not analysed");
+  if (nrhs < 1 || nrhs > 56 || ldb < h->n || ldx < h->n) return set_err(h, SPTRSV_ERR_ARG, "residual args");
+  unsigned long long *out = reinterpret_cast<unsigned long long *>(h->d_aux.p + 128);
+  HIPCHK(h, hipMemsetAsync(out, 0, sizeof(unsigned long long) * (size_t)nrhs, s));
+  HIPCHK(h, launch_residual(h->n, nrhs, h->rp.p, h->ci.p, h->va.p, d_b, ldb, d_x, ldx, out, s));
+  std::vector<unsigned long long> hv((size_t)nrhs);
+  HIPCHK(h, hipMemcpyAsync(hv.data(), out, sizeof(unsigned long long) * (size_t)nrhs, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  for (int c = 0; c < nrhs; ++c) std::memcpy(&h_out[c], &hv[(size_t)c], sizeof(double));
+  return SPTRSV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// Autotuner and hipGraph capture of solves.
+#include <algorithm>
+#include <cstring>
+
+#include "common.h"
+
+namespace {
+
+__global__ void k_fill(double *a, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+Plan *plan_of(sptrsv_ctx *h, int which) {
+  if (which == SPTRSV_ORIGINAL) return &h->orig;
+  if (which == SPTRSV_REWRITTEN) return &h->rew;
+  return nullptr;
+}
+
+// Candidate schedules: all-wide, all-in-one-workgroup, and thin/wide splits at
+// several widths, workgroup sizes and (one RHS) lanes per row.
+std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
+  std::vector<sptrsv_schedule_t> c;
+  const int thin_list[] = {64, 256, 1024, 4096, 16384};
+  const int wg_list[] = {256, 512, 1024};
+  const int lpr1[] = {1, 4};
+  for (int wg : wg_list) {
+    sptrsv_schedule_t s{2, 0, wg, 256, 1};
+    c.push_back(s);
+  }
+  for (int lpr : lpr1) {
+    if (nrhs > 1 && lpr > 1) continue;
+    c.push_back(sptrsv_schedule_t{1, 0, 512, 256, lpr});
+    for (int thr : thin_list) {
+      if ((int64_t)thr * nrhs > thin_lds_doubles()) continue;
+      for (int wg : wg_list) c.push_back(sptrsv_schedule_t{0, thr, wg, 256, lpr});
+    }
+  }
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms) {
+  if (!h) return SPTRSV_ERR_ARG;
+  Plan *P = plan_of(h, which);
+  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  if (!P->ready) return set_err(h, SPTRSV_ERR_STATE, "matrix not analysed/rewritten");
+  if (nrhs < 1) return set_err(h, SPTRSV_ERR_ARG, "nrhs=%d", nrhs);
+  const int64_t n = P->n;
+  if (n == 0) {
+    if (best_ms) *best_ms = 0.f;
+    return SPTRSV_OK;
+  }
+  DArr<double> b, x;
+  HIPCHK(h, b.alloc((size_t)(n * nrhs)));
+  HIPCHK(h, x.alloc((size_t)(n * nrhs)));
+  hipLaunchKernelGGL(k_fill, dim3(1024), dim3(256), 0, s, b.p, n * nrhs, 1.0);
+  HIPCHK(h, hipGetLastError());
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  const sptrsv_schedule_t keep = P->sched;
+  float best = 1e30f;
+  sptrsv_schedule_t best_s = keep;
+  sptrsv_status_t st = SPTRSV_OK;
+  for (const sptrsv_schedule_t &cand : candidates(nrhs)) {
+    P->sched = cand;
+    P->runs_nrhs = -1;
+    P->tuned.erase(nrhs);
+    float t[3];
+    st = plan_solve(h, *P, nrhs, b.p, n, x.p, n, s);  // warm-up
+    if (st != SPTRSV_OK) break;
+    for (int rep = 0; rep < 3 && st == SPTRSV_OK; ++rep) {
+      (void)hipEventRecord(e0, s);
+      st = plan_solve(h, *P, nrhs, b.p, n, x.p, n, s);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      (void)hipEventElapsedTime(&t[rep], e0, e1);
+    }
+    if (st != SPTRSV_OK) break;
+    std::sort(t, t + 3);
+    if (t[1] < best) {
+      best = t[1];
+      best_s = cand;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->sched = keep;
+  P->runs_nrhs = -1;
+  if (st != SPTRSV_OK) return st;
+  HIPCHK(h, hipStreamSynchronize(s));
+  P->tuned[nrhs] = best_s;
+  if (best_ms) *best_ms = best;
+  return sptrsv_check(h, s);
+}
+
+sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
+                                    double *d_x, int64_t ldx, hipStream_t s, int32_t *graph_id) {
+  if (!h || !graph_id) return SPTRSV_ERR_ARG;
+  if (!s) return set_err(h, SPTRSV_ERR_ARG, "graph capture needs a non-null stream");
+  if (h->graphs.size() >= 16) return set_err(h, SPTRSV_ERR_ARG, "at most 16 graphs per handle");
+  STCHK(sptrsv_prepare(h, which, nrhs, s));
+  Graph g;
+  HIPCHK(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  sptrsv_status_t st = sptrsv_solve(h, which, nrhs, d_b, ldb, d_x, ldx, s);
+  hipError_t e = hipStreamEndCapture(s, &g.g);
+  if (st != SPTRSV_OK) {
+    if (g.g) (void)hipGraphDestroy(g.g);
+    return st;
+  }
+  if (e != hipSuccess) return set_err(h, SPTRSV_ERR_HIP, "capture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&g.ge, g.g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g.g);
+    return set_err(h, SPTRSV_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  h->graphs.push_back(g);
+  *graph_id = (int32_t)h->graphs.size() - 1;
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_graph_launch(sptrsv_handle_t h, int32_t graph_id, hipStream_t s) {
+  if (!h) return SPTRSV_ERR_ARG;
+  if (graph_id < 0 || graph_id >= (int32_t)h->graphs.size()) return set_err(h, SPTRSV_ERR_ARG, "graph id");
+  HIPCHK(h, hipGraphLaunch(h->graphs[(size_t)graph_id].ge, s));
+  return SPTRSV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+// Internal declarations of libsptrsv: device buffers, the handle, plans and
+// the host-side launchers of every kernel. Nothing here is part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "sptrsv.h"
+
+// Error bits latched on the device (atomicOr into a handle-owned int).
+enum : int {
+  EB_ARG = 1 << 0,
+  EB_NOT_LOWER = 1 << 1,
+  EB_UNSORTED = 1 << 2,
+  EB_MISSING_DIAG = 1 << 3,
+  EB_ZERO_PIVOT = 1 << 4,
+  EB_NONFINITE = 1 << 5,
+  EB_OVERFLOW = 1 << 6,
+  EB_TIMEOUT = 1 << 7,
+};
+sptrsv_status_t status_from_bits(int bits);
+
+// Owned device array (hipMalloc'd, freed on destruction or re-allocation).
+template <class T>
+struct DArr {
+  T *p = nullptr;
+  size_t n = 0;
+  DArr() = default;
+  DArr(const DArr &) = delete;
+  DArr &operator=(const DArr &) = delete;
+  DArr(DArr &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr, o.n = 0; }
+  DArr &operator=(DArr &&o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p, n = o.n, o.p = nullptr, o.n = 0;
+    }
+    return *this;
+  }
+  ~DArr() { release(); }
+  hipError_t alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;  // keep a valid pointer for empty arrays
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    n = count;
+    return hipSuccess;
+  }
+  // grow-only allocation
+  hipError_t reserve(size_t count) { return count <= n && p ? hipSuccess : alloc(count); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+// One run of the solve schedule: a range of levels done inside one workgroup
+// (thin) or a single level spread over the device (wide).
+struct Run {
+  int32_t l0, l1;  // levels [l0, l1)
+  bool thin;
+};
+
+// Everything needed to solve one lower-triangular matrix level by level:
+// its level sets, a level-ordered copy with columns renumbered to positions,
+// the optional b-transform T (off-diagonals, same numbering) and work vectors.
+struct Plan {
+  bool ready = false;
+  int32_t n = 0, nlev = 0;
+  int64_t nnz = 0;                     // nonzeros including the diagonal
+  DArr<int32_t> level_ptr;             // [nlev+1] positions
+  DArr<int32_t> perm;                  // [n] position -> row (= level_rows)
+  DArr<int32_t> iperm;                 // [n] row -> position
+  DArr<int32_t> row_level;             // [n]
+  std::vector<int32_t> h_level_ptr;    // host copy for scheduling
+  DArr<int32_t> srp, sci;              // level-ordered off-diagonal CSR
+  DArr<double> sva, sdg;               // values, diagonal per position
+  bool has_t = false;
+  int64_t nnz_t_off = 0;
+  DArr<int32_t> trp, tci;              // T off-diagonals per position
+  DArr<double> tva;
+  DArr<int64_t> lv_rows, lv_nnz, lv_cost;
+  int64_t total_cost = 0;
+  double avg_cost = 0.0;
+  sptrsv_schedule_t sched{};           // knobs in force (mode 0 = automatic)
+  std::map<int32_t, sptrsv_schedule_t> tuned;  // per nrhs
+  std::vector<Run> runs;
+  int32_t runs_nrhs = -1;
+  sptrsv_schedule_t runs_sched{};
+  DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
+  int32_t work_nrhs = 0;
+};
+
+struct BatchMat {
+  int32_t n;
+  int64_t row_off, nnz_off;
+};
+
+struct Graph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+};
+
+struct sptrsv_ctx {
+  int dev = 0;
+  std::string last_error;
+  DArr<int32_t> d_err;     // latched error bits of solves
+  DArr<int32_t> d_aux;     // small scratch: counters, tickets, maxima
+  // original matrix (owned copy)
+  int32_t n = 0;
+  int64_t nnz = 0;
+  DArr<int32_t> rp, ci;
+  DArr<double> va;
+  Plan orig, rew;
+  // rewritten matrix in original numbering
+  bool has_rewrite = false;
+  DArr<int32_t> lp_rp, lp_ci, t_rp, t_ci, target;
+  DArr<double> lp_va, t_va;
+  sptrsv_rewrite_stats_t rstats{};
+  // batched matrices
+  std::vector<BatchMat> bmats;
+  std::vector<int32_t> b_nlev;
+  std::vector<int64_t> b_lvl_off;      // offset of each matrix's level_ptr
+  DArr<int32_t> b_rp, b_ci, b_lptr, b_perm, b_iperm, b_srp, b_sci;
+  DArr<double> b_sva, b_sdg;
+  DArr<int64_t> b_desc;                // per matrix: row_off, nnz_off, lvl_off, n, nlev (packed)
+  DArr<int32_t> b_order;               // matrices in processing order (longest first)
+  DArr<double> b_bp, b_xp;
+  int64_t b_total_n = 0, b_total_nnz = 0;
+  int32_t b_work_nrhs = 0;
+  std::vector<Graph> graphs;
+  // scan scratch
+  DArr<long long> scan_tmp;
+};
+
+// Status plumbing ------------------------------------------------------------
+sptrsv_status_t set_err(sptrsv_ctx *h, sptrsv_status_t st, const char *fmt, ...);
+#define HIPCHK(h, expr)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return set_err((h), e_ == hipErrorOutOfMemory ? SPTRSV_ERR_ALLOC : SPTRSV_ERR_HIP,     \
+                     "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+  } while (0)
+#define STCHK(expr)                          \
+  do {                                       \
+    sptrsv_status_t st_ = (expr);            \
+    if (st_ != SPTRSV_OK) return st_;        \
+  } while (0)
+
+// Launchers (k_analyze.hip) ----------------------------------------------------
+hipError_t launch_validate(int32_t n, int32_t nnz, const int32_t *rp, const int32_t *ci, const double *va, int *err,
+                           hipStream_t s);
+hipError_t launch_levels(int32_t n, const int32_t *rp, const int32_t *ci, int32_t *lev1, unsigned *ticket, int *err,
+                         hipStream_t s);
+hipError_t launch_max(const int32_t *a, int32_t n, int32_t *out, hipStream_t s);
+// exclusive scan of int64 values in place-compatible form: out may equal in
+size_t scan_scratch_elems(int64_t n);
+hipError_t launch_scan_i64(const long long *in, long long *out, int64_t n, long long *scratch, hipStream_t s);
+hipError_t launch_radix_by_key(int32_t *keys, int32_t *vals, int32_t *keys_tmp, int32_t *vals_tmp, int32_t n,
+                               int bits, int32_t *hist, long long *hist64, long long *scratch, hipStream_t s);
+size_t radix_hist_elems(int32_t n);
+hipError_t launch_level_ptr_from_sorted(const int32_t *sorted_keys, int32_t n, int32_t *level_ptr, int32_t nlev,
+                                        hipStream_t s);
+hipError_t launch_iota(int32_t *a, int32_t n, hipStream_t s);
+hipError_t launch_invert_perm(const int32_t *perm, int32_t n, int32_t *iperm, hipStream_t s);
+hipError_t launch_sub1(const int32_t *a, int32_t n, int32_t *out, hipStream_t s);
+hipError_t launch_count_off(const int32_t *perm, const int32_t *rp, int32_t n, long long *cnt, hipStream_t s);
+hipError_t launch_ptr_from_scan(const long long *ex, const long long *cnt, int32_t n, int32_t *ptr, int *err,
+                                hipStream_t s);
+hipError_t launch_fill_solve(int32_t n, const int32_t *perm, const int32_t *iperm, const int32_t *rp,
+                             const int32_t *ci, const double *va, const int32_t *srp, int32_t *sci, double *sva,
+                             double *sdg, hipStream_t s);
+hipError_t launch_fill_t(int32_t n, const int32_t *perm, const int32_t *iperm, const int32_t *trp,
+                         const int32_t *tci, const double *tva, const int32_t *strp, int32_t *stci, double *stva,
+                         hipStream_t s);
+hipError_t launch_level_stats(int32_t nlev, const int32_t *level_ptr, const int32_t *srp, int64_t *rows,
+                              int64_t *nnz, int64_t *cost, long long *total, hipStream_t s);
+
+// Launchers (k_solve.hip) ------------------------------------------------------
+hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
+                         hipStream_t s);
+hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
+                          hipStream_t s);
+int thin_lds_doubles();
+hipError_t launch_thin_run(int wg, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
+                           const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
+                           const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
+                           double *xp, int *err, hipStream_t s);
+hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
+                             const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
+                             const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
+                             double *xp, int *err, hipStream_t s);
+hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,
+                           const double *b, int64_t ldb, const double *x, int64_t ldx, unsigned long long *out,
+                           hipStream_t s);
+void solve_kernels_init();
+
+// Plan building (api.hip) --------------------------------------------------------
+sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                           const double *va, const int32_t *trp, const int32_t *tci, const double *tva,
+                           hipStream_t s);
+sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
+                           int64_t ldx, hipStream_t s);

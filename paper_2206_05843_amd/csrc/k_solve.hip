@@ -1,0 +1,333 @@
+// Solve kernels: level-by-level forward substitution (Sec. II.A, Algorithm 1)
+// over the level-ordered copy of L (or of the rewritten L' with the b-transform
+// T applied on the fly, Sec. II.B).
+//
+// Work vectors are permuted to level order and RHS-interleaved: entry (pos, c)
+// of bp/xp is at pos*nrhs + c, so the rows of one level are contiguous and one
+// row's right-hand sides share cache lines.
+//
+// Two schedules per level:
+//  * thin runs: consecutive narrow levels inside ONE workgroup; the levels are
+//    separated by workgroup barriers (no device-wide synchronisation). Values a
+//    run produces are kept in LDS as well, so later levels of the run read
+//    them from LDS; the LDS window restarts (after a full barrier that makes the
+//    global copies visible) when it is full.
+//  * wide levels: one launch over the device per level (kernel boundaries order
+//    the levels).
+#include "common.h"
+
+namespace {
+
+constexpr int kLdsBytes = 128 * 1024;
+constexpr int kLdsDoubles = kLdsBytes / 8;
+
+// Workgroup barrier that orders LDS only: global stores may still be in flight
+// (the global copy of x is only read across an LDS-window restart, which uses a
+// full barrier).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// x(pos, c) = (b'(pos, c) - sum_k L(pos,k) x(k,c)) / L(pos,pos), with
+// b' = b + T_off b when T is present. Columns < lds_base come from global
+// memory, columns >= lds_base from the LDS window.
+template <bool kUseLds, bool kOne>
+__device__ __forceinline__ double row_solve(int32_t pos, int32_t c, int32_t nrhs, const int32_t *__restrict__ srp,
+                                            const int32_t *__restrict__ sci, const double *__restrict__ sva,
+                                            const double *__restrict__ sdg, const int32_t *__restrict__ trp,
+                                            const int32_t *__restrict__ tci, const double *__restrict__ tva,
+                                            const double *__restrict__ bp, const double *xp, const double *lds,
+                                            int32_t lds_base) {
+  const int64_t nr = kOne ? 1 : nrhs;
+  double acc = bp[(int64_t)pos * nr + c];
+  if (trp) {
+    const int32_t tb = trp[pos], te = trp[pos + 1];
+    for (int32_t q = tb; q < te; ++q) acc += tva[q] * bp[(int64_t)tci[q] * nr + c];
+  }
+  const int32_t b = srp[pos], e = srp[pos + 1];
+  for (int32_t q = b; q < e; ++q) {
+    const int32_t k = sci[q];
+    double xv;
+    if (kUseLds && k >= lds_base)
+      xv = lds[(int64_t)(k - lds_base) * nr + c];
+    else
+      xv = xp[(int64_t)k * nr + c];
+    acc -= sva[q] * xv;
+  }
+  return acc / sdg[pos];
+}
+
+template <int WG, bool kOne>
+__global__ __launch_bounds__(WG) void k_thin_run(int32_t l0, int32_t l1, const int32_t *__restrict__ level_ptr,
+                                                 int32_t nrhs, const int32_t *__restrict__ srp,
+                                                 const int32_t *__restrict__ sci, const double *__restrict__ sva,
+                                                 const double *__restrict__ sdg, const int32_t *__restrict__ trp,
+                                                 const int32_t *__restrict__ tci, const double *__restrict__ tva,
+                                                 const double *__restrict__ bp, double *xp, int *err) {
+  extern __shared__ double lds[];
+  const int32_t nr = kOne ? 1 : nrhs;
+  const int32_t cap_rows = kLdsDoubles / nr;
+  int32_t base = level_ptr[l0];
+  int bits = 0;
+  int32_t pb = base;
+  for (int32_t l = l0; l < l1; ++l) {
+    const int32_t pe = level_ptr[l + 1];
+    if (pe - pb > cap_rows) {  // a level wider than the LDS window never runs here
+      if (threadIdx.x == 0) atomicOr(err, EB_ARG);
+      return;
+    }
+    if (pe - base > cap_rows) {
+      __syncthreads();  // global copies of the window become visible
+      base = pb;
+    }
+    const int32_t items = (pe - pb) * nr;
+    for (int32_t it = threadIdx.x; it < items; it += WG) {
+      const int32_t pos = kOne ? pb + it : pb + it / nr;
+      const int32_t c = kOne ? 0 : it - (pos - pb) * nr;
+      const double xv = row_solve<true, kOne>(pos, c, nr, srp, sci, sva, sdg, trp, tci, tva, bp, xp, lds, base);
+      if (!isfinite(xv)) bits |= EB_NONFINITE;
+      lds[(int64_t)(pos - base) * nr + c] = xv;
+      xp[(int64_t)pos * nr + c] = xv;
+    }
+    lds_barrier();
+    pb = pe;
+  }
+  if (bits) atomicOr(err, bits);
+}
+
+// One wide level, one item (row, rhs) per thread.
+template <bool kOne>
+__global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t *__restrict__ srp,
+                             const int32_t *__restrict__ sci, const double *__restrict__ sva,
+                             const double *__restrict__ sdg, const int32_t *__restrict__ trp,
+                             const int32_t *__restrict__ tci, const double *__restrict__ tva,
+                             const double *__restrict__ bp, double *xp, int *err) {
+  const int32_t nr = kOne ? 1 : nrhs;
+  const int64_t items = (int64_t)(pe - pb) * nr;
+  int bits = 0;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t pos = kOne ? pb + (int32_t)it : pb + (int32_t)(it / nr);
+    const int32_t c = kOne ? 0 : (int32_t)(it - (int64_t)(pos - pb) * nr);
+    const double xv = row_solve<false, kOne>(pos, c, nr, srp, sci, sva, sdg, trp, tci, tva, bp, xp, nullptr, 0);
+    if (!isfinite(xv)) bits |= EB_NONFINITE;
+    xp[(int64_t)pos * nr + c] = xv;
+  }
+  if (bits) atomicOr(err, bits);
+}
+
+// One wide level, single RHS, G lanes per row: lanes split the row's products
+// and combine them with a fixed butterfly, so the result is deterministic.
+template <int G>
+__global__ void k_wide_level_group(int32_t pb, int32_t pe, const int32_t *__restrict__ srp,
+                                   const int32_t *__restrict__ sci, const double *__restrict__ sva,
+                                   const double *__restrict__ sdg, const int32_t *__restrict__ trp,
+                                   const int32_t *__restrict__ tci, const double *__restrict__ tva,
+                                   const double *__restrict__ bp, double *xp, int *err) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x & (G - 1);
+  int bits = 0;
+  const int64_t rows = pe - pb;
+  for (int64_t rr = gid / G; rr < (rows + 0); rr += ((int64_t)gridDim.x * blockDim.x) / G) {
+    const int32_t pos = pb + (int32_t)rr;
+    double acc = 0.0;
+    if (trp) {
+      const int32_t tb = trp[pos], te = trp[pos + 1];
+      for (int32_t q = tb + sub; q < te; q += G) acc += tva[q] * bp[tci[q]];
+    }
+    const int32_t b = srp[pos], e = srp[pos + 1];
+    for (int32_t q = b + sub; q < e; q += G) acc -= sva[q] * xp[sci[q]];
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+    if (sub == 0) {
+      const double xv = (bp[pos] + acc) / sdg[pos];
+      if (!isfinite(xv)) bits |= EB_NONFINITE;
+      xp[pos] = xv;
+    }
+  }
+  if (bits) atomicOr(err, bits);
+}
+
+// b (column-major, original rows) -> bp (level order, RHS-interleaved). A tile
+// of 64 rows x up to 32 columns is staged in LDS so both sides are coalesced.
+__global__ void k_gather(int32_t n, int32_t nrhs, const double *__restrict__ b, int64_t ldb,
+                         const int32_t *__restrict__ iperm, double *bp) {
+  __shared__ double tile[64][33];
+  const int32_t r0 = blockIdx.x * 64;
+  for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
+    const int32_t nc = min(32, nrhs - c0);
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int c = idx / 64, rr = idx % 64;
+      if (r0 + rr < n) tile[rr][c] = b[(int64_t)(c0 + c) * ldb + r0 + rr];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int rr = idx / nc, c = idx % nc;
+      if (r0 + rr < n) bp[(int64_t)iperm[r0 + rr] * nrhs + c0 + c] = tile[rr][c];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_gather1(int32_t n, const double *__restrict__ b, const int32_t *__restrict__ iperm, double *bp) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    bp[iperm[r]] = b[r];
+}
+
+__global__ void k_scatter(int32_t n, int32_t nrhs, const double *__restrict__ xp, const int32_t *__restrict__ iperm,
+                          double *x, int64_t ldx) {
+  __shared__ double tile[64][33];
+  const int32_t r0 = blockIdx.x * 64;
+  for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
+    const int32_t nc = min(32, nrhs - c0);
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int rr = idx / nc, c = idx % nc;
+      if (r0 + rr < n) tile[rr][c] = xp[(int64_t)iperm[r0 + rr] * nrhs + c0 + c];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int c = idx / 64, rr = idx % 64;
+      if (r0 + rr < n) x[(int64_t)(c0 + c) * ldx + r0 + rr] = tile[rr][c];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_scatter1(int32_t n, const double *__restrict__ xp, const int32_t *__restrict__ iperm, double *x) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    x[r] = xp[iperm[r]];
+}
+
+// max_i |(L x - b)[i, c]| per column, original numbering; results as the bit
+// patterns of non-negative doubles (monotone as unsigned integers).
+__global__ void k_residual(int32_t n, int32_t nrhs, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ va, const double *__restrict__ b, int64_t ldb,
+                           const double *__restrict__ x, int64_t ldx, unsigned long long *out) {
+  for (int32_t c = 0; c < nrhs; ++c) {
+    double m = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+      double s = 0.0;
+      for (int32_t q = rp[r]; q < rp[r + 1]; ++q) s += va[q] * x[(int64_t)c * ldx + ci[q]];
+      const double d = fabs(s - b[(int64_t)c * ldb + r]);
+      m = (d > m || d != d) ? d : m;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(m, off, 64);
+      m = (o > m || o != o) ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out + c, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+inline int grid_for(int64_t items, int threads, int cap) {
+  int64_t g = (items + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+template <int WG, bool kOne>
+void set_lds_attr() {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_thin_run<WG, kOne>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+}
+
+}  // namespace
+
+int thin_lds_doubles() { return kLdsDoubles; }
+
+void solve_kernels_init() {
+  set_lds_attr<256, true>();
+  set_lds_attr<256, false>();
+  set_lds_attr<512, true>();
+  set_lds_attr<512, false>();
+  set_lds_attr<1024, true>();
+  set_lds_attr<1024, false>();
+}
+
+hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
+                         hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_gather1, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, b, iperm, bp);
+  else
+    hipLaunchKernelGGL(k_gather, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, b, ldb, iperm, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
+                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_scatter1, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, xp, iperm, x);
+  else
+    hipLaunchKernelGGL(k_scatter, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, xp, iperm, x, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_thin_run(int wg, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
+                           const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
+                           const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
+                           double *xp, int *err, hipStream_t s) {
+  const bool one = nrhs == 1;
+#define THIN(W)                                                                                                   \
+  if (one)                                                                                                        \
+    hipLaunchKernelGGL((k_thin_run<W, true>), dim3(1), dim3(W), kLdsBytes, s, l0, l1, level_ptr, nrhs, srp, sci, \
+                       sva, sdg, trp, tci, tva, bp, xp, err);                                                     \
+  else                                                                                                            \
+    hipLaunchKernelGGL((k_thin_run<W, false>), dim3(1), dim3(W), kLdsBytes, s, l0, l1, level_ptr, nrhs, srp,     \
+                       sci, sva, sdg, trp, tci, tva, bp, xp, err);
+  if (wg == 256) {
+    THIN(256)
+  } else if (wg == 1024) {
+    THIN(1024)
+  } else {
+    THIN(512)
+  }
+#undef THIN
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
+                             const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
+                             const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
+                             double *xp, int *err, hipStream_t s) {
+  const int64_t rows = pe - pb;
+  if (rows <= 0) return hipSuccess;
+  if (nrhs == 1 && lanes_per_row > 1) {
+    const int64_t items = rows * lanes_per_row;
+    const int g = grid_for(items, threads, 65536);
+#define GRP(G)                                                                                                   \
+  hipLaunchKernelGGL((k_wide_level_group<G>), dim3(g), dim3(threads), 0, s, pb, pe, srp, sci, sva, sdg, trp, tci, \
+                     tva, bp, xp, err);
+    switch (lanes_per_row) {
+      case 2: GRP(2) break;
+      case 4: GRP(4) break;
+      case 8: GRP(8) break;
+      case 16: GRP(16) break;
+      default: GRP(32) break;
+    }
+#undef GRP
+    return hipGetLastError();
+  }
+  const int64_t items = rows * nrhs;
+  const int g = grid_for(items, threads, 65536);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_wide_level<true>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, trp,
+                       tci, tva, bp, xp, err);
+  else
+    hipLaunchKernelGGL((k_wide_level<false>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, trp,
+                       tci, tva, bp, xp, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,
+                           const double *b, int64_t ldb, const double *x, int64_t ldx, unsigned long long *out,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, nrhs, rp, ci, va, b, ldb, x,
+                     ldx, out);
+  return hipGetLastError();
+}

@@ -1,0 +1,363 @@
+"""Python binding of libsptrsv.so (ctypes). Argument marshalling only: every
+step of the solve, the analysis and the rewrite runs in the library's HIP
+kernels. torch supplies device memory (CUDA tensors on ROCm) and the stream.
+
+Names mirror the C ABI in include/sptrsv.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
+
+ORIGINAL, REWRITTEN = 0, 1
+THIN_ROWS, THIN_COST = 0, 1
+MLP_NPARAM = 5313
+
+STATUS_NAMES = ["OK", "ARG", "STATE", "NOT_LOWER", "UNSORTED", "MISSING_DIAG", "ZERO_PIVOT", "NONFINITE",
+                "OVERFLOW", "ALLOC", "HIP", "TIMEOUT"]
+
+EXPORTS = [
+    "sptrsv_create", "sptrsv_destroy", "sptrsv_last_error", "sptrsv_status_name", "sptrsv_analyze",
+    "sptrsv_get_levels", "sptrsv_level_stats", "sptrsv_rewrite", "sptrsv_get_rewritten", "sptrsv_get_targets",
+    "sptrsv_solve", "sptrsv_prepare", "sptrsv_check", "sptrsv_set_schedule", "sptrsv_get_schedule",
+    "sptrsv_autotune", "sptrsv_graph_create", "sptrsv_graph_launch", "sptrsv_residual", "sptrsv_batch_analyze",
+    "sptrsv_batch_solve", "sptrsv_batch_solve_looped", "sptrsv_batch_levels", "sptrsv_plan_save",
+    "sptrsv_plan_load", "sptrsv_level_features", "sptrsv_mlp_forward", "sptrsv_mlp_backward", "sptrsv_mlp_adam",
+    "sptrsv_mlp_mask",
+]
+
+
+class SptrsvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        self.name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{self.name}: {msg}")
+
+
+class RewriteOpts(C.Structure):
+    _fields_ = [("thin_metric", C.c_int32), ("thin_threshold", C.c_double), ("fill_cap", C.c_double),
+                ("max_distance", C.c_int32), ("d_level_mask", C.c_void_p)]
+
+
+class RewriteStats(C.Structure):
+    _fields_ = [("nlev_before", C.c_int32), ("nlev_after", C.c_int32), ("rows_rewritten", C.c_int32),
+                ("max_distance", C.c_int32), ("target_steps", C.c_int32), ("nnz_L", C.c_int64),
+                ("nnz_Lp", C.c_int64), ("nnz_T", C.c_int64), ("total_cost_before", C.c_int64),
+                ("total_cost_after", C.c_int64), ("avg_level_cost_before", C.c_double),
+                ("avg_level_cost_after", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Schedule(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("thin_rows", C.c_int32), ("wg_threads", C.c_int32),
+                ("wide_threads", C.c_int32), ("lanes_per_row", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libsptrsv.so; fails loudly if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_05843_amd.build` "
+                           "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, f32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+    sig = {
+        "sptrsv_create": [C.POINTER(vp)],
+        "sptrsv_destroy": [vp],
+        "sptrsv_analyze": [vp, i32, i32, vp, vp, vp, vp, C.POINTER(i32)],
+        "sptrsv_get_levels": [vp, C.c_int, vp, vp, vp, vp],
+        "sptrsv_level_stats": [vp, C.c_int, vp, vp, vp, C.POINTER(i64), C.POINTER(dbl), vp],
+        "sptrsv_rewrite": [vp, C.POINTER(RewriteOpts), vp, C.POINTER(RewriteStats)],
+        "sptrsv_get_rewritten": [vp, vp, vp, vp, vp, vp, vp, vp],
+        "sptrsv_get_targets": [vp, vp, vp],
+        "sptrsv_solve": [vp, C.c_int, i32, vp, i64, vp, i64, vp],
+        "sptrsv_prepare": [vp, C.c_int, i32, vp],
+        "sptrsv_check": [vp, vp],
+        "sptrsv_set_schedule": [vp, C.c_int, C.POINTER(Schedule)],
+        "sptrsv_get_schedule": [vp, C.c_int, C.POINTER(Schedule)],
+        "sptrsv_autotune": [vp, C.c_int, i32, vp, C.POINTER(f32)],
+        "sptrsv_graph_create": [vp, C.c_int, i32, vp, i64, vp, i64, vp, C.POINTER(i32)],
+        "sptrsv_graph_launch": [vp, i32, vp],
+        "sptrsv_residual": [vp, i32, vp, i64, vp, i64, C.POINTER(dbl), vp],
+        "sptrsv_batch_analyze": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
+        "sptrsv_batch_solve": [vp, i32, vp, vp, vp],
+        "sptrsv_batch_solve_looped": [vp, i32, vp, vp, vp],
+        "sptrsv_batch_levels": [vp, i32, C.POINTER(i32), vp, vp, vp],
+        "sptrsv_plan_save": [vp, C.c_char_p],
+        "sptrsv_plan_load": [vp, C.c_char_p],
+        "sptrsv_level_features": [vp, vp, vp],
+        "sptrsv_mlp_forward": [vp, vp, i32, vp, vp],
+        "sptrsv_mlp_backward": [vp, vp, vp, vp, i32, vp, vp, vp],
+        "sptrsv_mlp_adam": [vp, vp, vp, vp, i32, f32, vp],
+        "sptrsv_mlp_mask": [vp, i32, f32, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.sptrsv_last_error.argtypes = [vp]
+    L.sptrsv_last_error.restype = C.c_char_p
+    L.sptrsv_status_name.argtypes = [C.c_int]
+    L.sptrsv_status_name.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda, "device tensor expected"
+    return t.data_ptr()
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(cond, msg):
+    if not cond:
+        raise ValueError(msg)
+
+
+def _check_free(st: int, msg: str = ""):
+    if st != 0:
+        raise SptrsvError(st, msg)
+
+
+def mlp_forward(params, feat, prob=None):
+    B = feat.shape[0]
+    prob = prob if prob is not None else torch.empty(B, dtype=torch.float32, device=feat.device)
+    _check_free(lib().sptrsv_mlp_forward(_ptr(params), _ptr(feat), B, _ptr(prob), _stream()), "mlp_forward")
+    return prob
+
+
+def mlp_backward(params, feat, label, weight=None):
+    B = feat.shape[0]
+    grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=feat.device)
+    loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+    _check_free(lib().sptrsv_mlp_backward(_ptr(params), _ptr(feat), _ptr(label), _ptr(weight), B, _ptr(grad),
+                                          _ptr(loss), _stream()), "mlp_backward")
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, step: int, lr: float):
+    _check_free(lib().sptrsv_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, _stream()), "mlp_adam")
+
+
+def mlp_mask(prob, threshold: float = 0.5):
+    mask = torch.empty(prob.shape[0], dtype=torch.uint8, device=prob.device)
+    _check_free(lib().sptrsv_mlp_mask(_ptr(prob), prob.shape[0], threshold, _ptr(mask), _stream()), "mlp_mask")
+    return mask
+
+
+class Handle:
+    """One analysed matrix (plus its rewrite and batched matrices)."""
+
+    def __init__(self):
+        self._L = lib()
+        h = C.c_void_p()
+        st = self._L.sptrsv_create(C.byref(h))
+        if st != 0:
+            raise SptrsvError(st, "sptrsv_create failed")
+        self._h = h
+        self.n = 0
+        self.nlev = 0
+        self.rstats = None
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sptrsv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != 0:
+            raise SptrsvError(st, self._L.sptrsv_last_error(self._h).decode())
+
+    # ------------------------------------------------------------------ analysis
+    def analyze(self, row_ptr, col, val) -> int:
+        _need(row_ptr.dtype == torch.int32 and col.dtype == torch.int32 and val.dtype == torch.float64,
+              "int32 row_ptr/col and float64 val expected")
+        n = row_ptr.numel() - 1
+        nnz = col.numel()
+        nl = C.c_int32(0)
+        self._check(self._L.sptrsv_analyze(self._h, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val), _stream(),
+                                           C.byref(nl)))
+        self.n, self.nlev, self.rstats = n, nl.value, None
+        return nl.value
+
+    def levels(self, which=ORIGINAL):
+        nlev = self.nlev if which == ORIGINAL else self.rstats["nlev_after"]
+        dev = torch.device("cuda")
+        lp = torch.empty(nlev + 1, dtype=torch.int32, device=dev)
+        lr = torch.empty(self.n, dtype=torch.int32, device=dev)
+        rl = torch.empty(self.n, dtype=torch.int32, device=dev)
+        self._check(self._L.sptrsv_get_levels(self._h, which, _ptr(lp), _ptr(lr), _ptr(rl), _stream()))
+        return lp, lr, rl
+
+    def level_stats(self, which=ORIGINAL):
+        nlev = self.nlev if which == ORIGINAL else self.rstats["nlev_after"]
+        dev = torch.device("cuda")
+        rows, nnz, cost = (torch.empty(nlev, dtype=torch.int64, device=dev) for _ in range(3))
+        tot, avg = C.c_int64(0), C.c_double(0)
+        self._check(self._L.sptrsv_level_stats(self._h, which, _ptr(rows), _ptr(nnz), _ptr(cost), C.byref(tot),
+                                               C.byref(avg), _stream()))
+        return dict(rows=rows, nnz=nnz, cost=cost, total=tot.value, avg=avg.value)
+
+    # ------------------------------------------------------------------- rewrite
+    def rewrite(self, thin_metric=THIN_ROWS, thin_threshold=32.0, fill_cap=4.0, max_distance=0, mask=None):
+        o = RewriteOpts(thin_metric, float(thin_threshold), float(fill_cap), int(max_distance),
+                        _ptr(mask) if mask is not None else None)
+        if mask is not None:
+            _need(mask.dtype == torch.uint8 and mask.numel() >= self.nlev, "uint8 mask of nlev entries expected")
+        st = RewriteStats()
+        self._check(self._L.sptrsv_rewrite(self._h, C.byref(o), _stream(), C.byref(st)))
+        self.rstats = st.as_dict()
+        return self.rstats
+
+    def rewritten(self):
+        s = self.rstats
+        dev = torch.device("cuda")
+        out = dict(lp_ptr=torch.empty(self.n + 1, dtype=torch.int32, device=dev),
+                   lp_col=torch.empty(s["nnz_Lp"], dtype=torch.int32, device=dev),
+                   lp_val=torch.empty(s["nnz_Lp"], dtype=torch.float64, device=dev),
+                   t_ptr=torch.empty(self.n + 1, dtype=torch.int32, device=dev),
+                   t_col=torch.empty(s["nnz_T"], dtype=torch.int32, device=dev),
+                   t_val=torch.empty(s["nnz_T"], dtype=torch.float64, device=dev))
+        self._check(self._L.sptrsv_get_rewritten(self._h, *[_ptr(out[k]) for k in
+                                                            ["lp_ptr", "lp_col", "lp_val", "t_ptr", "t_col",
+                                                             "t_val"]], _stream()))
+        return out
+
+    def targets(self):
+        t = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        self._check(self._L.sptrsv_get_targets(self._h, _ptr(t), _stream()))
+        return t
+
+    # --------------------------------------------------------------------- solve
+    def solve(self, b, which=ORIGINAL, x=None):
+        """b: float64 device tensor of shape (n,) or (nrhs, n) (column c = b[c])."""
+        _need(b.dtype == torch.float64 and b.is_cuda, "float64 device tensor expected")
+        bb = b if b.dim() == 2 else b.view(1, -1)
+        _need(bb.shape[1] == self.n and bb.stride(1) == 1, "b must be (nrhs, n) with unit row stride")
+        nrhs = bb.shape[0]
+        ldb = bb.stride(0) if nrhs > 1 else self.n
+        if x is None:
+            x = torch.empty_like(bb)
+        xx = x if x.dim() == 2 else x.view(1, -1)
+        ldx = xx.stride(0) if nrhs > 1 else self.n
+        self._check(self._L.sptrsv_solve(self._h, which, nrhs, _ptr(bb), ldb, _ptr(xx), ldx, _stream()))
+        return x if b.dim() == 2 else x.view(-1)
+
+    def prepare(self, which=ORIGINAL, nrhs=1):
+        self._check(self._L.sptrsv_prepare(self._h, which, nrhs, _stream()))
+
+    def check(self):
+        self._check(self._L.sptrsv_check(self._h, _stream()))
+
+    def residual(self, b, x):
+        bb = b if b.dim() == 2 else b.view(1, -1)
+        xx = x if x.dim() == 2 else x.view(1, -1)
+        nrhs = bb.shape[0]
+        out = (C.c_double * nrhs)()
+        self._check(self._L.sptrsv_residual(self._h, nrhs, _ptr(bb), bb.stride(0) if nrhs > 1 else self.n,
+                                            _ptr(xx), xx.stride(0) if nrhs > 1 else self.n, out, _stream()))
+        return list(out)
+
+    def set_schedule(self, which=ORIGINAL, mode=0, thin_rows=4096, wg_threads=512, wide_threads=256,
+                     lanes_per_row=1):
+        s = Schedule(mode, thin_rows, wg_threads, wide_threads, lanes_per_row)
+        self._check(self._L.sptrsv_set_schedule(self._h, which, C.byref(s)))
+
+    def get_schedule(self, which=ORIGINAL):
+        s = Schedule()
+        self._check(self._L.sptrsv_get_schedule(self._h, which, C.byref(s)))
+        return s.as_dict()
+
+    def autotune(self, which=ORIGINAL, nrhs=1) -> float:
+        ms = C.c_float(0)
+        self._check(self._L.sptrsv_autotune(self._h, which, nrhs, _stream(), C.byref(ms)))
+        return ms.value
+
+    def graph_create(self, b, x, which=ORIGINAL) -> int:
+        bb = b if b.dim() == 2 else b.view(1, -1)
+        xx = x if x.dim() == 2 else x.view(1, -1)
+        nrhs = bb.shape[0]
+        gid = C.c_int32(0)
+        self._check(self._L.sptrsv_graph_create(self._h, which, nrhs, _ptr(bb), bb.stride(0) if nrhs > 1 else self.n,
+                                                _ptr(xx), xx.stride(0) if nrhs > 1 else self.n, _stream(),
+                                                C.byref(gid)))
+        self._keep.append((b, x))
+        return gid.value
+
+    def graph_launch(self, gid: int):
+        self._check(self._L.sptrsv_graph_launch(self._h, gid, _stream()))
+
+    # ------------------------------------------------------------------- batched
+    def batch_analyze(self, ns, row_ptr_cat, col_cat, val_cat):
+        """ns: list of sizes; *_cat: concatenated device arrays (local indices;
+        row pointers of matrix i occupy n_i+1 entries)."""
+        import numpy as np
+        ns = np.asarray(ns, np.int32)
+        row_off = np.zeros(len(ns), np.int64)
+        row_off[1:] = np.cumsum(ns.astype(np.int64))[:-1]
+        self._bn = ns
+        self._brow_off = row_off
+        nnz_off = np.zeros(len(ns), np.int64)
+        rp_host = row_ptr_cat.cpu().numpy()
+        acc = 0
+        for i in range(len(ns)):
+            nnz_off[i] = acc
+            acc += int(rp_host[row_off[i] + i + ns[i]])
+        self._check(self._L.sptrsv_batch_analyze(self._h, len(ns), ns.ctypes.data, row_off.ctypes.data,
+                                                 nnz_off.ctypes.data, _ptr(row_ptr_cat), _ptr(col_cat),
+                                                 _ptr(val_cat), _stream()))
+        return nnz_off
+
+    def batch_solve(self, b_cat, x_cat, nrhs: int, looped: bool = False):
+        f = self._L.sptrsv_batch_solve_looped if looped else self._L.sptrsv_batch_solve
+        self._check(f(self._h, nrhs, _ptr(b_cat), _ptr(x_cat), _stream()))
+        return x_cat
+
+    def batch_levels(self, i: int):
+        nl = C.c_int32(0)
+        self._check(self._L.sptrsv_batch_levels(self._h, i, C.byref(nl), None, None, _stream()))
+        n = int(self._bn[i])
+        lp = torch.empty(nl.value + 1, dtype=torch.int32, device="cuda")
+        lr = torch.empty(n, dtype=torch.int32, device="cuda")
+        self._check(self._L.sptrsv_batch_levels(self._h, i, C.byref(nl), _ptr(lp), _ptr(lr), _stream()))
+        return lp, lr
+
+    # ---------------------------------------------------------------- plan files
+    def plan_save(self, path: str):
+        self._check(self._L.sptrsv_plan_save(self._h, path.encode()))
+
+    def plan_load(self, path: str):
+        self._check(self._L.sptrsv_plan_load(self._h, path.encode()))
+
+    # ------------------------------------------------------------ learned policy
+    def level_features(self):
+        f = torch.empty((self.nlev, 16), dtype=torch.float32, device="cuda")
+        self._check(self._L.sptrsv_level_features(self._h, _ptr(f), _stream()))
+        return f

@@ -1,0 +1,213 @@
+"""GPU parity: sptrsv_analyze (levels, statistics, validation) and
+sptrsv_solve against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from tests.gpu_util import dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+sp = pytest.importorskip("paper_2206_05843_amd")
+
+TOL = 1e-10  # relative error bound on x (normwise, per RHS column)
+
+
+def _matrices():
+    yield "diag", gen.diagonal(100, 1)
+    yield "bidiag", gen.bidiagonal(700, 2)
+    yield "one", gen.diagonal(1, 3)
+    yield "cfg0", gen.config_matrix(0)[0]
+    yield "cfg1_small", gen.config_matrix(1, "small")[0]
+    yield "cfg2_small", gen.config_matrix(2, "small")[0]
+    yield "cfg4_small", gen.config_matrix(4, "small")[0]
+    yield "window_ragged", gen.window_random(5003, 9, window=200, draws=7)
+
+
+MATS = list(_matrices())
+
+
+@pytest.fixture(scope="module")
+def handles():
+    out = {}
+    for name, m in MATS:
+        h = sp.Handle()
+        nlev = h.analyze(*dev(m))
+        out[name] = (m, h, nlev)
+    return out
+
+
+@pytest.mark.parametrize("name", [n for n, _ in MATS])
+def test_levels_bit_exact(handles, name):
+    m, h, nlev = handles[name]
+    lv = oracle.levels(m)
+    assert nlev == lv.nlev
+    lp, lr, rl = h.levels()
+    assert np.array_equal(lp.cpu().numpy(), lv.level_ptr)
+    assert np.array_equal(lr.cpu().numpy(), lv.level_rows)
+    assert np.array_equal(rl.cpu().numpy(), lv.row_level)
+
+
+@pytest.mark.parametrize("name", [n for n, _ in MATS])
+def test_level_stats_exact(handles, name):
+    m, h, _ = handles[name]
+    c = oracle.level_costs(m)
+    st = h.level_stats()
+    assert np.array_equal(st["rows"].cpu().numpy(), c.rows)
+    assert np.array_equal(st["nnz"].cpu().numpy(), c.nnz)
+    assert np.array_equal(st["cost"].cpu().numpy(), c.cost)
+    assert st["total"] == c.total and st["avg"] == c.avg
+
+
+SCHEDS = [dict(mode=0), dict(mode=1), dict(mode=2), dict(mode=0, thin_rows=64, wg_threads=256),
+          dict(mode=1, lanes_per_row=4), dict(mode=0, thin_rows=300, wg_threads=1024, lanes_per_row=8)]
+
+
+@pytest.mark.parametrize("name", [n for n, _ in MATS])
+@pytest.mark.parametrize("si", range(len(SCHEDS)))
+@pytest.mark.parametrize("nrhs", [1, 3, 40])
+def test_solve_parity(handles, name, si, nrhs):
+    m, h, _ = handles[name]
+    h.set_schedule(**SCHEDS[si])
+    b = gen.rhs(m, nrhs)
+    xr = oracle.solve(m, b)
+    x = h.solve(to_dev(b))
+    h.check()
+    assert oracle.relerr(x.cpu().numpy(), xr) <= TOL
+    h.set_schedule()
+
+
+def test_solve_deterministic(handles):
+    m, h, _ = handles["cfg2_small"]
+    b = to_dev(gen.rhs(m, 2))
+    x1 = h.solve(b).clone()
+    x2 = h.solve(b)
+    assert torch.equal(x1, x2)
+
+
+def test_ones_solution(handles):
+    m, h, _ = handles["cfg1_small"]
+    b = m.to_scipy() @ np.ones(m.n)
+    x = h.solve(to_dev(b))
+    assert float((x - 1).abs().max()) < 1e-12
+
+
+def test_strided_ld(handles):
+    m, h, _ = handles["cfg0"]
+    nrhs, ld = 3, m.n + 17
+    bb = np.zeros((nrhs, ld))
+    bb[:, :m.n] = gen.rhs(m, nrhs)
+    xr = oracle.solve(m, bb[:, :m.n])
+    B = to_dev(bb)
+    X = torch.full((nrhs, ld), 7.0, dtype=torch.float64, device="cuda")
+    h.solve(B[:, :m.n], x=X[:, :m.n])
+    assert oracle.relerr(X[:, :m.n].cpu().numpy(), xr) <= TOL
+    assert torch.all(X[:, m.n:] == 7.0)
+
+
+def _csr(n, rows):
+    rp, ci, v = [0], [], []
+    for r in rows:
+        for c, x in r:
+            ci.append(c)
+            v.append(x)
+        rp.append(len(ci))
+    return gen.Csr(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(v, np.float64), "t")
+
+
+BAD = [
+    [[(0, 2.0)], [(1, 3.0), (0, 1.0)]],
+    [[(0, 2.0)], [(0, 1.0), (0, 1.0), (1, 3.0)]],
+    [[(0, 2.0), (1, 1.0)], [(1, 3.0)]],
+    [[(0, 2.0)], [(0, 1.0)]],
+    [[(0, 0.0)], [(0, 1.0), (1, 3.0)]],
+    [[(0, 2.0)], [(0, float("nan")), (1, 3.0)]],
+    [[(0, 2.0)], [(1, 3.0), (0, 1.0)], [(3, 1.0), (2, 1.0)]],
+]
+
+
+@pytest.mark.parametrize("rows", BAD)
+def test_validation_matches_oracle(rows):
+    m = _csr(len(rows), rows)
+    expect = oracle.validate(m)
+    h = sp.Handle()
+    with pytest.raises(sp.SptrsvError) as ei:
+        h.analyze(*dev(m))
+    assert ei.value.name == expect
+
+
+def test_bad_row_ptr():
+    m = gen.window_random(50, 1)
+    rp = m.row_ptr.copy()
+    rp[10], rp[11] = rp[11], rp[10]
+    h = sp.Handle()
+    with pytest.raises(sp.SptrsvError) as ei:
+        h.analyze(to_dev(rp), to_dev(m.col), to_dev(m.val))
+    assert ei.value.name == "ARG" == oracle.validate(gen.Csr(m.n, rp, m.col, m.val))
+
+
+def test_state_and_arg_errors(handles):
+    m, h, _ = handles["cfg0"]
+    b = to_dev(gen.rhs(m, 1)[0])
+    with pytest.raises(sp.SptrsvError) as ei:
+        h.solve(b, which=sp.REWRITTEN)
+    assert ei.value.name == "STATE"
+    with pytest.raises(sp.SptrsvError) as ei:
+        h.solve(b, x=b)  # aliasing
+    assert ei.value.name == "ARG"
+
+
+def test_nonfinite_latched(handles):
+    m, h, _ = handles["cfg0"]
+    b = gen.rhs(m, 1)[0]
+    b[17] = np.nan
+    h.solve(to_dev(b))
+    with pytest.raises(sp.SptrsvError) as ei:
+        h.check()
+    assert ei.value.name == "NONFINITE"
+    h.check()  # cleared
+
+
+def test_residual(handles):
+    m, h, _ = handles["cfg4_small"]
+    b = to_dev(gen.rhs(m, 2))
+    x = h.solve(b)
+    r = h.residual(b, x)
+    assert max(r) < 1e-12
+
+
+def test_graph_replays(handles):
+    m, h, _ = handles["cfg1_small"]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = to_dev(gen.rhs(m, 1))
+        x = torch.zeros_like(b)
+        gid = h.graph_create(b, x)
+        xr = oracle.solve(m, b.cpu().numpy())
+        for rep in range(3):
+            x.zero_()
+            h.graph_launch(gid)
+            torch.cuda.synchronize()
+            assert oracle.relerr(x.cpu().numpy(), xr) <= TOL
+            b2 = b * 2.0  # eager work between replays
+            torch.cuda.synchronize()
+            del b2
+
+
+def test_autotune_keeps_parity(handles):
+    m, h, _ = handles["cfg2_small"]
+    ms = h.autotune(nrhs=1)
+    assert ms > 0
+    b = gen.rhs(m, 1)
+    x = h.solve(to_dev(b))
+    assert oracle.relerr(x.cpu().numpy(), oracle.solve(m, b)) <= TOL
+
+
+def test_empty_matrix():
+    h = sp.Handle()
+    z = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nlev = h.analyze(z, torch.zeros(0, dtype=torch.int32, device="cuda"),
+                     torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert nlev == 0

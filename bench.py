@@ -1,0 +1,251 @@
+"""Benchmark: SpTRSV solves/s and HBM GB/s, rewritten vs plain level-set.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
+
+Workload (default): the lower factor of the 1000x1000 2D 5-point stencil
+(pattern only, diagonally dominant random values) followed by a 20,000-row
+near-serial chain; n = 1,020,000, nnz = 3,078,000, one right-hand side, FP64.
+Variants on the same matrix and right-hand side, each autotuned first:
+  plain    level-set solve of L
+  naive    L' after the naive rewrite (levels with < 32 rows, fill cap 4x)
+  learned  L' after the rewrite with levels chosen by the trained policy
+A step is one solve of the headline variant (learned if a trained policy is
+available, else naive). Every variant is checked against the CPU oracle
+(relative error <= 1e-10) before it is timed; rewriting and tuning are
+preprocessing and are reported separately.
+
+Prints ONE JSON line. Inputs are resident in HBM when the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SpTRSV solves/s & HBM GB/s: learned-rewrite vs plain level-set, relerr<=1e-10"
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-10
+
+WORKLOADS = {
+    0: "window-64 random lower CSR, n=2,000, up to 5 off-diagonals/row, nrhs=1",
+    1: "2D 1000x1000 5-point lower factor + 20,000-row chain, n=1,020,000, nnz=3,078,000, nrhs=1",
+    2: "power-law (Zipf 1.2 in-degree) lower CSR, n=4,000,000, mean 8 off-diagonals/row, nrhs=1",
+    4: "3D 200^3 7-point lower factor + 5,000-row tail, n=8,005,000, nnz=31,900,000, nrhs=32",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes(n, nnz, nlev, nrhs, nnz_t=0, rewritten=False):
+    """Compulsory traffic of one solve: 12 B per nonzero (value + column),
+    8 B per row (row pointer + level row map), 4 B per level pointer, 16 B per
+    row and right-hand side (read b, write x); a rewritten solve adds T's
+    nonzeros and its row pointers."""
+    if not rewritten:
+        return 12.0 * nnz + 8.0 * n + 4.0 * (nlev + 1) + 16.0 * n * nrhs
+    return 12.0 * (nnz + nnz_t) + 12.0 * n + 4.0 * (nlev + 1) + 16.0 * n * nrhs
+
+
+def source_hash():
+    h = hashlib.sha256()
+    p = os.path.join(ROOT, "paper_2206_05843_amd", "csrc", "k_solve.hip")
+    with open(p, "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload_key):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
+    were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(p) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(f"{kernel}:{workload_key}")
+    if not e or e.get("source_hash") != source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=1, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-learned", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the solve of one matrix is not sharded "
+                                   "across GPUs (see DESIGN.md, multi-GPU section)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import oracle
+    import paper_2206_05843_amd as sp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    m, nrhs = gen.config_matrix(args.config)
+    b_np = gen.rhs(m, nrhs)
+    log(f"[bench] generated n={m.n} nnz={m.nnz} nrhs={nrhs} in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    x_ref = oracle.solve(m, b_np)
+    t_oracle_one = time.perf_counter() - t0
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (m.row_ptr, m.col, m.val))
+    b = torch.from_numpy(b_np).to(dev)
+    if nrhs == 1:
+        b = b.view(-1)
+
+    variants = {}
+
+    def setup(name, mask_fn=None, rewrite=True):
+        h = sp.Handle()
+        t = time.perf_counter()
+        nlev = h.analyze(rp, ci, va)
+        which = sp.ORIGINAL
+        info = dict(nlev=nlev, nnz=m.nnz, nnz_t=0)
+        if rewrite:
+            mask = mask_fn(h) if mask_fn else None
+            st = h.rewrite(sp.THIN_ROWS, 32, 4.0, 0, mask)
+            which = sp.REWRITTEN
+            info.update(nlev=st["nlev_after"], nnz=st["nnz_Lp"], nnz_t=st["nnz_T"], rows_rewritten=st["rows_rewritten"],
+                        nlev_before=st["nlev_before"], max_distance=st["max_distance"])
+        torch.cuda.synchronize()
+        info["preprocess_s"] = time.perf_counter() - t
+        t = time.perf_counter()
+        info["tuned_ms"] = h.autotune(which, nrhs)
+        info["schedule"] = h.get_schedule(which)
+        info["autotune_s"] = time.perf_counter() - t
+        x = h.solve(b, which)
+        h.check()
+        info["relerr"] = oracle.relerr(x.view(nrhs, -1).cpu().numpy(), x_ref)
+        if not info["relerr"] <= TOL:
+            raise SystemExit(f"[bench] variant {name} failed parity: relerr={info['relerr']:.3e}")
+        info["bytes"] = alg_bytes(m.n, info["nnz"], info["nlev"], nrhs, info["nnz_t"], rewrite)
+        variants[name] = (h, which, info)
+        log(f"[bench] {name}: nlev={info['nlev']} relerr={info['relerr']:.2e} pre={info['preprocess_s']:.2f}s "
+            f"tuned={info['tuned_ms']:.3f}ms")
+
+    setup("plain", rewrite=False)
+    try:
+        setup("naive")
+    except sp.SptrsvError as e:
+        log(f"[bench] naive rewrite unavailable: {e}")
+    if not args.no_learned:
+        try:
+            from paper_2206_05843_amd import policy
+            pol = policy.load_default()
+            if pol is not None:
+                setup("learned", mask_fn=pol.mask_for)
+        except (ImportError, sp.SptrsvError, FileNotFoundError) as e:
+            log(f"[bench] learned policy unavailable: {e}")
+
+    def timed(name, steps, warmup, profile=False):
+        h, which, _ = variants[name]
+        x = torch.empty_like(b)
+        for _ in range(warmup):
+            h.solve(b, which, x)
+        torch.cuda.synchronize()
+        if profile:
+            h.profile_start()
+        t = time.perf_counter()
+        for _ in range(steps):
+            h.solve(b, which, x)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        prof = h.profile_stop() if profile else None
+        h.check()
+        return el, prof
+
+    headline = "learned" if "learned" in variants else ("naive" if "naive" in variants else "plain")
+    for name in variants:
+        if name == headline:
+            continue
+        el, _ = timed(name, max(5, args.steps // 2), args.warmup)
+        variants[name][2]["ms"] = el * 1e3 / max(5, args.steps // 2)
+    el, prof = timed(headline, args.steps, args.warmup, profile=True)
+    variants[headline][2]["ms"] = el * 1e3 / args.steps
+    ms = el * 1e3 / args.steps
+
+    # roofline of the dominant kernel class, from the live profile
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    dp = prof[dom]
+    per_launch_ms = dp["ms"] / max(1, dp["launches"])
+    bytes_per_launch = dp["bytes"] / max(1, dp["launches"])
+    achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    kname = {"thin_run": "k_thin_run", "wide_level": "k_wide_level", "gather": "k_gather",
+             "scatter": "k_scatter"}[dom]
+    traffic = load_traffic(kname, f"config{args.config}_{headline}")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic, "kernel": kname,
+                "launches": dp["launches"], "avg_launch_ms": round(per_launch_ms, 5),
+                "alg_bytes_per_launch": bytes_per_launch,
+                "kernel_share_of_step": round(sum(v["ms"] for v in prof.values()) and dp["ms"] /
+                                              sum(v["ms"] for v in prof.values()), 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        reps = max(1, min(2000, int(12.0 / max(t_oracle_one, 1e-6))))
+        t = time.perf_counter()
+        for _ in range(reps):
+            oracle.solve(m, b_np)
+        el_c = time.perf_counter() - t
+        cpu = {"value": round(reps / el_c, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full solves of the same matrix and right-hand side(s) by the serial FP64 oracle "
+                         f"({el_c:.1f}s); host nproc={os.cpu_count()}"}
+
+    out_var = {}
+    for name, (_, _, info) in variants.items():
+        gbs = info["bytes"] / (info["ms"] * 1e-3) / 1e9
+        out_var[name] = {"solves_per_s": round(1e3 / info["ms"], 3), "ms": round(info["ms"], 5),
+                         "alg_GBps": round(gbs, 3), "hbm_frac": round(gbs / HBM_PEAK_GBS, 6), "nlev": info["nlev"],
+                         "nnz": info["nnz"], "nnz_T": info["nnz_t"], "relerr": info["relerr"],
+                         "preprocess_s": round(info["preprocess_s"], 3), "autotune_s": round(info["autotune_s"], 3),
+                         "schedule": info["schedule"],
+                         "us_per_level": round(info["ms"] * 1e3 / max(1, info["nlev"]), 4)}
+        for k in ("rows_rewritten", "max_distance"):
+            if k in info:
+                out_var[name][k] = info[k]
+    res = {
+        "metric": METRIC,
+        "value": round(1e3 / ms, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator of the workload's structure; no dataset)",
+        "config": {"workload": WORKLOADS[args.config], "variant": headline, "nrhs": nrhs, "n": m.n, "nnz": m.nnz,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": out_var,
+        "speedup_vs_plain": round(out_var["plain"]["ms"] / ms, 4) if "plain" in out_var else None,
+        "kernel_profile": prof,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

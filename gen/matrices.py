@@ -189,8 +189,9 @@ def batch_window(nmat: int = 512, seed: int = 3, nmin: int = 1000, nmax: int = 5
 def rhs(m: Csr, nrhs: int = 1) -> np.ndarray:
     """U(-1,1) right-hand sides continuing the matrix's generator; returned
     column-major as an array of shape (nrhs, n) (column c is ``b[c]``)."""
-    rng = np.random.default_rng()
-    rng.bit_generator.state = m.rng_state
+    rng = np.random.default_rng(12345)
+    if m.rng_state is not None:  # hand-built fixtures carry no generator state
+        rng.bit_generator.state = m.rng_state
     return rng.uniform(-1.0, 1.0, size=(nrhs, m.n))
 
 

@@ -187,6 +187,19 @@ sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, 
                                     double *d_x, int64_t ldx, hipStream_t s, int32_t *graph_id);
 sptrsv_status_t sptrsv_graph_launch(sptrsv_handle_t h, int32_t graph_id, hipStream_t s);
 
+/* Live kernel profile of solves: enable = 1 clears the counters and starts
+ * bracketing every solve launch on its stream with HIP events (at most 65536
+ * launches are recorded); enable = 0 stops, synchronises s and fills out[4]
+ * for the launch classes {gather b, thin runs, wide levels, scatter x}: number
+ * of launches, summed device time (ms), and algorithmic bytes (index, value,
+ * diagonal and right-hand-side bytes the launches must move at least once). */
+typedef struct {
+  int64_t launches;
+  double ms;
+  double bytes;
+} sptrsv_kernel_profile_t;
+sptrsv_status_t sptrsv_profile(sptrsv_handle_t h, int enable, sptrsv_kernel_profile_t *out, hipStream_t s);
+
 /* Residual check: h_out[c] = max_i |(L x - b)[i,c]| for the ORIGINAL L, host
  * double[nrhs]. Synchronous. */
 sptrsv_status_t sptrsv_residual(sptrsv_handle_t h, int32_t nrhs, const double *d_b, int64_t ldb, const double *d_x,

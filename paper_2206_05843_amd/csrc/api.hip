@@ -78,21 +78,58 @@ sptrsv_schedule_t effective_sched(const Plan &P, int32_t nrhs) {
   return P.sched;
 }
 
-void make_runs(Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc) {
+// LDS bytes of a thin-run window holding `rows` rows, `ents` off-diagonals and
+// `nl` levels (must match the layout in k_thin_run).
+int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
+  return rows * (8 * (int64_t)nrhs + 16) + ents * 12 + 4 * (nl + 1);
+}
+
+sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc) {
   P.runs.clear();
-  const int32_t cap_rows = thin_lds_doubles() / nrhs;
-  int64_t thr = sc.thin_rows;
+  P.h_win.clear();
+  const int64_t cap = thin_win_bytes();
+  const int64_t thr = sc.thin_rows;
+  auto rows_of = [&](int32_t l) -> int64_t { return P.h_level_ptr[l + 1] - P.h_level_ptr[l]; };
+  auto offd_of = [&](int32_t l) -> int64_t { return P.h_lv_nnz[l] - rows_of(l); };
   for (int32_t l = 0; l < P.nlev; ++l) {
-    const int32_t rows = P.h_level_ptr[l + 1] - P.h_level_ptr[l];
+    const int64_t rows = rows_of(l);
     bool thin = sc.mode == 2 || (sc.mode == 0 && rows <= thr);
-    if (rows > cap_rows) thin = false;
+    if (win_bytes(rows, offd_of(l), 1, nrhs) > cap) thin = false;  // must fit one window alone
     if (thin && !P.runs.empty() && P.runs.back().thin && P.runs.back().l1 == l)
       P.runs.back().l1 = l + 1;
     else
       P.runs.push_back(Run{l, l + 1, thin});
   }
+  // cut every thin run into LDS windows; flag windows whose levels fit one wave
+  for (Run &r : P.runs) {
+    if (!r.thin) continue;
+    r.wi = (int32_t)P.h_win.size();
+    int32_t ws = r.l0;
+    int64_t rows = 0, ents = 0;
+    bool one_wave = true;
+    for (int32_t l = r.l0; l < r.l1; ++l) {
+      const int64_t rl = rows_of(l), el = offd_of(l);
+      if (l > ws && win_bytes(rows + rl, ents + el, l - ws + 1, nrhs) > cap) {
+        P.h_win.push_back(int2{ws, one_wave ? 1 : 0});
+        ws = l;
+        rows = ents = 0;
+        one_wave = true;
+      }
+      rows += rl;
+      ents += el;
+      one_wave = one_wave && rl * nrhs <= 64;
+    }
+    P.h_win.push_back(int2{ws, one_wave ? 1 : 0});
+    r.nw = (int32_t)P.h_win.size() - r.wi;
+    P.h_win.push_back(int2{r.l1, 0});
+  }
+  if (!P.h_win.empty()) {
+    if (P.win.n < P.h_win.size()) HIPCHK(h, P.win.alloc(P.h_win.size()));
+    HIPCHK(h, hipMemcpy(P.win.p, P.h_win.data(), sizeof(int2) * P.h_win.size(), hipMemcpyHostToDevice));
+  }
   P.runs_nrhs = nrhs;
   P.runs_sched = sc;
+  return SPTRSV_OK;
 }
 
 sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs) {
@@ -196,9 +233,21 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   P.h_level_ptr.resize((size_t)nlev + 1);
   HIPCHK(h, hipMemcpyAsync(P.h_level_ptr.data(), P.level_ptr.p, sizeof(int32_t) * ((size_t)nlev + 1),
                            hipMemcpyDeviceToHost, s));
+  P.h_lv_nnz.resize((size_t)nlev);
+  HIPCHK(h, hipMemcpyAsync(P.h_lv_nnz.data(), P.lv_nnz.p, sizeof(int64_t) * (size_t)nlev, hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> htrp;
+  if (P.has_t) {
+    htrp.resize((size_t)n + 1);
+    HIPCHK(h, hipMemcpyAsync(htrp.data(), P.trp.p, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+  }
   HIPCHK(h, hipMemcpyAsync(haux, aux, sizeof(haux), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   if (haux[1]) return set_err(h, status_from_bits(haux[1]), "plan construction failed (bits 0x%x)", haux[1]);
+  if (P.has_t) {
+    P.h_lv_tnnz.resize((size_t)nlev);
+    for (int32_t l = 0; l < nlev; ++l)
+      P.h_lv_tnnz[(size_t)l] = htrp[(size_t)P.h_level_ptr[l + 1]] - htrp[(size_t)P.h_level_ptr[l]];
+  }
   long long tot;
   std::memcpy(&tot, haux + 4, sizeof(tot));
   P.total_cost = tot;
@@ -207,26 +256,62 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   return SPTRSV_OK;
 }
 
+// Algorithmic bytes of solving levels [l0, l1): each off-diagonal (and T entry)
+// once as value + column, each row's pointer and diagonal once, b read and x
+// written once per right-hand side, and the level pointers.
+static double run_bytes(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs) {
+  double b = 4.0 * (l1 - l0 + 1);
+  for (int32_t l = l0; l < l1; ++l) {
+    const double rows = P.h_level_ptr[l + 1] - P.h_level_ptr[l];
+    const double off = (double)P.h_lv_nnz[l] - rows;
+    b += 12.0 * off + 12.0 * rows + 16.0 * rows * nrhs;
+    if (P.has_t) b += 12.0 * (double)P.h_lv_tnnz[l] + 4.0 * rows;
+  }
+  return b;
+}
+
+// Live profile: an event pair around one launch (class cls).
+static int prof_begin(sptrsv_ctx *h, int cls, double bytes, hipStream_t s) {
+  if (!h->prof || h->prof_used + 2 > h->prof_ev.size()) return -1;
+  const int slot = (int)(h->prof_used / 2);
+  if (hipEventRecord(h->prof_ev[h->prof_used], s) != hipSuccess) return -1;
+  h->prof_used += 2;
+  h->prof_cls[(size_t)slot] = cls;
+  h->prof_bytes[(size_t)slot] = bytes;
+  return slot;
+}
+static void prof_end(sptrsv_ctx *h, int slot, hipStream_t s) {
+  if (slot >= 0) (void)hipEventRecord(h->prof_ev[(size_t)slot * 2 + 1], s);
+}
+
 sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
                            int64_t ldx, hipStream_t s) {
   if (P.n == 0) return SPTRSV_OK;
   STCHK(ensure_work(h, P, nrhs));
   const sptrsv_schedule_t sc = effective_sched(P, nrhs);
-  if (P.runs_nrhs != nrhs || !same_sched(sc, P.runs_sched)) make_runs(P, nrhs, sc);
+  if (P.runs_nrhs != nrhs || !same_sched(sc, P.runs_sched)) STCHK(make_runs(h, P, nrhs, sc));
   int *err = h->d_err.p;
+  const double vec_bytes = 16.0 * (double)P.n * nrhs + 4.0 * P.n;
+  int slot = prof_begin(h, 0, vec_bytes, s);
   HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.bp.p, s));
+  prof_end(h, slot, s);
   const int32_t *trp = P.has_t ? P.trp.p : nullptr;
   for (const Run &r : P.runs) {
+    slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
     if (r.thin) {
-      HIPCHK(h, launch_thin_run(sc.wg_threads, r.l0, r.l1, P.level_ptr.p, nrhs, P.srp.p, P.sci.p, P.sva.p, P.sdg.p,
+      HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, P.level_ptr.p, nrhs, P.srp.p, P.sci.p, P.sva.p,
+                                P.sdg.p,
                                 trp, P.tci.p, P.tva.p, P.bp.p, P.xp.p, err, s));
     } else {
       HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
                                   P.srp.p, P.sci.p, P.sva.p, P.sdg.p, trp, P.tci.p, P.tva.p, P.bp.p, P.xp.p, err,
                                   s));
     }
+    prof_end(h, slot, s);
   }
+  slot = prof_begin(h, 3, vec_bytes, s);
   HIPCHK(h, launch_scatter(P.n, nrhs, P.xp.p, P.iperm.p, x, ldx, s));
+  prof_end(h, slot, s);
   return SPTRSV_OK;
 }
 
@@ -366,7 +451,7 @@ sptrsv_status_t sptrsv_prepare(sptrsv_handle_t h, int which, int32_t nrhs, hipSt
   if (nrhs < 1) return set_err(h, SPTRSV_ERR_ARG, "nrhs=%d", nrhs);
   STCHK(ensure_work(h, *P, nrhs));
   const sptrsv_schedule_t sc = effective_sched(*P, nrhs);
-  make_runs(*P, nrhs, sc);
+  STCHK(make_runs(h, *P, nrhs, sc));
   return SPTRSV_OK;
 }
 
@@ -418,6 +503,36 @@ sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, sptrsv_schedul
   Plan *P = plan_of(h, which);
   if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
   *sched = P->sched;
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_profile(sptrsv_handle_t h, int enable, sptrsv_kernel_profile_t *out, hipStream_t s) {
+  if (!h) return SPTRSV_ERR_ARG;
+  constexpr size_t kPairs = 16384;
+  if (enable) {
+    if (h->prof_ev.empty()) {
+      h->prof_ev.resize(2 * kPairs);
+      for (auto &e : h->prof_ev) HIPCHK(h, hipEventCreate(&e));
+      h->prof_cls.assign(kPairs, 0);
+      h->prof_bytes.assign(kPairs, 0.0);
+    }
+    h->prof_used = 0;
+    h->prof = true;
+    return SPTRSV_OK;
+  }
+  h->prof = false;
+  HIPCHK(h, hipStreamSynchronize(s));
+  sptrsv_kernel_profile_t acc[4] = {};
+  for (size_t i = 0; i < h->prof_used / 2; ++i) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->prof_ev[2 * i], h->prof_ev[2 * i + 1]));
+    const int c = h->prof_cls[i];
+    acc[c].launches += 1;
+    acc[c].ms += ms;
+    acc[c].bytes += h->prof_bytes[i];
+  }
+  if (out)
+    for (int c = 0; c < 4; ++c) out[c] = acc[c];
   return SPTRSV_OK;
 }
 

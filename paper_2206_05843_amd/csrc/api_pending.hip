@@ -5,9 +5,6 @@
 #define PENDING(h) return set_err((h), SPTRSV_ERR_STATE, "%s: not available in this build", __func__)
 
 extern "C" {
-sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *, hipStream_t, sptrsv_rewrite_stats_t *) { PENDING(h); }
-sptrsv_status_t sptrsv_get_rewritten(sptrsv_handle_t h, int32_t *, int32_t *, double *, int32_t *, int32_t *, double *, hipStream_t) { PENDING(h); }
-sptrsv_status_t sptrsv_get_targets(sptrsv_handle_t h, int32_t *, hipStream_t) { PENDING(h); }
 sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t, const int32_t *, const int64_t *, const int64_t *, const int32_t *, const int32_t *, const double *, hipStream_t) { PENDING(h); }
 sptrsv_status_t sptrsv_batch_solve(sptrsv_handle_t h, int32_t, const double *, double *, hipStream_t) { PENDING(h); }
 sptrsv_status_t sptrsv_batch_solve_looped(sptrsv_handle_t h, int32_t, const double *, double *, hipStream_t) { PENDING(h); }

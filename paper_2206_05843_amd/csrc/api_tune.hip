@@ -32,7 +32,7 @@ std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
     if (nrhs > 1 && lpr > 1) continue;
     c.push_back(sptrsv_schedule_t{1, 0, 512, 256, lpr});
     for (int thr : thin_list) {
-      if ((int64_t)thr * nrhs > thin_lds_doubles()) continue;
+      if ((int64_t)thr * (8 * nrhs + 16) > thin_win_bytes()) continue;
       for (int wg : wg_list) c.push_back(sptrsv_schedule_t{0, thr, wg, 256, lpr});
     }
   }
@@ -105,9 +105,12 @@ sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, 
   if (h->graphs.size() >= 16) return set_err(h, SPTRSV_ERR_ARG, "at most 16 graphs per handle");
   STCHK(sptrsv_prepare(h, which, nrhs, s));
   Graph g;
+  const bool prof = h->prof;  // no event records inside a captured graph
+  h->prof = false;
   HIPCHK(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   sptrsv_status_t st = sptrsv_solve(h, which, nrhs, d_b, ldb, d_x, ldx, s);
   hipError_t e = hipStreamEndCapture(s, &g.g);
+  h->prof = prof;
   if (st != SPTRSV_OK) {
     if (g.g) (void)hipGraphDestroy(g.g);
     return st;

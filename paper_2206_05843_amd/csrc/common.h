@@ -66,6 +66,7 @@ struct DArr {
 struct Run {
   int32_t l0, l1;  // levels [l0, l1)
   bool thin;
+  int32_t wi = 0, nw = 0;  // thin: its LDS windows in Plan::win [wi, wi + nw], entry wi + nw = end
 };
 
 // Everything needed to solve one lower-triangular matrix level by level:
@@ -87,11 +88,15 @@ struct Plan {
   DArr<int32_t> trp, tci;              // T off-diagonals per position
   DArr<double> tva;
   DArr<int64_t> lv_rows, lv_nnz, lv_cost;
+  std::vector<int64_t> h_lv_nnz;       // per level: nnz incl. diagonal (host copy)
+  std::vector<int64_t> h_lv_tnnz;      // per level: off-diagonal nnz of T
   int64_t total_cost = 0;
   double avg_cost = 0.0;
   sptrsv_schedule_t sched{};           // knobs in force (mode 0 = automatic)
   std::map<int32_t, sptrsv_schedule_t> tuned;  // per nrhs
   std::vector<Run> runs;
+  std::vector<int2> h_win;             // LDS windows of all thin runs
+  DArr<int2> win;
   int32_t runs_nrhs = -1;
   sptrsv_schedule_t runs_sched{};
   DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
@@ -124,6 +129,7 @@ struct sptrsv_ctx {
   DArr<int32_t> lp_rp, lp_ci, t_rp, t_ci, target;
   DArr<double> lp_va, t_va;
   sptrsv_rewrite_stats_t rstats{};
+  DArr<char> rw_big;       // global workspace of the decision scan
   // batched matrices
   std::vector<BatchMat> bmats;
   std::vector<int32_t> b_nlev;
@@ -136,6 +142,12 @@ struct sptrsv_ctx {
   int64_t b_total_n = 0, b_total_nnz = 0;
   int32_t b_work_nrhs = 0;
   std::vector<Graph> graphs;
+  // live profile of solve launches
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;   // 2 per recorded launch
+  std::vector<int> prof_cls;
+  std::vector<double> prof_bytes;
+  size_t prof_used = 0;
   // scan scratch
   DArr<long long> scan_tmp;
 };
@@ -189,8 +201,8 @@ hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, 
                          hipStream_t s);
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
-int thin_lds_doubles();
-hipError_t launch_thin_run(int wg, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
+int thin_win_bytes();
+hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                            const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
                            double *xp, int *err, hipStream_t s);
@@ -202,6 +214,28 @@ hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int
                            const double *b, int64_t ldb, const double *x, int64_t ldx, unsigned long long *out,
                            hipStream_t s);
 void solve_kernels_init();
+
+// Launchers (k_rewrite.hip) ----------------------------------------------------
+size_t rewrite_big_ws_bytes(int32_t C, int32_t H);
+int32_t rewrite_lds_capacity();
+int32_t rewrite_waves_per_block();
+hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const int32_t *ci, const double *va,
+                               const int32_t *level_ptr, const int32_t *level_rows, const int64_t *lv_rows,
+                               const int64_t *lv_cost, const uint8_t *mask, int32_t metric, double W, double fill_cap,
+                               int32_t max_dist, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
+                               char *big, int32_t bigC, int32_t bigH, int32_t *out, hipStream_t s);
+hipError_t launch_row_counts(int32_t n, const int32_t *rp, const int32_t *target, const int32_t *cntL,
+                             const int32_t *cntT, long long *cl, long long *ct, hipStream_t s);
+hipError_t launch_collect_moved(int32_t n, const int32_t *target, const int32_t *cntL, const int32_t *cntT,
+                                int32_t *small_rows, int32_t *nsmall, int32_t *big_rows, int32_t *nbig,
+                                int32_t *max_entries, hipStream_t s);
+hipError_t launch_copy_unmoved(int32_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                               const int32_t *target, const int32_t *lrp, int32_t *lci, double *lva,
+                               const int32_t *trp, int32_t *tci, double *tva, hipStream_t s);
+hipError_t launch_rewrite_rows(int32_t nrows, const int32_t *rows, const int32_t *rp, const int32_t *ci,
+                               const double *va, const int32_t *cur, const int32_t *target, const int32_t *lrp,
+                               int32_t *lci, double *lva, const int32_t *trp, int32_t *tci, double *tva, char *big,
+                               int32_t bigC, int32_t bigH, int32_t big_blocks, int *err, hipStream_t s);
 
 // Plan building (api.hip) --------------------------------------------------------
 sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,

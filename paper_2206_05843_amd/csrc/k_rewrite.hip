@@ -1,0 +1,613 @@
+// Equation rewriting on the device (Sec. II.B, Fig. 2; naive strategy of Sec. III).
+//
+// Rewriting row r toward target level t substitutes, largest column first,
+// every unknown x[j] of the row whose row sits at level >= t (B set) by row j's
+// own equation; what is left are unknowns of rows above t (A set). Rearranged,
+// the row becomes L'[r] x = T[r] b: L'[r] holds the A coefficients and the
+// unchanged diagonal, T[r] holds minus each elimination multiplier and a unit
+// diagonal. Fill that cancels to zero stays in the pattern.
+//
+// One wave computes one row, in a workspace indexed by an open-addressing hash
+// on the column: every entry of the row being built is (column, value, state)
+// with state 0 = A (kept in L'), 1 = B (still to eliminate), 2 = eliminated
+// (its value is the T coefficient). Products and differences are rounded one
+// by one (no contraction) and every coefficient receives its updates in the
+// same order as the serial definition, so values are reproducible bit for bit.
+//
+// Decision scan: while the target is t, the B set is fixed (a row moving into t
+// stays at or below t), so the candidates of one step are independent; one
+// workgroup evaluates a chunk of candidates (one per wave) and its first thread
+// accepts them in order until the first refusal.
+#include "common.h"
+
+namespace {
+
+constexpr int kWaves = 8;          // waves per workgroup in both kernels
+constexpr int kLdsC = 512;         // LDS workspace entries per wave
+constexpr int kLdsH = 1024;        // LDS hash slots per wave
+
+enum : int { SUB_OK = 0, SUB_REJECT = 1, SUB_OVERFLOW = 2 };
+
+struct Ws {
+  int32_t *hkey;    // [H] column or -1
+  int32_t *hslot;   // [H] entry index
+  int32_t *col;     // [C]
+  double *val;      // [C]
+  uint8_t *st;      // [C]
+  int32_t *cnt;     // entries used
+  int32_t *na;      // entries in state 0
+  int32_t C, H;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ long long wave_max_ll(long long v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const long long o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Find column k or insert it (keys inserted concurrently by the lanes of a
+// wave are distinct). Returns the entry index, or -1 if the workspace is full.
+__device__ __forceinline__ int32_t ws_find_or_insert(Ws &w, int32_t k, bool &isnew) {
+  uint32_t hh = ((uint32_t)k * 2654435761u) & (uint32_t)(w.H - 1);
+  for (int32_t probe = 0; probe < w.H; ++probe) {
+    const int32_t prev = atomicCAS(w.hkey + hh, -1, k);
+    if (prev == -1) {
+      const int32_t s = atomicAdd(w.cnt, 1);
+      isnew = true;
+      if (s >= w.C) {
+        w.hslot[hh] = -1;
+        return -1;
+      }
+      w.hslot[hh] = s;
+      return s;
+    }
+    if (prev == k) {
+      isnew = false;
+      return w.hslot[hh];
+    }
+    hh = (hh + 1) & (uint32_t)(w.H - 1);
+  }
+  isnew = true;
+  return -1;
+}
+
+// Rewrite row r toward target t (B = rows with cur >= t). Stops early with
+// SUB_REJECT once more than capA A-columns exist (their number only grows).
+__device__ int subst_row(Ws &w, int32_t r, int32_t t, const int32_t *__restrict__ rp,
+                         const int32_t *__restrict__ ci, const double *__restrict__ va, const int32_t *cur,
+                         int64_t capA, int32_t *nT_out) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & 63;
+  for (int32_t i = lane; i < w.H; i += 64) w.hkey[i] = -1;
+  if (lane == 0) {
+    *w.cnt = 0;
+    *w.na = 0;
+  }
+  wave_sync();
+  int overflow = 0;
+  {
+    const int32_t b = rp[r], e = rp[r + 1] - 1;
+    for (int32_t p = b + lane; p < e; p += 64) {
+      const int32_t k = ci[p];
+      bool isnew;
+      const int32_t s = ws_find_or_insert(w, k, isnew);
+      if (s < 0) {
+        overflow = 1;
+        continue;
+      }
+      const bool inB = cur[k] >= t;
+      w.col[s] = k;
+      w.val[s] = va[p];
+      w.st[s] = inB ? 1 : 0;
+      if (!inB) atomicAdd(w.na, 1);
+    }
+  }
+  wave_sync();
+  if (__ballot(overflow) != 0ull) return SUB_OVERFLOW;
+  if ((int64_t)*w.na > capA) return SUB_REJECT;
+  int32_t nT = 0;
+  for (;;) {
+    const int32_t nE = *w.cnt;
+    long long best = -1;
+    for (int32_t s = lane; s < nE; s += 64)
+      if (w.st[s] == 1) {
+        const long long key = ((long long)w.col[s] << 32) | (long long)s;
+        best = key > best ? key : best;
+      }
+    best = wave_max_ll(best);
+    if (best < 0) break;
+    const int32_t j = (int32_t)(best >> 32), sj = (int32_t)(best & 0xffffffffll);
+    const double m = w.val[sj] / va[rp[j + 1] - 1];
+    wave_sync();
+    if (lane == 0) {
+      w.st[sj] = 2;
+      w.val[sj] = -m;
+    }
+    ++nT;
+    const int32_t jb = rp[j], je = rp[j + 1] - 1;
+    for (int32_t p = jb + lane; p < je; p += 64) {
+      const int32_t k = ci[p];
+      const double v = va[p];
+      bool isnew;
+      const int32_t s = ws_find_or_insert(w, k, isnew);
+      if (s < 0) {
+        overflow = 1;
+        continue;
+      }
+      const double prod = m * v;
+      if (isnew) {
+        const bool inB = cur[k] >= t;
+        w.col[s] = k;
+        w.val[s] = 0.0 - prod;
+        w.st[s] = inB ? 1 : 0;
+        if (!inB) atomicAdd(w.na, 1);
+      } else {
+        w.val[s] = w.val[s] - prod;
+      }
+    }
+    wave_sync();
+    if (__ballot(overflow) != 0ull) return SUB_OVERFLOW;
+    if ((int64_t)*w.na > capA) return SUB_REJECT;
+  }
+  *nT_out = nT;
+  return SUB_OK;
+}
+
+__device__ __forceinline__ Ws lds_ws(char *base, int wave) {
+  // per wave: hkey[H] hslot[H] col[C] val[C] st[C] cnt na
+  constexpr size_t per = (size_t)kLdsH * 8 + (size_t)kLdsC * 13 + 16;
+  constexpr size_t per_al = (per + 15) & ~(size_t)15;
+  char *p = base + (size_t)wave * per_al;
+  Ws w;
+  w.val = reinterpret_cast<double *>(p);
+  w.hkey = reinterpret_cast<int32_t *>(p + (size_t)kLdsC * 8);
+  w.hslot = w.hkey + kLdsH;
+  w.col = w.hslot + kLdsH;
+  w.cnt = w.col + kLdsC;
+  w.na = w.cnt + 1;
+  w.st = reinterpret_cast<uint8_t *>(w.na + 3);
+  w.C = kLdsC;
+  w.H = kLdsH;
+  return w;
+}
+constexpr size_t kLdsWsBytes = (((size_t)kLdsH * 8 + (size_t)kLdsC * 13 + 16 + 15) & ~(size_t)15) * kWaves;
+
+__device__ __forceinline__ Ws global_ws(char *base, int32_t C, int32_t H) {
+  Ws w;
+  w.val = reinterpret_cast<double *>(base);
+  w.hkey = reinterpret_cast<int32_t *>(base + (size_t)C * 8);
+  w.hslot = w.hkey + H;
+  w.col = w.hslot + H;
+  w.cnt = w.col + C;
+  w.na = w.cnt + 1;
+  w.st = reinterpret_cast<uint8_t *>(w.na + 3);
+  w.C = C;
+  w.H = H;
+  return w;
+}
+
+struct ScanArgs {
+  int32_t n, nlev;
+  const int32_t *rp, *ci;
+  const double *va;
+  const int32_t *level_ptr, *level_rows;
+  const int64_t *lv_rows, *lv_cost;
+  const uint8_t *mask;
+  int32_t metric;
+  double W, fill_cap;
+  int32_t max_dist;
+  int32_t *cur, *target, *cntL, *cntT;
+  char *big;        // global workspace for candidates that overflow LDS
+  int32_t bigC, bigH;
+  int32_t *out;     // [0] rows moved [1] max distance [2] target steps [3] error bits
+};
+
+// The whole decision scan in one workgroup (levels in order, targets only
+// move forward). Thread 0 owns the scan state; waves evaluate candidates.
+__global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
+  extern __shared__ __align__(16) char lds_raw[];
+  __shared__ int32_t c_row[kWaves], c_lvl[kWaves], c_q[kWaves], c_st[kWaves], c_na[kWaves], c_nt[kWaves];
+  __shared__ int32_t s_nc, s_done, s_redo, s_t;
+  __shared__ int64_t s_capA_cost;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  Ws w = lds_ws(lds_raw, wave);
+  // scan state (thread 0)
+  int32_t t = 0, l = 1, q = 0, moved = 0, maxd = 0, steps = a.nlev > 0 ? 1 : 0;
+  int64_t size = a.nlev > 0 ? a.lv_rows[0] : 0, cost = a.nlev > 0 ? a.lv_cost[0] : 0;
+  int bits = 0;
+  auto is_src = [&](int32_t lvl) -> bool {
+    if (a.mask) return a.mask[lvl] != 0;
+    if (a.metric == SPTRSV_THIN_ROWS) return (double)a.lv_rows[lvl] < a.W;
+    return (double)a.lv_cost[lvl] < a.W;
+  };
+  const int64_t guard = (int64_t)a.n + 2 * (int64_t)a.nlev + 16;
+  for (int64_t iter = 0;; ++iter) {
+    if (tid == 0) {
+      // next chunk of candidates: rows of consecutive source levels
+      int32_t nc = 0;
+      int32_t limit = kWaves;
+      if (a.metric == SPTRSV_THIN_ROWS) {
+        const double room = a.W - (double)size;  // rows the target can still take
+        if (room < (double)kWaves) limit = room < 0.0 ? 1 : (int32_t)room + 1;
+      }
+      while (l < a.nlev && nc < limit) {
+        if (!is_src(l)) {
+          if (nc > 0) break;
+          t = l;
+          size = a.lv_rows[l];
+          cost = a.lv_cost[l];
+          ++steps;
+          ++l;
+          q = 0;
+          if (a.metric == SPTRSV_THIN_ROWS) {
+            const double room = a.W - (double)size;
+            limit = room < (double)kWaves ? (room < 0.0 ? 1 : (int32_t)room + 1) : kWaves;
+          }
+          continue;
+        }
+        const int32_t lb = a.level_ptr[l], lr = a.level_ptr[l + 1] - lb;
+        while (q < lr && nc < limit) {
+          c_row[nc] = a.level_rows[lb + q];
+          c_lvl[nc] = l;
+          c_q[nc] = q;
+          ++nc;
+          ++q;
+        }
+        if (q == lr) {
+          ++l;
+          q = 0;
+        }
+      }
+      s_nc = nc;
+      s_t = t;
+      s_done = (nc == 0) || iter > guard;
+      if (iter > guard) bits |= EB_TIMEOUT;
+      // bound on A columns: fill cap, and for a cost budget the room left
+      int64_t capA = INT64_MAX;
+      s_capA_cost = capA;
+      if (a.metric == SPTRSV_THIN_COST) {
+        // cost_t + 2*(nA+1) - 1 <= W  =>  nA <= (W - cost_t - 1) / 2
+        const double room = a.W - (double)cost - 1.0;
+        s_capA_cost = room < 0.0 ? -1 : (int64_t)(room / 2.0);
+      }
+    }
+    __syncthreads();
+    if (s_done) break;
+    const int32_t nc = s_nc, tt = s_t;
+    if (wave < nc) {
+      const int32_t r = c_row[wave];
+      const int64_t nnz_old = a.rp[r + 1] - a.rp[r];
+      int64_t capA = s_capA_cost;
+      if (a.fill_cap > 0.0) {
+        // nA + 1 <= fill_cap * nnz_old
+        const double lim = a.fill_cap * (double)nnz_old - 1.0;
+        const int64_t c2 = lim < 0.0 ? -1 : (int64_t)lim;
+        capA = c2 < capA ? c2 : capA;
+      }
+      int32_t nT = 0;
+      const int stt = subst_row(w, r, tt, a.rp, a.ci, a.va, a.cur, capA, &nT);
+      if (lane == 0) {
+        c_st[wave] = stt;
+        c_na[wave] = *w.na;
+        c_nt[wave] = nT;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s_redo = -1;
+      for (int32_t i = 0; i < nc; ++i) {
+        if (c_st[i] == SUB_OVERFLOW) {
+          s_redo = i;
+          break;
+        }
+        const int32_t r = c_row[i], lvl = c_lvl[i];
+        const int64_t nnz_old = a.rp[r + 1] - a.rp[r];
+        const int64_t nnz_new = (int64_t)c_na[i] + 1;
+        bool ok = c_st[i] == SUB_OK;
+        if (ok) {
+          if (a.metric == SPTRSV_THIN_ROWS)
+            ok = (double)(size + 1) <= a.W;
+          else
+            ok = (double)(cost + 2 * nnz_new - 1) <= a.W;
+          if (a.fill_cap > 0.0) ok = ok && (double)nnz_new <= a.fill_cap * (double)nnz_old;
+          if (a.max_dist > 0) ok = ok && (lvl - t) <= a.max_dist;
+        }
+        if (ok) {
+          a.cur[r] = t;
+          a.target[r] = t;
+          a.cntL[r] = (int32_t)nnz_new;
+          a.cntT[r] = c_nt[i] + 1;
+          size += 1;
+          cost += 2 * nnz_new - 1;
+          ++moved;
+          if (lvl - t > maxd) maxd = lvl - t;
+          // the scan position is already past this candidate
+        } else {
+          // its level becomes the target with the rows not moved
+          t = lvl;
+          ++steps;
+          const int32_t lb = a.level_ptr[lvl], le = a.level_ptr[lvl + 1];
+          size = 0;
+          cost = 0;
+          for (int32_t p = lb + c_q[i]; p < le; ++p) {
+            const int32_t rr = a.level_rows[p];
+            size += 1;
+            cost += 2 * (int64_t)(a.rp[rr + 1] - a.rp[rr]) - 1;
+          }
+          l = lvl + 1;
+          q = 0;
+          break;
+        }
+      }
+      if (s_redo >= 0) {  // resume right at the overflowing candidate
+        l = c_lvl[s_redo];
+        q = c_q[s_redo];
+      }
+    }
+    __syncthreads();
+    if (s_redo >= 0) {
+      // evaluate that candidate alone with the large global workspace
+      if (wave == 0) {
+        const int32_t i = s_redo, r = c_row[i];
+        Ws g = global_ws(a.big, a.bigC, a.bigH);
+        int32_t nT = 0;
+        const int stt = subst_row(g, r, s_t, a.rp, a.ci, a.va, a.cur, INT64_MAX, &nT);
+        if (lane == 0) {
+          c_st[0] = stt;
+          c_na[0] = *g.na;
+          c_nt[0] = nT;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const int32_t i = s_redo, r = c_row[i], lvl = c_lvl[i];
+        if (c_st[0] == SUB_OVERFLOW) {
+          bits |= EB_OVERFLOW;
+          s_done = 1;
+        } else {
+          const int64_t nnz_old = a.rp[r + 1] - a.rp[r];
+          const int64_t nnz_new = (int64_t)c_na[0] + 1;
+          bool ok;
+          if (a.metric == SPTRSV_THIN_ROWS)
+            ok = (double)(size + 1) <= a.W;
+          else
+            ok = (double)(cost + 2 * nnz_new - 1) <= a.W;
+          if (a.fill_cap > 0.0) ok = ok && (double)nnz_new <= a.fill_cap * (double)nnz_old;
+          if (a.max_dist > 0) ok = ok && (lvl - t) <= a.max_dist;
+          if (ok) {
+            a.cur[r] = t;
+            a.target[r] = t;
+            a.cntL[r] = (int32_t)nnz_new;
+            a.cntT[r] = c_nt[0] + 1;
+            size += 1;
+            cost += 2 * nnz_new - 1;
+            ++moved;
+            if (lvl - t > maxd) maxd = lvl - t;
+            // advance past it
+            q = c_q[i] + 1;
+            l = lvl;
+            if (q == a.level_ptr[lvl + 1] - a.level_ptr[lvl]) {
+              ++l;
+              q = 0;
+            }
+          } else {
+            t = lvl;
+            ++steps;
+            const int32_t lb = a.level_ptr[lvl], le = a.level_ptr[lvl + 1];
+            size = 0;
+            cost = 0;
+            for (int32_t p = lb + c_q[i]; p < le; ++p) {
+              const int32_t rr = a.level_rows[p];
+              size += 1;
+              cost += 2 * (int64_t)(a.rp[rr + 1] - a.rp[rr]) - 1;
+            }
+            l = lvl + 1;
+            q = 0;
+          }
+        }
+      }
+      __syncthreads();
+      if (s_done) break;
+    }
+  }
+  if (tid == 0) {
+    a.out[0] = moved;
+    a.out[1] = maxd;
+    a.out[2] = steps;
+    a.out[3] = bits;
+  }
+}
+
+// Rows not rewritten: copied; their T row is the unit row.
+__global__ void k_copy_unmoved(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                               const double *__restrict__ va, const int32_t *__restrict__ target,
+                               const int32_t *__restrict__ lrp, int32_t *lci, double *lva,
+                               const int32_t *__restrict__ trp, int32_t *tci, double *tva) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    if (target[r] >= 0) continue;
+    const int32_t b = rp[r], e = rp[r + 1];
+    int32_t o = lrp[r];
+    for (int32_t p = b; p < e; ++p, ++o) {
+      lci[o] = ci[p];
+      lva[o] = va[p];
+    }
+    tci[trp[r]] = (int32_t)r;
+    tva[trp[r]] = 1.0;
+  }
+}
+
+// Rows rewritten: recomputed with their final target (the B set of a row's
+// step is exactly the rows whose final level is >= its target), then written
+// in ascending column order with the diagonal last.
+__global__ __launch_bounds__(64 * kWaves) void k_rewrite_rows(
+    int32_t nrows, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const double *__restrict__ va, const int32_t *__restrict__ cur, const int32_t *__restrict__ target,
+    const int32_t *__restrict__ lrp, int32_t *lci, double *lva, const int32_t *__restrict__ trp, int32_t *tci,
+    double *tva, char *big, int32_t bigC, int32_t bigH, int use_big, int *err) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  Ws w = use_big ? global_ws(big + (size_t)(blockIdx.x * kWaves + wave) *
+                                       ((size_t)bigC * 13 + (size_t)bigH * 8 + 64),
+                             bigC, bigH)
+                 : lds_ws(lds_raw, wave);
+  const int64_t gw = (int64_t)blockIdx.x * kWaves + wave, nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t i = gw; i < nrows; i += nw) {
+    const int32_t r = rows[i];
+    const int32_t t = target[r];
+    int32_t nT = 0;
+    const int stt = subst_row(w, r, t, rp, ci, va, cur, INT64_MAX, &nT);
+    if (stt != SUB_OK) {
+      if (lane == 0) atomicOr(err, EB_OVERFLOW);
+      continue;
+    }
+    const int32_t nA = *w.na, nE = *w.cnt;
+    const int32_t lb = lrp[r], tb = trp[r];
+    if (lrp[r + 1] - lb != nA + 1 || trp[r + 1] - tb != nT + 1) {
+      if (lane == 0) atomicOr(err, EB_ARG);  // disagrees with the scan's counts
+      continue;
+    }
+    for (int32_t s = lane; s < nE; s += 64) {
+      const uint8_t cls = w.st[s];
+      const int32_t c = w.col[s];
+      int32_t rank = 0;
+      for (int32_t s2 = 0; s2 < nE; ++s2) rank += (w.st[s2] == cls && w.col[s2] < c) ? 1 : 0;
+      if (cls == 0) {
+        lci[lb + rank] = c;
+        lva[lb + rank] = w.val[s];
+      } else {
+        tci[tb + rank] = c;
+        tva[tb + rank] = w.val[s];
+      }
+    }
+    if (lane == 0) {
+      lci[lb + nA] = r;
+      lva[lb + nA] = va[rp[r + 1] - 1];
+      tci[tb + nT] = r;
+      tva[tb + nT] = 1.0;
+    }
+    wave_sync();
+  }
+}
+
+// Row counts of L' and T (unmoved rows keep theirs), as int64 for the scan.
+__global__ void k_row_counts(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ target,
+                             const int32_t *__restrict__ cntL, const int32_t *__restrict__ cntT, long long *cl,
+                             long long *ct) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const bool mv = target[r] >= 0;
+    cl[r] = mv ? cntL[r] : rp[r + 1] - rp[r];
+    ct[r] = mv ? cntT[r] : 1;
+  }
+}
+
+// Compact the rewritten rows, split by the size of the workspace they need.
+__global__ void k_collect_moved(int32_t n, const int32_t *__restrict__ target, const int32_t *__restrict__ cntL,
+                                const int32_t *__restrict__ cntT, int32_t small_cap, int32_t *small_rows,
+                                int32_t *nsmall, int32_t *big_rows, int32_t *nbig, int32_t *max_entries) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    if (target[r] < 0) continue;
+    const int32_t ent = (cntL[r] - 1) + (cntT[r] - 1);
+    if (ent <= small_cap) {
+      small_rows[atomicAdd(nsmall, 1)] = (int32_t)r;
+    } else {
+      big_rows[atomicAdd(nbig, 1)] = (int32_t)r;
+      atomicMax(max_entries, ent);
+    }
+  }
+}
+
+inline int grid_for(int64_t items, int threads, int cap) {
+  int64_t g = (items + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+size_t rewrite_big_ws_bytes(int32_t C, int32_t H) { return (size_t)C * 13 + (size_t)H * 8 + 64; }
+
+hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const int32_t *ci, const double *va,
+                               const int32_t *level_ptr, const int32_t *level_rows, const int64_t *lv_rows,
+                               const int64_t *lv_cost, const uint8_t *mask, int32_t metric, double W, double fill_cap,
+                               int32_t max_dist, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
+                               char *big, int32_t bigC, int32_t bigH, int32_t *out, hipStream_t s) {
+  ScanArgs a;
+  a.n = n;
+  a.nlev = nlev;
+  a.rp = rp;
+  a.ci = ci;
+  a.va = va;
+  a.level_ptr = level_ptr;
+  a.level_rows = level_rows;
+  a.lv_rows = lv_rows;
+  a.lv_cost = lv_cost;
+  a.mask = mask;
+  a.metric = metric;
+  a.W = W;
+  a.fill_cap = fill_cap;
+  a.max_dist = max_dist;
+  a.cur = cur;
+  a.target = target;
+  a.cntL = cntL;
+  a.cntT = cntT;
+  a.big = big;
+  a.bigC = bigC;
+  a.bigH = bigH;
+  a.out = out;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rewrite_scan),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsWsBytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rewrite_rows),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsWsBytes);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_rewrite_scan, dim3(1), dim3(64 * kWaves), kLdsWsBytes, s, a);
+  return hipGetLastError();
+}
+
+int32_t rewrite_lds_capacity() { return kLdsC; }
+
+hipError_t launch_row_counts(int32_t n, const int32_t *rp, const int32_t *target, const int32_t *cntL,
+                             const int32_t *cntT, long long *cl, long long *ct, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_counts, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, rp, target, cntL, cntT, cl, ct);
+  return hipGetLastError();
+}
+
+hipError_t launch_collect_moved(int32_t n, const int32_t *target, const int32_t *cntL, const int32_t *cntT,
+                                int32_t *small_rows, int32_t *nsmall, int32_t *big_rows, int32_t *nbig,
+                                int32_t *max_entries, hipStream_t s) {
+  hipLaunchKernelGGL(k_collect_moved, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, target, cntL, cntT, kLdsC,
+                     small_rows, nsmall, big_rows, nbig, max_entries);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_unmoved(int32_t n, const int32_t *rp, const int32_t *ci, const double *va,
+                               const int32_t *target, const int32_t *lrp, int32_t *lci, double *lva,
+                               const int32_t *trp, int32_t *tci, double *tva, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_unmoved, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, rp, ci, va, target, lrp, lci,
+                     lva, trp, tci, tva);
+  return hipGetLastError();
+}
+
+hipError_t launch_rewrite_rows(int32_t nrows, const int32_t *rows, const int32_t *rp, const int32_t *ci,
+                               const double *va, const int32_t *cur, const int32_t *target, const int32_t *lrp,
+                               int32_t *lci, double *lva, const int32_t *trp, int32_t *tci, double *tva, char *big,
+                               int32_t bigC, int32_t bigH, int32_t big_blocks, int *err, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const bool use_big = big != nullptr;
+  const int blocks = use_big ? big_blocks : grid_for(nrows, kWaves, 2048);
+  hipLaunchKernelGGL(k_rewrite_rows, dim3(blocks), dim3(64 * kWaves), use_big ? 0 : kLdsWsBytes, s, nrows, rows, rp,
+                     ci, va, cur, target, lrp, lci, lva, trp, tci, tva, big, bigC, bigH, use_big ? 1 : 0, err);
+  return hipGetLastError();
+}
+
+int32_t rewrite_waves_per_block() { return kWaves; }

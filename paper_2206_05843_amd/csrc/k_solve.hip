@@ -18,8 +18,7 @@
 
 namespace {
 
-constexpr int kLdsBytes = 128 * 1024;
-constexpr int kLdsDoubles = kLdsBytes / 8;
+constexpr int kWinBytes = 150 * 1024;  // LDS of one thin-run window
 
 // Workgroup barrier that orders LDS only: global stores may still be in flight
 // (the global copy of x is only read across an LDS-window restart, which uses a
@@ -59,40 +58,118 @@ __device__ __forceinline__ double row_solve(int32_t pos, int32_t c, int32_t nrhs
   return acc / sdg[pos];
 }
 
+// A thin run is cut into LDS windows (consecutive levels, chosen on the host so
+// that the window's rows and off-diagonals fit in LDS). Per window:
+//  phase 1 (all rows in parallel): v = b' - sum of L(pos,k) x(k) over the
+//    dependencies k that precede the window (final values, read from global),
+//    and the dependencies inside the window are copied into LDS (slot, value);
+//  phase 2 (level by level): x = (v - sum over in-window dependencies) / diag,
+//    reading and writing LDS only; the global copy of x is written as well.
+// Windows whose every level has at most 64 (row, rhs) items run phase 2 on one
+// wave without workgroup barriers. win[i] = {first level, flags}; the run's last
+// entry holds the end level.
 template <int WG, bool kOne>
-__global__ __launch_bounds__(WG) void k_thin_run(int32_t l0, int32_t l1, const int32_t *__restrict__ level_ptr,
-                                                 int32_t nrhs, const int32_t *__restrict__ srp,
-                                                 const int32_t *__restrict__ sci, const double *__restrict__ sva,
-                                                 const double *__restrict__ sdg, const int32_t *__restrict__ trp,
-                                                 const int32_t *__restrict__ tci, const double *__restrict__ tva,
-                                                 const double *__restrict__ bp, double *xp, int *err) {
+__global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, int32_t nwin,
+                                                 const int32_t *__restrict__ level_ptr, int32_t nrhs,
+                                                 const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
+                                                 const double *__restrict__ sva, const double *__restrict__ sdg,
+                                                 const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
+                                                 const double *__restrict__ tva, const double *__restrict__ bp,
+                                                 double *xp, int *err) {
   extern __shared__ double lds[];
   const int32_t nr = kOne ? 1 : nrhs;
-  const int32_t cap_rows = kLdsDoubles / nr;
-  int32_t base = level_ptr[l0];
+  const int tid = threadIdx.x;
   int bits = 0;
-  int32_t pb = base;
-  for (int32_t l = l0; l < l1; ++l) {
-    const int32_t pe = level_ptr[l + 1];
-    if (pe - pb > cap_rows) {  // a level wider than the LDS window never runs here
-      if (threadIdx.x == 0) atomicOr(err, EB_ARG);
+  for (int32_t w = 0; w < nwin; ++w) {
+    const int32_t lA = win[w].x, lB = win[w + 1].x, flags = win[w].y;
+    const int32_t P0 = level_ptr[lA], P1 = level_ptr[lB];
+    const int32_t R = P1 - P0;
+    const int32_t E0 = srp[P0], E = srp[P1] - E0;
+    const int32_t NL = lB - lA;
+    const int64_t need = (int64_t)R * (8 * nr + 16) + (int64_t)E * 12 + 4 * (int64_t)(NL + 1);
+    if (need > kWinBytes) {  // the host sizes windows to fit; never index past LDS
+      if (tid == 0) atomicOr(err, EB_ARG);
       return;
     }
-    if (pe - base > cap_rows) {
-      __syncthreads();  // global copies of the window become visible
-      base = pb;
+    double *v = lds;            // [R * nr] partial sums, then x
+    double *dg = v + (int64_t)R * nr;  // [R]
+    double *ev = dg + R;        // [E] in-window dependency values
+    int32_t *es = reinterpret_cast<int32_t *>(ev + E);  // [E] in-window dependency slots
+    int32_t *eo = es + E;       // [R] first entry of each row
+    int32_t *en = eo + R;       // [R] number of in-window entries
+    int32_t *lv = en + R;       // [NL + 1] level boundaries, relative to P0
+    for (int32_t i = tid; i <= NL; i += WG) lv[i] = level_ptr[lA + i] - P0;
+    // phase 1
+    for (int32_t it = tid; it < R * nr; it += WG) {
+      const int32_t s = kOne ? it : it / nr;
+      const int32_t c = kOne ? 0 : it - s * nr;
+      const int32_t pos = P0 + s;
+      double acc = bp[(int64_t)pos * nr + c];
+      if (trp) {
+        const int32_t tb = trp[pos], te = trp[pos + 1];
+        for (int32_t q = tb; q < te; ++q) acc += tva[q] * bp[(int64_t)tci[q] * nr + c];
+      }
+      const int32_t qb = srp[pos], qe = srp[pos + 1];
+      int32_t o = qb - E0;
+      for (int32_t q = qb; q < qe; ++q) {
+        const int32_t k = sci[q];
+        if (k < P0) {
+          acc -= sva[q] * xp[(int64_t)k * nr + c];
+        } else {
+          if (c == 0) {
+            es[o] = k - P0;
+            ev[o] = sva[q];
+          }
+          ++o;
+        }
+      }
+      v[(int64_t)s * nr + c] = acc;
+      if (c == 0) {
+        dg[s] = sdg[pos];
+        eo[s] = qb - E0;
+        en[s] = o - (qb - E0);
+      }
     }
-    const int32_t items = (pe - pb) * nr;
-    for (int32_t it = threadIdx.x; it < items; it += WG) {
-      const int32_t pos = kOne ? pb + it : pb + it / nr;
-      const int32_t c = kOne ? 0 : it - (pos - pb) * nr;
-      const double xv = row_solve<true, kOne>(pos, c, nr, srp, sci, sva, sdg, trp, tci, tva, bp, xp, lds, base);
-      if (!isfinite(xv)) bits |= EB_NONFINITE;
-      lds[(int64_t)(pos - base) * nr + c] = xv;
-      xp[(int64_t)pos * nr + c] = xv;
+    __syncthreads();
+    // phase 2
+    if (flags & 1) {
+      if (tid < 64) {
+        for (int32_t l = 0; l < NL; ++l) {
+          const int32_t pb = lv[l], items = (lv[l + 1] - pb) * nr;
+          if (tid < items) {
+            const int32_t s = kOne ? pb + tid : pb + tid / nr;
+            const int32_t c = kOne ? 0 : tid - (s - pb) * nr;
+            double acc = v[(int64_t)s * nr + c];
+            const int32_t o = eo[s], k = en[s];
+            for (int32_t i = 0; i < k; ++i) acc -= ev[o + i] * v[(int64_t)es[o + i] * nr + c];
+            const double x = acc / dg[s];
+            if (!isfinite(x)) bits |= EB_NONFINITE;
+            v[(int64_t)s * nr + c] = x;
+            xp[(int64_t)(P0 + s) * nr + c] = x;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        }
+      }
+    } else {
+      for (int32_t l = 0; l < NL; ++l) {
+        const int32_t pb = lv[l], items = (lv[l + 1] - pb) * nr;
+        for (int32_t it = tid; it < items; it += WG) {
+          const int32_t s = kOne ? pb + it : pb + it / nr;
+          const int32_t c = kOne ? 0 : it - (s - pb) * nr;
+          double acc = v[(int64_t)s * nr + c];
+          const int32_t o = eo[s], k = en[s];
+          for (int32_t i = 0; i < k; ++i) acc -= ev[o + i] * v[(int64_t)es[o + i] * nr + c];
+          const double x = acc / dg[s];
+          if (!isfinite(x)) bits |= EB_NONFINITE;
+          v[(int64_t)s * nr + c] = x;
+          xp[(int64_t)(P0 + s) * nr + c] = x;
+        }
+        lds_barrier();
+      }
     }
-    lds_barrier();
-    pb = pe;
+    __syncthreads();  // the window's global x is complete before the next phase 1 reads it
   }
   if (bits) atomicOr(err, bits);
 }
@@ -231,12 +308,12 @@ inline int grid_for(int64_t items, int threads, int cap) {
 template <int WG, bool kOne>
 void set_lds_attr() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_thin_run<WG, kOne>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
 }
 
 }  // namespace
 
-int thin_lds_doubles() { return kLdsDoubles; }
+int thin_win_bytes() { return kWinBytes; }
 
 void solve_kernels_init() {
   set_lds_attr<256, true>();
@@ -267,17 +344,17 @@ hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32
   return hipGetLastError();
 }
 
-hipError_t launch_thin_run(int wg, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
+hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                            const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
                            double *xp, int *err, hipStream_t s) {
   const bool one = nrhs == 1;
 #define THIN(W)                                                                                                   \
   if (one)                                                                                                        \
-    hipLaunchKernelGGL((k_thin_run<W, true>), dim3(1), dim3(W), kLdsBytes, s, l0, l1, level_ptr, nrhs, srp, sci, \
+    hipLaunchKernelGGL((k_thin_run<W, true>), dim3(1), dim3(W), kWinBytes, s, win, nwin, level_ptr, nrhs, srp, sci, \
                        sva, sdg, trp, tci, tva, bp, xp, err);                                                     \
   else                                                                                                            \
-    hipLaunchKernelGGL((k_thin_run<W, false>), dim3(1), dim3(W), kLdsBytes, s, l0, l1, level_ptr, nrhs, srp,     \
+    hipLaunchKernelGGL((k_thin_run<W, false>), dim3(1), dim3(W), kWinBytes, s, win, nwin, level_ptr, nrhs, srp,     \
                        sci, sva, sdg, trp, tci, tva, bp, xp, err);
   if (wg == 256) {
     THIN(256)

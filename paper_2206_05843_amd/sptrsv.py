@@ -28,7 +28,7 @@ EXPORTS = [
     "sptrsv_autotune", "sptrsv_graph_create", "sptrsv_graph_launch", "sptrsv_residual", "sptrsv_batch_analyze",
     "sptrsv_batch_solve", "sptrsv_batch_solve_looped", "sptrsv_batch_levels", "sptrsv_plan_save",
     "sptrsv_plan_load", "sptrsv_level_features", "sptrsv_mlp_forward", "sptrsv_mlp_backward", "sptrsv_mlp_adam",
-    "sptrsv_mlp_mask",
+    "sptrsv_mlp_mask", "sptrsv_profile",
 ]
 
 
@@ -53,6 +53,13 @@ class RewriteStats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("bytes", C.c_double)]
+
+
+PROFILE_CLASSES = ["gather", "thin_run", "wide_level", "scatter"]
 
 
 class Schedule(C.Structure):
@@ -105,6 +112,7 @@ def lib():
         "sptrsv_mlp_backward": [vp, vp, vp, vp, i32, vp, vp, vp],
         "sptrsv_mlp_adam": [vp, vp, vp, vp, i32, f32, vp],
         "sptrsv_mlp_mask": [vp, i32, f32, vp, vp],
+        "sptrsv_profile": [vp, C.c_int, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -299,6 +307,15 @@ class Handle:
         ms = C.c_float(0)
         self._check(self._L.sptrsv_autotune(self._h, which, nrhs, _stream(), C.byref(ms)))
         return ms.value
+
+    def profile_start(self):
+        self._check(self._L.sptrsv_profile(self._h, 1, None, _stream()))
+
+    def profile_stop(self):
+        out = (KernelProfile * 4)()
+        self._check(self._L.sptrsv_profile(self._h, 0, out, _stream()))
+        return {PROFILE_CLASSES[i]: dict(launches=out[i].launches, ms=out[i].ms, bytes=out[i].bytes)
+                for i in range(4)}
 
     def graph_create(self, b, x, which=ORIGINAL) -> int:
         bb = b if b.dim() == 2 else b.view(1, -1)

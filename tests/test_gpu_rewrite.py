@@ -1,0 +1,148 @@
+"""GPU parity of sptrsv_rewrite against the oracle: decisions (targets), the
+rewritten patterns and values of L' and T, the re-levelled L', Table I style
+statistics, and the solve of the rewritten system, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from tests.gpu_util import dev, to_dev
+from tests.test_oracle_rewrite import costmap_matrix
+from tests.test_oracle_solve_levels import fig2_matrix
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_2206_05843_amd")
+
+TOL = 1e-10
+
+
+def _cases():
+    yield "cfg0", gen.config_matrix(0)[0]
+    yield "cfg1_small", gen.config_matrix(1, "small")[0]
+    yield "cfg2_small", gen.config_matrix(2, "small")[0]
+    yield "cfg4_small", gen.config_matrix(4, "small")[0]
+    yield "bidiag", gen.bidiagonal(1000, 5)
+    yield "window_ragged", gen.window_random(3001, 4, window=12, draws=3)
+
+
+MATS = list(_cases())
+OPTS = {
+    "rows32_cap4": dict(thin_metric=0, thin_threshold=32, fill_cap=4.0, max_distance=0),
+    "rows8": dict(thin_metric=0, thin_threshold=8, fill_cap=0.0, max_distance=0),
+    "cost_avg": dict(thin_metric=1, thin_threshold=0.0, fill_cap=0.0, max_distance=0),
+    "cost_avg_cap3_d4": dict(thin_metric=1, thin_threshold=0.0, fill_cap=3.0, max_distance=4),
+    "rows64_d2": dict(thin_metric=0, thin_threshold=64, fill_cap=6.0, max_distance=2),
+}
+
+
+def compare(m, h, st, rw, lv, nrhs=(1, 5)):
+    assert st["rows_rewritten"] == rw.rows_rewritten
+    assert st["max_distance"] == rw.max_distance
+    assert st["target_steps"] == rw.steps
+    assert np.array_equal(h.targets().cpu().numpy(), rw.target)
+    out = {k: v.cpu().numpy() for k, v in h.rewritten().items()}
+    for k in ["lp_ptr", "lp_col", "t_ptr", "t_col"]:
+        assert np.array_equal(out[k], getattr(rw, k)), k
+    # values: same operations in the same order, no contraction -> bit for bit
+    assert np.array_equal(out["lp_val"], rw.lp_val)
+    assert np.array_equal(out["t_val"], rw.t_val)
+    ost = oracle.rewrite_stats(m, rw, lv)
+    for k in ["nlev_before", "nlev_after", "nnz_L", "nnz_Lp", "nnz_T", "total_cost_before", "total_cost_after",
+              "avg_level_cost_before", "avg_level_cost_after"]:
+        assert st[k] == ost[k], k
+    lv2 = oracle.levels(rw.lp)
+    lp, lr, rl = h.levels(sp.REWRITTEN)
+    assert np.array_equal(lp.cpu().numpy(), lv2.level_ptr)
+    assert np.array_equal(lr.cpu().numpy(), lv2.level_rows)
+    assert np.array_equal(rl.cpu().numpy(), lv2.row_level)
+    for k in nrhs:
+        b = gen.rhs(m, k)
+        xr = oracle.solve(m, b)
+        x = h.solve(to_dev(b), which=sp.REWRITTEN)
+        h.check()
+        assert oracle.relerr(x.cpu().numpy(), xr) <= TOL
+
+
+@pytest.mark.parametrize("name", [n for n, _ in MATS])
+@pytest.mark.parametrize("opt", list(OPTS))
+def test_rewrite_parity(name, opt):
+    m = dict(MATS)[name]
+    o = OPTS[opt]
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(**o)
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, o["thin_metric"], o["thin_threshold"], o["fill_cap"], o["max_distance"], None, lv)
+    compare(m, h, st, rw, lv)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_rewrite_with_mask(seed):
+    m = gen.config_matrix(2, "small")[0]
+    lv = oracle.levels(m)
+    rng = np.random.default_rng(seed)
+    mask = (rng.random(lv.nlev) < 0.5).astype(np.uint8)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(0, 32, 4.0, 0, mask=to_dev(mask))
+    rw = oracle.rewrite(m, 0, 32, 4.0, 0, mask, lv)
+    compare(m, h, st, rw, lv, nrhs=(1,))
+
+
+def test_fig2_and_costmap_on_gpu():
+    m = fig2_matrix()
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(0, 100, 0.0, 0, mask=to_dev(np.array([0, 1, 1], np.uint8)))
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, 0, 100, 0.0, 0, np.array([0, 1, 1], np.uint8), lv)
+    compare(m, h, st, rw, lv, nrhs=(1,))
+    assert st["nlev_after"] == 1
+    m = costmap_matrix()
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    mask = np.array([0, 0, 1, 1, 1], np.uint8)
+    st = h.rewrite(1, 22.0, 0.0, 0, mask=to_dev(mask))
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, 1, 22.0, 0.0, 0, mask, lv)
+    compare(m, h, st, rw, lv, nrhs=(1,))
+    assert st["nlev_after"] == 3 and st["rows_rewritten"] == 5
+
+
+def test_config1_full_naive():
+    m = gen.config_matrix(1)[0]
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(0, 32, 4.0, 0)
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, 0, 32, 4.0, 0, None, lv)
+    compare(m, h, st, rw, lv, nrhs=(1,))
+    assert st["nlev_before"] == 21999 and st["nlev_after"] == 4826
+
+
+def test_rewrite_long_rows_use_global_workspace():
+    # without a fill cap and with a large budget, rewritten rows outgrow the
+    # per-wave LDS workspace and take the global-memory path
+    m = gen.window_random(1500, 7, window=40, draws=6)
+    lv = oracle.levels(m)
+    mask = np.ones(lv.nlev, np.uint8)
+    mask[0] = 0
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(0, 1e9, 0.0, 0, mask=to_dev(mask))
+    rw = oracle.rewrite(m, 0, 1e9, 0.0, 0, mask, lv)
+    assert int(np.max(np.diff(rw.t_ptr))) > 600  # exceeds the LDS workspace
+    compare(m, h, st, rw, lv, nrhs=(1,))
+
+
+def test_rewrite_errors():
+    h = sp.Handle()
+    with pytest.raises(sp.SptrsvError) as ei:
+        h.rewrite()
+    assert ei.value.name == "STATE"
+    m = gen.config_matrix(0)[0]
+    h.analyze(*dev(m))
+    with pytest.raises(sp.SptrsvError) as ei:
+        h.rewrite(thin_metric=5)
+    assert ei.value.name == "ARG"

@@ -10,6 +10,7 @@ from .matrices import (  # noqa: F401
     stencil2d_chain,
     stencil3d_tail,
     powerlaw,
+    policy_training_matrix,
     batch_window,
     rhs,
     from_dense_lower,

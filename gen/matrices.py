@@ -22,7 +22,7 @@ import numpy as np
 
 __all__ = [
     "Csr", "window_random", "stencil2d_chain", "stencil3d_tail", "powerlaw",
-    "batch_window", "rhs", "from_dense_lower", "bidiagonal", "diagonal",
+    "batch_window", "policy_training_matrix", "rhs", "from_dense_lower", "bidiagonal", "diagonal",
     "config_matrix",
 ]
 
@@ -175,6 +175,17 @@ def powerlaw(n: int = 4_000_000, seed: int = 2, mean_deg: float = 8.0, w_loc: in
     cols = np.concatenate([loc, ec])
     rows, cols = _unique_pairs(n, rows, cols)
     return _assemble(n, rows, cols, rng, f"powerlaw_n{n}_s{seed}_w{w_loc}_g{nseg}")
+
+
+def policy_training_matrix(seed: int) -> Csr:
+    """One matrix of the learned policy's training or held-out set: power-law
+    recipe with n ~ U[50k, 500k], local window ~ U{256..4096} and 0-16
+    near-serial segments of 250 rows, all drawn from ``seed``."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(50_000, 500_001))
+    w_loc = int(rng.integers(256, 4097))
+    nseg = int(rng.integers(0, 17))
+    return powerlaw(n, seed, w_loc=w_loc, nseg=nseg, seglen=250)
 
 
 def batch_window(nmat: int = 512, seed: int = 3, nmin: int = 1000, nmax: int = 50000,

@@ -248,18 +248,31 @@ sptrsv_status_t sptrsv_plan_load(sptrsv_handle_t h, const char *path);
  * rewritten into the level before it, level/nlev, log1p(rows of previous level).
  * ASYNC. */
 sptrsv_status_t sptrsv_level_features(sptrsv_handle_t h, float *d_feat, hipStream_t s);
-/* p[i] = sigmoid(MLP(feat[i])) for batch rows (ASYNC). */
-sptrsv_status_t sptrsv_mlp_forward(const float *d_params, const float *d_feat, int32_t batch, float *d_prob,
-                                   hipStream_t s);
-/* Gradient of the mean binary cross-entropy over the batch w.r.t. every
- * parameter (d_grad float[NPARAM], overwritten) and the loss (d_loss float[1]);
- * d_weight (optional, float[batch]) scales each sample's loss term. ASYNC. */
-sptrsv_status_t sptrsv_mlp_backward(const float *d_params, const float *d_feat, const float *d_label,
-                                    const float *d_weight, int32_t batch, float *d_grad, float *d_loss,
-                                    hipStream_t s);
+/* p[i] = sigmoid(MLP(f[i])) for the batch rows, f = (feat - mean) * inv_std
+ * when d_norm (float[32]: mean[16], inv_std[16]) is given, else f = feat.
+ * d_feat float[batch][16], d_prob float[batch]. ASYNC. */
+sptrsv_status_t sptrsv_mlp_forward(const float *d_params, const float *d_feat, const float *d_norm, int32_t batch,
+                                   float *d_prob, hipStream_t s);
+/* Gradient of the mean binary cross-entropy, (1/batch) sum_i w_i BCE(p_i, y_i),
+ * w.r.t. every parameter (d_grad float[NPARAM], overwritten) and that loss
+ * (d_loss float[1]); d_label float[batch] in {0,1}; d_weight (optional,
+ * float[batch], default 1); d_norm as in forward. The batch reduction has a
+ * fixed order (deterministic). ASYNC. */
+sptrsv_status_t sptrsv_mlp_backward(const float *d_params, const float *d_feat, const float *d_norm,
+                                    const float *d_label, const float *d_weight, int32_t batch, float *d_grad,
+                                    float *d_loss, hipStream_t s);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1). ASYNC. */
 sptrsv_status_t sptrsv_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t step, float lr,
                                 hipStream_t s);
+/* Measured per-level device time of one solve of the ORIGINAL or REWRITTEN
+ * matrix with every level run inside one workgroup where it fits (levels too
+ * wide for one workgroup report 0): ns per level into d_times float[nlev], from
+ * the device wall clock; the bulk phase of an LDS window is shared among its
+ * levels in proportion to their rows. b as in sptrsv_solve (nrhs columns, ld =
+ * n); the solution is discarded. Synchronous. These times label levels when the
+ * policy is trained (the change in solve time a rewrite causes). */
+sptrsv_status_t sptrsv_level_times(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, float *d_times,
+                                   hipStream_t s);
 /* mask[l] = (p[l] >= threshold) for l >= 1, mask[0] = 0: the rewrite mask of
  * the learned policy from probabilities (ASYNC). */
 sptrsv_status_t sptrsv_mlp_mask(const float *d_prob, int32_t nlev, float threshold, uint8_t *d_mask, hipStream_t s);

@@ -78,9 +78,11 @@ sptrsv_schedule_t effective_sched(const Plan &P, int32_t nrhs) {
   return P.sched;
 }
 
+}  // namespace
+
 // LDS bytes of a thin-run window holding `rows` rows, `ents` off-diagonals and
 // `nl` levels (must match the layout in k_thin_run).
-int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
+static int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
   return rows * (8 * (int64_t)nrhs + 16) + ents * 12 + 4 * (nl + 1);
 }
 
@@ -139,8 +141,6 @@ sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs) {
   P.work_nrhs = std::max(P.work_nrhs, nrhs);
   return SPTRSV_OK;
 }
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 // Plan construction: levels (longest path), stable bucketing of rows by level,

@@ -5,15 +5,17 @@
 #define PENDING(h) return set_err((h), SPTRSV_ERR_STATE, "%s: not available in this build", __func__)
 
 extern "C" {
-sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t, const int32_t *, const int64_t *, const int64_t *, const int32_t *, const int32_t *, const double *, hipStream_t) { PENDING(h); }
+sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t, const int32_t *, const int64_t *, const int64_t *,
+                                     const int32_t *, const int32_t *, const double *, hipStream_t) {
+  PENDING(h);
+}
 sptrsv_status_t sptrsv_batch_solve(sptrsv_handle_t h, int32_t, const double *, double *, hipStream_t) { PENDING(h); }
-sptrsv_status_t sptrsv_batch_solve_looped(sptrsv_handle_t h, int32_t, const double *, double *, hipStream_t) { PENDING(h); }
-sptrsv_status_t sptrsv_batch_levels(sptrsv_handle_t h, int32_t, int32_t *, int32_t *, int32_t *, hipStream_t) { PENDING(h); }
+sptrsv_status_t sptrsv_batch_solve_looped(sptrsv_handle_t h, int32_t, const double *, double *, hipStream_t) {
+  PENDING(h);
+}
+sptrsv_status_t sptrsv_batch_levels(sptrsv_handle_t h, int32_t, int32_t *, int32_t *, int32_t *, hipStream_t) {
+  PENDING(h);
+}
 sptrsv_status_t sptrsv_plan_save(sptrsv_handle_t h, const char *) { PENDING(h); }
 sptrsv_status_t sptrsv_plan_load(sptrsv_handle_t h, const char *) { PENDING(h); }
-sptrsv_status_t sptrsv_level_features(sptrsv_handle_t h, float *, hipStream_t) { PENDING(h); }
-sptrsv_status_t sptrsv_mlp_forward(const float *, const float *, int32_t, float *, hipStream_t) { return SPTRSV_ERR_STATE; }
-sptrsv_status_t sptrsv_mlp_backward(const float *, const float *, const float *, const float *, int32_t, float *, float *, hipStream_t) { return SPTRSV_ERR_STATE; }
-sptrsv_status_t sptrsv_mlp_adam(float *, const float *, float *, float *, int32_t, float, hipStream_t) { return SPTRSV_ERR_STATE; }
-sptrsv_status_t sptrsv_mlp_mask(const float *, int32_t, float, uint8_t *, hipStream_t) { return SPTRSV_ERR_STATE; }
 }

@@ -205,7 +205,7 @@ int thin_win_bytes();
 hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                            const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
-                           double *xp, int *err, hipStream_t s);
+                           double *xp, int *err, hipStream_t s, float *times = nullptr, float ns_per_tick = 0.f);
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                              const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
@@ -236,6 +236,27 @@ hipError_t launch_rewrite_rows(int32_t nrows, const int32_t *rows, const int32_t
                                const double *va, const int32_t *cur, const int32_t *target, const int32_t *lrp,
                                int32_t *lci, double *lva, const int32_t *trp, int32_t *tci, double *tva, char *big,
                                int32_t bigC, int32_t bigH, int32_t big_blocks, int *err, hipStream_t s);
+
+// Launchers (k_mlp.hip, k_rewrite.hip features) -----------------------------------
+int mlp_backward_parts();
+hipError_t launch_mlp_forward(const float *P, const float *feat, const float *norm, int32_t B, float *prob,
+                              hipStream_t s);
+hipError_t launch_mlp_backward(const float *P, const float *feat, const float *norm, const float *label,
+                               const float *weight, int32_t B, float *part, float *part_loss, float *grad,
+                               float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(float *P, const float *g, float *m, float *v, float lr, float c1, float c2,
+                           hipStream_t s);
+hipError_t launch_mlp_mask(const float *prob, int32_t nlev, float thr, uint8_t *mask, hipStream_t s);
+hipError_t launch_feat_finalize(int32_t nlev, const int64_t *rows, const int64_t *nnz, const int64_t *cost,
+                                double avg, const int32_t *hist, const long long *sum_lp, const long long *sum_t,
+                                float *feat, hipStream_t s);
+hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const int32_t *rp, const int32_t *ci,
+                            const double *va, const int32_t *lev, long long *sum_lp, long long *sum_t, int32_t *hist,
+                            int32_t *redo, int32_t *nredo, char *big, int32_t bigC, int32_t bigH, int32_t big_blocks,
+                            int *err, hipStream_t s);
+// Schedule helpers (api.hip) -----------------------------------------------------
+sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc);
+sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs);
 
 // Plan building (api.hip) --------------------------------------------------------
 sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,

@@ -523,6 +523,60 @@ __global__ void k_collect_moved(int32_t n, const int32_t *__restrict__ target, c
   }
 }
 
+// Per-row inputs of the learned policy's level features: the row's
+// off-diagonal count bin, and the sizes of L'[r] and T[r] if its level alone
+// were rewritten into the level before it (every other row in place: the B set
+// is the rows at level >= lev(r) - 1 of the original levels). Rows whose
+// rewrite outgrows the LDS workspace are listed for a second pass with a
+// global workspace.
+__global__ __launch_bounds__(64 * kWaves) void k_feat_rows(int32_t n, const int32_t *__restrict__ rows,
+                                                           int32_t nrows, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const double *__restrict__ va,
+                                                           const int32_t *__restrict__ lev, long long *sum_lp,
+                                                           long long *sum_t, int32_t *hist, int32_t *redo,
+                                                           int32_t *nredo, char *big, int32_t bigC, int32_t bigH,
+                                                           int *err) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const bool use_big = big != nullptr;
+  Ws w = use_big ? global_ws(big + (size_t)(blockIdx.x * kWaves + wave) * ((size_t)bigC * 13 + (size_t)bigH * 8 + 64),
+                             bigC, bigH)
+                 : lds_ws(lds_raw, wave);
+  const int64_t total = rows ? nrows : n;
+  const int64_t gw = (int64_t)blockIdx.x * kWaves + wave, nw = (int64_t)gridDim.x * kWaves;
+  for (int64_t i = gw; i < total; i += nw) {
+    const int32_t r = rows ? rows[i] : (int32_t)i;
+    const int32_t l = lev[r];
+    const int32_t off = rp[r + 1] - rp[r] - 1;
+    int32_t lp = off + 1, tn = 1;
+    if (l > 0) {
+      int32_t nT = 0;
+      const int stt = subst_row(w, r, l - 1, rp, ci, va, lev, INT64_MAX, &nT);
+      if (stt == SUB_OVERFLOW) {
+        if (lane == 0) {
+          if (use_big)
+            atomicOr(err, EB_OVERFLOW);
+          else
+            redo[atomicAdd(nredo, 1)] = r;
+        }
+        wave_sync();
+        continue;
+      }
+      lp = *w.na + 1;
+      tn = nT + 1;
+    }
+    if (lane == 0) {
+      atomicAdd((unsigned long long *)(sum_lp + l), (unsigned long long)lp);
+      atomicAdd((unsigned long long *)(sum_t + l), (unsigned long long)tn);
+      // counted once per row: rows sent to the second pass skipped this block
+      const int bin = off == 0 ? 0 : off == 1 ? 1 : off == 2 ? 2 : off <= 4 ? 3 : off <= 8 ? 4 : 5;
+      atomicAdd(hist + (int64_t)l * 6 + bin, 1);
+    }
+    wave_sync();
+  }
+}
+
 inline int grid_for(int64_t items, int threads, int cap) {
   int64_t g = (items + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -611,3 +665,22 @@ hipError_t launch_rewrite_rows(int32_t nrows, const int32_t *rows, const int32_t
 }
 
 int32_t rewrite_waves_per_block() { return kWaves; }
+
+hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const int32_t *rp, const int32_t *ci,
+                            const double *va, const int32_t *lev, long long *sum_lp, long long *sum_t, int32_t *hist,
+                            int32_t *redo, int32_t *nredo, char *big, int32_t bigC, int32_t bigH, int32_t big_blocks,
+                            int *err, hipStream_t s) {
+  const int64_t total = rows ? nrows : n;
+  if (total <= 0) return hipSuccess;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_feat_rows),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsWsBytes);
+    attr = true;
+  }
+  const bool use_big = big != nullptr;
+  const int blocks = use_big ? big_blocks : grid_for(total, kWaves, 4096);
+  hipLaunchKernelGGL(k_feat_rows, dim3(blocks), dim3(64 * kWaves), use_big ? 0 : kLdsWsBytes, s, n, rows, nrows, rp,
+                     ci, va, lev, sum_lp, sum_t, hist, redo, nredo, big, bigC, bigH, err);
+  return hipGetLastError();
+}

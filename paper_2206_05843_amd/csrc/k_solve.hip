@@ -68,19 +68,24 @@ __device__ __forceinline__ double row_solve(int32_t pos, int32_t c, int32_t nrhs
 // Windows whose every level has at most 64 (row, rhs) items run phase 2 on one
 // wave without workgroup barriers. win[i] = {first level, flags}; the run's last
 // entry holds the end level.
-template <int WG, bool kOne>
+// kTimed (used only to label levels for the learned policy): thread 0 stamps the
+// device wall clock around every level and writes per-level times (ns).
+template <int WG, bool kOne, bool kTimed = false>
 __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, int32_t nwin,
                                                  const int32_t *__restrict__ level_ptr, int32_t nrhs,
                                                  const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
                                                  const double *__restrict__ sva, const double *__restrict__ sdg,
                                                  const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
                                                  const double *__restrict__ tva, const double *__restrict__ bp,
-                                                 double *xp, int *err) {
+                                                 double *xp, int *err, float *times, float ns_per_tick) {
   extern __shared__ double lds[];
   const int32_t nr = kOne ? 1 : nrhs;
   const int tid = threadIdx.x;
   int bits = 0;
+  unsigned long long t_w0 = 0, t_prev = 0;
+  float p1_per_row = 0.f;
   for (int32_t w = 0; w < nwin; ++w) {
+    if (kTimed && tid == 0) t_w0 = wall_clock64();
     const int32_t lA = win[w].x, lB = win[w + 1].x, flags = win[w].y;
     const int32_t P0 = level_ptr[lA], P1 = level_ptr[lB];
     const int32_t R = P1 - P0;
@@ -125,31 +130,77 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, i
       }
       v[(int64_t)s * nr + c] = acc;
       if (c == 0) {
-        dg[s] = sdg[pos];
+        dg[s] = 1.0 / sdg[pos];  // reciprocal: one multiply on the level chain
         eo[s] = qb - E0;
         en[s] = o - (qb - E0);
       }
     }
     __syncthreads();
+    if (kTimed && tid == 0) {
+      t_prev = wall_clock64();
+      p1_per_row = R > 0 ? (float)(t_prev - t_w0) * ns_per_tick / (float)R : 0.f;
+    }
     // phase 2
     if (flags & 1) {
       if (tid < 64) {
-        for (int32_t l = 0; l < NL; ++l) {
+        // Software pipeline: everything a level needs except the x values of
+        // its dependencies (row, partial sum, reciprocal diagonal, the first
+        // four in-window dependency slots and values) is loaded before the
+        // previous level's wave barrier.
+        struct Pre {
+          bool act;
+          int32_t s, c, o, k;
+          double acc, dinv;
+          int32_t e0, e1, e2, e3;
+          double w0, w1, w2, w3;
+        };
+        auto fetch = [&](int32_t l) {
+          Pre p;
           const int32_t pb = lv[l], items = (lv[l + 1] - pb) * nr;
-          if (tid < items) {
-            const int32_t s = kOne ? pb + tid : pb + tid / nr;
-            const int32_t c = kOne ? 0 : tid - (s - pb) * nr;
-            double acc = v[(int64_t)s * nr + c];
-            const int32_t o = eo[s], k = en[s];
-            for (int32_t i = 0; i < k; ++i) acc -= ev[o + i] * v[(int64_t)es[o + i] * nr + c];
-            const double x = acc / dg[s];
-            if (!isfinite(x)) bits |= EB_NONFINITE;
-            v[(int64_t)s * nr + c] = x;
-            xp[(int64_t)(P0 + s) * nr + c] = x;
+          p.act = tid < items;
+          p.s = kOne ? pb + tid : pb + tid / nr;
+          p.c = kOne ? 0 : tid - (p.s - pb) * nr;
+          p.acc = 0.0, p.dinv = 0.0, p.o = 0, p.k = 0;
+          p.e0 = p.e1 = p.e2 = p.e3 = 0;
+          p.w0 = p.w1 = p.w2 = p.w3 = 0.0;
+          if (p.act) {
+            p.acc = v[(int64_t)p.s * nr + p.c];
+            p.dinv = dg[p.s];
+            p.o = eo[p.s];
+            p.k = en[p.s];
+            if (p.k > 0) p.e0 = es[p.o], p.w0 = ev[p.o];
+            if (p.k > 1) p.e1 = es[p.o + 1], p.w1 = ev[p.o + 1];
+            if (p.k > 2) p.e2 = es[p.o + 2], p.w2 = ev[p.o + 2];
+            if (p.k > 3) p.e3 = es[p.o + 3], p.w3 = ev[p.o + 3];
           }
+          return p;
+        };
+        Pre cur = fetch(0);
+        for (int32_t l = 0; l < NL; ++l) {
+          if (cur.act) {
+            const int32_t c = cur.c;
+            double acc = cur.acc;
+            if (cur.k > 0) acc -= cur.w0 * v[(int64_t)cur.e0 * nr + c];
+            if (cur.k > 1) acc -= cur.w1 * v[(int64_t)cur.e1 * nr + c];
+            if (cur.k > 2) acc -= cur.w2 * v[(int64_t)cur.e2 * nr + c];
+            if (cur.k > 3) acc -= cur.w3 * v[(int64_t)cur.e3 * nr + c];
+            for (int32_t i = 4; i < cur.k; ++i) acc -= ev[cur.o + i] * v[(int64_t)es[cur.o + i] * nr + c];
+            const double x = acc * cur.dinv;
+            if (!isfinite(x)) bits |= EB_NONFINITE;
+            v[(int64_t)cur.s * nr + c] = x;
+            xp[(int64_t)(P0 + cur.s) * nr + c] = x;
+          }
+          Pre nxt{};
+          if (l + 1 < NL) nxt = fetch(l + 1);
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+          if (kTimed && tid == 0) {
+            const unsigned long long now = wall_clock64();
+            times[lA + l] = (float)(now - t_prev) * ns_per_tick + p1_per_row * (float)(lv[l + 1] - lv[l]);
+            t_prev = now;
+          }
+          cur = nxt;
         }
       }
     } else {
@@ -161,12 +212,17 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, i
           double acc = v[(int64_t)s * nr + c];
           const int32_t o = eo[s], k = en[s];
           for (int32_t i = 0; i < k; ++i) acc -= ev[o + i] * v[(int64_t)es[o + i] * nr + c];
-          const double x = acc / dg[s];
+          const double x = acc * dg[s];
           if (!isfinite(x)) bits |= EB_NONFINITE;
           v[(int64_t)s * nr + c] = x;
           xp[(int64_t)(P0 + s) * nr + c] = x;
         }
         lds_barrier();
+        if (kTimed && tid == 0) {
+          const unsigned long long now = wall_clock64();
+          times[lA + l] = (float)(now - t_prev) * ns_per_tick + p1_per_row * (float)(lv[l + 1] - lv[l]);
+          t_prev = now;
+        }
       }
     }
     __syncthreads();  // the window's global x is complete before the next phase 1 reads it
@@ -322,6 +378,10 @@ void solve_kernels_init() {
   set_lds_attr<512, false>();
   set_lds_attr<1024, true>();
   set_lds_attr<1024, false>();
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_thin_run<512, true, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_thin_run<512, false, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
 }
 
 hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
@@ -347,15 +407,24 @@ hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32
 hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                            const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
-                           double *xp, int *err, hipStream_t s) {
+                           double *xp, int *err, hipStream_t s, float *times, float ns_per_tick) {
   const bool one = nrhs == 1;
+  if (times) {  // labelling runs only: 512 threads
+    if (one)
+      hipLaunchKernelGGL((k_thin_run<512, true, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, level_ptr, nrhs,
+                         srp, sci, sva, sdg, trp, tci, tva, bp, xp, err, times, ns_per_tick);
+    else
+      hipLaunchKernelGGL((k_thin_run<512, false, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, level_ptr, nrhs,
+                         srp, sci, sva, sdg, trp, tci, tva, bp, xp, err, times, ns_per_tick);
+    return hipGetLastError();
+  }
 #define THIN(W)                                                                                                   \
   if (one)                                                                                                        \
     hipLaunchKernelGGL((k_thin_run<W, true>), dim3(1), dim3(W), kWinBytes, s, win, nwin, level_ptr, nrhs, srp, sci, \
-                       sva, sdg, trp, tci, tva, bp, xp, err);                                                     \
+                       sva, sdg, trp, tci, tva, bp, xp, err, (float *)nullptr, 0.f);                              \
   else                                                                                                            \
     hipLaunchKernelGGL((k_thin_run<W, false>), dim3(1), dim3(W), kWinBytes, s, win, nwin, level_ptr, nrhs, srp,     \
-                       sci, sva, sdg, trp, tci, tva, bp, xp, err);
+                       sci, sva, sdg, trp, tci, tva, bp, xp, err, (float *)nullptr, 0.f);
   if (wg == 256) {
     THIN(256)
   } else if (wg == 1024) {

@@ -28,7 +28,7 @@ EXPORTS = [
     "sptrsv_autotune", "sptrsv_graph_create", "sptrsv_graph_launch", "sptrsv_residual", "sptrsv_batch_analyze",
     "sptrsv_batch_solve", "sptrsv_batch_solve_looped", "sptrsv_batch_levels", "sptrsv_plan_save",
     "sptrsv_plan_load", "sptrsv_level_features", "sptrsv_mlp_forward", "sptrsv_mlp_backward", "sptrsv_mlp_adam",
-    "sptrsv_mlp_mask", "sptrsv_profile",
+    "sptrsv_mlp_mask", "sptrsv_profile", "sptrsv_level_times",
 ]
 
 
@@ -108,8 +108,9 @@ def lib():
         "sptrsv_plan_save": [vp, C.c_char_p],
         "sptrsv_plan_load": [vp, C.c_char_p],
         "sptrsv_level_features": [vp, vp, vp],
-        "sptrsv_mlp_forward": [vp, vp, i32, vp, vp],
-        "sptrsv_mlp_backward": [vp, vp, vp, vp, i32, vp, vp, vp],
+        "sptrsv_mlp_forward": [vp, vp, vp, i32, vp, vp],
+        "sptrsv_mlp_backward": [vp, vp, vp, vp, vp, i32, vp, vp, vp],
+        "sptrsv_level_times": [vp, C.c_int, i32, vp, vp, vp],
         "sptrsv_mlp_adam": [vp, vp, vp, vp, i32, f32, vp],
         "sptrsv_mlp_mask": [vp, i32, f32, vp, vp],
         "sptrsv_profile": [vp, C.c_int, vp, vp],
@@ -147,19 +148,20 @@ def _check_free(st: int, msg: str = ""):
         raise SptrsvError(st, msg)
 
 
-def mlp_forward(params, feat, prob=None):
+def mlp_forward(params, feat, norm=None, prob=None):
     B = feat.shape[0]
     prob = prob if prob is not None else torch.empty(B, dtype=torch.float32, device=feat.device)
-    _check_free(lib().sptrsv_mlp_forward(_ptr(params), _ptr(feat), B, _ptr(prob), _stream()), "mlp_forward")
+    _check_free(lib().sptrsv_mlp_forward(_ptr(params), _ptr(feat), _ptr(norm), B, _ptr(prob), _stream()),
+                "mlp_forward")
     return prob
 
 
-def mlp_backward(params, feat, label, weight=None):
+def mlp_backward(params, feat, label, weight=None, norm=None):
     B = feat.shape[0]
     grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=feat.device)
     loss = torch.empty(1, dtype=torch.float32, device=feat.device)
-    _check_free(lib().sptrsv_mlp_backward(_ptr(params), _ptr(feat), _ptr(label), _ptr(weight), B, _ptr(grad),
-                                          _ptr(loss), _stream()), "mlp_backward")
+    _check_free(lib().sptrsv_mlp_backward(_ptr(params), _ptr(feat), _ptr(norm), _ptr(label), _ptr(weight), B,
+                                          _ptr(grad), _ptr(loss), _stream()), "mlp_backward")
     return grad, loss
 
 
@@ -374,6 +376,14 @@ class Handle:
         self._check(self._L.sptrsv_plan_load(self._h, path.encode()))
 
     # ------------------------------------------------------------ learned policy
+    def level_times(self, b, which=ORIGINAL):
+        """Per-level device time (ns) of one solve with every level in one workgroup."""
+        bb = b if b.dim() == 2 else b.view(1, -1)
+        nlev = self.nlev if which == ORIGINAL else self.rstats["nlev_after"]
+        t = torch.empty(nlev, dtype=torch.float32, device="cuda")
+        self._check(self._L.sptrsv_level_times(self._h, which, bb.shape[0], _ptr(bb.contiguous()), _ptr(t), _stream()))
+        return t
+
     def level_features(self):
         f = torch.empty((self.nlev, 16), dtype=torch.float32, device="cuda")
         self._check(self._L.sptrsv_level_features(self._h, _ptr(f), _stream()))

@@ -1,0 +1,122 @@
+"""GPU parity of the learned policy's kernels: level features against the
+oracle's, and the network's forward, backward (gradients) and Adam against
+the FP64 network oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from oracle import mlp
+from tests.gpu_util import dev, to_dev
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_2206_05843_amd")
+
+
+@pytest.mark.parametrize("mk", [lambda: gen.config_matrix(0)[0], lambda: gen.config_matrix(1, "small")[0],
+                                lambda: gen.config_matrix(2, "small")[0], lambda: gen.window_random(3000, 5, 30, 9)])
+def test_features_match_oracle(mk):
+    m = mk()
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    f = h.level_features().cpu().numpy().astype(np.float64)
+    fo = oracle.level_features(m)
+    np.testing.assert_allclose(f, fo, rtol=2e-6, atol=1e-6)
+
+
+def _batch(seed, B=300):
+    rng = np.random.default_rng(seed)
+    f = rng.normal(size=(B, 16))
+    y = (rng.random(B) < 0.3).astype(np.float64)
+    th = mlp.init(seed) + rng.normal(scale=0.05, size=mlp.NPARAM)
+    return th.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64), y
+
+
+def test_forward_matches_oracle():
+    th, f, _ = _batch(1)
+    p = sp.mlp_forward(to_dev(th, torch.float32), to_dev(f, torch.float32)).cpu().numpy()
+    po, _ = mlp.forward(th, f)
+    np.testing.assert_allclose(p, po, rtol=1e-5, atol=1e-6)
+
+
+def test_forward_normalisation():
+    th, f, _ = _batch(2)
+    mean = np.linspace(-1, 1, 16)
+    inv = np.linspace(0.5, 2, 16)
+    norm = np.concatenate([mean, inv]).astype(np.float32)
+    p = sp.mlp_forward(to_dev(th, torch.float32), to_dev(f, torch.float32), to_dev(norm)).cpu().numpy()
+    fz = (f - norm[:16].astype(np.float64)) * norm[16:].astype(np.float64)
+    po, _ = mlp.forward(th, fz)
+    np.testing.assert_allclose(p, po, rtol=2e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("B", [1, 7, 300, 1100])
+def test_backward_matches_oracle(B):
+    th, f, y = _batch(3, B)
+    g, loss = sp.mlp_backward(to_dev(th, torch.float32), to_dev(f, torch.float32), to_dev(y, torch.float32))
+    go, lo = mlp.backward(th, f, y)
+    g = g.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+    np.testing.assert_allclose(g, go, rtol=1e-3, atol=1e-6 * np.abs(go).max())
+    assert abs(float(loss) - lo) <= 1e-5 * abs(lo)
+
+
+def test_backward_weights_and_determinism():
+    th, f, y = _batch(4)
+    P, F, Y = to_dev(th, torch.float32), to_dev(f, torch.float32), to_dev(y, torch.float32)
+    g1, l1 = sp.mlp_backward(P, F, Y)
+    g2, l2 = sp.mlp_backward(P, F, Y, weight=torch.ones_like(Y))
+    g3, _ = sp.mlp_backward(P, F, Y)
+    assert torch.equal(g1, g3)  # fixed reduction order
+    assert torch.allclose(g1, g2) and torch.allclose(l1, l2)
+    g4, l4 = sp.mlp_backward(P, F, Y, weight=2 * torch.ones_like(Y))
+    assert torch.allclose(g4, 2 * g1, rtol=1e-6, atol=1e-9) and torch.allclose(l4, 2 * l1)
+
+
+def test_adam_matches_oracle():
+    th, f, y = _batch(5)
+    P = to_dev(th, torch.float32)
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    tho, mo, vo = th.copy(), np.zeros_like(th), np.zeros_like(th)
+    F, Y = to_dev(f, torch.float32), to_dev(y, torch.float32)
+    for step in range(1, 6):
+        g, _ = sp.mlp_backward(P, F, Y)
+        go = g.cpu().numpy().astype(np.float64)  # same gradient for both updates
+        sp.mlp_adam(P, g, m, v, step, 1e-3)
+        tho, mo, vo = mlp.adam(tho, go, mo, vo, step, 1e-3)
+    np.testing.assert_allclose(P.cpu().numpy(), tho, rtol=1e-5, atol=1e-6)
+
+
+def test_training_reduces_loss_on_separable_data():
+    rng = np.random.default_rng(9)
+    f = rng.normal(size=(512, 16)).astype(np.float32)
+    y = (f[:, 0] + 0.5 * f[:, 3] > 0).astype(np.float32)
+    P = to_dev(mlp.init(0), torch.float32)
+    m, v = torch.zeros_like(P), torch.zeros_like(P)
+    F, Y = to_dev(f), to_dev(y)
+    losses = []
+    for step in range(1, 201):
+        g, loss = sp.mlp_backward(P, F, Y)
+        sp.mlp_adam(P, g, m, v, step, 3e-3)
+        losses.append(float(loss))
+    assert losses[-1] < 0.2 * losses[0]
+    acc = ((sp.mlp_forward(P, F) >= 0.5).float() == Y).float().mean()
+    assert float(acc) > 0.95
+
+
+def test_mask():
+    p = torch.tensor([0.9, 0.2, 0.5, 0.7, 0.49], device="cuda")
+    assert sp.mlp_mask(p, 0.5).cpu().tolist() == [0, 0, 1, 1, 0]
+
+
+def test_level_times():
+    m = gen.config_matrix(1, "small")[0]
+    h = sp.Handle()
+    nlev = h.analyze(*dev(m))
+    b = to_dev(gen.rhs(m, 1)[0])
+    t = h.level_times(b).cpu().numpy()
+    assert t.shape == (nlev,) and np.all(t >= 0) and t.sum() > 0
+    x = h.solve(b)  # ordinary solves still right after a timed run
+    assert oracle.relerr(x.cpu().numpy()[None], oracle.solve(m, b.cpu().numpy()[None])) <= 1e-10

@@ -83,7 +83,7 @@ sptrsv_schedule_t effective_sched(const Plan &P, int32_t nrhs) {
 // LDS bytes of a thin-run window holding `rows` rows, `ents` off-diagonals and
 // `nl` levels (must match the layout in k_thin_run).
 static int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
-  return rows * (8 * (int64_t)nrhs + 16) + ents * 12 + 4 * (nl + 1);
+  return rows * (8 * (int64_t)nrhs + 40) + ents * 16 + 4 * (nl + 1);
 }
 
 sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc) {
@@ -92,7 +92,7 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
   const int64_t cap = thin_win_bytes();
   const int64_t thr = sc.thin_rows;
   auto rows_of = [&](int32_t l) -> int64_t { return P.h_level_ptr[l + 1] - P.h_level_ptr[l]; };
-  auto offd_of = [&](int32_t l) -> int64_t { return P.h_lv_nnz[l] - rows_of(l); };
+  auto offd_of = [&](int32_t l) -> int64_t { return P.h_lv_ovf[l]; };  // overflow dependency records
   for (int32_t l = 0; l < P.nlev; ++l) {
     const int64_t rows = rows_of(l);
     bool thin = sc.mode == 2 || (sc.mode == 0 && rows <= thr);
@@ -102,26 +102,26 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
     else
       P.runs.push_back(Run{l, l + 1, thin});
   }
-  // cut every thin run into LDS windows; flag windows whose levels fit one wave
+  // cut every thin run into LDS windows; flag windows whose levels fit one
+  // wave (bit 0) or one item per thread of the workgroup (bit 1)
   for (Run &r : P.runs) {
     if (!r.thin) continue;
     r.wi = (int32_t)P.h_win.size();
     int32_t ws = r.l0;
-    int64_t rows = 0, ents = 0;
-    bool one_wave = true;
+    int64_t rows = 0, ents = 0, maxit = 0;
+    auto flags = [&]() { return (maxit <= 64 ? 1 : 0) | (maxit <= sc.wg_threads ? 2 : 0); };
     for (int32_t l = r.l0; l < r.l1; ++l) {
       const int64_t rl = rows_of(l), el = offd_of(l);
       if (l > ws && win_bytes(rows + rl, ents + el, l - ws + 1, nrhs) > cap) {
-        P.h_win.push_back(int2{ws, one_wave ? 1 : 0});
+        P.h_win.push_back(int2{ws, flags()});
         ws = l;
-        rows = ents = 0;
-        one_wave = true;
+        rows = ents = maxit = 0;
       }
       rows += rl;
       ents += el;
-      one_wave = one_wave && rl * nrhs <= 64;
+      maxit = std::max<int64_t>(maxit, rl * nrhs);
     }
-    P.h_win.push_back(int2{ws, one_wave ? 1 : 0});
+    P.h_win.push_back(int2{ws, flags()});
     r.nw = (int32_t)P.h_win.size() - r.wi;
     P.h_win.push_back(int2{r.l1, 0});
   }
@@ -210,6 +210,12 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   HIPCHK(h, P.sva.alloc((size_t)std::max<int64_t>(noff, 1)));
   HIPCHK(h, P.sdg.alloc(n));
   HIPCHK(h, launch_fill_solve(n, P.perm.p, P.iperm.p, rp, ci, va, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, s));
+  HIPCHK(h, P.ovp.alloc((size_t)n + 1));
+  HIPCHK(h, launch_count_ovf(P.srp.p, n, cnt.p, s));
+  HIPCHK(h, launch_scan_i64(cnt.p, ex.p, n, h->scan_tmp.p, s));
+  HIPCHK(h, launch_ptr_from_scan(ex.p, cnt.p, n, P.ovp.p, aux + 1, s));
+  std::vector<int32_t> hovp((size_t)n + 1);
+  HIPCHK(h, hipMemcpyAsync(hovp.data(), P.ovp.p, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
   if (trp) {
     P.has_t = true;
     HIPCHK(h, P.trp.alloc((size_t)n + 1));
@@ -243,6 +249,9 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   HIPCHK(h, hipMemcpyAsync(haux, aux, sizeof(haux), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   if (haux[1]) return set_err(h, status_from_bits(haux[1]), "plan construction failed (bits 0x%x)", haux[1]);
+  P.h_lv_ovf.resize((size_t)nlev);
+  for (int32_t l = 0; l < nlev; ++l)
+    P.h_lv_ovf[(size_t)l] = hovp[(size_t)P.h_level_ptr[l + 1]] - hovp[(size_t)P.h_level_ptr[l]];
   if (P.has_t) {
     P.h_lv_tnnz.resize((size_t)nlev);
     for (int32_t l = 0; l < nlev; ++l)
@@ -300,7 +309,7 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
     slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
     if (r.thin) {
       HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, P.level_ptr.p, nrhs, P.srp.p, P.sci.p, P.sva.p,
-                                P.sdg.p,
+                                P.sdg.p, P.ovp.p,
                                 trp, P.tci.p, P.tva.p, P.bp.p, P.xp.p, err, s));
     } else {
       HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,

@@ -107,7 +107,7 @@ sptrsv_status_t sptrsv_level_times(sptrsv_handle_t h, int which, int32_t nrhs, c
   for (const Run &r : P->runs) {
     if (r.thin) {
       HIPCHK(h, launch_thin_run(512, P->win.p + r.wi, r.nw, P->level_ptr.p, nrhs, P->srp.p, P->sci.p, P->sva.p,
-                                P->sdg.p, trp, P->tci.p, P->tva.p, P->bp.p, P->xp.p, h->d_err.p, s, d_times,
+                                P->sdg.p, P->ovp.p, trp, P->tci.p, P->tva.p, P->bp.p, P->xp.p, h->d_err.p, s, d_times,
                                 ns_per_tick));
     } else {
       HIPCHK(h, launch_wide_level(256, 1, P->h_level_ptr[r.l0], P->h_level_ptr[r.l1], nrhs, P->srp.p, P->sci.p,

@@ -90,6 +90,8 @@ struct Plan {
   DArr<int64_t> lv_rows, lv_nnz, lv_cost;
   std::vector<int64_t> h_lv_nnz;       // per level: nnz incl. diagonal (host copy)
   std::vector<int64_t> h_lv_tnnz;      // per level: off-diagonal nnz of T
+  DArr<int32_t> ovp;                   // [n+1] prefix of max(0, off-diagonals - 2) per position
+  std::vector<int64_t> h_lv_ovf;       // per level: sum of max(0, off-diagonals - 2)
   int64_t total_cost = 0;
   double avg_cost = 0.0;
   sptrsv_schedule_t sched{};           // knobs in force (mode 0 = automatic)
@@ -202,9 +204,10 @@ hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, 
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
 int thin_win_bytes();
+hipError_t launch_count_ovf(const int32_t *srp, int32_t n, long long *cnt, hipStream_t s);
 hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                           const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
+                           const int32_t *ovp, const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
                            double *xp, int *err, hipStream_t s, float *times = nullptr, float ns_per_tick = 0.f);
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,

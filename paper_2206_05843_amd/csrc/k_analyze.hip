@@ -459,3 +459,19 @@ hipError_t launch_level_stats(int32_t nlev, const int32_t *level_ptr, const int3
                      rows, nnz, cost, total);
   return hipGetLastError();
 }
+
+namespace {
+// Dependencies beyond the first two of each row (the solve keeps two per row
+// in a fixed record and lists the rest).
+__global__ void k_count_ovf(const int32_t *__restrict__ srp, int32_t n, long long *cnt) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t k = srp[p + 1] - srp[p] - 2;
+    cnt[p] = k > 0 ? k : 0;
+  }
+}
+}  // namespace
+
+hipError_t launch_count_ovf(const int32_t *srp, int32_t n, long long *cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_ovf, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, srp, n, cnt);
+  return hipGetLastError();
+}

@@ -59,25 +59,99 @@ __device__ __forceinline__ double row_solve(int32_t pos, int32_t c, int32_t nrhs
 }
 
 // A thin run is cut into LDS windows (consecutive levels, chosen on the host so
-// that the window's rows and off-diagonals fit in LDS). Per window:
+// that the window's rows and dependency records fit in LDS). Per window:
 //  phase 1 (all rows in parallel): v = b' - sum of L(pos,k) x(k) over the
-//    dependencies k that precede the window (final values, read from global),
-//    and the dependencies inside the window are copied into LDS (slot, value);
-//  phase 2 (level by level): x = (v - sum over in-window dependencies) / diag,
+//    dependencies k that precede the window (final values, read from global);
+//    the dependencies inside the window go to a 32-byte record per row
+//    {w0, w1 | slot0, slot1, count, first overflow}; a row's third and later
+//    in-window dependencies go to an overflow list of {value, slot} records
+//    (its offset is a precomputed prefix sum, ovp);
+//  phase 2 (level by level): x = (v - sum over in-window dependencies) * (1/diag),
 //    reading and writing LDS only; the global copy of x is written as well.
-// Windows whose every level has at most 64 (row, rhs) items run phase 2 on one
-// wave without workgroup barriers. win[i] = {first level, flags}; the run's last
-// entry holds the end level.
+// When every level of the window has at most one item per thread, phase 2 is
+// software-pipelined: the next level's records are requested before the
+// current level is computed, and the level bounds are read from registers,
+// so a level waits only for the x values it reads. Windows whose levels have
+// at most 64 items run phase 2 on one wave without workgroup barriers.
+// win[i] = {first level, flags}; the run's last entry holds the end level.
 // kTimed (used only to label levels for the learned policy): thread 0 stamps the
 // device wall clock around every level and writes per-level times (ns).
+struct __align__(16) Dep {
+  double w;
+  int32_t slot, pad;
+};
+
+constexpr int kBatch = 8;
+
+// acc - sum_j w_j x(slot_j, c) over n overflow records starting at d, in order,
+// in batches of 8 (tail clamped to a valid record).
+template <bool kOne>
+__device__ __forceinline__ double ovf_sum(double acc, const Dep *__restrict__ d, int32_t n, const double *v,
+                                          int32_t nr, int32_t c) {
+  for (int32_t i0 = 0; i0 < n; i0 += kBatch) {
+    const int32_t cnt = n - i0;
+    double w[kBatch];
+    int32_t e[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const Dep dj = d[i0 + (j < cnt ? j : 0)];
+      w[j] = dj.w;
+      e[j] = dj.slot;
+    }
+    double xv[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) xv[j] = v[(int64_t)e[j] * (kOne ? 1 : nr) + c];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) acc = j < cnt ? acc - w[j] * xv[j] : acc;
+  }
+  return acc;
+}
+
+// The static inputs of one (row, rhs) item in phase 2.
+struct Item {
+  double acc, dinv, w0, w1;
+  int4 ri;  // slot0, slot1, count, first overflow record
+  int32_t s, c, act;
+};
+
+template <bool kOne>
+__device__ __forceinline__ Item load_item(int32_t pb, int32_t items, int32_t t, int32_t nr, const double *v,
+                                          const double *dg, const double2 *rw, const int4 *rix) {
+  Item it;
+  it.act = t < items;
+  it.s = kOne ? pb + t : pb + t / nr;
+  it.c = kOne ? 0 : t - (it.s - pb) * nr;
+  const int32_t ss = it.act ? it.s : pb;
+  const double2 w = rw[ss];
+  it.w0 = w.x;
+  it.w1 = w.y;
+  it.ri = rix[ss];
+  it.dinv = dg[ss];
+  it.acc = v[(int64_t)ss * nr + (it.act ? it.c : 0)];
+  return it;
+}
+
+template <bool kOne>
+__device__ __forceinline__ double solve_item(const Item &it, int32_t nr, const double *v, const Dep *ovf) {
+  const int32_t k = it.ri.z, c = it.c;
+  const double xa = v[(int64_t)(k > 0 ? it.ri.x : 0) * nr + c];
+  const double xb = v[(int64_t)(k > 1 ? it.ri.y : 0) * nr + c];
+  double acc = it.acc;
+  acc = k > 0 ? acc - it.w0 * xa : acc;
+  acc = k > 1 ? acc - it.w1 * xb : acc;
+  if (k > 2) acc = ovf_sum<kOne>(acc, ovf + it.ri.w, k - 2, v, nr, c);
+  return acc * it.dinv;
+}
+
 template <int WG, bool kOne, bool kTimed = false>
 __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, int32_t nwin,
                                                  const int32_t *__restrict__ level_ptr, int32_t nrhs,
                                                  const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
                                                  const double *__restrict__ sva, const double *__restrict__ sdg,
-                                                 const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
-                                                 const double *__restrict__ tva, const double *__restrict__ bp,
-                                                 double *xp, int *err, float *times, float ns_per_tick) {
+                                                 const int32_t *__restrict__ ovp, const int32_t *__restrict__ trp,
+                                                 const int32_t *__restrict__ tci, const double *__restrict__ tva,
+                                                 const double *__restrict__ bp, double *xp, int *err, float *times,
+                                                 float ns_per_tick) {
   extern __shared__ double lds[];
   const int32_t nr = kOne ? 1 : nrhs;
   const int tid = threadIdx.x;
@@ -89,20 +163,19 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, i
     const int32_t lA = win[w].x, lB = win[w + 1].x, flags = win[w].y;
     const int32_t P0 = level_ptr[lA], P1 = level_ptr[lB];
     const int32_t R = P1 - P0;
-    const int32_t E0 = srp[P0], E = srp[P1] - E0;
+    const int32_t O0 = ovp[P0], NO = ovp[P1] - O0;
     const int32_t NL = lB - lA;
-    const int64_t need = (int64_t)R * (8 * nr + 16) + (int64_t)E * 12 + 4 * (int64_t)(NL + 1);
+    const int64_t need = (int64_t)R * (8 * nr + 40) + (int64_t)NO * 16 + 4 * (int64_t)(NL + 1);
     if (need > kWinBytes) {  // the host sizes windows to fit; never index past LDS
       if (tid == 0) atomicOr(err, EB_ARG);
       return;
     }
-    double *v = lds;            // [R * nr] partial sums, then x
-    double *dg = v + (int64_t)R * nr;  // [R]
-    double *ev = dg + R;        // [E] in-window dependency values
-    int32_t *es = reinterpret_cast<int32_t *>(ev + E);  // [E] in-window dependency slots
-    int32_t *eo = es + E;       // [R] first entry of each row
-    int32_t *en = eo + R;       // [R] number of in-window entries
-    int32_t *lv = en + R;       // [NL + 1] level boundaries, relative to P0
+    double2 *rw = reinterpret_cast<double2 *>(lds);          // [R] w0, w1
+    int4 *rix = reinterpret_cast<int4 *>(rw + R);             // [R] slot0, slot1, count, overflow
+    Dep *ovf = reinterpret_cast<Dep *>(rix + R);              // [NO] third and later dependencies
+    double *v = reinterpret_cast<double *>(ovf + NO);         // [R * nr] partial sums, then x
+    double *dg = v + (int64_t)R * nr;                         // [R] 1 / diagonal
+    int32_t *lv = reinterpret_cast<int32_t *>(dg + R);        // [NL + 1] level bounds, relative to P0
     for (int32_t i = tid; i <= NL; i += WG) lv[i] = level_ptr[lA + i] - P0;
     // phase 1
     for (int32_t it = tid; it < R * nr; it += WG) {
@@ -115,24 +188,35 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, i
         for (int32_t q = tb; q < te; ++q) acc += tva[q] * bp[(int64_t)tci[q] * nr + c];
       }
       const int32_t qb = srp[pos], qe = srp[pos + 1];
-      int32_t o = qb - E0;
+      const int32_t ob = ovp[pos] - O0;
+      int32_t kin = 0, s0 = 0, s1 = 0;
+      double w0 = 0.0, w1 = 0.0;
       for (int32_t q = qb; q < qe; ++q) {
         const int32_t k = sci[q];
         if (k < P0) {
           acc -= sva[q] * xp[(int64_t)k * nr + c];
         } else {
-          if (c == 0) {
-            es[o] = k - P0;
-            ev[o] = sva[q];
+          if (kin == 0) {
+            s0 = k - P0;
+            w0 = sva[q];
+          } else if (kin == 1) {
+            s1 = k - P0;
+            w1 = sva[q];
+          } else if (c == 0) {
+            Dep d;
+            d.w = sva[q];
+            d.slot = k - P0;
+            d.pad = 0;
+            ovf[ob + kin - 2] = d;
           }
-          ++o;
+          ++kin;
         }
       }
       v[(int64_t)s * nr + c] = acc;
       if (c == 0) {
         dg[s] = 1.0 / sdg[pos];  // reciprocal: one multiply on the level chain
-        eo[s] = qb - E0;
-        en[s] = o - (qb - E0);
+        rw[s] = make_double2(w0, w1);
+        rix[s] = make_int4(s0, s1, kin, ob);
       }
     }
     __syncthreads();
@@ -141,60 +225,42 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, i
       p1_per_row = R > 0 ? (float)(t_prev - t_w0) * ns_per_tick / (float)R : 0.f;
     }
     // phase 2
-    if (flags & 1) {
-      if (tid < 64) {
-        // Software pipeline: everything a level needs except the x values of
-        // its dependencies (row, partial sum, reciprocal diagonal, the first
-        // four in-window dependency slots and values) is loaded before the
-        // previous level's wave barrier.
-        struct Pre {
-          bool act;
-          int32_t s, c, o, k;
-          double acc, dinv;
-          int32_t e0, e1, e2, e3;
-          double w0, w1, w2, w3;
-        };
-        auto fetch = [&](int32_t l) {
-          Pre p;
-          const int32_t pb = lv[l], items = (lv[l + 1] - pb) * nr;
-          p.act = tid < items;
-          p.s = kOne ? pb + tid : pb + tid / nr;
-          p.c = kOne ? 0 : tid - (p.s - pb) * nr;
-          p.acc = 0.0, p.dinv = 0.0, p.o = 0, p.k = 0;
-          p.e0 = p.e1 = p.e2 = p.e3 = 0;
-          p.w0 = p.w1 = p.w2 = p.w3 = 0.0;
-          if (p.act) {
-            p.acc = v[(int64_t)p.s * nr + p.c];
-            p.dinv = dg[p.s];
-            p.o = eo[p.s];
-            p.k = en[p.s];
-            if (p.k > 0) p.e0 = es[p.o], p.w0 = ev[p.o];
-            if (p.k > 1) p.e1 = es[p.o + 1], p.w1 = ev[p.o + 1];
-            if (p.k > 2) p.e2 = es[p.o + 2], p.w2 = ev[p.o + 2];
-            if (p.k > 3) p.e3 = es[p.o + 3], p.w3 = ev[p.o + 3];
+    if (flags & 3) {
+      const bool one_wave = flags & 1;
+      if (!one_wave || tid < 64) {
+        const int lane = tid & 63;
+        int32_t lvbase = 0;
+        int32_t lvreg = lv[lane <= NL ? lane : NL];
+        auto bounds = [&](int32_t l, int32_t &pb, int32_t &items) {
+          if (l - lvbase >= 63) {
+            lvbase += 63;
+            lvreg = lv[lvbase + lane <= NL ? lvbase + lane : NL];
           }
-          return p;
+          pb = __builtin_amdgcn_readlane(lvreg, l - lvbase);
+          items = (__builtin_amdgcn_readlane(lvreg, l - lvbase + 1) - pb) * nr;
         };
-        Pre cur = fetch(0);
+        int32_t pb, items;
+        bounds(0, pb, items);
+        Item cur = load_item<kOne>(pb, items, tid, nr, v, dg, rw, rix);
         for (int32_t l = 0; l < NL; ++l) {
-          if (cur.act) {
-            const int32_t c = cur.c;
-            double acc = cur.acc;
-            if (cur.k > 0) acc -= cur.w0 * v[(int64_t)cur.e0 * nr + c];
-            if (cur.k > 1) acc -= cur.w1 * v[(int64_t)cur.e1 * nr + c];
-            if (cur.k > 2) acc -= cur.w2 * v[(int64_t)cur.e2 * nr + c];
-            if (cur.k > 3) acc -= cur.w3 * v[(int64_t)cur.e3 * nr + c];
-            for (int32_t i = 4; i < cur.k; ++i) acc -= ev[cur.o + i] * v[(int64_t)es[cur.o + i] * nr + c];
-            const double x = acc * cur.dinv;
-            if (!isfinite(x)) bits |= EB_NONFINITE;
-            v[(int64_t)cur.s * nr + c] = x;
-            xp[(int64_t)(P0 + cur.s) * nr + c] = x;
+          Item nxt = cur;
+          if (l + 1 < NL) {
+            bounds(l + 1, pb, items);
+            nxt = load_item<kOne>(pb, items, tid, nr, v, dg, rw, rix);
           }
-          Pre nxt{};
-          if (l + 1 < NL) nxt = fetch(l + 1);
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+          if (cur.act) {
+            const double x = solve_item<kOne>(cur, nr, v, ovf);
+            if (!isfinite(x)) bits |= EB_NONFINITE;
+            v[(int64_t)cur.s * nr + cur.c] = x;
+            xp[(int64_t)(P0 + cur.s) * nr + cur.c] = x;
+          }
+          if (one_wave) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+          } else {
+            lds_barrier();
+          }
           if (kTimed && tid == 0) {
             const unsigned long long now = wall_clock64();
             times[lA + l] = (float)(now - t_prev) * ns_per_tick + p1_per_row * (float)(lv[l + 1] - lv[l]);
@@ -206,16 +272,12 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, i
     } else {
       for (int32_t l = 0; l < NL; ++l) {
         const int32_t pb = lv[l], items = (lv[l + 1] - pb) * nr;
-        for (int32_t it = tid; it < items; it += WG) {
-          const int32_t s = kOne ? pb + it : pb + it / nr;
-          const int32_t c = kOne ? 0 : it - (s - pb) * nr;
-          double acc = v[(int64_t)s * nr + c];
-          const int32_t o = eo[s], k = en[s];
-          for (int32_t i = 0; i < k; ++i) acc -= ev[o + i] * v[(int64_t)es[o + i] * nr + c];
-          const double x = acc * dg[s];
+        for (int32_t t = tid; t < items; t += WG) {
+          const Item it = load_item<kOne>(pb, items, t, nr, v, dg, rw, rix);
+          const double x = solve_item<kOne>(it, nr, v, ovf);
           if (!isfinite(x)) bits |= EB_NONFINITE;
-          v[(int64_t)s * nr + c] = x;
-          xp[(int64_t)(P0 + s) * nr + c] = x;
+          v[(int64_t)it.s * nr + it.c] = x;
+          xp[(int64_t)(P0 + it.s) * nr + it.c] = x;
         }
         lds_barrier();
         if (kTimed && tid == 0) {
@@ -406,25 +468,25 @@ hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32
 
 hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                           const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
+                           const int32_t *ovp, const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
                            double *xp, int *err, hipStream_t s, float *times, float ns_per_tick) {
   const bool one = nrhs == 1;
   if (times) {  // labelling runs only: 512 threads
     if (one)
       hipLaunchKernelGGL((k_thin_run<512, true, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, level_ptr, nrhs,
-                         srp, sci, sva, sdg, trp, tci, tva, bp, xp, err, times, ns_per_tick);
+                         srp, sci, sva, sdg, ovp, trp, tci, tva, bp, xp, err, times, ns_per_tick);
     else
       hipLaunchKernelGGL((k_thin_run<512, false, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, level_ptr, nrhs,
-                         srp, sci, sva, sdg, trp, tci, tva, bp, xp, err, times, ns_per_tick);
+                         srp, sci, sva, sdg, ovp, trp, tci, tva, bp, xp, err, times, ns_per_tick);
     return hipGetLastError();
   }
 #define THIN(W)                                                                                                   \
   if (one)                                                                                                        \
     hipLaunchKernelGGL((k_thin_run<W, true>), dim3(1), dim3(W), kWinBytes, s, win, nwin, level_ptr, nrhs, srp, sci, \
-                       sva, sdg, trp, tci, tva, bp, xp, err, (float *)nullptr, 0.f);                              \
+                       sva, sdg, ovp, trp, tci, tva, bp, xp, err, (float *)nullptr, 0.f);                              \
   else                                                                                                            \
     hipLaunchKernelGGL((k_thin_run<W, false>), dim3(1), dim3(W), kWinBytes, s, win, nwin, level_ptr, nrhs, srp,     \
-                       sci, sva, sdg, trp, tci, tva, bp, xp, err, (float *)nullptr, 0.f);
+                       sci, sva, sdg, ovp, trp, tci, tva, bp, xp, err, (float *)nullptr, 0.f);
   if (wg == 256) {
     THIN(256)
   } else if (wg == 1024) {

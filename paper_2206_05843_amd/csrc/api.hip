@@ -86,6 +86,37 @@ static int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
   return rows * (8 * (int64_t)nrhs + 40) + ents * 16 + 4 * (nl + 1);
 }
 
+bool level_fits_window(const Plan &P, int32_t l, int32_t nrhs) {
+  const int64_t rows = P.h_level_ptr[l + 1] - P.h_level_ptr[l];
+  return win_bytes(rows, P.h_lv_ovf[l], 1, nrhs) <= thin_win_bytes();
+}
+
+// Cut levels [l0, l1) into LDS windows; flag windows whose levels fit one wave
+// (bit 0) or one item per thread of a workgroup of wg threads (bit 1). Appends
+// the windows and a terminator holding l1; returns the number of windows.
+int32_t cut_windows(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs, int32_t wg, std::vector<int2> &out) {
+  const int64_t cap = thin_win_bytes();
+  const size_t first = out.size();
+  int32_t ws = l0;
+  int64_t rows = 0, ents = 0, maxit = 0;
+  auto flags = [&]() { return (maxit <= 64 ? 1 : 0) | (maxit <= wg ? 2 : 0); };
+  for (int32_t l = l0; l < l1; ++l) {
+    const int64_t rl = P.h_level_ptr[l + 1] - P.h_level_ptr[l], el = P.h_lv_ovf[l];
+    if (l > ws && win_bytes(rows + rl, ents + el, l - ws + 1, nrhs) > cap) {
+      out.push_back(int2{ws, flags()});
+      ws = l;
+      rows = ents = maxit = 0;
+    }
+    rows += rl;
+    ents += el;
+    maxit = std::max<int64_t>(maxit, rl * nrhs);
+  }
+  out.push_back(int2{ws, flags()});
+  const int32_t nw = (int32_t)(out.size() - first);
+  out.push_back(int2{l1, 0});
+  return nw;
+}
+
 sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc) {
   P.runs.clear();
   P.h_win.clear();
@@ -102,28 +133,10 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
     else
       P.runs.push_back(Run{l, l + 1, thin});
   }
-  // cut every thin run into LDS windows; flag windows whose levels fit one
-  // wave (bit 0) or one item per thread of the workgroup (bit 1)
   for (Run &r : P.runs) {
     if (!r.thin) continue;
     r.wi = (int32_t)P.h_win.size();
-    int32_t ws = r.l0;
-    int64_t rows = 0, ents = 0, maxit = 0;
-    auto flags = [&]() { return (maxit <= 64 ? 1 : 0) | (maxit <= sc.wg_threads ? 2 : 0); };
-    for (int32_t l = r.l0; l < r.l1; ++l) {
-      const int64_t rl = rows_of(l), el = offd_of(l);
-      if (l > ws && win_bytes(rows + rl, ents + el, l - ws + 1, nrhs) > cap) {
-        P.h_win.push_back(int2{ws, flags()});
-        ws = l;
-        rows = ents = maxit = 0;
-      }
-      rows += rl;
-      ents += el;
-      maxit = std::max<int64_t>(maxit, rl * nrhs);
-    }
-    P.h_win.push_back(int2{ws, flags()});
-    r.nw = (int32_t)P.h_win.size() - r.wi;
-    P.h_win.push_back(int2{r.l1, 0});
+    r.nw = cut_windows(P, r.l0, r.l1, nrhs, sc.wg_threads, P.h_win);
   }
   if (!P.h_win.empty()) {
     if (P.win.n < P.h_win.size()) HIPCHK(h, P.win.alloc(P.h_win.size()));

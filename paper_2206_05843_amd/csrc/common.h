@@ -133,16 +133,20 @@ struct sptrsv_ctx {
   sptrsv_rewrite_stats_t rstats{};
   DArr<char> rw_big;       // global workspace of the decision scan
   // batched matrices
-  std::vector<BatchMat> bmats;
-  std::vector<int32_t> b_nlev;
-  std::vector<int64_t> b_lvl_off;      // offset of each matrix's level_ptr
-  DArr<int32_t> b_rp, b_ci, b_lptr, b_perm, b_iperm, b_srp, b_sci;
-  DArr<double> b_sva, b_sdg;
-  DArr<int64_t> b_desc;                // per matrix: row_off, nnz_off, lvl_off, n, nlev (packed)
-  DArr<int32_t> b_order;               // matrices in processing order (longest first)
-  DArr<double> b_bp, b_xp;
-  int64_t b_total_n = 0, b_total_nnz = 0;
-  int32_t b_work_nrhs = 0;
+  // batched matrices: one plan over the block-diagonal union whose positions
+  // are grouped by matrix, then by level (levels of matrix m are
+  // [b_lvl_off[m], b_lvl_off[m+1]) of the plan)
+  int32_t b_nmat = 0;
+  bool b_ready = false;
+  Plan bat;
+  std::vector<int32_t> b_n, b_nlev;
+  std::vector<int64_t> b_row_off, b_lvl_off;
+  DArr<int32_t> b_rp, b_ci, b_mat_of_row, b_order, b_mwin;
+  DArr<double> b_va;
+  DArr<int64_t> b_row_off_d;           // [nmat+1]
+  DArr<unsigned> b_q;                  // persistent-launch queue counters
+  std::vector<int32_t> b_h_mwin;       // window index of each matrix's run, for the cached nrhs
+  int32_t b_win_nrhs = -1;
   std::vector<Graph> graphs;
   // live profile of solve launches
   bool prof = false;
@@ -257,7 +261,19 @@ hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const
                             const double *va, const int32_t *lev, long long *sum_lp, long long *sum_t, int32_t *hist,
                             int32_t *redo, int32_t *nredo, char *big, int32_t bigC, int32_t bigH, int32_t big_blocks,
                             int *err, hipStream_t s);
+// Batched launchers (k_solve.hip) -------------------------------------------------
+hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int2 *win,
+                            const int32_t *level_ptr, int32_t nrhs, const int32_t *srp, const int32_t *sci,
+                            const double *sva, const double *sdg, const int32_t *ovp, const double *bp, double *xp,
+                            unsigned *q, int *err, hipStream_t s);
+hipError_t launch_batch_gather(int64_t total, int32_t nrhs, const double *b, const int32_t *mat_of_row,
+                               const int64_t *row_off, const int32_t *iperm, double *bp, hipStream_t s);
+hipError_t launch_batch_scatter(int64_t total, int32_t nrhs, const double *xp, const int32_t *mat_of_row,
+                                const int64_t *row_off, const int32_t *iperm, double *x, hipStream_t s);
+int batch_resident_blocks();
 // Schedule helpers (api.hip) -----------------------------------------------------
+bool level_fits_window(const Plan &P, int32_t l, int32_t nrhs);
+int32_t cut_windows(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs, int32_t wg, std::vector<int2> &out);
 sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc);
 sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs);
 

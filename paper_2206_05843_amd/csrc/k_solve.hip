@@ -143,16 +143,17 @@ __device__ __forceinline__ double solve_item(const Item &it, int32_t nr, const d
   return acc * it.dinv;
 }
 
-template <int WG, bool kOne, bool kTimed = false>
-__global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, int32_t nwin,
-                                                 const int32_t *__restrict__ level_ptr, int32_t nrhs,
-                                                 const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
-                                                 const double *__restrict__ sva, const double *__restrict__ sdg,
-                                                 const int32_t *__restrict__ ovp, const int32_t *__restrict__ trp,
-                                                 const int32_t *__restrict__ tci, const double *__restrict__ tva,
-                                                 const double *__restrict__ bp, double *xp, int *err, float *times,
-                                                 float ns_per_tick) {
-  extern __shared__ double lds[];
+// The windows [win, win + nwin) of one thin run, by the calling workgroup.
+// Returns the latched error bits; a window that does not fit aborts the run.
+template <int WG, bool kOne, bool kTimed>
+__device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict__ win, int32_t nwin,
+                                             const int32_t *__restrict__ level_ptr, int32_t nrhs,
+                                             const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
+                                             const double *__restrict__ sva, const double *__restrict__ sdg,
+                                             const int32_t *__restrict__ ovp, const int32_t *__restrict__ trp,
+                                             const int32_t *__restrict__ tci, const double *__restrict__ tva,
+                                             const double *__restrict__ bp, double *xp, float *times,
+                                             float ns_per_tick) {
   const int32_t nr = kOne ? 1 : nrhs;
   const int tid = threadIdx.x;
   int bits = 0;
@@ -166,10 +167,7 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, i
     const int32_t O0 = ovp[P0], NO = ovp[P1] - O0;
     const int32_t NL = lB - lA;
     const int64_t need = (int64_t)R * (8 * nr + 40) + (int64_t)NO * 16 + 4 * (int64_t)(NL + 1);
-    if (need > kWinBytes) {  // the host sizes windows to fit; never index past LDS
-      if (tid == 0) atomicOr(err, EB_ARG);
-      return;
-    }
+    if (need > kWinBytes) return bits | EB_ARG;  // the host sizes windows to fit; never index past LDS
     double2 *rw = reinterpret_cast<double2 *>(lds);          // [R] w0, w1
     int4 *rix = reinterpret_cast<int4 *>(rw + R);             // [R] slot0, slot1, count, overflow
     Dep *ovf = reinterpret_cast<Dep *>(rix + R);              // [NO] third and later dependencies
@@ -289,7 +287,60 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, i
     }
     __syncthreads();  // the window's global x is complete before the next phase 1 reads it
   }
+  return bits;
+}
+
+template <int WG, bool kOne, bool kTimed = false>
+__global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, int32_t nwin,
+                                                 const int32_t *__restrict__ level_ptr, int32_t nrhs,
+                                                 const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
+                                                 const double *__restrict__ sva, const double *__restrict__ sdg,
+                                                 const int32_t *__restrict__ ovp, const int32_t *__restrict__ trp,
+                                                 const int32_t *__restrict__ tci, const double *__restrict__ tva,
+                                                 const double *__restrict__ bp, double *xp, int *err, float *times,
+                                                 float ns_per_tick) {
+  extern __shared__ double lds[];
+  const int bits = thin_run_body<WG, kOne, kTimed>(lds, win, nwin, level_ptr, nrhs, srp, sci, sva, sdg, ovp, trp,
+                                                   tci, tva, bp, xp, times, ns_per_tick);
   if (bits) atomicOr(err, bits);
+}
+
+// Many independent matrices in one persistent launch: each workgroup takes
+// the next matrix from a device queue (matrices are queued largest first) and
+// solves all of it with the thin-run windows of that matrix; the levels of a
+// matrix are separated by workgroup barriers. The last workgroup to finish
+// resets the queue, so the launch can be replayed (graph capture) without a
+// host-side reset. q[0] = next ticket, q[1] = finished workgroups.
+template <int WG, bool kOne>
+__global__ __launch_bounds__(WG) void k_batch_run(int32_t nmat, const int32_t *__restrict__ order,
+                                                  const int32_t *__restrict__ mwin, const int2 *__restrict__ win,
+                                                  const int32_t *__restrict__ level_ptr, int32_t nrhs,
+                                                  const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
+                                                  const double *__restrict__ sva, const double *__restrict__ sdg,
+                                                  const int32_t *__restrict__ ovp, const double *__restrict__ bp,
+                                                  double *xp, unsigned *q, int *err) {
+  extern __shared__ double lds[];
+  __shared__ int32_t s_m;
+  int bits = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_m = (int32_t)atomicAdd(q, 1u);
+    __syncthreads();
+    const int32_t t = s_m;
+    __syncthreads();
+    if (t >= nmat) break;
+    const int32_t m = order[t];
+    bits |= thin_run_body<WG, kOne, false>(lds, win + mwin[m], mwin[m + 1] - mwin[m] - 1, level_ptr, nrhs, srp, sci,
+                                           sva, sdg, ovp, nullptr, nullptr, nullptr, bp, xp, nullptr, 0.f);
+  }
+  if (threadIdx.x == 0) {
+    if (bits) atomicOr(err, bits);
+    __threadfence();
+    if (atomicAdd(q + 1, 1u) == gridDim.x - 1) {
+      q[0] = 0;
+      q[1] = 0;
+      __threadfence();
+    }
+  }
 }
 
 // One wide level, one item (row, rhs) per thread.
@@ -416,6 +467,35 @@ __global__ void k_residual(int32_t n, int32_t nrhs, const int32_t *__restrict__ 
   }
 }
 
+// Batched right-hand sides: matrix m's b and x are n_m x nrhs column-major at
+// offset nrhs * row_off[m], ld = n_m. Items run over (global row, column) with
+// the row fastest, so each column of each matrix is read/written contiguously.
+__global__ void k_batch_gather(int64_t total, int32_t nrhs, const double *__restrict__ b,
+                               const int32_t *__restrict__ mat_of_row, const int64_t *__restrict__ row_off,
+                               const int32_t *__restrict__ iperm, double *bp) {
+  const int64_t items = total * nrhs;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = it / total, r = it - c * total;
+    const int32_t m = mat_of_row[r];
+    const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
+    bp[(int64_t)iperm[r] * nrhs + c] = b[nrhs * ro + c * nm + (r - ro)];
+  }
+}
+
+__global__ void k_batch_scatter(int64_t total, int32_t nrhs, const double *__restrict__ xp,
+                                const int32_t *__restrict__ mat_of_row, const int64_t *__restrict__ row_off,
+                                const int32_t *__restrict__ iperm, double *x) {
+  const int64_t items = total * nrhs;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = it / total, r = it - c * total;
+    const int32_t m = mat_of_row[r];
+    const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
+    x[nrhs * ro + c * nm + (r - ro)] = xp[(int64_t)iperm[r] * nrhs + c];
+  }
+}
+
 inline int grid_for(int64_t items, int threads, int cap) {
   int64_t g = (items + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -538,4 +618,50 @@ hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int
   hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, nrhs, rp, ci, va, b, ldb, x,
                      ldx, out);
   return hipGetLastError();
+}
+
+hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int2 *win,
+                            const int32_t *level_ptr, int32_t nrhs, const int32_t *srp, const int32_t *sci,
+                            const double *sva, const double *sdg, const int32_t *ovp, const double *bp, double *xp,
+                            unsigned *q, int *err, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_run<512, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_run<512, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
+    attr = true;
+  }
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_batch_run<512, true>), dim3(grid), dim3(512), kWinBytes, s, nmat, order, mwin, win,
+                       level_ptr, nrhs, srp, sci, sva, sdg, ovp, bp, xp, q, err);
+  else
+    hipLaunchKernelGGL((k_batch_run<512, false>), dim3(grid), dim3(512), kWinBytes, s, nmat, order, mwin, win,
+                       level_ptr, nrhs, srp, sci, sva, sdg, ovp, bp, xp, q, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(int64_t total, int32_t nrhs, const double *b, const int32_t *mat_of_row,
+                               const int64_t *row_off, const int32_t *iperm, double *bp, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_gather, dim3(grid_for(total * nrhs, 256, 16384)), dim3(256), 0, s, total, nrhs, b,
+                     mat_of_row, row_off, iperm, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_scatter(int64_t total, int32_t nrhs, const double *xp, const int32_t *mat_of_row,
+                                const int64_t *row_off, const int32_t *iperm, double *x, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_scatter, dim3(grid_for(total * nrhs, 256, 16384)), dim3(256), 0, s, total, nrhs, xp,
+                     mat_of_row, row_off, iperm, x);
+  return hipGetLastError();
+}
+
+int batch_resident_blocks() {
+  int dev = 0, cus = 256, occ = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(&k_batch_run<512, false>),
+                                                     512, kWinBytes);
+  return cus * (occ > 0 ? occ : 1);
 }

@@ -2,6 +2,9 @@
 strategy's scan): the paper's Fig. 2 closed form and its cost-map example, a
 bidiagonal closed form, the unique-row characterisation by a dense solve,
 reachability by breadth-first search, and invariants on random inputs."""
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -13,6 +16,14 @@ from tests.test_oracle_solve_levels import _csr, fig2_matrix
 THIN_ROWS, THIN_COST = oracle.THIN_ROWS, oracle.THIN_COST
 
 
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
 def _row(rw_ptr, rw_col, rw_val, r):
     s, e = rw_ptr[r], rw_ptr[r + 1]
     return list(zip(rw_col[s:e].tolist(), rw_val[s:e].tolist()))
@@ -21,12 +32,23 @@ def _row(rw_ptr, rw_col, rw_val, r):
 # ------------------------------------------------------------- Fig. 2 example
 def test_fig2_closed_form():
     v00, v10, v11, v22, v31, v33 = 2.0, 0.5, 3.0, 1.5, -0.75, 4.0
+    g = golden("fig2_example.json")
     m = fig2_matrix(v00, v10, v11, v22, v31, v33)
+    for r, deps in g["dependencies"].items():
+        s, e = m.row_ptr[int(r)], m.row_ptr[int(r) + 1]
+        assert m.col[s:e - 1].tolist() == deps
     lv = oracle.levels(m)
-    assert lv.nlev == 3 and list(lv.row_level) == [0, 1, 0, 2]
+    assert [lv_ + 1 for lv_ in lv.row_level] == g["levels_1based"]
+    assert lv.nlev == max(g["levels_1based"])
+    # first rewrite of row 3 (Fig. 2, middle): one level up, dependency on row 0
+    rw1 = oracle.rewrite(m, THIN_ROWS, 100, mask=np.array([0, 0, 1], np.uint8))
+    assert rw1.target[3] + 1 == g["row3_after_first_rewrite"]["level_1based"]
+    assert [c for c, _ in _row(rw1.lp_ptr, rw1.lp_col, rw1.lp_val, 3)][:-1] == \
+        g["row3_after_first_rewrite"]["dependencies"]
     # rewrite every level toward level 0 (the two substitutions of Fig. 2)
     rw = oracle.rewrite(m, THIN_ROWS, 100, mask=np.array([0, 1, 1], np.uint8))
     assert list(rw.target) == [-1, 0, -1, 0]
+    assert rw.target[3] + 1 == g["row3_after_second_rewrite"]["level_1based"]
     l3 = _row(rw.lp_ptr, rw.lp_col, rw.lp_val, 3)
     t3 = _row(rw.t_ptr, rw.t_col, rw.t_val, 3)
     assert l3 == [(3, v33)]  # rewritten row keeps only its diagonal
@@ -38,7 +60,8 @@ def test_fig2_closed_form():
     x3 = (b[0, 3] - v31 * ((b[0, 1] - v10 * (b[0, 0] / v00)) / v11)) / v33
     assert abs(x[0, 3] - x3) <= 4e-16 * abs(x3)
     # cost after rearrangement: row 3 costs 1 (Sec. III)
-    assert 2 * (rw.lp_ptr[4] - rw.lp_ptr[3]) - 1 == 1
+    assert 2 * (rw.lp_ptr[4] - rw.lp_ptr[3]) - 1 == g["row3_after_second_rewrite"]["cost_rearranged"]
+    assert [c for c, _ in l3][:-1] == g["row3_after_second_rewrite"]["dependencies"]
     assert oracle.levels(rw.lp).nlev == 1
 
 
@@ -59,23 +82,28 @@ def costmap_matrix():
 
 
 def test_costmap_movement_pattern():
+    g = golden("costmap_example.json")
     m = costmap_matrix()
     lv = oracle.levels(m)
     assert lv.nlev == 5
+    r = list(range(5, 13))                    # example row i is matrix row r[i]
+    lvl = {"n": 1, "n+1": 2, "n+2": 3, "n+3": 4}  # level 0 holds the ancestors
+    for name, rows in g["levels"].items():
+        assert [int(lv.row_level[r[i]]) for i in rows] == [lvl[name]] * len(rows)
     mask = np.array([0, 0, 1, 1, 1], np.uint8)
-    rw = oracle.rewrite(m, THIN_COST, 22.0, mask=mask, lv=lv)
-    r = list(range(5, 13))
+    rw = oracle.rewrite(m, THIN_COST, float(g["budget"]), mask=mask, lv=lv)
     tg = rw.target
-    # rows of level n+1 and the first row of level n+2 go to level n ...
-    assert [tg[r[2]], tg[r[3]], tg[r[4]]] == [1, 1, 1]
-    # ... the next row would push level n past the budget: it stays, and its
-    # level becomes the next target, which receives both rows of level n+3
-    assert tg[r[5]] == -1 and [tg[r[6]], tg[r[7]]] == [3, 3]
-    assert rw.rows_rewritten == 5
+    for i, name in g["moved"].items():
+        assert tg[r[int(i)]] == lvl[name]
+    for i in g["not_moved"]:
+        assert tg[r[i]] == -1
+    assert rw.rows_rewritten == len(g["moved"])
     lv2 = oracle.levels(rw.lp)
-    assert lv2.nlev == lv.nlev - 2  # two levels emptied and removed
-    # level n ends with 5 rows; the next one with 3 (as in the example's result)
-    assert np.diff(lv2.level_ptr).tolist() == [5, 5, 3]
+    assert lv2.nlev == lv.nlev - g["levels_removed"]
+    # the example's final levels, below the ancestors' level
+    for k, rows in enumerate(g["final_levels"]):
+        got = sorted(int(x) for x in lv2.level_rows[lv2.level_ptr[k + 1]:lv2.level_ptr[k + 2]])
+        assert [r.index(x) for x in got] == rows
 
 
 # --------------------------------------------------- bidiagonal closed form

@@ -1,6 +1,9 @@
 """Pins for the oracle's validation, forward substitution, level sets and
 cost model, each against something other than the oracle itself: closed forms,
 library routines, error bounds, brute force and the paper's worked examples."""
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -191,15 +194,18 @@ def test_level_invariants_powerlaw():
 # ---------------------------------------------------------------- O4 cost model
 def test_row7_example_cost():
     # Sec. II.A: row 7 reads rows 0, 3 and 6; cost of a row = 2*nnz - 1 (Sec. III)
-    rows = [[(i, 2.0)] for i in range(7)] + [[(0, .1), (3, .2), (6, .3), (7, 2.0)]]
+    with open(os.path.join(os.path.dirname(__file__), "golden", "row7_example.json")) as f:
+        g = json.load(f)
+    r7 = g["row"]
+    rows = [[(i, 2.0)] for i in range(r7)] + [[(d, .1 * (k + 1)) for k, d in enumerate(g["dependencies"])] + [(r7, 2.0)]]
     rows[3] = [(1, .5), (3, 2.0)]
     rows[6] = [(3, .5), (6, 2.0)]
-    m = _csr(8, rows)
+    m = _csr(r7 + 1, rows)
+    assert m.row_ptr[r7 + 1] - m.row_ptr[r7] == g["nnz"]
     lv = oracle.levels(m)
-    assert lv.row_level[7] == 1 + max(lv.row_level[[0, 3, 6]])
+    assert lv.row_level[r7] == 1 + max(lv.row_level[g["dependencies"]])
     c = oracle.level_costs(m, lv)
-    lvl7 = lv.row_level[7]
-    assert c.cost[lvl7] == 7  # the only row of its level
+    assert c.cost[lv.row_level[r7]] == g["cost"]  # the only row of its level
 
 
 def fig2_matrix(v00=2.0, v10=0.5, v11=3.0, v22=1.5, v31=-0.75, v33=4.0):

@@ -78,6 +78,19 @@ def load_traffic(kernel, workload_key):
     return e.get("bytes_per_launch")
 
 
+def calibrate_copy(torch, mib):
+    """Ten device-to-device copies of a buffer of known size: the FETCH_SIZE and
+    WRITE_SIZE counters of these launches scale the counters of the solve
+    kernels to bytes."""
+    n = mib * (1 << 20) // 8
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n * 8, "launches": 10}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +99,13 @@ def main():
     ap.add_argument("--config", type=int, default=1, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--variants", default="plain,naive,learned",
+                    help="comma-separated subset of plain,naive,learned to set up and time")
+    ap.add_argument("--schedules", default=None,
+                    help="JSON object variant -> schedule (mode, thin_rows, wg_threads, wide_threads, "
+                         "lanes_per_row); those variants skip the autotuner (for profiled runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 10 device copies of MIB MiB (the reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the solve of one matrix is not sharded "
@@ -94,6 +114,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        calibrate_copy(torch, args.calibrate_copy)
+        return
 
     import gen
     import oracle
@@ -130,8 +154,12 @@ def main():
         torch.cuda.synchronize()
         info["preprocess_s"] = time.perf_counter() - t
         t = time.perf_counter()
-        info["tuned_ms"] = h.autotune(which, nrhs)
-        info["schedule"] = h.get_schedule(which)
+        if name in fixed_sched:
+            h.set_schedule(which, **fixed_sched[name])
+            info["tuned_ms"] = None
+        else:
+            info["tuned_ms"] = h.autotune(which, nrhs)
+        info["schedule"] = h.get_schedule(which, nrhs)
         info["autotune_s"] = time.perf_counter() - t
         x = h.solve(b, which)
         h.check()
@@ -141,14 +169,18 @@ def main():
         info["bytes"] = alg_bytes(m.n, info["nnz"], info["nlev"], nrhs, info["nnz_t"], rewrite)
         variants[name] = (h, which, info)
         log(f"[bench] {name}: nlev={info['nlev']} relerr={info['relerr']:.2e} pre={info['preprocess_s']:.2f}s "
-            f"tuned={info['tuned_ms']:.3f}ms")
+            f"schedule={info['schedule']}")
 
-    setup("plain", rewrite=False)
-    try:
-        setup("naive")
-    except sp.SptrsvError as e:
-        log(f"[bench] naive rewrite unavailable: {e}")
-    if not args.no_learned:
+    want = set(v.strip() for v in args.variants.split(",") if v.strip())
+    fixed_sched = json.loads(args.schedules) if args.schedules else {}
+    if "plain" in want:
+        setup("plain", rewrite=False)
+    if "naive" in want:
+        try:
+            setup("naive")
+        except sp.SptrsvError as e:
+            log(f"[bench] naive rewrite unavailable: {e}")
+    if "learned" in want and not args.no_learned:
         try:
             from paper_2206_05843_amd import policy
             pol = policy.load_default()

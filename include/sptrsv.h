@@ -164,8 +164,11 @@ sptrsv_status_t sptrsv_check(sptrsv_handle_t h, hipStream_t s);
 /* Schedule knobs of the solve (see the autotuner): a level with at most
  * thin_rows rows runs inside one workgroup of wg_threads threads, together with
  * its thin neighbours; wider levels get one multi-workgroup launch each with
- * wide_threads threads per workgroup. mode: 0 = automatic (tuned or default),
- * 1 = every level as a wide launch, 2 = every level inside one workgroup. */
+ * wide_threads threads per workgroup. mode: 0 = split at thin_rows,
+ * 1 = every level as a wide launch, 2 = every level inside one workgroup.
+ * set_schedule replaces the schedules sptrsv_autotune picked for this matrix;
+ * get_schedule reports the schedule a solve with nrhs right-hand sides uses
+ * (the tuned one for that nrhs if there is one, else the one set). */
 typedef struct {
   int32_t mode;
   int32_t thin_rows;
@@ -174,7 +177,7 @@ typedef struct {
   int32_t lanes_per_row;  /* wide levels, nrhs == 1: 1, 2, 4, 8, 16 or 32 lanes per row */
 } sptrsv_schedule_t;
 sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_schedule_t *sched);
-sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, sptrsv_schedule_t *sched);
+sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, sptrsv_schedule_t *sched);
 
 /* Autotuner: times candidate schedules with HIP events on s (inputs b = 1) and
  * keeps the fastest for (which, nrhs). best_ms (host, may be NULL) receives the

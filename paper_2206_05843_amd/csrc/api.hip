@@ -71,19 +71,14 @@ sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
 // The schedule actually used for (P, nrhs): a tuned one if present, else the
 // handle's knobs.
 sptrsv_schedule_t effective_sched(const Plan &P, int32_t nrhs) {
-  if (P.sched.mode == 0) {
-    auto it = P.tuned.find(nrhs);
-    if (it != P.tuned.end()) return it->second;
-  }
-  return P.sched;
+  auto it = P.tuned.find(nrhs);
+  return it != P.tuned.end() ? it->second : P.sched;
 }
 
 }  // namespace
 
-// LDS bytes of a thin-run window holding `rows` rows, `ents` off-diagonals and
-// `nl` levels (must match the layout in k_thin_run).
 static int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
-  return rows * (8 * (int64_t)nrhs + 40) + ents * 16 + 4 * (nl + 1);
+  return thin_window_bytes(rows, ents, nl, nrhs);
 }
 
 bool level_fits_window(const Plan &P, int32_t l, int32_t nrhs) {
@@ -223,6 +218,9 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   HIPCHK(h, P.sva.alloc((size_t)std::max<int64_t>(noff, 1)));
   HIPCHK(h, P.sdg.alloc(n));
   HIPCHK(h, launch_fill_solve(n, P.perm.p, P.iperm.p, rp, ci, va, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, s));
+  HIPCHK(h, P.ell_c.alloc(n));
+  HIPCHK(h, P.ell_v.alloc((size_t)2 * n));
+  HIPCHK(h, launch_fill_ell(n, P.srp.p, P.sci.p, P.sva.p, P.ell_c.p, P.ell_v.p, s));
   HIPCHK(h, P.ovp.alloc((size_t)n + 1));
   HIPCHK(h, launch_count_ovf(P.srp.p, n, cnt.p, s));
   HIPCHK(h, launch_scan_i64(cnt.p, ex.p, n, h->scan_tmp.p, s));
@@ -286,8 +284,7 @@ static double run_bytes(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs) {
   for (int32_t l = l0; l < l1; ++l) {
     const double rows = P.h_level_ptr[l + 1] - P.h_level_ptr[l];
     const double off = (double)P.h_lv_nnz[l] - rows;
-    b += 12.0 * off + 12.0 * rows + 16.0 * rows * nrhs;
-    if (P.has_t) b += 12.0 * (double)P.h_lv_tnnz[l] + 4.0 * rows;
+    b += 12.0 * off + 12.0 * rows + 16.0 * rows * nrhs;  // T b is applied in the gather
   }
   return b;
 }
@@ -306,6 +303,22 @@ static void prof_end(sptrsv_ctx *h, int slot, hipStream_t s) {
   if (slot >= 0) (void)hipEventRecord(h->prof_ev[(size_t)slot * 2 + 1], s);
 }
 
+ThinArgs thin_args(const Plan &P) {
+  return ThinArgs{P.level_ptr.p, P.srp.p, P.sci.p, P.ovp.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, P.bp.p, P.xp.p};
+}
+
+// b (caller's layout) -> bp (level order, interleaved); for the rewritten
+// system b' = T b, with the plain gather staged in xp (the solve overwrites it).
+sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, hipStream_t s) {
+  if (!P.has_t) {
+    HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.bp.p, s));
+    return SPTRSV_OK;
+  }
+  HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.xp.p, s));
+  HIPCHK(h, launch_apply_t(P.n, nrhs, P.trp.p, P.tci.p, P.tva.p, P.xp.p, P.bp.p, s));
+  return SPTRSV_OK;
+}
+
 sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
                            int64_t ldx, hipStream_t s) {
   if (P.n == 0) return SPTRSV_OK;
@@ -314,20 +327,16 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
   if (P.runs_nrhs != nrhs || !same_sched(sc, P.runs_sched)) STCHK(make_runs(h, P, nrhs, sc));
   int *err = h->d_err.p;
   const double vec_bytes = 16.0 * (double)P.n * nrhs + 4.0 * P.n;
-  int slot = prof_begin(h, 0, vec_bytes, s);
-  HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.bp.p, s));
+  int slot = prof_begin(h, 0, vec_bytes + (P.has_t ? 12.0 * (double)P.nnz_t_off + 4.0 * P.n : 0.0), s);
+  STCHK(gather_b(h, P, nrhs, b, ldb, s));
   prof_end(h, slot, s);
-  const int32_t *trp = P.has_t ? P.trp.p : nullptr;
   for (const Run &r : P.runs) {
     slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
     if (r.thin) {
-      HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, P.level_ptr.p, nrhs, P.srp.p, P.sci.p, P.sva.p,
-                                P.sdg.p, P.ovp.p,
-                                trp, P.tci.p, P.tva.p, P.bp.p, P.xp.p, err, s));
+      HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, thin_args(P), err, s));
     } else {
       HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
-                                  P.srp.p, P.sci.p, P.sva.p, P.sdg.p, trp, P.tci.p, P.tva.p, P.bp.p, P.xp.p, err,
-                                  s));
+                                  P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.bp.p, P.xp.p, err, s));
     }
     prof_end(h, slot, s);
   }
@@ -516,15 +525,17 @@ sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_s
   if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
   STCHK(check_sched(h, *sched));
   P->sched = *sched;
+  P->tuned.clear();
   P->runs_nrhs = -1;
   return SPTRSV_OK;
 }
 
-sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, sptrsv_schedule_t *sched) {
+sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, sptrsv_schedule_t *sched) {
   if (!h || !sched) return SPTRSV_ERR_ARG;
   Plan *P = plan_of(h, which);
   if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
-  *sched = P->sched;
+  if (nrhs < 1) return set_err(h, SPTRSV_ERR_ARG, "nrhs=%d", nrhs);
+  *sched = effective_sched(*P, nrhs);
   return SPTRSV_OK;
 }
 

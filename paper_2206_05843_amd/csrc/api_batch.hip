@@ -230,6 +230,9 @@ sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t nmat, const int3
   HIPCHK(h, P.sdg.alloc(n));
   HIPCHK(h, launch_fill_solve(n, P.perm.p, P.iperm.p, h->b_rp.p, h->b_ci.p, h->b_va.p, P.srp.p, P.sci.p, P.sva.p,
                               P.sdg.p, s));
+  HIPCHK(h, P.ell_c.alloc(n));
+  HIPCHK(h, P.ell_v.alloc((size_t)2 * n));
+  HIPCHK(h, launch_fill_ell(n, P.srp.p, P.sci.p, P.sva.p, P.ell_c.p, P.ell_v.p, s));
   HIPCHK(h, P.ovp.alloc((size_t)n + 1));
   HIPCHK(h, launch_count_ovf(P.srp.p, n, cnt.p, s));
   HIPCHK(h, launch_scan_i64(cnt.p, ex.p, n, h->scan_tmp.p, s));
@@ -281,8 +284,8 @@ sptrsv_status_t sptrsv_batch_solve(sptrsv_handle_t h, int32_t nrhs, const double
   STCHK(batch_windows(h, nrhs));
   HIPCHK(h, launch_batch_gather(P.n, nrhs, d_b_cat, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, P.bp.p, s));
   const int32_t grid = std::min(h->b_nmat, batch_resident_blocks());
-  HIPCHK(h, launch_batch_run(h->b_nmat, grid, h->b_order.p, h->b_mwin.p, P.win.p, P.level_ptr.p, nrhs, P.srp.p,
-                             P.sci.p, P.sva.p, P.sdg.p, P.ovp.p, P.bp.p, P.xp.p, h->b_q.p, h->d_err.p, s));
+  HIPCHK(h, launch_batch_run(h->b_nmat, grid, h->b_order.p, h->b_mwin.p, P.win.p, nrhs, thin_args(P), h->b_q.p,
+                             h->d_err.p, s));
   HIPCHK(h, launch_batch_scatter(P.n, nrhs, P.xp.p, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, d_x_cat, s));
   return SPTRSV_OK;
 }
@@ -298,8 +301,7 @@ sptrsv_status_t sptrsv_batch_solve_looped(sptrsv_handle_t h, int32_t nrhs, const
   HIPCHK(h, launch_batch_gather(P.n, nrhs, d_b_cat, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, P.bp.p, s));
   for (int32_t m = 0; m < h->b_nmat; ++m) {
     const int32_t wi = h->b_h_mwin[(size_t)m], nw = h->b_h_mwin[(size_t)m + 1] - wi - 1;
-    HIPCHK(h, launch_thin_run(512, P.win.p + wi, nw, P.level_ptr.p, nrhs, P.srp.p, P.sci.p, P.sva.p, P.sdg.p,
-                              P.ovp.p, nullptr, nullptr, nullptr, P.bp.p, P.xp.p, h->d_err.p, s));
+    HIPCHK(h, launch_thin_run(512, P.win.p + wi, nw, nrhs, thin_args(P), h->d_err.p, s));
   }
   HIPCHK(h, launch_batch_scatter(P.n, nrhs, P.xp.p, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, d_x_cat, s));
   return SPTRSV_OK;

@@ -102,16 +102,13 @@ sptrsv_status_t sptrsv_level_times(sptrsv_handle_t h, int which, int32_t nrhs, c
   sptrsv_schedule_t sc{2, 0, 512, 256, 1};  // every level that fits runs in one workgroup
   STCHK(make_runs(h, *P, nrhs, sc));
   HIPCHK(h, hipMemsetAsync(d_times, 0, sizeof(float) * (size_t)P->nlev, s));
-  const int32_t *trp = P->has_t ? P->trp.p : nullptr;
-  HIPCHK(h, launch_gather(P->n, nrhs, d_b, P->n, P->iperm.p, P->bp.p, s));
+  STCHK(gather_b(h, *P, nrhs, d_b, P->n, s));
   for (const Run &r : P->runs) {
     if (r.thin) {
-      HIPCHK(h, launch_thin_run(512, P->win.p + r.wi, r.nw, P->level_ptr.p, nrhs, P->srp.p, P->sci.p, P->sva.p,
-                                P->sdg.p, P->ovp.p, trp, P->tci.p, P->tva.p, P->bp.p, P->xp.p, h->d_err.p, s, d_times,
-                                ns_per_tick));
+      HIPCHK(h, launch_thin_run(512, P->win.p + r.wi, r.nw, nrhs, thin_args(*P), h->d_err.p, s, d_times, ns_per_tick));
     } else {
       HIPCHK(h, launch_wide_level(256, 1, P->h_level_ptr[r.l0], P->h_level_ptr[r.l1], nrhs, P->srp.p, P->sci.p,
-                                  P->sva.p, P->sdg.p, trp, P->tci.p, P->tva.p, P->bp.p, P->xp.p, h->d_err.p, s));
+                                  P->sva.p, P->sdg.p, P->bp.p, P->xp.p, h->d_err.p, s));
     }
   }
   HIPCHK(h, hipStreamSynchronize(s));

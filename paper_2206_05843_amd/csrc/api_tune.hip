@@ -32,7 +32,7 @@ std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
     if (nrhs > 1 && lpr > 1) continue;
     c.push_back(sptrsv_schedule_t{1, 0, 512, 256, lpr});
     for (int thr : thin_list) {
-      if ((int64_t)thr * (8 * nrhs + 40) > thin_win_bytes()) continue;
+      if (thin_window_bytes(thr, 0, 1, nrhs) > thin_win_bytes()) continue;
       for (int wg : wg_list) c.push_back(sptrsv_schedule_t{0, thr, wg, 256, lpr});
     }
   }

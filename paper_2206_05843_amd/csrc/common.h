@@ -91,6 +91,8 @@ struct Plan {
   std::vector<int64_t> h_lv_nnz;       // per level: nnz incl. diagonal (host copy)
   std::vector<int64_t> h_lv_tnnz;      // per level: off-diagonal nnz of T
   DArr<int32_t> ovp;                   // [n+1] prefix of max(0, off-diagonals - 2) per position
+  DArr<int4> ell_c;                    // [n] first four off-diagonal columns per position (-1: none)
+  DArr<double2> ell_v;                 // [2n] their values
   std::vector<int64_t> h_lv_ovf;       // per level: sum of max(0, off-diagonals - 2)
   int64_t total_cost = 0;
   double avg_cost = 0.0;
@@ -202,21 +204,41 @@ hipError_t launch_fill_t(int32_t n, const int32_t *perm, const int32_t *iperm, c
 hipError_t launch_level_stats(int32_t nlev, const int32_t *level_ptr, const int32_t *srp, int64_t *rows,
                               int64_t *nnz, int64_t *cost, long long *total, hipStream_t s);
 
+// LDS bytes of a thin-run window of `rows` rows, `ovf` overflow dependency
+// records and `nl` levels: per row the partial sum or x of every RHS (8 nrhs),
+// two inline weights (16) and packed slots/count/offset (8); one zero entry
+// per RHS that absent dependencies point to; 16 per overflow record; the level
+// bounds.
+__host__ __device__ inline int64_t thin_window_bytes(int64_t rows, int64_t ovf, int64_t nl, int32_t nrhs) {
+  return rows * (8 * (int64_t)nrhs + 24) + 8 * (int64_t)nrhs + ovf * 16 + 4 * (nl + 1);
+}
+
+// Device arrays a thin run reads (the level-ordered plan and work vectors).
+struct ThinArgs {
+  const int32_t *level_ptr, *srp, *sci, *ovp;
+  const double *sva, *sdg;
+  const int4 *ell_c;
+  const double2 *ell_v;
+  const double *bp;
+  double *xp;
+};
+
 // Launchers (k_solve.hip) ------------------------------------------------------
 hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
                          hipStream_t s);
+hipError_t launch_apply_t(int32_t n, int32_t nrhs, const int32_t *trp, const int32_t *tci, const double *tva,
+                          const double *t, double *bp, hipStream_t s);
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
 int thin_win_bytes();
 hipError_t launch_count_ovf(const int32_t *srp, int32_t n, long long *cnt, hipStream_t s);
-hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, const int32_t *level_ptr, int32_t nrhs,
-                           const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                           const int32_t *ovp, const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
-                           double *xp, int *err, hipStream_t s, float *times = nullptr, float ns_per_tick = 0.f);
+hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
+                           hipStream_t s, float *times = nullptr, float ns_per_tick = 0.f);
+hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, const double *sva, int4 *ell_c,
+                           double2 *ell_v, hipStream_t s);
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                             const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
-                             double *xp, int *err, hipStream_t s);
+                             const double *bp, double *xp, int *err, hipStream_t s);
 hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,
                            const double *b, int64_t ldb, const double *x, int64_t ldx, unsigned long long *out,
                            hipStream_t s);
@@ -263,9 +285,7 @@ hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const
                             int *err, hipStream_t s);
 // Batched launchers (k_solve.hip) -------------------------------------------------
 hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int2 *win,
-                            const int32_t *level_ptr, int32_t nrhs, const int32_t *srp, const int32_t *sci,
-                            const double *sva, const double *sdg, const int32_t *ovp, const double *bp, double *xp,
-                            unsigned *q, int *err, hipStream_t s);
+                            int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s);
 hipError_t launch_batch_gather(int64_t total, int32_t nrhs, const double *b, const int32_t *mat_of_row,
                                const int64_t *row_off, const int32_t *iperm, double *bp, hipStream_t s);
 hipError_t launch_batch_scatter(int64_t total, int32_t nrhs, const double *xp, const int32_t *mat_of_row,
@@ -281,5 +301,7 @@ sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs);
 sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
                            const double *va, const int32_t *trp, const int32_t *tci, const double *tva,
                            hipStream_t s);
+ThinArgs thin_args(const Plan &P);
+sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, hipStream_t s);
 sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
                            int64_t ldx, hipStream_t s);

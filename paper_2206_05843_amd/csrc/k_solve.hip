@@ -1,6 +1,7 @@
 // Solve kernels: level-by-level forward substitution (Sec. II.A, Algorithm 1)
-// over the level-ordered copy of L (or of the rewritten L' with the b-transform
-// T applied on the fly, Sec. II.B).
+// over the level-ordered copy of L, or of the rewritten L' (Sec. II.B) after
+// the b-transform b' = T b, which does not depend on x and so runs as one
+// parallel pass before the level chain starts.
 //
 // Work vectors are permuted to level order and RHS-interleaved: entry (pos, c)
 // of bp/xp is at pos*nrhs + c, so the rows of one level are contiguous and one
@@ -29,22 +30,15 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// x(pos, c) = (b'(pos, c) - sum_k L(pos,k) x(k,c)) / L(pos,pos), with
-// b' = b + T_off b when T is present. Columns < lds_base come from global
-// memory, columns >= lds_base from the LDS window.
+// x(pos, c) = (b'(pos, c) - sum_k L(pos,k) x(k,c)) / L(pos,pos). Columns
+// < lds_base come from global memory, columns >= lds_base from the LDS window.
 template <bool kUseLds, bool kOne>
 __device__ __forceinline__ double row_solve(int32_t pos, int32_t c, int32_t nrhs, const int32_t *__restrict__ srp,
                                             const int32_t *__restrict__ sci, const double *__restrict__ sva,
-                                            const double *__restrict__ sdg, const int32_t *__restrict__ trp,
-                                            const int32_t *__restrict__ tci, const double *__restrict__ tva,
-                                            const double *__restrict__ bp, const double *xp, const double *lds,
-                                            int32_t lds_base) {
+                                            const double *__restrict__ sdg, const double *__restrict__ bp,
+                                            const double *xp, const double *lds, int32_t lds_base) {
   const int64_t nr = kOne ? 1 : nrhs;
   double acc = bp[(int64_t)pos * nr + c];
-  if (trp) {
-    const int32_t tb = trp[pos], te = trp[pos + 1];
-    for (int32_t q = tb; q < te; ++q) acc += tva[q] * bp[(int64_t)tci[q] * nr + c];
-  }
   const int32_t b = srp[pos], e = srp[pos + 1];
   for (int32_t q = b; q < e; ++q) {
     const int32_t k = sci[q];
@@ -60,14 +54,22 @@ __device__ __forceinline__ double row_solve(int32_t pos, int32_t c, int32_t nrhs
 
 // A thin run is cut into LDS windows (consecutive levels, chosen on the host so
 // that the window's rows and dependency records fit in LDS). Per window:
-//  phase 1 (all rows in parallel): v = b' - sum of L(pos,k) x(k) over the
-//    dependencies k that precede the window (final values, read from global);
-//    the dependencies inside the window go to a 32-byte record per row
-//    {w0, w1 | slot0, slot1, count, first overflow}; a row's third and later
-//    in-window dependencies go to an overflow list of {value, slot} records
-//    (its offset is a precomputed prefix sum, ovp);
-//  phase 2 (level by level): x = (v - sum over in-window dependencies) * (1/diag),
-//    reading and writing LDS only; the global copy of x is written as well.
+//  phase 1 (all rows in parallel): v = (b' - sum of L(pos,k) x(k)) / L(pos,pos)
+//    over the dependencies k that precede the window (final values, read from
+//    global memory); the dependencies inside the window, scaled by
+//    1/L(pos,pos), go to an inline record per row {w0, w1 | slot0, slot1,
+//    count, first overflow}; a row's third and later in-window dependencies go
+//    to an overflow list of {weight, slot} records (its offset is a
+//    precomputed prefix sum, ovp). Absent inline dependencies point to a zero
+//    entry with weight 0, so phase 2 needs no predication. A row's first four
+//    dependencies come from a fixed-width copy indexed by position (no row
+//    pointer on the load chain), and each thread takes several rows at once
+//    and issues all their loads before it uses any of them, so a window costs
+//    two memory round trips;
+//  phase 2 (level by level): x = v - sum over in-window dependencies of w x,
+//    in LDS only;
+//  then the window's x goes to global memory in one coalesced pass (where the
+//    finiteness check happens too), before the next window reads it.
 // When every level of the window has at most one item per thread, phase 2 is
 // software-pipelined: the next level's records are requested before the
 // current level is computed, and the level bounds are read from registers,
@@ -107,16 +109,23 @@ __device__ __forceinline__ double ovf_sum(double acc, const Dep *__restrict__ d,
   return acc;
 }
 
+// Inline record of a row: slots, in-window dependency count and first
+// overflow record, 16 bits each (a window holds far fewer than 65536 rows or
+// records).
+__device__ __forceinline__ uint2 pack_rix(int32_t s0, int32_t s1, int32_t cnt, int32_t ob) {
+  return make_uint2((uint32_t)s0 | ((uint32_t)s1 << 16), (uint32_t)cnt | ((uint32_t)ob << 16));
+}
+
 // The static inputs of one (row, rhs) item in phase 2.
 struct Item {
-  double acc, dinv, w0, w1;
-  int4 ri;  // slot0, slot1, count, first overflow record
+  double acc, w0, w1;
+  int32_t s0, s1, cnt, ob;
   int32_t s, c, act;
 };
 
 template <bool kOne>
 __device__ __forceinline__ Item load_item(int32_t pb, int32_t items, int32_t t, int32_t nr, const double *v,
-                                          const double *dg, const double2 *rw, const int4 *rix) {
+                                          const double2 *rw, const uint2 *rix) {
   Item it;
   it.act = t < items;
   it.s = kOne ? pb + t : pb + t / nr;
@@ -125,37 +134,50 @@ __device__ __forceinline__ Item load_item(int32_t pb, int32_t items, int32_t t, 
   const double2 w = rw[ss];
   it.w0 = w.x;
   it.w1 = w.y;
-  it.ri = rix[ss];
-  it.dinv = dg[ss];
+  const uint2 r = rix[ss];
+  it.s0 = (int32_t)(r.x & 0xffffu);
+  it.s1 = (int32_t)(r.x >> 16);
+  it.cnt = (int32_t)(r.y & 0xffffu);
+  it.ob = (int32_t)(r.y >> 16);
   it.acc = v[(int64_t)ss * nr + (it.act ? it.c : 0)];
   return it;
 }
 
 template <bool kOne>
 __device__ __forceinline__ double solve_item(const Item &it, int32_t nr, const double *v, const Dep *ovf) {
-  const int32_t k = it.ri.z, c = it.c;
-  const double xa = v[(int64_t)(k > 0 ? it.ri.x : 0) * nr + c];
-  const double xb = v[(int64_t)(k > 1 ? it.ri.y : 0) * nr + c];
-  double acc = it.acc;
-  acc = k > 0 ? acc - it.w0 * xa : acc;
-  acc = k > 1 ? acc - it.w1 * xb : acc;
-  if (k > 2) acc = ovf_sum<kOne>(acc, ovf + it.ri.w, k - 2, v, nr, c);
-  return acc * it.dinv;
+  const int32_t c = it.c;
+  const double xa = v[(int64_t)it.s0 * (kOne ? 1 : nr) + c];
+  const double xb = v[(int64_t)it.s1 * (kOne ? 1 : nr) + c];
+  double acc = it.acc - it.w0 * xa;
+  acc = acc - it.w1 * xb;
+  if (it.cnt > 2) acc = ovf_sum<kOne>(acc, ovf + it.ob, it.cnt - 2, v, nr, c);
+  return acc;
+}
+
+// Phase 1: items per thread whose loads are in flight together (fewer at 1024
+// threads, where a thread has 128 registers).
+template <int WG, bool kOne>
+constexpr int p1_items() {
+  return WG >= 1024 ? (kOne ? 3 : 2) : 6;
 }
 
 // The windows [win, win + nwin) of one thin run, by the calling workgroup.
 // Returns the latched error bits; a window that does not fit aborts the run.
 template <int WG, bool kOne, bool kTimed>
-__device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict__ win, int32_t nwin,
-                                             const int32_t *__restrict__ level_ptr, int32_t nrhs,
-                                             const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
-                                             const double *__restrict__ sva, const double *__restrict__ sdg,
-                                             const int32_t *__restrict__ ovp, const int32_t *__restrict__ trp,
-                                             const int32_t *__restrict__ tci, const double *__restrict__ tva,
-                                             const double *__restrict__ bp, double *xp, float *times,
-                                             float ns_per_tick) {
+__device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict__ win, int32_t nwin, int32_t nrhs,
+                                             const ThinArgs &A, float *times, float ns_per_tick) {
   const int32_t nr = kOne ? 1 : nrhs;
   const int tid = threadIdx.x;
+  const int32_t *__restrict__ level_ptr = A.level_ptr;
+  const int32_t *__restrict__ srp = A.srp;
+  const int32_t *__restrict__ sci = A.sci;
+  const int32_t *__restrict__ ovp = A.ovp;
+  const double *__restrict__ sva = A.sva;
+  const double *__restrict__ sdg = A.sdg;
+  const int4 *__restrict__ ell_c = A.ell_c;
+  const double2 *__restrict__ ell_v = A.ell_v;
+  const double *__restrict__ bp = A.bp;
+  double *xp = A.xp;
   int bits = 0;
   unsigned long long t_w0 = 0, t_prev = 0;
   float p1_per_row = 0.f;
@@ -166,55 +188,89 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
     const int32_t R = P1 - P0;
     const int32_t O0 = ovp[P0], NO = ovp[P1] - O0;
     const int32_t NL = lB - lA;
-    const int64_t need = (int64_t)R * (8 * nr + 40) + (int64_t)NO * 16 + 4 * (int64_t)(NL + 1);
-    if (need > kWinBytes) return bits | EB_ARG;  // the host sizes windows to fit; never index past LDS
-    double2 *rw = reinterpret_cast<double2 *>(lds);          // [R] w0, w1
-    int4 *rix = reinterpret_cast<int4 *>(rw + R);             // [R] slot0, slot1, count, overflow
-    Dep *ovf = reinterpret_cast<Dep *>(rix + R);              // [NO] third and later dependencies
-    double *v = reinterpret_cast<double *>(ovf + NO);         // [R * nr] partial sums, then x
-    double *dg = v + (int64_t)R * nr;                         // [R] 1 / diagonal
-    int32_t *lv = reinterpret_cast<int32_t *>(dg + R);        // [NL + 1] level bounds, relative to P0
+    // the host sizes windows to fit, and 16-bit slots and offsets must hold R and NO
+    if (thin_window_bytes(R, NO, NL, nr) > kWinBytes || R >= 65536 || NO >= 65536) return bits | EB_ARG;
+    double2 *rw = reinterpret_cast<double2 *>(lds);          // [R] w0, w1 (scaled by 1/diagonal)
+    Dep *ovf = reinterpret_cast<Dep *>(rw + R);               // [NO] third and later dependencies
+    uint2 *rix = reinterpret_cast<uint2 *>(ovf + NO);         // [R] slot0, slot1, count, overflow
+    double *v = reinterpret_cast<double *>(rix + R);          // [(R + 1) * nr] partial sums, then x; zero row R
+    int32_t *lv = reinterpret_cast<int32_t *>(v + (int64_t)(R + 1) * nr);  // [NL + 1] level bounds from P0
     for (int32_t i = tid; i <= NL; i += WG) lv[i] = level_ptr[lA + i] - P0;
+    for (int32_t i = tid; i < nr; i += WG) v[(int64_t)R * nr + i] = 0.0;
     // phase 1
-    for (int32_t it = tid; it < R * nr; it += WG) {
-      const int32_t s = kOne ? it : it / nr;
-      const int32_t c = kOne ? 0 : it - s * nr;
-      const int32_t pos = P0 + s;
-      double acc = bp[(int64_t)pos * nr + c];
-      if (trp) {
-        const int32_t tb = trp[pos], te = trp[pos + 1];
-        for (int32_t q = tb; q < te; ++q) acc += tva[q] * bp[(int64_t)tci[q] * nr + c];
+    const int32_t nitems = R * nr;
+    constexpr int kP1Items = p1_items<WG, kOne>();
+    for (int32_t base = 0; base < nitems; base += WG * kP1Items) {
+      int32_t sj[kP1Items], cj[kP1Items], qb[kP1Items], deg[kP1Items], ob[kP1Items];
+      int4 ec[kP1Items];
+      double2 ev0[kP1Items], ev1[kP1Items];
+      double acc[kP1Items], dgv[kP1Items];
+#pragma unroll
+      for (int j = 0; j < kP1Items; ++j) {
+        const int32_t it = base + j * WG + tid;
+        const int32_t itc = it < nitems ? it : nitems - 1;
+        sj[j] = kOne ? itc : itc / nr;
+        cj[j] = kOne ? 0 : itc - sj[j] * nr;
+        const int32_t pos = P0 + sj[j];
+        qb[j] = srp[pos];
+        deg[j] = it < nitems ? srp[pos + 1] - qb[j] : 0;
+        ob[j] = ovp[pos] - O0;
+        ec[j] = ell_c[pos];
+        ev0[j] = ell_v[2 * (int64_t)pos];
+        ev1[j] = ell_v[2 * (int64_t)pos + 1];
+        acc[j] = bp[(int64_t)pos * nr + cj[j]];
+        dgv[j] = sdg[pos];
       }
-      const int32_t qb = srp[pos], qe = srp[pos + 1];
-      const int32_t ob = ovp[pos] - O0;
-      int32_t kin = 0, s0 = 0, s1 = 0;
-      double w0 = 0.0, w1 = 0.0;
-      for (int32_t q = qb; q < qe; ++q) {
-        const int32_t k = sci[q];
-        if (k < P0) {
-          acc -= sva[q] * xp[(int64_t)k * nr + c];
-        } else {
-          if (kin == 0) {
-            s0 = k - P0;
-            w0 = sva[q];
-          } else if (kin == 1) {
-            s1 = k - P0;
-            w1 = sva[q];
-          } else if (c == 0) {
-            Dep d;
-            d.w = sva[q];
-            d.slot = k - P0;
-            d.pad = 0;
-            ovf[ob + kin - 2] = d;
+      double xv[kP1Items][4];
+#pragma unroll
+      for (int j = 0; j < kP1Items; ++j) {
+        const int32_t kk[4] = {ec[j].x, ec[j].y, ec[j].z, ec[j].w};
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+          xv[j][d] = (d < deg[j] && kk[d] < P0) ? xp[(int64_t)kk[d] * nr + cj[j]] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < kP1Items; ++j) {
+        const int32_t it = base + j * WG + tid;
+        if (it >= nitems) continue;
+        const int32_t c = cj[j];
+        const double dinv = 1.0 / dgv[j];
+        int32_t kin = 0, s0 = R, s1 = R;
+        double w0 = 0.0, w1 = 0.0, a = acc[j];
+        auto take = [&](int32_t k, double wv, double x) {
+          if (k < P0) {
+            a -= wv * x;
+          } else {
+            if (kin == 0) {
+              s0 = k - P0;
+              w0 = wv * dinv;
+            } else if (kin == 1) {
+              s1 = k - P0;
+              w1 = wv * dinv;
+            } else if (c == 0) {
+              Dep dd;
+              dd.w = wv * dinv;
+              dd.slot = k - P0;
+              dd.pad = 0;
+              ovf[ob[j] + kin - 2] = dd;
+            }
+            ++kin;
           }
-          ++kin;
+        };
+        const int32_t kk[4] = {ec[j].x, ec[j].y, ec[j].z, ec[j].w};
+        const double vv[4] = {ev0[j].x, ev0[j].y, ev1[j].x, ev1[j].y};
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+          if (d < deg[j]) take(kk[d], vv[d], xv[j][d]);
+        for (int32_t q = qb[j] + 4; q < qb[j] + deg[j]; ++q) {
+          const int32_t k = sci[q];
+          take(k, sva[q], k < P0 ? xp[(int64_t)k * nr + c] : 0.0);
         }
-      }
-      v[(int64_t)s * nr + c] = acc;
-      if (c == 0) {
-        dg[s] = 1.0 / sdg[pos];  // reciprocal: one multiply on the level chain
-        rw[s] = make_double2(w0, w1);
-        rix[s] = make_int4(s0, s1, kin, ob);
+        v[(int64_t)sj[j] * nr + c] = a * dinv;
+        if (c == 0) {
+          rw[sj[j]] = make_double2(w0, w1);
+          rix[sj[j]] = pack_rix(s0, s1, kin, ob[j]);
+        }
       }
     }
     __syncthreads();
@@ -239,19 +295,14 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
         };
         int32_t pb, items;
         bounds(0, pb, items);
-        Item cur = load_item<kOne>(pb, items, tid, nr, v, dg, rw, rix);
+        Item cur = load_item<kOne>(pb, items, tid, nr, v, rw, rix);
         for (int32_t l = 0; l < NL; ++l) {
           Item nxt = cur;
           if (l + 1 < NL) {
             bounds(l + 1, pb, items);
-            nxt = load_item<kOne>(pb, items, tid, nr, v, dg, rw, rix);
+            nxt = load_item<kOne>(pb, items, tid, nr, v, rw, rix);
           }
-          if (cur.act) {
-            const double x = solve_item<kOne>(cur, nr, v, ovf);
-            if (!isfinite(x)) bits |= EB_NONFINITE;
-            v[(int64_t)cur.s * nr + cur.c] = x;
-            xp[(int64_t)(P0 + cur.s) * nr + cur.c] = x;
-          }
+          if (cur.act) v[(int64_t)cur.s * nr + cur.c] = solve_item<kOne>(cur, nr, v, ovf);
           if (one_wave) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
             __builtin_amdgcn_wave_barrier();
@@ -271,11 +322,8 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
       for (int32_t l = 0; l < NL; ++l) {
         const int32_t pb = lv[l], items = (lv[l + 1] - pb) * nr;
         for (int32_t t = tid; t < items; t += WG) {
-          const Item it = load_item<kOne>(pb, items, t, nr, v, dg, rw, rix);
-          const double x = solve_item<kOne>(it, nr, v, ovf);
-          if (!isfinite(x)) bits |= EB_NONFINITE;
-          v[(int64_t)it.s * nr + it.c] = x;
-          xp[(int64_t)(P0 + it.s) * nr + it.c] = x;
+          const Item it = load_item<kOne>(pb, items, t, nr, v, rw, rix);
+          v[(int64_t)it.s * nr + it.c] = solve_item<kOne>(it, nr, v, ovf);
         }
         lds_barrier();
         if (kTimed && tid == 0) {
@@ -285,24 +333,42 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
         }
       }
     }
+    __syncthreads();  // every x of the window is in LDS
+    double *xw = xp + (int64_t)P0 * nr;
+    for (int32_t i = tid; i < nitems; i += WG) {
+      const double x = v[i];
+      if (!isfinite(x)) bits |= EB_NONFINITE;
+      xw[i] = x;
+    }
     __syncthreads();  // the window's global x is complete before the next phase 1 reads it
   }
   return bits;
 }
 
 template <int WG, bool kOne, bool kTimed = false>
-__global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, int32_t nwin,
-                                                 const int32_t *__restrict__ level_ptr, int32_t nrhs,
-                                                 const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
-                                                 const double *__restrict__ sva, const double *__restrict__ sdg,
-                                                 const int32_t *__restrict__ ovp, const int32_t *__restrict__ trp,
-                                                 const int32_t *__restrict__ tci, const double *__restrict__ tva,
-                                                 const double *__restrict__ bp, double *xp, int *err, float *times,
-                                                 float ns_per_tick) {
+__global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, int32_t nwin, int32_t nrhs, ThinArgs A,
+                                                 int *err, float *times, float ns_per_tick) {
   extern __shared__ double lds[];
-  const int bits = thin_run_body<WG, kOne, kTimed>(lds, win, nwin, level_ptr, nrhs, srp, sci, sva, sdg, ovp, trp,
-                                                   tci, tva, bp, xp, times, ns_per_tick);
+  const int bits = thin_run_body<WG, kOne, kTimed>(lds, win, nwin, nrhs, A, times, ns_per_tick);
   if (bits) atomicOr(err, bits);
+}
+
+// A row's first four off-diagonals (column position, value), -1 / 0 padded.
+__global__ void k_fill_ell(int32_t n, const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
+                           const double *__restrict__ sva, int4 *ell_c, double2 *ell_v) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t qb = srp[p], deg = srp[p + 1] - qb;
+    int32_t c[4];
+    double v[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      c[d] = d < deg ? sci[qb + d] : -1;
+      v[d] = d < deg ? sva[qb + d] : 0.0;
+    }
+    ell_c[p] = make_int4(c[0], c[1], c[2], c[3]);
+    ell_v[2 * p] = make_double2(v[0], v[1]);
+    ell_v[2 * p + 1] = make_double2(v[2], v[3]);
+  }
 }
 
 // Many independent matrices in one persistent launch: each workgroup takes
@@ -314,11 +380,7 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, i
 template <int WG, bool kOne>
 __global__ __launch_bounds__(WG) void k_batch_run(int32_t nmat, const int32_t *__restrict__ order,
                                                   const int32_t *__restrict__ mwin, const int2 *__restrict__ win,
-                                                  const int32_t *__restrict__ level_ptr, int32_t nrhs,
-                                                  const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
-                                                  const double *__restrict__ sva, const double *__restrict__ sdg,
-                                                  const int32_t *__restrict__ ovp, const double *__restrict__ bp,
-                                                  double *xp, unsigned *q, int *err) {
+                                                  int32_t nrhs, ThinArgs A, unsigned *q, int *err) {
   extern __shared__ double lds[];
   __shared__ int32_t s_m;
   int bits = 0;
@@ -329,8 +391,7 @@ __global__ __launch_bounds__(WG) void k_batch_run(int32_t nmat, const int32_t *_
     __syncthreads();
     if (t >= nmat) break;
     const int32_t m = order[t];
-    bits |= thin_run_body<WG, kOne, false>(lds, win + mwin[m], mwin[m + 1] - mwin[m] - 1, level_ptr, nrhs, srp, sci,
-                                           sva, sdg, ovp, nullptr, nullptr, nullptr, bp, xp, nullptr, 0.f);
+    bits |= thin_run_body<WG, kOne, false>(lds, win + mwin[m], mwin[m + 1] - mwin[m] - 1, nrhs, A, nullptr, 0.f);
   }
   if (threadIdx.x == 0) {
     if (bits) atomicOr(err, bits);
@@ -347,9 +408,7 @@ __global__ __launch_bounds__(WG) void k_batch_run(int32_t nmat, const int32_t *_
 template <bool kOne>
 __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t *__restrict__ srp,
                              const int32_t *__restrict__ sci, const double *__restrict__ sva,
-                             const double *__restrict__ sdg, const int32_t *__restrict__ trp,
-                             const int32_t *__restrict__ tci, const double *__restrict__ tva,
-                             const double *__restrict__ bp, double *xp, int *err) {
+                             const double *__restrict__ sdg, const double *__restrict__ bp, double *xp, int *err) {
   const int32_t nr = kOne ? 1 : nrhs;
   const int64_t items = (int64_t)(pe - pb) * nr;
   int bits = 0;
@@ -357,7 +416,7 @@ __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t
        it += (int64_t)gridDim.x * blockDim.x) {
     const int32_t pos = kOne ? pb + (int32_t)it : pb + (int32_t)(it / nr);
     const int32_t c = kOne ? 0 : (int32_t)(it - (int64_t)(pos - pb) * nr);
-    const double xv = row_solve<false, kOne>(pos, c, nr, srp, sci, sva, sdg, trp, tci, tva, bp, xp, nullptr, 0);
+    const double xv = row_solve<false, kOne>(pos, c, nr, srp, sci, sva, sdg, bp, xp, nullptr, 0);
     if (!isfinite(xv)) bits |= EB_NONFINITE;
     xp[(int64_t)pos * nr + c] = xv;
   }
@@ -369,9 +428,8 @@ __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t
 template <int G>
 __global__ void k_wide_level_group(int32_t pb, int32_t pe, const int32_t *__restrict__ srp,
                                    const int32_t *__restrict__ sci, const double *__restrict__ sva,
-                                   const double *__restrict__ sdg, const int32_t *__restrict__ trp,
-                                   const int32_t *__restrict__ tci, const double *__restrict__ tva,
-                                   const double *__restrict__ bp, double *xp, int *err) {
+                                   const double *__restrict__ sdg, const double *__restrict__ bp, double *xp,
+                                   int *err) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int sub = threadIdx.x & (G - 1);
   int bits = 0;
@@ -379,10 +437,6 @@ __global__ void k_wide_level_group(int32_t pb, int32_t pe, const int32_t *__rest
   for (int64_t rr = gid / G; rr < (rows + 0); rr += ((int64_t)gridDim.x * blockDim.x) / G) {
     const int32_t pos = pb + (int32_t)rr;
     double acc = 0.0;
-    if (trp) {
-      const int32_t tb = trp[pos], te = trp[pos + 1];
-      for (int32_t q = tb + sub; q < te; q += G) acc += tva[q] * bp[tci[q]];
-    }
     const int32_t b = srp[pos], e = srp[pos + 1];
     for (int32_t q = b + sub; q < e; q += G) acc -= sva[q] * xp[sci[q]];
 #pragma unroll
@@ -420,6 +474,23 @@ __global__ void k_gather(int32_t n, int32_t nrhs, const double *__restrict__ b, 
 __global__ void k_gather1(int32_t n, const double *__restrict__ b, const int32_t *__restrict__ iperm, double *bp) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
     bp[iperm[r]] = b[r];
+}
+
+// The b-transform of the rewritten system (Sec. II.B): b'(pos, c) = t(pos, c) +
+// sum over the off-diagonal entries of T's row, in the row's order, of
+// T(pos, k) t(k, c), where t is b already in level order (T's unit diagonal is
+// implicit). t and bp must not overlap.
+__global__ void k_apply_t(int32_t n, int32_t nrhs, const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
+                          const double *__restrict__ tva, const double *__restrict__ t, double *__restrict__ bp) {
+  const int64_t total = (int64_t)n * nrhs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t pos = (int32_t)(i / nrhs);
+    const int32_t c = (int32_t)(i - (int64_t)pos * nrhs);
+    double acc = t[i];
+    const int32_t qb = trp[pos], qe = trp[pos + 1];
+    for (int32_t q = qb; q < qe; ++q) acc += tva[q] * t[(int64_t)tci[q] * nrhs + c];
+    bp[i] = acc;
+  }
 }
 
 __global__ void k_scatter(int32_t n, int32_t nrhs, const double *__restrict__ xp, const int32_t *__restrict__ iperm,
@@ -536,6 +607,14 @@ hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, 
   return hipGetLastError();
 }
 
+hipError_t launch_apply_t(int32_t n, int32_t nrhs, const int32_t *trp, const int32_t *tci, const double *tva,
+                          const double *t, double *bp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_apply_t, dim3(grid_for((int64_t)n * nrhs, 256, 16384)), dim3(256), 0, s, n, nrhs, trp, tci, tva,
+                     t, bp);
+  return hipGetLastError();
+}
+
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -546,27 +625,25 @@ hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32
   return hipGetLastError();
 }
 
-hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, const int32_t *level_ptr, int32_t nrhs,
-                           const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                           const int32_t *ovp, const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
-                           double *xp, int *err, hipStream_t s, float *times, float ns_per_tick) {
+hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
+                           hipStream_t s, float *times, float ns_per_tick) {
   const bool one = nrhs == 1;
   if (times) {  // labelling runs only: 512 threads
     if (one)
-      hipLaunchKernelGGL((k_thin_run<512, true, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, level_ptr, nrhs,
-                         srp, sci, sva, sdg, ovp, trp, tci, tva, bp, xp, err, times, ns_per_tick);
+      hipLaunchKernelGGL((k_thin_run<512, true, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, nrhs, a, err,
+                         times, ns_per_tick);
     else
-      hipLaunchKernelGGL((k_thin_run<512, false, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, level_ptr, nrhs,
-                         srp, sci, sva, sdg, ovp, trp, tci, tva, bp, xp, err, times, ns_per_tick);
+      hipLaunchKernelGGL((k_thin_run<512, false, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, nrhs, a, err,
+                         times, ns_per_tick);
     return hipGetLastError();
   }
-#define THIN(W)                                                                                                   \
-  if (one)                                                                                                        \
-    hipLaunchKernelGGL((k_thin_run<W, true>), dim3(1), dim3(W), kWinBytes, s, win, nwin, level_ptr, nrhs, srp, sci, \
-                       sva, sdg, ovp, trp, tci, tva, bp, xp, err, (float *)nullptr, 0.f);                              \
-  else                                                                                                            \
-    hipLaunchKernelGGL((k_thin_run<W, false>), dim3(1), dim3(W), kWinBytes, s, win, nwin, level_ptr, nrhs, srp,     \
-                       sci, sva, sdg, ovp, trp, tci, tva, bp, xp, err, (float *)nullptr, 0.f);
+#define THIN(W)                                                                                              \
+  if (one)                                                                                                   \
+    hipLaunchKernelGGL((k_thin_run<W, true>), dim3(1), dim3(W), kWinBytes, s, win, nwin, nrhs, a, err,       \
+                       (float *)nullptr, 0.f);                                                               \
+  else                                                                                                       \
+    hipLaunchKernelGGL((k_thin_run<W, false>), dim3(1), dim3(W), kWinBytes, s, win, nwin, nrhs, a, err,      \
+                       (float *)nullptr, 0.f);
   if (wg == 256) {
     THIN(256)
   } else if (wg == 1024) {
@@ -578,18 +655,24 @@ hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, const int32_t 
   return hipGetLastError();
 }
 
+hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, const double *sva, int4 *ell_c,
+                           double2 *ell_v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_ell, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, n, srp, sci, sva, ell_c, ell_v);
+  return hipGetLastError();
+}
+
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                             const int32_t *trp, const int32_t *tci, const double *tva, const double *bp,
-                             double *xp, int *err, hipStream_t s) {
+                             const double *bp, double *xp, int *err, hipStream_t s) {
   const int64_t rows = pe - pb;
   if (rows <= 0) return hipSuccess;
   if (nrhs == 1 && lanes_per_row > 1) {
     const int64_t items = rows * lanes_per_row;
     const int g = grid_for(items, threads, 65536);
 #define GRP(G)                                                                                                   \
-  hipLaunchKernelGGL((k_wide_level_group<G>), dim3(g), dim3(threads), 0, s, pb, pe, srp, sci, sva, sdg, trp, tci, \
-                     tva, bp, xp, err);
+  hipLaunchKernelGGL((k_wide_level_group<G>), dim3(g), dim3(threads), 0, s, pb, pe, srp, sci, sva, sdg, bp, xp, \
+                     err);
     switch (lanes_per_row) {
       case 2: GRP(2) break;
       case 4: GRP(4) break;
@@ -603,11 +686,11 @@ hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t
   const int64_t items = rows * nrhs;
   const int g = grid_for(items, threads, 65536);
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_wide_level<true>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, trp,
-                       tci, tva, bp, xp, err);
+    hipLaunchKernelGGL((k_wide_level<true>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, bp, xp,
+                       err);
   else
-    hipLaunchKernelGGL((k_wide_level<false>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, trp,
-                       tci, tva, bp, xp, err);
+    hipLaunchKernelGGL((k_wide_level<false>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, bp, xp,
+                       err);
   return hipGetLastError();
 }
 
@@ -621,9 +704,7 @@ hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int
 }
 
 hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int2 *win,
-                            const int32_t *level_ptr, int32_t nrhs, const int32_t *srp, const int32_t *sci,
-                            const double *sva, const double *sdg, const int32_t *ovp, const double *bp, double *xp,
-                            unsigned *q, int *err, hipStream_t s) {
+                            int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_run<512, true>),
@@ -633,11 +714,11 @@ hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, co
     attr = true;
   }
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_batch_run<512, true>), dim3(grid), dim3(512), kWinBytes, s, nmat, order, mwin, win,
-                       level_ptr, nrhs, srp, sci, sva, sdg, ovp, bp, xp, q, err);
+    hipLaunchKernelGGL((k_batch_run<512, true>), dim3(grid), dim3(512), kWinBytes, s, nmat, order, mwin, win, nrhs, a,
+                       q, err);
   else
-    hipLaunchKernelGGL((k_batch_run<512, false>), dim3(grid), dim3(512), kWinBytes, s, nmat, order, mwin, win,
-                       level_ptr, nrhs, srp, sci, sva, sdg, ovp, bp, xp, q, err);
+    hipLaunchKernelGGL((k_batch_run<512, false>), dim3(grid), dim3(512), kWinBytes, s, nmat, order, mwin, win, nrhs,
+                       a, q, err);
   return hipGetLastError();
 }
 

@@ -96,7 +96,7 @@ def lib():
         "sptrsv_prepare": [vp, C.c_int, i32, vp],
         "sptrsv_check": [vp, vp],
         "sptrsv_set_schedule": [vp, C.c_int, C.POINTER(Schedule)],
-        "sptrsv_get_schedule": [vp, C.c_int, C.POINTER(Schedule)],
+        "sptrsv_get_schedule": [vp, C.c_int, C.c_int32, C.POINTER(Schedule)],
         "sptrsv_autotune": [vp, C.c_int, i32, vp, C.POINTER(f32)],
         "sptrsv_graph_create": [vp, C.c_int, i32, vp, i64, vp, i64, vp, C.POINTER(i32)],
         "sptrsv_graph_launch": [vp, i32, vp],
@@ -300,9 +300,10 @@ class Handle:
         s = Schedule(mode, thin_rows, wg_threads, wide_threads, lanes_per_row)
         self._check(self._L.sptrsv_set_schedule(self._h, which, C.byref(s)))
 
-    def get_schedule(self, which=ORIGINAL):
+    def get_schedule(self, which=ORIGINAL, nrhs=1):
+        """The schedule a solve with nrhs right-hand sides uses."""
         s = Schedule()
-        self._check(self._L.sptrsv_get_schedule(self._h, which, C.byref(s)))
+        self._check(self._L.sptrsv_get_schedule(self._h, which, nrhs, C.byref(s)))
         return s.as_dict()
 
     def autotune(self, which=ORIGINAL, nrhs=1) -> float:

@@ -203,6 +203,23 @@ def test_autotune_keeps_parity(handles):
     b = gen.rhs(m, 1)
     x = h.solve(to_dev(b))
     assert oracle.relerr(x.cpu().numpy(), oracle.solve(m, b)) <= TOL
+    h.set_schedule()
+
+
+def test_set_schedule_replaces_tuned(handles):
+    m, h, _ = handles["cfg2_small"]
+    h.autotune(nrhs=2)
+    tuned = h.get_schedule(nrhs=2)
+    assert tuned["mode"] in (0, 1, 2)
+    assert h.get_schedule(nrhs=1) == dict(mode=0, thin_rows=4096, wg_threads=512, wide_threads=256, lanes_per_row=1)
+    want = dict(mode=0, thin_rows=64, wg_threads=256, wide_threads=128, lanes_per_row=1)
+    h.set_schedule(**want)
+    assert h.get_schedule(nrhs=2) == want  # an explicit schedule replaces the tuned one
+    h.prepare(nrhs=2)
+    b = gen.rhs(m, 2)
+    x = h.solve(to_dev(b))
+    assert oracle.relerr(x.cpu().numpy(), oracle.solve(m, b)) <= TOL
+    h.set_schedule()
 
 
 def test_empty_matrix():

@@ -37,8 +37,10 @@ WORKLOADS = {
     0: "window-64 random lower CSR, n=2,000, up to 5 off-diagonals/row, nrhs=1",
     1: "2D 1000x1000 5-point lower factor + 20,000-row chain, n=1,020,000, nnz=3,078,000, nrhs=1",
     2: "power-law (Zipf 1.2 in-degree) lower CSR, n=4,000,000, mean 8 off-diagonals/row, nrhs=1",
+    3: "512 window-64 random lower CSR matrices, n_i uniform in [1000, 50000], ~6 nnz/row, nrhs=16 each",
     4: "3D 200^3 7-point lower factor + 5,000-row tail, n=8,005,000, nnz=31,900,000, nrhs=32",
 }
+GRAPH_DEFAULT = {4}  # workloads timed as hipGraph replays of the solve
 
 
 def log(*a):
@@ -55,11 +57,16 @@ def alg_bytes(n, nnz, nlev, nrhs, nnz_t=0, rewritten=False):
     return 12.0 * (nnz + nnz_t) + 12.0 * n + 4.0 * (nlev + 1) + 16.0 * n * nrhs
 
 
-def source_hash():
+KERNEL_SOURCE = {"k_thin_run": "k_thin.hip", "k_batch_run": "k_thin.hip", "k_wide_level": "k_wide.hip",
+                 "k_gather": "k_vec.hip", "k_scatter": "k_vec.hip"}
+
+
+def source_hash(kernel):
+    """Hash of the source file of a kernel together with the shared header."""
     h = hashlib.sha256()
-    p = os.path.join(ROOT, "paper_2206_05843_amd", "csrc", "k_solve.hip")
-    with open(p, "rb") as f:
-        h.update(f.read())
+    for name in (KERNEL_SOURCE[kernel], "common.h"):
+        with open(os.path.join(ROOT, "paper_2206_05843_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -73,9 +80,112 @@ def load_traffic(kernel, workload_key):
     except (OSError, ValueError):
         return None
     e = d.get(f"{kernel}:{workload_key}")
-    if not e or e.get("source_hash") != source_hash():
+    if not e or e.get("source_hash") != source_hash(kernel):
         return None
     return e.get("bytes_per_launch")
+
+
+def bench_batch(args, np, torch, gen, oracle, sp):
+    """The batched workload: every matrix and right-hand side in one persistent
+    launch (captured in a hipGraph and replayed) against the loop of
+    per-matrix solves it replaces. A step solves all matrices."""
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    mats, nrhs = gen.config_matrix(3)
+    ns = [m.n for m in mats]
+    rp = torch.from_numpy(np.concatenate([m.row_ptr for m in mats]).astype(np.int32)).to(dev)
+    ci = torch.from_numpy(np.concatenate([m.col for m in mats])).to(dev)
+    va = torch.from_numpy(np.concatenate([m.val for m in mats])).to(dev)
+    b_np = [gen.rhs(m, nrhs) for m in mats]
+    b = torch.from_numpy(np.concatenate([x.reshape(-1) for x in b_np])).to(dev)
+    n_tot, nnz_tot = sum(ns), sum(m.nnz for m in mats)
+    log(f"[bench] generated {len(mats)} matrices, n={n_tot} nnz={nnz_tot} nrhs={nrhs} "
+        f"in {time.perf_counter() - t0:.1f}s")
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    h = sp.Handle()
+    t = time.perf_counter()
+    h.batch_analyze(ns, rp, ci, va)
+    torch.cuda.synchronize()
+    pre = time.perf_counter() - t
+    nlev = [int(h.batch_levels(i)[0].numel()) - 1 for i in range(len(mats))]
+    x = torch.zeros_like(b)
+    h.batch_solve(b, x, nrhs)
+    h.check()
+    xs = x.cpu().numpy()
+    off, worst = 0, 0.0
+    t = time.perf_counter()
+    for m, bm in zip(mats, b_np):
+        xm = xs[off * nrhs:(off + m.n) * nrhs].reshape(nrhs, m.n)
+        worst = max(worst, oracle.relerr(xm, oracle.solve(m, bm)))
+        off += m.n
+    t_oracle_all = time.perf_counter() - t
+    if not worst <= TOL:
+        raise SystemExit(f"[bench] batched solve failed parity: relerr={worst:.3e}")
+    x2 = torch.zeros_like(b)
+    h.batch_solve(b, x2, nrhs, looped=True)
+    h.check()
+    if not torch.equal(x, x2):
+        raise SystemExit("[bench] looped and batched solutions differ")
+    log(f"[bench] parity ok: max relerr {worst:.2e} over {len(mats)} matrices; oracle {t_oracle_all:.1f}s")
+
+    def run_steps(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / steps
+
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        h.batch_solve(b, x, nrhs)
+    ms = run_steps(g.replay, args.steps, args.warmup)
+    h.check()
+    ms_eager = run_steps(lambda: h.batch_solve(b, x, nrhs), max(5, args.steps // 2), args.warmup)
+    ms_loop = run_steps(lambda: h.batch_solve(b, x2, nrhs, looped=True), max(5, args.steps // 2), args.warmup)
+    h.check()
+    # live event timing of the persistent kernel on the solve stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        h.batch_solve(b, x, nrhs)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms_ev = sum(e0.elapsed_time(e1) for e0, e1 in ev) / len(ev)
+    alg = sum(12.0 * m.nnz + 8.0 * m.n + 4.0 * (nl + 1) + 16.0 * m.n * nrhs for m, nl in zip(mats, nlev))
+    achieved = alg / (ms_ev * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu:
+        reps = max(1, int(12.0 / max(t_oracle_all, 1e-6)))
+        t = time.perf_counter()
+        for _ in range(reps):
+            for m, bm in zip(mats, b_np):
+                oracle.solve(m, bm)
+        el_c = time.perf_counter() - t
+        cpu = {"value": round(reps / el_c, 4), "unit": "batch solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} passes over all {len(mats)} matrices x {nrhs} RHS by the serial FP64 oracle "
+                         f"({el_c:.1f}s); host nproc={os.cpu_count()}"}
+    res = {
+        "metric": METRIC, "value": round(1e3 / ms, 3), "unit": "batch solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator of the workload's structure; no dataset)",
+        "config": {"workload": WORKLOADS[3], "variant": "batched persistent launch, hipGraph replays",
+                   "nmat": len(mats), "n": n_tot, "nnz": nnz_tot, "nrhs": nrhs, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None, "kernel": "k_batch_run",
+                     "avg_step_ms_events": round(ms_ev, 5), "alg_bytes_per_step": alg},
+        "cpu_baseline": cpu,
+        "variants": {"batched_graph": {"ms": round(ms, 5)}, "batched_eager": {"ms": round(ms_eager, 5)},
+                     "looped_per_matrix": {"ms": round(ms_loop, 5)}},
+        "speedup_vs_looped": round(ms_loop / ms, 4),
+        "matrix_solves_per_s": round(len(mats) * 1e3 / ms, 1),
+        "preprocess_s": round(pre, 3), "max_relerr": worst,
+        "levels": {"min": min(nlev), "max": max(nlev), "total": sum(nlev)},
+    }
+    print(json.dumps(res), flush=True)
 
 
 def calibrate_copy(torch, mib):
@@ -104,6 +214,8 @@ def main():
     ap.add_argument("--schedules", default=None,
                     help="JSON object variant -> schedule (mode, thin_rows, wg_threads, wide_threads, "
                          "lanes_per_row); those variants skip the autotuner (for profiled runs)")
+    ap.add_argument("--graph", type=int, default=None, choices=(0, 1),
+                    help="time hipGraph replays of the solve (default: on for the 3D stencil workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (the reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -125,6 +237,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.config == 3:
+        bench_batch(args, np, torch, gen, oracle, sp)
+        return
+    use_graph = (args.config in GRAPH_DEFAULT) if args.graph is None else bool(args.graph)
+    stream = torch.cuda.Stream()  # graph capture needs a non-default stream
+    torch.cuda.set_stream(stream)
     t0 = time.perf_counter()
     m, nrhs = gen.config_matrix(args.config)
     b_np = gen.rhs(m, nrhs)
@@ -190,19 +308,43 @@ def main():
             log(f"[bench] learned policy unavailable: {e}")
 
     def timed(name, steps, warmup, profile=False):
+        """Wall time of `steps` solves (graph replays if use_graph), and with
+        profile=True the per-kernel-class HIP-event profile: of these solves
+        when a solve is a few launches, else (the events would add host work
+        to every launch) and for graph replays (no events inside a graph) of
+        as many eager solves right after."""
         h, which, _ = variants[name]
         x = torch.empty_like(b)
+        if use_graph:
+            gid = h.graph_create(b, x, which)
+            run = lambda: h.graph_launch(gid)  # noqa: E731
+        else:
+            run = lambda: h.solve(b, which, x)  # noqa: E731
         for _ in range(warmup):
-            h.solve(b, which, x)
+            run()
         torch.cuda.synchronize()
-        if profile:
+        in_region = False
+        if profile and not use_graph:
+            h.profile_start()
+            h.solve(b, which, x)
+            torch.cuda.synchronize()
+            in_region = sum(v["launches"] for v in h.profile_stop().values()) <= 4
+        if in_region:
             h.profile_start()
         t = time.perf_counter()
         for _ in range(steps):
-            h.solve(b, which, x)
+            run()
         torch.cuda.synchronize()
         el = time.perf_counter() - t
-        prof = h.profile_stop() if profile else None
+        prof = None
+        if profile:
+            if not in_region:
+                h.profile_start()
+                for _ in range(steps):
+                    h.solve(b, which, x)
+                torch.cuda.synchronize()
+            prof = h.profile_stop()
+            prof["in_timed_region"] = in_region
         h.check()
         return el, prof
 
@@ -217,6 +359,7 @@ def main():
     ms = el * 1e3 / args.steps
 
     # roofline of the dominant kernel class, from the live profile
+    in_region = prof.pop("in_timed_region")
     dom = max(prof, key=lambda k: prof[k]["ms"])
     dp = prof[dom]
     per_launch_ms = dp["ms"] / max(1, dp["launches"])
@@ -229,6 +372,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic, "kernel": kname,
                 "launches": dp["launches"], "avg_launch_ms": round(per_launch_ms, 5),
                 "alg_bytes_per_launch": bytes_per_launch,
+                "events": "timed region" if in_region else "eager solves after the timed region",
                 "kernel_share_of_step": round(sum(v["ms"] for v in prof.values()) and dp["ms"] /
                                               sum(v["ms"] for v in prof.values()), 4)}
 
@@ -269,7 +413,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded generator of the workload's structure; no dataset)",
         "config": {"workload": WORKLOADS[args.config], "variant": headline, "nrhs": nrhs, "n": m.n, "nnz": m.nnz,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "timing": "hipGraph replays" if use_graph else "stream launches"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": out_var,

@@ -175,6 +175,9 @@ typedef struct {
   int32_t wg_threads;     /* 256, 512 or 1024 */
   int32_t wide_threads;   /* 64 .. 1024, multiple of 64 */
   int32_t lanes_per_row;  /* wide levels, nrhs == 1: 1, 2, 4, 8, 16 or 32 lanes per row */
+  int32_t wide_grid;      /* 0: one launch per wide level; > 0: consecutive wide levels in one persistent launch
+                             of up to wide_grid workgroups (capped to what is resident at once) with a
+                             device-wide barrier between levels (lanes_per_row is then 1) */
 } sptrsv_schedule_t;
 sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_schedule_t *sched);
 sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, sptrsv_schedule_t *sched);

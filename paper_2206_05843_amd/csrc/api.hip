@@ -47,12 +47,13 @@ sptrsv_schedule_t default_schedule() {
   s.wg_threads = 512;
   s.wide_threads = 256;
   s.lanes_per_row = 1;
+  s.wide_grid = 0;
   return s;
 }
 
 bool same_sched(const sptrsv_schedule_t &a, const sptrsv_schedule_t &b) {
   return a.mode == b.mode && a.thin_rows == b.thin_rows && a.wg_threads == b.wg_threads &&
-         a.wide_threads == b.wide_threads && a.lanes_per_row == b.lanes_per_row;
+         a.wide_threads == b.wide_threads && a.lanes_per_row == b.lanes_per_row && a.wide_grid == b.wide_grid;
 }
 
 sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
@@ -65,6 +66,7 @@ sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
   if (g != 1 && g != 2 && g != 4 && g != 8 && g != 16 && g != 32)
     return set_err(h, SPTRSV_ERR_ARG, "lanes_per_row %d", g);
   if (s.thin_rows < 0) return set_err(h, SPTRSV_ERR_ARG, "thin_rows %d", s.thin_rows);
+  if (s.wide_grid < 0 || s.wide_grid > 65536) return set_err(h, SPTRSV_ERR_ARG, "wide_grid %d", s.wide_grid);
   return SPTRSV_OK;
 }
 
@@ -123,7 +125,8 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
     const int64_t rows = rows_of(l);
     bool thin = sc.mode == 2 || (sc.mode == 0 && rows <= thr);
     if (win_bytes(rows, offd_of(l), 1, nrhs) > cap) thin = false;  // must fit one window alone
-    if (thin && !P.runs.empty() && P.runs.back().thin && P.runs.back().l1 == l)
+    // consecutive thin levels share a run; so do consecutive wide levels with a persistent launch
+    if (!P.runs.empty() && P.runs.back().thin == thin && P.runs.back().l1 == l && (thin || sc.wide_grid > 0))
       P.runs.back().l1 = l + 1;
     else
       P.runs.push_back(Run{l, l + 1, thin});
@@ -221,6 +224,8 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   HIPCHK(h, P.ell_c.alloc(n));
   HIPCHK(h, P.ell_v.alloc((size_t)2 * n));
   HIPCHK(h, launch_fill_ell(n, P.srp.p, P.sci.p, P.sva.p, P.ell_c.p, P.ell_v.p, s));
+  HIPCHK(h, P.wbar.alloc(2));
+  HIPCHK(h, hipMemsetAsync(P.wbar.p, 0, 2 * sizeof(unsigned), s));
   HIPCHK(h, P.ovp.alloc((size_t)n + 1));
   HIPCHK(h, launch_count_ovf(P.srp.p, n, cnt.p, s));
   HIPCHK(h, launch_scan_i64(cnt.p, ex.p, n, h->scan_tmp.p, s));
@@ -267,6 +272,14 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
     P.h_lv_tnnz.resize((size_t)nlev);
     for (int32_t l = 0; l < nlev; ++l)
       P.h_lv_tnnz[(size_t)l] = htrp[(size_t)P.h_level_ptr[l + 1]] - htrp[(size_t)P.h_level_ptr[l]];
+    // positions whose row of T has off-diagonals: the only rows b' = T b changes
+    std::vector<int32_t> tpos;
+    for (int32_t p = 0; p < n; ++p)
+      if (htrp[(size_t)p + 1] > htrp[(size_t)p]) tpos.push_back(p);
+    P.n_tpos = (int32_t)tpos.size();
+    HIPCHK(h, P.tpos.alloc(std::max<size_t>(tpos.size(), 1)));
+    if (!tpos.empty())
+      HIPCHK(h, hipMemcpy(P.tpos.p, tpos.data(), sizeof(int32_t) * tpos.size(), hipMemcpyHostToDevice));
   }
   long long tot;
   std::memcpy(&tot, haux + 4, sizeof(tot));
@@ -308,14 +321,12 @@ ThinArgs thin_args(const Plan &P) {
 }
 
 // b (caller's layout) -> bp (level order, interleaved); for the rewritten
-// system b' = T b, with the plain gather staged in xp (the solve overwrites it).
+// system b' = T b, where only the rows of T with off-diagonals differ from b:
+// those are recomputed from the caller's b after the plain gather.
 sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, hipStream_t s) {
-  if (!P.has_t) {
-    HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.bp.p, s));
-    return SPTRSV_OK;
-  }
-  HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.xp.p, s));
-  HIPCHK(h, launch_apply_t(P.n, nrhs, P.trp.p, P.tci.p, P.tva.p, P.xp.p, P.bp.p, s));
+  HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.bp.p, s));
+  if (P.has_t && P.n_tpos > 0)
+    HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.tpos.p, P.perm.p, P.trp.p, P.tci.p, P.tva.p, b, ldb, P.bp.p, s));
   return SPTRSV_OK;
 }
 
@@ -334,6 +345,9 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
     slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
     if (r.thin) {
       HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, thin_args(P), err, s));
+    } else if (sc.wide_grid > 0) {
+      HIPCHK(h, launch_wide_run(sc.wide_grid, sc.wide_threads, r.l0, r.l1, P.level_ptr.p, nrhs, P.srp.p, P.sci.p,
+                                P.sva.p, P.sdg.p, P.bp.p, P.xp.p, P.wbar.p, err, s));
     } else {
       HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
                                   P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.bp.p, P.xp.p, err, s));

@@ -58,11 +58,6 @@ __global__ void k_offset_copy(const int32_t *__restrict__ src, int32_t n, int32_
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i] - off;
 }
 
-int grid_for(int64_t items, int threads, int cap) {
-  int64_t g = (items + threads - 1) / threads;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
-}
-
 int bit_width64(int64_t v) {
   int b = 0;
   while (v > 0) ++b, v >>= 1;

@@ -25,17 +25,20 @@ std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
   const int wg_list[] = {256, 512, 1024};
   const int lpr1[] = {1, 4};
   for (int wg : wg_list) {
-    sptrsv_schedule_t s{2, 0, wg, 256, 1};
+    sptrsv_schedule_t s{2, 0, wg, 256, 1, 0};
     c.push_back(s);
   }
   for (int lpr : lpr1) {
     if (nrhs > 1 && lpr > 1) continue;
-    c.push_back(sptrsv_schedule_t{1, 0, 512, 256, lpr});
+    c.push_back(sptrsv_schedule_t{1, 0, 512, 256, lpr, 0});
     for (int thr : thin_list) {
       if (thin_window_bytes(thr, 0, 1, nrhs) > thin_win_bytes()) continue;
-      for (int wg : wg_list) c.push_back(sptrsv_schedule_t{0, thr, wg, 256, lpr});
+      for (int wg : wg_list) c.push_back(sptrsv_schedule_t{0, thr, wg, 256, lpr, 0});
     }
   }
+  // Persistent wide runs (wide_grid > 0) are not candidates: their device-wide
+  // barrier (device-scope release/acquire fences in every wave) costs more per
+  // level than a kernel launch on a device whose L2 is split across dies.
   return c;
 }
 

@@ -87,6 +87,8 @@ struct Plan {
   int64_t nnz_t_off = 0;
   DArr<int32_t> trp, tci;              // T off-diagonals per position
   DArr<double> tva;
+  DArr<int32_t> tpos;                  // positions whose row of T has off-diagonals
+  int32_t n_tpos = 0;
   DArr<int64_t> lv_rows, lv_nnz, lv_cost;
   std::vector<int64_t> h_lv_nnz;       // per level: nnz incl. diagonal (host copy)
   std::vector<int64_t> h_lv_tnnz;      // per level: off-diagonal nnz of T
@@ -104,6 +106,7 @@ struct Plan {
   int32_t runs_nrhs = -1;
   sptrsv_schedule_t runs_sched{};
   DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
+  DArr<unsigned> wbar;                 // [2] barrier counters of persistent wide runs (zero between launches)
   int32_t work_nrhs = 0;
 };
 
@@ -213,6 +216,14 @@ __host__ __device__ inline int64_t thin_window_bytes(int64_t rows, int64_t ovf, 
   return rows * (8 * (int64_t)nrhs + 24) + 8 * (int64_t)nrhs + ovf * 16 + 4 * (nl + 1);
 }
 
+// Workgroups for a grid-stride launch over `items` items, at most `cap`.
+inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
+  int64_t g = (items + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
 // Device arrays a thin run reads (the level-ordered plan and work vectors).
 struct ThinArgs {
   const int32_t *level_ptr, *srp, *sci, *ovp;
@@ -226,8 +237,9 @@ struct ThinArgs {
 // Launchers (k_solve.hip) ------------------------------------------------------
 hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
                          hipStream_t s);
-hipError_t launch_apply_t(int32_t n, int32_t nrhs, const int32_t *trp, const int32_t *tci, const double *tva,
-                          const double *t, double *bp, hipStream_t s);
+hipError_t launch_apply_t(int32_t nt, int32_t nrhs, const int32_t *tpos, const int32_t *perm, const int32_t *trp,
+                          const int32_t *tci, const double *tva, const double *b, int64_t ldb, double *bp,
+                          hipStream_t s);
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
 int thin_win_bytes();
@@ -239,6 +251,10 @@ hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, co
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                              const double *bp, double *xp, int *err, hipStream_t s);
+hipError_t launch_wide_run(int grid, int threads, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
+                           const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
+                           const double *bp, double *xp, unsigned *bar, int *err, hipStream_t s);
+int wide_run_resident_blocks(int threads);
 hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,
                            const double *b, int64_t ldb, const double *x, int64_t ldx, unsigned long long *out,
                            hipStream_t s);

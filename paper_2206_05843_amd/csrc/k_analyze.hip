@@ -7,13 +7,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
-  int64_t g = (items + threads - 1) / threads;
-  if (g < 1) g = 1;
-  if (g > cap) g = cap;
-  return static_cast<int>(g);
-}
-
 // ---------------------------------------------------------------------------
 // Validation (Algorithm 1 reads the diagonal at the last slot of each row):
 // one thread per row; row ranges are checked before they are dereferenced so

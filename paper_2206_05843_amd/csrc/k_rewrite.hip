@@ -577,13 +577,6 @@ __global__ __launch_bounds__(64 * kWaves) void k_feat_rows(int32_t n, const int3
   }
 }
 
-inline int grid_for(int64_t items, int threads, int cap) {
-  int64_t g = (items + threads - 1) / threads;
-  if (g < 1) g = 1;
-  if (g > cap) g = cap;
-  return (int)g;
-}
-
 }  // namespace
 
 size_t rewrite_big_ws_bytes(int32_t C, int32_t H) { return (size_t)C * 13 + (size_t)H * 8 + 64; }

@@ -1,7 +1,7 @@
-// Solve kernels: level-by-level forward substitution (Sec. II.A, Algorithm 1)
-// over the level-ordered copy of L, or of the rewritten L' (Sec. II.B) after
-// the b-transform b' = T b, which does not depend on x and so runs as one
-// parallel pass before the level chain starts.
+// Thin-run solve kernels: level-by-level forward substitution (Sec. II.A,
+// Algorithm 1) over the level-ordered copy of L, or of the rewritten L'
+// (Sec. II.B) after the b-transform b' = T b (applied before the level chain
+// starts, since it does not depend on x). Wide levels are in k_wide.hip.
 //
 // Work vectors are permuted to level order and RHS-interleaved: entry (pos, c)
 // of bp/xp is at pos*nrhs + c, so the rows of one level are contiguous and one
@@ -28,28 +28,6 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// x(pos, c) = (b'(pos, c) - sum_k L(pos,k) x(k,c)) / L(pos,pos). Columns
-// < lds_base come from global memory, columns >= lds_base from the LDS window.
-template <bool kUseLds, bool kOne>
-__device__ __forceinline__ double row_solve(int32_t pos, int32_t c, int32_t nrhs, const int32_t *__restrict__ srp,
-                                            const int32_t *__restrict__ sci, const double *__restrict__ sva,
-                                            const double *__restrict__ sdg, const double *__restrict__ bp,
-                                            const double *xp, const double *lds, int32_t lds_base) {
-  const int64_t nr = kOne ? 1 : nrhs;
-  double acc = bp[(int64_t)pos * nr + c];
-  const int32_t b = srp[pos], e = srp[pos + 1];
-  for (int32_t q = b; q < e; ++q) {
-    const int32_t k = sci[q];
-    double xv;
-    if (kUseLds && k >= lds_base)
-      xv = lds[(int64_t)(k - lds_base) * nr + c];
-    else
-      xv = xp[(int64_t)k * nr + c];
-    acc -= sva[q] * xv;
-  }
-  return acc / sdg[pos];
 }
 
 // A thin run is cut into LDS windows (consecutive levels, chosen on the host so
@@ -160,6 +138,11 @@ template <int WG, bool kOne>
 constexpr int p1_items() {
   return WG >= 1024 ? (kOne ? 3 : 2) : 6;
 }
+// ... and dependencies per batch beyond a row's first four.
+template <int WG, bool kOne>
+constexpr int p1_tail() {
+  return WG >= 1024 && kOne ? 2 : 4;
+}
 
 // The windows [win, win + nwin) of one thin run, by the calling workgroup.
 // Returns the latched error bits; a window that does not fit aborts the run.
@@ -262,9 +245,23 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
 #pragma unroll
         for (int d = 0; d < 4; ++d)
           if (d < deg[j]) take(kk[d], vv[d], xv[j][d]);
-        for (int32_t q = qb[j] + 4; q < qb[j] + deg[j]; ++q) {
-          const int32_t k = sci[q];
-          take(k, sva[q], k < P0 ? xp[(int64_t)k * nr + c] : 0.0);
+        // dependencies beyond the fixed-width copy: kTail at a time, loads first
+        constexpr int kTail = p1_tail<WG, kOne>();
+        for (int32_t q0 = qb[j] + 4; q0 < qb[j] + deg[j]; q0 += kTail) {
+          const int32_t qe = qb[j] + deg[j];
+          int32_t k4[kTail];
+          double w4[kTail], x4[kTail];
+#pragma unroll
+          for (int d = 0; d < kTail; ++d) {
+            k4[d] = q0 + d < qe ? sci[q0 + d] : -1;
+            w4[d] = q0 + d < qe ? sva[q0 + d] : 0.0;
+          }
+#pragma unroll
+          for (int d = 0; d < kTail; ++d)
+            x4[d] = (k4[d] >= 0 && k4[d] < P0) ? xp[(int64_t)k4[d] * nr + c] : 0.0;
+#pragma unroll
+          for (int d = 0; d < kTail; ++d)
+            if (k4[d] >= 0) take(k4[d], w4[d], x4[d]);
         }
         v[(int64_t)sj[j] * nr + c] = a * dinv;
         if (c == 0) {
@@ -404,176 +401,6 @@ __global__ __launch_bounds__(WG) void k_batch_run(int32_t nmat, const int32_t *_
   }
 }
 
-// One wide level, one item (row, rhs) per thread.
-template <bool kOne>
-__global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t *__restrict__ srp,
-                             const int32_t *__restrict__ sci, const double *__restrict__ sva,
-                             const double *__restrict__ sdg, const double *__restrict__ bp, double *xp, int *err) {
-  const int32_t nr = kOne ? 1 : nrhs;
-  const int64_t items = (int64_t)(pe - pb) * nr;
-  int bits = 0;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t pos = kOne ? pb + (int32_t)it : pb + (int32_t)(it / nr);
-    const int32_t c = kOne ? 0 : (int32_t)(it - (int64_t)(pos - pb) * nr);
-    const double xv = row_solve<false, kOne>(pos, c, nr, srp, sci, sva, sdg, bp, xp, nullptr, 0);
-    if (!isfinite(xv)) bits |= EB_NONFINITE;
-    xp[(int64_t)pos * nr + c] = xv;
-  }
-  if (bits) atomicOr(err, bits);
-}
-
-// One wide level, single RHS, G lanes per row: lanes split the row's products
-// and combine them with a fixed butterfly, so the result is deterministic.
-template <int G>
-__global__ void k_wide_level_group(int32_t pb, int32_t pe, const int32_t *__restrict__ srp,
-                                   const int32_t *__restrict__ sci, const double *__restrict__ sva,
-                                   const double *__restrict__ sdg, const double *__restrict__ bp, double *xp,
-                                   int *err) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int sub = threadIdx.x & (G - 1);
-  int bits = 0;
-  const int64_t rows = pe - pb;
-  for (int64_t rr = gid / G; rr < (rows + 0); rr += ((int64_t)gridDim.x * blockDim.x) / G) {
-    const int32_t pos = pb + (int32_t)rr;
-    double acc = 0.0;
-    const int32_t b = srp[pos], e = srp[pos + 1];
-    for (int32_t q = b + sub; q < e; q += G) acc -= sva[q] * xp[sci[q]];
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-    if (sub == 0) {
-      const double xv = (bp[pos] + acc) / sdg[pos];
-      if (!isfinite(xv)) bits |= EB_NONFINITE;
-      xp[pos] = xv;
-    }
-  }
-  if (bits) atomicOr(err, bits);
-}
-
-// b (column-major, original rows) -> bp (level order, RHS-interleaved). A tile
-// of 64 rows x up to 32 columns is staged in LDS so both sides are coalesced.
-__global__ void k_gather(int32_t n, int32_t nrhs, const double *__restrict__ b, int64_t ldb,
-                         const int32_t *__restrict__ iperm, double *bp) {
-  __shared__ double tile[64][33];
-  const int32_t r0 = blockIdx.x * 64;
-  for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
-    const int32_t nc = min(32, nrhs - c0);
-    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
-      const int c = idx / 64, rr = idx % 64;
-      if (r0 + rr < n) tile[rr][c] = b[(int64_t)(c0 + c) * ldb + r0 + rr];
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
-      const int rr = idx / nc, c = idx % nc;
-      if (r0 + rr < n) bp[(int64_t)iperm[r0 + rr] * nrhs + c0 + c] = tile[rr][c];
-    }
-    __syncthreads();
-  }
-}
-
-__global__ void k_gather1(int32_t n, const double *__restrict__ b, const int32_t *__restrict__ iperm, double *bp) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    bp[iperm[r]] = b[r];
-}
-
-// The b-transform of the rewritten system (Sec. II.B): b'(pos, c) = t(pos, c) +
-// sum over the off-diagonal entries of T's row, in the row's order, of
-// T(pos, k) t(k, c), where t is b already in level order (T's unit diagonal is
-// implicit). t and bp must not overlap.
-__global__ void k_apply_t(int32_t n, int32_t nrhs, const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
-                          const double *__restrict__ tva, const double *__restrict__ t, double *__restrict__ bp) {
-  const int64_t total = (int64_t)n * nrhs;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t pos = (int32_t)(i / nrhs);
-    const int32_t c = (int32_t)(i - (int64_t)pos * nrhs);
-    double acc = t[i];
-    const int32_t qb = trp[pos], qe = trp[pos + 1];
-    for (int32_t q = qb; q < qe; ++q) acc += tva[q] * t[(int64_t)tci[q] * nrhs + c];
-    bp[i] = acc;
-  }
-}
-
-__global__ void k_scatter(int32_t n, int32_t nrhs, const double *__restrict__ xp, const int32_t *__restrict__ iperm,
-                          double *x, int64_t ldx) {
-  __shared__ double tile[64][33];
-  const int32_t r0 = blockIdx.x * 64;
-  for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
-    const int32_t nc = min(32, nrhs - c0);
-    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
-      const int rr = idx / nc, c = idx % nc;
-      if (r0 + rr < n) tile[rr][c] = xp[(int64_t)iperm[r0 + rr] * nrhs + c0 + c];
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
-      const int c = idx / 64, rr = idx % 64;
-      if (r0 + rr < n) x[(int64_t)(c0 + c) * ldx + r0 + rr] = tile[rr][c];
-    }
-    __syncthreads();
-  }
-}
-
-__global__ void k_scatter1(int32_t n, const double *__restrict__ xp, const int32_t *__restrict__ iperm, double *x) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    x[r] = xp[iperm[r]];
-}
-
-// max_i |(L x - b)[i, c]| per column, original numbering; results as the bit
-// patterns of non-negative doubles (monotone as unsigned integers).
-__global__ void k_residual(int32_t n, int32_t nrhs, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                           const double *__restrict__ va, const double *__restrict__ b, int64_t ldb,
-                           const double *__restrict__ x, int64_t ldx, unsigned long long *out) {
-  for (int32_t c = 0; c < nrhs; ++c) {
-    double m = 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-      double s = 0.0;
-      for (int32_t q = rp[r]; q < rp[r + 1]; ++q) s += va[q] * x[(int64_t)c * ldx + ci[q]];
-      const double d = fabs(s - b[(int64_t)c * ldb + r]);
-      m = (d > m || d != d) ? d : m;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double o = __shfl_xor(m, off, 64);
-      m = (o > m || o != o) ? o : m;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMax(out + c, (unsigned long long)__double_as_longlong(m));
-  }
-}
-
-// Batched right-hand sides: matrix m's b and x are n_m x nrhs column-major at
-// offset nrhs * row_off[m], ld = n_m. Items run over (global row, column) with
-// the row fastest, so each column of each matrix is read/written contiguously.
-__global__ void k_batch_gather(int64_t total, int32_t nrhs, const double *__restrict__ b,
-                               const int32_t *__restrict__ mat_of_row, const int64_t *__restrict__ row_off,
-                               const int32_t *__restrict__ iperm, double *bp) {
-  const int64_t items = total * nrhs;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = it / total, r = it - c * total;
-    const int32_t m = mat_of_row[r];
-    const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
-    bp[(int64_t)iperm[r] * nrhs + c] = b[nrhs * ro + c * nm + (r - ro)];
-  }
-}
-
-__global__ void k_batch_scatter(int64_t total, int32_t nrhs, const double *__restrict__ xp,
-                                const int32_t *__restrict__ mat_of_row, const int64_t *__restrict__ row_off,
-                                const int32_t *__restrict__ iperm, double *x) {
-  const int64_t items = total * nrhs;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = it / total, r = it - c * total;
-    const int32_t m = mat_of_row[r];
-    const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
-    x[nrhs * ro + c * nm + (r - ro)] = xp[(int64_t)iperm[r] * nrhs + c];
-  }
-}
-
-inline int grid_for(int64_t items, int threads, int cap) {
-  int64_t g = (items + threads - 1) / threads;
-  if (g < 1) g = 1;
-  if (g > cap) g = cap;
-  return (int)g;
-}
-
 template <int WG, bool kOne>
 void set_lds_attr() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_thin_run<WG, kOne>),
@@ -595,34 +422,6 @@ void solve_kernels_init() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_thin_run<512, false, true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
-}
-
-hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
-                         hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  if (nrhs == 1)
-    hipLaunchKernelGGL(k_gather1, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, b, iperm, bp);
-  else
-    hipLaunchKernelGGL(k_gather, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, b, ldb, iperm, bp);
-  return hipGetLastError();
-}
-
-hipError_t launch_apply_t(int32_t n, int32_t nrhs, const int32_t *trp, const int32_t *tci, const double *tva,
-                          const double *t, double *bp, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_apply_t, dim3(grid_for((int64_t)n * nrhs, 256, 16384)), dim3(256), 0, s, n, nrhs, trp, tci, tva,
-                     t, bp);
-  return hipGetLastError();
-}
-
-hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
-                          hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  if (nrhs == 1)
-    hipLaunchKernelGGL(k_scatter1, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, xp, iperm, x);
-  else
-    hipLaunchKernelGGL(k_scatter, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, xp, iperm, x, ldx);
-  return hipGetLastError();
 }
 
 hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
@@ -662,47 +461,6 @@ hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, co
   return hipGetLastError();
 }
 
-hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
-                             const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                             const double *bp, double *xp, int *err, hipStream_t s) {
-  const int64_t rows = pe - pb;
-  if (rows <= 0) return hipSuccess;
-  if (nrhs == 1 && lanes_per_row > 1) {
-    const int64_t items = rows * lanes_per_row;
-    const int g = grid_for(items, threads, 65536);
-#define GRP(G)                                                                                                   \
-  hipLaunchKernelGGL((k_wide_level_group<G>), dim3(g), dim3(threads), 0, s, pb, pe, srp, sci, sva, sdg, bp, xp, \
-                     err);
-    switch (lanes_per_row) {
-      case 2: GRP(2) break;
-      case 4: GRP(4) break;
-      case 8: GRP(8) break;
-      case 16: GRP(16) break;
-      default: GRP(32) break;
-    }
-#undef GRP
-    return hipGetLastError();
-  }
-  const int64_t items = rows * nrhs;
-  const int g = grid_for(items, threads, 65536);
-  if (nrhs == 1)
-    hipLaunchKernelGGL((k_wide_level<true>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, bp, xp,
-                       err);
-  else
-    hipLaunchKernelGGL((k_wide_level<false>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, bp, xp,
-                       err);
-  return hipGetLastError();
-}
-
-hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,
-                           const double *b, int64_t ldb, const double *x, int64_t ldx, unsigned long long *out,
-                           hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, nrhs, rp, ci, va, b, ldb, x,
-                     ldx, out);
-  return hipGetLastError();
-}
-
 hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int2 *win,
                             int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s) {
   static bool attr = false;
@@ -719,22 +477,6 @@ hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, co
   else
     hipLaunchKernelGGL((k_batch_run<512, false>), dim3(grid), dim3(512), kWinBytes, s, nmat, order, mwin, win, nrhs,
                        a, q, err);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_gather(int64_t total, int32_t nrhs, const double *b, const int32_t *mat_of_row,
-                               const int64_t *row_off, const int32_t *iperm, double *bp, hipStream_t s) {
-  if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_gather, dim3(grid_for(total * nrhs, 256, 16384)), dim3(256), 0, s, total, nrhs, b,
-                     mat_of_row, row_off, iperm, bp);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_scatter(int64_t total, int32_t nrhs, const double *xp, const int32_t *mat_of_row,
-                                const int64_t *row_off, const int32_t *iperm, double *x, hipStream_t s) {
-  if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_scatter, dim3(grid_for(total * nrhs, 256, 16384)), dim3(256), 0, s, total, nrhs, xp,
-                     mat_of_row, row_off, iperm, x);
   return hipGetLastError();
 }
 

@@ -1,0 +1,184 @@
+// Vector kernels around the level chain: b (caller's column-major layout) to
+// the level-ordered, RHS-interleaved work vector and back, the b-transform of
+// the rewritten system (Sec. II.B), the residual check, and the batched
+// variants of the gather and scatter.
+#include "common.h"
+
+namespace {
+
+// b (column-major, original rows) -> bp (level order, RHS-interleaved). A tile
+// of 64 rows x up to 32 columns is staged in LDS so both sides are coalesced.
+__global__ void k_gather(int32_t n, int32_t nrhs, const double *__restrict__ b, int64_t ldb,
+                         const int32_t *__restrict__ iperm, double *bp) {
+  __shared__ double tile[64][33];
+  const int32_t r0 = blockIdx.x * 64;
+  for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
+    const int32_t nc = min(32, nrhs - c0);
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int c = idx / 64, rr = idx % 64;
+      if (r0 + rr < n) tile[rr][c] = b[(int64_t)(c0 + c) * ldb + r0 + rr];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int rr = idx / nc, c = idx % nc;
+      if (r0 + rr < n) bp[(int64_t)iperm[r0 + rr] * nrhs + c0 + c] = tile[rr][c];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_gather1(int32_t n, const double *__restrict__ b, const int32_t *__restrict__ iperm, double *bp) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    bp[iperm[r]] = b[r];
+}
+
+// The b-transform of the rewritten system (Sec. II.B) on the rows where T has
+// off-diagonals (positions tpos): b'(pos, c) = b(row, c) + sum over T's row, in
+// its order, of T(pos, k) b(perm[k], c), with row = perm[pos] and b the
+// caller's column-major right-hand sides (T's unit diagonal is implicit). Only
+// b is read, so the items are independent.
+__global__ void k_apply_t(int32_t nt, int32_t nrhs, const int32_t *__restrict__ tpos, const int32_t *__restrict__ perm,
+                          const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
+                          const double *__restrict__ tva, const double *__restrict__ b, int64_t ldb, double *bp) {
+  const int64_t total = (int64_t)nt * nrhs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t j = (int32_t)(i / nrhs);
+    const int32_t c = (int32_t)(i - (int64_t)j * nrhs);
+    const int32_t pos = tpos[j];
+    const double *bc = b + (int64_t)c * ldb;
+    double acc = bc[perm[pos]];
+    const int32_t qb = trp[pos], qe = trp[pos + 1];
+    for (int32_t q = qb; q < qe; ++q) acc += tva[q] * bc[perm[tci[q]]];
+    bp[(int64_t)pos * nrhs + c] = acc;
+  }
+}
+
+__global__ void k_scatter(int32_t n, int32_t nrhs, const double *__restrict__ xp, const int32_t *__restrict__ iperm,
+                          double *x, int64_t ldx) {
+  __shared__ double tile[64][33];
+  const int32_t r0 = blockIdx.x * 64;
+  for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
+    const int32_t nc = min(32, nrhs - c0);
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int rr = idx / nc, c = idx % nc;
+      if (r0 + rr < n) tile[rr][c] = xp[(int64_t)iperm[r0 + rr] * nrhs + c0 + c];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int c = idx / 64, rr = idx % 64;
+      if (r0 + rr < n) x[(int64_t)(c0 + c) * ldx + r0 + rr] = tile[rr][c];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_scatter1(int32_t n, const double *__restrict__ xp, const int32_t *__restrict__ iperm, double *x) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    x[r] = xp[iperm[r]];
+}
+
+// max_i |(L x - b)[i, c]| per column, original numbering; results as the bit
+// patterns of non-negative doubles (monotone as unsigned integers).
+__global__ void k_residual(int32_t n, int32_t nrhs, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ va, const double *__restrict__ b, int64_t ldb,
+                           const double *__restrict__ x, int64_t ldx, unsigned long long *out) {
+  for (int32_t c = 0; c < nrhs; ++c) {
+    double m = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+      double s = 0.0;
+      for (int32_t q = rp[r]; q < rp[r + 1]; ++q) s += va[q] * x[(int64_t)c * ldx + ci[q]];
+      const double d = fabs(s - b[(int64_t)c * ldb + r]);
+      m = (d > m || d != d) ? d : m;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(m, off, 64);
+      m = (o > m || o != o) ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out + c, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// Batched right-hand sides: matrix m's b and x are n_m x nrhs column-major at
+// offset nrhs * row_off[m], ld = n_m. Items run over (global row, column) with
+// the row fastest, so each column of each matrix is read/written contiguously.
+__global__ void k_batch_gather(int64_t total, int32_t nrhs, const double *__restrict__ b,
+                               const int32_t *__restrict__ mat_of_row, const int64_t *__restrict__ row_off,
+                               const int32_t *__restrict__ iperm, double *bp) {
+  const int64_t items = total * nrhs;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = it / total, r = it - c * total;
+    const int32_t m = mat_of_row[r];
+    const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
+    bp[(int64_t)iperm[r] * nrhs + c] = b[nrhs * ro + c * nm + (r - ro)];
+  }
+}
+
+__global__ void k_batch_scatter(int64_t total, int32_t nrhs, const double *__restrict__ xp,
+                                const int32_t *__restrict__ mat_of_row, const int64_t *__restrict__ row_off,
+                                const int32_t *__restrict__ iperm, double *x) {
+  const int64_t items = total * nrhs;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = it / total, r = it - c * total;
+    const int32_t m = mat_of_row[r];
+    const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
+    x[nrhs * ro + c * nm + (r - ro)] = xp[(int64_t)iperm[r] * nrhs + c];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
+                         hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_gather1, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, b, iperm, bp);
+  else
+    hipLaunchKernelGGL(k_gather, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, b, ldb, iperm, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_t(int32_t nt, int32_t nrhs, const int32_t *tpos, const int32_t *perm, const int32_t *trp,
+                          const int32_t *tci, const double *tva, const double *b, int64_t ldb, double *bp,
+                          hipStream_t s) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_apply_t, dim3(grid_for((int64_t)nt * nrhs, 256, 16384)), dim3(256), 0, s, nt, nrhs, tpos, perm,
+                     trp, tci, tva, b, ldb, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
+                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_scatter1, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, xp, iperm, x);
+  else
+    hipLaunchKernelGGL(k_scatter, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, xp, iperm, x, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,
+                           const double *b, int64_t ldb, const double *x, int64_t ldx, unsigned long long *out,
+                           hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, nrhs, rp, ci, va, b, ldb, x,
+                     ldx, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gather(int64_t total, int32_t nrhs, const double *b, const int32_t *mat_of_row,
+                               const int64_t *row_off, const int32_t *iperm, double *bp, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_gather, dim3(grid_for(total * nrhs, 256, 16384)), dim3(256), 0, s, total, nrhs, b,
+                     mat_of_row, row_off, iperm, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_scatter(int64_t total, int32_t nrhs, const double *xp, const int32_t *mat_of_row,
+                                const int64_t *row_off, const int32_t *iperm, double *x, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_scatter, dim3(grid_for(total * nrhs, 256, 16384)), dim3(256), 0, s, total, nrhs, xp,
+                     mat_of_row, row_off, iperm, x);
+  return hipGetLastError();
+}

@@ -1,0 +1,211 @@
+// Wide-level solve kernels: the rows of one level of the level-ordered L (or
+// L') are independent (Sec. II.A), so a wide level is spread over the whole
+// device. Either one launch per level (kernel boundaries order the levels), or
+// one persistent launch for a run of consecutive wide levels with a
+// device-wide barrier between levels.
+#include "common.h"
+
+namespace {
+
+// x(pos, c) = (b'(pos, c) - sum_k L(pos,k) x(k,c)) / L(pos,pos). Columns
+// < lds_base come from global memory, columns >= lds_base from the LDS window.
+template <bool kUseLds, bool kOne>
+__device__ __forceinline__ double row_solve(int32_t pos, int32_t c, int32_t nrhs, const int32_t *__restrict__ srp,
+                                            const int32_t *__restrict__ sci, const double *__restrict__ sva,
+                                            const double *__restrict__ sdg, const double *__restrict__ bp,
+                                            const double *xp, const double *lds, int32_t lds_base) {
+  const int64_t nr = kOne ? 1 : nrhs;
+  double acc = bp[(int64_t)pos * nr + c];
+  const int32_t b = srp[pos], e = srp[pos + 1];
+  for (int32_t q = b; q < e; ++q) {
+    const int32_t k = sci[q];
+    double xv;
+    if (kUseLds && k >= lds_base)
+      xv = lds[(int64_t)(k - lds_base) * nr + c];
+    else
+      xv = xp[(int64_t)k * nr + c];
+    acc -= sva[q] * xv;
+  }
+  return acc / sdg[pos];
+}
+
+// One wide level, one item (row, rhs) per thread.
+template <bool kOne>
+__global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t *__restrict__ srp,
+                             const int32_t *__restrict__ sci, const double *__restrict__ sva,
+                             const double *__restrict__ sdg, const double *__restrict__ bp, double *xp, int *err) {
+  const int32_t nr = kOne ? 1 : nrhs;
+  const int64_t items = (int64_t)(pe - pb) * nr;
+  int bits = 0;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t pos = kOne ? pb + (int32_t)it : pb + (int32_t)(it / nr);
+    const int32_t c = kOne ? 0 : (int32_t)(it - (int64_t)(pos - pb) * nr);
+    const double xv = row_solve<false, kOne>(pos, c, nr, srp, sci, sva, sdg, bp, xp, nullptr, 0);
+    if (!isfinite(xv)) bits |= EB_NONFINITE;
+    xp[(int64_t)pos * nr + c] = xv;
+  }
+  if (bits) atomicOr(err, bits);
+}
+
+// One wide level, single RHS, G lanes per row: lanes split the row's products
+// and combine them with a fixed butterfly, so the result is deterministic.
+template <int G>
+__global__ void k_wide_level_group(int32_t pb, int32_t pe, const int32_t *__restrict__ srp,
+                                   const int32_t *__restrict__ sci, const double *__restrict__ sva,
+                                   const double *__restrict__ sdg, const double *__restrict__ bp, double *xp,
+                                   int *err) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x & (G - 1);
+  int bits = 0;
+  const int64_t rows = pe - pb;
+  for (int64_t rr = gid / G; rr < (rows + 0); rr += ((int64_t)gridDim.x * blockDim.x) / G) {
+    const int32_t pos = pb + (int32_t)rr;
+    double acc = 0.0;
+    const int32_t b = srp[pos], e = srp[pos + 1];
+    for (int32_t q = b + sub; q < e; q += G) acc -= sva[q] * xp[sci[q]];
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+    if (sub == 0) {
+      const double xv = (bp[pos] + acc) / sdg[pos];
+      if (!isfinite(xv)) bits |= EB_NONFINITE;
+      xp[pos] = xv;
+    }
+  }
+  if (bits) atomicOr(err, bits);
+}
+
+// Consecutive wide levels [l0, l1) in one launch of gridDim.x workgroups,
+// which must all be resident at once (the host sizes the grid from the
+// occupancy): every level's items are spread over all threads, and levels are
+// separated by a device-wide barrier (workgroup barrier, then one thread per
+// workgroup: device-scope release fence, arrival on bar[0], wait for all
+// arrivals, device-scope acquire fence). Waits are bounded by the wall clock:
+// on expiry the launch stops and reports a time-out instead of hanging. The
+// last workgroup to leave resets bar[0] and bar[1] (departures), so the launch
+// can be replayed (graph capture) with no host-side reset.
+template <bool kOne>
+__global__ void k_wide_run(int32_t l0, int32_t l1, const int32_t *__restrict__ level_ptr, int32_t nrhs,
+                           const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
+                           const double *__restrict__ sva, const double *__restrict__ sdg,
+                           const double *__restrict__ bp, double *xp, unsigned *bar, int *err,
+                           unsigned long long tlimit) {
+  __shared__ int s_abort;
+  const int32_t nr = kOne ? 1 : nrhs;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.x == 0) s_abort = 0;
+  const unsigned long long t0 = wall_clock64();
+  int bits = 0;
+  for (int32_t l = l0; l < l1; ++l) {
+    const int32_t pb = level_ptr[l], pe = level_ptr[l + 1];
+    const int64_t items = (int64_t)(pe - pb) * nr;
+    for (int64_t it = gid; it < items; it += nthreads) {
+      const int32_t pos = kOne ? pb + (int32_t)it : pb + (int32_t)(it / nr);
+      const int32_t c = kOne ? 0 : (int32_t)(it - (int64_t)(pos - pb) * nr);
+      const double xv = row_solve<false, kOne>(pos, c, nr, srp, sci, sva, sdg, bp, xp, nullptr, 0);
+      if (!isfinite(xv)) bits |= EB_NONFINITE;
+      xp[(int64_t)pos * nr + c] = xv;
+    }
+    if (l + 1 == l1) break;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's x, visible device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned target = (unsigned)(l - l0 + 1) * gridDim.x;
+      atomicAdd(bar, 1u);
+      unsigned spins = 0;
+      while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 255u) == 0u && wall_clock64() - t0 > tlimit) {
+          s_abort = 1;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other workgroups' x
+    if (s_abort) {
+      bits |= EB_TIMEOUT;
+      break;
+    }
+  }
+  if (bits) atomicOr(err, bits);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(bar + 1, 1u) == gridDim.x - 1) {
+      atomicExch(bar, 0u);
+      atomicExch(bar + 1, 0u);
+      __threadfence();
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
+                             const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
+                             const double *bp, double *xp, int *err, hipStream_t s) {
+  const int64_t rows = pe - pb;
+  if (rows <= 0) return hipSuccess;
+  if (nrhs == 1 && lanes_per_row > 1) {
+    const int64_t items = rows * lanes_per_row;
+    const int g = grid_for(items, threads, 65536);
+#define GRP(G)                                                                                                   \
+  hipLaunchKernelGGL((k_wide_level_group<G>), dim3(g), dim3(threads), 0, s, pb, pe, srp, sci, sva, sdg, bp, xp, \
+                     err);
+    switch (lanes_per_row) {
+      case 2: GRP(2) break;
+      case 4: GRP(4) break;
+      case 8: GRP(8) break;
+      case 16: GRP(16) break;
+      default: GRP(32) break;
+    }
+#undef GRP
+    return hipGetLastError();
+  }
+  const int64_t items = rows * nrhs;
+  const int g = grid_for(items, threads, 65536);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_wide_level<true>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, bp, xp,
+                       err);
+  else
+    hipLaunchKernelGGL((k_wide_level<false>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, bp, xp,
+                       err);
+  return hipGetLastError();
+}
+
+int wide_run_resident_blocks(int threads) {
+  static int cached[17] = {0};
+  const int key = threads / 64;
+  if (key < 1 || key > 16) return 0;
+  if (!cached[key]) {
+    int dev = 0, cus = 0, occ = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(&k_wide_run<false>),
+                                                       threads, 0);
+    int occ1 = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, reinterpret_cast<const void *>(&k_wide_run<true>),
+                                                       threads, 0);
+    cached[key] = cus * std::max(0, std::min(occ, occ1));
+  }
+  return cached[key];
+}
+
+hipError_t launch_wide_run(int grid, int threads, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
+                           const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
+                           const double *bp, double *xp, unsigned *bar, int *err, hipStream_t s) {
+  if (l1 <= l0) return hipSuccess;
+  const int cap = wide_run_resident_blocks(threads);
+  if (cap < 1) return hipErrorInvalidConfiguration;
+  grid = std::max(1, std::min(grid, cap));  // every workgroup must be resident for the barrier
+  const unsigned long long limit = 100000000ull * 10;  // 10 s of the 100 MHz wall clock
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_wide_run<true>), dim3(grid), dim3(threads), 0, s, l0, l1, level_ptr, nrhs, srp, sci, sva,
+                       sdg, bp, xp, bar, err, limit);
+  else
+    hipLaunchKernelGGL((k_wide_run<false>), dim3(grid), dim3(threads), 0, s, l0, l1, level_ptr, nrhs, srp, sci, sva,
+                       sdg, bp, xp, bar, err, limit);
+  return hipGetLastError();
+}

@@ -16,8 +16,14 @@ backward and the Adam step are the library's kernels. Features are
 standardised with the training set's mean and standard deviation, which are
 stored in the checkpoint with the weights.
 
-Evaluation. On held-out seeds, both the naive and the learned rewrite are
-autotuned and timed; every solve is checked against the CPU oracle.
+Calibration. The decision threshold on the network's probability is chosen
+on separate validation matrices (seeds 1900..): the one with the best
+geometric-mean solve-time ratio against the naive rewrite (ties: the higher
+threshold, which rewrites less).
+
+Evaluation. On held-out seeds, plain, naive and learned are autotuned and
+timed; the rewritten solutions are checked against the plain solution
+(relative error <= 1e-10) and the plain one by its residual.
 """
 from __future__ import annotations
 
@@ -138,6 +144,30 @@ def time_variant(h, which, b, reps=20):
     return (time.perf_counter() - t) / reps, x
 
 
+def calibrate(params, norm, seeds, thresholds=(0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.99)):
+    """Threshold with the best geometric-mean time ratio naive / learned on
+    the given matrices (each variant autotuned)."""
+    ratios = {t: [] for t in thresholds}
+    for s in seeds:
+        m = gen.policy_training_matrix(s)
+        b = torch.from_numpy(gen.rhs(m, 1)[0]).to("cuda")
+        h = sp.Handle()
+        h.analyze(*to_dev(m))
+        h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0)
+        t_naive, _ = time_variant(h, sp.REWRITTEN, b)
+        for t in thresholds:
+            pol = Policy(params, norm, t)
+            h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0, pol.mask_for(h))
+            t_l, _ = time_variant(h, sp.REWRITTEN, b)
+            ratios[t].append(t_naive / t_l)
+        h.close()
+    score = {t: math.exp(np.mean(np.log(r))) for t, r in ratios.items()}
+    best = max(sorted(thresholds, reverse=True), key=lambda t: score[t])
+    log(f"[calibrate] geomean naive/learned by threshold: {json.dumps({str(k): round(v, 4) for k, v in score.items()})}"
+        f" -> {best}")
+    return best, score
+
+
 def evaluate(policy: Policy, seeds, check=True):
     """Autotuned solve time of plain, naive and learned on each seed. The
     rewritten solutions are checked against the plain solution (relative error
@@ -187,6 +217,7 @@ def main():
     ap.add_argument("--first-seed", type=int, default=1000)
     ap.add_argument("--heldout", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--calib", type=int, default=10, help="validation matrices for the threshold (seeds 1900..)")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     seeds = list(range(args.first_seed, args.first_seed + args.matrices))
@@ -211,10 +242,15 @@ def main():
     acc_tr = accuracy(params, norm, F[~val], Y[~val])
     acc_va = accuracy(params, norm, F[val], Y[val])
     log(f"[train] train {acc_tr} val {acc_va}")
+    thr, score = (0.5, {})
+    if args.calib > 0:
+        thr, score = calibrate(params, norm, list(range(1900, 1900 + args.calib)))
     meta = {"train_seeds": [seeds[0], seeds[-1]], "levels": int(F.shape[0]), "positive_rate": float(Y.mean()),
             "epochs": args.epochs, "loss_history": hist, "train_metrics": acc_tr, "val_metrics": acc_va,
-            "label": "1 = emptied by the naive rewrite and its rows cost less time in L' than the level in L"}
-    pol = Policy(params, norm, 0.5, meta)
+            "label": "1 = emptied by the naive rewrite and its rows cost less time in L' than the level in L",
+            "threshold": thr, "calibration_seeds": [1900, 1900 + args.calib - 1] if args.calib > 0 else [],
+            "calibration_geomean_naive_over_learned": {str(k): v for k, v in score.items()}}
+    pol = Policy(params, norm, thr, meta)
     pol.save(os.path.join(args.out, "policy_ckpt.npz"))
     if args.heldout > 0:
         res, g, gp = evaluate(pol, list(range(2000, 2000 + args.heldout)))

@@ -62,7 +62,9 @@ def test_level_stats_exact(handles, name):
 
 
 SCHEDS = [dict(mode=0), dict(mode=1), dict(mode=2), dict(mode=0, thin_rows=64, wg_threads=256),
-          dict(mode=1, lanes_per_row=4), dict(mode=0, thin_rows=300, wg_threads=1024, lanes_per_row=8)]
+          dict(mode=1, lanes_per_row=4), dict(mode=0, thin_rows=300, wg_threads=1024, lanes_per_row=8),
+          dict(mode=1, wide_grid=256), dict(mode=0, thin_rows=64, wide_threads=512, wide_grid=1024),
+          dict(mode=1, wide_threads=64, wide_grid=3)]
 
 
 @pytest.mark.parametrize("name", [n for n, _ in MATS])
@@ -196,6 +198,30 @@ def test_graph_replays(handles):
             del b2
 
 
+@pytest.mark.parametrize("sched", [dict(mode=1, wide_grid=256), dict(mode=0, thin_rows=16, wide_grid=64)])
+def test_graph_replays_persistent_wide(handles, sched):
+    # the barrier counters of a persistent wide run reset themselves at the end
+    # of every launch, so graph replays and eager solves can alternate
+    m, h, _ = handles["cfg4_small"]
+    h.set_schedule(**sched)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = to_dev(gen.rhs(m, 3))
+        x = torch.zeros_like(b)
+        gid = h.graph_create(b, x)
+        xr = oracle.solve(m, b.cpu().numpy())
+        for rep in range(3):
+            x.zero_()
+            h.graph_launch(gid)
+            torch.cuda.synchronize()
+            assert oracle.relerr(x.cpu().numpy(), xr) <= TOL
+            xe = h.solve(b)
+            torch.cuda.synchronize()
+            assert torch.equal(xe, x)
+    h.check()
+    h.set_schedule()
+
+
 def test_autotune_keeps_parity(handles):
     m, h, _ = handles["cfg2_small"]
     ms = h.autotune(nrhs=1)
@@ -211,8 +237,9 @@ def test_set_schedule_replaces_tuned(handles):
     h.autotune(nrhs=2)
     tuned = h.get_schedule(nrhs=2)
     assert tuned["mode"] in (0, 1, 2)
-    assert h.get_schedule(nrhs=1) == dict(mode=0, thin_rows=4096, wg_threads=512, wide_threads=256, lanes_per_row=1)
-    want = dict(mode=0, thin_rows=64, wg_threads=256, wide_threads=128, lanes_per_row=1)
+    assert h.get_schedule(nrhs=1) == dict(mode=0, thin_rows=4096, wg_threads=512, wide_threads=256, lanes_per_row=1,
+                                          wide_grid=0)
+    want = dict(mode=0, thin_rows=64, wg_threads=256, wide_threads=128, lanes_per_row=1, wide_grid=0)
     h.set_schedule(**want)
     assert h.get_schedule(nrhs=2) == want  # an explicit schedule replaces the tuned one
     h.prepare(nrhs=2)

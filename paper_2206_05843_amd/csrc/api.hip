@@ -83,34 +83,50 @@ static int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
   return thin_window_bytes(rows, ents, nl, nrhs);
 }
 
+// A level alone in a window reads all its dependencies from earlier windows,
+// so it needs no overflow records.
 bool level_fits_window(const Plan &P, int32_t l, int32_t nrhs) {
   const int64_t rows = P.h_level_ptr[l + 1] - P.h_level_ptr[l];
-  return win_bytes(rows, P.h_lv_ovf[l], 1, nrhs) <= thin_win_bytes();
+  return win_bytes(rows, 0, 1, nrhs) <= thin_win_bytes();
+}
+
+// Upper bound on the overflow records of level l's rows in a window that
+// starts at level ws: dependencies (beyond each row's two at the highest
+// levels) at most l - ws levels up, counted by whole distance buckets.
+static int64_t extras_in(const Plan &P, int32_t l, int32_t ws) {
+  const int32_t d = l - ws;
+  const int32_t *hx = P.h_xh.data() + (size_t)l * kExtraBuckets;
+  int64_t e = 0;
+  for (int b = 0; b < kExtraBuckets && kExtraLo[b] <= d; ++b) e += hx[b];
+  return e;
 }
 
 // Cut levels [l0, l1) into LDS windows; flag windows whose levels fit one wave
-// (bit 0) or one item per thread of a workgroup of wg threads (bit 1). Appends
-// the windows and a terminator holding l1; returns the number of windows.
-int32_t cut_windows(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs, int32_t wg, std::vector<int2> &out) {
+// (bit 0) or one item per thread of a workgroup of wg threads (bit 1), and
+// give each window its bound on overflow records. Appends the windows and a
+// terminator holding l1; returns the number of windows.
+int32_t cut_windows(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs, int32_t wg, std::vector<int4> &out) {
   const int64_t cap = thin_win_bytes();
   const size_t first = out.size();
   int32_t ws = l0;
   int64_t rows = 0, ents = 0, maxit = 0;
   auto flags = [&]() { return (maxit <= 64 ? 1 : 0) | (maxit <= wg ? 2 : 0); };
   for (int32_t l = l0; l < l1; ++l) {
-    const int64_t rl = P.h_level_ptr[l + 1] - P.h_level_ptr[l], el = P.h_lv_ovf[l];
+    const int64_t rl = P.h_level_ptr[l + 1] - P.h_level_ptr[l];
+    int64_t el = extras_in(P, l, ws);
     if (l > ws && win_bytes(rows + rl, ents + el, l - ws + 1, nrhs) > cap) {
-      out.push_back(int2{ws, flags()});
+      out.push_back(int4{ws, flags(), (int32_t)ents, 0});
       ws = l;
       rows = ents = maxit = 0;
+      el = 0;
     }
     rows += rl;
     ents += el;
     maxit = std::max<int64_t>(maxit, rl * nrhs);
   }
-  out.push_back(int2{ws, flags()});
+  out.push_back(int4{ws, flags(), (int32_t)ents, 0});
   const int32_t nw = (int32_t)(out.size() - first);
-  out.push_back(int2{l1, 0});
+  out.push_back(int4{l1, 0, 0, 0});
   return nw;
 }
 
@@ -120,11 +136,10 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
   const int64_t cap = thin_win_bytes();
   const int64_t thr = sc.thin_rows;
   auto rows_of = [&](int32_t l) -> int64_t { return P.h_level_ptr[l + 1] - P.h_level_ptr[l]; };
-  auto offd_of = [&](int32_t l) -> int64_t { return P.h_lv_ovf[l]; };  // overflow dependency records
   for (int32_t l = 0; l < P.nlev; ++l) {
     const int64_t rows = rows_of(l);
     bool thin = sc.mode == 2 || (sc.mode == 0 && rows <= thr);
-    if (win_bytes(rows, offd_of(l), 1, nrhs) > cap) thin = false;  // must fit one window alone
+    if (win_bytes(rows, 0, 1, nrhs) > cap) thin = false;  // must fit one window alone
     // consecutive thin levels share a run; so do consecutive wide levels with a persistent launch
     if (!P.runs.empty() && P.runs.back().thin == thin && P.runs.back().l1 == l && (thin || sc.wide_grid > 0))
       P.runs.back().l1 = l + 1;
@@ -138,7 +153,7 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
   }
   if (!P.h_win.empty()) {
     if (P.win.n < P.h_win.size()) HIPCHK(h, P.win.alloc(P.h_win.size()));
-    HIPCHK(h, hipMemcpy(P.win.p, P.h_win.data(), sizeof(int2) * P.h_win.size(), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(P.win.p, P.h_win.data(), sizeof(int4) * P.h_win.size(), hipMemcpyHostToDevice));
   }
   P.runs_nrhs = nrhs;
   P.runs_sched = sc;
@@ -226,12 +241,6 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   HIPCHK(h, launch_fill_ell(n, P.srp.p, P.sci.p, P.sva.p, P.ell_c.p, P.ell_v.p, s));
   HIPCHK(h, P.wbar.alloc(2));
   HIPCHK(h, hipMemsetAsync(P.wbar.p, 0, 2 * sizeof(unsigned), s));
-  HIPCHK(h, P.ovp.alloc((size_t)n + 1));
-  HIPCHK(h, launch_count_ovf(P.srp.p, n, cnt.p, s));
-  HIPCHK(h, launch_scan_i64(cnt.p, ex.p, n, h->scan_tmp.p, s));
-  HIPCHK(h, launch_ptr_from_scan(ex.p, cnt.p, n, P.ovp.p, aux + 1, s));
-  std::vector<int32_t> hovp((size_t)n + 1);
-  HIPCHK(h, hipMemcpyAsync(hovp.data(), P.ovp.p, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
   if (trp) {
     P.has_t = true;
     HIPCHK(h, P.trp.alloc((size_t)n + 1));
@@ -265,9 +274,7 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   HIPCHK(h, hipMemcpyAsync(haux, aux, sizeof(haux), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   if (haux[1]) return set_err(h, status_from_bits(haux[1]), "plan construction failed (bits 0x%x)", haux[1]);
-  P.h_lv_ovf.resize((size_t)nlev);
-  for (int32_t l = 0; l < nlev; ++l)
-    P.h_lv_ovf[(size_t)l] = hovp[(size_t)P.h_level_ptr[l + 1]] - hovp[(size_t)P.h_level_ptr[l]];
+  STCHK(build_extra_hist(h, P, s));
   if (P.has_t) {
     P.h_lv_tnnz.resize((size_t)nlev);
     for (int32_t l = 0; l < nlev; ++l)
@@ -317,7 +324,22 @@ static void prof_end(sptrsv_ctx *h, int slot, hipStream_t s) {
 }
 
 ThinArgs thin_args(const Plan &P) {
-  return ThinArgs{P.level_ptr.p, P.srp.p, P.sci.p, P.ovp.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, P.bp.p, P.xp.p};
+  return ThinArgs{P.level_ptr.p, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, P.bp.p, P.xp.p};
+}
+
+// The level-distance histogram of the dependencies that need overflow records
+// (host copy, for cutting LDS windows).
+sptrsv_status_t build_extra_hist(sptrsv_ctx *h, Plan &P, hipStream_t s) {
+  P.h_xh.assign((size_t)P.nlev * kExtraBuckets, 0);
+  if (P.n == 0 || P.nlev == 0) return SPTRSV_OK;
+  DArr<int32_t> lop, hist;
+  HIPCHK(h, lop.alloc(P.n));
+  HIPCHK(h, hist.alloc(P.h_xh.size()));
+  HIPCHK(h, hipMemsetAsync(hist.p, 0, sizeof(int32_t) * P.h_xh.size(), s));
+  HIPCHK(h, launch_extra_hist(P.n, P.level_ptr.p, P.nlev, P.srp.p, P.sci.p, lop.p, hist.p, s));
+  HIPCHK(h, hipMemcpyAsync(P.h_xh.data(), hist.p, sizeof(int32_t) * P.h_xh.size(), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return SPTRSV_OK;
 }
 
 // b (caller's layout) -> bp (level order, interleaved); for the rewritten

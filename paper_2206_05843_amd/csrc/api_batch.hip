@@ -81,7 +81,7 @@ sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs) {
   }
   h->b_h_mwin[(size_t)h->b_nmat] = (int32_t)P.h_win.size();
   HIPCHK(h, P.win.alloc(std::max<size_t>(P.h_win.size(), 1)));
-  HIPCHK(h, hipMemcpy(P.win.p, P.h_win.data(), sizeof(int2) * P.h_win.size(), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(P.win.p, P.h_win.data(), sizeof(int4) * P.h_win.size(), hipMemcpyHostToDevice));
   HIPCHK(h, h->b_mwin.alloc((size_t)h->b_nmat + 1));
   HIPCHK(h, hipMemcpy(h->b_mwin.p, h->b_h_mwin.data(), sizeof(int32_t) * ((size_t)h->b_nmat + 1),
                       hipMemcpyHostToDevice));
@@ -228,10 +228,6 @@ sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t nmat, const int3
   HIPCHK(h, P.ell_c.alloc(n));
   HIPCHK(h, P.ell_v.alloc((size_t)2 * n));
   HIPCHK(h, launch_fill_ell(n, P.srp.p, P.sci.p, P.sva.p, P.ell_c.p, P.ell_v.p, s));
-  HIPCHK(h, P.ovp.alloc((size_t)n + 1));
-  HIPCHK(h, launch_count_ovf(P.srp.p, n, cnt.p, s));
-  HIPCHK(h, launch_scan_i64(cnt.p, ex.p, n, h->scan_tmp.p, s));
-  HIPCHK(h, launch_ptr_from_scan(ex.p, cnt.p, n, P.ovp.p, aux + 1, s));
   HIPCHK(h, P.lv_rows.alloc(nlev));
   HIPCHK(h, P.lv_nnz.alloc(nlev));
   HIPCHK(h, P.lv_cost.alloc(nlev));
@@ -242,14 +238,10 @@ sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t nmat, const int3
                            hipMemcpyDeviceToHost, s));
   P.h_lv_nnz.resize((size_t)nlev);
   HIPCHK(h, hipMemcpyAsync(P.h_lv_nnz.data(), P.lv_nnz.p, sizeof(int64_t) * (size_t)nlev, hipMemcpyDeviceToHost, s));
-  std::vector<int32_t> hovp((size_t)n + 1);
-  HIPCHK(h, hipMemcpyAsync(hovp.data(), P.ovp.p, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipMemcpyAsync(&bits, aux + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
   if (bits) return set_err(h, status_from_bits(bits), "batch: plan construction failed (bits 0x%x)", bits);
-  P.h_lv_ovf.resize((size_t)nlev);
-  for (int32_t l = 0; l < nlev; ++l)
-    P.h_lv_ovf[(size_t)l] = hovp[(size_t)P.h_level_ptr[l + 1]] - hovp[(size_t)P.h_level_ptr[l]];
+  STCHK(build_extra_hist(h, P, s));
   // longest-processing-time order: deepest matrices first, then largest
   std::vector<int32_t> order((size_t)nmat);
   std::iota(order.begin(), order.end(), 0);

@@ -92,17 +92,17 @@ struct Plan {
   DArr<int64_t> lv_rows, lv_nnz, lv_cost;
   std::vector<int64_t> h_lv_nnz;       // per level: nnz incl. diagonal (host copy)
   std::vector<int64_t> h_lv_tnnz;      // per level: off-diagonal nnz of T
-  DArr<int32_t> ovp;                   // [n+1] prefix of max(0, off-diagonals - 2) per position
   DArr<int4> ell_c;                    // [n] first four off-diagonal columns per position (-1: none)
   DArr<double2> ell_v;                 // [2n] their values
-  std::vector<int64_t> h_lv_ovf;       // per level: sum of max(0, off-diagonals - 2)
+  std::vector<int32_t> h_xh;           // [nlev * kExtraBuckets] level-distance histogram of dependencies
+                                       // that need overflow records when inside an LDS window
   int64_t total_cost = 0;
   double avg_cost = 0.0;
   sptrsv_schedule_t sched{};           // knobs in force (mode 0 = automatic)
   std::map<int32_t, sptrsv_schedule_t> tuned;  // per nrhs
   std::vector<Run> runs;
-  std::vector<int2> h_win;             // LDS windows of all thin runs
-  DArr<int2> win;
+  std::vector<int4> h_win;             // LDS windows of all thin runs {first level, flags, overflow bound, 0}
+  DArr<int4> win;
   int32_t runs_nrhs = -1;
   sptrsv_schedule_t runs_sched{};
   DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
@@ -216,6 +216,11 @@ __host__ __device__ inline int64_t thin_window_bytes(int64_t rows, int64_t ovf, 
   return rows * (8 * (int64_t)nrhs + 24) + 8 * (int64_t)nrhs + ovf * 16 + 4 * (nl + 1);
 }
 
+// Level-distance buckets of the overflow-record histogram: lower bounds of
+// the distances 1, 2, 3, 4, 5-8, 9-16, 17-32, 33-64, 65-256, >256.
+constexpr int kExtraBuckets = 10;
+constexpr int32_t kExtraLo[kExtraBuckets] = {1, 2, 3, 4, 5, 9, 17, 33, 65, 257};
+
 // Workgroups for a grid-stride launch over `items` items, at most `cap`.
 inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
   int64_t g = (items + threads - 1) / threads;
@@ -226,7 +231,7 @@ inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
 
 // Device arrays a thin run reads (the level-ordered plan and work vectors).
 struct ThinArgs {
-  const int32_t *level_ptr, *srp, *sci, *ovp;
+  const int32_t *level_ptr, *srp, *sci;
   const double *sva, *sdg;
   const int4 *ell_c;
   const double2 *ell_v;
@@ -243,8 +248,9 @@ hipError_t launch_apply_t(int32_t nt, int32_t nrhs, const int32_t *tpos, const i
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
 int thin_win_bytes();
-hipError_t launch_count_ovf(const int32_t *srp, int32_t n, long long *cnt, hipStream_t s);
-hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
+hipError_t launch_extra_hist(int32_t n, const int32_t *level_ptr, int32_t nlev, const int32_t *srp,
+                             const int32_t *sci, int32_t *lop, int32_t *hist, hipStream_t s);
+hipError_t launch_thin_run(int wg, const int4 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
                            hipStream_t s, float *times = nullptr, float ns_per_tick = 0.f);
 hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, const double *sva, int4 *ell_c,
                            double2 *ell_v, hipStream_t s);
@@ -300,7 +306,7 @@ hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const
                             int32_t *redo, int32_t *nredo, char *big, int32_t bigC, int32_t bigH, int32_t big_blocks,
                             int *err, hipStream_t s);
 // Batched launchers (k_solve.hip) -------------------------------------------------
-hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int2 *win,
+hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int4 *win,
                             int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s);
 hipError_t launch_batch_gather(int64_t total, int32_t nrhs, const double *b, const int32_t *mat_of_row,
                                const int64_t *row_off, const int32_t *iperm, double *bp, hipStream_t s);
@@ -309,7 +315,8 @@ hipError_t launch_batch_scatter(int64_t total, int32_t nrhs, const double *xp, c
 int batch_resident_blocks();
 // Schedule helpers (api.hip) -----------------------------------------------------
 bool level_fits_window(const Plan &P, int32_t l, int32_t nrhs);
-int32_t cut_windows(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs, int32_t wg, std::vector<int2> &out);
+int32_t cut_windows(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs, int32_t wg, std::vector<int4> &out);
+sptrsv_status_t build_extra_hist(sptrsv_ctx *h, Plan &P, hipStream_t s);
 sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc);
 sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs);
 

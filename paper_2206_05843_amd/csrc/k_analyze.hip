@@ -454,17 +454,62 @@ hipError_t launch_level_stats(int32_t nlev, const int32_t *level_ptr, const int3
 }
 
 namespace {
-// Dependencies beyond the first two of each row (the solve keeps two per row
-// in a fixed record and lists the rest).
-__global__ void k_count_ovf(const int32_t *__restrict__ srp, int32_t n, long long *cnt) {
+// Level of every position of the level-ordered numbering (last l with
+// level_ptr[l] <= p).
+__global__ void k_level_of_pos(int32_t n, const int32_t *__restrict__ level_ptr, int32_t nlev, int32_t *lop) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t k = srp[p + 1] - srp[p] - 2;
-    cnt[p] = k > 0 ? k : 0;
+    int32_t lo = 0, hi = nlev - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (level_ptr[mid] <= (int32_t)p) lo = mid; else hi = mid - 1;
+    }
+    lop[p] = lo;
+  }
+}
+
+// Per level, a histogram of the level distance l - level(k) over each row's
+// dependencies k except the two at the highest levels (a row keeps two
+// in-window dependencies inline; the others need overflow records). Distance
+// buckets: 1, 2, 3, 4, 5-8, 9-16, 17-32, 33-64, 65-256, >256.
+__global__ void k_extra_hist(int32_t n, const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
+                             const int32_t *__restrict__ lop, int32_t *hist) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t qb = srp[p], qe = srp[p + 1];
+    if (qe - qb <= 2) continue;
+    const int32_t l = lop[p];
+    int32_t m1 = -1, m2 = -1;  // the two highest dependency levels (with multiplicity)
+    for (int32_t q = qb; q < qe; ++q) {
+      const int32_t a = lop[sci[q]];
+      if (a > m1) {
+        m2 = m1;
+        m1 = a;
+      } else if (a > m2) {
+        m2 = a;
+      }
+    }
+    bool skip1 = false, skip2 = false;
+    for (int32_t q = qb; q < qe; ++q) {
+      const int32_t a = lop[sci[q]];
+      if (!skip1 && a == m1) {
+        skip1 = true;
+        continue;
+      }
+      if (!skip2 && a == m2) {
+        skip2 = true;
+        continue;
+      }
+      const int32_t d = l - a;
+      const int32_t b = d <= 4 ? d - 1 : d <= 8 ? 4 : d <= 16 ? 5 : d <= 32 ? 6 : d <= 64 ? 7 : d <= 256 ? 8 : 9;
+      atomicAdd(hist + (int64_t)l * kExtraBuckets + b, 1);
+    }
   }
 }
 }  // namespace
 
-hipError_t launch_count_ovf(const int32_t *srp, int32_t n, long long *cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_count_ovf, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, srp, n, cnt);
+hipError_t launch_extra_hist(int32_t n, const int32_t *level_ptr, int32_t nlev, const int32_t *srp,
+                             const int32_t *sci, int32_t *lop, int32_t *hist, hipStream_t s) {
+  if (n == 0 || nlev == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_level_of_pos, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, n, level_ptr, nlev, lop);
+  hipLaunchKernelGGL(k_extra_hist, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, n, srp, sci, lop, hist);
   return hipGetLastError();
 }

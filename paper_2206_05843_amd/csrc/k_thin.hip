@@ -19,7 +19,15 @@
 
 namespace {
 
-constexpr int kWinBytes = 150 * 1024;  // LDS of one thin-run window
+constexpr int kWinBytes = 150 * 1024;  // dynamic LDS of a thin-run workgroup
+// Its first 16 bytes hold control words (no static LDS in these kernels: it
+// would offset the dynamic region and misalign its 16-byte records); the
+// window layout starts after them.
+constexpr int kCtlBytes = 16;
+struct Ctl {
+  int32_t no;    // overflow records allocated in the current window
+  int32_t next;  // batched launch: the workgroup's next queue ticket
+};
 
 // Workgroup barrier that orders LDS only: global stores may still be in flight
 // (the global copy of x is only read across an LDS-window restart, which uses a
@@ -37,8 +45,10 @@ __device__ __forceinline__ void lds_barrier() {
 //    global memory); the dependencies inside the window, scaled by
 //    1/L(pos,pos), go to an inline record per row {w0, w1 | slot0, slot1,
 //    count, first overflow}; a row's third and later in-window dependencies go
-//    to an overflow list of {weight, slot} records (its offset is a
-//    precomputed prefix sum, ovp). Absent inline dependencies point to a zero
+//    to an overflow list of {weight, slot} records (a row's records are
+//    contiguous, allocated from a window counter after the row has counted
+//    its in-window dependencies; the host bounds the window's total from a
+//    histogram of dependency level distances). Absent inline dependencies point to a zero
 //    entry with weight 0, so phase 2 needs no predication. A row's first four
 //    dependencies come from a fixed-width copy indexed by position (no row
 //    pointer on the load chain), and each thread takes several rows at once
@@ -147,14 +157,15 @@ constexpr int p1_tail() {
 // The windows [win, win + nwin) of one thin run, by the calling workgroup.
 // Returns the latched error bits; a window that does not fit aborts the run.
 template <int WG, bool kOne, bool kTimed>
-__device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict__ win, int32_t nwin, int32_t nrhs,
+__device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restrict__ win, int32_t nwin, int32_t nrhs,
                                              const ThinArgs &A, float *times, float ns_per_tick) {
+  int32_t &s_no = reinterpret_cast<Ctl *>(lds_raw)->no;
+  double *lds = reinterpret_cast<double *>(lds_raw + kCtlBytes);
   const int32_t nr = kOne ? 1 : nrhs;
   const int tid = threadIdx.x;
   const int32_t *__restrict__ level_ptr = A.level_ptr;
   const int32_t *__restrict__ srp = A.srp;
   const int32_t *__restrict__ sci = A.sci;
-  const int32_t *__restrict__ ovp = A.ovp;
   const double *__restrict__ sva = A.sva;
   const double *__restrict__ sdg = A.sdg;
   const int4 *__restrict__ ell_c = A.ell_c;
@@ -164,15 +175,17 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
   int bits = 0;
   unsigned long long t_w0 = 0, t_prev = 0;
   float p1_per_row = 0.f;
+  if (tid == 0) s_no = 0;
+  __syncthreads();
   for (int32_t w = 0; w < nwin; ++w) {
     if (kTimed && tid == 0) t_w0 = wall_clock64();
     const int32_t lA = win[w].x, lB = win[w + 1].x, flags = win[w].y;
     const int32_t P0 = level_ptr[lA], P1 = level_ptr[lB];
     const int32_t R = P1 - P0;
-    const int32_t O0 = ovp[P0], NO = ovp[P1] - O0;
+    const int32_t NO = win[w].z;  // bound on the window's overflow records
     const int32_t NL = lB - lA;
     // the host sizes windows to fit, and 16-bit slots and offsets must hold R and NO
-    if (thin_window_bytes(R, NO, NL, nr) > kWinBytes || R >= 65536 || NO >= 65536) return bits | EB_ARG;
+    if (thin_window_bytes(R, NO, NL, nr) > kWinBytes - kCtlBytes || R >= 65536 || NO >= 65536) return bits | EB_ARG;
     double2 *rw = reinterpret_cast<double2 *>(lds);          // [R] w0, w1 (scaled by 1/diagonal)
     Dep *ovf = reinterpret_cast<Dep *>(rw + R);               // [NO] third and later dependencies
     uint2 *rix = reinterpret_cast<uint2 *>(ovf + NO);         // [R] slot0, slot1, count, overflow
@@ -184,7 +197,7 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
     const int32_t nitems = R * nr;
     constexpr int kP1Items = p1_items<WG, kOne>();
     for (int32_t base = 0; base < nitems; base += WG * kP1Items) {
-      int32_t sj[kP1Items], cj[kP1Items], qb[kP1Items], deg[kP1Items], ob[kP1Items];
+      int32_t sj[kP1Items], cj[kP1Items], qb[kP1Items], deg[kP1Items];
       int4 ec[kP1Items];
       double2 ev0[kP1Items], ev1[kP1Items];
       double acc[kP1Items], dgv[kP1Items];
@@ -197,7 +210,6 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
         const int32_t pos = P0 + sj[j];
         qb[j] = srp[pos];
         deg[j] = it < nitems ? srp[pos + 1] - qb[j] : 0;
-        ob[j] = ovp[pos] - O0;
         ec[j] = ell_c[pos];
         ev0[j] = ell_v[2 * (int64_t)pos];
         ev1[j] = ell_v[2 * (int64_t)pos + 1];
@@ -218,6 +230,22 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
         if (it >= nitems) continue;
         const int32_t c = cj[j];
         const double dinv = 1.0 / dgv[j];
+        const int32_t kk[4] = {ec[j].x, ec[j].y, ec[j].z, ec[j].w};
+        // the row's overflow records: count its in-window dependencies first
+        int32_t ob = 0;
+        if (c == 0) {
+          int32_t cnt = 0;
+#pragma unroll
+          for (int d = 0; d < 4; ++d) cnt += (d < deg[j] && kk[d] >= P0) ? 1 : 0;
+          for (int32_t q = qb[j] + 4; q < qb[j] + deg[j]; ++q) cnt += sci[q] >= P0 ? 1 : 0;
+          if (cnt > 2) {
+            ob = atomicAdd(&s_no, cnt - 2);
+            if (ob + cnt - 2 > NO) {  // never with the host's bound; keeps every access in LDS
+              bits |= EB_ARG;
+              ob = -1;
+            }
+          }
+        }
         int32_t kin = 0, s0 = R, s1 = R;
         double w0 = 0.0, w1 = 0.0, a = acc[j];
         auto take = [&](int32_t k, double wv, double x) {
@@ -230,17 +258,16 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
             } else if (kin == 1) {
               s1 = k - P0;
               w1 = wv * dinv;
-            } else if (c == 0) {
+            } else if (c == 0 && ob >= 0) {
               Dep dd;
               dd.w = wv * dinv;
               dd.slot = k - P0;
               dd.pad = 0;
-              ovf[ob[j] + kin - 2] = dd;
+              ovf[ob + kin - 2] = dd;
             }
             ++kin;
           }
         };
-        const int32_t kk[4] = {ec[j].x, ec[j].y, ec[j].z, ec[j].w};
         const double vv[4] = {ev0[j].x, ev0[j].y, ev1[j].x, ev1[j].y};
 #pragma unroll
         for (int d = 0; d < 4; ++d)
@@ -266,7 +293,7 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
         v[(int64_t)sj[j] * nr + c] = a * dinv;
         if (c == 0) {
           rw[sj[j]] = make_double2(w0, w1);
-          rix[sj[j]] = pack_rix(s0, s1, kin, ob[j]);
+          rix[sj[j]] = ob >= 0 ? pack_rix(s0, s1, kin, ob) : pack_rix(s0, s1, kin < 2 ? kin : 2, 0);
         }
       }
     }
@@ -337,16 +364,17 @@ __device__ __forceinline__ int thin_run_body(double *lds, const int2 *__restrict
       if (!isfinite(x)) bits |= EB_NONFINITE;
       xw[i] = x;
     }
+    if (tid == 0) s_no = 0;
     __syncthreads();  // the window's global x is complete before the next phase 1 reads it
   }
   return bits;
 }
 
 template <int WG, bool kOne, bool kTimed = false>
-__global__ __launch_bounds__(WG) void k_thin_run(const int2 *__restrict__ win, int32_t nwin, int32_t nrhs, ThinArgs A,
+__global__ __launch_bounds__(WG) void k_thin_run(const int4 *__restrict__ win, int32_t nwin, int32_t nrhs, ThinArgs A,
                                                  int *err, float *times, float ns_per_tick) {
-  extern __shared__ double lds[];
-  const int bits = thin_run_body<WG, kOne, kTimed>(lds, win, nwin, nrhs, A, times, ns_per_tick);
+  extern __shared__ __align__(16) char lds_raw[];
+  const int bits = thin_run_body<WG, kOne, kTimed>(lds_raw, win, nwin, nrhs, A, times, ns_per_tick);
   if (bits) atomicOr(err, bits);
 }
 
@@ -376,10 +404,10 @@ __global__ void k_fill_ell(int32_t n, const int32_t *__restrict__ srp, const int
 // host-side reset. q[0] = next ticket, q[1] = finished workgroups.
 template <int WG, bool kOne>
 __global__ __launch_bounds__(WG) void k_batch_run(int32_t nmat, const int32_t *__restrict__ order,
-                                                  const int32_t *__restrict__ mwin, const int2 *__restrict__ win,
+                                                  const int32_t *__restrict__ mwin, const int4 *__restrict__ win,
                                                   int32_t nrhs, ThinArgs A, unsigned *q, int *err) {
-  extern __shared__ double lds[];
-  __shared__ int32_t s_m;
+  extern __shared__ __align__(16) char lds_raw[];
+  int32_t &s_m = reinterpret_cast<Ctl *>(lds_raw)->next;
   int bits = 0;
   for (;;) {
     if (threadIdx.x == 0) s_m = (int32_t)atomicAdd(q, 1u);
@@ -388,7 +416,7 @@ __global__ __launch_bounds__(WG) void k_batch_run(int32_t nmat, const int32_t *_
     __syncthreads();
     if (t >= nmat) break;
     const int32_t m = order[t];
-    bits |= thin_run_body<WG, kOne, false>(lds, win + mwin[m], mwin[m + 1] - mwin[m] - 1, nrhs, A, nullptr, 0.f);
+    bits |= thin_run_body<WG, kOne, false>(lds_raw, win + mwin[m], mwin[m + 1] - mwin[m] - 1, nrhs, A, nullptr, 0.f);
   }
   if (threadIdx.x == 0) {
     if (bits) atomicOr(err, bits);
@@ -409,7 +437,7 @@ void set_lds_attr() {
 
 }  // namespace
 
-int thin_win_bytes() { return kWinBytes; }
+int thin_win_bytes() { return kWinBytes - kCtlBytes; }
 
 void solve_kernels_init() {
   set_lds_attr<256, true>();
@@ -424,7 +452,7 @@ void solve_kernels_init() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
 }
 
-hipError_t launch_thin_run(int wg, const int2 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
+hipError_t launch_thin_run(int wg, const int4 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
                            hipStream_t s, float *times, float ns_per_tick) {
   const bool one = nrhs == 1;
   if (times) {  // labelling runs only: 512 threads
@@ -461,7 +489,7 @@ hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, co
   return hipGetLastError();
 }
 
-hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int2 *win,
+hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int4 *win,
                             int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s) {
   static bool attr = false;
   if (!attr) {

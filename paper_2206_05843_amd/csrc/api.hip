@@ -372,7 +372,7 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
                                 P.sva.p, P.sdg.p, P.bp.p, P.xp.p, P.wbar.p, err, s));
     } else {
       HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
-                                  P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.bp.p, P.xp.p, err, s));
+                                  P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, P.bp.p, P.xp.p, err, s));
     }
     prof_end(h, slot, s);
   }

@@ -108,7 +108,7 @@ sptrsv_status_t sptrsv_level_times(sptrsv_handle_t h, int which, int32_t nrhs, c
       HIPCHK(h, launch_thin_run(512, P->win.p + r.wi, r.nw, nrhs, thin_args(*P), h->d_err.p, s, d_times, ns_per_tick));
     } else {
       HIPCHK(h, launch_wide_level(256, 1, P->h_level_ptr[r.l0], P->h_level_ptr[r.l1], nrhs, P->srp.p, P->sci.p,
-                                  P->sva.p, P->sdg.p, P->bp.p, P->xp.p, h->d_err.p, s));
+                                  P->sva.p, P->sdg.p, P->ell_c.p, P->ell_v.p, P->bp.p, P->xp.p, h->d_err.p, s));
     }
   }
   HIPCHK(h, hipStreamSynchronize(s));

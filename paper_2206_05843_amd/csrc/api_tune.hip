@@ -36,9 +36,15 @@ std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
       for (int wg : wg_list) c.push_back(sptrsv_schedule_t{0, thr, wg, 256, lpr, 0});
     }
   }
-  // Persistent wide runs (wide_grid > 0) are not candidates: their device-wide
-  // barrier (device-scope release/acquire fences in every wave) costs more per
-  // level than a kernel launch on a device whose L2 is split across dies.
+  // consecutive wide levels in one persistent launch (one lane per item)
+  const int grids[] = {32, 256};
+  for (int g : grids) {
+    c.push_back(sptrsv_schedule_t{1, 0, 512, 256, 1, g});
+    for (int thr : thin_list) {
+      if (thin_window_bytes(thr, 0, 1, nrhs) > thin_win_bytes()) continue;
+      c.push_back(sptrsv_schedule_t{0, thr, 1024, 256, 1, g});
+    }
+  }
   return c;
 }
 

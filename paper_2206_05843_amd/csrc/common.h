@@ -256,7 +256,8 @@ hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, co
                            double2 *ell_v, hipStream_t s);
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                             const double *bp, double *xp, int *err, hipStream_t s);
+                             const int4 *ell_c, const double2 *ell_v, const double *bp, double *xp, int *err,
+                             hipStream_t s);
 hipError_t launch_wide_run(int grid, int threads, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                            const double *bp, double *xp, unsigned *bar, int *err, hipStream_t s);

@@ -107,7 +107,7 @@ __device__ __forceinline__ uint2 pack_rix(int32_t s0, int32_t s1, int32_t cnt, i
 // The static inputs of one (row, rhs) item in phase 2.
 struct Item {
   double acc, w0, w1;
-  int32_t s0, s1, cnt, ob;
+  uint2 r;  // packed slots/count/offset, unpacked where used (a prefetch never waits for it)
   int32_t s, c, act;
 };
 
@@ -122,11 +122,7 @@ __device__ __forceinline__ Item load_item(int32_t pb, int32_t items, int32_t t, 
   const double2 w = rw[ss];
   it.w0 = w.x;
   it.w1 = w.y;
-  const uint2 r = rix[ss];
-  it.s0 = (int32_t)(r.x & 0xffffu);
-  it.s1 = (int32_t)(r.x >> 16);
-  it.cnt = (int32_t)(r.y & 0xffffu);
-  it.ob = (int32_t)(r.y >> 16);
+  it.r = rix[ss];
   it.acc = v[(int64_t)ss * nr + (it.act ? it.c : 0)];
   return it;
 }
@@ -134,11 +130,13 @@ __device__ __forceinline__ Item load_item(int32_t pb, int32_t items, int32_t t, 
 template <bool kOne>
 __device__ __forceinline__ double solve_item(const Item &it, int32_t nr, const double *v, const Dep *ovf) {
   const int32_t c = it.c;
-  const double xa = v[(int64_t)it.s0 * (kOne ? 1 : nr) + c];
-  const double xb = v[(int64_t)it.s1 * (kOne ? 1 : nr) + c];
+  const int32_t s0 = (int32_t)(it.r.x & 0xffffu), s1 = (int32_t)(it.r.x >> 16);
+  const int32_t cnt = (int32_t)(it.r.y & 0xffffu), ob = (int32_t)(it.r.y >> 16);
+  const double xa = v[(int64_t)s0 * (kOne ? 1 : nr) + c];
+  const double xb = v[(int64_t)s1 * (kOne ? 1 : nr) + c];
   double acc = it.acc - it.w0 * xa;
   acc = acc - it.w1 * xb;
-  if (it.cnt > 2) acc = ovf_sum<kOne>(acc, ovf + it.ob, it.cnt - 2, v, nr, c);
+  if (cnt > 2) acc = ovf_sum<kOne>(acc, ovf + ob, cnt - 2, v, nr, c);
   return acc;
 }
 
@@ -307,39 +305,37 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
       const bool one_wave = flags & 1;
       if (!one_wave || tid < 64) {
         const int lane = tid & 63;
-        int32_t lvbase = 0;
-        int32_t lvreg = lv[lane <= NL ? lane : NL];
-        auto bounds = [&](int32_t l, int32_t &pb, int32_t &items) {
-          if (l - lvbase >= 63) {
-            lvbase += 63;
-            lvreg = lv[lvbase + lane <= NL ? lvbase + lane : NL];
+        // levels in chunks of 63: lane i holds the bound of level c0 + i, read
+        // once per chunk, so a level's bounds come from registers
+        for (int32_t c0 = 0; c0 < NL; c0 += 63) {
+          const int32_t nlc = NL - c0 < 63 ? NL - c0 : 63;
+          const int32_t lvreg = lv[c0 + lane <= NL ? c0 + lane : NL];
+          int32_t pb = __builtin_amdgcn_readlane(lvreg, 0);
+          int32_t items = (__builtin_amdgcn_readlane(lvreg, 1) - pb) * nr;
+          Item cur = load_item<kOne>(pb, items, tid, nr, v, rw, rix);
+          for (int32_t l = 0; l < nlc; ++l) {
+            Item nxt = cur;
+            if (l + 1 < nlc) {
+              pb = __builtin_amdgcn_readlane(lvreg, l + 1);
+              items = (__builtin_amdgcn_readlane(lvreg, l + 2) - pb) * nr;
+              nxt = load_item<kOne>(pb, items, tid, nr, v, rw, rix);
+            }
+            if (cur.act) v[(int64_t)cur.s * nr + cur.c] = solve_item<kOne>(cur, nr, v, ovf);
+            if (one_wave) {
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+            } else {
+              lds_barrier();
+            }
+            if (kTimed && tid == 0) {
+              const int32_t lg = c0 + l;
+              const unsigned long long now = wall_clock64();
+              times[lA + lg] = (float)(now - t_prev) * ns_per_tick + p1_per_row * (float)(lv[lg + 1] - lv[lg]);
+              t_prev = now;
+            }
+            cur = nxt;
           }
-          pb = __builtin_amdgcn_readlane(lvreg, l - lvbase);
-          items = (__builtin_amdgcn_readlane(lvreg, l - lvbase + 1) - pb) * nr;
-        };
-        int32_t pb, items;
-        bounds(0, pb, items);
-        Item cur = load_item<kOne>(pb, items, tid, nr, v, rw, rix);
-        for (int32_t l = 0; l < NL; ++l) {
-          Item nxt = cur;
-          if (l + 1 < NL) {
-            bounds(l + 1, pb, items);
-            nxt = load_item<kOne>(pb, items, tid, nr, v, rw, rix);
-          }
-          if (cur.act) v[(int64_t)cur.s * nr + cur.c] = solve_item<kOne>(cur, nr, v, ovf);
-          if (one_wave) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-          } else {
-            lds_barrier();
-          }
-          if (kTimed && tid == 0) {
-            const unsigned long long now = wall_clock64();
-            times[lA + l] = (float)(now - t_prev) * ns_per_tick + p1_per_row * (float)(lv[l + 1] - lv[l]);
-            t_prev = now;
-          }
-          cur = nxt;
         }
       }
     } else {

@@ -7,43 +7,74 @@
 
 namespace {
 
-// x(pos, c) = (b'(pos, c) - sum_k L(pos,k) x(k,c)) / L(pos,pos). Columns
-// < lds_base come from global memory, columns >= lds_base from the LDS window.
-template <bool kUseLds, bool kOne>
-__device__ __forceinline__ double row_solve(int32_t pos, int32_t c, int32_t nrhs, const int32_t *__restrict__ srp,
-                                            const int32_t *__restrict__ sci, const double *__restrict__ sva,
-                                            const double *__restrict__ sdg, const double *__restrict__ bp,
-                                            const double *xp, const double *lds, int32_t lds_base) {
-  const int64_t nr = kOne ? 1 : nrhs;
-  double acc = bp[(int64_t)pos * nr + c];
-  const int32_t b = srp[pos], e = srp[pos + 1];
-  for (int32_t q = b; q < e; ++q) {
-    const int32_t k = sci[q];
-    double xv;
-    if (kUseLds && k >= lds_base)
-      xv = lds[(int64_t)(k - lds_base) * nr + c];
-    else
-      xv = xp[(int64_t)k * nr + c];
-    acc -= sva[q] * xv;
-  }
-  return acc / sdg[pos];
-}
-
-// One wide level, one item (row, rhs) per thread.
+// One wide level, items (row, rhs) spread over the device, two per thread in
+// flight: a row's first four dependencies come from the fixed-width copy
+// indexed by position (no row pointer on the load chain), the rest from the
+// CSR four at a time; all loads of a step are issued before they are used and
+// the products are subtracted in the row's column order.
 template <bool kOne>
 __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t *__restrict__ srp,
                              const int32_t *__restrict__ sci, const double *__restrict__ sva,
-                             const double *__restrict__ sdg, const double *__restrict__ bp, double *xp, int *err) {
+                             const double *__restrict__ sdg, const int4 *__restrict__ ell_c,
+                             const double2 *__restrict__ ell_v, const double *__restrict__ bp, double *xp, int *err) {
+  constexpr int kI = 2;
   const int32_t nr = kOne ? 1 : nrhs;
   const int64_t items = (int64_t)(pe - pb) * nr;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int bits = 0;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t pos = kOne ? pb + (int32_t)it : pb + (int32_t)(it / nr);
-    const int32_t c = kOne ? 0 : (int32_t)(it - (int64_t)(pos - pb) * nr);
-    const double xv = row_solve<false, kOne>(pos, c, nr, srp, sci, sva, sdg, bp, xp, nullptr, 0);
-    if (!isfinite(xv)) bits |= EB_NONFINITE;
-    xp[(int64_t)pos * nr + c] = xv;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; base < items; base += stride * kI) {
+    int32_t pos[kI], c[kI], qb[kI], deg[kI];
+    int4 ec[kI];
+    double2 e0[kI], e1[kI];
+    double acc[kI], dg[kI];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      const int64_t it = base + j * stride;
+      const int64_t itc = it < items ? it : items - 1;
+      pos[j] = kOne ? pb + (int32_t)itc : pb + (int32_t)(itc / nr);
+      c[j] = kOne ? 0 : (int32_t)(itc - (int64_t)(pos[j] - pb) * nr);
+      qb[j] = srp[pos[j]];
+      deg[j] = it < items ? srp[pos[j] + 1] - qb[j] : 0;
+      ec[j] = ell_c[pos[j]];
+      e0[j] = ell_v[2 * (int64_t)pos[j]];
+      e1[j] = ell_v[2 * (int64_t)pos[j] + 1];
+      acc[j] = bp[(int64_t)pos[j] * nr + c[j]];
+      dg[j] = sdg[pos[j]];
+    }
+    double xv[kI][4];
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      const int32_t kk[4] = {ec[j].x, ec[j].y, ec[j].z, ec[j].w};
+#pragma unroll
+      for (int d = 0; d < 4; ++d) xv[j][d] = d < deg[j] ? xp[(int64_t)kk[d] * nr + c[j]] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kI; ++j) {
+      if (base + j * stride >= items) continue;
+      const double vv[4] = {e0[j].x, e0[j].y, e1[j].x, e1[j].y};
+      double a = acc[j];
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (d < deg[j]) a -= vv[d] * xv[j][d];
+      const int32_t qe = qb[j] + deg[j];
+      for (int32_t q0 = qb[j] + 4; q0 < qe; q0 += 4) {
+        int32_t k4[4];
+        double w4[4], x4[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          k4[d] = q0 + d < qe ? sci[q0 + d] : -1;
+          w4[d] = q0 + d < qe ? sva[q0 + d] : 0.0;
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) x4[d] = k4[d] >= 0 ? xp[(int64_t)k4[d] * nr + c[j]] : 0.0;
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+          if (k4[d] >= 0) a -= w4[d] * x4[d];
+      }
+      const double x = a / dg[j];
+      if (!isfinite(x)) bits |= EB_NONFINITE;
+      xp[(int64_t)pos[j] * nr + c[j]] = x;
+    }
   }
   if (bits) atomicOr(err, bits);
 }
@@ -78,12 +109,14 @@ __global__ void k_wide_level_group(int32_t pb, int32_t pe, const int32_t *__rest
 // Consecutive wide levels [l0, l1) in one launch of gridDim.x workgroups,
 // which must all be resident at once (the host sizes the grid from the
 // occupancy): every level's items are spread over all threads, and levels are
-// separated by a device-wide barrier (workgroup barrier, then one thread per
-// workgroup: device-scope release fence, arrival on bar[0], wait for all
-// arrivals, device-scope acquire fence). Waits are bounded by the wall clock:
-// on expiry the launch stops and reports a time-out instead of hanging. The
-// last workgroup to leave resets bar[0] and bar[1] (departures), so the launch
-// can be replayed (graph capture) with no host-side reset.
+// separated by a device-wide barrier. Inside the launch x is written and read
+// with device-scope atomic stores and loads, which are coherent across the
+// dies' separate L2 caches without writing back or invalidating them, so the
+// barrier is: wait for this thread's stores to complete, workgroup barrier,
+// one arrival per workgroup on bar[0], wait for all arrivals. Waits are
+// bounded by the wall clock: on expiry the launch stops and reports a
+// time-out instead of hanging. The last workgroup to leave resets bar[0] and
+// bar[1] (departures), so the launch can be replayed with no host-side reset.
 template <bool kOne>
 __global__ void k_wide_run(int32_t l0, int32_t l1, const int32_t *__restrict__ level_ptr, int32_t nrhs,
                            const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
@@ -103,16 +136,34 @@ __global__ void k_wide_run(int32_t l0, int32_t l1, const int32_t *__restrict__ l
     for (int64_t it = gid; it < items; it += nthreads) {
       const int32_t pos = kOne ? pb + (int32_t)it : pb + (int32_t)(it / nr);
       const int32_t c = kOne ? 0 : (int32_t)(it - (int64_t)(pos - pb) * nr);
-      const double xv = row_solve<false, kOne>(pos, c, nr, srp, sci, sva, sdg, bp, xp, nullptr, 0);
+      double acc = bp[(int64_t)pos * nr + c];
+      const int32_t qb = srp[pos], qe = srp[pos + 1];
+      for (int32_t q0 = qb; q0 < qe; q0 += 4) {  // four dependencies' loads in flight, summed in order
+        int32_t k4[4];
+        double w4[4], x4[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          k4[d] = q0 + d < qe ? sci[q0 + d] : -1;
+          w4[d] = q0 + d < qe ? sva[q0 + d] : 0.0;
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+          x4[d] = k4[d] >= 0 ? __hip_atomic_load(xp + (int64_t)k4[d] * nr + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : 0.0;
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+          if (k4[d] >= 0) acc -= w4[d] * x4[d];
+      }
+      const double xv = acc / sdg[pos];
       if (!isfinite(xv)) bits |= EB_NONFINITE;
-      xp[(int64_t)pos * nr + c] = xv;
+      __hip_atomic_store(xp + (int64_t)pos * nr + c, xv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (l + 1 == l1) break;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's x, visible device-wide
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores of x have completed
     __syncthreads();
     if (threadIdx.x == 0) {
       const unsigned target = (unsigned)(l - l0 + 1) * gridDim.x;
-      atomicAdd(bar, 1u);
+      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       unsigned spins = 0;
       while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         __builtin_amdgcn_s_sleep(1);
@@ -123,7 +174,6 @@ __global__ void k_wide_run(int32_t l0, int32_t l1, const int32_t *__restrict__ l
       }
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other workgroups' x
     if (s_abort) {
       bits |= EB_TIMEOUT;
       break;
@@ -145,7 +195,8 @@ __global__ void k_wide_run(int32_t l0, int32_t l1, const int32_t *__restrict__ l
 
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                             const double *bp, double *xp, int *err, hipStream_t s) {
+                             const int4 *ell_c, const double2 *ell_v, const double *bp, double *xp, int *err,
+                             hipStream_t s) {
   const int64_t rows = pe - pb;
   if (rows <= 0) return hipSuccess;
   if (nrhs == 1 && lanes_per_row > 1) {
@@ -165,13 +216,13 @@ hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t
     return hipGetLastError();
   }
   const int64_t items = rows * nrhs;
-  const int g = grid_for(items, threads, 65536);
+  const int g = grid_for((items + 1) / 2, threads, 65536);  // two items per thread
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_wide_level<true>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, bp, xp,
-                       err);
+    hipLaunchKernelGGL((k_wide_level<true>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, ell_c,
+                       ell_v, bp, xp, err);
   else
-    hipLaunchKernelGGL((k_wide_level<false>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, bp, xp,
-                       err);
+    hipLaunchKernelGGL((k_wide_level<false>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, ell_c,
+                       ell_v, bp, xp, err);
   return hipGetLastError();
 }
 

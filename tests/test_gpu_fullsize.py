@@ -1,0 +1,99 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration the
+benchmark times (each variant autotuned first): levels bit for bit, every
+output of x within relative 1e-10 of the oracle, rewritten patterns and values
+bit for bit, and the whole batch of matrices."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from tests.gpu_util import dev, to_dev
+
+pytestmark = pytest.mark.gpu
+sp = pytest.importorskip("paper_2206_05843_amd")
+
+TOL = 1e-10
+FULL = [1, 2, 4]
+
+
+@pytest.fixture(scope="module")
+def full():
+    out = {}
+    for c in FULL:
+        m, nrhs = gen.config_matrix(c)
+        b = gen.rhs(m, nrhs)
+        out[c] = (m, nrhs, b, oracle.solve(m, b))
+    return out
+
+
+@pytest.mark.parametrize("cfg", FULL)
+def test_full_levels(full, cfg):
+    m = full[cfg][0]
+    h = sp.Handle()
+    nlev = h.analyze(*dev(m))
+    lv = oracle.levels(m)
+    assert nlev == lv.nlev
+    lp, lr, rl = (t.cpu().numpy() for t in h.levels())
+    assert np.array_equal(lp, lv.level_ptr) and np.array_equal(lr, lv.level_rows)
+    assert np.array_equal(rl, lv.row_level)
+
+
+@pytest.mark.parametrize("cfg", FULL)
+@pytest.mark.parametrize("variant", ["plain", "naive", "learned"])
+def test_full_solve_autotuned(full, cfg, variant):
+    m, nrhs, b, xr = full[cfg]
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    which = sp.ORIGINAL
+    if variant == "naive":
+        h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0)
+        which = sp.REWRITTEN
+    elif variant == "learned":
+        from paper_2206_05843_amd import policy
+        pol = policy.load_default()
+        h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0, pol.mask_for(h) if pol is not None else None)
+        which = sp.REWRITTEN
+    h.autotune(which, nrhs)
+    bd = to_dev(b)
+    x = h.solve(bd if nrhs > 1 else bd.view(-1), which)
+    h.check()
+    assert oracle.relerr(x.view(nrhs, -1).cpu().numpy(), xr) <= TOL
+    # a second solve into the same buffers gives the same bits
+    x2 = h.solve(bd if nrhs > 1 else bd.view(-1), which)
+    assert torch.equal(x, x2)
+
+
+def test_full_rewrite_patterns_3d():
+    m = gen.config_matrix(4)[0]
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0)
+    rw = oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0)
+    assert st["nlev_after"] == oracle.levels(rw.lp).nlev
+    g = {k: v.cpu().numpy() for k, v in h.rewritten().items()}
+    assert np.array_equal(g["lp_ptr"], rw.lp.row_ptr) and np.array_equal(g["lp_col"], rw.lp.col)
+    assert np.array_equal(g["t_ptr"], rw.t_ptr) and np.array_equal(g["t_col"], rw.t_col)
+    assert np.array_equal(g["lp_val"], rw.lp.val) and np.array_equal(g["t_val"], rw.t_val)
+    assert np.array_equal(h.targets().cpu().numpy(), rw.target)
+
+
+def test_full_batch():
+    mats, nrhs = gen.config_matrix(3)
+    h = sp.Handle()
+    h.batch_analyze([m.n for m in mats], to_dev(np.concatenate([m.row_ptr for m in mats]).astype(np.int32)),
+                    to_dev(np.concatenate([m.col for m in mats])), to_dev(np.concatenate([m.val for m in mats])))
+    bs = [gen.rhs(m, nrhs) for m in mats]
+    b = to_dev(np.concatenate([x.reshape(-1) for x in bs]))
+    x = torch.zeros_like(b)
+    h.batch_solve(b, x, nrhs)
+    h.check()
+    xs = x.cpu().numpy()
+    off = 0
+    for i, (m, bm) in enumerate(zip(mats, bs)):
+        assert oracle.relerr(xs[off * nrhs:(off + m.n) * nrhs].reshape(nrhs, m.n), oracle.solve(m, bm)) <= TOL
+        if i % 64 == 0:  # levels of a sample of the matrices
+            lp, lr = h.batch_levels(i)
+            lv = oracle.levels(m)
+            assert np.array_equal(lp.cpu().numpy(), lv.level_ptr) and np.array_equal(lr.cpu().numpy(), lv.level_rows)
+        off += m.n

@@ -71,10 +71,10 @@ struct __align__(16) Dep {
   int32_t slot, pad;
 };
 
-constexpr int kBatch = 8;
+constexpr int kBatch = 4;
 
 // acc - sum_j w_j x(slot_j, c) over n overflow records starting at d, in order,
-// in batches of 8 (tail clamped to a valid record).
+// in batches of 4 (tail clamped to a valid record).
 template <bool kOne>
 __device__ __forceinline__ double ovf_sum(double acc, const Dep *__restrict__ d, int32_t n, const double *v,
                                           int32_t nr, int32_t c) {

@@ -99,31 +99,59 @@ __global__ void k_residual(int32_t n, int32_t nrhs, const int32_t *__restrict__ 
 }
 
 // Batched right-hand sides: matrix m's b and x are n_m x nrhs column-major at
-// offset nrhs * row_off[m], ld = n_m. Items run over (global row, column) with
-// the row fastest, so each column of each matrix is read/written contiguously.
+// offset nrhs * row_off[m], ld = n_m. A tile of 64 global rows x up to 32
+// columns is staged in LDS: the caller's side is read/written down columns
+// (contiguous within each matrix), the work vector's side one row's
+// right-hand sides at a time (contiguous at the row's position).
 __global__ void k_batch_gather(int64_t total, int32_t nrhs, const double *__restrict__ b,
                                const int32_t *__restrict__ mat_of_row, const int64_t *__restrict__ row_off,
                                const int32_t *__restrict__ iperm, double *bp) {
-  const int64_t items = total * nrhs;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = it / total, r = it - c * total;
-    const int32_t m = mat_of_row[r];
-    const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
-    bp[(int64_t)iperm[r] * nrhs + c] = b[nrhs * ro + c * nm + (r - ro)];
+  __shared__ double tile[64][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
+    const int32_t nc = min(32, nrhs - c0);
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int c = idx / 64, rr = idx % 64;
+      const int64_t r = r0 + rr;
+      if (r < total) {
+        const int32_t m = mat_of_row[r];
+        const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
+        tile[rr][c] = b[nrhs * ro + (int64_t)(c0 + c) * nm + (r - ro)];
+      }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int rr = idx / nc, c = idx % nc;
+      const int64_t r = r0 + rr;
+      if (r < total) bp[(int64_t)iperm[r] * nrhs + c0 + c] = tile[rr][c];
+    }
+    __syncthreads();
   }
 }
 
 __global__ void k_batch_scatter(int64_t total, int32_t nrhs, const double *__restrict__ xp,
                                 const int32_t *__restrict__ mat_of_row, const int64_t *__restrict__ row_off,
                                 const int32_t *__restrict__ iperm, double *x) {
-  const int64_t items = total * nrhs;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = it / total, r = it - c * total;
-    const int32_t m = mat_of_row[r];
-    const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
-    x[nrhs * ro + c * nm + (r - ro)] = xp[(int64_t)iperm[r] * nrhs + c];
+  __shared__ double tile[64][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
+    const int32_t nc = min(32, nrhs - c0);
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int rr = idx / nc, c = idx % nc;
+      const int64_t r = r0 + rr;
+      if (r < total) tile[rr][c] = xp[(int64_t)iperm[r] * nrhs + c0 + c];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+      const int c = idx / 64, rr = idx % 64;
+      const int64_t r = r0 + rr;
+      if (r < total) {
+        const int32_t m = mat_of_row[r];
+        const int64_t ro = row_off[m], nm = row_off[m + 1] - ro;
+        x[nrhs * ro + (int64_t)(c0 + c) * nm + (r - ro)] = tile[rr][c];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -170,15 +198,15 @@ hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int
 hipError_t launch_batch_gather(int64_t total, int32_t nrhs, const double *b, const int32_t *mat_of_row,
                                const int64_t *row_off, const int32_t *iperm, double *bp, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_gather, dim3(grid_for(total * nrhs, 256, 16384)), dim3(256), 0, s, total, nrhs, b,
-                     mat_of_row, row_off, iperm, bp);
+  hipLaunchKernelGGL(k_batch_gather, dim3((unsigned)((total + 63) / 64)), dim3(256), 0, s, total, nrhs, b, mat_of_row,
+                     row_off, iperm, bp);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_scatter(int64_t total, int32_t nrhs, const double *xp, const int32_t *mat_of_row,
                                 const int64_t *row_off, const int32_t *iperm, double *x, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_scatter, dim3(grid_for(total * nrhs, 256, 16384)), dim3(256), 0, s, total, nrhs, xp,
+  hipLaunchKernelGGL(k_batch_scatter, dim3((unsigned)((total + 63) / 64)), dim3(256), 0, s, total, nrhs, xp,
                      mat_of_row, row_off, iperm, x);
   return hipGetLastError();
 }

@@ -108,6 +108,11 @@ def bench_batch(args, np, torch, gen, oracle, sp):
     h.batch_analyze(ns, rp, ci, va)
     torch.cuda.synchronize()
     pre = time.perf_counter() - t
+    t = time.perf_counter()
+    h.autotune(sp.BATCH, nrhs)
+    tune_s = time.perf_counter() - t
+    sched = h.get_schedule(sp.BATCH, nrhs)
+    log(f"[bench] batch schedule {sched} (tuned in {tune_s:.2f}s)")
     nlev = [int(h.batch_levels(i)[0].numel()) - 1 for i in range(len(mats))]
     x = torch.zeros_like(b)
     h.batch_solve(b, x, nrhs)
@@ -182,7 +187,7 @@ def bench_batch(args, np, torch, gen, oracle, sp):
                      "looped_per_matrix": {"ms": round(ms_loop, 5)}},
         "speedup_vs_looped": round(ms_loop / ms, 4),
         "matrix_solves_per_s": round(len(mats) * 1e3 / ms, 1),
-        "preprocess_s": round(pre, 3), "max_relerr": worst,
+        "preprocess_s": round(pre, 3), "autotune_s": round(tune_s, 3), "schedule": sched, "max_relerr": worst,
         "levels": {"min": min(nlev), "max": max(nlev), "total": sum(nlev)},
     }
     print(json.dumps(res), flush=True)

@@ -54,7 +54,10 @@ typedef enum {
   SPTRSV_ERR_TIMEOUT = 11      /* a bounded device-side wait expired           */
 } sptrsv_status_t;
 
-enum { SPTRSV_ORIGINAL = 0, SPTRSV_REWRITTEN = 1 };
+/* Which plan: the analysed matrix, its rewrite, or (schedule and autotuner
+ * only) the batched matrices of sptrsv_batch_analyze, whose persistent launch
+ * uses the wg_threads knob (256, 512 or 1024). */
+enum { SPTRSV_ORIGINAL = 0, SPTRSV_REWRITTEN = 1, SPTRSV_BATCH = 2 };
 enum { SPTRSV_THIN_ROWS = 0, SPTRSV_THIN_COST = 1 };
 
 /* Handle lifetime. create: makes a handle bound to the current HIP device.
@@ -183,7 +186,8 @@ sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_s
 sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, sptrsv_schedule_t *sched);
 
 /* Autotuner: times candidate schedules with HIP events on s (inputs b = 1) and
- * keeps the fastest for (which, nrhs). best_ms (host, may be NULL) receives the
+ * keeps the fastest for (which, nrhs); for SPTRSV_BATCH the candidates are the
+ * workgroup sizes of the persistent launch. best_ms (host, may be NULL) receives the
  * best solve time. Synchronous. */
 sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms);
 

@@ -40,6 +40,8 @@ int bit_width(int64_t v) {
   return b;
 }
 
+}  // namespace
+
 sptrsv_schedule_t default_schedule() {
   sptrsv_schedule_t s{};
   s.mode = 0;
@@ -50,6 +52,8 @@ sptrsv_schedule_t default_schedule() {
   s.wide_grid = 0;
   return s;
 }
+
+namespace {
 
 bool same_sched(const sptrsv_schedule_t &a, const sptrsv_schedule_t &b) {
   return a.mode == b.mode && a.thin_rows == b.thin_rows && a.wg_threads == b.wg_threads &&
@@ -70,14 +74,14 @@ sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
   return SPTRSV_OK;
 }
 
+}  // namespace
+
 // The schedule actually used for (P, nrhs): a tuned one if present, else the
 // handle's knobs.
 sptrsv_schedule_t effective_sched(const Plan &P, int32_t nrhs) {
   auto it = P.tuned.find(nrhs);
   return it != P.tuned.end() ? it->second : P.sched;
 }
-
-}  // namespace
 
 static int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
   return thin_window_bytes(rows, ents, nl, nrhs);
@@ -383,6 +387,19 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
 }
 
 // ------------------------------------------------------------------- ABI
+// The plan a solve-side entry point addresses (the analysed matrix or its rewrite).
+Plan *plan_of(sptrsv_ctx *h, int which) {
+  if (which == SPTRSV_ORIGINAL) return &h->orig;
+  if (which == SPTRSV_REWRITTEN) return &h->rew;
+  return nullptr;
+}
+
+// Plans whose schedule can be set, read and tuned (the batched one as well).
+Plan *sched_plan_of(sptrsv_ctx *h, int which) {
+  if (which == SPTRSV_BATCH) return h->b_ready ? &h->bat : nullptr;
+  return plan_of(h, which);
+}
+
 extern "C" {
 
 const char *sptrsv_status_name(sptrsv_status_t s) {
@@ -470,11 +487,6 @@ sptrsv_status_t sptrsv_analyze(sptrsv_handle_t h, int32_t n, int32_t nnz, const 
   return SPTRSV_OK;
 }
 
-static Plan *plan_of(sptrsv_ctx *h, int which) {
-  if (which == SPTRSV_ORIGINAL) return &h->orig;
-  if (which == SPTRSV_REWRITTEN) return &h->rew;
-  return nullptr;
-}
 
 sptrsv_status_t sptrsv_get_levels(sptrsv_handle_t h, int which, int32_t *d_level_ptr, int32_t *d_level_rows,
                                   int32_t *d_row_level, hipStream_t s) {
@@ -557,7 +569,7 @@ sptrsv_status_t sptrsv_check(sptrsv_handle_t h, hipStream_t s) {
 
 sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_schedule_t *sched) {
   if (!h || !sched) return SPTRSV_ERR_ARG;
-  Plan *P = plan_of(h, which);
+  Plan *P = sched_plan_of(h, which);
   if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
   STCHK(check_sched(h, *sched));
   P->sched = *sched;
@@ -568,7 +580,7 @@ sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_s
 
 sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, sptrsv_schedule_t *sched) {
   if (!h || !sched) return SPTRSV_ERR_ARG;
-  Plan *P = plan_of(h, which);
+  Plan *P = sched_plan_of(h, which);
   if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
   if (nrhs < 1) return set_err(h, SPTRSV_ERR_ARG, "nrhs=%d", nrhs);
   *sched = effective_sched(*P, nrhs);

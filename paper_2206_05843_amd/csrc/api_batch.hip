@@ -65,8 +65,8 @@ int bit_width64(int64_t v) {
 }
 
 // Per-matrix LDS windows for nrhs (cached).
-sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs) {
-  if (h->b_win_nrhs == nrhs) return SPTRSV_OK;
+sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs, int32_t wg) {
+  if (h->b_win_nrhs == nrhs && h->b_win_wg == wg) return SPTRSV_OK;
   Plan &P = h->bat;
   P.h_win.clear();
   h->b_h_mwin.assign((size_t)h->b_nmat + 1, 0);
@@ -77,7 +77,7 @@ sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs) {
         return set_err(h, SPTRSV_ERR_ARG, "batch: level %d of matrix %d is too wide for one workgroup at nrhs=%d",
                        l - l0, m, nrhs);
     h->b_h_mwin[(size_t)m] = (int32_t)P.h_win.size();
-    cut_windows(P, l0, l1, nrhs, 512, P.h_win);
+    cut_windows(P, l0, l1, nrhs, wg, P.h_win);
   }
   h->b_h_mwin[(size_t)h->b_nmat] = (int32_t)P.h_win.size();
   HIPCHK(h, P.win.alloc(std::max<size_t>(P.h_win.size(), 1)));
@@ -86,6 +86,7 @@ sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs) {
   HIPCHK(h, hipMemcpy(h->b_mwin.p, h->b_h_mwin.data(), sizeof(int32_t) * ((size_t)h->b_nmat + 1),
                       hipMemcpyHostToDevice));
   h->b_win_nrhs = nrhs;
+  h->b_win_wg = wg;
   return SPTRSV_OK;
 }
 
@@ -162,6 +163,7 @@ sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t nmat, const int3
   const int32_t n = (int32_t)total;
   Plan &P = h->bat;
   P = Plan{};
+  P.sched = default_schedule();
   P.n = n;
   P.nnz = total_nnz;
   DArr<int32_t> lev1, keys, ktmp, vtmp, hist, mx, lvl_off_d;
@@ -268,10 +270,11 @@ sptrsv_status_t sptrsv_batch_solve(sptrsv_handle_t h, int32_t nrhs, const double
   const char *b0 = reinterpret_cast<const char *>(d_b_cat), *x0 = reinterpret_cast<const char *>(d_x_cat);
   if (b0 < x0 + len && x0 < b0 + len) return set_err(h, SPTRSV_ERR_ARG, "b and x overlap");
   STCHK(ensure_work(h, P, nrhs));
-  STCHK(batch_windows(h, nrhs));
+  const int32_t wg = effective_sched(P, nrhs).wg_threads;
+  STCHK(batch_windows(h, nrhs, wg));
   HIPCHK(h, launch_batch_gather(P.n, nrhs, d_b_cat, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, P.bp.p, s));
-  const int32_t grid = std::min(h->b_nmat, batch_resident_blocks());
-  HIPCHK(h, launch_batch_run(h->b_nmat, grid, h->b_order.p, h->b_mwin.p, P.win.p, nrhs, thin_args(P), h->b_q.p,
+  const int32_t grid = std::min(h->b_nmat, batch_resident_blocks(wg));
+  HIPCHK(h, launch_batch_run(wg, h->b_nmat, grid, h->b_order.p, h->b_mwin.p, P.win.p, nrhs, thin_args(P), h->b_q.p,
                              h->d_err.p, s));
   HIPCHK(h, launch_batch_scatter(P.n, nrhs, P.xp.p, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, d_x_cat, s));
   return SPTRSV_OK;
@@ -284,11 +287,12 @@ sptrsv_status_t sptrsv_batch_solve_looped(sptrsv_handle_t h, int32_t nrhs, const
   if (nrhs < 1 || !d_b_cat || !d_x_cat) return set_err(h, SPTRSV_ERR_ARG, "batch solve args");
   Plan &P = h->bat;
   STCHK(ensure_work(h, P, nrhs));
-  STCHK(batch_windows(h, nrhs));
+  const int32_t wg = effective_sched(P, nrhs).wg_threads;
+  STCHK(batch_windows(h, nrhs, wg));
   HIPCHK(h, launch_batch_gather(P.n, nrhs, d_b_cat, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, P.bp.p, s));
   for (int32_t m = 0; m < h->b_nmat; ++m) {
     const int32_t wi = h->b_h_mwin[(size_t)m], nw = h->b_h_mwin[(size_t)m + 1] - wi - 1;
-    HIPCHK(h, launch_thin_run(512, P.win.p + wi, nw, nrhs, thin_args(P), h->d_err.p, s));
+    HIPCHK(h, launch_thin_run(wg, P.win.p + wi, nw, nrhs, thin_args(P), h->d_err.p, s));
   }
   HIPCHK(h, launch_batch_scatter(P.n, nrhs, P.xp.p, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, d_x_cat, s));
   return SPTRSV_OK;

@@ -11,12 +11,6 @@ __global__ void k_fill(double *a, int64_t n, double v) {
     a[i] = v;
 }
 
-Plan *plan_of(sptrsv_ctx *h, int which) {
-  if (which == SPTRSV_ORIGINAL) return &h->orig;
-  if (which == SPTRSV_REWRITTEN) return &h->rew;
-  return nullptr;
-}
-
 // Candidate schedules: all-wide, all-in-one-workgroup, and thin/wide splits at
 // several widths, workgroup sizes and (one RHS) lanes per row.
 std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
@@ -54,7 +48,7 @@ extern "C" {
 
 sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms) {
   if (!h) return SPTRSV_ERR_ARG;
-  Plan *P = plan_of(h, which);
+  Plan *P = sched_plan_of(h, which);
   if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
   if (!P->ready) return set_err(h, SPTRSV_ERR_STATE, "matrix not analysed/rewritten");
   if (nrhs < 1) return set_err(h, SPTRSV_ERR_ARG, "nrhs=%d", nrhs);
@@ -75,16 +69,27 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
   float best = 1e30f;
   sptrsv_schedule_t best_s = keep;
   sptrsv_status_t st = SPTRSV_OK;
-  for (const sptrsv_schedule_t &cand : candidates(nrhs)) {
+  // the batched matrices: workgroup size of the persistent launch
+  const bool batch = which == SPTRSV_BATCH;
+  std::vector<sptrsv_schedule_t> cands;
+  if (batch) {
+    for (int wg : {256, 512, 1024}) cands.push_back(sptrsv_schedule_t{2, 0, wg, 256, 1, 0});
+  } else {
+    cands = candidates(nrhs);
+  }
+  auto run = [&]() {
+    return batch ? sptrsv_batch_solve(h, nrhs, b.p, x.p, s) : plan_solve(h, *P, nrhs, b.p, n, x.p, n, s);
+  };
+  for (const sptrsv_schedule_t &cand : cands) {
     P->sched = cand;
     P->runs_nrhs = -1;
     P->tuned.erase(nrhs);
     float t[3];
-    st = plan_solve(h, *P, nrhs, b.p, n, x.p, n, s);  // warm-up
+    st = run();  // warm-up
     if (st != SPTRSV_OK) break;
     for (int rep = 0; rep < 3 && st == SPTRSV_OK; ++rep) {
       (void)hipEventRecord(e0, s);
-      st = plan_solve(h, *P, nrhs, b.p, n, x.p, n, s);
+      st = run();
       (void)hipEventRecord(e1, s);
       (void)hipEventSynchronize(e1);
       (void)hipEventElapsedTime(&t[rep], e0, e1);

@@ -151,7 +151,7 @@ struct sptrsv_ctx {
   DArr<int64_t> b_row_off_d;           // [nmat+1]
   DArr<unsigned> b_q;                  // persistent-launch queue counters
   std::vector<int32_t> b_h_mwin;       // window index of each matrix's run, for the cached nrhs
-  int32_t b_win_nrhs = -1;
+  int32_t b_win_nrhs = -1, b_win_wg = -1;
   std::vector<Graph> graphs;
   // live profile of solve launches
   bool prof = false;
@@ -307,13 +307,17 @@ hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const
                             int32_t *redo, int32_t *nredo, char *big, int32_t bigC, int32_t bigH, int32_t big_blocks,
                             int *err, hipStream_t s);
 // Batched launchers (k_solve.hip) -------------------------------------------------
-hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int4 *win,
-                            int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s);
+hipError_t launch_batch_run(int wg, int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin,
+                            const int4 *win, int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s);
 hipError_t launch_batch_gather(int64_t total, int32_t nrhs, const double *b, const int32_t *mat_of_row,
                                const int64_t *row_off, const int32_t *iperm, double *bp, hipStream_t s);
 hipError_t launch_batch_scatter(int64_t total, int32_t nrhs, const double *xp, const int32_t *mat_of_row,
                                 const int64_t *row_off, const int32_t *iperm, double *x, hipStream_t s);
-int batch_resident_blocks();
+int batch_resident_blocks(int wg);
+sptrsv_schedule_t effective_sched(const Plan &P, int32_t nrhs);
+Plan *plan_of(sptrsv_ctx *h, int which);
+Plan *sched_plan_of(sptrsv_ctx *h, int which);
+sptrsv_schedule_t default_schedule();
 // Schedule helpers (api.hip) -----------------------------------------------------
 bool level_fits_window(const Plan &P, int32_t l, int32_t nrhs);
 int32_t cut_windows(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs, int32_t wg, std::vector<int4> &out);

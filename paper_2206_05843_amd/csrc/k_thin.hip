@@ -485,30 +485,48 @@ hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, co
   return hipGetLastError();
 }
 
-hipError_t launch_batch_run(int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin, const int4 *win,
-                            int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s) {
+template <int WG>
+void batch_attr() {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_run<WG, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_run<WG, false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
+}
+
+hipError_t launch_batch_run(int wg, int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin,
+                            const int4 *win, int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_run<512, true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_run<512, false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
+    batch_attr<256>();
+    batch_attr<512>();
+    batch_attr<1024>();
     attr = true;
   }
-  if (nrhs == 1)
-    hipLaunchKernelGGL((k_batch_run<512, true>), dim3(grid), dim3(512), kWinBytes, s, nmat, order, mwin, win, nrhs, a,
-                       q, err);
-  else
-    hipLaunchKernelGGL((k_batch_run<512, false>), dim3(grid), dim3(512), kWinBytes, s, nmat, order, mwin, win, nrhs,
+#define BATCH(W)                                                                                                \
+  if (nrhs == 1)                                                                                                \
+    hipLaunchKernelGGL((k_batch_run<W, true>), dim3(grid), dim3(W), kWinBytes, s, nmat, order, mwin, win, nrhs, a, \
+                       q, err);                                                                                 \
+  else                                                                                                          \
+    hipLaunchKernelGGL((k_batch_run<W, false>), dim3(grid), dim3(W), kWinBytes, s, nmat, order, mwin, win, nrhs,   \
                        a, q, err);
+  if (wg == 256) {
+    BATCH(256)
+  } else if (wg == 1024) {
+    BATCH(1024)
+  } else {
+    BATCH(512)
+  }
+#undef BATCH
   return hipGetLastError();
 }
 
-int batch_resident_blocks() {
+int batch_resident_blocks(int wg) {
   int dev = 0, cus = 256, occ = 1;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(&k_batch_run<512, false>),
-                                                     512, kWinBytes);
+  const void *f = wg == 256    ? reinterpret_cast<const void *>(&k_batch_run<256, false>)
+                  : wg == 1024 ? reinterpret_cast<const void *>(&k_batch_run<1024, false>)
+                               : reinterpret_cast<const void *>(&k_batch_run<512, false>);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, wg, kWinBytes);
   return cus * (occ > 0 ? occ : 1);
 }

@@ -14,7 +14,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
 
-ORIGINAL, REWRITTEN = 0, 1
+ORIGINAL, REWRITTEN, BATCH = 0, 1, 2
 THIN_ROWS, THIN_COST = 0, 1
 MLP_NPARAM = 5313
 

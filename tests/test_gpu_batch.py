@@ -100,6 +100,41 @@ def test_batch_graph_replays(batch):
         _ = (b * 3.0).sum().item()  # eager work between replays
 
 
+@pytest.mark.parametrize("wg", [256, 1024])
+def test_batch_workgroup_sizes(batch, wg):
+    mats, nrhs, h = batch
+    b = _rhs_cat(mats, nrhs)
+    ref = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    h.batch_solve(to_dev(b), ref, nrhs)
+    h.set_schedule(sp.BATCH, mode=2, wg_threads=wg)
+    assert h.get_schedule(sp.BATCH, nrhs)["wg_threads"] == wg
+    x = torch.zeros_like(ref)
+    h.batch_solve(to_dev(b), x, nrhs)
+    h.check()
+    xs = x.cpu().numpy()
+    off = 0
+    for m in mats:
+        xm = xs[off * nrhs:(off + m.n) * nrhs].reshape(nrhs, m.n)
+        bm = b[off * nrhs:(off + m.n) * nrhs].reshape(nrhs, m.n)
+        assert oracle.relerr(xm, oracle.solve(m, bm)) <= TOL
+        off += m.n
+    h.set_schedule(sp.BATCH)
+
+
+def test_batch_autotune(batch):
+    mats, nrhs, h = batch
+    assert h.autotune(sp.BATCH, nrhs) > 0
+    assert h.get_schedule(sp.BATCH, nrhs)["wg_threads"] in (256, 512, 1024)
+    b = _rhs_cat(mats, nrhs)
+    x = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    h.batch_solve(to_dev(b), x, nrhs)
+    h.check()
+    m = mats[0]
+    xm = x[:m.n * nrhs].cpu().numpy().reshape(nrhs, m.n)
+    assert oracle.relerr(xm, oracle.solve(m, b[:m.n * nrhs].reshape(nrhs, m.n))) <= TOL
+    h.set_schedule(sp.BATCH)
+
+
 def test_batch_errors():
     h = sp.Handle()
     with pytest.raises(sp.SptrsvError) as ei:

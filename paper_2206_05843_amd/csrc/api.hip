@@ -257,7 +257,7 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
     P.nnz_t_off = tn;
     HIPCHK(h, P.tci.alloc((size_t)std::max(tn, 1)));
     HIPCHK(h, P.tva.alloc((size_t)std::max(tn, 1)));
-    HIPCHK(h, launch_fill_t(n, P.perm.p, P.iperm.p, trp, tci, tva, P.trp.p, P.tci.p, P.tva.p, s));
+    HIPCHK(h, launch_fill_t(n, P.perm.p, trp, tci, tva, P.trp.p, P.tci.p, P.tva.p, s));
   }
   // statistics of the cost model
   HIPCHK(h, P.lv_rows.alloc(nlev));
@@ -288,6 +288,10 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
     for (int32_t p = 0; p < n; ++p)
       if (htrp[(size_t)p + 1] > htrp[(size_t)p]) tpos.push_back(p);
     P.n_tpos = (int32_t)tpos.size();
+    // lanes per row of T: enough that a group's reads of a row coalesce, few
+    // enough that most lanes hold an entry
+    const double avg_t = P.n_tpos > 0 ? (double)P.nnz_t_off / (double)P.n_tpos : 0.0;
+    P.t_lanes = avg_t >= 48.0 ? 64 : avg_t >= 12.0 ? 16 : avg_t >= 3.0 ? 4 : 1;
     HIPCHK(h, P.tpos.alloc(std::max<size_t>(tpos.size(), 1)));
     if (!tpos.empty())
       HIPCHK(h, hipMemcpy(P.tpos.p, tpos.data(), sizeof(int32_t) * tpos.size(), hipMemcpyHostToDevice));
@@ -352,7 +356,7 @@ sptrsv_status_t build_extra_hist(sptrsv_ctx *h, Plan &P, hipStream_t s) {
 sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, hipStream_t s) {
   HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.bp.p, s));
   if (P.has_t && P.n_tpos > 0)
-    HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.tpos.p, P.perm.p, P.trp.p, P.tci.p, P.tva.p, b, ldb, P.bp.p, s));
+    HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, P.perm.p, P.trp.p, P.tci.p, P.tva.p, b, ldb, P.bp.p, s));
   return SPTRSV_OK;
 }
 

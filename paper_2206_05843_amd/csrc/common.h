@@ -85,10 +85,11 @@ struct Plan {
   DArr<double> sva, sdg;               // values, diagonal per position
   bool has_t = false;
   int64_t nnz_t_off = 0;
-  DArr<int32_t> trp, tci;              // T off-diagonals per position
+  DArr<int32_t> trp, tci;              // T off-diagonals per position (columns: caller's rows)
   DArr<double> tva;
   DArr<int32_t> tpos;                  // positions whose row of T has off-diagonals
   int32_t n_tpos = 0;
+  int32_t t_lanes = 1;                 // lanes per row of T in the b-transform
   DArr<int64_t> lv_rows, lv_nnz, lv_cost;
   std::vector<int64_t> h_lv_nnz;       // per level: nnz incl. diagonal (host copy)
   std::vector<int64_t> h_lv_tnnz;      // per level: off-diagonal nnz of T
@@ -201,9 +202,8 @@ hipError_t launch_ptr_from_scan(const long long *ex, const long long *cnt, int32
 hipError_t launch_fill_solve(int32_t n, const int32_t *perm, const int32_t *iperm, const int32_t *rp,
                              const int32_t *ci, const double *va, const int32_t *srp, int32_t *sci, double *sva,
                              double *sdg, hipStream_t s);
-hipError_t launch_fill_t(int32_t n, const int32_t *perm, const int32_t *iperm, const int32_t *trp,
-                         const int32_t *tci, const double *tva, const int32_t *strp, int32_t *stci, double *stva,
-                         hipStream_t s);
+hipError_t launch_fill_t(int32_t n, const int32_t *perm, const int32_t *trp, const int32_t *tci,
+                         const double *tva, const int32_t *strp, int32_t *stci, double *stva, hipStream_t s);
 hipError_t launch_level_stats(int32_t nlev, const int32_t *level_ptr, const int32_t *srp, int64_t *rows,
                               int64_t *nnz, int64_t *cost, long long *total, hipStream_t s);
 
@@ -242,9 +242,10 @@ struct ThinArgs {
 // Launchers (k_solve.hip) ------------------------------------------------------
 hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
                          hipStream_t s);
-hipError_t launch_apply_t(int32_t nt, int32_t nrhs, const int32_t *tpos, const int32_t *perm, const int32_t *trp,
-                          const int32_t *tci, const double *tva, const double *b, int64_t ldb, double *bp,
-                          hipStream_t s);
+// lanes: 1 (a thread per row and column of b) or 4, 16, 64 (a group per row)
+hipError_t launch_apply_t(int32_t nt, int32_t nrhs, int32_t lanes, const int32_t *tpos, const int32_t *perm,
+                          const int32_t *trp, const int32_t *tcol, const double *tva, const double *b, int64_t ldb,
+                          double *bp, hipStream_t s);
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
 int thin_win_bytes();

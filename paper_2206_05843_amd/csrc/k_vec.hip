@@ -33,12 +33,14 @@ __global__ void k_gather1(int32_t n, const double *__restrict__ b, const int32_t
 }
 
 // The b-transform of the rewritten system (Sec. II.B) on the rows where T has
-// off-diagonals (positions tpos): b'(pos, c) = b(row, c) + sum over T's row, in
-// its order, of T(pos, k) b(perm[k], c), with row = perm[pos] and b the
-// caller's column-major right-hand sides (T's unit diagonal is implicit). Only
-// b is read, so the items are independent.
+// off-diagonals (positions tpos): b'(pos, c) = b(row, c) + sum over T's row
+// of T(pos, k) b(k, c), with row = perm[pos], T's columns k in the caller's
+// row numbering and b the caller's column-major right-hand sides (T's unit
+// diagonal is implicit). Only b is read, so the items are independent.
+//
+// One thread per (row, column of b): for short rows of T.
 __global__ void k_apply_t(int32_t nt, int32_t nrhs, const int32_t *__restrict__ tpos, const int32_t *__restrict__ perm,
-                          const int32_t *__restrict__ trp, const int32_t *__restrict__ tci,
+                          const int32_t *__restrict__ trp, const int32_t *__restrict__ tcol,
                           const double *__restrict__ tva, const double *__restrict__ b, int64_t ldb, double *bp) {
   const int64_t total = (int64_t)nt * nrhs;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
@@ -48,8 +50,35 @@ __global__ void k_apply_t(int32_t nt, int32_t nrhs, const int32_t *__restrict__ 
     const double *bc = b + (int64_t)c * ldb;
     double acc = bc[perm[pos]];
     const int32_t qb = trp[pos], qe = trp[pos + 1];
-    for (int32_t q = qb; q < qe; ++q) acc += tva[q] * bc[perm[tci[q]]];
+    for (int32_t q = qb; q < qe; ++q) acc += tva[q] * bc[tcol[q]];
     bp[(int64_t)pos * nrhs + c] = acc;
+  }
+}
+
+// G lanes per row of T (G divides 64): the lanes stride the row together, so
+// its columns and values are read in coalesced runs, and the partial sums are
+// combined by a butterfly inside the group. For long rows of T.
+template <int G>
+__global__ void k_apply_t_group(int32_t nt, int32_t nrhs, const int32_t *__restrict__ tpos,
+                                const int32_t *__restrict__ perm, const int32_t *__restrict__ trp,
+                                const int32_t *__restrict__ tcol, const double *__restrict__ tva,
+                                const double *__restrict__ b, int64_t ldb, double *bp) {
+  const int lane = threadIdx.x % G;
+  const int64_t ng = (int64_t)gridDim.x * (blockDim.x / G);
+  // every lane of a group takes the same trip count, so the butterfly sees
+  // the whole group
+  for (int64_t j = (int64_t)blockIdx.x * (blockDim.x / G) + threadIdx.x / G; j < nt; j += ng) {
+    const int32_t pos = tpos[j];
+    const int32_t qb = trp[pos], qe = trp[pos + 1];
+    const int32_t row = perm[pos];
+    for (int32_t c = 0; c < nrhs; ++c) {
+      const double *bc = b + (int64_t)c * ldb;
+      double acc = 0.0;
+      for (int32_t q = qb + lane; q < qe; q += G) acc += tva[q] * bc[tcol[q]];
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+      if (lane == 0) bp[(int64_t)pos * nrhs + c] = bc[row] + acc;
+    }
   }
 }
 
@@ -167,12 +196,31 @@ hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, 
   return hipGetLastError();
 }
 
-hipError_t launch_apply_t(int32_t nt, int32_t nrhs, const int32_t *tpos, const int32_t *perm, const int32_t *trp,
-                          const int32_t *tci, const double *tva, const double *b, int64_t ldb, double *bp,
-                          hipStream_t s) {
+hipError_t launch_apply_t(int32_t nt, int32_t nrhs, int32_t lanes, const int32_t *tpos, const int32_t *perm,
+                          const int32_t *trp, const int32_t *tcol, const double *tva, const double *b, int64_t ldb,
+                          double *bp, hipStream_t s) {
   if (nt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_apply_t, dim3(grid_for((int64_t)nt * nrhs, 256, 16384)), dim3(256), 0, s, nt, nrhs, tpos, perm,
-                     trp, tci, tva, b, ldb, bp);
+  const int64_t groups = nt;
+  switch (lanes) {
+    case 1:
+      hipLaunchKernelGGL(k_apply_t, dim3(grid_for((int64_t)nt * nrhs, 256, 16384)), dim3(256), 0, s, nt, nrhs, tpos,
+                         perm, trp, tcol, tva, b, ldb, bp);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_apply_t_group<4>, dim3(grid_for(groups * 4, 256, 16384)), dim3(256), 0, s, nt, nrhs, tpos,
+                         perm, trp, tcol, tva, b, ldb, bp);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_apply_t_group<16>, dim3(grid_for(groups * 16, 256, 16384)), dim3(256), 0, s, nt, nrhs,
+                         tpos, perm, trp, tcol, tva, b, ldb, bp);
+      break;
+    case 64:
+      hipLaunchKernelGGL(k_apply_t_group<64>, dim3(grid_for(groups * 64, 256, 16384)), dim3(256), 0, s, nt, nrhs,
+                         tpos, perm, trp, tcol, tva, b, ldb, bp);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -146,3 +146,32 @@ def test_rewrite_errors():
     with pytest.raises(sp.SptrsvError) as ei:
         h.rewrite(thin_metric=5)
     assert ei.value.name == "ARG"
+
+
+@pytest.mark.parametrize("w", [4, 8, 40, 130])
+def test_b_transform_row_lengths(w):
+    # Rows of T of every length class the b-transform distinguishes: on a chain
+    # under the W-row rule with no fill cap, a target takes W - 1 moved rows and
+    # T's rows hold 1 .. W - 1 off-diagonals (averages about 2, 4, 20 and 64,
+    # so a thread per row and 4-, 16- and 64-lane groups). Strided b and x, 1
+    # and 3 right-hand sides, n not a multiple of anything
+    m = gen.bidiagonal(2011, 7)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(0, w, 0.0, 0)
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, 0, w, 0.0, 0, None, lv)
+    assert st["nnz_T"] == int(rw.t_ptr[-1])
+    for k in (1, 3):
+        b = gen.rhs(m, k)
+        xr = oracle.solve(m, b)
+        bd = torch.zeros((k, m.n + 13), dtype=torch.float64, device="cuda")
+        bd[:, :m.n] = to_dev(b.reshape(k, m.n))
+        xd = torch.full((k, m.n + 5), float("nan"), dtype=torch.float64, device="cuda")
+        bb, xx = bd[:, :m.n], xd[:, :m.n]
+        if k == 1:
+            bb, xx = bb[0], xx[0]
+        h.solve(bb, sp.REWRITTEN, xx)
+        h.check()
+        assert oracle.relerr(xd[:, :m.n].cpu().numpy().reshape(k, m.n), xr.reshape(k, m.n)) <= TOL
+        assert torch.isnan(xd[:, m.n:]).all()  # nothing written past each column

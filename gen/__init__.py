@@ -11,6 +11,8 @@ from .matrices import (  # noqa: F401
     stencil3d_tail,
     powerlaw,
     policy_training_matrix,
+    lung2_like,
+    torso2_like,
     batch_window,
     rhs,
     from_dense_lower,

@@ -177,6 +177,89 @@ def powerlaw(n: int = 4_000_000, seed: int = 2, mean_deg: float = 8.0, w_loc: in
     return _assemble(n, rows, cols, rng, f"powerlaw_n{n}_s{seed}_w{w_loc}_g{nseg}")
 
 
+def _leveled(widths, extra, pick, rng, name) -> Csr:
+    """Rows grouped by level in natural order, level l holding widths[l] rows.
+    Every row of level l >= 1 reads one random row of level l-1 (so its
+    longest-path level is exactly l) plus extra(l, count) further rows drawn by
+    pick(l, count) from earlier levels; duplicates are merged."""
+    widths = np.asarray(widths, dtype=np.int64)
+    start = np.zeros(widths.size + 1, dtype=np.int64)
+    np.cumsum(widths, out=start[1:])
+    rs, cs = [], []
+    for lv in range(1, widths.size):
+        r = np.arange(start[lv], start[lv + 1])
+        rs.append(r)
+        cs.append(rng.integers(start[lv - 1], start[lv], size=r.size))
+        k = extra(lv, r.size)
+        if k.sum():
+            rs.append(np.repeat(r, k))
+            cs.append(pick(lv, int(k.sum())))
+    rows = np.concatenate(rs)
+    cols = np.concatenate(cs)
+    key = np.unique(rows * int(start[-1]) + cols)
+    return _assemble(int(start[-1]), key // int(start[-1]), key % int(start[-1]), rng, name)
+
+
+def lung2_like(seed: int = 0, fat_rows: int = 108_554, fat_levels: int = 26, two_row_levels: int = 453,
+               extra_mean: float = 2.646) -> Csr:
+    """Stand-in for SuiteSparse lung2 from its published statistics only
+    (Sec. IV, Table I: n = 109,460, nnz = 492,564, 479 levels of which 453
+    hold 2 rows): a fat head of ``fat_levels`` levels, each row reading one
+    row of the level before and Poisson(extra_mean) rows of the three levels
+    before, then ``two_row_levels`` levels of 2 rows, each row reading a row of
+    the level before and one row of the head."""
+    rng = np.random.default_rng(seed)
+    base, rem = divmod(fat_rows, fat_levels)
+    widths = [base + (1 if i < rem else 0) for i in range(fat_levels)] + [2] * two_row_levels
+    start = np.concatenate([[0], np.cumsum(widths)])
+
+    def extra(lv, cnt):
+        if lv < fat_levels:
+            return rng.poisson(extra_mean, size=cnt)
+        return np.ones(cnt, dtype=np.int64)
+
+    def pick(lv, cnt):
+        if lv < fat_levels:
+            return rng.integers(start[max(0, lv - 3)], start[lv], size=cnt)
+        return rng.integers(0, start[fat_levels], size=cnt)
+
+    return _leveled(widths, extra, pick, rng, f"lung2_like_s{seed}")
+
+
+def torso2_like(seed: int = 0, n: int = 115_967, nlev: int = 513, extra_mean: float = 7.8, spread: int = 2,
+                back: int = 8) -> Csr:
+    """Stand-in for SuiteSparse torso2 from its published statistics only
+    (Sec. IV, Table I: n = 115,967, nnz = 1,033,473, 513 levels, a triangular
+    profile of rows per level). torso2 is a mesh model, so coupling is local:
+    a row at relative position f of its level reads the row near f (within
+    +-``spread``) of the level before, plus Poisson(extra_mean) rows near f of
+    levels drawn uniformly from the ``back`` levels before."""
+    rng = np.random.default_rng(seed)
+    tri = np.minimum(np.arange(1, nlev + 1), np.arange(nlev, 0, -1)).astype(np.float64)
+    widths = np.maximum(1, np.floor(tri * (n / tri.sum()))).astype(np.int64)
+    widths[nlev // 2] += n - int(widths.sum())
+    start = np.concatenate([[0], np.cumsum(widths)])
+
+    def near(src, f):
+        pos = np.floor(f * widths[src]).astype(np.int64) + rng.integers(-spread, spread + 1, size=f.size)
+        return start[src] + np.clip(pos, 0, widths[src] - 1)
+
+    rs, cs = [], []
+    for lv in range(1, nlev):
+        w = int(widths[lv])
+        r = np.arange(start[lv], start[lv + 1])
+        f = (np.arange(w) + 0.5) / w
+        rs.append(r)
+        cs.append(near(np.full(w, lv - 1), f))  # fixes the row's level at lv
+        k = rng.poisson(extra_mean, size=w)
+        if k.sum():
+            src = lv - rng.integers(1, min(back, lv) + 1, size=int(k.sum()))
+            rs.append(np.repeat(r, k))
+            cs.append(near(src, np.repeat(f, k)))
+    key = np.unique(np.concatenate(rs) * n + np.concatenate(cs))
+    return _assemble(n, key // n, key % n, rng, f"torso2_like_s{seed}")
+
+
 def policy_training_matrix(seed: int) -> Csr:
     """One matrix of the learned policy's training or held-out set: power-law
     recipe with n ~ U[50k, 500k], local window ~ U{256..4096} and 0-16

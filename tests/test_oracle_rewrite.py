@@ -339,3 +339,69 @@ def test_planted_sign_error_is_caught(tmp_path):
         importlib.reload(oracle)
         oracle._lib, oracle._LIB_PATH = good_lib, good_path
     del C
+
+
+# ------------------------------------------------- strategies of Sec. III / IV
+def test_standin_generators_match_published_statistics():
+    # lung2 / torso2 stand-ins (Sec. IV, Table I): sizes, level counts and the
+    # share of 2-row levels are the published ones; nnz within 1 %
+    m = gen.lung2_like(0)
+    lv = oracle.levels(m)
+    w = np.diff(lv.level_ptr)
+    assert m.n == 109_460 and lv.nlev == 479 and int((w == 2).sum()) == 453
+    assert abs(m.nnz - 492_564) <= 0.01 * 492_564
+    m = gen.torso2_like(0)
+    lv = oracle.levels(m)
+    w = np.diff(lv.level_ptr)
+    assert m.n == 115_967 and lv.nlev == 513
+    assert abs(m.nnz - 1_033_473) <= 0.01 * 1_033_473
+    peak = int(np.argmax(w))
+    assert np.all(np.diff(w[:peak]) >= 0) and np.all(np.diff(w[peak + 1:]) <= 0)  # triangular profile
+
+
+def test_manual_preset_on_the_lung2_standin_closed_form():
+    # Sec. IV: the levels cheaper than avgLevelCost are grouped ten at a time,
+    # nine rewritten into the first. On the lung2 stand-in these are exactly
+    # the 453 two-row levels after the 26 fat ones, so the result has
+    # 26 + ceil(453 / 10) levels, 2 * (453 - 46) rows move, each by at most 9
+    # levels, and each moved row goes to the first level of its group of ten
+    m = gen.lung2_like(0)
+    lv = oracle.levels(m)
+    c = oracle.level_costs(m, lv)
+    thin = c.cost.astype(np.float64) < c.avg
+    thin[0] = False
+    assert np.array_equal(np.flatnonzero(thin), np.arange(26, 479))
+    rank = np.cumsum(thin) - 1
+    mask = (thin & (rank % 10 != 0)).astype(np.uint8)
+    rw = oracle.rewrite(m, THIN_COST, 1e300, 0.0, 9, mask=mask, lv=lv)
+    st = oracle.rewrite_stats(m, rw, lv)
+    assert st["nlev_after"] == 26 + 46 and st["rows_rewritten"] == 2 * (453 - 46) and st["max_distance"] == 9
+    lev = lv.row_level
+    moved = rw.target >= 0
+    assert np.array_equal(moved, mask[lev].astype(bool))
+    assert np.array_equal(rw.target[moved], 26 + 10 * ((lev[moved] - 26) // 10))
+
+
+def test_manual_distance_ten_preset_on_a_chain():
+    # the comparison approach of Sec. IV: every 9 levels go into the 10th. On a
+    # bidiagonal chain (one row per level) with no cost or fill limit, row r
+    # moves to level 10 * (r // 10) and L' keeps one dependency per moved row
+    n = 45
+    m = gen.bidiagonal(n, 5)
+    lv = oracle.levels(m)
+    mask = (np.arange(lv.nlev) % 10 != 0).astype(np.uint8)
+    rw = oracle.rewrite(m, THIN_COST, 1e300, 0.0, 9, mask=mask, lv=lv)
+    r = np.arange(n)
+    want = np.where(r % 10 == 0, -1, 10 * (r // 10))
+    assert np.array_equal(rw.target, want)
+    assert rw.max_distance == 9
+    lv2 = oracle.levels(rw.lp)
+    assert lv2.nlev == (n + 9) // 10
+    # every moved row now reads the row just before its group's target (or nothing in group 0)
+    for x in range(n):
+        cols = rw.lp_col[rw.lp_ptr[x]:rw.lp_ptr[x + 1] - 1].tolist()
+        if x % 10 == 0:
+            assert cols == ([x - 1] if x else [])
+        else:
+            g = 10 * (x // 10)
+            assert cols == ([g - 1] if g else [])

@@ -130,11 +130,73 @@ int32_t cut_windows(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs, int32_t
   }
   out.push_back(int4{ws, flags(), (int32_t)ents, 0});
   const int32_t nw = (int32_t)(out.size() - first);
-  out.push_back(int4{l1, 0, 0, 0});
+  out.push_back(int4{l1, -1, 0, 0});
   return nw;
 }
 
-sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc) {
+// Static images of every window in P.h_win (entries with y >= 0; the others
+// end a run): exact overflow counts replace the host bounds in .z, image
+// offsets (16-byte units) go to .w, and the table is uploaded.
+sptrsv_status_t build_images(sptrsv_ctx *h, Plan &P, hipStream_t s) {
+  const int32_t nent = (int32_t)P.h_win.size();
+  if (nent == 0 || P.n == 0) return SPTRSV_OK;
+  std::vector<int32_t> lvl_win((size_t)P.nlev, -1);
+  for (int32_t e = 0; e < nent; ++e) {
+    if (P.h_win[(size_t)e].y < 0) continue;
+    for (int32_t l = P.h_win[(size_t)e].x; l < P.h_win[(size_t)e + 1].x; ++l) lvl_win[(size_t)l] = e;
+  }
+  const int32_t n = P.n;
+  DArr<int32_t> d_lw;
+  DArr<long long> ocnt, oex, ecnt, eex, wpre;
+  HIPCHK(h, d_lw.alloc((size_t)P.nlev));
+  HIPCHK(h, ocnt.alloc(n));
+  HIPCHK(h, oex.alloc(n));
+  HIPCHK(h, ecnt.alloc(n));
+  HIPCHK(h, eex.alloc(n));
+  HIPCHK(h, wpre.alloc((size_t)nent));
+  if (P.win.n < (size_t)nent) HIPCHK(h, P.win.alloc((size_t)nent));
+  HIPCHK(h, hipMemcpyAsync(d_lw.p, lvl_win.data(), sizeof(int32_t) * (size_t)P.nlev, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(P.win.p, P.h_win.data(), sizeof(int4) * (size_t)nent, hipMemcpyHostToDevice, s));
+  HIPCHK(h, launch_img_count(n, P.level_ptr.p, P.nlev, d_lw.p, P.win.p, P.srp.p, P.sci.p, ocnt.p, ecnt.p, s));
+  const size_t scr = scan_scratch_elems(n) + 16;
+  if (h->scan_tmp.n < scr) HIPCHK(h, h->scan_tmp.alloc(scr));
+  HIPCHK(h, launch_scan_i64(ocnt.p, oex.p, n, h->scan_tmp.p, s));
+  HIPCHK(h, launch_scan_i64(ecnt.p, eex.p, n, h->scan_tmp.p, s));
+  int32_t *aux = h->d_aux.p;
+  HIPCHK(h, hipMemsetAsync(aux + 1, 0, sizeof(int32_t), s));
+  HIPCHK(h, P.ext_ptr.reserve((size_t)n + 1));
+  HIPCHK(h, launch_ptr_from_scan(eex.p, ecnt.p, n, P.ext_ptr.p, aux + 1, s));
+  HIPCHK(h, launch_win_prefix(nent, P.win.p, P.level_ptr.p, n, oex.p, ocnt.p, wpre.p, s));
+  std::vector<long long> hpre((size_t)nent);
+  int32_t next = 0, bits = 0;
+  HIPCHK(h, hipMemcpyAsync(hpre.data(), wpre.p, sizeof(long long) * (size_t)nent, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(&next, P.ext_ptr.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(&bits, aux + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (bits) return set_err(h, SPTRSV_ERR_OVERFLOW, "dependencies before LDS windows exceed int32 indexing");
+  int64_t units = 0;
+  for (int32_t e = 0; e < nent; ++e) {
+    int4 &W = P.h_win[(size_t)e];
+    if (W.y < 0) continue;
+    const long long no = hpre[(size_t)e + 1] - hpre[(size_t)e];
+    if (no > W.z)  // the host bound is an upper bound by construction
+      return set_err(h, SPTRSV_ERR_ARG, "window %d: %lld overflow records exceed the bound %d", e, no, W.z);
+    const int64_t R = P.h_level_ptr[(size_t)P.h_win[(size_t)e + 1].x] - P.h_level_ptr[(size_t)W.x];
+    W.z = (int32_t)no;
+    W.w = (int32_t)units;
+    units += window_image_units(R, no);
+    if (units >= ((int64_t)1 << 31)) return set_err(h, SPTRSV_ERR_OVERFLOW, "window images exceed int32 indexing");
+  }
+  HIPCHK(h, P.img.reserve((size_t)units));
+  HIPCHK(h, P.ext.reserve((size_t)next));
+  HIPCHK(h, hipMemcpyAsync(P.win.p, P.h_win.data(), sizeof(int4) * (size_t)nent, hipMemcpyHostToDevice, s));
+  HIPCHK(h, launch_img_fill(n, P.level_ptr.p, P.nlev, d_lw.p, P.win.p, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, oex.p,
+                            P.ext_ptr.p, P.img.p, P.ext.p, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc, hipStream_t s) {
   P.runs.clear();
   P.h_win.clear();
   const int64_t cap = thin_win_bytes();
@@ -155,10 +217,8 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
     r.wi = (int32_t)P.h_win.size();
     r.nw = cut_windows(P, r.l0, r.l1, nrhs, sc.wg_threads, P.h_win);
   }
-  if (!P.h_win.empty()) {
-    if (P.win.n < P.h_win.size()) HIPCHK(h, P.win.alloc(P.h_win.size()));
-    HIPCHK(h, hipMemcpy(P.win.p, P.h_win.data(), sizeof(int4) * P.h_win.size(), hipMemcpyHostToDevice));
-  }
+  P.runs_nrhs = -1;  // until the images are built
+  STCHK(build_images(h, P, s));
   P.runs_nrhs = nrhs;
   P.runs_sched = sc;
   return SPTRSV_OK;
@@ -332,7 +392,7 @@ static void prof_end(sptrsv_ctx *h, int slot, hipStream_t s) {
 }
 
 ThinArgs thin_args(const Plan &P) {
-  return ThinArgs{P.level_ptr.p, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, P.bp.p, P.xp.p};
+  return ThinArgs{P.level_ptr.p, P.sdg.p, P.img.p, P.ext_ptr.p, P.ext.p, P.bp.p, P.xp.p};
 }
 
 // The level-distance histogram of the dependencies that need overflow records
@@ -365,7 +425,7 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
   if (P.n == 0) return SPTRSV_OK;
   STCHK(ensure_work(h, P, nrhs));
   const sptrsv_schedule_t sc = effective_sched(P, nrhs);
-  if (P.runs_nrhs != nrhs || !same_sched(sc, P.runs_sched)) STCHK(make_runs(h, P, nrhs, sc));
+  if (P.runs_nrhs != nrhs || !same_sched(sc, P.runs_sched)) STCHK(make_runs(h, P, nrhs, sc, s));
   int *err = h->d_err.p;
   const double vec_bytes = 16.0 * (double)P.n * nrhs + 4.0 * P.n;
   int slot = prof_begin(h, 0, vec_bytes + (P.has_t ? 12.0 * (double)P.nnz_t_off + 4.0 * P.n : 0.0), s);
@@ -526,7 +586,6 @@ sptrsv_status_t sptrsv_level_stats(sptrsv_handle_t h, int which, int64_t *d_rows
 }
 
 sptrsv_status_t sptrsv_prepare(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s) {
-  (void)s;
   if (!h) return SPTRSV_ERR_ARG;
   Plan *P = plan_of(h, which);
   if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
@@ -534,7 +593,7 @@ sptrsv_status_t sptrsv_prepare(sptrsv_handle_t h, int which, int32_t nrhs, hipSt
   if (nrhs < 1) return set_err(h, SPTRSV_ERR_ARG, "nrhs=%d", nrhs);
   STCHK(ensure_work(h, *P, nrhs));
   const sptrsv_schedule_t sc = effective_sched(*P, nrhs);
-  STCHK(make_runs(h, *P, nrhs, sc));
+  STCHK(make_runs(h, *P, nrhs, sc, s));
   return SPTRSV_OK;
 }
 

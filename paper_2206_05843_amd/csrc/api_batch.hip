@@ -65,7 +65,7 @@ int bit_width64(int64_t v) {
 }
 
 // Per-matrix LDS windows for nrhs (cached).
-sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs, int32_t wg) {
+sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs, int32_t wg, hipStream_t s) {
   if (h->b_win_nrhs == nrhs && h->b_win_wg == wg) return SPTRSV_OK;
   Plan &P = h->bat;
   P.h_win.clear();
@@ -80,8 +80,8 @@ sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs, int32_t wg) {
     cut_windows(P, l0, l1, nrhs, wg, P.h_win);
   }
   h->b_h_mwin[(size_t)h->b_nmat] = (int32_t)P.h_win.size();
-  HIPCHK(h, P.win.alloc(std::max<size_t>(P.h_win.size(), 1)));
-  HIPCHK(h, hipMemcpy(P.win.p, P.h_win.data(), sizeof(int4) * P.h_win.size(), hipMemcpyHostToDevice));
+  h->b_win_nrhs = -1;  // until the images are built
+  STCHK(build_images(h, P, s));
   HIPCHK(h, h->b_mwin.alloc((size_t)h->b_nmat + 1));
   HIPCHK(h, hipMemcpy(h->b_mwin.p, h->b_h_mwin.data(), sizeof(int32_t) * ((size_t)h->b_nmat + 1),
                       hipMemcpyHostToDevice));
@@ -271,7 +271,7 @@ sptrsv_status_t sptrsv_batch_solve(sptrsv_handle_t h, int32_t nrhs, const double
   if (b0 < x0 + len && x0 < b0 + len) return set_err(h, SPTRSV_ERR_ARG, "b and x overlap");
   STCHK(ensure_work(h, P, nrhs));
   const int32_t wg = effective_sched(P, nrhs).wg_threads;
-  STCHK(batch_windows(h, nrhs, wg));
+  STCHK(batch_windows(h, nrhs, wg, s));
   HIPCHK(h, launch_batch_gather(P.n, nrhs, d_b_cat, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, P.bp.p, s));
   const int32_t grid = std::min(h->b_nmat, batch_resident_blocks(wg));
   HIPCHK(h, launch_batch_run(wg, h->b_nmat, grid, h->b_order.p, h->b_mwin.p, P.win.p, nrhs, thin_args(P), h->b_q.p,
@@ -288,7 +288,7 @@ sptrsv_status_t sptrsv_batch_solve_looped(sptrsv_handle_t h, int32_t nrhs, const
   Plan &P = h->bat;
   STCHK(ensure_work(h, P, nrhs));
   const int32_t wg = effective_sched(P, nrhs).wg_threads;
-  STCHK(batch_windows(h, nrhs, wg));
+  STCHK(batch_windows(h, nrhs, wg, s));
   HIPCHK(h, launch_batch_gather(P.n, nrhs, d_b_cat, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, P.bp.p, s));
   for (int32_t m = 0; m < h->b_nmat; ++m) {
     const int32_t wi = h->b_h_mwin[(size_t)m], nw = h->b_h_mwin[(size_t)m + 1] - wi - 1;

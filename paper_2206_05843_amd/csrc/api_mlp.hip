@@ -100,7 +100,7 @@ sptrsv_status_t sptrsv_level_times(sptrsv_handle_t h, int which, int32_t nrhs, c
   const float ns_per_tick = 1.0e6f / (float)(rate_khz > 0 ? rate_khz : 100000);
   STCHK(ensure_work(h, *P, nrhs));
   sptrsv_schedule_t sc{2, 0, 512, 256, 1};  // every level that fits runs in one workgroup
-  STCHK(make_runs(h, *P, nrhs, sc));
+  STCHK(make_runs(h, *P, nrhs, sc, s));
   HIPCHK(h, hipMemsetAsync(d_times, 0, sizeof(float) * (size_t)P->nlev, s));
   STCHK(gather_b(h, *P, nrhs, d_b, P->n, s));
   for (const Run &r : P->runs) {

@@ -61,6 +61,20 @@ struct DArr {
   }
 };
 
+// One in-window dependency beyond a row's two inline ones: weight scaled by
+// 1/diagonal and the slot (row of the window) it reads.
+struct __align__(16) Dep {
+  double w;
+  int32_t slot, pad;
+};
+
+// One dependency on a row before the row's LDS window: the unscaled weight and
+// the position whose final x it reads.
+struct __align__(16) ExtDep {
+  double w;
+  int32_t col, pad;
+};
+
 // One run of the solve schedule: a range of levels done inside one workgroup
 // (thin) or a single level spread over the device (wide).
 struct Run {
@@ -102,8 +116,13 @@ struct Plan {
   sptrsv_schedule_t sched{};           // knobs in force (mode 0 = automatic)
   std::map<int32_t, sptrsv_schedule_t> tuned;  // per nrhs
   std::vector<Run> runs;
-  std::vector<int4> h_win;             // LDS windows of all thin runs {first level, flags, overflow bound, 0}
+  // LDS windows of all thin runs {first level, flags, overflow records, image
+  // offset in 16-byte units}; each run's list ends with {end level, -1, 0, 0}
+  std::vector<int4> h_win;
   DArr<int4> win;
+  DArr<uint4> img;                     // static window images, back to back
+  DArr<int32_t> ext_ptr;               // [n+1] dependencies before the row's window (CSR over positions)
+  DArr<ExtDep> ext;
   int32_t runs_nrhs = -1;
   sptrsv_schedule_t runs_sched{};
   DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
@@ -211,9 +230,22 @@ hipError_t launch_level_stats(int32_t nlev, const int32_t *level_ptr, const int3
 // records and `nl` levels: per row the partial sum or x of every RHS (8 nrhs),
 // two inline weights (16) and packed slots/count/offset (8); one zero entry
 // per RHS that absent dependencies point to; 16 per overflow record; the level
-// bounds.
+// bounds; 16 for aligning the window's sections.
 __host__ __device__ inline int64_t thin_window_bytes(int64_t rows, int64_t ovf, int64_t nl, int32_t nrhs) {
-  return rows * (8 * (int64_t)nrhs + 24) + 8 * (int64_t)nrhs + ovf * 16 + 4 * (nl + 1);
+  return rows * (8 * (int64_t)nrhs + 24) + 8 * (int64_t)nrhs + ovf * 16 + 4 * (nl + 1) + 16;
+}
+
+// Inline record of a row: slots, in-window dependency count and first
+// overflow record, 16 bits each (a window holds far fewer than 65536 rows or
+// records).
+__host__ __device__ inline uint2 pack_rix(int32_t s0, int32_t s1, int32_t cnt, int32_t ob) {
+  return make_uint2((uint32_t)s0 | ((uint32_t)s1 << 16), (uint32_t)cnt | ((uint32_t)ob << 16));
+}
+
+// 16-byte units of a window's static image: weights (one unit per row),
+// overflow records (one each), packed records (two rows per unit).
+__host__ __device__ inline int64_t window_image_units(int64_t rows, int64_t ovf) {
+  return rows + ovf + ((rows + 1) >> 1);
 }
 
 // Level-distance buckets of the overflow-record histogram: lower bounds of
@@ -229,12 +261,15 @@ inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
   return (int)g;
 }
 
-// Device arrays a thin run reads (the level-ordered plan and work vectors).
+// Device arrays a thin run reads: level bounds, diagonal, the static window
+// images and each position's dependencies before its window (CSR), and the
+// work vectors.
 struct ThinArgs {
-  const int32_t *level_ptr, *srp, *sci;
-  const double *sva, *sdg;
-  const int4 *ell_c;
-  const double2 *ell_v;
+  const int32_t *level_ptr;
+  const double *sdg;
+  const uint4 *img;
+  const int32_t *ext_ptr;
+  const ExtDep *ext;
   const double *bp;
   double *xp;
 };
@@ -307,6 +342,19 @@ hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const
                             const double *va, const int32_t *lev, long long *sum_lp, long long *sum_t, int32_t *hist,
                             int32_t *redo, int32_t *nredo, char *big, int32_t bigC, int32_t bigH, int32_t big_blocks,
                             int *err, hipStream_t s);
+// Window images (k_image.hip) ------------------------------------------------------
+// Per position: overflow records and dependencies before its window (zero for
+// positions outside thin windows); lvl_win maps a level to its window in win
+// (-1: not in a thin run).
+hipError_t launch_img_count(int32_t n, const int32_t *level_ptr, int32_t nlev, const int32_t *lvl_win,
+                            const int4 *win, const int32_t *srp, const int32_t *sci, long long *ovf_cnt,
+                            long long *ext_cnt, hipStream_t s);
+// Per window-table entry e: the overflow prefix at the entry's first position.
+hipError_t launch_win_prefix(int32_t nent, const int4 *win, const int32_t *level_ptr, int32_t n,
+                             const long long *ovf_ex, const long long *ovf_cnt, long long *out, hipStream_t s);
+hipError_t launch_img_fill(int32_t n, const int32_t *level_ptr, int32_t nlev, const int32_t *lvl_win, const int4 *win,
+                           const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
+                           const long long *ovf_ex, const int32_t *ext_ptr, uint4 *img, ExtDep *ext, hipStream_t s);
 // Batched launchers (k_solve.hip) -------------------------------------------------
 hipError_t launch_batch_run(int wg, int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin,
                             const int4 *win, int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s);
@@ -323,7 +371,8 @@ sptrsv_schedule_t default_schedule();
 bool level_fits_window(const Plan &P, int32_t l, int32_t nrhs);
 int32_t cut_windows(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs, int32_t wg, std::vector<int4> &out);
 sptrsv_status_t build_extra_hist(sptrsv_ctx *h, Plan &P, hipStream_t s);
-sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc);
+sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc, hipStream_t s);
+sptrsv_status_t build_images(sptrsv_ctx *h, Plan &P, hipStream_t s);
 sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs);
 
 // Plan building (api.hip) --------------------------------------------------------

@@ -25,8 +25,8 @@ constexpr int kWinBytes = 150 * 1024;  // dynamic LDS of a thin-run workgroup
 // window layout starts after them.
 constexpr int kCtlBytes = 16;
 struct Ctl {
-  int32_t no;    // overflow records allocated in the current window
   int32_t next;  // batched launch: the workgroup's next queue ticket
+  int32_t pad[3];
 };
 
 // Workgroup barrier that orders LDS only: global stores may still be in flight
@@ -40,20 +40,16 @@ __device__ __forceinline__ void lds_barrier() {
 
 // A thin run is cut into LDS windows (consecutive levels, chosen on the host so
 // that the window's rows and dependency records fit in LDS). Per window:
-//  phase 1 (all rows in parallel): v = (b' - sum of L(pos,k) x(k)) / L(pos,pos)
-//    over the dependencies k that precede the window (final values, read from
-//    global memory); the dependencies inside the window, scaled by
-//    1/L(pos,pos), go to an inline record per row {w0, w1 | slot0, slot1,
-//    count, first overflow}; a row's third and later in-window dependencies go
-//    to an overflow list of {weight, slot} records (a row's records are
-//    contiguous, allocated from a window counter after the row has counted
-//    its in-window dependencies; the host bounds the window's total from a
-//    histogram of dependency level distances). Absent inline dependencies point to a zero
-//    entry with weight 0, so phase 2 needs no predication. A row's first four
-//    dependencies come from a fixed-width copy indexed by position (no row
-//    pointer on the load chain), and each thread takes several rows at once
-//    and issues all their loads before it uses any of them, so a window costs
-//    two memory round trips;
+//  phase 1 (all rows in parallel): the window's static image, built once per
+//    schedule, is streamed into LDS: per row an inline record {w0, w1 | slot0,
+//    slot1, count, first overflow} of its first two in-window dependencies
+//    (weights scaled by 1/L(pos,pos); absent ones point to a zero entry with
+//    weight 0, so phase 2 needs no predication) and a list of {weight, slot}
+//    records for its third and later ones. Meanwhile each thread loads, for
+//    several rows at once, b', the diagonal and the row's range of
+//    dependencies on earlier windows, then forms
+//    v = (b' - sum of L(pos,k) x(k)) / L(pos,pos) over those (final values,
+//    read from global memory, in the row's column order);
 //  phase 2 (level by level): x = v - sum over in-window dependencies of w x,
 //    in LDS only;
 //  then the window's x goes to global memory in one coalesced pass (where the
@@ -66,11 +62,6 @@ __device__ __forceinline__ void lds_barrier() {
 // win[i] = {first level, flags}; the run's last entry holds the end level.
 // kTimed (used only to label levels for the learned policy): thread 0 stamps the
 // device wall clock around every level and writes per-level times (ns).
-struct __align__(16) Dep {
-  double w;
-  int32_t slot, pad;
-};
-
 constexpr int kBatch = 4;
 
 // acc - sum_j w_j x(slot_j, c) over n overflow records starting at d, in order,
@@ -95,13 +86,6 @@ __device__ __forceinline__ double ovf_sum(double acc, const Dep *__restrict__ d,
     for (int j = 0; j < kBatch; ++j) acc = j < cnt ? acc - w[j] * xv[j] : acc;
   }
   return acc;
-}
-
-// Inline record of a row: slots, in-window dependency count and first
-// overflow record, 16 bits each (a window holds far fewer than 65536 rows or
-// records).
-__device__ __forceinline__ uint2 pack_rix(int32_t s0, int32_t s1, int32_t cnt, int32_t ob) {
-  return make_uint2((uint32_t)s0 | ((uint32_t)s1 << 16), (uint32_t)cnt | ((uint32_t)ob << 16));
 }
 
 // The static inputs of one (row, rhs) item in phase 2.
@@ -140,16 +124,15 @@ __device__ __forceinline__ double solve_item(const Item &it, int32_t nr, const d
   return acc;
 }
 
-// Phase 1: items per thread whose loads are in flight together (fewer at 1024
-// threads, where a thread has 128 registers).
+// Phase 1: (row, rhs) items per thread whose loads are in flight together,
+// and 16-byte image units per thread per copy round.
 template <int WG, bool kOne>
 constexpr int p1_items() {
-  return WG >= 1024 ? (kOne ? 3 : 2) : 6;
+  return WG >= 1024 ? 5 : WG >= 512 ? 6 : 8;
 }
-// ... and dependencies per batch beyond a row's first four.
-template <int WG, bool kOne>
-constexpr int p1_tail() {
-  return WG >= 1024 && kOne ? 2 : 4;
+template <int WG>
+constexpr int p1_copy() {
+  return WG >= 1024 ? 8 : 12;
 }
 
 // The windows [win, win + nwin) of one thin run, by the calling workgroup.
@@ -157,142 +140,96 @@ constexpr int p1_tail() {
 template <int WG, bool kOne, bool kTimed>
 __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restrict__ win, int32_t nwin, int32_t nrhs,
                                              const ThinArgs &A, float *times, float ns_per_tick) {
-  int32_t &s_no = reinterpret_cast<Ctl *>(lds_raw)->no;
   double *lds = reinterpret_cast<double *>(lds_raw + kCtlBytes);
   const int32_t nr = kOne ? 1 : nrhs;
   const int tid = threadIdx.x;
   const int32_t *__restrict__ level_ptr = A.level_ptr;
-  const int32_t *__restrict__ srp = A.srp;
-  const int32_t *__restrict__ sci = A.sci;
-  const double *__restrict__ sva = A.sva;
   const double *__restrict__ sdg = A.sdg;
-  const int4 *__restrict__ ell_c = A.ell_c;
-  const double2 *__restrict__ ell_v = A.ell_v;
+  const int32_t *__restrict__ ext_ptr = A.ext_ptr;
+  const ExtDep *__restrict__ ext = A.ext;
   const double *__restrict__ bp = A.bp;
   double *xp = A.xp;
   int bits = 0;
   unsigned long long t_w0 = 0, t_prev = 0;
   float p1_per_row = 0.f;
-  if (tid == 0) s_no = 0;
-  __syncthreads();
   for (int32_t w = 0; w < nwin; ++w) {
     if (kTimed && tid == 0) t_w0 = wall_clock64();
-    const int32_t lA = win[w].x, lB = win[w + 1].x, flags = win[w].y;
+    const int4 W = win[w];
+    const int32_t lA = W.x, lB = win[w + 1].x, flags = W.y;
     const int32_t P0 = level_ptr[lA], P1 = level_ptr[lB];
     const int32_t R = P1 - P0;
-    const int32_t NO = win[w].z;  // bound on the window's overflow records
+    const int32_t NO = W.z;  // the window's overflow records
     const int32_t NL = lB - lA;
     // the host sizes windows to fit, and 16-bit slots and offsets must hold R and NO
     if (thin_window_bytes(R, NO, NL, nr) > kWinBytes - kCtlBytes || R >= 65536 || NO >= 65536) return bits | EB_ARG;
     double2 *rw = reinterpret_cast<double2 *>(lds);          // [R] w0, w1 (scaled by 1/diagonal)
     Dep *ovf = reinterpret_cast<Dep *>(rw + R);               // [NO] third and later dependencies
-    uint2 *rix = reinterpret_cast<uint2 *>(ovf + NO);         // [R] slot0, slot1, count, overflow
-    double *v = reinterpret_cast<double *>(rix + R);          // [(R + 1) * nr] partial sums, then x; zero row R
+    uint2 *rix = reinterpret_cast<uint2 *>(ovf + NO);         // [R, padded to even] slot0, slot1, count, overflow
+    double *v = reinterpret_cast<double *>(rix + ((R + 1) & ~1));  // [(R + 1) * nr] partial sums, then x; zero row R
     int32_t *lv = reinterpret_cast<int32_t *>(v + (int64_t)(R + 1) * nr);  // [NL + 1] level bounds from P0
-    for (int32_t i = tid; i <= NL; i += WG) lv[i] = level_ptr[lA + i] - P0;
-    for (int32_t i = tid; i < nr; i += WG) v[(int64_t)R * nr + i] = 0.0;
-    // phase 1
+    // phase 1. Each thread requests its items' right-hand side, diagonal and
+    // range of dependencies before the window; in the first round it streams
+    // the window's static image into LDS while those are in flight; then it
+    // subtracts the dependencies before the window (in the row's column order).
     const int32_t nitems = R * nr;
-    constexpr int kP1Items = p1_items<WG, kOne>();
-    for (int32_t base = 0; base < nitems; base += WG * kP1Items) {
-      int32_t sj[kP1Items], cj[kP1Items], qb[kP1Items], deg[kP1Items];
-      int4 ec[kP1Items];
-      double2 ev0[kP1Items], ev1[kP1Items];
-      double acc[kP1Items], dgv[kP1Items];
+    constexpr int kI = p1_items<WG, kOne>();
+    for (int32_t base = 0; base < nitems; base += WG * kI) {
+      double acc[kI], dg[kI];
+      int32_t e0[kI], e1[kI];
 #pragma unroll
-      for (int j = 0; j < kP1Items; ++j) {
+      for (int j = 0; j < kI; ++j) {
         const int32_t it = base + j * WG + tid;
         const int32_t itc = it < nitems ? it : nitems - 1;
-        sj[j] = kOne ? itc : itc / nr;
-        cj[j] = kOne ? 0 : itc - sj[j] * nr;
-        const int32_t pos = P0 + sj[j];
-        qb[j] = srp[pos];
-        deg[j] = it < nitems ? srp[pos + 1] - qb[j] : 0;
-        ec[j] = ell_c[pos];
-        ev0[j] = ell_v[2 * (int64_t)pos];
-        ev1[j] = ell_v[2 * (int64_t)pos + 1];
-        acc[j] = bp[(int64_t)pos * nr + cj[j]];
-        dgv[j] = sdg[pos];
+        const int32_t sj = kOne ? itc : itc / nr;
+        const int32_t pos = P0 + sj;
+        acc[j] = bp[(int64_t)pos * nr + (kOne ? 0 : itc - sj * nr)];
+        dg[j] = sdg[pos];
+        e0[j] = ext_ptr[pos];
+        e1[j] = it < nitems ? ext_ptr[pos + 1] : e0[j];
       }
-      double xv[kP1Items][4];
+      if (base == 0) {
+        for (int32_t i = tid; i <= NL; i += WG) lv[i] = level_ptr[lA + i] - P0;
+        for (int32_t i = tid; i < nr; i += WG) v[(int64_t)R * nr + i] = 0.0;
+        const uint4 *__restrict__ im = A.img + W.w;
+        uint4 *dst = reinterpret_cast<uint4 *>(lds);
+        const int32_t nu = (int32_t)window_image_units(R, NO);
+        constexpr int kC = p1_copy<WG>();
+        for (int32_t u0 = 0; u0 < nu; u0 += WG * kC) {
+          uint4 t[kC];
 #pragma unroll
-      for (int j = 0; j < kP1Items; ++j) {
-        const int32_t kk[4] = {ec[j].x, ec[j].y, ec[j].z, ec[j].w};
+          for (int j = 0; j < kC; ++j) {
+            const int32_t u = u0 + j * WG + tid;
+            t[j] = im[u < nu ? u : nu - 1];
+          }
 #pragma unroll
-        for (int d = 0; d < 4; ++d)
-          xv[j][d] = (d < deg[j] && kk[d] < P0) ? xp[(int64_t)kk[d] * nr + cj[j]] : 0.0;
+          for (int j = 0; j < kC; ++j) {
+            const int32_t u = u0 + j * WG + tid;
+            if (u < nu) dst[u] = t[j];
+          }
+        }
       }
 #pragma unroll
-      for (int j = 0; j < kP1Items; ++j) {
+      for (int j = 0; j < kI; ++j) {
         const int32_t it = base + j * WG + tid;
         if (it >= nitems) continue;
-        const int32_t c = cj[j];
-        const double dinv = 1.0 / dgv[j];
-        const int32_t kk[4] = {ec[j].x, ec[j].y, ec[j].z, ec[j].w};
-        // the row's overflow records: count its in-window dependencies first
-        int32_t ob = 0;
-        if (c == 0) {
-          int32_t cnt = 0;
+        const int32_t c = kOne ? 0 : it - (it / nr) * nr;
+        double a = acc[j];
+        for (int32_t e = e0[j]; e < e1[j]; e += kBatch) {
+          double wv[kBatch], xv[kBatch];
+          int32_t k[kBatch];
 #pragma unroll
-          for (int d = 0; d < 4; ++d) cnt += (d < deg[j] && kk[d] >= P0) ? 1 : 0;
-          for (int32_t q = qb[j] + 4; q < qb[j] + deg[j]; ++q) cnt += sci[q] >= P0 ? 1 : 0;
-          if (cnt > 2) {
-            ob = atomicAdd(&s_no, cnt - 2);
-            if (ob + cnt - 2 > NO) {  // never with the host's bound; keeps every access in LDS
-              bits |= EB_ARG;
-              ob = -1;
-            }
-          }
-        }
-        int32_t kin = 0, s0 = R, s1 = R;
-        double w0 = 0.0, w1 = 0.0, a = acc[j];
-        auto take = [&](int32_t k, double wv, double x) {
-          if (k < P0) {
-            a -= wv * x;
-          } else {
-            if (kin == 0) {
-              s0 = k - P0;
-              w0 = wv * dinv;
-            } else if (kin == 1) {
-              s1 = k - P0;
-              w1 = wv * dinv;
-            } else if (c == 0 && ob >= 0) {
-              Dep dd;
-              dd.w = wv * dinv;
-              dd.slot = k - P0;
-              dd.pad = 0;
-              ovf[ob + kin - 2] = dd;
-            }
-            ++kin;
-          }
-        };
-        const double vv[4] = {ev0[j].x, ev0[j].y, ev1[j].x, ev1[j].y};
-#pragma unroll
-        for (int d = 0; d < 4; ++d)
-          if (d < deg[j]) take(kk[d], vv[d], xv[j][d]);
-        // dependencies beyond the fixed-width copy: kTail at a time, loads first
-        constexpr int kTail = p1_tail<WG, kOne>();
-        for (int32_t q0 = qb[j] + 4; q0 < qb[j] + deg[j]; q0 += kTail) {
-          const int32_t qe = qb[j] + deg[j];
-          int32_t k4[kTail];
-          double w4[kTail], x4[kTail];
-#pragma unroll
-          for (int d = 0; d < kTail; ++d) {
-            k4[d] = q0 + d < qe ? sci[q0 + d] : -1;
-            w4[d] = q0 + d < qe ? sva[q0 + d] : 0.0;
+          for (int d = 0; d < kBatch; ++d) {
+            const ExtDep x = ext[e + d < e1[j] ? e + d : e];
+            wv[d] = x.w;
+            k[d] = x.col;
           }
 #pragma unroll
-          for (int d = 0; d < kTail; ++d)
-            x4[d] = (k4[d] >= 0 && k4[d] < P0) ? xp[(int64_t)k4[d] * nr + c] : 0.0;
+          for (int d = 0; d < kBatch; ++d) xv[d] = xp[(int64_t)k[d] * nr + c];
 #pragma unroll
-          for (int d = 0; d < kTail; ++d)
-            if (k4[d] >= 0) take(k4[d], w4[d], x4[d]);
+          for (int d = 0; d < kBatch; ++d)
+            if (e + d < e1[j]) a -= wv[d] * xv[d];
         }
-        v[(int64_t)sj[j] * nr + c] = a * dinv;
-        if (c == 0) {
-          rw[sj[j]] = make_double2(w0, w1);
-          rix[sj[j]] = ob >= 0 ? pack_rix(s0, s1, kin, ob) : pack_rix(s0, s1, kin < 2 ? kin : 2, 0);
-        }
+        v[(int64_t)it] = a * (1.0 / dg[j]);
       }
     }
     __syncthreads();
@@ -360,7 +297,6 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
       if (!isfinite(x)) bits |= EB_NONFINITE;
       xw[i] = x;
     }
-    if (tid == 0) s_no = 0;
     __syncthreads();  // the window's global x is complete before the next phase 1 reads it
   }
   return bits;

@@ -305,6 +305,8 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   HIPCHK(h, launch_fill_ell(n, P.srp.p, P.sci.p, P.sva.p, P.ell_c.p, P.ell_v.p, s));
   HIPCHK(h, P.wbar.alloc(2));
   HIPCHK(h, hipMemsetAsync(P.wbar.p, 0, 2 * sizeof(unsigned), s));
+  HIPCHK(h, P.tp.alloc(4));
+  HIPCHK(h, hipMemsetAsync(P.tp.p, 0, 4 * sizeof(unsigned), s));
   if (trp) {
     P.has_t = true;
     HIPCHK(h, P.trp.alloc((size_t)n + 1));
@@ -392,7 +394,7 @@ static void prof_end(sptrsv_ctx *h, int slot, hipStream_t s) {
 }
 
 ThinArgs thin_args(const Plan &P) {
-  return ThinArgs{P.level_ptr.p, P.sdg.p, P.img.p, P.ext_ptr.p, P.ext.p, P.bp.p, P.xp.p};
+  return ThinArgs{P.level_ptr.p, P.sdg.p, P.img.p, P.ext_ptr.p, P.ext.p, P.bp.p, P.xp.p, P.tp.p};
 }
 
 // The level-distance histogram of the dependencies that need overflow records

@@ -126,6 +126,7 @@ struct Plan {
   int32_t runs_nrhs = -1;
   sptrsv_schedule_t runs_sched{};
   DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
+  DArr<unsigned> tp;                   // [4] thin-run launches: epoch, progress, helper sink
   DArr<unsigned> wbar;                 // [2] barrier counters of persistent wide runs (zero between launches)
   int32_t work_nrhs = 0;
 };
@@ -272,6 +273,7 @@ struct ThinArgs {
   const ExtDep *ext;
   const double *bp;
   double *xp;
+  unsigned *tp;  // pacing words of the L2 prefetch helpers of a single-run launch (null: no helpers)
 };
 
 // Launchers (k_solve.hip) ------------------------------------------------------

@@ -139,7 +139,8 @@ constexpr int p1_copy() {
 // Returns the latched error bits; a window that does not fit aborts the run.
 template <int WG, bool kOne, bool kTimed>
 __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restrict__ win, int32_t nwin, int32_t nrhs,
-                                             const ThinArgs &A, float *times, float ns_per_tick) {
+                                             const ThinArgs &A, float *times, float ns_per_tick,
+                                             unsigned *prog = nullptr, unsigned ptag = 0) {
   double *lds = reinterpret_cast<double *>(lds_raw + kCtlBytes);
   const int32_t nr = kOne ? 1 : nrhs;
   const int tid = threadIdx.x;
@@ -153,6 +154,7 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
   unsigned long long t_w0 = 0, t_prev = 0;
   float p1_per_row = 0.f;
   for (int32_t w = 0; w < nwin; ++w) {
+    if (prog && tid == 0) __hip_atomic_store(prog, ptag | (unsigned)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (kTimed && tid == 0) t_w0 = wall_clock64();
     const int4 W = win[w];
     const int32_t lA = W.x, lB = win[w + 1].x, flags = W.y;
@@ -302,12 +304,89 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
   return bits;
 }
 
+// L2 prefetch helpers of a single thin run. One workgroup solves; a few more
+// workgroups on the same XCD (workgroups are dispatched to the 8 XCDs in turn,
+// so workgroup 8 h shares workgroup 0's L2) touch one word of every cache line
+// of the next windows' images, b', diagonals and outside-dependency lists, so
+// the solver's phase 1 finds them in L2. They keep at most kAhead windows ahead
+// of the solver, which publishes (epoch tag | window) in tp[1] as it starts
+// each window and advances the epoch tp[0] when it ends; launches on a stream
+// do not overlap, so the epoch read at the start names this launch. The solver
+// never waits for a helper; a helper stops when the epoch moves on, when it
+// has done its windows, or when one wait exceeds kWaitTicks of the device
+// wall clock, so every helper finishes.
+constexpr int kXcd = 8;
+constexpr int kHelp = 4;            // helpers per launch
+constexpr int kAhead = 4;           // windows a helper may run ahead of the solver
+constexpr int kHelpMinWin = 8;      // runs with fewer windows launch no helpers
+constexpr unsigned long long kWaitTicks = 5000;  // 50 us at the 100 MHz wall clock
+constexpr int kTagShift = 20;       // progress word: (epoch mod 2^12) << 20 | window
+
+__device__ __forceinline__ unsigned epoch_tag(unsigned ep) { return (ep & 0xfffu) << kTagShift; }
+
+template <int WG>
+__device__ void prefetch_windows(char *lds_raw, const int4 *__restrict__ win, int32_t nwin, int32_t nrhs,
+                                 const ThinArgs &A, int hh) {
+  int32_t &s_go = reinterpret_cast<Ctl *>(lds_raw)->next;
+  unsigned *tp = A.tp;
+  const int tid = threadIdx.x;
+  const unsigned ep = __hip_atomic_load(tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned sink = 0;
+  for (int32_t j = hh; j < nwin; j += kHelp) {
+    if (tid == 0) {
+      int go = 1;
+      const unsigned long long t0 = wall_clock64();
+      for (;;) {
+        if (__hip_atomic_load(tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != ep) {
+          go = 0;  // the solver has finished
+          break;
+        }
+        const unsigned p = __hip_atomic_load(tp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t at = (p >> kTagShift) == (ep & 0xfffu) ? (int32_t)(p & ((1u << kTagShift) - 1)) : 0;
+        if (j <= at + kAhead) break;
+        if (wall_clock64() - t0 > kWaitTicks) {
+          go = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) break;
+    const int4 W = win[j];
+    const int32_t P0 = A.level_ptr[W.x], P1 = A.level_ptr[win[j + 1].x], R = P1 - P0;
+    const int32_t nu = (int32_t)window_image_units(R, W.z);
+    const uint4 *im = A.img + W.w;
+    for (int32_t u = tid * 8; u < nu; u += WG * 8) sink ^= im[u].x;
+    const double *bw = A.bp + (int64_t)P0 * nrhs;
+    for (int32_t u = tid * 16; u < R * nrhs; u += WG * 16) sink ^= (unsigned)__double_as_longlong(bw[u]);
+    for (int32_t u = tid * 16; u < R; u += WG * 16) sink ^= (unsigned)__double_as_longlong(A.sdg[P0 + u]);
+    for (int32_t u = tid * 32; u <= R; u += WG * 32) sink ^= (unsigned)A.ext_ptr[P0 + u];
+    const int32_t e0 = A.ext_ptr[P0], e1 = A.ext_ptr[P1];
+    for (int32_t e = e0 + tid * 8; e < e1; e += WG * 8) sink ^= (unsigned)A.ext[e].col;
+    __syncthreads();  // s_go is rewritten only after every thread has read it
+  }
+  if (sink == 0x9e3779b9u) tp[2] = sink;  // keeps the loads; the value is never read
+}
+
 template <int WG, bool kOne, bool kTimed = false>
 __global__ __launch_bounds__(WG) void k_thin_run(const int4 *__restrict__ win, int32_t nwin, int32_t nrhs, ThinArgs A,
                                                  int *err, float *times, float ns_per_tick) {
   extern __shared__ __align__(16) char lds_raw[];
-  const int bits = thin_run_body<WG, kOne, kTimed>(lds_raw, win, nwin, nrhs, A, times, ns_per_tick);
-  if (bits) atomicOr(err, bits);
+  if (blockIdx.x != 0) {  // helpers exist only when the launcher gave the grid room for them
+    if (blockIdx.x % kXcd == 0) prefetch_windows<WG>(lds_raw, win, nwin, nrhs, A, (int)(blockIdx.x / kXcd) - 1);
+    return;
+  }
+  unsigned ep = 0;
+  if (A.tp) ep = __hip_atomic_load(A.tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int bits =
+      thin_run_body<WG, kOne, kTimed>(lds_raw, win, nwin, nrhs, A, times, ns_per_tick, A.tp ? A.tp + 1 : nullptr,
+                                      epoch_tag(ep));
+  if (threadIdx.x == 0) {
+    if (bits) atomicOr(err, bits);
+    if (A.tp) __hip_atomic_store(A.tp, ep + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // A row's first four off-diagonals (column position, value), -1 / 0 padded.
@@ -387,21 +466,24 @@ void solve_kernels_init() {
 hipError_t launch_thin_run(int wg, const int4 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
                            hipStream_t s, float *times, float ns_per_tick) {
   const bool one = nrhs == 1;
+  // the solver, plus kHelp prefetch helpers on its XCD for runs long enough to
+  // use them (windows are numbered below 2^20 in the progress word)
+  const unsigned grid = a.tp && nwin >= kHelpMinWin && nwin < (1 << kTagShift) ? 1 + kXcd * kHelp : 1;
   if (times) {  // labelling runs only: 512 threads
     if (one)
-      hipLaunchKernelGGL((k_thin_run<512, true, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, nrhs, a, err,
+      hipLaunchKernelGGL((k_thin_run<512, true, true>), dim3(grid), dim3(512), kWinBytes, s, win, nwin, nrhs, a, err,
                          times, ns_per_tick);
     else
-      hipLaunchKernelGGL((k_thin_run<512, false, true>), dim3(1), dim3(512), kWinBytes, s, win, nwin, nrhs, a, err,
+      hipLaunchKernelGGL((k_thin_run<512, false, true>), dim3(grid), dim3(512), kWinBytes, s, win, nwin, nrhs, a, err,
                          times, ns_per_tick);
     return hipGetLastError();
   }
 #define THIN(W)                                                                                              \
   if (one)                                                                                                   \
-    hipLaunchKernelGGL((k_thin_run<W, true>), dim3(1), dim3(W), kWinBytes, s, win, nwin, nrhs, a, err,       \
+    hipLaunchKernelGGL((k_thin_run<W, true>), dim3(grid), dim3(W), kWinBytes, s, win, nwin, nrhs, a, err,       \
                        (float *)nullptr, 0.f);                                                               \
   else                                                                                                       \
-    hipLaunchKernelGGL((k_thin_run<W, false>), dim3(1), dim3(W), kWinBytes, s, win, nwin, nrhs, a, err,      \
+    hipLaunchKernelGGL((k_thin_run<W, false>), dim3(grid), dim3(W), kWinBytes, s, win, nwin, nrhs, a, err,      \
                        (float *)nullptr, 0.f);
   if (wg == 256) {
     THIN(256)

@@ -81,6 +81,38 @@ def test_solve_parity(handles, name, si, nrhs):
     h.set_schedule()
 
 
+def _band(n, k, seed):
+    # every row reads the k rows before it: one row per level, min(r, k)
+    # in-window dependencies
+    rng = np.random.default_rng(seed)
+    a = np.zeros((n, n))
+    for i in range(n):
+        lo = max(0, i - k)
+        a[i, lo:i] = rng.uniform(-1.0, 1.0, i - lo)
+        a[i, i] = 1.0 + np.abs(a[i, lo:i]).sum()
+    return gen.from_dense_lower(a, f"band{k}_n{n}")
+
+
+@pytest.mark.parametrize("k", [3, 6, 12, 24, 40])
+@pytest.mark.parametrize("nrhs", [1, 3, 5])
+@pytest.mark.parametrize("wg", [256, 1024])
+def test_band_chain_parity(k, nrhs, wg):
+    # one row per level with up to k in-window dependencies: the overflow
+    # records of one-wave windows in several batches, 1 to 5 items per level
+    m = _band(301, k, k + 7 * nrhs)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    h.set_schedule(sp.ORIGINAL, mode=2, wg_threads=wg)
+    b = gen.rhs(m, nrhs)
+    xr = oracle.solve(m, b)
+    bd = to_dev(b)
+    x = h.solve(bd if nrhs > 1 else bd.view(-1))
+    h.check()
+    assert oracle.relerr(x.view(nrhs, -1).cpu().numpy(), xr) <= TOL
+    x2 = h.solve(bd if nrhs > 1 else bd.view(-1))
+    assert torch.equal(x, x2)
+
+
 def test_solve_deterministic(handles):
     m, h, _ = handles["cfg2_small"]
     b = to_dev(gen.rhs(m, 2))

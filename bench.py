@@ -57,14 +57,16 @@ def alg_bytes(n, nnz, nlev, nrhs, nnz_t=0, rewritten=False):
     return 12.0 * (nnz + nnz_t) + 12.0 * n + 4.0 * (nlev + 1) + 16.0 * n * nrhs
 
 
-KERNEL_SOURCE = {"k_thin_run": "k_thin.hip", "k_batch_run": "k_thin.hip", "k_wide_level": "k_wide.hip",
-                 "k_gather": "k_vec.hip", "k_scatter": "k_vec.hip"}
+# Sources whose text decides what a kernel reads and writes (thin runs read
+# the window images k_image.hip builds).
+KERNEL_SOURCE = {"k_thin_run": ("k_thin.hip", "k_image.hip"), "k_batch_run": ("k_thin.hip", "k_image.hip"),
+                 "k_wide_level": ("k_wide.hip",), "k_gather": ("k_vec.hip",), "k_scatter": ("k_vec.hip",)}
 
 
 def source_hash(kernel):
-    """Hash of the source file of a kernel together with the shared header."""
+    """Hash of the source files of a kernel together with the shared header."""
     h = hashlib.sha256()
-    for name in (KERNEL_SOURCE[kernel], "common.h"):
+    for name in KERNEL_SOURCE[kernel] + ("common.h",):
         with open(os.path.join(ROOT, "paper_2206_05843_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

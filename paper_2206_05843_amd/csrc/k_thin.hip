@@ -19,7 +19,7 @@
 
 namespace {
 
-constexpr int kWinBytes = 150 * 1024;  // dynamic LDS of a thin-run workgroup
+constexpr int kWinBytes = 159 * 1024;  // dynamic LDS of a thin-run workgroup (of the CU's 160 KB)
 // Its first 16 bytes hold control words (no static LDS in these kernels: it
 // would offset the dynamic region and misalign its 16-byte records); the
 // window layout starts after them.

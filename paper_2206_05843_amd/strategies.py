@@ -114,6 +114,17 @@ def report(matrices, reps: int = 20):
     return out
 
 
+def profile(costs, bins: int = 16):
+    """Per-level costs in the manner of Figs. 5 and 6: the levels cut into
+    `bins` consecutive groups of (nearly) equal size, each group's mean and
+    largest level cost, and the largest level cost overall."""
+    c = np.asarray(costs, dtype=np.float64)
+    edges = np.linspace(0, c.size, min(bins, c.size) + 1).astype(int)
+    return {"mean": [float(c[a:b].mean()) for a, b in zip(edges[:-1], edges[1:])],
+            "max": [float(c[a:b].max()) for a, b in zip(edges[:-1], edges[1:])],
+            "peak": float(c.max()), "levels_over_avg": int((c > c.mean()).sum())}
+
+
 def markdown(rows) -> str:
     lines = ["| matrix | strategy | levels | avg level cost | total level cost | rows rewritten | nnz(L') | nnz(T) | "
              "max distance | solve ms |", "|---|---|---|---|---|---|---|---|---|---|"]
@@ -121,6 +132,13 @@ def markdown(rows) -> str:
         lines.append(f"| {r['matrix']} | {r['strategy']} | {r['levels']} | {r['avg_level_cost']:.1f} | "
                      f"{r['total_cost']} | {r['rows_rewritten']} | {r['nnz_Lp']} | {r['nnz_T']} | "
                      f"{r['max_distance']} | {r['solve_ms']:.3f} |")
+    lines += ["", "Per-level cost profile (as in Figs. 5 and 6): the levels in 16 consecutive groups, each group's mean "
+              "level cost, then the largest level cost and the number of levels above the average.", "",
+              "| matrix | strategy | mean cost per group of levels | largest | levels > avg |", "|---|---|---|---|---|"]
+    for r in rows:
+        pr = profile(r["level_costs"])
+        lines.append(f"| {r['matrix']} | {r['strategy']} | {' '.join(f'{v:.0f}' for v in pr['mean'])} | "
+                     f"{pr['peak']:.0f} | {pr['levels_over_avg']} |")
     return "\n".join(lines) + "\n"
 
 

@@ -67,6 +67,12 @@ def _load():
     lib.orc_rewrite.argtypes = [C.c_int32, i32p, i32p, f64p, C.c_int32, i32p, i32p, i32p, C.c_int32,
                                 C.c_double, C.c_double, C.c_int32, C.c_void_p, i32p, C.POINTER(C.c_int32)]
     lib.orc_rewrite.restype = C.c_void_p
+    lib.orc_rewrite_rc.argtypes = [C.c_int32, i32p, i32p, f64p, C.c_int32, i32p, i32p, i32p, C.c_int32,
+                                   C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32, C.c_int64, C.c_int32,
+                                   i32p, C.POINTER(C.c_int32)]
+    lib.orc_rewrite_rc.restype = C.c_void_p
+    lib.orc_rewrite_skipped.argtypes = [C.c_void_p]
+    lib.orc_rewrite_skipped.restype = C.c_int32
     lib.orc_rewrite_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.orc_rewrite_sizes.restype = None
@@ -157,6 +163,7 @@ class Rewrite:
     rows_rewritten: int
     max_distance: int
     steps: int
+    rows_skipped: int = 0   # rows a row constraint left in place
 
     @property
     def lp(self):
@@ -173,7 +180,11 @@ THIN_ROWS, THIN_COST = 0, 1
 
 
 def rewrite(m, thin_metric: int = THIN_ROWS, thin_threshold: float = 32.0, fill_cap: float = 0.0,
-            max_distance: int = 0, mask: np.ndarray | None = None, lv: Levels | None = None) -> Rewrite:
+            max_distance: int = 0, mask: np.ndarray | None = None, lv: Levels | None = None, max_indegree: int = 0,
+            max_spread: int = 0, critical_only: bool = False) -> Rewrite:
+    """The scan and rewriting of Sec. II.B / Sec. III (oracle.c O5), with the
+    row constraints of Sec. III.A: max_indegree (alpha), max_spread (beta) and
+    critical_only; 0 / False disable them."""
     lib = _load()
     lv = lv or levels(m)
     rp, ci, v = _arrs(m)
@@ -183,9 +194,10 @@ def rewrite(m, thin_metric: int = THIN_ROWS, thin_threshold: float = 32.0, fill_
     if mask is not None:
         mk = np.ascontiguousarray(mask, np.uint8)
         assert mk.size >= lv.nlev
-    ctx = lib.orc_rewrite(m.n, rp, ci, v, lv.nlev, lv.row_level, lv.level_ptr, lv.level_rows, thin_metric,
-                          float(thin_threshold), float(fill_cap), int(max_distance),
-                          mk.ctypes.data if mk is not None else None, tgt, C.byref(st))
+    ctx = lib.orc_rewrite_rc(m.n, rp, ci, v, lv.nlev, lv.row_level, lv.level_ptr, lv.level_rows, thin_metric,
+                             float(thin_threshold), float(fill_cap), int(max_distance),
+                             mk.ctypes.data if mk is not None else None, int(max_indegree), int(max_spread),
+                             int(bool(critical_only)), tgt, C.byref(st))
     if not ctx:
         raise RuntimeError(f"oracle rewrite failed: {STATUS[st.value]}")
     try:
@@ -199,9 +211,10 @@ def rewrite(m, thin_metric: int = THIN_ROWS, thin_threshold: float = 32.0, fill_
         t_col = np.zeros(b.value, np.int32)
         t_val = np.zeros(b.value, np.float64)
         lib.orc_rewrite_copy(ctx, lp_ptr, lp_col, lp_val, t_ptr, t_col, t_val)
+        skipped = lib.orc_rewrite_skipped(ctx)
     finally:
         lib.orc_rewrite_free(ctx)
-    return Rewrite(m.n, lp_ptr, lp_col, lp_val, t_ptr, t_col, t_val, tgt, rr.value, md.value, steps.value)
+    return Rewrite(m.n, lp_ptr, lp_col, lp_val, t_ptr, t_col, t_val, tgt, rr.value, md.value, steps.value, skipped)
 
 
 def rewrite_stats(m, rw: Rewrite, lv: Levels | None = None) -> dict:

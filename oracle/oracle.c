@@ -335,8 +335,17 @@ static int32_t alive_count(const subst_ws *s) {
  * is rewritten toward the current target; it is accepted while the target stays
  * within budget (and, optionally, the rewritten row stays within fill_cap times
  * its original nnz and the move is at most max_distance levels). The first row
- * that is refused stops the run and its level becomes the new target; rows
- * moved before it stay moved.
+ * that is refused stops the run and its level becomes the new target, with
+ * every row of that level not moved; rows moved before it stay moved.
+ *
+ * Row constraints (Sec. III.A lists them as refinements of the level-wise
+ * strategy): a row that passes the tests above is still left where it is,
+ * without stopping the run, when its rewritten form has max_indeg or more
+ * dependencies (indegree < alpha), when the columns of its rewritten form span
+ * max_spread or more (distance between dependencies < beta, the locality
+ * limit), or, with crit_only, when it is not on a longest path of the original
+ * DAG (level + height = nlev - 1, height = longest path to a row nothing
+ * depends on). Zero disables a limit.
  *
  * Outputs per row: tgt[r] = target level if the row was rewritten, else -1.
  * The rewritten rows are kept inside the returned context until collected.
@@ -350,6 +359,7 @@ typedef struct {
   int64_t nnz_lp, nnz_t;
   int32_t rows_rewritten, max_distance;
   int32_t steps;             /* number of target steps */
+  int32_t rows_skipped;      /* rows left in place by a row constraint */
 } orc_rewrite_ctx;
 
 typedef struct {
@@ -385,10 +395,11 @@ static void sort_pairs(int32_t *col, double *val, int32_t len) {
   }
 }
 
-orc_rewrite_ctx *orc_rewrite(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nlev,
-                             const int32_t *lev, const int32_t *level_ptr, const int32_t *level_rows,
-                             int32_t thin_metric, double thin_threshold, double fill_cap, int32_t max_distance,
-                             const uint8_t *mask, int32_t *tgt, int32_t *status) {
+orc_rewrite_ctx *orc_rewrite_rc(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nlev,
+                                const int32_t *lev, const int32_t *level_ptr, const int32_t *level_rows,
+                                int32_t thin_metric, double thin_threshold, double fill_cap, int32_t max_distance,
+                                const uint8_t *mask, int32_t max_indeg, int64_t max_spread, int32_t crit_only,
+                                int32_t *tgt, int32_t *status) {
   *status = ORC_OK;
   int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nlev + 1));
   int64_t *nzl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nlev + 1));
@@ -414,6 +425,23 @@ orc_rewrite_ctx *orc_rewrite(int32_t n, const int32_t *rp, const int32_t *ci, co
     cur[r] = lev[r];
     tgt[r] = -1;
   }
+  /* critical-path membership: heights by a sweep from the last row back (a
+     row's dependents all come after it) */
+  uint8_t *oncrit = NULL;
+  if (crit_only) {
+    int32_t *height = (int32_t *)calloc((size_t)(n + 1), sizeof(int32_t));
+    oncrit = (uint8_t *)malloc((size_t)(n + 1));
+    if (!height || !oncrit) {
+      *status = ORC_ERR_ALLOC;
+      return NULL;
+    }
+    for (int32_t r = n - 1; r >= 0; --r)
+      for (int32_t p = rp[r]; p < rp[r + 1] - 1; ++p)
+        if (height[ci[p]] < height[r] + 1) height[ci[p]] = height[r] + 1;
+    for (int32_t r = 0; r < n; ++r) oncrit[r] = (uint8_t)(lev[r] + height[r] == nlev - 1);
+    free(height);
+  }
+  int32_t skipped = 0;
 
   int32_t t = 0, dist_max = 0, moved = 0, steps = nlev > 0 ? 1 : 0;
   int64_t size_t_ = nlev > 0 ? rows[0] : 0;
@@ -448,6 +476,25 @@ orc_rewrite_ctx *orc_rewrite(int32_t n, const int32_t *rp, const int32_t *ci, co
         ok = (double)(cost_t + 2 * nnz_new - 1) <= W;
       if (fill_cap > 0.0) ok = ok && (double)nnz_new <= fill_cap * (double)nnz_old;
       if (max_distance > 0) ok = ok && (l - t) <= max_distance;
+      if (ok) {
+        int skip = 0;
+        if (max_indeg > 0 && (int64_t)alive_count(&s) >= max_indeg) skip = 1;
+        if (!skip && max_spread > 0) {
+          int32_t lo = INT32_MAX, hi = -1;
+          for (int32_t p = 0; p < s.wlen; ++p)
+            if (s.alive[p]) {
+              if (s.wcol[p] < lo) lo = s.wcol[p];
+              if (s.wcol[p] > hi) hi = s.wcol[p];
+            }
+          if (hi >= 0 && (int64_t)hi - lo >= max_spread) skip = 1;
+        }
+        if (!skip && crit_only && !oncrit[r]) skip = 1;
+        if (skip) { /* the row stays in its level; the run goes on */
+          ws_reset_pos(&s);
+          skipped += 1;
+          continue;
+        }
+      }
       if (ok) {
         /* commit: L'[r] = surviving columns + diagonal, T[r] = eliminated + 1 */
         int32_t la = alive_count(&s);
@@ -489,8 +536,9 @@ orc_rewrite_ctx *orc_rewrite(int32_t n, const int32_t *rp, const int32_t *ci, co
         steps++;
         size_t_ = 0;
         cost_t = 0;
-        for (int32_t q2 = q; q2 < level_ptr[l + 1]; ++q2) {
+        for (int32_t q2 = level_ptr[l]; q2 < level_ptr[l + 1]; ++q2) {
           int32_t r2 = level_rows[q2];
+          if (cur[r2] != l) continue; /* moved before the refusal */
           int64_t k2 = rp[r2 + 1] - rp[r2];
           size_t_ += 1;
           cost_t += 2 * k2 - 1;
@@ -556,6 +604,8 @@ orc_rewrite_ctx *orc_rewrite(int32_t n, const int32_t *rp, const int32_t *ci, co
   ctx->rows_rewritten = moved;
   ctx->max_distance = dist_max;
   ctx->steps = steps;
+  ctx->rows_skipped = skipped;
+  free(oncrit);
   free(rows);
   free(nzl);
   free(cost);
@@ -571,6 +621,16 @@ orc_rewrite_ctx *orc_rewrite(int32_t n, const int32_t *rp, const int32_t *ci, co
   free(s.tval);
   return ctx;
 }
+
+orc_rewrite_ctx *orc_rewrite(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nlev,
+                             const int32_t *lev, const int32_t *level_ptr, const int32_t *level_rows,
+                             int32_t thin_metric, double thin_threshold, double fill_cap, int32_t max_distance,
+                             const uint8_t *mask, int32_t *tgt, int32_t *status) {
+  return orc_rewrite_rc(n, rp, ci, v, nlev, lev, level_ptr, level_rows, thin_metric, thin_threshold, fill_cap,
+                        max_distance, mask, 0, 0, 0, tgt, status);
+}
+
+int32_t orc_rewrite_skipped(const orc_rewrite_ctx *c) { return c->rows_skipped; }
 
 void orc_rewrite_sizes(const orc_rewrite_ctx *c, int64_t *nnz_lp, int64_t *nnz_t, int32_t *rows_rewritten,
                        int32_t *max_distance, int32_t *steps) {

@@ -405,3 +405,158 @@ def test_manual_distance_ten_preset_on_a_chain():
         else:
             g = 10 * (x // 10)
             assert cols == ([g - 1] if g else [])
+
+
+# ------------------------------------------------ row constraints of Sec. III.A
+def _dense_chains(lengths, extra=()):
+    """Lower matrix of independent bidiagonal chains of the given lengths, in
+    order, plus extra (row, column) dependencies."""
+    n = int(sum(lengths))
+    a = np.zeros((n, n))
+    o = 0
+    for L in lengths:
+        for i in range(o + 1, o + L):
+            a[i, i - 1] = -0.5
+        o += L
+    for r, c in extra:
+        a[r, c] = 0.25
+    for i in range(n):
+        a[i, i] = 1.0 + np.abs(a[i, :i]).sum()
+    return gen.from_dense_lower(a)
+
+
+def _heights(m):
+    """Longest path from each row to a row nothing depends on: the levels of
+    the reversed DAG (row i <-> n-1-i, dependencies transposed)."""
+    n = m.n
+    L = m.to_scipy().tocoo()
+    off = L.row != L.col
+    R = sp.coo_matrix((L.data[off], (n - 1 - L.col[off], n - 1 - L.row[off])), shape=(n, n)).tolil()
+    R.setdiag(1.0)
+    rc = R.tocsr()
+    rc.sort_indices()
+    mr = gen.Csr(n, rc.indptr.astype(np.int32), rc.indices.astype(np.int32), rc.data, "reversed")
+    return oracle.levels(mr).row_level[::-1].copy()
+
+
+def _scan_replay_rc(m, lv, rw, thin_metric, thr, fill_cap, max_distance, alpha, beta, crit):
+    """Every decision re-derived from the definitions: the would-be row from
+    reachability (B = current level >= target), the stopping tests first
+    (budget, fill, distance: refuse and restart at this level with its unmoved
+    rows), then the row constraints (leave the row and go on)."""
+    c = oracle.level_costs(m, lv)
+    W = thr if (thin_metric == THIN_ROWS or thr > 0) else c.avg
+    nnz_l = np.diff(m.row_ptr)
+    oncrit = lv.row_level + _heights(m) == lv.nlev - 1
+    cur = lv.row_level.copy()
+    t, size, cost, skipped = 0, c.rows[0], c.cost[0], 0
+    for l in range(1, lv.nlev):
+        src = c.rows[l] < W if thin_metric == THIN_ROWS else c.cost[l] < W
+        rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
+        if not src:
+            assert np.all(rw.target[rows] == -1)
+            t, size, cost = l, c.rows[l], c.cost[l]
+            continue
+        for r in rows:
+            _, A = _reach(m, r, cur >= t)
+            nnz_new = len(A) + 1
+            ok = (size + 1 <= W) if thin_metric == THIN_ROWS else (cost + 2 * nnz_new - 1 <= W)
+            if fill_cap > 0:
+                ok = ok and nnz_new <= fill_cap * nnz_l[r]
+            if max_distance > 0:
+                ok = ok and l - t <= max_distance
+            if not ok:
+                assert rw.target[r] == -1
+                t = l
+                left = [q for q in rows if cur[q] == l]
+                size, cost = len(left), int(np.sum(2 * nnz_l[left] - 1))
+                break
+            skip = (alpha > 0 and len(A) >= alpha) or (beta > 0 and len(A) > 0 and max(A) - min(A) >= beta) or \
+                (crit and not oncrit[r])
+            if skip:
+                assert rw.target[r] == -1
+                skipped += 1
+                continue
+            assert rw.target[r] == t
+            cur[r] = t
+            size += 1
+            cost += 2 * nnz_new - 1
+    assert skipped == rw.rows_skipped
+
+
+def test_indegree_limit_on_a_chain():
+    # a 40-row chain under the 8-row rule: rows moved into level 0 keep no
+    # dependency, later groups keep one (the row before their target). With
+    # indegree < 1 only rows 1..7 move; row 8 is refused by the budget and
+    # becomes the target; rows 9..39 are left in place
+    m = gen.bidiagonal(40, 3)
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, THIN_ROWS, 8, 0.0, 0, None, lv, max_indegree=1)
+    want = np.full(40, -1)
+    want[1:8] = 0
+    assert np.array_equal(rw.target, want)
+    assert rw.rows_rewritten == 7 and rw.rows_skipped == 31
+    assert oracle.levels(rw.lp).nlev == 33
+    # indegree < 2 admits every move the unconstrained scan makes
+    free = oracle.rewrite(m, THIN_ROWS, 8, 0.0, 0, None, lv)
+    rw2 = oracle.rewrite(m, THIN_ROWS, 8, 0.0, 0, None, lv, max_indegree=2)
+    assert np.array_equal(rw2.target, free.target) and rw2.rows_skipped == 0
+    assert np.array_equal(rw2.lp_col, free.lp_col) and np.array_equal(rw2.t_val, free.t_val)
+
+
+def test_critical_path_limit_on_two_chains():
+    # a 30-row chain beside a 10-row chain: only the long chain lies on a
+    # longest path, so only its rows move (all into level 0 under a 64-row
+    # budget) and the short chain's 9 movable rows stay
+    m = _dense_chains([30, 10])
+    lv = oracle.levels(m)
+    assert lv.nlev == 30
+    rw = oracle.rewrite(m, THIN_ROWS, 64, 0.0, 0, None, lv, critical_only=True)
+    want = np.full(40, -1)
+    want[1:30] = 0
+    assert np.array_equal(rw.target, want)
+    assert rw.rows_skipped == 9
+    free = oracle.rewrite(m, THIN_ROWS, 64, 0.0, 0, None, lv)
+    assert free.rows_rewritten == 38
+
+
+def test_spread_limit_on_a_chain_reading_row0():
+    # rows 2..39 read the row before and row 0. Under the 8-row rule group k
+    # (rows 8k+1..8k+7, target level 8k) keeps dependencies {8k-1, 0}: span
+    # 8k-1. Span < 10 admits groups 0 and 1; row 16 is refused by the budget
+    # and becomes the target; rows 17..39 are left in place
+    m = _dense_chains([40], extra=[(r, 0) for r in range(2, 40)])
+    lv = oracle.levels(m)
+    assert lv.nlev == 40
+    rw = oracle.rewrite(m, THIN_ROWS, 8, 0.0, 0, None, lv, max_spread=10)
+    want = np.full(40, -1)
+    want[1:8] = 0
+    want[9:16] = 8
+    assert np.array_equal(rw.target, want)
+    assert rw.rows_skipped == 23
+    lcols = rw.lp_col[rw.lp_ptr[12]:rw.lp_ptr[13] - 1].tolist()
+    assert lcols == [0, 7]
+
+
+RC_CASES = [
+    (THIN_ROWS, 6, 0.0, 0, 2, 0, False),
+    (THIN_ROWS, 8, 4.0, 0, 0, 6, False),
+    (THIN_ROWS, 8, 0.0, 3, 0, 0, True),
+    (THIN_COST, 0.0, 0.0, 0, 3, 12, True),
+    (THIN_COST, 40.0, 3.0, 0, 0, 0, True),
+]
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("case", RC_CASES)
+def test_row_constraints_random(seed, case):
+    # scan decisions re-derived from the definitions, and the rewritten system
+    # still exact (L' = T L, unmoved rows untouched, same x)
+    rng = np.random.default_rng(300 + seed)
+    m = gen.window_random(int(rng.integers(20, 60)), 40 + seed, window=int(rng.integers(2, 9)),
+                          draws=int(rng.integers(1, 4)))
+    lv = oracle.levels(m)
+    tm, thr, cap, md, alpha, beta, crit = case
+    rw = oracle.rewrite(m, tm, thr, cap, md, None, lv, max_indegree=alpha, max_spread=beta, critical_only=crit)
+    check_rewrite_invariants(m, rw, lv, tm, thr, cap, md)
+    _scan_replay_rc(m, lv, rw, tm, thr, cap, md, alpha, beta, crit)

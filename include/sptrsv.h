@@ -110,7 +110,15 @@ sptrsv_status_t sptrsv_level_stats(sptrsv_handle_t h, int which, int64_t *d_rows
  * (THIN_COST: target cost, each row costing 2*nnz'-1, <= the threshold;
  * THIN_ROWS: target rows <= thin_threshold), optionally while nnz(L'[r]) <=
  * fill_cap * nnz(L[r]) and the distance is <= max_distance. The first refusal
- * makes its level the next target (rows already moved stay moved).
+ * makes its level the next target with every row of it not moved (rows already
+ * moved stay moved).
+ * Row constraints (the refinements Sec. III.A lists): a row that passes the
+ * tests above is left in place, and the run goes on, when its rewritten form
+ * has max_indegree or more off-diagonals (indegree < alpha), when its
+ * off-diagonal columns span max_spread or more (distance between dependencies
+ * < beta, the locality limit), or, with critical_only, when it is not on a
+ * longest path of the original DAG (level + longest path to a row nothing
+ * depends on = nlev - 1). Zero disables each.
  * A row is rewritten by substituting, largest column first, every unknown whose
  * row currently sits at or below the target level (Sec. II.B, Fig. 2) and
  * rearranging (Sec. II.B): L'[r] keeps its diagonal; T[r] collects the b terms
@@ -123,12 +131,16 @@ typedef struct {
   double fill_cap;              /* accept iff nnz(L'[r]) <= fill_cap * nnz(L[r]); <= 0 disables  */
   int32_t max_distance;         /* 0 = unlimited                                                 */
   const uint8_t *d_level_mask;  /* optional device uint8[nlev]: 1 = source; NULL = thin test     */
+  int32_t max_indegree;         /* alpha: 0 = no limit                                           */
+  int32_t critical_only;        /* 1: only rows on a longest path are rewritten                  */
+  int64_t max_spread;           /* beta, in columns: 0 = no limit                                */
 } sptrsv_rewrite_opts_t;
 
 typedef struct {
   int32_t nlev_before, nlev_after, rows_rewritten, max_distance, target_steps;
   int64_t nnz_L, nnz_Lp, nnz_T, total_cost_before, total_cost_after;
   double avg_level_cost_before, avg_level_cost_after; /* Table I metrics (Sec. IV) */
+  int32_t rows_skipped;         /* rows a row constraint left in place                           */
 } sptrsv_rewrite_stats_t;
 
 /* Errors: STATE (no analysis), ARG (bad opts), OVERFLOW (rewritten sizes beyond

@@ -30,6 +30,9 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
   if (o->max_distance < 0) return set_err(h, SPTRSV_ERR_ARG, "rewrite: max_distance %d", o->max_distance);
   if (!(o->thin_threshold == o->thin_threshold) || !(o->fill_cap == o->fill_cap))
     return set_err(h, SPTRSV_ERR_ARG, "rewrite: NaN option");
+  if (o->max_indegree < 0 || o->max_spread < 0 || (o->critical_only != 0 && o->critical_only != 1))
+    return set_err(h, SPTRSV_ERR_ARG, "rewrite: row constraints max_indegree %d max_spread %lld critical_only %d",
+                   o->max_indegree, (long long)o->max_spread, o->critical_only);
   h->has_rewrite = false;
   h->rew.ready = false;
   const int32_t n = P.n, nlev = P.nlev;
@@ -49,17 +52,29 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
     HIPCHK(h, hipMemcpyAsync(cur.p, P.row_level.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
     HIPCHK(h, hipMemsetAsync(h->target.p, 0xff, sizeof(int32_t) * (size_t)n, s));
   }
-  int32_t *aux = h->d_aux.p;  // [16..19] scan outputs, [20] error bits, [21..23] collect counters
+  // [16..19] scan outputs, [20] error bits, [21..23] collect counters, [32] rows held by a row constraint
+  int32_t *aux = h->d_aux.p;
   HIPCHK(h, hipMemsetAsync(aux + 16, 0, 8 * sizeof(int32_t), s));
-  int32_t hout[8] = {0};
+  HIPCHK(h, hipMemsetAsync(aux + 32, 0, sizeof(int32_t), s));
+  int32_t hout[8] = {0}, held = 0;
+  DArr<int32_t> height;
+  DArr<uint8_t> oncrit;
+  if (n > 0 && nlev > 1 && o->critical_only) {
+    HIPCHK(h, height.alloc(n));
+    HIPCHK(h, oncrit.alloc(n));
+    HIPCHK(h, hipMemsetAsync(height.p, 0, sizeof(int32_t) * (size_t)n, s));
+    HIPCHK(h, launch_crit_rows(nlev, P.level_ptr.p, P.perm.p, h->rp.p, h->ci.p, P.row_level.p, height.p, oncrit.p, s));
+  }
   if (n > 0 && nlev > 1) {
     const size_t big_bytes = rewrite_big_ws_bytes(kScanBigC, kScanBigH);
     if (h->rw_big.n < big_bytes) HIPCHK(h, h->rw_big.alloc(big_bytes));
     HIPCHK(h, launch_rewrite_scan(n, nlev, h->rp.p, h->ci.p, h->va.p, P.level_ptr.p, P.perm.p, P.lv_rows.p,
                                   P.lv_cost.p, o->d_level_mask, o->thin_metric, W, o->fill_cap, o->max_distance,
+                                  o->max_indegree, o->max_spread, o->critical_only ? oncrit.p : nullptr, aux + 32,
                                   cur.p, h->target.p, cntL.p, cntT.p, h->rw_big.p, kScanBigC, kScanBigH, aux + 16,
                                   s));
     HIPCHK(h, hipMemcpyAsync(hout, aux + 16, sizeof(hout), hipMemcpyDeviceToHost, s));
+    HIPCHK(h, hipMemcpyAsync(&held, aux + 32, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
     if (hout[3]) return set_err(h, status_from_bits(hout[3]), "rewrite scan failed (bits 0x%x)", hout[3]);
   }
@@ -138,6 +153,7 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
   r.total_cost_after = h->rew.total_cost;
   r.avg_level_cost_before = P.avg_cost;
   r.avg_level_cost_after = h->rew.avg_cost;
+  r.rows_skipped = held;
   h->rstats = r;
   h->has_rewrite = true;
   if (st) *st = r;

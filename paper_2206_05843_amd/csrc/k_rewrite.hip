@@ -160,6 +160,26 @@ __device__ int subst_row(Ws &w, int32_t r, int32_t t, const int32_t *__restrict_
   return SUB_OK;
 }
 
+// Smallest and largest A column of the row just built in the workspace
+// (wave-wide; {INT32_MAX, -1} when it has none).
+__device__ __forceinline__ int2 ws_a_span(const Ws &w) {
+  wave_sync();
+  const int lane = threadIdx.x & 63;
+  const int32_t nE = *w.cnt;
+  int32_t lo = INT32_MAX, hi = -1;
+  for (int32_t s = lane; s < nE; s += 64)
+    if (w.st[s] == 0) {
+      lo = w.col[s] < lo ? w.col[s] : lo;
+      hi = w.col[s] > hi ? w.col[s] : hi;
+    }
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t ol = __shfl_xor(lo, off, 64), oh = __shfl_xor(hi, off, 64);
+    lo = ol < lo ? ol : lo;
+    hi = oh > hi ? oh : hi;
+  }
+  return make_int2(lo, hi);
+}
+
 __device__ __forceinline__ Ws lds_ws(char *base, int wave) {
   // per wave: hkey[H] hslot[H] col[C] val[C] st[C] cnt na
   constexpr size_t per = (size_t)kLdsH * 8 + (size_t)kLdsC * 13 + 16;
@@ -203,23 +223,52 @@ struct ScanArgs {
   int32_t metric;
   double W, fill_cap;
   int32_t max_dist;
+  // row constraints (Sec. III.A): alpha, beta, and critical-path membership
+  // of the original rows (null: no such constraint)
+  int32_t max_indeg;
+  int64_t max_spread;
+  const uint8_t *oncrit;
+  int32_t *skipped;  // rows a row constraint left in place
   int32_t *cur, *target, *cntL, *cntT;
   char *big;        // global workspace for candidates that overflow LDS
   int32_t bigC, bigH;
   int32_t *out;     // [0] rows moved [1] max distance [2] target steps [3] error bits
 };
 
+// Whether a row constraint leaves candidate r (already within budget, fill
+// and distance) where it is: na A columns spanning [lo, hi].
+__device__ __forceinline__ bool row_held(const ScanArgs &a, int32_t r, int32_t na, int32_t lo, int32_t hi) {
+  if (a.max_indeg > 0 && na >= a.max_indeg) return true;
+  if (a.max_spread > 0 && na > 0 && (int64_t)hi - (int64_t)lo >= a.max_spread) return true;
+  if (a.oncrit && !a.oncrit[r]) return true;
+  return false;
+}
+
+// Size and cost of level lvl counting only its rows still there (the target a
+// refusal creates keeps the rows skipped or not yet tried).
+__device__ __forceinline__ void level_left(const ScanArgs &a, int32_t lvl, int64_t &size, int64_t &cost) {
+  size = 0;
+  cost = 0;
+  for (int32_t p = a.level_ptr[lvl]; p < a.level_ptr[lvl + 1]; ++p) {
+    const int32_t rr = a.level_rows[p];
+    if (a.cur[rr] != lvl) continue;
+    size += 1;
+    cost += 2 * (int64_t)(a.rp[rr + 1] - a.rp[rr]) - 1;
+  }
+}
+
 // The whole decision scan in one workgroup (levels in order, targets only
 // move forward). Thread 0 owns the scan state; waves evaluate candidates.
 __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ int32_t c_row[kWaves], c_lvl[kWaves], c_q[kWaves], c_st[kWaves], c_na[kWaves], c_nt[kWaves];
+  __shared__ int32_t c_lo[kWaves], c_hi[kWaves];
   __shared__ int32_t s_nc, s_done, s_redo, s_t;
   __shared__ int64_t s_capA_cost;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   Ws w = lds_ws(lds_raw, wave);
   // scan state (thread 0)
-  int32_t t = 0, l = 1, q = 0, moved = 0, maxd = 0, steps = a.nlev > 0 ? 1 : 0;
+  int32_t t = 0, l = 1, q = 0, moved = 0, maxd = 0, steps = a.nlev > 0 ? 1 : 0, held = 0;
   int64_t size = a.nlev > 0 ? a.lv_rows[0] : 0, cost = a.nlev > 0 ? a.lv_cost[0] : 0;
   int bits = 0;
   auto is_src = [&](int32_t lvl) -> bool {
@@ -293,10 +342,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
       }
       int32_t nT = 0;
       const int stt = subst_row(w, r, tt, a.rp, a.ci, a.va, a.cur, capA, &nT);
+      const int2 span = stt == SUB_OK && a.max_spread > 0 ? ws_a_span(w) : make_int2(0, 0);
       if (lane == 0) {
         c_st[wave] = stt;
         c_na[wave] = *w.na;
         c_nt[wave] = nT;
+        c_lo[wave] = span.x;
+        c_hi[wave] = span.y;
       }
     }
     __syncthreads();
@@ -319,6 +371,10 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
           if (a.fill_cap > 0.0) ok = ok && (double)nnz_new <= a.fill_cap * (double)nnz_old;
           if (a.max_dist > 0) ok = ok && (lvl - t) <= a.max_dist;
         }
+        if (ok && row_held(a, r, c_na[i], c_lo[i], c_hi[i])) {
+          ++held;  // stays in its level; the scan position is already past it
+          continue;
+        }
         if (ok) {
           a.cur[r] = t;
           a.target[r] = t;
@@ -333,14 +389,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
           // its level becomes the target with the rows not moved
           t = lvl;
           ++steps;
-          const int32_t lb = a.level_ptr[lvl], le = a.level_ptr[lvl + 1];
-          size = 0;
-          cost = 0;
-          for (int32_t p = lb + c_q[i]; p < le; ++p) {
-            const int32_t rr = a.level_rows[p];
-            size += 1;
-            cost += 2 * (int64_t)(a.rp[rr + 1] - a.rp[rr]) - 1;
-          }
+          level_left(a, lvl, size, cost);
           l = lvl + 1;
           q = 0;
           break;
@@ -359,10 +408,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
         Ws g = global_ws(a.big, a.bigC, a.bigH);
         int32_t nT = 0;
         const int stt = subst_row(g, r, s_t, a.rp, a.ci, a.va, a.cur, INT64_MAX, &nT);
+        const int2 span = stt == SUB_OK && a.max_spread > 0 ? ws_a_span(g) : make_int2(0, 0);
         if (lane == 0) {
           c_st[0] = stt;
           c_na[0] = *g.na;
           c_nt[0] = nT;
+          c_lo[0] = span.x;
+          c_hi[0] = span.y;
         }
       }
       __syncthreads();
@@ -381,7 +433,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
             ok = (double)(cost + 2 * nnz_new - 1) <= a.W;
           if (a.fill_cap > 0.0) ok = ok && (double)nnz_new <= a.fill_cap * (double)nnz_old;
           if (a.max_dist > 0) ok = ok && (lvl - t) <= a.max_dist;
-          if (ok) {
+          const bool keep = ok && row_held(a, r, c_na[0], c_lo[0], c_hi[0]);
+          if (keep) ++held;
+          if (ok && !keep) {
             a.cur[r] = t;
             a.target[r] = t;
             a.cntL[r] = (int32_t)nnz_new;
@@ -390,7 +444,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
             cost += 2 * nnz_new - 1;
             ++moved;
             if (lvl - t > maxd) maxd = lvl - t;
-            // advance past it
+          }
+          if (ok) {  // moved or held: advance past it
             q = c_q[i] + 1;
             l = lvl;
             if (q == a.level_ptr[lvl + 1] - a.level_ptr[lvl]) {
@@ -400,14 +455,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
           } else {
             t = lvl;
             ++steps;
-            const int32_t lb = a.level_ptr[lvl], le = a.level_ptr[lvl + 1];
-            size = 0;
-            cost = 0;
-            for (int32_t p = lb + c_q[i]; p < le; ++p) {
-              const int32_t rr = a.level_rows[p];
-              size += 1;
-              cost += 2 * (int64_t)(a.rp[rr + 1] - a.rp[rr]) - 1;
-            }
+            level_left(a, lvl, size, cost);
             l = lvl + 1;
             q = 0;
           }
@@ -422,6 +470,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
     a.out[1] = maxd;
     a.out[2] = steps;
     a.out[3] = bits;
+    *a.skipped = held;
   }
 }
 
@@ -577,14 +626,46 @@ __global__ __launch_bounds__(64 * kWaves) void k_feat_rows(int32_t n, const int3
   }
 }
 
+// Critical-path membership of the rows of L: heights (longest path to a row
+// nothing depends on) by one workgroup sweeping the levels from the last back;
+// a row's dependents all sit in later levels, so its height is final when its
+// level comes, and it raises its dependencies' heights with atomic maxima.
+// oncrit[r] = level(r) + height(r) == nlev - 1. height must start at zero.
+__global__ __launch_bounds__(1024) void k_crit_rows(int32_t nlev, const int32_t *__restrict__ level_ptr,
+                                                    const int32_t *__restrict__ level_rows,
+                                                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                    const int32_t *__restrict__ row_level, int32_t *height,
+                                                    uint8_t *oncrit) {
+  for (int32_t l = nlev - 1; l >= 0; --l) {
+    for (int32_t q = level_ptr[l] + (int32_t)threadIdx.x; q < level_ptr[l + 1]; q += (int32_t)blockDim.x) {
+      const int32_t r = level_rows[q];
+      const int32_t hr = __hip_atomic_load(height + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int32_t p = rp[r]; p < rp[r + 1] - 1; ++p) atomicMax(height + ci[p], hr + 1);
+      oncrit[r] = (uint8_t)(row_level[r] + hr == nlev - 1 ? 1 : 0);
+    }
+    __threadfence();
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_crit_rows(int32_t nlev, const int32_t *level_ptr, const int32_t *level_rows, const int32_t *rp,
+                            const int32_t *ci, const int32_t *row_level, int32_t *height, uint8_t *oncrit,
+                            hipStream_t s) {
+  if (nlev == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_crit_rows, dim3(1), dim3(1024), 0, s, nlev, level_ptr, level_rows, rp, ci, row_level, height,
+                     oncrit);
+  return hipGetLastError();
+}
 
 size_t rewrite_big_ws_bytes(int32_t C, int32_t H) { return (size_t)C * 13 + (size_t)H * 8 + 64; }
 
 hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const int32_t *ci, const double *va,
                                const int32_t *level_ptr, const int32_t *level_rows, const int64_t *lv_rows,
                                const int64_t *lv_cost, const uint8_t *mask, int32_t metric, double W, double fill_cap,
-                               int32_t max_dist, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
+                               int32_t max_dist, int32_t max_indeg, int64_t max_spread, const uint8_t *oncrit,
+                               int32_t *skipped, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
                                char *big, int32_t bigC, int32_t bigH, int32_t *out, hipStream_t s) {
   ScanArgs a;
   a.n = n;
@@ -601,6 +682,10 @@ hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const
   a.W = W;
   a.fill_cap = fill_cap;
   a.max_dist = max_dist;
+  a.max_indeg = max_indeg;
+  a.max_spread = max_spread;
+  a.oncrit = oncrit;
+  a.skipped = skipped;
   a.cur = cur;
   a.target = target;
   a.cntL = cntL;

@@ -41,7 +41,8 @@ class SptrsvError(RuntimeError):
 
 class RewriteOpts(C.Structure):
     _fields_ = [("thin_metric", C.c_int32), ("thin_threshold", C.c_double), ("fill_cap", C.c_double),
-                ("max_distance", C.c_int32), ("d_level_mask", C.c_void_p)]
+                ("max_distance", C.c_int32), ("d_level_mask", C.c_void_p), ("max_indegree", C.c_int32),
+                ("critical_only", C.c_int32), ("max_spread", C.c_int64)]
 
 
 class RewriteStats(C.Structure):
@@ -49,7 +50,7 @@ class RewriteStats(C.Structure):
                 ("max_distance", C.c_int32), ("target_steps", C.c_int32), ("nnz_L", C.c_int64),
                 ("nnz_Lp", C.c_int64), ("nnz_T", C.c_int64), ("total_cost_before", C.c_int64),
                 ("total_cost_after", C.c_int64), ("avg_level_cost_before", C.c_double),
-                ("avg_level_cost_after", C.c_double)]
+                ("avg_level_cost_after", C.c_double), ("rows_skipped", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -236,9 +237,11 @@ class Handle:
         return dict(rows=rows, nnz=nnz, cost=cost, total=tot.value, avg=avg.value)
 
     # ------------------------------------------------------------------- rewrite
-    def rewrite(self, thin_metric=THIN_ROWS, thin_threshold=32.0, fill_cap=4.0, max_distance=0, mask=None):
+    def rewrite(self, thin_metric=THIN_ROWS, thin_threshold=32.0, fill_cap=4.0, max_distance=0, mask=None,
+                max_indegree=0, max_spread=0, critical_only=False):
         o = RewriteOpts(thin_metric, float(thin_threshold), float(fill_cap), int(max_distance),
-                        _ptr(mask) if mask is not None else None)
+                        _ptr(mask) if mask is not None else None, int(max_indegree), int(bool(critical_only)),
+                        int(max_spread))
         if mask is not None:
             _need(mask.dtype == torch.uint8 and mask.numel() >= self.nlev, "uint8 mask of nlev entries expected")
         st = RewriteStats()

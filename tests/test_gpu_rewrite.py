@@ -175,3 +175,81 @@ def test_b_transform_row_lengths(w):
         h.check()
         assert oracle.relerr(xd[:, :m.n].cpu().numpy().reshape(k, m.n), xr.reshape(k, m.n)) <= TOL
         assert torch.isnan(xd[:, m.n:]).all()  # nothing written past each column
+
+
+# ---------------------------------------------- row constraints (Sec. III.A)
+def _chains(lengths, extra=()):
+    n = int(sum(lengths))
+    a = np.zeros((n, n))
+    o = 0
+    for L in lengths:
+        for i in range(o + 1, o + L):
+            a[i, i - 1] = -0.5
+        o += L
+    for r, c in extra:
+        a[r, c] = 0.25
+    for i in range(n):
+        a[i, i] = 1.0 + np.abs(a[i, :i]).sum()
+    return gen.from_dense_lower(a)
+
+
+RC_MATS = [
+    ("bidiag40", lambda: gen.bidiagonal(40, 3)),
+    ("two_chains", lambda: _chains([30, 10])),
+    ("chain_row0", lambda: _chains([40], extra=[(r, 0) for r in range(2, 40)])),
+    ("window_ragged", lambda: gen.window_random(3001, 4, window=12, draws=3)),
+    ("cfg1_small", lambda: gen.config_matrix(1, "small")[0]),
+    ("cfg2_small", lambda: gen.config_matrix(2, "small")[0]),
+]
+RC_OPTS = {
+    "alpha1": dict(thin_metric=0, thin_threshold=8, fill_cap=0.0, max_distance=0, max_indegree=1),
+    "alpha3_cap4": dict(thin_metric=0, thin_threshold=32, fill_cap=4.0, max_distance=0, max_indegree=3),
+    "beta10": dict(thin_metric=0, thin_threshold=8, fill_cap=0.0, max_distance=0, max_spread=10),
+    "crit": dict(thin_metric=0, thin_threshold=64, fill_cap=0.0, max_distance=0, critical_only=True),
+    "cost_all": dict(thin_metric=1, thin_threshold=0.0, fill_cap=0.0, max_distance=0, max_indegree=4,
+                     max_spread=200, critical_only=True),
+}
+
+
+@pytest.mark.parametrize("name", [n for n, _ in RC_MATS])
+@pytest.mark.parametrize("opt", list(RC_OPTS))
+def test_row_constraints_parity(name, opt):
+    m = dict(RC_MATS)[name]()
+    o = RC_OPTS[opt]
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(**o)
+    lv = oracle.levels(m)
+    rw = oracle.rewrite(m, o["thin_metric"], o["thin_threshold"], o["fill_cap"], o["max_distance"], None, lv,
+                        max_indegree=o.get("max_indegree", 0), max_spread=o.get("max_spread", 0),
+                        critical_only=o.get("critical_only", False))
+    assert st["rows_skipped"] == rw.rows_skipped
+    compare(m, h, st, rw, lv, nrhs=(1, 3))
+
+
+def test_row_constraints_with_global_workspace():
+    # rows whose rewritten form overflows the LDS workspace are evaluated again
+    # in the global one; some of them are then held by a constraint
+    # (levels 0 and 10 are the targets; rows beyond level 10 keep 11
+    # dependencies on levels before it, so indegree < 11 holds them)
+    m = gen.window_random(1500, 7, window=40, draws=6)
+    lv = oracle.levels(m)
+    mask = np.ones(lv.nlev, np.uint8)
+    mask[0] = 0
+    mask[10] = 0
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(0, 1e9, 0.0, 0, mask=to_dev(mask), max_indegree=11)
+    rw = oracle.rewrite(m, 0, 1e9, 0.0, 0, mask, lv, max_indegree=11)
+    assert rw.rows_skipped > 1000 and rw.rows_rewritten > 0
+    assert st["rows_skipped"] == rw.rows_skipped
+    compare(m, h, st, rw, lv, nrhs=(1,))
+
+
+def test_row_constraint_errors():
+    m = gen.bidiagonal(50, 1)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    for bad in (dict(max_indegree=-1), dict(max_spread=-5)):
+        with pytest.raises(sp.SptrsvError):
+            h.rewrite(sp.THIN_ROWS, 8.0, 0.0, 0, **bad)

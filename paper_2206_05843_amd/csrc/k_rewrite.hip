@@ -25,6 +25,13 @@ namespace {
 constexpr int kWaves = 8;          // waves per workgroup in both kernels
 constexpr int kLdsC = 512;         // LDS workspace entries per wave
 constexpr int kLdsH = 1024;        // LDS hash slots per wave
+// A scan candidate that outgrows its LDS workspace is evaluated again at once
+// by the same wave in a private region of the global workspace of this size
+// (cleared per candidate, so kept far below the full workspace); only a row
+// that outgrows that too takes the serial path through the full workspace.
+constexpr int kTier1C = 1 << 14;
+constexpr int kTier1H = 1 << 15;
+constexpr size_t kTier1Bytes = (((size_t)kTier1C * 13 + (size_t)kTier1H * 8 + 64) + 255) & ~(size_t)255;
 
 enum : int { SUB_OK = 0, SUB_REJECT = 1, SUB_OVERFLOW = 2 };
 
@@ -341,11 +348,17 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
         capA = c2 < capA ? c2 : capA;
       }
       int32_t nT = 0;
-      const int stt = subst_row(w, r, tt, a.rp, a.ci, a.va, a.cur, capA, &nT);
-      const int2 span = stt == SUB_OK && a.max_spread > 0 ? ws_a_span(w) : make_int2(0, 0);
+      int stt = subst_row(w, r, tt, a.rp, a.ci, a.va, a.cur, capA, &nT);
+      Ws used = w;
+      if (stt == SUB_OVERFLOW) {
+        used = global_ws(a.big + (size_t)wave * kTier1Bytes, kTier1C, kTier1H);
+        nT = 0;
+        stt = subst_row(used, r, tt, a.rp, a.ci, a.va, a.cur, capA, &nT);
+      }
+      const int2 span = stt == SUB_OK && a.max_spread > 0 ? ws_a_span(used) : make_int2(0, 0);
       if (lane == 0) {
         c_st[wave] = stt;
-        c_na[wave] = *w.na;
+        c_na[wave] = *used.na;
         c_nt[wave] = nT;
         c_lo[wave] = span.x;
         c_hi[wave] = span.y;
@@ -693,6 +706,8 @@ hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const
   a.big = big;
   a.bigC = bigC;
   a.bigH = bigH;
+  // the full workspace also holds the waves' first-retry regions
+  if (rewrite_big_ws_bytes(bigC, bigH) < (size_t)kWaves * kTier1Bytes) return hipErrorInvalidValue;
   a.out = out;
   static bool attr = false;
   if (!attr) {

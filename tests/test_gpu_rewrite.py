@@ -253,3 +253,39 @@ def test_row_constraint_errors():
     for bad in (dict(max_indegree=-1), dict(max_spread=-5)):
         with pytest.raises(sp.SptrsvError):
             h.rewrite(sp.THIN_ROWS, 8.0, 0.0, 0, **bad)
+
+
+def _wide_row_matrix(k=17000):
+    # rows 0..k-1 stand alone; row k reads all of them; row k+1 reads all of
+    # them and row k: rewriting either row takes more than 2^14 workspace
+    # entries, past the per-wave retry region, into the full workspace
+    rng = np.random.default_rng(5)
+    cols = [np.array([i]) for i in range(k)]
+    cols.append(np.arange(k + 1))
+    cols.append(np.arange(k + 2))
+    rp = np.zeros(k + 3, np.int64)
+    rp[1:] = np.cumsum([c.size for c in cols])
+    ci = np.concatenate(cols).astype(np.int32)
+    va = rng.uniform(-1.0, 1.0, ci.size) / k
+    va[rp[1:] - 1] = 2.0
+    return gen.Csr(k + 2, rp.astype(np.int32), ci, va, "wide_rows")
+
+
+@pytest.mark.parametrize("held", [False, True])
+def test_rewrite_rows_past_the_retry_region(held):
+    m = _wide_row_matrix()
+    lv = oracle.levels(m)
+    assert lv.nlev == 3
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    if held:  # level 1 is a target: row k+1 keeps k columns, indegree < 100 holds it
+        mask = np.array([0, 0, 1], np.uint8)
+        st = h.rewrite(0, 1e9, 0.0, 0, mask=to_dev(mask), max_indegree=100)
+        rw = oracle.rewrite(m, 0, 1e9, 0.0, 0, mask, lv, max_indegree=100)
+        assert rw.rows_skipped == 1 and rw.rows_rewritten == 0
+    else:
+        st = h.rewrite(0, 1e9, 0.0, 0)
+        rw = oracle.rewrite(m, 0, 1e9, 0.0, 0, None, lv)
+        assert rw.rows_rewritten == 2 and int(np.max(np.diff(rw.t_ptr))) > 1 << 14
+    assert st["rows_skipped"] == rw.rows_skipped
+    compare(m, h, st, rw, lv, nrhs=(1,))

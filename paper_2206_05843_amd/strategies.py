@@ -10,6 +10,10 @@ Strategies (Sec. III and the comparison of Sec. IV):
                 avgLevelCost are taken in order, ten at a time; the first of
                 each ten is the target and the other nine are rewritten into
                 it as whole levels (distance at most 9, no cost or fill limit)
+  avgLevelCost_indeg4
+                avgLevelCost with the first row constraint of Sec. III.A: a
+                row is rewritten only if its rewritten form has fewer than 4
+                dependencies (otherwise it stays, and the run goes on)
   naive32       this library's benchmark rule: levels with fewer than 32 rows,
                 at most 32 rows per target, fill at most 4x per row
 
@@ -39,7 +43,7 @@ if ROOT not in sys.path:
 
 from paper_2206_05843_amd import sptrsv as sp  # noqa: E402
 
-STRATEGIES = ("none", "avgLevelCost", "manual10", "naive32")
+STRATEGIES = ("none", "avgLevelCost", "avgLevelCost_indeg4", "manual10", "naive32")
 
 
 def manual_mask(h: sp.Handle) -> torch.Tensor:
@@ -61,6 +65,8 @@ def apply(h: sp.Handle, name: str):
         return None
     if name == "avgLevelCost":
         return h.rewrite(sp.THIN_COST, 0.0, 0.0, 0)
+    if name == "avgLevelCost_indeg4":
+        return h.rewrite(sp.THIN_COST, 0.0, 0.0, 0, max_indegree=4)
     if name == "manual10":
         return h.rewrite(sp.THIN_COST, 1e300, 0.0, 9, manual_mask(h))
     if name == "naive32":
@@ -104,6 +110,7 @@ def report(matrices, reps: int = 20):
             row = {"matrix": m.name, "n": m.n, "nnz": m.nnz, "strategy": name, "levels": len(cost["cost"]),
                    "total_cost": int(cost["total"]), "avg_level_cost": float(cost["avg"]),
                    "rows_rewritten": 0 if st is None else st["rows_rewritten"],
+                   "rows_held": 0 if st is None else st["rows_skipped"],
                    "nnz_Lp": m.nnz if st is None else st["nnz_Lp"], "nnz_T": m.n if st is None else st["nnz_T"],
                    "max_distance": 0 if st is None else st["max_distance"], "solve_ms": ms,
                    "level_costs": cost["cost"].cpu().numpy().tolist()}
@@ -126,11 +133,11 @@ def profile(costs, bins: int = 16):
 
 
 def markdown(rows) -> str:
-    lines = ["| matrix | strategy | levels | avg level cost | total level cost | rows rewritten | nnz(L') | nnz(T) | "
-             "max distance | solve ms |", "|---|---|---|---|---|---|---|---|---|---|"]
+    lines = ["| matrix | strategy | levels | avg level cost | total level cost | rows rewritten | rows held | nnz(L') | "
+             "nnz(T) | max distance | solve ms |", "|---|---|---|---|---|---|---|---|---|---|---|"]
     for r in rows:
         lines.append(f"| {r['matrix']} | {r['strategy']} | {r['levels']} | {r['avg_level_cost']:.1f} | "
-                     f"{r['total_cost']} | {r['rows_rewritten']} | {r['nnz_Lp']} | {r['nnz_T']} | "
+                     f"{r['total_cost']} | {r['rows_rewritten']} | {r.get('rows_held', 0)} | {r['nnz_Lp']} | {r['nnz_T']} | "
                      f"{r['max_distance']} | {r['solve_ms']:.3f} |")
     lines += ["", "Per-level cost profile (as in Figs. 5 and 6): the levels in 16 consecutive groups, each group's mean "
               "level cost, then the largest level cost and the number of levels above the average.", "",

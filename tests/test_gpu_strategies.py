@@ -30,13 +30,15 @@ def _oracle_rewrite(m, name, lv):
         return oracle.rewrite(m, oracle.THIN_COST, 0.0, 0.0, 0, lv=lv)
     if name == "manual10":
         return oracle.rewrite(m, oracle.THIN_COST, 1e300, 0.0, 9, mask=_manual_sources(m, lv), lv=lv)
+    if name == "avgLevelCost_indeg4":
+        return oracle.rewrite(m, oracle.THIN_COST, 0.0, 0.0, 0, lv=lv, max_indegree=4)
     if name == "naive32":
         return oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0, 0, lv=lv)
     raise ValueError(name)
 
 
 @pytest.mark.parametrize("mk", [gen.lung2_like, gen.torso2_like])
-@pytest.mark.parametrize("name", ["avgLevelCost", "manual10", "naive32"])
+@pytest.mark.parametrize("name", ["avgLevelCost", "avgLevelCost_indeg4", "manual10", "naive32"])
 def test_strategy_parity(mk, name):
     m = mk(0)
     lv = oracle.levels(m)
@@ -55,6 +57,7 @@ def test_strategy_parity(mk, name):
     ref = oracle.rewrite_stats(m, rw, lv)
     for k in ("nlev_before", "nlev_after", "rows_rewritten", "max_distance", "nnz_Lp", "nnz_T"):
         assert st[k] == ref[k], k
+    assert st["rows_skipped"] == rw.rows_skipped
     for k in ("total_cost_before", "total_cost_after", "avg_level_cost_before", "avg_level_cost_after"):
         assert st[k] == ref[k], k
     b = gen.rhs(m, 1)

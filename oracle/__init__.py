@@ -64,6 +64,8 @@ def _load():
     lib.orc_level_costs.argtypes = [C.c_int32, i32p, C.c_int32, i32p, i32p, i64p, i64p, i64p,
                                     C.POINTER(C.c_int64)]
     lib.orc_level_costs.restype = C.c_double
+    lib.orc_solve_upper.argtypes = lib.orc_solve.argtypes
+    lib.orc_solve_upper.restype = None
     lib.orc_rewrite.argtypes = [C.c_int32, i32p, i32p, f64p, C.c_int32, i32p, i32p, i32p, C.c_int32,
                                 C.c_double, C.c_double, C.c_int32, C.c_void_p, i32p, C.POINTER(C.c_int32)]
     lib.orc_rewrite.restype = C.c_void_p
@@ -103,6 +105,42 @@ def solve(m, b: np.ndarray) -> np.ndarray:
     x = np.zeros_like(b)
     _load().orc_solve(m.n, rp, ci, v, b.shape[0], b, m.n, x, m.n)
     return x
+
+
+def solve_upper(m, b: np.ndarray) -> np.ndarray:
+    """x = U^{-1} b by backward substitution; ``m`` upper-triangular CSR with
+    the diagonal first in each row; ``b`` has shape (nrhs, n)."""
+    rp, ci, v = _arrs(m)
+    b = np.ascontiguousarray(np.atleast_2d(b), np.float64)
+    x = np.zeros_like(b)
+    _load().orc_solve_upper(m.n, rp, ci, v, b.shape[0], b, m.n, x, m.n)
+    return x
+
+
+def transpose(m):
+    """The transpose as a CSR with sorted rows (a plain library transpose)."""
+    import scipy.sparse as sps
+    from gen import Csr
+    a = sps.csr_matrix((m.val, m.col, m.row_ptr), shape=(m.n, m.n)).T.tocsr()
+    a.sort_indices()
+    return Csr(m.n, a.indptr.astype(np.int32), a.indices.astype(np.int32), a.data.astype(np.float64), m.name + "^T")
+
+
+LOWER, UPPER, LOWER_TRANS, UPPER_TRANS = 0, 1, 2, 3
+
+
+def solve_form(m, b: np.ndarray, form: int) -> np.ndarray:
+    """x for the system ``m`` stands for: L x = b (LOWER), U x = b (UPPER),
+    L^T x = b (LOWER_TRANS, m lower) or U^T x = b (UPPER_TRANS, m upper)."""
+    if form == LOWER:
+        return solve(m, b)
+    if form == UPPER:
+        return solve_upper(m, b)
+    if form == LOWER_TRANS:
+        return solve_upper(transpose(m), b)
+    if form == UPPER_TRANS:
+        return solve(transpose(m), b)
+    raise ValueError(form)
 
 
 def spmv(rp, ci, v, n, b: np.ndarray) -> np.ndarray:

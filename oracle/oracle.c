@@ -14,6 +14,8 @@
  *
  *   O1 orc_validate        CSR well-formedness, diagonal last   (Sec. II.A, Algorithm 1)
  *   O2 orc_solve           serial forward substitution          (Sec. II.A, Algorithm 1)
+ *      orc_solve_upper     serial backward substitution for an upper-triangular
+ *                          matrix (the same recurrence from the last row up)
  *   O3 orc_levels          level sets by longest path in DAG_L  (Sec. II.A)
  *   O4 orc_level_costs     row/level cost, avgLevelCost         (Sec. III, cost model)
  *   O5 orc_rewrite_*       thin/target/source scan + explicit
@@ -77,6 +79,22 @@ int orc_validate(int32_t n, int32_t nnz, const int32_t *rp, const int32_t *ci, c
  * row). The printed listing indexes its accumulator by column; a single scalar
  * per row is the reading that computes x = L^{-1} b. Column-major b and x.
  * ------------------------------------------------------------------------- */
+/* Backward substitution, U x = b, U upper-triangular in CSR with the diagonal
+ * first in each row: x_i = (b_i - sum_{j > i} U_ij x_j) / U_ii for i from n-1
+ * down to 0, the off-diagonals in ascending column order. */
+void orc_solve_upper(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nrhs,
+                     const double *b, int64_t ldb, double *x, int64_t ldx) {
+  for (int32_t c = 0; c < nrhs; ++c) {
+    const double *bc = b + (int64_t)c * ldb;
+    double *xc = x + (int64_t)c * ldx;
+    for (int32_t i = n - 1; i >= 0; --i) {
+      double sum = 0.0;
+      for (int32_t p = rp[i] + 1; p < rp[i + 1]; ++p) sum = sum + v[p] * xc[ci[p]];
+      xc[i] = (bc[i] - sum) / v[rp[i]];
+    }
+  }
+}
+
 void orc_solve(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nrhs,
                const double *b, int64_t ldb, double *x, int64_t ldx) {
   for (int32_t c = 0; c < nrhs; ++c) {

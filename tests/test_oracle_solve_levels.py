@@ -221,3 +221,60 @@ def test_fig2_costs_before():
     c = oracle.level_costs(m, lv)
     assert c.total == int(np.sum(2 * nnz - 1))
     assert c.avg == c.total / lv.nlev
+
+
+# ---------------------------------------- upper-triangular and transposed forms
+def _upper_of(m):
+    return oracle.transpose(m)
+
+
+def test_upper_bidiagonal_closed_form():
+    # U = 2 on the diagonal, -1 above it; b = U 1 gives x = 1 exactly
+    n = 57
+    rp = np.arange(0, 2 * n, 2, dtype=np.int32)
+    rp = np.append(rp, 2 * n - 1).astype(np.int32)
+    ci = np.empty(2 * n - 1, np.int32)
+    va = np.empty(2 * n - 1)
+    for i in range(n):
+        ci[2 * i] = i
+        va[2 * i] = 2.0
+        if i + 1 < n:
+            ci[2 * i + 1] = i + 1
+            va[2 * i + 1] = -1.0
+    u = gen.Csr(n, rp, ci, va, "upper_bidiag")
+    b = np.ones((1, n))
+    b[0, -1] = 2.0
+    assert np.array_equal(oracle.solve_upper(u, b), np.ones((1, n)))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_upper_and_transposed_forms_against_dense(seed):
+    import scipy.linalg as sla
+    m = gen.window_random(150 + 7 * seed, seed, window=9, draws=3)
+    u = _upper_of(gen.window_random(150 + 7 * seed, 50 + seed, window=9, draws=3))
+    b = gen.rhs(m, 3)
+    L, U = m.to_scipy().toarray(), u.to_scipy().toarray()
+    for form, mat, dense in ((oracle.UPPER, u, U), (oracle.LOWER_TRANS, m, L.T), (oracle.UPPER_TRANS, u, U.T),
+                             (oracle.LOWER, m, L)):
+        x = oracle.solve_form(mat, b, form)
+        xr = sla.solve_triangular(dense, b.T, lower=form in (oracle.LOWER, oracle.UPPER_TRANS)).T
+        assert oracle.relerr(x, xr) < 1e-12, form
+        # and the residual of the system itself
+        assert np.abs(dense @ x.T - b.T).max() <= 1e-12 * (1.0 + np.abs(b).max())
+
+
+def test_reversal_turns_upper_into_lower():
+    # J U J (rows and columns in reverse order) is lower-triangular with the
+    # diagonal last, and solving it on J b gives J x
+    u = _upper_of(gen.window_random(300, 4, window=20, draws=4))
+    n = u.n
+    nnz = u.nnz
+    rp = (nnz - u.row_ptr[::-1]).astype(np.int32)
+    ci = (n - 1 - u.col[::-1]).astype(np.int32)
+    va = u.val[::-1].copy()
+    r = gen.Csr(n, rp, ci, va, "JUJ")
+    assert oracle.validate(r) == "OK"
+    b = gen.rhs(u, 2)
+    x = oracle.solve_upper(u, b)
+    xr = oracle.solve(r, b[:, ::-1].copy())[:, ::-1]
+    assert oracle.relerr(xr, x) < 1e-13

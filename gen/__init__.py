@@ -16,6 +16,7 @@ from .matrices import (  # noqa: F401
     batch_window,
     rhs,
     from_dense_lower,
+    transpose,
     bidiagonal,
     diagonal,
     config_matrix,

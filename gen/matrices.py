@@ -308,6 +308,17 @@ def from_dense_lower(a: np.ndarray, name: str = "dense") -> Csr:
                np.random.default_rng(0).bit_generator.state)
 
 
+def transpose(m: Csr) -> Csr:
+    """The transpose (an upper-triangular CSR for a lower input, diagonal first
+    in each row), by a counting sort of the entries on their column."""
+    n = m.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(m.row_ptr))
+    order = np.lexsort((rows, m.col))
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(m.col, minlength=n), out=rp[1:])
+    return Csr(n, rp.astype(np.int32), rows[order].astype(np.int32), m.val[order].copy(), m.name + "^T")
+
+
 def diagonal(n: int, seed: int = 0) -> Csr:
     return _assemble(n, np.zeros(0, np.int64), np.zeros(0, np.int64), np.random.default_rng(seed),
                      f"diag_n{n}_s{seed}")

@@ -59,6 +59,8 @@ typedef enum {
  * uses the wg_threads knob (256, 512 or 1024). */
 enum { SPTRSV_ORIGINAL = 0, SPTRSV_REWRITTEN = 1, SPTRSV_BATCH = 2 };
 enum { SPTRSV_THIN_ROWS = 0, SPTRSV_THIN_COST = 1 };
+/* Triangular forms a handle can solve (sptrsv_analyze_form). */
+enum { SPTRSV_LOWER = 0, SPTRSV_UPPER = 1, SPTRSV_LOWER_TRANS = 2, SPTRSV_UPPER_TRANS = 3 };
 
 /* Handle lifetime. create: makes a handle bound to the current HIP device.
  * destroy: frees every handle-owned buffer (NULL is accepted). */
@@ -85,6 +87,27 @@ const char *sptrsv_status_name(sptrsv_status_t s);
 sptrsv_status_t sptrsv_analyze(sptrsv_handle_t h, int32_t n, int32_t nnz, const int32_t *d_row_ptr,
                                const int32_t *d_col, const double *d_val, hipStream_t s,
                                int32_t *nlevels_out);
+
+/* ---------------------------------------------------------------------------
+ * sptrsv_analyze_form -- sptrsv_analyze for the other triangular systems a
+ * preconditioner application needs (the solve of Sec. II.A run the other way):
+ *   SPTRSV_LOWER        L x = b, the CSR is lower-triangular (= sptrsv_analyze)
+ *   SPTRSV_UPPER        U x = b, the CSR is upper-triangular with the diagonal
+ *                       first in each row and columns ascending
+ *   SPTRSV_LOWER_TRANS  L^T x = b, the CSR is lower-triangular (as above)
+ *   SPTRSV_UPPER_TRANS  U^T x = b, the CSR is upper-triangular (as above)
+ * The handle keeps the system in lower-triangular form: L; J U J and J L^T J
+ * (J reverses the order of rows and columns); U^T. Levels, statistics, the
+ * rewrite (Sec. II.B, Sec. III: for U and L^T it runs in reverse row order)
+ * and the getters refer to that form and its row numbering; sptrsv_solve and
+ * sptrsv_residual take b and return x in the caller's numbering of the
+ * original system. Arguments and errors as sptrsv_analyze (the input is
+ * checked in its own triangular form; an entry on the wrong side of the
+ * diagonal is NOT_LOWER), plus ARG for an unknown form. Synchronous. Replaces
+ * any previous analysis and rewrite held by the handle.
+ * ------------------------------------------------------------------------- */
+sptrsv_status_t sptrsv_analyze_form(sptrsv_handle_t h, int32_t form, int32_t n, int32_t nnz, const int32_t *d_row_ptr,
+                                    const int32_t *d_col, const double *d_val, hipStream_t s, int32_t *nlevels_out);
 
 /* Copy the level sets of the ORIGINAL matrix or of the REWRITTEN matrix L'
  * into caller buffers (device): level_ptr int32[nlev+1], level_rows int32[n]

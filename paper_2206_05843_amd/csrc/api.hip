@@ -237,7 +237,7 @@ sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs) {
 // level-ordered copy, optional T, statistics.
 sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
                            const double *va, const int32_t *trp, const int32_t *tci, const double *tva,
-                           hipStream_t s) {
+                           hipStream_t s, bool rev_io) {
   sptrsv_schedule_t keep_sched = P.ready ? P.sched : default_schedule();
   P = Plan{};
   P.sched = keep_sched;
@@ -290,6 +290,12 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
                                 h->scan_tmp.p, s));
   HIPCHK(h, launch_level_ptr_from_sorted(keys.p, n, P.level_ptr.p, nlev, s));
   HIPCHK(h, launch_invert_perm(P.perm.p, n, P.iperm.p, s));
+  if (rev_io) {
+    P.rev_io = true;
+    HIPCHK(h, P.perm_io.alloc(n));
+    HIPCHK(h, P.iperm_io.alloc(n));
+    HIPCHK(h, launch_rev_io(n, P.perm.p, P.iperm.p, P.perm_io.p, P.iperm_io.p, s));
+  }
   HIPCHK(h, launch_sub1(lev1.p, n, P.row_level.p, s));
   // level-ordered copy of the off-diagonals
   HIPCHK(h, launch_count_off(P.perm.p, rp, n, cnt.p, s));
@@ -319,7 +325,7 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
     P.nnz_t_off = tn;
     HIPCHK(h, P.tci.alloc((size_t)std::max(tn, 1)));
     HIPCHK(h, P.tva.alloc((size_t)std::max(tn, 1)));
-    HIPCHK(h, launch_fill_t(n, P.perm.p, trp, tci, tva, P.trp.p, P.tci.p, P.tva.p, s));
+    HIPCHK(h, launch_fill_t(n, P.perm.p, trp, tci, tva, P.trp.p, P.tci.p, P.tva.p, rev_io, s));
   }
   // statistics of the cost model
   HIPCHK(h, P.lv_rows.alloc(nlev));
@@ -416,9 +422,10 @@ sptrsv_status_t build_extra_hist(sptrsv_ctx *h, Plan &P, hipStream_t s) {
 // system b' = T b, where only the rows of T with off-diagonals differ from b:
 // those are recomputed from the caller's b after the plain gather.
 sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, hipStream_t s) {
-  HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, P.iperm.p, P.bp.p, s));
+  HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, io_iperm(P), P.bp.p, s));
   if (P.has_t && P.n_tpos > 0)
-    HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, P.perm.p, P.trp.p, P.tci.p, P.tva.p, b, ldb, P.bp.p, s));
+    HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, io_perm(P), P.trp.p, P.tci.p, P.tva.p, b, ldb,
+                             P.bp.p, s));
   return SPTRSV_OK;
 }
 
@@ -447,7 +454,7 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
     prof_end(h, slot, s);
   }
   slot = prof_begin(h, 3, vec_bytes, s);
-  HIPCHK(h, launch_scatter(P.n, nrhs, P.xp.p, P.iperm.p, x, ldx, s));
+  HIPCHK(h, launch_scatter(P.n, nrhs, P.xp.p, io_iperm(P), x, ldx, s));
   prof_end(h, slot, s);
   return SPTRSV_OK;
 }
@@ -521,36 +528,117 @@ sptrsv_status_t sptrsv_destroy(sptrsv_handle_t h) {
 
 const char *sptrsv_last_error(sptrsv_handle_t h) { return h ? h->last_error.c_str() : "null handle"; }
 
-sptrsv_status_t sptrsv_analyze(sptrsv_handle_t h, int32_t n, int32_t nnz, const int32_t *d_row_ptr,
-                               const int32_t *d_col, const double *d_val, hipStream_t s, int32_t *nlevels_out) {
+}  // extern "C"
+
+namespace {
+
+bool form_reversed(int32_t f) { return f == SPTRSV_UPPER || f == SPTRSV_LOWER_TRANS; }
+
+// Transpose of a CSR with sorted rows (stable sort of the entries by column).
+sptrsv_status_t transpose_csr(sptrsv_ctx *h, int32_t n, int32_t nnz, const int32_t *rp, const int32_t *ci,
+                              const double *va, int32_t *orp, int32_t *oci, double *ova, hipStream_t s) {
+  DArr<int32_t> keys, order, ktmp, vtmp, row_of, hist;
+  DArr<long long> hist64;
+  HIPCHK(h, keys.alloc(nnz));
+  HIPCHK(h, order.alloc(nnz));
+  HIPCHK(h, ktmp.alloc(nnz));
+  HIPCHK(h, vtmp.alloc(nnz));
+  HIPCHK(h, row_of.alloc(nnz));
+  const size_t hn = radix_hist_elems(nnz);
+  HIPCHK(h, hist.alloc(hn));
+  HIPCHK(h, hist64.alloc(hn));
+  const size_t scr = std::max(scan_scratch_elems((int64_t)hn), scan_scratch_elems(nnz)) + 16;
+  if (h->scan_tmp.n < scr) HIPCHK(h, h->scan_tmp.alloc(scr));
+  HIPCHK(h, hipMemcpyAsync(keys.p, ci, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, launch_iota(order.p, nnz, s));
+  HIPCHK(h, launch_radix_by_key(keys.p, order.p, ktmp.p, vtmp.p, nnz, bit_width(n), hist.p, hist64.p,
+                                h->scan_tmp.p, s));
+  HIPCHK(h, launch_ptr_from_sorted(keys.p, nnz, n, orp, s));
+  HIPCHK(h, launch_row_of_entry(n, rp, row_of.p, s));
+  HIPCHK(h, launch_take_entries(nnz, order.p, row_of.p, va, oci, ova, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return SPTRSV_OK;
+}
+
+// Validate the input in its own triangular form and store its lower form in
+// the handle: L as is; J U J; J L^T J; U^T (see k_form.hip).
+sptrsv_status_t analyze_form(sptrsv_ctx *h, int32_t form, int32_t n, int32_t nnz, const int32_t *d_row_ptr,
+                             const int32_t *d_col, const double *d_val, hipStream_t s, int32_t *nlevels_out) {
   if (!h) return SPTRSV_ERR_ARG;
   h->last_error.clear();
+  if (form < SPTRSV_LOWER || form > SPTRSV_UPPER_TRANS) return set_err(h, SPTRSV_ERR_ARG, "analyze: form %d", form);
   if (n < 0 || nnz < 0 || !d_row_ptr || (nnz > 0 && (!d_col || !d_val)))
     return set_err(h, SPTRSV_ERR_ARG, "analyze: n=%d nnz=%d", n, nnz);
   if (nnz < n) return set_err(h, SPTRSV_ERR_MISSING_DIAG, "analyze: nnz %d < n %d", nnz, n);
   h->orig.ready = false;
   h->rew.ready = false;
   h->has_rewrite = false;
+  const bool upper_in = form == SPTRSV_UPPER || form == SPTRSV_UPPER_TRANS;
+  const bool trans = form == SPTRSV_LOWER_TRANS || form == SPTRSV_UPPER_TRANS;
+  // the input as a lower matrix: itself, or its reversal for an upper input
+  DArr<int32_t> r_rp, r_ci;
+  DArr<double> r_va;
+  const int32_t *lrp = d_row_ptr, *lci = d_col;
+  const double *lva = d_val;
+  if (upper_in) {
+    HIPCHK(h, r_rp.alloc((size_t)n + 1));
+    HIPCHK(h, r_ci.alloc((size_t)std::max(nnz, 1)));
+    HIPCHK(h, r_va.alloc((size_t)std::max(nnz, 1)));
+    HIPCHK(h, launch_rev_entries(n, nnz, d_row_ptr, d_col, d_val, r_rp.p, r_ci.p, r_va.p, s));
+    lrp = r_rp.p;
+    lci = r_ci.p;
+    lva = r_va.p;
+  }
   int32_t *aux = h->d_aux.p;
   HIPCHK(h, hipMemsetAsync(aux + 1, 0, sizeof(int32_t), s));
-  HIPCHK(h, launch_validate(n, nnz, d_row_ptr, d_col, d_val, aux + 1, s));
+  HIPCHK(h, launch_validate(n, nnz, lrp, lci, lva, aux + 1, s));
   int32_t bits = 0;
   HIPCHK(h, hipMemcpyAsync(&bits, aux + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
-  if (bits) return set_err(h, status_from_bits(bits), "analyze: invalid matrix (bits 0x%x)", bits);
+  if (bits)
+    return set_err(h, status_from_bits(bits), "analyze: invalid %s matrix (bits 0x%x)",
+                   upper_in ? "upper-triangular" : "lower-triangular", bits);
   h->n = n;
   h->nnz = nnz;
+  h->form = form;
   HIPCHK(h, h->rp.alloc((size_t)n + 1));
   HIPCHK(h, h->ci.alloc((size_t)std::max(nnz, 1)));
   HIPCHK(h, h->va.alloc((size_t)std::max(nnz, 1)));
-  HIPCHK(h, hipMemcpyAsync(h->rp.p, d_row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
-  if (nnz) {
-    HIPCHK(h, hipMemcpyAsync(h->ci.p, d_col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
-    HIPCHK(h, hipMemcpyAsync(h->va.p, d_val, sizeof(double) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+  if (!trans) {
+    HIPCHK(h, hipMemcpyAsync(h->rp.p, lrp, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz) {
+      HIPCHK(h, hipMemcpyAsync(h->ci.p, lci, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+      HIPCHK(h, hipMemcpyAsync(h->va.p, lva, sizeof(double) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+    }
+  } else if (n > 0) {
+    // (lower)^T is upper; its reversal is the lower form
+    DArr<int32_t> t_rp, t_ci;
+    DArr<double> t_va;
+    HIPCHK(h, t_rp.alloc((size_t)n + 1));
+    HIPCHK(h, t_ci.alloc((size_t)std::max(nnz, 1)));
+    HIPCHK(h, t_va.alloc((size_t)std::max(nnz, 1)));
+    STCHK(transpose_csr(h, n, nnz, lrp, lci, lva, t_rp.p, t_ci.p, t_va.p, s));
+    HIPCHK(h, launch_rev_entries(n, nnz, t_rp.p, t_ci.p, t_va.p, h->rp.p, h->ci.p, h->va.p, s));
+  } else {
+    HIPCHK(h, hipMemsetAsync(h->rp.p, 0, sizeof(int32_t), s));
   }
-  STCHK(build_plan(h, h->orig, n, nnz, h->rp.p, h->ci.p, h->va.p, nullptr, nullptr, nullptr, s));
+  STCHK(build_plan(h, h->orig, n, nnz, h->rp.p, h->ci.p, h->va.p, nullptr, nullptr, nullptr, s, form_reversed(form)));
   if (nlevels_out) *nlevels_out = h->orig.nlev;
   return SPTRSV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sptrsv_status_t sptrsv_analyze(sptrsv_handle_t h, int32_t n, int32_t nnz, const int32_t *d_row_ptr,
+                               const int32_t *d_col, const double *d_val, hipStream_t s, int32_t *nlevels_out) {
+  return analyze_form(h, SPTRSV_LOWER, n, nnz, d_row_ptr, d_col, d_val, s, nlevels_out);
+}
+
+sptrsv_status_t sptrsv_analyze_form(sptrsv_handle_t h, int32_t form, int32_t n, int32_t nnz, const int32_t *d_row_ptr,
+                                    const int32_t *d_col, const double *d_val, hipStream_t s, int32_t *nlevels_out) {
+  return analyze_form(h, form, n, nnz, d_row_ptr, d_col, d_val, s, nlevels_out);
 }
 
 
@@ -689,7 +777,7 @@ sptrsv_status_t sptrsv_residual(sptrsv_handle_t h, int32_t nrhs, const double *d
   if (nrhs < 1 || nrhs > 56 || ldb < h->n || ldx < h->n) return set_err(h, SPTRSV_ERR_ARG, "residual args");
   unsigned long long *out = reinterpret_cast<unsigned long long *>(h->d_aux.p + 128);
   HIPCHK(h, hipMemsetAsync(out, 0, sizeof(unsigned long long) * (size_t)nrhs, s));
-  HIPCHK(h, launch_residual(h->n, nrhs, h->rp.p, h->ci.p, h->va.p, d_b, ldb, d_x, ldx, out, s));
+  HIPCHK(h, launch_residual(h->n, nrhs, h->rp.p, h->ci.p, h->va.p, d_b, ldb, d_x, ldx, out, h->orig.rev_io, s));
   std::vector<unsigned long long> hv((size_t)nrhs);
   HIPCHK(h, hipMemcpyAsync(hv.data(), out, sizeof(unsigned long long) * (size_t)nrhs, hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));

@@ -139,7 +139,8 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
     }
   }
   // re-level L' (empty levels disappear) and build its solve plan with T
-  STCHK(build_plan(h, h->rew, n, nnz_lp, h->lp_rp.p, h->lp_ci.p, h->lp_va.p, h->t_rp.p, h->t_ci.p, h->t_va.p, s));
+  STCHK(build_plan(h, h->rew, n, nnz_lp, h->lp_rp.p, h->lp_ci.p, h->lp_va.p, h->t_rp.p, h->t_ci.p, h->t_va.p, s,
+                   h->orig.rev_io));
   sptrsv_rewrite_stats_t r{};
   r.nlev_before = nlev;
   r.nlev_after = h->rew.nlev;

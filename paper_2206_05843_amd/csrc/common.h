@@ -93,6 +93,10 @@ struct Plan {
   DArr<int32_t> level_ptr;             // [nlev+1] positions
   DArr<int32_t> perm;                  // [n] position -> row (= level_rows)
   DArr<int32_t> iperm;                 // [n] row -> position
+  // reversed systems (U x = b, L^T x = b): the caller's numbering is the
+  // reverse of the lower form's; these maps replace perm/iperm for b and x
+  bool rev_io = false;
+  DArr<int32_t> perm_io, iperm_io;
   DArr<int32_t> row_level;             // [n]
   std::vector<int32_t> h_level_ptr;    // host copy for scheduling
   DArr<int32_t> srp, sci;              // level-ordered off-diagonal CSR
@@ -131,6 +135,10 @@ struct Plan {
   int32_t work_nrhs = 0;
 };
 
+// Index maps between positions and the caller's rows.
+inline const int32_t *io_perm(const Plan &P) { return P.rev_io ? P.perm_io.p : P.perm.p; }
+inline const int32_t *io_iperm(const Plan &P) { return P.rev_io ? P.iperm_io.p : P.iperm.p; }
+
 struct BatchMat {
   int32_t n;
   int64_t row_off, nnz_off;
@@ -146,7 +154,9 @@ struct sptrsv_ctx {
   std::string last_error;
   DArr<int32_t> d_err;     // latched error bits of solves
   DArr<int32_t> d_aux;     // small scratch: counters, tickets, maxima
-  // original matrix (owned copy)
+  // the matrix in lower-triangular form (owned; for the other triangular forms
+  // its conversion, see form)
+  int32_t form = SPTRSV_LOWER;
   int32_t n = 0;
   int64_t nnz = 0;
   DArr<int32_t> rp, ci;
@@ -222,8 +232,9 @@ hipError_t launch_ptr_from_scan(const long long *ex, const long long *cnt, int32
 hipError_t launch_fill_solve(int32_t n, const int32_t *perm, const int32_t *iperm, const int32_t *rp,
                              const int32_t *ci, const double *va, const int32_t *srp, int32_t *sci, double *sva,
                              double *sdg, hipStream_t s);
+// rev: T's columns go to the caller's numbering of a reversed system (n-1-c)
 hipError_t launch_fill_t(int32_t n, const int32_t *perm, const int32_t *trp, const int32_t *tci,
-                         const double *tva, const int32_t *strp, int32_t *stci, double *stva, hipStream_t s);
+                         const double *tva, const int32_t *strp, int32_t *stci, double *stva, bool rev, hipStream_t s);
 hipError_t launch_level_stats(int32_t nlev, const int32_t *level_ptr, const int32_t *srp, int64_t *rows,
                               int64_t *nnz, int64_t *cost, long long *total, hipStream_t s);
 
@@ -300,9 +311,10 @@ hipError_t launch_wide_run(int grid, int threads, int32_t l0, int32_t l1, const 
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                            const double *bp, double *xp, unsigned *bar, int *err, hipStream_t s);
 int wide_run_resident_blocks(int threads);
+// rev: b and x in the reversed (caller's) numbering of the lower form
 hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,
                            const double *b, int64_t ldb, const double *x, int64_t ldx, unsigned long long *out,
-                           hipStream_t s);
+                           bool rev, hipStream_t s);
 void solve_kernels_init();
 
 // Launchers (k_rewrite.hip) ----------------------------------------------------
@@ -385,7 +397,16 @@ sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs);
 // Plan building (api.hip) --------------------------------------------------------
 sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
                            const double *va, const int32_t *trp, const int32_t *tci, const double *tva,
-                           hipStream_t s);
+                           hipStream_t s, bool rev_io = false);
+// Triangular forms (k_form.hip) ---------------------------------------------------
+hipError_t launch_rev_entries(int32_t n, int32_t nnz, const int32_t *rp, const int32_t *ci, const double *va,
+                              int32_t *orp, int32_t *oci, double *ova, hipStream_t s);
+hipError_t launch_row_of_entry(int32_t n, const int32_t *rp, int32_t *row_of, hipStream_t s);
+hipError_t launch_ptr_from_sorted(const int32_t *keys, int32_t nnz, int32_t n, int32_t *ptr, hipStream_t s);
+hipError_t launch_take_entries(int32_t nnz, const int32_t *order, const int32_t *row_of, const double *va,
+                               int32_t *oci, double *ova, hipStream_t s);
+hipError_t launch_rev_io(int32_t n, const int32_t *perm, const int32_t *iperm, int32_t *perm_io, int32_t *iperm_io,
+                         hipStream_t s);
 ThinArgs thin_args(const Plan &P);
 sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, hipStream_t s);
 sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,

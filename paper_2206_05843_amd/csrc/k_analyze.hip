@@ -284,7 +284,7 @@ __global__ void k_fill_solve(int32_t n, const int32_t *__restrict__ perm, const 
 }
 
 __global__ void k_fill_t(int32_t n, const int32_t *__restrict__ perm, const int32_t *__restrict__ trp,
-                         const int32_t *__restrict__ tci,
+                         const int32_t *__restrict__ tci, int rev,
                          const double *__restrict__ tva, const int32_t *__restrict__ strp, int32_t *stci,
                          double *stva) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
@@ -292,7 +292,7 @@ __global__ void k_fill_t(int32_t n, const int32_t *__restrict__ perm, const int3
     const int32_t b = trp[r], e = trp[r + 1] - 1;  // last entry is the unit diagonal
     int32_t o = strp[p];
     for (int32_t q = b; q < e; ++q, ++o) {
-      stci[o] = tci[q];  // columns stay in the caller's numbering: b is read there
+      stci[o] = rev ? n - 1 - tci[q] : tci[q];  // columns in the caller's numbering: b is read there
       stva[o] = tva[q];
     }
   }
@@ -439,9 +439,9 @@ hipError_t launch_fill_solve(int32_t n, const int32_t *perm, const int32_t *iper
 }
 
 hipError_t launch_fill_t(int32_t n, const int32_t *perm, const int32_t *trp, const int32_t *tci,
-                         const double *tva, const int32_t *strp, int32_t *stci, double *stva, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_t, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, perm, trp, tci, tva, strp,
-                     stci, stva);
+                         const double *tva, const int32_t *strp, int32_t *stci, double *stva, bool rev, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_t, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, perm, trp, tci, rev ? 1 : 0,
+                     tva, strp, stci, stva);
   return hipGetLastError();
 }
 

@@ -110,13 +110,13 @@ __global__ void k_scatter1(int32_t n, const double *__restrict__ xp, const int32
 // patterns of non-negative doubles (monotone as unsigned integers).
 __global__ void k_residual(int32_t n, int32_t nrhs, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                            const double *__restrict__ va, const double *__restrict__ b, int64_t ldb,
-                           const double *__restrict__ x, int64_t ldx, unsigned long long *out) {
+                           const double *__restrict__ x, int64_t ldx, int rev, unsigned long long *out) {
   for (int32_t c = 0; c < nrhs; ++c) {
     double m = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
       double s = 0.0;
-      for (int32_t q = rp[r]; q < rp[r + 1]; ++q) s += va[q] * x[(int64_t)c * ldx + ci[q]];
-      const double d = fabs(s - b[(int64_t)c * ldb + r]);
+      for (int32_t q = rp[r]; q < rp[r + 1]; ++q) s += va[q] * x[(int64_t)c * ldx + (rev ? n - 1 - ci[q] : ci[q])];
+      const double d = fabs(s - b[(int64_t)c * ldb + (rev ? n - 1 - r : r)]);
       m = (d > m || d != d) ? d : m;
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -236,10 +236,10 @@ hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32
 
 hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,
                            const double *b, int64_t ldb, const double *x, int64_t ldx, unsigned long long *out,
-                           hipStream_t s) {
+                           bool rev, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_residual, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, nrhs, rp, ci, va, b, ldb, x,
-                     ldx, out);
+                     ldx, rev ? 1 : 0, out);
   return hipGetLastError();
 }
 

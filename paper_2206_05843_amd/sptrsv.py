@@ -16,13 +16,14 @@ LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
 
 ORIGINAL, REWRITTEN, BATCH = 0, 1, 2
 THIN_ROWS, THIN_COST = 0, 1
+LOWER, UPPER, LOWER_TRANS, UPPER_TRANS = 0, 1, 2, 3  # triangular forms (sptrsv_analyze_form)
 MLP_NPARAM = 5313
 
 STATUS_NAMES = ["OK", "ARG", "STATE", "NOT_LOWER", "UNSORTED", "MISSING_DIAG", "ZERO_PIVOT", "NONFINITE",
                 "OVERFLOW", "ALLOC", "HIP", "TIMEOUT"]
 
 EXPORTS = [
-    "sptrsv_create", "sptrsv_destroy", "sptrsv_last_error", "sptrsv_status_name", "sptrsv_analyze",
+    "sptrsv_create", "sptrsv_destroy", "sptrsv_last_error", "sptrsv_status_name", "sptrsv_analyze", "sptrsv_analyze_form",
     "sptrsv_get_levels", "sptrsv_level_stats", "sptrsv_rewrite", "sptrsv_get_rewritten", "sptrsv_get_targets",
     "sptrsv_solve", "sptrsv_prepare", "sptrsv_check", "sptrsv_set_schedule", "sptrsv_get_schedule",
     "sptrsv_autotune", "sptrsv_graph_create", "sptrsv_graph_launch", "sptrsv_residual", "sptrsv_batch_analyze",
@@ -88,6 +89,7 @@ def lib():
         "sptrsv_create": [C.POINTER(vp)],
         "sptrsv_destroy": [vp],
         "sptrsv_analyze": [vp, i32, i32, vp, vp, vp, vp, C.POINTER(i32)],
+        "sptrsv_analyze_form": [vp, i32, i32, i32, vp, vp, vp, vp, C.POINTER(i32)],
         "sptrsv_get_levels": [vp, C.c_int, vp, vp, vp, vp],
         "sptrsv_level_stats": [vp, C.c_int, vp, vp, vp, C.POINTER(i64), C.POINTER(dbl), vp],
         "sptrsv_rewrite": [vp, C.POINTER(RewriteOpts), vp, C.POINTER(RewriteStats)],
@@ -207,14 +209,17 @@ class Handle:
             raise SptrsvError(st, self._L.sptrsv_last_error(self._h).decode())
 
     # ------------------------------------------------------------------ analysis
-    def analyze(self, row_ptr, col, val) -> int:
+    def analyze(self, row_ptr, col, val, form=LOWER) -> int:
+        """form: LOWER (L x = b), UPPER (U x = b), LOWER_TRANS (L^T x = b, given
+        L) or UPPER_TRANS (U^T x = b, given U); solves take and return b, x in
+        the caller's numbering."""
         _need(row_ptr.dtype == torch.int32 and col.dtype == torch.int32 and val.dtype == torch.float64,
               "int32 row_ptr/col and float64 val expected")
         n = row_ptr.numel() - 1
         nnz = col.numel()
         nl = C.c_int32(0)
-        self._check(self._L.sptrsv_analyze(self._h, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val), _stream(),
-                                           C.byref(nl)))
+        self._check(self._L.sptrsv_analyze_form(self._h, int(form), n, nnz, _ptr(row_ptr), _ptr(col), _ptr(val),
+                                                _stream(), C.byref(nl)))
         self.n, self.nlev, self.rstats = n, nl.value, None
         return nl.value
 

@@ -39,6 +39,8 @@ WORKLOADS = {
     2: "power-law (Zipf 1.2 in-degree) lower CSR, n=4,000,000, mean 8 off-diagonals/row, nrhs=1",
     3: "512 window-64 random lower CSR matrices, n_i uniform in [1000, 50000], ~6 nnz/row, nrhs=16 each",
     4: "3D 200^3 7-point lower factor + 5,000-row tail, n=8,005,000, nnz=31,900,000, nrhs=32",
+    5: "preconditioner application z = L^-T L^-1 r (incomplete-Cholesky style) with the 3D 200^3 7-point lower "
+       "factor + 5,000-row tail, n=8,005,000, nnz=31,900,000, nrhs=32",
 }
 GRAPH_DEFAULT = {4}  # workloads timed as hipGraph replays of the solve
 
@@ -195,6 +197,114 @@ def bench_batch(args, np, torch, gen, oracle, sp):
     print(json.dumps(res), flush=True)
 
 
+def bench_precond(args, np, torch, gen, oracle, sp):
+    """One step = z = L^-T (L^-1 r): a forward solve with L and a transposed
+    solve with the same factor (sptrsv_analyze_form, LOWER_TRANS), each
+    rewritten by the naive rule and autotuned, replayed as hipGraphs."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    m, nrhs = gen.config_matrix(4)
+    r_np = gen.rhs(m, nrhs)
+    t0 = time.perf_counter()
+    z_ref = oracle.solve_form(m, oracle.solve(m, r_np), oracle.LOWER_TRANS)
+    t_oracle = time.perf_counter() - t0
+    log(f"[bench] oracle application {t_oracle:.1f}s")
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (m.row_ptr, m.col, m.val))
+    r = torch.from_numpy(r_np).to(dev)
+    out_var = {}
+    best = None
+    for name, rewrite in (("plain", False), ("naive", True)):
+        hs, info = [], {}
+        y = torch.empty_like(r)
+        z = torch.empty_like(r)
+        for form in (sp.LOWER, sp.LOWER_TRANS):
+            h = sp.Handle()
+            nlev = h.analyze(rp, ci, va, form=form)
+            which = sp.ORIGINAL
+            key = "L" if form == sp.LOWER else "LT"
+            info[f"nlev_{key}"] = nlev
+            if rewrite:
+                st = h.rewrite(sp.THIN_ROWS, 32, 4.0, 0)
+                which = sp.REWRITTEN
+                info[f"nlev_{key}"] = st["nlev_after"]
+                info[f"nnz_T_{key}"] = st["nnz_T"]
+            h.autotune(which, nrhs)
+            info[f"schedule_{key}"] = h.get_schedule(which, nrhs)
+            hs.append((h, which))
+        hs[0][0].solve(r, hs[0][1], y)
+        hs[1][0].solve(y, hs[1][1], z)
+        for h, _ in hs:
+            h.check()
+        info["relerr"] = oracle.relerr(z.cpu().numpy(), z_ref)
+        if not info["relerr"] <= TOL:
+            raise SystemExit(f"[bench] {name} application failed parity: relerr={info['relerr']:.3e}")
+        g0 = hs[0][0].graph_create(r, y, hs[0][1])
+        g1 = hs[1][0].graph_create(y, z, hs[1][1])
+        for _ in range(args.warmup):
+            hs[0][0].graph_launch(g0)
+            hs[1][0].graph_launch(g1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            hs[0][0].graph_launch(g0)
+            hs[1][0].graph_launch(g1)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        # per-kernel-class profile of as many eager applications
+        for h, _ in hs:
+            h.profile_start()
+        for _ in range(args.steps):
+            hs[0][0].solve(r, hs[0][1], y)
+            hs[1][0].solve(y, hs[1][1], z)
+        torch.cuda.synchronize()
+        prof = {}
+        for h, _ in hs:
+            for k, v in h.profile_stop().items():
+                if k == "in_timed_region":
+                    continue
+                acc = prof.setdefault(k, {"launches": 0, "ms": 0.0, "bytes": 0.0})
+                for f in ("launches", "ms", "bytes"):
+                    acc[f] += v[f]
+        for h, _ in hs:
+            h.check()
+        info["ms"] = ms
+        info["profile"] = prof
+        out_var[name] = info
+        log(f"[bench] {name}: {ms:.3f} ms per application, relerr {info['relerr']:.2e}")
+        if best is None or ms < out_var[best]["ms"]:
+            best = name
+    head = out_var[best]
+    prof = head["profile"]
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    dp = prof[dom]
+    per_launch_ms = dp["ms"] / max(1, dp["launches"])
+    bpl = dp["bytes"] / max(1, dp["launches"])
+    achieved = bpl / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+    kname = {"thin_run": "k_thin_run", "wide_level": "k_wide_level", "gather": "k_gather", "scatter": "k_scatter"}[dom]
+    cpu = None
+    if not args.no_cpu:
+        cpu = {"value": round(1.0 / t_oracle, 5), "unit": "applications/s", "cores": 1, "kind": "oracle",
+               "sample": f"one application (forward and transposed substitution, {nrhs} right-hand sides) by the "
+                         f"serial FP64 oracle ({t_oracle:.1f}s, includes its transpose of L)"}
+    res = {
+        "metric": "preconditioner applications/s (z = L^-T L^-1 r), relerr<=1e-10",
+        "value": round(1e3 / head["ms"], 3), "unit": "applications/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(head["ms"], 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator of the workload's structure; no dataset)",
+        "config": {"workload": WORKLOADS[5], "variant": best, "nrhs": nrhs, "n": m.n, "nnz": m.nnz,
+                   "parallelism": "single GPU", "timing": "hipGraph replays (one graph per solve)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": load_traffic(kname, "config5_" + best),
+                     "kernel": kname, "launches": dp["launches"], "avg_launch_ms": round(per_launch_ms, 5),
+                     "alg_bytes_per_launch": bpl, "events": "eager applications after the timed region"},
+        "cpu_baseline": cpu,
+        "variants": {k: {kk: (round(vv, 5) if isinstance(vv, float) and kk != "relerr" else vv)
+                         for kk, vv in v.items() if kk != "profile"} for k, v in out_var.items()},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def calibrate_copy(torch, mib):
     """Ten device-to-device copies of a buffer of known size: the FETCH_SIZE and
     WRITE_SIZE counters of these launches scale the counters of the solve
@@ -246,6 +356,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.config == 3:
         bench_batch(args, np, torch, gen, oracle, sp)
+        return
+    if args.config == 5:
+        bench_precond(args, np, torch, gen, oracle, sp)
         return
     use_graph = (args.config in GRAPH_DEFAULT) if args.graph is None else bool(args.graph)
     stream = torch.cuda.Stream()  # graph capture needs a non-default stream

@@ -62,7 +62,8 @@ def alg_bytes(n, nnz, nlev, nrhs, nnz_t=0, rewritten=False):
 # Sources whose text decides what a kernel reads and writes (thin runs read
 # the window images k_image.hip builds).
 KERNEL_SOURCE = {"k_thin_run": ("k_thin.hip", "k_image.hip"), "k_batch_run": ("k_thin.hip", "k_image.hip"),
-                 "k_wide_level": ("k_wide.hip",), "k_gather": ("k_vec.hip",), "k_scatter": ("k_vec.hip",)}
+                 "k_wide_level": ("k_wide.hip",), "k_gather": ("k_vec.hip",), "k_scatter": ("k_vec.hip",),
+                 "k_sf_solve": ("k_syncfree.hip",)}
 
 
 def source_hash(kernel):
@@ -487,6 +488,8 @@ def main():
     achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     kname = {"thin_run": "k_thin_run", "wide_level": "k_wide_level", "gather": "k_gather",
              "scatter": "k_scatter"}[dom]
+    if dom == "wide_level" and variants[headline][2]["schedule"]["mode"] == 3:
+        kname = "k_sf_solve"  # the synchronisation-free launch is profiled with the device-wide class
     traffic = load_traffic(kname, f"config{args.config}_{headline}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic, "kernel": kname,

@@ -203,7 +203,11 @@ sptrsv_status_t sptrsv_check(sptrsv_handle_t h, hipStream_t s);
  * thin_rows rows runs inside one workgroup of wg_threads threads, together with
  * its thin neighbours; wider levels get one multi-workgroup launch each with
  * wide_threads threads per workgroup. mode: 0 = split at thin_rows,
- * 1 = every level as a wide launch, 2 = every level inside one workgroup.
+ * 1 = every level as a wide launch, 2 = every level inside one workgroup,
+ * 3 = no level barriers at all: one synchronisation-free launch in which each
+ * (row, right-hand side) waits only for the values it reads (the comparison
+ * executor; wide_grid gives its workgroups of 256 threads, 0 = 512, at most
+ * 2048; the other knobs are ignored).
  * set_schedule replaces the schedules sptrsv_autotune picked for this matrix;
  * get_schedule reports the schedule a solve with nrhs right-hand sides uses
  * (the tuned one for that nrhs if there is one, else the one set). */

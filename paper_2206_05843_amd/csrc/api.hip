@@ -61,7 +61,7 @@ bool same_sched(const sptrsv_schedule_t &a, const sptrsv_schedule_t &b) {
 }
 
 sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
-  if (s.mode < 0 || s.mode > 2) return set_err(h, SPTRSV_ERR_ARG, "schedule mode %d", s.mode);
+  if (s.mode < 0 || s.mode > 3) return set_err(h, SPTRSV_ERR_ARG, "schedule mode %d", s.mode);
   if (s.wg_threads != 256 && s.wg_threads != 512 && s.wg_threads != 1024)
     return set_err(h, SPTRSV_ERR_ARG, "wg_threads %d", s.wg_threads);
   if (s.wide_threads < 64 || s.wide_threads > 1024 || s.wide_threads % 64)
@@ -71,6 +71,9 @@ sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
     return set_err(h, SPTRSV_ERR_ARG, "lanes_per_row %d", g);
   if (s.thin_rows < 0) return set_err(h, SPTRSV_ERR_ARG, "thin_rows %d", s.thin_rows);
   if (s.wide_grid < 0 || s.wide_grid > 65536) return set_err(h, SPTRSV_ERR_ARG, "wide_grid %d", s.wide_grid);
+  if (s.mode == 3 && s.wide_grid > 2048)
+    return set_err(h, SPTRSV_ERR_ARG, "wide_grid %d: the synchronisation-free launch takes at most 2048 workgroups",
+                   s.wide_grid);
   return SPTRSV_OK;
 }
 
@@ -313,6 +316,7 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   HIPCHK(h, hipMemsetAsync(P.wbar.p, 0, 2 * sizeof(unsigned), s));
   HIPCHK(h, P.tp.alloc(4));
   HIPCHK(h, hipMemsetAsync(P.tp.p, 0, 4 * sizeof(unsigned), s));
+  HIPCHK(h, P.sf_ticket.alloc(1));
   if (trp) {
     P.has_t = true;
     HIPCHK(h, P.trp.alloc((size_t)n + 1));
@@ -440,7 +444,14 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
   int slot = prof_begin(h, 0, vec_bytes + (P.has_t ? 12.0 * (double)P.nnz_t_off + 4.0 * P.n : 0.0), s);
   STCHK(gather_b(h, P, nrhs, b, ldb, s));
   prof_end(h, slot, s);
+  if (sc.mode == 3) {  // synchronisation-free: one launch for the whole solve (profiled with the wide class)
+    slot = h->prof ? prof_begin(h, 2, run_bytes(P, 0, P.nlev, nrhs), s) : -1;
+    HIPCHK(h, launch_syncfree(P.n, nrhs, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.bp.p, P.xp.p, P.sf_ticket.p, err,
+                              sc.wide_grid, s));
+    prof_end(h, slot, s);
+  }
   for (const Run &r : P.runs) {
+    if (sc.mode == 3) break;
     slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
     if (r.thin) {
       HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, thin_args(P), err, s));

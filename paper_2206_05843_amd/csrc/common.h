@@ -131,6 +131,7 @@ struct Plan {
   sptrsv_schedule_t runs_sched{};
   DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
   DArr<unsigned> tp;                   // [4] thin-run launches: epoch, progress, helper sink
+  DArr<unsigned long long> sf_ticket;  // [1] ticket counter of the synchronisation-free solve
   DArr<unsigned> wbar;                 // [2] barrier counters of persistent wide runs (zero between launches)
   int32_t work_nrhs = 0;
 };
@@ -398,6 +399,11 @@ sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs);
 sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
                            const double *va, const int32_t *trp, const int32_t *tci, const double *tva,
                            hipStream_t s, bool rev_io = false);
+// Synchronisation-free solve of the whole plan (k_syncfree.hip): bp -> xp.
+// blocks: workgroups of 256 threads (0: 512).
+hipError_t launch_syncfree(int32_t n, int32_t nrhs, const int32_t *srp, const int32_t *sci, const double *sva,
+                           const double *sdg, const double *bp, double *xp, unsigned long long *ticket, int *err,
+                           int32_t blocks, hipStream_t s);
 // Triangular forms (k_form.hip) ---------------------------------------------------
 hipError_t launch_rev_entries(int32_t n, int32_t nnz, const int32_t *rp, const int32_t *ci, const double *va,
                               int32_t *orp, int32_t *oci, double *ova, hipStream_t s);

@@ -1,0 +1,132 @@
+// Synchronisation-free forward substitution (Algorithm 1 without level
+// barriers): every (row, right-hand side) item waits only for the x values it
+// reads. It is the comparison executor for the level-set schedules, and a
+// schedule the autotuner can pick (mode 3).
+//
+// Items are taken in level order (positions of the level-ordered copy) from a
+// ticket counter, 64 per wave; a row's dependencies sit at smaller positions,
+// so they were claimed earlier by a running wave and every wait ends. x starts
+// as a signalling-NaN pattern that arithmetic never produces (division quiets
+// every NaN), so one device-coherent 64-bit load returns both "done" and the
+// value. A lane requests its next four dependencies' values at once and takes
+// the ready ones in column order, so the sum keeps the row's order. A wave
+// none of whose lanes moved in an iteration sleeps briefly before it polls
+// again, and the launch is kept to a few thousand waves: the waiting lanes'
+// polling otherwise saturates the memory system and slows every hop (on a
+// 4M-row power-law matrix, 8,192 waves without the pause ran past the time
+// limit; 2,048 waves with it solve in 5 ms). Waits are bounded by the device
+// wall clock (timeout error).
+#include "common.h"
+
+namespace {
+
+constexpr unsigned long long kPending = 0x7ff4dead5eed5a1dull;
+constexpr int kBlock = 256;
+constexpr int kDeps = 4;
+
+__global__ void k_sf_init(int64_t total, unsigned long long *xb, unsigned long long *ticket) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    xb[i] = kPending;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0ull;
+}
+
+template <bool kOne>
+__global__ __launch_bounds__(kBlock) void k_sf_solve(int32_t n, int32_t nrhs, const int32_t *__restrict__ srp,
+                                                     const int32_t *__restrict__ sci, const double *__restrict__ sva,
+                                                     const double *__restrict__ sdg, const double *__restrict__ bp,
+                                                     double *xp, unsigned long long *ticket, int *err,
+                                                     unsigned long long tlimit) {
+  const int lane = threadIdx.x & 63;
+  const int32_t nr = kOne ? 1 : nrhs;
+  const int64_t total = (int64_t)n * nr;
+  unsigned long long *xb = reinterpret_cast<unsigned long long *>(xp);
+  const unsigned long long t0 = wall_clock64();
+  int bits = 0;
+  bool timed_out = false;
+  while (!timed_out) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(ticket, 64ull);
+    base = __shfl(base, 0, 64);
+    if ((int64_t)base >= total) break;
+    const int64_t it = (int64_t)base + lane;
+    bool pend = it < total;
+    int32_t q = 0, qe = 0, c = 0;
+    double acc = 0.0, d = 1.0;
+    if (pend) {
+      const int32_t pos = kOne ? (int32_t)it : (int32_t)(it / nr);
+      c = kOne ? 0 : (int32_t)(it - (int64_t)pos * nr);
+      q = srp[pos];
+      qe = srp[pos + 1];
+      acc = bp[it];
+      d = sdg[pos];
+    }
+    unsigned spins = 0;
+    while (__ballot(pend) != 0ull) {
+      bool moved = false;
+      if (pend) {
+        const int32_t q_in = q;
+        while (q < qe) {
+          const int32_t cnt = qe - q < kDeps ? qe - q : kDeps;
+          int32_t k[kDeps];
+          double w[kDeps];
+          unsigned long long v[kDeps];
+#pragma unroll
+          for (int j = 0; j < kDeps; ++j) {
+            const int32_t qq = q + (j < cnt ? j : 0);
+            k[j] = sci[qq];
+            w[j] = sva[qq];
+          }
+#pragma unroll
+          for (int j = 0; j < kDeps; ++j)
+            v[j] = __hip_atomic_load(xb + (int64_t)k[j] * nr + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          int32_t done = 0;
+#pragma unroll
+          for (int j = 0; j < kDeps; ++j) {
+            if (j < cnt && done == j && v[j] != kPending) {
+              acc -= w[j] * __longlong_as_double((long long)v[j]);
+              done = j + 1;
+            }
+          }
+          q += done;
+          if (done < cnt) break;  // a dependency is still pending
+        }
+        moved = q != q_in;
+        if (q == qe) {
+          const double x = acc / d;
+          if (!isfinite(x)) bits |= EB_NONFINITE;
+          __hip_atomic_store(xb + it, (unsigned long long)__double_as_longlong(x), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          pend = false;
+          moved = true;
+        }
+      }
+      if (__ballot(moved) == 0ull) __builtin_amdgcn_s_sleep(8);
+      if ((++spins & 63u) == 0u && wall_clock64() - t0 > tlimit) {
+        bits |= EB_TIMEOUT;
+        timed_out = true;
+        break;
+      }
+    }
+  }
+  if (bits) atomicOr(err, bits);
+}
+
+}  // namespace
+
+hipError_t launch_syncfree(int32_t n, int32_t nrhs, const int32_t *srp, const int32_t *sci, const double *sva,
+                           const double *sdg, const double *bp, double *xp, unsigned long long *ticket, int *err,
+                           int32_t blocks, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t total = (int64_t)n * nrhs;
+  unsigned long long *xb = reinterpret_cast<unsigned long long *>(xp);
+  hipLaunchKernelGGL(k_sf_init, dim3(grid_for(total, kBlock, 8192)), dim3(kBlock), 0, s, total, xb, ticket);
+  const unsigned long long limit = 100000000ull * 10;  // 10 s of the 100 MHz wall clock
+  const dim3 grid(grid_for(total, kBlock, blocks > 0 ? blocks : 512));
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_sf_solve<true>, grid, dim3(kBlock), 0, s, n, nrhs, srp, sci, sva, sdg, bp, xp, ticket, err,
+                       limit);
+  else
+    hipLaunchKernelGGL(k_sf_solve<false>, grid, dim3(kBlock), 0, s, n, nrhs, srp, sci, sva, sdg, bp, xp, ticket, err,
+                       limit);
+  return hipGetLastError();
+}

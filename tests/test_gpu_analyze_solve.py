@@ -64,7 +64,7 @@ def test_level_stats_exact(handles, name):
 SCHEDS = [dict(mode=0), dict(mode=1), dict(mode=2), dict(mode=0, thin_rows=64, wg_threads=256),
           dict(mode=1, lanes_per_row=4), dict(mode=0, thin_rows=300, wg_threads=1024, lanes_per_row=8),
           dict(mode=1, wide_grid=256), dict(mode=0, thin_rows=64, wide_threads=512, wide_grid=1024),
-          dict(mode=1, wide_threads=64, wide_grid=3)]
+          dict(mode=1, wide_threads=64, wide_grid=3), dict(mode=3)]
 
 
 @pytest.mark.parametrize("name", [n for n, _ in MATS])
@@ -268,7 +268,7 @@ def test_set_schedule_replaces_tuned(handles):
     m, h, _ = handles["cfg2_small"]
     h.autotune(nrhs=2)
     tuned = h.get_schedule(nrhs=2)
-    assert tuned["mode"] in (0, 1, 2)
+    assert tuned["mode"] in (0, 1, 2, 3)
     assert h.get_schedule(nrhs=1) == dict(mode=0, thin_rows=4096, wg_threads=512, wide_threads=256, lanes_per_row=1,
                                           wide_grid=0)
     want = dict(mode=0, thin_rows=64, wg_threads=256, wide_threads=128, lanes_per_row=1, wide_grid=0)
@@ -287,3 +287,52 @@ def test_empty_matrix():
     nlev = h.analyze(z, torch.zeros(0, dtype=torch.int32, device="cuda"),
                      torch.zeros(0, dtype=torch.float64, device="cuda"))
     assert nlev == 0
+
+
+def test_syncfree_graph_replays_and_rewrite(handles):
+    # the synchronisation-free executor (mode 3): graph replays (its ticket and
+    # pending marks are reset by a kernel of the graph), repeated solves give
+    # the same bits, and the rewritten system of the chain matrix
+    m, h, _ = handles["cfg1_small"]
+    h.set_schedule(mode=3)
+    b = to_dev(gen.rhs(m, 1))
+    xr = oracle.solve(m, b.cpu().numpy())
+    x1 = h.solve(b.view(-1))
+    x2 = h.solve(b.view(-1))
+    h.check()
+    assert torch.equal(x1, x2)
+    assert oracle.relerr(x1.cpu().numpy(), xr) <= TOL
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        x = torch.zeros_like(b)
+        gid = h.graph_create(b, x)
+        for _ in range(3):
+            x.zero_()
+            h.graph_launch(gid)
+            torch.cuda.synchronize()
+            assert oracle.relerr(x.cpu().numpy(), xr) <= TOL
+    h.check()
+    h.rewrite(sp.THIN_ROWS, 32, 4.0, 0)
+    h.set_schedule(sp.REWRITTEN, mode=3)
+    for nrhs in (1, 5):
+        bb = gen.rhs(m, nrhs)
+        x = h.solve(to_dev(bb) if nrhs > 1 else to_dev(bb[0]), sp.REWRITTEN)
+        h.check()
+        assert oracle.relerr(x.cpu().numpy().reshape(nrhs, -1), oracle.solve(m, bb)) <= TOL
+    h.set_schedule(mode=0)
+
+
+@pytest.mark.parametrize("grid", [1, 16, 2048])
+def test_syncfree_grid_sizes(handles, grid):
+    # one workgroup still finishes (it takes every ticket in turn)
+    m, h, _ = handles["window_ragged"]
+    h.set_schedule(mode=3, wide_grid=grid)
+    for nrhs in (1, 3):
+        b = gen.rhs(m, nrhs)
+        x = h.solve(to_dev(b))
+        h.check()
+        assert oracle.relerr(x.cpu().numpy().reshape(nrhs, -1), oracle.solve(m, b)) <= TOL
+    with pytest.raises(sp.SptrsvError) as ei:
+        h.set_schedule(mode=3, wide_grid=4096)
+    assert ei.value.name == "ARG"
+    h.set_schedule(mode=0)

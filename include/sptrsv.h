@@ -284,22 +284,27 @@ sptrsv_status_t sptrsv_plan_load(sptrsv_handle_t h, const char *path);
 /* ---------------------------------------------------------------------------
  * Learned rewrite policy (not in the paper; replaces the thin-level test of
  * Sec. III with a small network). Parameters are float32[SPTRSV_MLP_NPARAM]:
- * W1[64,16] b1[64] W2[64,64] b2[64] W3[64] b3[1], row-major.
+ * W1[64,20] b1[64] W2[64,64] b2[64] W3[64] b3[1], row-major.
  * ------------------------------------------------------------------------- */
-#define SPTRSV_MLP_NIN 16
+#define SPTRSV_MLP_NIN 20
 #define SPTRSV_MLP_HID 64
-#define SPTRSV_MLP_NPARAM 5313
+#define SPTRSV_MLP_NPARAM 5569
 
-/* 16 float features per level of the ORIGINAL matrix (layout float[nlev][16]):
+/* 20 float features per level of the ORIGINAL matrix (layout float[nlev][20]):
  * log1p(rows), log1p(sum nnz), log1p(cost), cost/avgLevelCost, rows/32,
  * sum nnz/rows, fractions of rows with 0,1,2,3-4,5-8,>=9 off-diagonals,
  * sum nnz(L'[r])/sum nnz(L[r]) and log1p(sum nnz(T[r])) if the level alone were
- * rewritten into the level before it, level/nlev, log1p(rows of previous level).
- * ASYNC. */
+ * rewritten into the level before it, level/nlev, log1p(rows of previous level),
+ * then the row constraints of Sec. III.A on that same move: the fraction of
+ * rows left with fewer than 4 off-diagonals (indegree < alpha), the fraction on
+ * a longest path of the DAG (level + height = nlev - 1), log1p of the mean
+ * column span (largest minus smallest off-diagonal column) and the fraction of
+ * rows spanning fewer than 1024 columns (spread < beta). Level 0 counts its rows
+ * as they are. Synchronous (host reads of overflow counts). */
 sptrsv_status_t sptrsv_level_features(sptrsv_handle_t h, float *d_feat, hipStream_t s);
 /* p[i] = sigmoid(MLP(f[i])) for the batch rows, f = (feat - mean) * inv_std
- * when d_norm (float[32]: mean[16], inv_std[16]) is given, else f = feat.
- * d_feat float[batch][16], d_prob float[batch]. ASYNC. */
+ * when d_norm (float[40]: mean[20], inv_std[20]) is given, else f = feat.
+ * d_feat float[batch][20], d_prob float[batch]. ASYNC. */
 sptrsv_status_t sptrsv_mlp_forward(const float *d_params, const float *d_feat, const float *d_norm, int32_t batch,
                                    float *d_prob, hipStream_t s);
 /* Gradient of the mean binary cross-entropy, (1/batch) sum_i w_i BCE(p_i, y_i),

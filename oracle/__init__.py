@@ -215,6 +215,7 @@ class Rewrite:
 
 
 THIN_ROWS, THIN_COST = 0, 1
+NFEAT = 20  # per-level features of the learned policy (see orc_level_features)
 
 
 def rewrite(m, thin_metric: int = THIN_ROWS, thin_threshold: float = 32.0, fill_cap: float = 0.0,
@@ -277,7 +278,7 @@ def solve_rewritten(rw: Rewrite, b: np.ndarray) -> np.ndarray:
 def level_features(m, lv: Levels | None = None) -> np.ndarray:
     lv = lv or levels(m)
     rp, ci, v = _arrs(m)
-    f = np.zeros((lv.nlev, 16), np.float64)
+    f = np.zeros((lv.nlev, NFEAT), np.float64)
     st = _load().orc_level_features(m.n, rp, ci, v, lv.nlev, lv.row_level, lv.level_ptr, lv.level_rows, f)
     if st != 0:
         raise RuntimeError(STATUS[st])

@@ -2,19 +2,19 @@
 
 The paper does not define a learned policy; this network is this library's
 addition, a replacement for the thin-level test of the naive strategy (Sec. III).
-Architecture: 16 inputs -> 64 -> 64 -> 1, ReLU after the hidden layers, sigmoid
+Architecture: 20 inputs -> 64 -> 64 -> 1, ReLU after the hidden layers, sigmoid
 on the output, mean binary cross-entropy loss, Adam. Written plainly with numpy
 matrix products so it can be read against the definitions; used to check the
 GPU's FP32 forward/backward/Adam kernels.
 
-Flat parameter layout (5313 values):
-  W1[64,16] | b1[64] | W2[64,64] | b2[64] | W3[64] | b3[1]   (row-major)
+Flat parameter layout (5569 values):
+  W1[64,20] | b1[64] | W2[64,64] | b2[64] | W3[64] | b3[1]   (row-major)
 """
 from __future__ import annotations
 
 import numpy as np
 
-F_IN, H = 16, 64
+F_IN, H = 20, 64
 SIZES = [("W1", (H, F_IN)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (H,)), ("b3", (1,))]
 NPARAM = sum(int(np.prod(s)) for _, s in SIZES)
 

@@ -43,6 +43,9 @@ enum {
   ORC_ERR_OVERFLOW = 8
 };
 
+/* per-level features of the learned policy */
+enum { ORC_NFEAT = 20 };
+
 /* ---------------------------------------------------------------------------
  * O1. Validation. Algorithm 1 reads the diagonal of row i at the last slot of
  * the row, so a usable row has its columns in ascending order, every column at
@@ -670,7 +673,7 @@ void orc_rewrite_copy(const orc_rewrite_ctx *c, int32_t *lp_ptr, int32_t *lp_col
 }
 
 /* ---------------------------------------------------------------------------
- * Per-level features for the learned rewrite policy (16 per level, FP64 here).
+ * Per-level features for the learned rewrite policy (20 per level, FP64 here).
  * None of these come from the paper; they summarise the quantities its strategy
  * discussion names as relevant (level cost against avgLevelCost, number of
  * dependencies, growth of a row when it is rewritten; Sec. III and Sec. III.A):
@@ -680,8 +683,18 @@ void orc_rewrite_copy(const orc_rewrite_ctx *c, int32_t *lp_ptr, int32_t *lp_col
  *   12 sum nnz(L'[r]) / sum nnz(L[r]) if the level were rewritten into the
  *      level before it (every other row in place)    13 log1p(sum nnz(T[r])) of that move
  *   14 level / nlev          15 log1p(rows of the level before)
- * For level 0 features 12..13 are those of an identity move (1 and log1p(rows))
- * and feature 15 is 0.
+ * and the row constraints of Sec. III.A, measured on the same move:
+ *   16 fraction of rows whose moved form keeps fewer than 4 off-diagonals
+ *      (indegree < alpha, alpha = 4)
+ *   17 fraction of rows on a longest path of the DAG (level + height = nlev - 1,
+ *      height = longest path from the row to a row nothing depends on)
+ *   18 log1p(mean over rows of the moved form's off-diagonal column span,
+ *      largest minus smallest column; 0 for a row with fewer than two)
+ *   19 fraction of rows whose moved form spans fewer than 1024 columns
+ *      (dependency spread < beta, beta = 1024: the x values a row reads lie
+ *      within 8 KB)
+ * For level 0 features 12..13 and 16..19 are those of an identity move (the
+ * row as it is: 1 and log1p(rows) for 12..13) and feature 15 is 0.
  * ------------------------------------------------------------------------- */
 int orc_level_features(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nlev,
                        const int32_t *lev, const int32_t *level_ptr, const int32_t *level_rows, double *feat) {
@@ -694,27 +707,51 @@ int orc_level_features(int32_t n, const int32_t *rp, const int32_t *ci, const do
   s.pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
   if (!rows || !nzl || !cost || !s.pos) return ORC_ERR_ALLOC;
   for (int32_t k = 0; k < n; ++k) s.pos[k] = -1;
+  int32_t *height = (int32_t *)calloc((size_t)(n + 1), sizeof(int32_t));
+  if (!height) return ORC_ERR_ALLOC;
+  /* a row's dependents all come after it: one sweep from the last row back */
+  for (int32_t r = n - 1; r >= 0; --r)
+    for (int32_t p = rp[r]; p < rp[r + 1] - 1; ++p)
+      if (height[ci[p]] < height[r] + 1) height[ci[p]] = height[r] + 1;
   int64_t total = 0;
   double avg = orc_level_costs(n, rp, nlev, level_ptr, level_rows, rows, nzl, cost, &total);
   for (int32_t l = 0; l < nlev; ++l) {
-    double *f = feat + (int64_t)l * 16;
+    double *f = feat + (int64_t)l * ORC_NFEAT;
     int64_t hist[6] = {0, 0, 0, 0, 0, 0};
     int64_t sum_lp = 0, sum_l = 0, sum_t = 0;
+    int64_t n_alpha = 0, n_crit = 0, n_local = 0, sum_span = 0;
     for (int32_t q = level_ptr[l]; q < level_ptr[l + 1]; ++q) {
       int32_t r = level_rows[q];
       int32_t off = rp[r + 1] - rp[r] - 1;
       int bin = off == 0 ? 0 : off == 1 ? 1 : off == 2 ? 2 : off <= 4 ? 3 : off <= 8 ? 4 : 5;
       hist[bin] += 1;
       sum_l += off + 1;
+      int32_t na, lo = INT32_MAX, hi = -1;
       if (l == 0) {
         sum_lp += off + 1;
         sum_t += 1;
+        na = off;
+        for (int32_t p = rp[r]; p < rp[r + 1] - 1; ++p) {
+          if (ci[p] < lo) lo = ci[p];
+          if (ci[p] > hi) hi = ci[p];
+        }
       } else {
         if (!substitute(&s, rp, ci, v, lev, r, l - 1)) return ORC_ERR_ALLOC;
-        sum_lp += alive_count(&s) + 1;
+        na = alive_count(&s);
+        sum_lp += na + 1;
         sum_t += s.tlen + 1;
+        for (int32_t p = 0; p < s.wlen; ++p)
+          if (s.alive[p]) {
+            if (s.wcol[p] < lo) lo = s.wcol[p];
+            if (s.wcol[p] > hi) hi = s.wcol[p];
+          }
         ws_reset_pos(&s);
       }
+      const int64_t span = hi >= 0 ? (int64_t)hi - lo : 0;
+      n_alpha += na < 4;
+      n_crit += lev[r] + height[r] == nlev - 1;
+      sum_span += span;
+      n_local += span < 1024;
     }
     double R = (double)rows[l];
     f[0] = log1p(R);
@@ -728,7 +765,12 @@ int orc_level_features(int32_t n, const int32_t *rp, const int32_t *ci, const do
     f[13] = log1p((double)sum_t);
     f[14] = (double)l / (double)nlev;
     f[15] = l > 0 ? log1p((double)rows[l - 1]) : 0.0;
+    f[16] = R > 0.0 ? (double)n_alpha / R : 0.0;
+    f[17] = R > 0.0 ? (double)n_crit / R : 0.0;
+    f[18] = R > 0.0 ? log1p((double)sum_span / R) : 0.0;
+    f[19] = R > 0.0 ? (double)n_local / R : 0.0;
   }
+  free(height);
   free(rows);
   free(nzl);
   free(cost);

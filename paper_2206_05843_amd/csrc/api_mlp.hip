@@ -20,19 +20,23 @@ sptrsv_status_t sptrsv_level_features(sptrsv_handle_t h, float *d_feat, hipStrea
   if (!P.ready) return set_err(h, SPTRSV_ERR_STATE, "features: matrix not analysed");
   const int32_t n = P.n, nlev = P.nlev;
   if (nlev == 0) return SPTRSV_OK;
-  DArr<long long> sum_lp, sum_t;
-  DArr<int32_t> hist, redo;
-  HIPCHK(h, sum_lp.alloc(nlev));
-  HIPCHK(h, sum_t.alloc(nlev));
-  HIPCHK(h, hist.alloc((size_t)nlev * 6));
+  DArr<long long> sums;  // sum_lp, sum_t, sum_span
+  DArr<int32_t> hist, redo, height;
+  DArr<uint8_t> oncrit;
+  HIPCHK(h, sums.alloc((size_t)nlev * 3));
+  HIPCHK(h, hist.alloc((size_t)nlev * kFeatHist));
   HIPCHK(h, redo.alloc(n));
-  HIPCHK(h, hipMemsetAsync(sum_lp.p, 0, sizeof(long long) * (size_t)nlev, s));
-  HIPCHK(h, hipMemsetAsync(sum_t.p, 0, sizeof(long long) * (size_t)nlev, s));
-  HIPCHK(h, hipMemsetAsync(hist.p, 0, sizeof(int32_t) * (size_t)nlev * 6, s));
+  HIPCHK(h, height.alloc(n));
+  HIPCHK(h, oncrit.alloc(n));
+  HIPCHK(h, hipMemsetAsync(sums.p, 0, sizeof(long long) * (size_t)nlev * 3, s));
+  HIPCHK(h, hipMemsetAsync(hist.p, 0, sizeof(int32_t) * (size_t)nlev * kFeatHist, s));
+  HIPCHK(h, hipMemsetAsync(height.p, 0, sizeof(int32_t) * (size_t)n, s));
+  HIPCHK(h, launch_crit_rows(nlev, P.level_ptr.p, P.perm.p, h->rp.p, h->ci.p, P.row_level.p, height.p, oncrit.p, s));
+  const FeatAcc acc{sums.p, sums.p + nlev, sums.p + 2 * (size_t)nlev, hist.p, oncrit.p};
   int32_t *aux = h->d_aux.p;  // [24] redo count, [25] error bits
   HIPCHK(h, hipMemsetAsync(aux + 24, 0, 2 * sizeof(int32_t), s));
-  HIPCHK(h, launch_feat_rows(n, nullptr, 0, h->rp.p, h->ci.p, h->va.p, P.row_level.p, sum_lp.p, sum_t.p, hist.p,
-                             redo.p, aux + 24, nullptr, 0, 0, 0, aux + 25, s));
+  HIPCHK(h, launch_feat_rows(n, nullptr, 0, h->rp.p, h->ci.p, h->va.p, P.row_level.p, acc, redo.p, aux + 24, nullptr,
+                             0, 0, 0, aux + 25, s));
   int32_t hc[2];
   HIPCHK(h, hipMemcpyAsync(hc, aux + 24, sizeof(hc), hipMemcpyDeviceToHost, s));
   HIPCHK(h, hipStreamSynchronize(s));
@@ -42,14 +46,13 @@ sptrsv_status_t sptrsv_level_features(sptrsv_handle_t h, float *d_feat, hipStrea
     const int32_t blocks = std::max(1, std::min(8, (hc[0] + rewrite_waves_per_block() - 1) / rewrite_waves_per_block()));
     DArr<char> big;
     HIPCHK(h, big.alloc(rewrite_big_ws_bytes(C, H) * (size_t)blocks * (size_t)rewrite_waves_per_block()));
-    HIPCHK(h, launch_feat_rows(n, redo.p, hc[0], h->rp.p, h->ci.p, h->va.p, P.row_level.p, sum_lp.p, sum_t.p, hist.p,
-                               redo.p, aux + 24, big.p, C, H, blocks, aux + 25, s));
+    HIPCHK(h, launch_feat_rows(n, redo.p, hc[0], h->rp.p, h->ci.p, h->va.p, P.row_level.p, acc, redo.p, aux + 24,
+                               big.p, C, H, blocks, aux + 25, s));
     HIPCHK(h, hipMemcpyAsync(hc, aux + 24, sizeof(hc), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));
   }
   if (hc[1]) return set_err(h, status_from_bits(hc[1]), "features: rewrite workspace overflow");
-  HIPCHK(h, launch_feat_finalize(nlev, P.lv_rows.p, P.lv_nnz.p, P.lv_cost.p, P.avg_cost, hist.p, sum_lp.p, sum_t.p,
-                                 d_feat, s));
+  HIPCHK(h, launch_feat_finalize(nlev, P.lv_rows.p, P.lv_nnz.p, P.lv_cost.p, P.avg_cost, acc, d_feat, s));
   HIPCHK(h, hipStreamSynchronize(s));
   return SPTRSV_OK;
 }

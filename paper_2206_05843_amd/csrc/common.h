@@ -355,13 +355,21 @@ hipError_t launch_mlp_backward(const float *P, const float *feat, const float *n
 hipError_t launch_mlp_adam(float *P, const float *g, float *m, float *v, float lr, float c1, float c2,
                            hipStream_t s);
 hipError_t launch_mlp_mask(const float *prob, int32_t nlev, float thr, uint8_t *mask, hipStream_t s);
+// Per-level sums behind the learned policy's level features, filled row by row:
+// hist[l * kFeatHist + b] holds the off-diagonal count bins (b < 6) and the
+// counts of rows passing the row-constraint tests (6: fewer than 4 dependencies
+// after the move, 7: on a longest path, 8: span under 1024 columns).
+constexpr int kFeatHist = 9;
+struct FeatAcc {
+  long long *sum_lp, *sum_t, *sum_span;
+  int32_t *hist;
+  const uint8_t *oncrit;  // longest-path membership per row
+};
 hipError_t launch_feat_finalize(int32_t nlev, const int64_t *rows, const int64_t *nnz, const int64_t *cost,
-                                double avg, const int32_t *hist, const long long *sum_lp, const long long *sum_t,
-                                float *feat, hipStream_t s);
+                                double avg, FeatAcc acc, float *feat, hipStream_t s);
 hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const int32_t *rp, const int32_t *ci,
-                            const double *va, const int32_t *lev, long long *sum_lp, long long *sum_t, int32_t *hist,
-                            int32_t *redo, int32_t *nredo, char *big, int32_t bigC, int32_t bigH, int32_t big_blocks,
-                            int *err, hipStream_t s);
+                            const double *va, const int32_t *lev, FeatAcc acc, int32_t *redo, int32_t *nredo,
+                            char *big, int32_t bigC, int32_t bigH, int32_t big_blocks, int *err, hipStream_t s);
 // Window images (k_image.hip) ------------------------------------------------------
 // Per position: overflow records and dependencies before its window (zero for
 // positions outside thin windows); lvl_win maps a level to its window in win

@@ -1,5 +1,5 @@
 // Learned rewrite policy: level features, and the network's forward, backward
-// and Adam kernels (FP32). The network is 16 -> 64 -> 64 -> 1 with ReLU and a
+// and Adam kernels (FP32). The network is 20 -> 64 -> 64 -> 1 with ReLU and a
 // sigmoid output; one wave evaluates one sample with lane j holding hidden unit
 // j of both layers, so every reduction is a fixed butterfly or a fixed loop
 // (deterministic). Parameters are staged in LDS with padded rows.
@@ -7,8 +7,10 @@
 
 namespace {
 
-constexpr int NIN = 16, HID = 64, NPAR = 5313;
-constexpr int OFF_W1 = 0, OFF_B1 = 1024, OFF_W2 = 1088, OFF_B2 = 5184, OFF_W3 = 5248, OFF_B3 = 5312;
+constexpr int NIN = 20, HID = 64, NPAR = 5569;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + HID * NIN, OFF_W2 = OFF_B1 + HID, OFF_B2 = OFF_W2 + HID * HID,
+              OFF_W3 = OFF_B2 + HID, OFF_B3 = OFF_W3 + HID;
+static_assert(OFF_B3 + 1 == NPAR, "parameter layout");
 constexpr int W1S = NIN + 1, W2S = HID + 1;  // padded LDS row strides
 constexpr int kWavesPerBlock = 4;
 constexpr int kBwdBlocks = 64;
@@ -166,14 +168,13 @@ __global__ void k_mlp_mask(const float *__restrict__ prob, int32_t nlev, float t
     mask[i] = (i > 0 && prob[i] >= thr) ? 1 : 0;
 }
 
-// The 16 features of each level (see sptrsv_level_features), from the level
+// The 20 features of each level (see sptrsv_level_features), from the level
 // statistics and the per-row sums of the distance-1 rewrite.
 __global__ void k_feat_finalize(int32_t nlev, const int64_t *__restrict__ rows, const int64_t *__restrict__ nnz,
-                                const int64_t *__restrict__ cost, double avg, const int32_t *__restrict__ hist,
-                                const long long *__restrict__ sum_lp, const long long *__restrict__ sum_t,
-                                float *feat) {
+                                const int64_t *__restrict__ cost, double avg, FeatAcc acc, float *feat) {
   for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nlev; l += (int64_t)gridDim.x * blockDim.x) {
     float *f = feat + l * NIN;
+    const int32_t *hist = acc.hist + l * kFeatHist;
     const double R = (double)rows[l];
     f[0] = (float)log1p(R);
     f[1] = (float)log1p((double)nnz[l]);
@@ -181,11 +182,15 @@ __global__ void k_feat_finalize(int32_t nlev, const int64_t *__restrict__ rows, 
     f[3] = (float)(avg > 0.0 ? (double)cost[l] / avg : 0.0);
     f[4] = (float)(R / 32.0);
     f[5] = (float)(R > 0.0 ? (double)nnz[l] / R : 0.0);
-    for (int b = 0; b < 6; ++b) f[6 + b] = (float)(R > 0.0 ? (double)hist[l * 6 + b] / R : 0.0);
-    f[12] = (float)(nnz[l] > 0 ? (double)sum_lp[l] / (double)nnz[l] : 0.0);
-    f[13] = (float)log1p((double)sum_t[l]);
+    for (int b = 0; b < 6; ++b) f[6 + b] = (float)(R > 0.0 ? (double)hist[b] / R : 0.0);
+    f[12] = (float)(nnz[l] > 0 ? (double)acc.sum_lp[l] / (double)nnz[l] : 0.0);
+    f[13] = (float)log1p((double)acc.sum_t[l]);
     f[14] = (float)((double)l / (double)nlev);
     f[15] = (float)(l > 0 ? log1p((double)rows[l - 1]) : 0.0);
+    f[16] = (float)(R > 0.0 ? (double)hist[6] / R : 0.0);
+    f[17] = (float)(R > 0.0 ? (double)hist[7] / R : 0.0);
+    f[18] = (float)(R > 0.0 ? log1p((double)acc.sum_span[l] / R) : 0.0);
+    f[19] = (float)(R > 0.0 ? (double)hist[8] / R : 0.0);
   }
 }
 
@@ -227,10 +232,9 @@ hipError_t launch_mlp_mask(const float *prob, int32_t nlev, float thr, uint8_t *
 }
 
 hipError_t launch_feat_finalize(int32_t nlev, const int64_t *rows, const int64_t *nnz, const int64_t *cost,
-                                double avg, const int32_t *hist, const long long *sum_lp, const long long *sum_t,
-                                float *feat, hipStream_t s) {
+                                double avg, FeatAcc acc, float *feat, hipStream_t s) {
   if (nlev <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_feat_finalize, dim3((nlev + 255) / 256 > 1024 ? 1024 : (nlev + 255) / 256), dim3(256), 0, s,
-                     nlev, rows, nnz, cost, avg, hist, sum_lp, sum_t, feat);
+                     nlev, rows, nnz, cost, avg, acc, feat);
   return hipGetLastError();
 }

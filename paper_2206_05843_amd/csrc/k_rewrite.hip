@@ -586,19 +586,20 @@ __global__ void k_collect_moved(int32_t n, const int32_t *__restrict__ target, c
 }
 
 // Per-row inputs of the learned policy's level features: the row's
-// off-diagonal count bin, and the sizes of L'[r] and T[r] if its level alone
-// were rewritten into the level before it (every other row in place: the B set
-// is the rows at level >= lev(r) - 1 of the original levels). Rows whose
-// rewrite outgrows the LDS workspace are listed for a second pass with a
+// off-diagonal count bin, the sizes of L'[r] and T[r] if its level alone were
+// rewritten into the level before it (every other row in place: the B set is
+// the rows at level >= lev(r) - 1 of the original levels), and the row
+// constraints of Sec. III.A on that moved form (dependencies, column span) and
+// on the row (longest-path membership). Level-0 rows count as they are. Rows
+// whose rewrite outgrows the LDS workspace are listed for a second pass with a
 // global workspace.
 __global__ __launch_bounds__(64 * kWaves) void k_feat_rows(int32_t n, const int32_t *__restrict__ rows,
                                                            int32_t nrows, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
                                                            const double *__restrict__ va,
-                                                           const int32_t *__restrict__ lev, long long *sum_lp,
-                                                           long long *sum_t, int32_t *hist, int32_t *redo,
-                                                           int32_t *nredo, char *big, int32_t bigC, int32_t bigH,
-                                                           int *err) {
+                                                           const int32_t *__restrict__ lev, FeatAcc acc,
+                                                           int32_t *redo, int32_t *nredo, char *big, int32_t bigC,
+                                                           int32_t bigH, int *err) {
   extern __shared__ __align__(16) char lds_raw[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool use_big = big != nullptr;
@@ -611,7 +612,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_feat_rows(int32_t n, const int3
     const int32_t r = rows ? rows[i] : (int32_t)i;
     const int32_t l = lev[r];
     const int32_t off = rp[r + 1] - rp[r] - 1;
-    int32_t lp = off + 1, tn = 1;
+    int32_t lp = off + 1, tn = 1, na = off;
+    int2 span = off > 0 ? make_int2(ci[rp[r]], ci[rp[r + 1] - 2]) : make_int2(INT32_MAX, -1);
     if (l > 0) {
       int32_t nT = 0;
       const int stt = subst_row(w, r, l - 1, rp, ci, va, lev, INT64_MAX, &nT);
@@ -625,15 +627,23 @@ __global__ __launch_bounds__(64 * kWaves) void k_feat_rows(int32_t n, const int3
         wave_sync();
         continue;
       }
-      lp = *w.na + 1;
+      na = *w.na;
+      lp = na + 1;
       tn = nT + 1;
+      span = ws_a_span(w);
     }
     if (lane == 0) {
-      atomicAdd((unsigned long long *)(sum_lp + l), (unsigned long long)lp);
-      atomicAdd((unsigned long long *)(sum_t + l), (unsigned long long)tn);
+      atomicAdd((unsigned long long *)(acc.sum_lp + l), (unsigned long long)lp);
+      atomicAdd((unsigned long long *)(acc.sum_t + l), (unsigned long long)tn);
+      const int64_t sp = span.y >= 0 ? (int64_t)span.y - span.x : 0;
+      atomicAdd((unsigned long long *)(acc.sum_span + l), (unsigned long long)sp);
       // counted once per row: rows sent to the second pass skipped this block
       const int bin = off == 0 ? 0 : off == 1 ? 1 : off == 2 ? 2 : off <= 4 ? 3 : off <= 8 ? 4 : 5;
-      atomicAdd(hist + (int64_t)l * 6 + bin, 1);
+      int32_t *hl = acc.hist + (int64_t)l * kFeatHist;
+      atomicAdd(hl + bin, 1);
+      if (na < 4) atomicAdd(hl + 6, 1);
+      if (acc.oncrit[r]) atomicAdd(hl + 7, 1);
+      if (sp < 1024) atomicAdd(hl + 8, 1);
     }
     wave_sync();
   }
@@ -760,9 +770,8 @@ hipError_t launch_rewrite_rows(int32_t nrows, const int32_t *rows, const int32_t
 int32_t rewrite_waves_per_block() { return kWaves; }
 
 hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const int32_t *rp, const int32_t *ci,
-                            const double *va, const int32_t *lev, long long *sum_lp, long long *sum_t, int32_t *hist,
-                            int32_t *redo, int32_t *nredo, char *big, int32_t bigC, int32_t bigH, int32_t big_blocks,
-                            int *err, hipStream_t s) {
+                            const double *va, const int32_t *lev, FeatAcc acc, int32_t *redo, int32_t *nredo,
+                            char *big, int32_t bigC, int32_t bigH, int32_t big_blocks, int *err, hipStream_t s) {
   const int64_t total = rows ? nrows : n;
   if (total <= 0) return hipSuccess;
   static bool attr = false;
@@ -774,6 +783,6 @@ hipError_t launch_feat_rows(int32_t n, const int32_t *rows, int32_t nrows, const
   const bool use_big = big != nullptr;
   const int blocks = use_big ? big_blocks : grid_for(total, kWaves, 4096);
   hipLaunchKernelGGL(k_feat_rows, dim3(blocks), dim3(64 * kWaves), use_big ? 0 : kLdsWsBytes, s, n, rows, nrows, rp,
-                     ci, va, lev, sum_lp, sum_t, hist, redo, nredo, big, bigC, bigH, err);
+                     ci, va, lev, acc, redo, nredo, big, bigC, bigH, err);
   return hipGetLastError();
 }

@@ -27,7 +27,7 @@ class Policy:
     def __init__(self, params: np.ndarray, norm: np.ndarray, threshold: float = 0.5, meta: dict | None = None):
         params = np.asarray(params, np.float32).reshape(-1)
         norm = np.asarray(norm, np.float32).reshape(-1)
-        if params.size != _sp.MLP_NPARAM or norm.size != 32:
+        if params.size != _sp.MLP_NPARAM or norm.size != 2 * _sp.MLP_NIN:
             raise ValueError("bad policy checkpoint shape")
         if not (np.all(np.isfinite(params)) and np.all(np.isfinite(norm))):
             raise ValueError("non-finite policy checkpoint")
@@ -63,10 +63,11 @@ class Policy:
 
 def init_params(seed: int = 0) -> np.ndarray:
     """He-uniform weights and zero biases in the flat layout of the C ABI
-    (W1[64,16] b1[64] W2[64,64] b2[64] W3[64] b3[1])."""
+    (W1[64,20] b1[64] W2[64,64] b2[64] W3[64] b3[1])."""
     rng = np.random.default_rng(seed)
     parts = []
-    for shape, fan_in in [((64, 16), 16), ((64,), 0), ((64, 64), 64), ((64,), 0), ((64,), 64), ((1,), 0)]:
+    nin = _sp.MLP_NIN
+    for shape, fan_in in [((64, nin), nin), ((64,), 0), ((64, 64), 64), ((64,), 0), ((64,), 64), ((1,), 0)]:
         if fan_in:
             lim = np.sqrt(6.0 / fan_in)
             parts.append(rng.uniform(-lim, lim, size=shape).reshape(-1))
@@ -83,7 +84,12 @@ def load_default() -> Policy | None:
         return None
 
 
-def rewrite_learned(h: _sp.Handle, policy: Policy | None, thin_threshold=32.0, fill_cap=4.0, max_distance=0):
-    """Rewrite with the policy's level mask (fallback: the thin-level test)."""
+def rewrite_learned(h: _sp.Handle, policy: Policy | None, thin_threshold=32.0, fill_cap=4.0, max_distance=0,
+                    max_indegree=0, max_spread=0, critical_only=False):
+    """Rewrite with the policy's level mask (fallback: the thin-level test).
+    The row constraints of Sec. III.A (indegree < max_indegree, column span <
+    max_spread, longest-path rows only) apply to each row of the chosen levels,
+    as in the plain strategies; 0 / False leaves them off."""
     mask = policy.mask_for(h) if policy is not None else None
-    return h.rewrite(_sp.THIN_ROWS, thin_threshold, fill_cap, max_distance, mask)
+    return h.rewrite(_sp.THIN_ROWS, thin_threshold, fill_cap, max_distance, mask, max_indegree=max_indegree,
+                     max_spread=max_spread, critical_only=critical_only)

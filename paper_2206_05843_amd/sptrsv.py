@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libsptrsv.so")
 ORIGINAL, REWRITTEN, BATCH = 0, 1, 2
 THIN_ROWS, THIN_COST = 0, 1
 LOWER, UPPER, LOWER_TRANS, UPPER_TRANS = 0, 1, 2, 3  # triangular forms (sptrsv_analyze_form)
-MLP_NPARAM = 5313
+MLP_NIN = 20
+MLP_NPARAM = 5569
 
 STATUS_NAMES = ["OK", "ARG", "STATE", "NOT_LOWER", "UNSORTED", "MISSING_DIAG", "ZERO_PIVOT", "NONFINITE",
                 "OVERFLOW", "ALLOC", "HIP", "TIMEOUT"]
@@ -394,6 +395,6 @@ class Handle:
         return t
 
     def level_features(self):
-        f = torch.empty((self.nlev, 16), dtype=torch.float32, device="cuda")
+        f = torch.empty((self.nlev, MLP_NIN), dtype=torch.float32, device="cuda")
         self._check(self._L.sptrsv_level_features(self._h, _ptr(f), _stream()))
         return f

@@ -9,7 +9,8 @@ cap 4x), with every level inside one workgroup (sptrsv_level_times). A level
 that the naive rewrite empties is labelled 1 when the time its rows cost in
 their new levels of L' (their share, by row entries, of those levels' times)
 is below the time the level took in L, else 0; levels that are not emptied are
-labelled 0. The features are the 16 per-level features of the original levels.
+labelled 0. The features are the 20 per-level features of the original levels
+(sptrsv_level_features), the row constraints of Sec. III.A among them.
 
 Training. Mean class-balanced binary cross-entropy, Adam, minibatches; forward,
 backward and the Adam step are the library's kernels. Features are
@@ -144,7 +145,7 @@ def time_variant(h, which, b, reps=20):
     return (time.perf_counter() - t) / reps, x
 
 
-def calibrate(params, norm, seeds, thresholds=(0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.99)):
+def calibrate(params, norm, seeds, thresholds=(0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.99)):
     """Threshold with the best geometric-mean time ratio naive / learned on
     the given matrices (each variant autotuned)."""
     ratios = {t: [] for t in thresholds}

@@ -27,7 +27,7 @@ def test_features_match_oracle(mk):
 
 def _batch(seed, B=300):
     rng = np.random.default_rng(seed)
-    f = rng.normal(size=(B, 16))
+    f = rng.normal(size=(B, mlp.F_IN))
     y = (rng.random(B) < 0.3).astype(np.float64)
     th = mlp.init(seed) + rng.normal(scale=0.05, size=mlp.NPARAM)
     return th.astype(np.float32).astype(np.float64), f.astype(np.float32).astype(np.float64), y
@@ -42,11 +42,11 @@ def test_forward_matches_oracle():
 
 def test_forward_normalisation():
     th, f, _ = _batch(2)
-    mean = np.linspace(-1, 1, 16)
-    inv = np.linspace(0.5, 2, 16)
+    mean = np.linspace(-1, 1, mlp.F_IN)
+    inv = np.linspace(0.5, 2, mlp.F_IN)
     norm = np.concatenate([mean, inv]).astype(np.float32)
     p = sp.mlp_forward(to_dev(th, torch.float32), to_dev(f, torch.float32), to_dev(norm)).cpu().numpy()
-    fz = (f - norm[:16].astype(np.float64)) * norm[16:].astype(np.float64)
+    fz = (f - norm[:mlp.F_IN].astype(np.float64)) * norm[mlp.F_IN:].astype(np.float64)
     po, _ = mlp.forward(th, fz)
     np.testing.assert_allclose(p, po, rtol=2e-5, atol=1e-6)
 
@@ -91,7 +91,7 @@ def test_adam_matches_oracle():
 
 def test_training_reduces_loss_on_separable_data():
     rng = np.random.default_rng(9)
-    f = rng.normal(size=(512, 16)).astype(np.float32)
+    f = rng.normal(size=(512, mlp.F_IN)).astype(np.float32)
     y = (f[:, 0] + 0.5 * f[:, 3] > 0).astype(np.float32)
     P = to_dev(mlp.init(0), torch.float32)
     m, v = torch.zeros_like(P), torch.zeros_like(P)
@@ -120,3 +120,37 @@ def test_level_times():
     assert t.shape == (nlev,) and np.all(t >= 0) and t.sum() > 0
     x = h.solve(b)  # ordinary solves still right after a timed run
     assert oracle.relerr(x.cpu().numpy()[None], oracle.solve(m, b.cpu().numpy()[None])) <= 1e-10
+
+
+@pytest.mark.parametrize("knobs", [dict(max_indegree=4), dict(max_spread=64), dict(critical_only=True)])
+def test_learned_rewrite_with_row_constraints(knobs):
+    """rewrite_learned with the Sec. III.A row constraints as knobs: the level
+    mask of a (random-weight) policy equals the FP64 oracle network's on the
+    oracle's features, with the threshold in the widest gap of the oracle's
+    probabilities so that no decision sits on the rounding edge, and the
+    rewritten matrices equal the oracle's rewrite with that mask and the same
+    constraints."""
+    from paper_2206_05843_amd import policy
+    m = gen.window_random(3000, 5, 30, 9)
+    lv = oracle.levels(m)
+    th = mlp.init(4)
+    fo = oracle.level_features(m, lv)
+    mean, sd = fo.mean(axis=0), fo.std(axis=0) + 1e-3
+    norm = np.concatenate([mean, 1.0 / sd]).astype(np.float32)
+    po, _ = mlp.forward(th.astype(np.float32).astype(np.float64),
+                        (fo - norm[:mlp.F_IN].astype(np.float64)) * norm[mlp.F_IN:].astype(np.float64))
+    q = np.sort(po[1:])
+    k = int(np.argmax(np.diff(q)))
+    thr = float((q[k] + q[k + 1]) / 2)
+    assert q[k + 1] - q[k] > 1e-3
+    mask = ((po >= thr) & (np.arange(lv.nlev) > 0)).astype(np.uint8)
+    pol = policy.Policy(th, norm, thr)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    assert np.array_equal(pol.mask_for(h).cpu().numpy(), mask)
+    st = policy.rewrite_learned(h, pol, **knobs)
+    rw = oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0, 0, mask, lv, **knobs)
+    g = {k2: v.cpu().numpy() for k2, v in h.rewritten().items()}
+    assert np.array_equal(g["lp_ptr"], rw.lp.row_ptr) and np.array_equal(g["lp_col"], rw.lp.col)
+    assert np.array_equal(g["t_ptr"], rw.t.row_ptr) and np.array_equal(g["t_col"], rw.t.col)
+    assert st["rows_skipped"] == rw.rows_skipped

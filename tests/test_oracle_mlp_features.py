@@ -11,14 +11,15 @@ from oracle import mlp
 
 def _batch(seed, B=37):
     rng = np.random.default_rng(seed)
-    f = rng.normal(size=(B, 16))
+    f = rng.normal(size=(B, mlp.F_IN))
     y = (rng.random(B) < 0.4).astype(np.float64)
     th = mlp.init(seed) + rng.normal(scale=0.05, size=mlp.NPARAM)  # nonzero biases
     return th, f, y
 
 
 def test_param_count():
-    assert mlp.NPARAM == 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1 == 5313
+    assert mlp.F_IN == oracle.NFEAT == 20
+    assert mlp.NPARAM == 20 * 64 + 64 + 64 * 64 + 64 + 64 + 1 == 5569
 
 
 def test_gradient_finite_differences():
@@ -72,7 +73,7 @@ def test_features_brute_force():
     lv = oracle.levels(m)
     F = oracle.level_features(m, lv)
     c = oracle.level_costs(m, lv)
-    assert F.shape == (lv.nlev, 16)
+    assert F.shape == (lv.nlev, 20)
     nnz = np.diff(m.row_ptr)
     for l in range(lv.nlev):
         rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
@@ -98,3 +99,73 @@ def test_features_brute_force():
         tn = np.diff(rw.t_ptr)[rows].sum()
         assert F[l, 12] == pytest.approx(lp / nnz[rows].sum())
         assert F[l, 13] == pytest.approx(np.log1p(tn))
+
+
+def _heights_by_dependents(m):
+    """Longest path from each row to a row nothing depends on, by memoised
+    recursion over the dependents (the other direction from the oracle's
+    sweep over dependencies)."""
+    dependents = [[] for _ in range(m.n)]
+    for r in range(m.n):
+        for p in range(m.row_ptr[r], m.row_ptr[r + 1] - 1):
+            dependents[int(m.col[p])].append(r)
+    h = [None] * m.n
+    for r in range(m.n - 1, -1, -1):  # dependents have larger indices
+        h[r] = 1 + max((h[d] for d in dependents[r]), default=-1)
+    return np.array(h)
+
+
+def _moved_rows(m, lv, l):
+    """Off-diagonal columns of each row of level l after the distance-1 move
+    (the oracle's rewrite with a one-level mask), or the rows as they are for
+    level 0."""
+    rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
+    if l == 0:
+        return [m.col[m.row_ptr[r]:m.row_ptr[r + 1] - 1] for r in rows]
+    mask = np.zeros(lv.nlev, np.uint8)
+    mask[l] = 1
+    rw = oracle.rewrite(m, oracle.THIN_ROWS, 1e9, 0.0, 0, mask, lv)
+    out = []
+    for r in rows:
+        c = rw.lp.col[rw.lp.row_ptr[r]:rw.lp.row_ptr[r + 1]]
+        out.append(c[c != r])
+    return out
+
+
+@pytest.mark.parametrize("case", ["window", "powerlaw"])
+def test_row_constraint_features_brute_force(case):
+    """Features 16..19 (the Sec. III.A row constraints on the distance-1 move)
+    against a direct count over the moved rows."""
+    m = gen.window_random(300, 8, window=6, draws=3) if case == "window" else gen.powerlaw(3000, seed=5, w_loc=2048, nseg=2, seglen=50)
+    lv = oracle.levels(m)
+    F = oracle.level_features(m, lv)
+    h = _heights_by_dependents(m)
+    for l in range(lv.nlev):
+        rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
+        cols = _moved_rows(m, lv, l)
+        span = np.array([int(c.max()) - int(c.min()) if len(c) else 0 for c in cols])
+        assert F[l, 16] == pytest.approx(np.mean([len(c) < 4 for c in cols]))
+        assert F[l, 17] == pytest.approx(np.mean(l + h[rows] == lv.nlev - 1))
+        assert F[l, 18] == pytest.approx(np.log1p(span.mean()))
+        assert F[l, 19] == pytest.approx(np.mean(span < 1024))
+
+
+def test_critical_path_feature_two_chains():
+    """Two independent chains of lengths 6 and 3 (rows 0..5 and 6..8): the
+    longest path is the long chain, so its rows are critical and the short
+    chain's are not; levels 0..2 hold one row of each, levels 3..5 only the
+    long chain's."""
+    import gen as G
+    rp, ci, va = [0], [], []
+    for r in range(9):
+        if r not in (0, 6):
+            ci.append(r - 1)
+            va.append(-0.5)
+        ci.append(r)
+        va.append(2.0)
+        rp.append(len(ci))
+    m = G.Csr(9, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va))
+    lv = oracle.levels(m)
+    F = oracle.level_features(m, lv)
+    assert lv.nlev == 6
+    np.testing.assert_allclose(F[:, 17], [0.5, 0.5, 0.5, 1.0, 1.0, 1.0])

@@ -420,7 +420,7 @@ orc_rewrite_ctx *orc_rewrite_rc(int32_t n, const int32_t *rp, const int32_t *ci,
                                 const int32_t *lev, const int32_t *level_ptr, const int32_t *level_rows,
                                 int32_t thin_metric, double thin_threshold, double fill_cap, int32_t max_distance,
                                 const uint8_t *mask, int32_t max_indeg, int64_t max_spread, int32_t crit_only,
-                                int32_t *tgt, int32_t *status) {
+                                int32_t both_ends, int32_t *tgt, int32_t *status) {
   *status = ORC_OK;
   int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nlev + 1));
   int64_t *nzl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nlev + 1));
@@ -464,110 +464,131 @@ orc_rewrite_ctx *orc_rewrite_rc(int32_t n, const int32_t *rp, const int32_t *ci,
   }
   int32_t skipped = 0;
 
-  int32_t t = 0, dist_max = 0, moved = 0, steps = nlev > 0 ? 1 : 0;
-  int64_t size_t_ = nlev > 0 ? rows[0] : 0;
-  int64_t cost_t = nlev > 0 ? cost[0] : 0;
-  for (int32_t l = 1; l < nlev; ++l) {
+  /* Segments: level 0 and every level that is not a source start one, and the
+   * scan above runs inside each. A segment's scan neither reads nor changes
+   * anything another one decides: its rows only move to levels inside it, and
+   * a substitution expands only unknowns at or below the current target, while
+   * every row of an earlier segment sits (moved or not) below the segment's
+   * first level. So the segments may be taken in any order with the same
+   * result; both_ends takes them alternately from the first and from the last
+   * (first, last, second, second to last, ...), the scan started at the
+   * beginning and at the end of the graph at once (Sec. III, the parallel
+   * sketch; empty levels are only removed afterwards, so level numbers hold). */
+  int32_t *seg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nlev + 1));
+  if (!seg) {
+    *status = ORC_ERR_ALLOC;
+    return NULL;
+  }
+  int32_t nseg = 0;
+  for (int32_t l = 0; l < nlev; ++l) {
     int src;
-    if (mask)
+    if (l == 0)
+      src = 0;
+    else if (mask)
       src = mask[l] != 0;
     else if (thin_metric == 0)
       src = (double)rows[l] < W;
     else
       src = (double)cost[l] < W;
-    if (!src) {
-      t = l;
-      size_t_ = rows[l];
-      cost_t = cost[l];
-      steps++;
-      continue;
-    }
-    for (int32_t q = level_ptr[l]; q < level_ptr[l + 1]; ++q) {
-      int32_t r = level_rows[q];
-      if (!substitute(&s, rp, ci, v, cur, r, t)) {
-        *status = ORC_ERR_ALLOC;
-        return NULL;
-      }
-      int64_t nnz_new = (int64_t)alive_count(&s) + 1;
-      int64_t nnz_old = rp[r + 1] - rp[r];
-      int ok;
-      if (thin_metric == 0)
-        ok = (double)(size_t_ + 1) <= W;
-      else
-        ok = (double)(cost_t + 2 * nnz_new - 1) <= W;
-      if (fill_cap > 0.0) ok = ok && (double)nnz_new <= fill_cap * (double)nnz_old;
-      if (max_distance > 0) ok = ok && (l - t) <= max_distance;
-      if (ok) {
-        int skip = 0;
-        if (max_indeg > 0 && (int64_t)alive_count(&s) >= max_indeg) skip = 1;
-        if (!skip && max_spread > 0) {
-          int32_t lo = INT32_MAX, hi = -1;
-          for (int32_t p = 0; p < s.wlen; ++p)
-            if (s.alive[p]) {
-              if (s.wcol[p] < lo) lo = s.wcol[p];
-              if (s.wcol[p] > hi) hi = s.wcol[p];
-            }
-          if (hi >= 0 && (int64_t)hi - lo >= max_spread) skip = 1;
-        }
-        if (!skip && crit_only && !oncrit[r]) skip = 1;
-        if (skip) { /* the row stays in its level; the run goes on */
-          ws_reset_pos(&s);
-          skipped += 1;
-          continue;
-        }
-      }
-      if (ok) {
-        /* commit: L'[r] = surviving columns + diagonal, T[r] = eliminated + 1 */
-        int32_t la = alive_count(&s);
-        lrow[r].col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(la + 1));
-        lrow[r].val = (double *)malloc(sizeof(double) * (size_t)(la + 1));
-        trow[r].col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s.tlen + 1));
-        trow[r].val = (double *)malloc(sizeof(double) * (size_t)(s.tlen + 1));
-        if (!lrow[r].col || !lrow[r].val || !trow[r].col || !trow[r].val) {
+    if (!src) seg[nseg++] = l;
+  }
+  seg[nseg] = nlev;
+  int32_t dist_max = 0, moved = 0, steps = 0;
+  for (int32_t k = 0; k < nseg; ++k) {
+    const int32_t sk = both_ends ? (k % 2 == 0 ? k / 2 : nseg - 1 - k / 2) : k;
+    int32_t t = seg[sk];
+    int64_t size_t_ = rows[t];
+    int64_t cost_t = cost[t];
+    steps++;
+    for (int32_t l = seg[sk] + 1; l < seg[sk + 1]; ++l) {
+      for (int32_t q = level_ptr[l]; q < level_ptr[l + 1]; ++q) {
+        int32_t r = level_rows[q];
+        if (!substitute(&s, rp, ci, v, cur, r, t)) {
           *status = ORC_ERR_ALLOC;
           return NULL;
         }
-        int32_t k = 0;
-        for (int32_t p = 0; p < s.wlen; ++p)
-          if (s.alive[p]) {
-            lrow[r].col[k] = s.wcol[p];
-            lrow[r].val[k] = s.wval[p];
-            ++k;
+        int64_t nnz_new = (int64_t)alive_count(&s) + 1;
+        int64_t nnz_old = rp[r + 1] - rp[r];
+        int ok;
+        if (thin_metric == 0)
+          ok = (double)(size_t_ + 1) <= W;
+        else
+          ok = (double)(cost_t + 2 * nnz_new - 1) <= W;
+        if (fill_cap > 0.0) ok = ok && (double)nnz_new <= fill_cap * (double)nnz_old;
+        if (max_distance > 0) ok = ok && (l - t) <= max_distance;
+        if (ok) {
+          int skip = 0;
+          if (max_indeg > 0 && (int64_t)alive_count(&s) >= max_indeg) skip = 1;
+          if (!skip && max_spread > 0) {
+            int32_t lo = INT32_MAX, hi = -1;
+            for (int32_t p = 0; p < s.wlen; ++p)
+              if (s.alive[p]) {
+                if (s.wcol[p] < lo) lo = s.wcol[p];
+                if (s.wcol[p] > hi) hi = s.wcol[p];
+              }
+            if (hi >= 0 && (int64_t)hi - lo >= max_spread) skip = 1;
           }
-        sort_pairs(lrow[r].col, lrow[r].val, la);
-        lrow[r].col[la] = r;
-        lrow[r].val[la] = v[rp[r + 1] - 1];
-        lrow[r].len = la + 1;
-        memcpy(trow[r].col, s.tcol, sizeof(int32_t) * (size_t)s.tlen);
-        memcpy(trow[r].val, s.tval, sizeof(double) * (size_t)s.tlen);
-        sort_pairs(trow[r].col, trow[r].val, s.tlen);
-        trow[r].col[s.tlen] = r;
-        trow[r].val[s.tlen] = 1.0;
-        trow[r].len = s.tlen + 1;
-        ws_reset_pos(&s);
-        cur[r] = t;
-        tgt[r] = t;
-        size_t_ += 1;
-        cost_t += 2 * nnz_new - 1;
-        moved += 1;
-        if (l - t > dist_max) dist_max = l - t;
-      } else {
-        ws_reset_pos(&s);
-        t = l;
-        steps++;
-        size_t_ = 0;
-        cost_t = 0;
-        for (int32_t q2 = level_ptr[l]; q2 < level_ptr[l + 1]; ++q2) {
-          int32_t r2 = level_rows[q2];
-          if (cur[r2] != l) continue; /* moved before the refusal */
-          int64_t k2 = rp[r2 + 1] - rp[r2];
-          size_t_ += 1;
-          cost_t += 2 * k2 - 1;
+          if (!skip && crit_only && !oncrit[r]) skip = 1;
+          if (skip) { /* the row stays in its level; the run goes on */
+            ws_reset_pos(&s);
+            skipped += 1;
+            continue;
+          }
         }
-        break;
+        if (ok) {
+          /* commit: L'[r] = surviving columns + diagonal, T[r] = eliminated + 1 */
+          int32_t la = alive_count(&s);
+          lrow[r].col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(la + 1));
+          lrow[r].val = (double *)malloc(sizeof(double) * (size_t)(la + 1));
+          trow[r].col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(s.tlen + 1));
+          trow[r].val = (double *)malloc(sizeof(double) * (size_t)(s.tlen + 1));
+          if (!lrow[r].col || !lrow[r].val || !trow[r].col || !trow[r].val) {
+            *status = ORC_ERR_ALLOC;
+            return NULL;
+          }
+          int32_t k = 0;
+          for (int32_t p = 0; p < s.wlen; ++p)
+            if (s.alive[p]) {
+              lrow[r].col[k] = s.wcol[p];
+              lrow[r].val[k] = s.wval[p];
+              ++k;
+            }
+          sort_pairs(lrow[r].col, lrow[r].val, la);
+          lrow[r].col[la] = r;
+          lrow[r].val[la] = v[rp[r + 1] - 1];
+          lrow[r].len = la + 1;
+          memcpy(trow[r].col, s.tcol, sizeof(int32_t) * (size_t)s.tlen);
+          memcpy(trow[r].val, s.tval, sizeof(double) * (size_t)s.tlen);
+          sort_pairs(trow[r].col, trow[r].val, s.tlen);
+          trow[r].col[s.tlen] = r;
+          trow[r].val[s.tlen] = 1.0;
+          trow[r].len = s.tlen + 1;
+          ws_reset_pos(&s);
+          cur[r] = t;
+          tgt[r] = t;
+          size_t_ += 1;
+          cost_t += 2 * nnz_new - 1;
+          moved += 1;
+          if (l - t > dist_max) dist_max = l - t;
+        } else {
+          ws_reset_pos(&s);
+          t = l;
+          steps++;
+          size_t_ = 0;
+          cost_t = 0;
+          for (int32_t q2 = level_ptr[l]; q2 < level_ptr[l + 1]; ++q2) {
+            int32_t r2 = level_rows[q2];
+            if (cur[r2] != l) continue; /* moved before the refusal */
+            int64_t k2 = rp[r2 + 1] - rp[r2];
+            size_t_ += 1;
+            cost_t += 2 * k2 - 1;
+          }
+          break;
+        }
       }
     }
   }
+  free(seg);
 
   /* Assemble L' and T; rows never rewritten are copied (T row = unit). */
   ctx->n = n;
@@ -648,7 +669,7 @@ orc_rewrite_ctx *orc_rewrite(int32_t n, const int32_t *rp, const int32_t *ci, co
                              int32_t thin_metric, double thin_threshold, double fill_cap, int32_t max_distance,
                              const uint8_t *mask, int32_t *tgt, int32_t *status) {
   return orc_rewrite_rc(n, rp, ci, v, nlev, lev, level_ptr, level_rows, thin_metric, thin_threshold, fill_cap,
-                        max_distance, mask, 0, 0, 0, tgt, status);
+                        max_distance, mask, 0, 0, 0, 0, tgt, status);
 }
 
 int32_t orc_rewrite_skipped(const orc_rewrite_ctx *c) { return c->rows_skipped; }

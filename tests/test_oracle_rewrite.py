@@ -560,3 +560,59 @@ def test_row_constraints_random(seed, case):
     rw = oracle.rewrite(m, tm, thr, cap, md, None, lv, max_indegree=alpha, max_spread=beta, critical_only=crit)
     check_rewrite_invariants(m, rw, lv, tm, thr, cap, md)
     _scan_replay_rc(m, lv, rw, tm, thr, cap, md, alpha, beta, crit)
+
+
+def _same_rewrite(a, b):
+    for f in ("lp_ptr", "lp_col", "lp_val", "t_ptr", "t_col", "t_val", "target"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    assert (a.rows_rewritten, a.max_distance, a.steps, a.rows_skipped) == \
+        (b.rows_rewritten, b.max_distance, b.steps, b.rows_skipped)
+
+
+def _segments(m, lv, tm, thr, mask=None):
+    c = oracle.level_costs(m, lv)
+    rows = np.diff(lv.level_ptr)
+    cost = c.cost
+    W = thr if not (tm == THIN_COST and thr <= 0) else c.total / lv.nlev
+    src = mask.astype(bool) if mask is not None else ((rows < W) if tm == THIN_ROWS else (cost < W))
+    src[0] = False
+    return int(np.sum(~src))
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("case", RC_CASES)
+def test_both_ends_equals_forward(seed, case):
+    """The scan taken alternately from the first and the last segment (level 0
+    and each non-source level start one) gives the forward scan's result, which
+    the replay re-derives from the definitions: a segment's decisions depend on
+    nothing outside it."""
+    rng = np.random.default_rng(500 + seed)
+    m = gen.window_random(int(rng.integers(40, 120)), 60 + seed, window=int(rng.integers(2, 9)),
+                          draws=int(rng.integers(1, 4)))
+    lv = oracle.levels(m)
+    tm, thr, cap, md, alpha, beta, crit = case
+    kw = dict(max_indegree=alpha, max_spread=beta, critical_only=crit)
+    fwd = oracle.rewrite(m, tm, thr, cap, md, None, lv, **kw)
+    both = oracle.rewrite(m, tm, thr, cap, md, None, lv, both_ends=True, **kw)
+    _same_rewrite(fwd, both)
+    _scan_replay_rc(m, lv, both, tm, thr, cap, md, alpha, beta, crit)
+
+
+@pytest.mark.parametrize("mk", [lambda: gen.stencil2d_chain(10, 60, 1), lambda: gen.stencil3d_tail(4, 30, 4),
+                                lambda: gen.powerlaw(800, 9, w_loc=16, nseg=2, seglen=25),
+                                lambda: gen.torso2_like(n=6000, nlev=120)])
+def test_both_ends_equals_forward_structured(mk):
+    m = mk()
+    lv = oracle.levels(m)
+    w = max(2, int(np.median(np.diff(lv.level_ptr))) + 1)  # about half the levels thin
+    for tm, thr, cap in [(THIN_ROWS, w, 4.0), (THIN_COST, 0.0, 0.0)]:
+        assert _segments(m, lv, tm, thr) >= 3  # several segments, so the order differs
+        fwd = oracle.rewrite(m, tm, thr, cap, 0, None, lv)
+        both = oracle.rewrite(m, tm, thr, cap, 0, None, lv, both_ends=True)
+        _same_rewrite(fwd, both)
+    rng = np.random.default_rng(3)
+    mask = (rng.random(lv.nlev) < 0.7).astype(np.uint8)
+    fwd = oracle.rewrite(m, THIN_ROWS, 16, 4.0, 0, mask, lv)
+    both = oracle.rewrite(m, THIN_ROWS, 16, 4.0, 0, mask, lv, both_ends=True)
+    _same_rewrite(fwd, both)
+    _scan_replay(m, lv, both, THIN_ROWS, 16, 4.0, 0, mask)

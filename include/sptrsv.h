@@ -147,7 +147,16 @@ sptrsv_status_t sptrsv_level_stats(sptrsv_handle_t h, int which, int64_t *d_rows
  * rearranging (Sec. II.B): L'[r] keeps its diagonal; T[r] collects the b terms
  * with a unit diagonal; explicit zeros from cancellation stay in the pattern.
  * L' is then re-levelled (empty levels vanish) and prepared for solving.
+ * The scan splits into segments, each starting at level 0 or at a non-source
+ * level and running to the next: a segment's decisions depend on nothing
+ * outside it (its rows move only within it, and every row of an earlier
+ * segment stays below its first level), so scan_workers workgroups can take
+ * segments at once, from the beginning and from the end of the level order
+ * (the parallel sketch of Sec. III: empty levels are removed only at the end,
+ * so level numbers stay valid while both scans run). Each worker holds a
+ * ~30 MB global workspace.
  * ------------------------------------------------------------------------- */
+#define SPTRSV_MAX_SCAN_WORKERS 16
 typedef struct {
   int32_t thin_metric;          /* SPTRSV_THIN_ROWS or SPTRSV_THIN_COST                         */
   double thin_threshold;        /* ROWS: W (e.g. 32). COST: <= 0 means avgLevelCost              */
@@ -157,6 +166,9 @@ typedef struct {
   int32_t max_indegree;         /* alpha: 0 = no limit                                           */
   int32_t critical_only;        /* 1: only rows on a longest path are rewritten                  */
   int64_t max_spread;           /* beta, in columns: 0 = no limit                                */
+  int32_t scan_workers;         /* workgroups running the scan at once, 0..SPTRSV_MAX_SCAN_WORKERS:
+                                   0 or 1 = one, from level 0 on; 2 = from both ends of the level
+                                   order at once; more = half from each end. Same result for all. */
 } sptrsv_rewrite_opts_t;
 
 typedef struct {

@@ -30,6 +30,9 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
   if (o->max_distance < 0) return set_err(h, SPTRSV_ERR_ARG, "rewrite: max_distance %d", o->max_distance);
   if (!(o->thin_threshold == o->thin_threshold) || !(o->fill_cap == o->fill_cap))
     return set_err(h, SPTRSV_ERR_ARG, "rewrite: NaN option");
+  if (o->scan_workers < 0 || o->scan_workers > SPTRSV_MAX_SCAN_WORKERS)
+    return set_err(h, SPTRSV_ERR_ARG, "rewrite: scan_workers %d outside [0, %d]", o->scan_workers,
+                   SPTRSV_MAX_SCAN_WORKERS);
   if (o->max_indegree < 0 || o->max_spread < 0 || (o->critical_only != 0 && o->critical_only != 1))
     return set_err(h, SPTRSV_ERR_ARG, "rewrite: row constraints max_indegree %d max_spread %lld critical_only %d",
                    o->max_indegree, (long long)o->max_spread, o->critical_only);
@@ -66,13 +69,18 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
     HIPCHK(h, launch_crit_rows(nlev, P.level_ptr.p, P.perm.p, h->rp.p, h->ci.p, P.row_level.p, height.p, oncrit.p, s));
   }
   if (n > 0 && nlev > 1) {
-    const size_t big_bytes = rewrite_big_ws_bytes(kScanBigC, kScanBigH);
+    const int32_t workers = std::max(1, o->scan_workers);
+    const size_t big_bytes = rewrite_big_ws_bytes(kScanBigC, kScanBigH) * (size_t)workers;
     if (h->rw_big.n < big_bytes) HIPCHK(h, h->rw_big.alloc(big_bytes));
+    DArr<int32_t> seg;
+    DArr<unsigned long long> claim;
+    HIPCHK(h, seg.alloc((size_t)nlev + 1));
+    HIPCHK(h, claim.alloc(1));
     HIPCHK(h, launch_rewrite_scan(n, nlev, h->rp.p, h->ci.p, h->va.p, P.level_ptr.p, P.perm.p, P.lv_rows.p,
                                   P.lv_cost.p, o->d_level_mask, o->thin_metric, W, o->fill_cap, o->max_distance,
                                   o->max_indegree, o->max_spread, o->critical_only ? oncrit.p : nullptr, aux + 32,
-                                  cur.p, h->target.p, cntL.p, cntT.p, h->rw_big.p, kScanBigC, kScanBigH, aux + 16,
-                                  s));
+                                  cur.p, h->target.p, cntL.p, cntT.p, workers, seg.p, claim.p, h->rw_big.p, kScanBigC,
+                                  kScanBigH, aux + 16, s));
     HIPCHK(h, hipMemcpyAsync(hout, aux + 16, sizeof(hout), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipMemcpyAsync(&held, aux + 32, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(h, hipStreamSynchronize(s));

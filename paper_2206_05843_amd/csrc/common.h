@@ -327,7 +327,8 @@ hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const
                                const int64_t *lv_cost, const uint8_t *mask, int32_t metric, double W, double fill_cap,
                                int32_t max_dist, int32_t max_indeg, int64_t max_spread, const uint8_t *oncrit,
                                int32_t *skipped, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
-                               char *big, int32_t bigC, int32_t bigH, int32_t *out, hipStream_t s);
+                               int32_t workers, int32_t *seg, unsigned long long *claim, char *big, int32_t bigC,
+                               int32_t bigH, int32_t *out, hipStream_t s);
 // Critical-path flags of the rows of L (height must be zeroed first).
 hipError_t launch_crit_rows(int32_t nlev, const int32_t *level_ptr, const int32_t *level_rows, const int32_t *rp,
                             const int32_t *ci, const int32_t *row_level, int32_t *height, uint8_t *oncrit,

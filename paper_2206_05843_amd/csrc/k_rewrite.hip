@@ -237,6 +237,9 @@ struct ScanArgs {
   const uint8_t *oncrit;
   int32_t *skipped;  // rows a row constraint left in place
   int32_t *cur, *target, *cntL, *cntT;
+  const int32_t *seg;            // first level of each segment, then nlev
+  unsigned long long *claim;     // (next segment from the front) << 32 | (end of those left)
+  size_t big_stride;             // bytes of global workspace per workgroup
   char *big;        // global workspace for candidates that overflow LDS
   int32_t bigC, bigH;
   int32_t *out;     // [0] rows moved [1] max distance [2] target steps [3] error bits
@@ -264,8 +267,68 @@ __device__ __forceinline__ void level_left(const ScanArgs &a, int32_t lvl, int64
   }
 }
 
-// The whole decision scan in one workgroup (levels in order, targets only
-// move forward). Thread 0 owns the scan state; waves evaluate candidates.
+__device__ __forceinline__ bool is_source(const ScanArgs &a, int32_t lvl) {
+  if (lvl == 0) return false;
+  if (a.mask) return a.mask[lvl] != 0;
+  if (a.metric == SPTRSV_THIN_ROWS) return (double)a.lv_rows[lvl] < a.W;
+  return (double)a.lv_cost[lvl] < a.W;
+}
+
+// The segments of the scan: level 0 and every level that is not a source
+// start one, and each runs to the next. A segment's scan reads nothing another
+// segment decides: its rows move only to levels inside it, and a substitution
+// expands only unknowns at or below the current target, while every row of an
+// earlier segment, moved or not, sits below the segment's first level. One
+// workgroup lists their first levels in order (ballot compaction) and sets the
+// claim word to all of them.
+__global__ __launch_bounds__(1024) void k_scan_segments(ScanArgs a, int32_t *seg) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t base;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  for (int32_t l0 = 0; l0 < a.nlev; l0 += 1024) {
+    const int32_t l = l0 + tid;
+    const bool f = l < a.nlev && !is_source(a, l);
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    int32_t off = base;
+    for (int w2 = 0; w2 < wave; ++w2) off += wsum[w2];
+    if (f) seg[off + __popcll(m & ((1ull << lane) - 1ull))] = l;
+    __syncthreads();
+    if (tid == 0) {
+      int32_t tot = 0;
+      for (int w2 = 0; w2 < 16; ++w2) tot += wsum[w2];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    seg[base] = a.nlev;
+    *a.claim = (unsigned long long)(uint32_t)base;  // front 0, end base
+  }
+}
+
+// Next segment for a workgroup taking them from the front (ascending) or from
+// the end (descending); -1 when none is left. Two workgroups are the scan
+// started at the beginning and at the end of the graph at once.
+__device__ int32_t claim_segment(unsigned long long *claim, bool front) {
+  unsigned long long old = __hip_atomic_load(claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const uint32_t lo = (uint32_t)(old >> 32), hi = (uint32_t)old;
+    if (lo >= hi) return -1;
+    const unsigned long long nw = front ? old + (1ull << 32) : old - 1ull;
+    const unsigned long long prev = atomicCAS(claim, old, nw);
+    if (prev == old) return front ? (int32_t)lo : (int32_t)(hi - 1);
+    old = prev;
+  }
+}
+
+// The decision scan: each workgroup takes segments (even-numbered workgroups
+// from the front, odd ones from the end) and scans each in level order
+// (targets only move forward). Thread 0 owns the scan state; waves evaluate
+// candidates. The result does not depend on the number of workgroups.
 __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ int32_t c_row[kWaves], c_lvl[kWaves], c_q[kWaves], c_st[kWaves], c_na[kWaves], c_nt[kWaves];
@@ -274,52 +337,48 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
   __shared__ int64_t s_capA_cost;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   Ws w = lds_ws(lds_raw, wave);
-  // scan state (thread 0)
-  int32_t t = 0, l = 1, q = 0, moved = 0, maxd = 0, steps = a.nlev > 0 ? 1 : 0, held = 0;
-  int64_t size = a.nlev > 0 ? a.lv_rows[0] : 0, cost = a.nlev > 0 ? a.lv_cost[0] : 0;
+  char *const big = a.big + (size_t)blockIdx.x * a.big_stride;
+  const bool front = (blockIdx.x & 1u) == 0u;
+  // scan state (thread 0); the first chunk claims a segment
+  int32_t t = 0, l = 0, q = 0, seg_end = 0, moved = 0, maxd = 0, steps = 0, held = 0;
+  int64_t size = 0, cost = 0;
   int bits = 0;
-  auto is_src = [&](int32_t lvl) -> bool {
-    if (a.mask) return a.mask[lvl] != 0;
-    if (a.metric == SPTRSV_THIN_ROWS) return (double)a.lv_rows[lvl] < a.W;
-    return (double)a.lv_cost[lvl] < a.W;
-  };
   const int64_t guard = (int64_t)a.n + 2 * (int64_t)a.nlev + 16;
   for (int64_t iter = 0;; ++iter) {
     if (tid == 0) {
-      // next chunk of candidates: rows of consecutive source levels
+      // next chunk of candidates: rows of consecutive source levels of the
+      // current segment, or of the next segment claimed
       int32_t nc = 0;
-      int32_t limit = kWaves;
-      if (a.metric == SPTRSV_THIN_ROWS) {
-        const double room = a.W - (double)size;  // rows the target can still take
-        if (room < (double)kWaves) limit = room < 0.0 ? 1 : (int32_t)room + 1;
-      }
-      while (l < a.nlev && nc < limit) {
-        if (!is_src(l)) {
-          if (nc > 0) break;
-          t = l;
-          size = a.lv_rows[l];
-          cost = a.lv_cost[l];
-          ++steps;
-          ++l;
-          q = 0;
-          if (a.metric == SPTRSV_THIN_ROWS) {
-            const double room = a.W - (double)size;
-            limit = room < (double)kWaves ? (room < 0.0 ? 1 : (int32_t)room + 1) : kWaves;
+      for (;;) {
+        int32_t limit = kWaves;
+        if (a.metric == SPTRSV_THIN_ROWS) {
+          const double room = a.W - (double)size;  // rows the target can still take
+          if (room < (double)kWaves) limit = room < 0.0 ? 1 : (int32_t)room + 1;
+        }
+        while (l < seg_end && nc < limit) {
+          const int32_t lb = a.level_ptr[l], lr = a.level_ptr[l + 1] - lb;
+          while (q < lr && nc < limit) {
+            c_row[nc] = a.level_rows[lb + q];
+            c_lvl[nc] = l;
+            c_q[nc] = q;
+            ++nc;
+            ++q;
           }
-          continue;
+          if (q == lr) {
+            ++l;
+            q = 0;
+          }
         }
-        const int32_t lb = a.level_ptr[l], lr = a.level_ptr[l + 1] - lb;
-        while (q < lr && nc < limit) {
-          c_row[nc] = a.level_rows[lb + q];
-          c_lvl[nc] = l;
-          c_q[nc] = q;
-          ++nc;
-          ++q;
-        }
-        if (q == lr) {
-          ++l;
-          q = 0;
-        }
+        if (nc > 0) break;
+        const int32_t k = claim_segment(a.claim, front);
+        if (k < 0) break;
+        t = a.seg[k];
+        seg_end = a.seg[k + 1];
+        size = a.lv_rows[t];
+        cost = a.lv_cost[t];
+        ++steps;
+        l = t + 1;
+        q = 0;
       }
       s_nc = nc;
       s_t = t;
@@ -351,7 +410,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
       int stt = subst_row(w, r, tt, a.rp, a.ci, a.va, a.cur, capA, &nT);
       Ws used = w;
       if (stt == SUB_OVERFLOW) {
-        used = global_ws(a.big + (size_t)wave * kTier1Bytes, kTier1C, kTier1H);
+        used = global_ws(big + (size_t)wave * kTier1Bytes, kTier1C, kTier1H);
         nT = 0;
         stt = subst_row(used, r, tt, a.rp, a.ci, a.va, a.cur, capA, &nT);
       }
@@ -418,7 +477,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
       // evaluate that candidate alone with the large global workspace
       if (wave == 0) {
         const int32_t i = s_redo, r = c_row[i];
-        Ws g = global_ws(a.big, a.bigC, a.bigH);
+        Ws g = global_ws(big, a.bigC, a.bigH);
         int32_t nT = 0;
         const int stt = subst_row(g, r, s_t, a.rp, a.ci, a.va, a.cur, INT64_MAX, &nT);
         const int2 span = stt == SUB_OK && a.max_spread > 0 ? ws_a_span(g) : make_int2(0, 0);
@@ -478,12 +537,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
       if (s_done) break;
     }
   }
-  if (tid == 0) {
-    a.out[0] = moved;
-    a.out[1] = maxd;
-    a.out[2] = steps;
-    a.out[3] = bits;
-    *a.skipped = held;
+  if (tid == 0) {  // the outputs start at zero; every workgroup adds its part
+    atomicAdd(a.out + 0, moved);
+    atomicMax(a.out + 1, maxd);
+    atomicAdd(a.out + 2, steps);
+    if (bits) atomicOr(a.out + 3, bits);
+    atomicAdd(a.skipped, held);
   }
 }
 
@@ -689,7 +748,9 @@ hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const
                                const int64_t *lv_cost, const uint8_t *mask, int32_t metric, double W, double fill_cap,
                                int32_t max_dist, int32_t max_indeg, int64_t max_spread, const uint8_t *oncrit,
                                int32_t *skipped, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
-                               char *big, int32_t bigC, int32_t bigH, int32_t *out, hipStream_t s) {
+                               int32_t workers, int32_t *seg, unsigned long long *claim, char *big, int32_t bigC,
+                               int32_t bigH, int32_t *out, hipStream_t s) {
+  if (workers < 1) return hipErrorInvalidValue;
   ScanArgs a;
   a.n = n;
   a.nlev = nlev;
@@ -713,11 +774,14 @@ hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const
   a.target = target;
   a.cntL = cntL;
   a.cntT = cntT;
+  a.seg = seg;
+  a.claim = claim;
   a.big = big;
   a.bigC = bigC;
   a.bigH = bigH;
+  a.big_stride = rewrite_big_ws_bytes(bigC, bigH);  // one full workspace per workgroup
   // the full workspace also holds the waves' first-retry regions
-  if (rewrite_big_ws_bytes(bigC, bigH) < (size_t)kWaves * kTier1Bytes) return hipErrorInvalidValue;
+  if (a.big_stride < (size_t)kWaves * kTier1Bytes) return hipErrorInvalidValue;
   a.out = out;
   static bool attr = false;
   if (!attr) {
@@ -727,7 +791,8 @@ hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsWsBytes);
     attr = true;
   }
-  hipLaunchKernelGGL(k_rewrite_scan, dim3(1), dim3(64 * kWaves), kLdsWsBytes, s, a);
+  hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(1024), 0, s, a, seg);
+  hipLaunchKernelGGL(k_rewrite_scan, dim3(workers), dim3(64 * kWaves), kLdsWsBytes, s, a);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ class SptrsvError(RuntimeError):
 class RewriteOpts(C.Structure):
     _fields_ = [("thin_metric", C.c_int32), ("thin_threshold", C.c_double), ("fill_cap", C.c_double),
                 ("max_distance", C.c_int32), ("d_level_mask", C.c_void_p), ("max_indegree", C.c_int32),
-                ("critical_only", C.c_int32), ("max_spread", C.c_int64)]
+                ("critical_only", C.c_int32), ("max_spread", C.c_int64), ("scan_workers", C.c_int32)]
 
 
 class RewriteStats(C.Structure):
@@ -244,10 +244,10 @@ class Handle:
 
     # ------------------------------------------------------------------- rewrite
     def rewrite(self, thin_metric=THIN_ROWS, thin_threshold=32.0, fill_cap=4.0, max_distance=0, mask=None,
-                max_indegree=0, max_spread=0, critical_only=False):
+                max_indegree=0, max_spread=0, critical_only=False, scan_workers=1):
         o = RewriteOpts(thin_metric, float(thin_threshold), float(fill_cap), int(max_distance),
                         _ptr(mask) if mask is not None else None, int(max_indegree), int(bool(critical_only)),
-                        int(max_spread))
+                        int(max_spread), int(scan_workers))
         if mask is not None:
             _need(mask.dtype == torch.uint8 and mask.numel() >= self.nlev, "uint8 mask of nlev entries expected")
         st = RewriteStats()

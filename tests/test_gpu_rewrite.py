@@ -289,3 +289,60 @@ def test_rewrite_rows_past_the_retry_region(held):
         assert rw.rows_rewritten == 2 and int(np.max(np.diff(rw.t_ptr))) > 1 << 14
     assert st["rows_skipped"] == rw.rows_skipped
     compare(m, h, st, rw, lv, nrhs=(1,))
+
+
+SEG_CASES = {
+    "cfg2_rows32": (lambda: gen.config_matrix(2, "small")[0], OPTS["rows32_cap4"]),
+    "cfg4_cost": (lambda: gen.config_matrix(4, "small")[0], OPTS["cost_avg"]),
+    "window_rc": (lambda: gen.window_random(3001, 4, window=12, draws=3), RC_OPTS["cost_all"]),
+    "torso_cost": (lambda: gen.torso2_like(n=20000, nlev=200), OPTS["cost_avg_cap3_d4"]),
+    "cfg1_rows8": (lambda: gen.config_matrix(1, "small")[0], OPTS["rows8"]),
+}
+
+
+@pytest.mark.parametrize("workers", [2, 3, 16])
+@pytest.mark.parametrize("case", list(SEG_CASES))
+def test_scan_from_both_ends_parity(case, workers):
+    """Several workgroups take the scan's segments from both ends of the level
+    order at once; every decision, pattern and value equals the oracle's."""
+    from tests.test_oracle_rewrite import _segments
+    mk, o = SEG_CASES[case]
+    m = mk()
+    lv = oracle.levels(m)
+    assert _segments(m, lv, o["thin_metric"], o["thin_threshold"]) >= workers
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(**o, scan_workers=workers)
+    rw = oracle.rewrite(m, o["thin_metric"], o["thin_threshold"], o["fill_cap"], o["max_distance"], None, lv,
+                        max_indegree=o.get("max_indegree", 0), max_spread=o.get("max_spread", 0),
+                        critical_only=o.get("critical_only", False), both_ends=True)
+    assert st["rows_skipped"] == rw.rows_skipped
+    compare(m, h, st, rw, lv, nrhs=(1,))
+
+
+def test_scan_from_both_ends_with_mask_and_global_workspace():
+    # segments start at the unmasked levels; rows that overflow the LDS
+    # workspace take each workgroup's own global one
+    m = gen.window_random(1500, 7, window=40, draws=6)
+    lv = oracle.levels(m)
+    mask = np.ones(lv.nlev, np.uint8)
+    mask[[0, 10, 40, 41, 90]] = 0
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(0, 1e9, 0.0, 0, mask=to_dev(mask), max_indegree=11, scan_workers=4)
+    rw = oracle.rewrite(m, 0, 1e9, 0.0, 0, mask, lv, max_indegree=11, both_ends=True)
+    assert rw.rows_rewritten > 0
+    assert st["rows_skipped"] == rw.rows_skipped
+    compare(m, h, st, rw, lv, nrhs=(1,))
+
+
+def test_scan_workers_errors():
+    m = gen.bidiagonal(50, 1)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    for bad in (-1, 17):
+        with pytest.raises(sp.SptrsvError):
+            h.rewrite(sp.THIN_ROWS, 8.0, 0.0, 0, scan_workers=bad)
+    st = h.rewrite(sp.THIN_ROWS, 8.0, 0.0, 0, scan_workers=0)  # 0 is one workgroup
+    rw = oracle.rewrite(m, sp.THIN_ROWS, 8.0, 0.0, 0)
+    assert st["rows_rewritten"] == rw.rows_rewritten

@@ -640,6 +640,36 @@ sptrsv_status_t analyze_form(sptrsv_ctx *h, int32_t form, int32_t n, int32_t nnz
 
 }  // namespace
 
+// Longest-path membership of the rows of the handle's lower matrix (row
+// constraints of Sec. III.A): heights are the levels of J L^T J, whose row
+// n - 1 - r lists the dependents of row r, found by the same level kernel as
+// the plan's levels; oncrit[r] = level(r) + height(r) == nlev - 1.
+sptrsv_status_t crit_rows(sptrsv_ctx *h, const Plan &P, uint8_t *oncrit, hipStream_t s) {
+  const int32_t n = P.n, nnz = h->nnz;
+  if (n == 0) return SPTRSV_OK;
+  DArr<int32_t> t_rp, t_ci, m_rp, m_ci, levr;
+  DArr<double> t_va, m_va;
+  HIPCHK(h, t_rp.alloc((size_t)n + 1));
+  HIPCHK(h, m_rp.alloc((size_t)n + 1));
+  HIPCHK(h, t_ci.alloc((size_t)nnz));
+  HIPCHK(h, m_ci.alloc((size_t)nnz));
+  HIPCHK(h, t_va.alloc((size_t)nnz));
+  HIPCHK(h, m_va.alloc((size_t)nnz));
+  HIPCHK(h, levr.alloc((size_t)n));
+  STCHK(transpose_csr(h, n, nnz, h->rp.p, h->ci.p, h->va.p, t_rp.p, t_ci.p, t_va.p, s));
+  HIPCHK(h, launch_rev_entries(n, nnz, t_rp.p, t_ci.p, t_va.p, m_rp.p, m_ci.p, m_va.p, s));
+  int32_t *aux = h->d_aux.p;  // [40] ticket, [41] error bits
+  HIPCHK(h, hipMemsetAsync(aux + 40, 0, 2 * sizeof(int32_t), s));
+  HIPCHK(h, hipMemsetAsync(levr.p, 0, sizeof(int32_t) * (size_t)n, s));
+  HIPCHK(h, launch_levels(n, m_rp.p, m_ci.p, levr.p, reinterpret_cast<unsigned *>(aux + 40), aux + 41, s));
+  int32_t bits = 0;
+  HIPCHK(h, hipMemcpyAsync(&bits, aux + 41, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  if (bits) return set_err(h, status_from_bits(bits), "critical-path heights failed (bits 0x%x)", bits);
+  HIPCHK(h, launch_crit_flags(n, P.nlev, P.row_level.p, levr.p, oncrit, s));
+  return SPTRSV_OK;
+}
+
 extern "C" {
 
 sptrsv_status_t sptrsv_analyze(sptrsv_handle_t h, int32_t n, int32_t nnz, const int32_t *d_row_ptr,

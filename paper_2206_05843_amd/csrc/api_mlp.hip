@@ -21,17 +21,15 @@ sptrsv_status_t sptrsv_level_features(sptrsv_handle_t h, float *d_feat, hipStrea
   const int32_t n = P.n, nlev = P.nlev;
   if (nlev == 0) return SPTRSV_OK;
   DArr<long long> sums;  // sum_lp, sum_t, sum_span
-  DArr<int32_t> hist, redo, height;
+  DArr<int32_t> hist, redo;
   DArr<uint8_t> oncrit;
   HIPCHK(h, sums.alloc((size_t)nlev * 3));
   HIPCHK(h, hist.alloc((size_t)nlev * kFeatHist));
   HIPCHK(h, redo.alloc(n));
-  HIPCHK(h, height.alloc(n));
   HIPCHK(h, oncrit.alloc(n));
   HIPCHK(h, hipMemsetAsync(sums.p, 0, sizeof(long long) * (size_t)nlev * 3, s));
   HIPCHK(h, hipMemsetAsync(hist.p, 0, sizeof(int32_t) * (size_t)nlev * kFeatHist, s));
-  HIPCHK(h, hipMemsetAsync(height.p, 0, sizeof(int32_t) * (size_t)n, s));
-  HIPCHK(h, launch_crit_rows(nlev, P.level_ptr.p, P.perm.p, h->rp.p, h->ci.p, P.row_level.p, height.p, oncrit.p, s));
+  STCHK(crit_rows(h, P, oncrit.p, s));
   const FeatAcc acc{sums.p, sums.p + nlev, sums.p + 2 * (size_t)nlev, hist.p, oncrit.p};
   int32_t *aux = h->d_aux.p;  // [24] redo count, [25] error bits
   HIPCHK(h, hipMemsetAsync(aux + 24, 0, 2 * sizeof(int32_t), s));

@@ -60,13 +60,10 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
   HIPCHK(h, hipMemsetAsync(aux + 16, 0, 8 * sizeof(int32_t), s));
   HIPCHK(h, hipMemsetAsync(aux + 32, 0, sizeof(int32_t), s));
   int32_t hout[8] = {0}, held = 0;
-  DArr<int32_t> height;
   DArr<uint8_t> oncrit;
   if (n > 0 && nlev > 1 && o->critical_only) {
-    HIPCHK(h, height.alloc(n));
     HIPCHK(h, oncrit.alloc(n));
-    HIPCHK(h, hipMemsetAsync(height.p, 0, sizeof(int32_t) * (size_t)n, s));
-    HIPCHK(h, launch_crit_rows(nlev, P.level_ptr.p, P.perm.p, h->rp.p, h->ci.p, P.row_level.p, height.p, oncrit.p, s));
+    STCHK(crit_rows(h, P, oncrit.p, s));
   }
   if (n > 0 && nlev > 1) {
     const int32_t workers = std::max(1, o->scan_workers);

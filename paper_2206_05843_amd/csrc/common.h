@@ -329,10 +329,10 @@ hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const
                                int32_t *skipped, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
                                int32_t workers, int32_t *seg, unsigned long long *claim, char *big, int32_t bigC,
                                int32_t bigH, int32_t *out, hipStream_t s);
-// Critical-path flags of the rows of L (height must be zeroed first).
-hipError_t launch_crit_rows(int32_t nlev, const int32_t *level_ptr, const int32_t *level_rows, const int32_t *rp,
-                            const int32_t *ci, const int32_t *row_level, int32_t *height, uint8_t *oncrit,
-                            hipStream_t s);
+// Critical-path flags of the rows of L from its levels and the 1-based levels
+// levr of J L^T J (the heights of L's rows, in reverse row order, plus one).
+hipError_t launch_crit_flags(int32_t n, int32_t nlev, const int32_t *row_level, const int32_t *levr,
+                             uint8_t *oncrit, hipStream_t s);
 hipError_t launch_row_counts(int32_t n, const int32_t *rp, const int32_t *target, const int32_t *cntL,
                              const int32_t *cntT, long long *cl, long long *ct, hipStream_t s);
 hipError_t launch_collect_moved(int32_t n, const int32_t *target, const int32_t *cntL, const int32_t *cntT,
@@ -405,6 +405,9 @@ sptrsv_status_t build_images(sptrsv_ctx *h, Plan &P, hipStream_t s);
 sptrsv_status_t ensure_work(sptrsv_ctx *h, Plan &P, int32_t nrhs);
 
 // Plan building (api.hip) --------------------------------------------------------
+// Longest-path membership flags of the rows of the handle's lower matrix
+// (plan P of it): oncrit[r] = level(r) + height(r) == nlev - 1. Synchronous.
+sptrsv_status_t crit_rows(sptrsv_ctx *h, const Plan &P, uint8_t *oncrit, hipStream_t s);
 sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
                            const double *va, const int32_t *trp, const int32_t *tci, const double *tva,
                            hipStream_t s, bool rev_io = false);

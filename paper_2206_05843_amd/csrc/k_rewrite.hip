@@ -708,36 +708,24 @@ __global__ __launch_bounds__(64 * kWaves) void k_feat_rows(int32_t n, const int3
   }
 }
 
-// Critical-path membership of the rows of L: heights (longest path to a row
-// nothing depends on) by one workgroup sweeping the levels from the last back;
-// a row's dependents all sit in later levels, so its height is final when its
-// level comes, and it raises its dependencies' heights with atomic maxima.
-// oncrit[r] = level(r) + height(r) == nlev - 1. height must start at zero.
-__global__ __launch_bounds__(1024) void k_crit_rows(int32_t nlev, const int32_t *__restrict__ level_ptr,
-                                                    const int32_t *__restrict__ level_rows,
-                                                    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                    const int32_t *__restrict__ row_level, int32_t *height,
-                                                    uint8_t *oncrit) {
-  for (int32_t l = nlev - 1; l >= 0; --l) {
-    for (int32_t q = level_ptr[l] + (int32_t)threadIdx.x; q < level_ptr[l + 1]; q += (int32_t)blockDim.x) {
-      const int32_t r = level_rows[q];
-      const int32_t hr = __hip_atomic_load(height + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      for (int32_t p = rp[r]; p < rp[r + 1] - 1; ++p) atomicMax(height + ci[p], hr + 1);
-      oncrit[r] = (uint8_t)(row_level[r] + hr == nlev - 1 ? 1 : 0);
-    }
-    __threadfence();
-    __syncthreads();
-  }
+// Critical-path membership of the rows of L from two level numberings:
+// row_level[r] (longest path from a source to r) and levr[n - 1 - r], the
+// 1-based level of row n - 1 - r in J L^T J, whose rows are the dependents of
+// the rows of L in reverse order, so that levr[n - 1 - r] - 1 is the height of
+// r (longest path from r to a row nothing depends on).
+// oncrit[r] = level(r) + height(r) == nlev - 1.
+__global__ void k_crit_flags(int32_t n, int32_t nlev, const int32_t *__restrict__ row_level,
+                             const int32_t *__restrict__ levr, uint8_t *oncrit) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+    oncrit[r] = (uint8_t)(row_level[r] + levr[n - 1 - r] - 1 == nlev - 1 ? 1 : 0);
 }
 
 }  // namespace
 
-hipError_t launch_crit_rows(int32_t nlev, const int32_t *level_ptr, const int32_t *level_rows, const int32_t *rp,
-                            const int32_t *ci, const int32_t *row_level, int32_t *height, uint8_t *oncrit,
-                            hipStream_t s) {
-  if (nlev == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_crit_rows, dim3(1), dim3(1024), 0, s, nlev, level_ptr, level_rows, rp, ci, row_level, height,
-                     oncrit);
+hipError_t launch_crit_flags(int32_t n, int32_t nlev, const int32_t *row_level, const int32_t *levr,
+                             uint8_t *oncrit, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_crit_flags, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, nlev, row_level, levr, oncrit);
   return hipGetLastError();
 }
 

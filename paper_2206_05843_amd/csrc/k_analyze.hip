@@ -45,7 +45,21 @@ __global__ void k_validate(int32_t n, int32_t nnz, const int32_t *__restrict__ r
 // index) is already claimed by a running wave. lev1[r] holds level+1 once row r
 // is done (0 = not yet). A lane finishes its row when all dependencies are
 // published; lanes waiting on lower lanes of their own wave are released as the
-// wave keeps iterating. Waits are bounded by a wall-clock limit.
+// wave keeps iterating. A row with more than kLongRow dependencies left is
+// swept by the whole wave first, kLongRow entries per step, one step after
+// another while every entry of a step is published (the dependents lists of a
+// power-law matrix's hub columns have millions of entries; one lane reading
+// them one by one took seconds). Waits are bounded by a wall-clock limit.
+constexpr int kLongRow = 256;
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 __global__ void k_levels(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, int32_t *lev1,
                          unsigned *ticket, int *err, unsigned long long tlimit) {
   const int lane = threadIdx.x & 63;
@@ -64,7 +78,35 @@ __global__ void k_levels(int32_t n, const int32_t *__restrict__ rp, const int32_
     }
     unsigned spins = 0;
     while (__ballot(pend) != 0ull) {
-      if (pend) {
+      unsigned long long lm = __ballot(pend && e - p > kLongRow);
+      while (lm != 0ull) {  // long rows, one at a time, by the whole wave
+        const int src = __builtin_ctzll(lm);
+        lm &= lm - 1ull;
+        int32_t sp = __shfl(p, src, 64), smx = __shfl(mx, src, 64);
+        const int32_t se = __shfl(e, src, 64);
+        for (int step = 0; step < 64 && se - sp > kLongRow; ++step) {
+          int32_t v[kLongRow / 64];
+#pragma unroll
+          for (int j = 0; j < kLongRow / 64; ++j)
+            v[j] = __hip_atomic_load(lev1 + ci[sp + j * 64 + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          bool ready = true;
+          int32_t m = 0;
+#pragma unroll
+          for (int j = 0; j < kLongRow / 64; ++j) {
+            ready = ready && v[j] != 0;
+            m = v[j] > m ? v[j] : m;
+          }
+          if (__ballot(!ready) != 0ull) break;  // a dependency is pending: come back to it later
+          m = wave_max_i32(m);
+          smx = m > smx ? m : smx;
+          sp += kLongRow;
+        }
+        if (lane == src) {
+          p = sp;
+          mx = smx;
+        }
+      }
+      if (pend && e - p <= kLongRow) {  // longer rows advance only through the sweep above
         while (p < e) {
           int32_t v = __hip_atomic_load(lev1 + ci[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (v == 0) break;

@@ -339,7 +339,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the solve of one matrix is not sharded "
-                                   "across GPUs (see DESIGN.md, multi-GPU section)", "n_gpus": args.gpus}))
+                                   "across GPUs (a level-set solve would need a device-wide exchange per level)",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

@@ -336,3 +336,46 @@ def test_syncfree_grid_sizes(handles, grid):
         h.set_schedule(mode=3, wide_grid=4096)
     assert ei.value.name == "ARG"
     h.set_schedule(mode=0)
+
+
+def _long_rows_matrix(n=6000, first=4000, reach=4000, seed=11):
+    """Rows first..first+63 (one wave's claim) each read every row below
+    `reach` and the row before them, so the whole wave sweeps long rows whose
+    last dependency is a lower lane of its own wave; a few later rows read
+    hundreds of spread-out rows; the rest are a random window pattern."""
+    rng = np.random.default_rng(seed)
+    rp, ci, va = [0], [], []
+    for r in range(n):
+        if first <= r < first + 64:
+            cols = list(range(0, reach, 1)) + ([r - 1] if r - 1 >= reach else [])
+        elif r >= first + 64 and r % 97 == 0:
+            cols = sorted(set(rng.choice(r, size=min(r, 700), replace=False).tolist()))
+        else:
+            k = min(r, 3)
+            cols = sorted(set((r - 1 - rng.integers(0, 40, size=k)).clip(0).tolist())) if r else []
+            cols = [c for c in cols if c < r]
+        for c in cols:
+            ci.append(c)
+            va.append(-0.5 / max(1, len(cols)))
+        ci.append(r)
+        va.append(2.0)
+        rp.append(len(ci))
+    return gen.Csr(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va))
+
+
+def test_levels_with_long_rows():
+    # rows with more than 256 dependencies left are swept by the whole wave,
+    # which steps back while a dependency (here a lower lane of the same wave)
+    # is still pending
+    m = _long_rows_matrix()
+    lv = oracle.levels(m)
+    h = sp.Handle()
+    nlev = h.analyze(*dev(m))
+    assert nlev == lv.nlev
+    lp, lr, rl = h.levels()
+    assert np.array_equal(rl.cpu().numpy(), lv.row_level)
+    assert np.array_equal(lr.cpu().numpy(), lv.level_rows)
+    b = gen.rhs(m, 1)
+    x = h.solve(to_dev(b))
+    h.check()
+    assert oracle.relerr(x.cpu().numpy(), oracle.solve(m, b)) <= TOL

@@ -154,7 +154,7 @@ sptrsv_status_t sptrsv_level_stats(sptrsv_handle_t h, int which, int64_t *d_rows
  * segments at once, from the beginning and from the end of the level order
  * (the parallel sketch of Sec. III: empty levels are removed only at the end,
  * so level numbers stay valid while both scans run). Each worker holds a
- * ~30 MB global workspace.
+ * ~34 MB global workspace.
  * ------------------------------------------------------------------------- */
 #define SPTRSV_MAX_SCAN_WORKERS 16
 typedef struct {

@@ -25,13 +25,19 @@ namespace {
 constexpr int kWaves = 8;          // waves per workgroup in both kernels
 constexpr int kLdsC = 512;         // LDS workspace entries per wave
 constexpr int kLdsH = 1024;        // LDS hash slots per wave
+// Bytes of a workspace of C entries and H hash slots: val[C], hkey[H],
+// hslot[H], col[C], four counters, st[C] (padded to 4 bytes), pend[C]; a
+// multiple of 16 so that consecutive workspaces stay aligned.
+__host__ __device__ constexpr size_t ws_core_bytes(size_t C, size_t H) {
+  return (C * 8 + H * 8 + C * 4 + 16 + ((C + 3) & ~(size_t)3) + C * 4 + 15) & ~(size_t)15;
+}
 // A scan candidate that outgrows its LDS workspace is evaluated again at once
 // by the same wave in a private region of the global workspace of this size
 // (cleared per candidate, so kept far below the full workspace); only a row
 // that outgrows that too takes the serial path through the full workspace.
 constexpr int kTier1C = 1 << 14;
 constexpr int kTier1H = 1 << 15;
-constexpr size_t kTier1Bytes = (((size_t)kTier1C * 13 + (size_t)kTier1H * 8 + 64) + 255) & ~(size_t)255;
+constexpr size_t kTier1Bytes = ((ws_core_bytes(kTier1C, kTier1H) + 48) + 255) & ~(size_t)255;
 
 enum : int { SUB_OK = 0, SUB_REJECT = 1, SUB_OVERFLOW = 2 };
 
@@ -43,8 +49,11 @@ struct Ws {
   uint8_t *st;      // [C]
   int32_t *cnt;     // entries used
   int32_t *na;      // entries in state 0
+  int32_t *np;      // entries in state 1 (listed in pend)
+  int32_t *pend;    // [C] entry indices of the state-1 entries, in no order
   int32_t C, H;
 };
+
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
@@ -87,6 +96,8 @@ __device__ __forceinline__ int32_t ws_find_or_insert(Ws &w, int32_t k, bool &isn
 
 // Rewrite row r toward target t (B = rows with cur >= t). Stops early with
 // SUB_REJECT once more than capA A-columns exist (their number only grows).
+// The entries still to substitute (state 1) are also listed in pend, so each
+// step finds the largest of them by reading that list, not every entry.
 __device__ int subst_row(Ws &w, int32_t r, int32_t t, const int32_t *__restrict__ rp,
                          const int32_t *__restrict__ ci, const double *__restrict__ va, const int32_t *cur,
                          int64_t capA, int32_t *nT_out) {
@@ -96,6 +107,7 @@ __device__ int subst_row(Ws &w, int32_t r, int32_t t, const int32_t *__restrict_
   if (lane == 0) {
     *w.cnt = 0;
     *w.na = 0;
+    *w.np = 0;
   }
   wave_sync();
   int overflow = 0;
@@ -113,7 +125,10 @@ __device__ int subst_row(Ws &w, int32_t r, int32_t t, const int32_t *__restrict_
       w.col[s] = k;
       w.val[s] = va[p];
       w.st[s] = inB ? 1 : 0;
-      if (!inB) atomicAdd(w.na, 1);
+      if (inB)
+        w.pend[atomicAdd(w.np, 1)] = s;
+      else
+        atomicAdd(w.na, 1);
     }
   }
   wave_sync();
@@ -121,22 +136,26 @@ __device__ int subst_row(Ws &w, int32_t r, int32_t t, const int32_t *__restrict_
   if ((int64_t)*w.na > capA) return SUB_REJECT;
   int32_t nT = 0;
   for (;;) {
-    const int32_t nE = *w.cnt;
+    // the largest column still to substitute, from the list of those entries
+    const int32_t npend = *w.np;
     long long best = -1;
-    for (int32_t s = lane; s < nE; s += 64)
-      if (w.st[s] == 1) {
-        const long long key = ((long long)w.col[s] << 32) | (long long)s;
-        best = key > best ? key : best;
-      }
+    for (int32_t i = lane; i < npend; i += 64) {
+      const long long key = ((long long)w.col[w.pend[i]] << 32) | (long long)i;
+      best = key > best ? key : best;
+    }
     best = wave_max_ll(best);
     if (best < 0) break;
-    const int32_t j = (int32_t)(best >> 32), sj = (int32_t)(best & 0xffffffffll);
+    const int32_t j = (int32_t)(best >> 32), ij = (int32_t)(best & 0xffffffffll);
+    const int32_t sj = w.pend[ij];
     const double m = w.val[sj] / va[rp[j + 1] - 1];
     wave_sync();
     if (lane == 0) {
       w.st[sj] = 2;
       w.val[sj] = -m;
+      w.pend[ij] = w.pend[npend - 1];
+      *w.np = npend - 1;
     }
+    wave_sync();
     ++nT;
     const int32_t jb = rp[j], je = rp[j + 1] - 1;
     for (int32_t p = jb + lane; p < je; p += 64) {
@@ -154,7 +173,10 @@ __device__ int subst_row(Ws &w, int32_t r, int32_t t, const int32_t *__restrict_
         w.col[s] = k;
         w.val[s] = 0.0 - prod;
         w.st[s] = inB ? 1 : 0;
-        if (!inB) atomicAdd(w.na, 1);
+        if (inB)
+          w.pend[atomicAdd(w.np, 1)] = s;
+        else
+          atomicAdd(w.na, 1);
       } else {
         w.val[s] = w.val[s] - prod;
       }
@@ -188,8 +210,8 @@ __device__ __forceinline__ int2 ws_a_span(const Ws &w) {
 }
 
 __device__ __forceinline__ Ws lds_ws(char *base, int wave) {
-  // per wave: hkey[H] hslot[H] col[C] val[C] st[C] cnt na
-  constexpr size_t per = (size_t)kLdsH * 8 + (size_t)kLdsC * 13 + 16;
+  // per wave: val[C] hkey[H] hslot[H] col[C] cnt na np - st[C] pend[C]
+  constexpr size_t per = ws_core_bytes(kLdsC, kLdsH);
   constexpr size_t per_al = (per + 15) & ~(size_t)15;
   char *p = base + (size_t)wave * per_al;
   Ws w;
@@ -199,12 +221,14 @@ __device__ __forceinline__ Ws lds_ws(char *base, int wave) {
   w.col = w.hslot + kLdsH;
   w.cnt = w.col + kLdsC;
   w.na = w.cnt + 1;
+  w.np = w.na + 1;
   w.st = reinterpret_cast<uint8_t *>(w.na + 3);
   w.C = kLdsC;
   w.H = kLdsH;
+  w.pend = reinterpret_cast<int32_t *>(w.st + ((w.C + 3) & ~3));
   return w;
 }
-constexpr size_t kLdsWsBytes = (((size_t)kLdsH * 8 + (size_t)kLdsC * 13 + 16 + 15) & ~(size_t)15) * kWaves;
+constexpr size_t kLdsWsBytes = ((ws_core_bytes(kLdsC, kLdsH) + 15) & ~(size_t)15) * kWaves;
 
 __device__ __forceinline__ Ws global_ws(char *base, int32_t C, int32_t H) {
   Ws w;
@@ -214,9 +238,11 @@ __device__ __forceinline__ Ws global_ws(char *base, int32_t C, int32_t H) {
   w.col = w.hslot + H;
   w.cnt = w.col + C;
   w.na = w.cnt + 1;
+  w.np = w.na + 1;
   w.st = reinterpret_cast<uint8_t *>(w.na + 3);
   w.C = C;
   w.H = H;
+  w.pend = reinterpret_cast<int32_t *>(w.st + ((w.C + 3) & ~3));
   return w;
 }
 
@@ -575,7 +601,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_rows(
   extern __shared__ __align__(16) char lds_raw[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   Ws w = use_big ? global_ws(big + (size_t)(blockIdx.x * kWaves + wave) *
-                                       ((size_t)bigC * 13 + (size_t)bigH * 8 + 64),
+                                       (ws_core_bytes(bigC, bigH) + 48),
                              bigC, bigH)
                  : lds_ws(lds_raw, wave);
   const int64_t gw = (int64_t)blockIdx.x * kWaves + wave, nw = (int64_t)gridDim.x * kWaves;
@@ -662,7 +688,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_feat_rows(int32_t n, const int3
   extern __shared__ __align__(16) char lds_raw[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool use_big = big != nullptr;
-  Ws w = use_big ? global_ws(big + (size_t)(blockIdx.x * kWaves + wave) * ((size_t)bigC * 13 + (size_t)bigH * 8 + 64),
+  Ws w = use_big ? global_ws(big + (size_t)(blockIdx.x * kWaves + wave) * (ws_core_bytes(bigC, bigH) + 48),
                              bigC, bigH)
                  : lds_ws(lds_raw, wave);
   const int64_t total = rows ? nrows : n;
@@ -729,7 +755,7 @@ hipError_t launch_crit_flags(int32_t n, int32_t nlev, const int32_t *row_level, 
   return hipGetLastError();
 }
 
-size_t rewrite_big_ws_bytes(int32_t C, int32_t H) { return (size_t)C * 13 + (size_t)H * 8 + 64; }
+size_t rewrite_big_ws_bytes(int32_t C, int32_t H) { return ws_core_bytes(C, H) + 48; }
 
 hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const int32_t *ci, const double *va,
                                const int32_t *level_ptr, const int32_t *level_rows, const int64_t *lv_rows,

@@ -11,9 +11,12 @@ Functions and the paper passages they follow (arXiv 2206.05843):
   solve           serial forward substitution               Sec. II.A, Algorithm 1
   levels          level sets by longest dependency path     Sec. II.A
   level_costs     2*nnz-1 per row, avgLevelCost             Sec. III, cost model
-  rewrite         thin/target/source scan + substitution    Sec. II.B, Sec. III
+  rewrite         thin/target/source scan + substitution    Sec. II.B, Sec. III; row constraints
+                  Sec. III.A; both_ends: segments taken from both ends (Sec. III, parallel sketch)
   spmv            b' = T b                                  Sec. II.B (rearrangement)
-  level_features  learned-policy inputs                     no paper passage (see oracle.c)
+  solve_upper / solve_form  U x = b and transposed forms    Sec. I (preconditioner use)
+  level_features  learned-policy inputs                     no paper passage for 0..15; 16..19 are the
+                  Sec. III.A row constraints measured per level (see oracle.c)
 """
 from __future__ import annotations
 

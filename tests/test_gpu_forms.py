@@ -78,21 +78,22 @@ def test_form_solve_parity(name, fname, nrhs):
     assert max(res) <= 1e-12 * (1.0 + float(np.abs(xr).max()))
 
 
+@pytest.mark.parametrize("workers", [1, 2])
 @pytest.mark.parametrize("fname", list(FORMS))
 @pytest.mark.parametrize("name", ["cfg1_small", "window_ragged"])
-def test_form_rewrite_parity(fname, name):
+def test_form_rewrite_parity(fname, name, workers):
     # the rewrite runs on the lower form the handle keeps (for U and L^T: the
-    # reverse row order), bit for bit with the oracle on that form; x in the
-    # caller's numbering
+    # reverse row order), bit for bit with the oracle on that form, with the
+    # scan from one end or from both; x in the caller's numbering
     m = dict(MATS)[name]
     form = FORMS[fname]
     a = _input(m, form)
     low = _lower_form(m, form)
     h = sp.Handle()
     h.analyze(*dev(a), form=form)
-    st = h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0)
+    st = h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0, scan_workers=workers)
     lv = oracle.levels(low)
-    rw = oracle.rewrite(low, oracle.THIN_ROWS, 32.0, 4.0, 0, None, lv)
+    rw = oracle.rewrite(low, oracle.THIN_ROWS, 32.0, 4.0, 0, None, lv, both_ends=workers > 1)
     assert st["rows_rewritten"] == rw.rows_rewritten and st["nlev_after"] == oracle.levels(rw.lp).nlev
     g = {k: v.cpu().numpy() for k, v in h.rewritten().items()}
     for k in ("lp_ptr", "lp_col", "lp_val", "t_ptr", "t_col", "t_val"):
@@ -145,3 +146,14 @@ def test_form_errors():
         assert h.analyze(*dev(e), form=f) == 1
         b = gen.rhs(e, 1)
         assert oracle.relerr(h.solve(to_dev(b[0])).cpu().numpy(), oracle.solve_form(e, b, f)) <= TOL
+
+
+@pytest.mark.parametrize("fname", list(FORMS))
+def test_form_level_features(fname):
+    # the learned policy's features describe the lower form the handle keeps
+    m = dict(MATS)["cfg1_small"]
+    form = FORMS[fname]
+    h = sp.Handle()
+    h.analyze(*dev(_input(m, form)), form=form)
+    f = h.level_features().cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(f, oracle.level_features(_lower_form(m, form)), rtol=2e-6, atol=1e-6)

@@ -169,3 +169,34 @@ def test_critical_path_feature_two_chains():
     F = oracle.level_features(m, lv)
     assert lv.nlev == 6
     np.testing.assert_allclose(F[:, 17], [0.5, 0.5, 0.5, 1.0, 1.0, 1.0])
+
+
+@pytest.mark.parametrize("old,new", [("n_alpha += na < 4;", "n_alpha += na <= 4;"),
+                                     ("n_local += span < 1024;", "n_local += span <= 1024;"),
+                                     ("n_crit += lev[r] + height[r] == nlev - 1;", "n_crit += lev[r] + height[r] >= nlev - 2;")])
+def test_planted_feature_errors_are_caught(tmp_path, old, new):
+    """Each row-constraint feature with a planted boundary error fails its
+    brute-force pin on a matrix where that boundary occurs."""
+    from tests.test_oracle_rewrite import _with_planted_oracle
+    m = gen.powerlaw(3000, seed=5, w_loc=2048, nseg=2, seglen=50)
+
+    def check():
+        with pytest.raises(AssertionError):
+            _brute(m)
+
+    _with_planted_oracle(tmp_path, old, new, check)
+
+
+def _brute(m):
+    """Features 16..19 of m against the direct count (the pin above)."""
+    lv = oracle.levels(m)
+    F = oracle.level_features(m, lv)
+    h = _heights_by_dependents(m)
+    for l in range(lv.nlev):
+        rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
+        cols = _moved_rows(m, lv, l)
+        span = np.array([int(c.max()) - int(c.min()) if len(c) else 0 for c in cols])
+        assert F[l, 16] == pytest.approx(np.mean([len(c) < 4 for c in cols]))
+        assert F[l, 17] == pytest.approx(np.mean(l + h[rows] == lv.nlev - 1))
+        assert F[l, 18] == pytest.approx(np.log1p(span.mean()))
+        assert F[l, 19] == pytest.approx(np.mean(span < 1024))

@@ -616,3 +616,44 @@ def test_both_ends_equals_forward_structured(mk):
     both = oracle.rewrite(m, THIN_ROWS, 16, 4.0, 0, mask, lv, both_ends=True)
     _same_rewrite(fwd, both)
     _scan_replay(m, lv, both, THIN_ROWS, 16, 4.0, 0, mask)
+
+
+def _with_planted_oracle(tmp_path, old, new, check):
+    """Run check() against a copy of the oracle compiled with one planted
+    change (old -> new in oracle.c); the good oracle is restored afterwards."""
+    import os
+    import subprocess
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "oracle.c")).read()
+    bad = src.replace(old, new)
+    assert bad != src
+    p = tmp_path / "bad.c"
+    p.write_text(bad)
+    so = tmp_path / "libbad.so"
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", str(p), "-o", str(so), "-lm"])
+    good_lib, good_path = oracle._lib, oracle._LIB_PATH
+    try:
+        oracle._lib = None
+        oracle._LIB_PATH = str(so)
+        oracle.build = lambda force=False: str(so)  # noqa: E731
+        check()
+    finally:
+        import importlib
+        importlib.reload(oracle)
+        oracle._lib, oracle._LIB_PATH = good_lib, good_path
+
+
+def test_planted_two_ended_order_error_is_caught(tmp_path):
+    """A two-ended order that takes one segment twice and skips another (an
+    off-by-one from the end) must fail the equality with the forward scan."""
+    m = gen.window_random(120, 61, window=5, draws=2)
+    lv = oracle.levels(m)
+    fwd = oracle.rewrite(m, THIN_COST, 0.0, 0.0, 0, None, lv)
+
+    def check():
+        assert _segments(m, lv, THIN_COST, 0.0) >= 3
+        both = oracle.rewrite(m, THIN_COST, 0.0, 0.0, 0, None, lv, both_ends=True)
+        with pytest.raises(AssertionError):
+            _same_rewrite(fwd, both)
+
+    _with_planted_oracle(tmp_path, "(k % 2 == 0 ? k / 2 : nseg - 1 - k / 2)", "(k % 2 == 0 ? k / 2 : nseg - k / 2 - (k == 1))",
+                         check)

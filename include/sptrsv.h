@@ -289,7 +289,9 @@ sptrsv_status_t sptrsv_batch_levels(sptrsv_handle_t h, int32_t i, int32_t *nlev,
                                     int32_t *d_level_rows, hipStream_t s);
 
 /* ---------------------------------------------------------------------------
- * Plan persistence: levels, rewritten matrix and schedules to a versioned file. */
+ * Plan persistence (levels, rewritten matrix and schedules in a file): not
+ * implemented; both calls return SPTRSV_ERR_STATE with a message and change
+ * nothing. A plan is rebuilt with sptrsv_analyze and sptrsv_rewrite. */
 sptrsv_status_t sptrsv_plan_save(sptrsv_handle_t h, const char *path);
 sptrsv_status_t sptrsv_plan_load(sptrsv_handle_t h, const char *path);
 

@@ -87,6 +87,7 @@ def test_features_brute_force():
         for bi, bm in enumerate(bins):
             assert F[l, 6 + bi] == pytest.approx(bm.mean())
         assert F[l, 14] == pytest.approx(l / lv.nlev)
+    _check_size_features(m, lv, F)
     # features 12, 13: a single-level move toward the level before; compare with
     # the oracle's own rewrite restricted to that one level (mask with one source)
     for l in [1, 2, lv.nlev // 2, lv.nlev - 1]:
@@ -99,6 +100,51 @@ def test_features_brute_force():
         tn = np.diff(rw.t_ptr)[rows].sum()
         assert F[l, 12] == pytest.approx(lp / nnz[rows].sum())
         assert F[l, 13] == pytest.approx(np.log1p(tn))
+
+
+def _check_size_features(m, lv, F):
+    """Features 4, 5 and 15 by direct count over the rows of each level: rows
+    over 32, mean nnz per row (diagonal included), and log1p of the number of
+    rows of the level before (0 for level 0)."""
+    nnz = np.diff(m.row_ptr)
+    sizes = np.diff(lv.level_ptr)
+    for l in range(lv.nlev):
+        rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
+        assert F[l, 4] == pytest.approx(len(rows) / 32.0)
+        assert F[l, 5] == pytest.approx(nnz[rows].sum() / len(rows))
+        assert F[l, 15] == pytest.approx(np.log1p(sizes[l - 1]) if l > 0 else 0.0)
+
+
+def _size_feature_case():
+    """A matrix whose consecutive levels differ in size and in mean row
+    length, so that reading the wrong level or the wrong count shows."""
+    return gen.window_random(400, 11, window=9, draws=4)
+
+
+@pytest.mark.parametrize("old,new", [("f[4] = R / 32.0;", "f[4] = R / 31.0;"),
+                                     ("f[5] = R > 0.0 ? (double)nzl[l] / R : 0.0;",
+                                      "f[5] = R > 0.0 ? (double)(nzl[l] - rows[l]) / R : 0.0;"),
+                                     ("f[15] = l > 0 ? log1p((double)rows[l - 1]) : 0.0;",
+                                      "f[15] = l > 0 ? log1p((double)rows[l]) : 0.0;")])
+def test_planted_size_feature_errors_are_caught(tmp_path, old, new):
+    """A planted mistake in feature 4, 5 or 15 (a wrong divisor, the
+    off-diagonal count in place of nnz, the current level's rows in place of
+    the previous level's) fails the direct count."""
+    from tests.test_oracle_rewrite import _with_planted_oracle
+    m = _size_feature_case()
+
+    def check():
+        lv = oracle.levels(m)
+        with pytest.raises(AssertionError):
+            _check_size_features(m, lv, oracle.level_features(m, lv))
+
+    _with_planted_oracle(tmp_path, old, new, check)
+
+
+def test_size_features_direct_count():
+    m = _size_feature_case()
+    lv = oracle.levels(m)
+    _check_size_features(m, lv, oracle.level_features(m, lv))
 
 
 def _heights_by_dependents(m):

@@ -36,7 +36,8 @@ TOL = 1e-10
 WORKLOADS = {
     0: "window-64 random lower CSR, n=2,000, up to 5 off-diagonals/row, nrhs=1",
     1: "2D 1000x1000 5-point lower factor + 20,000-row chain, n=1,020,000, nnz=3,078,000, nrhs=1",
-    2: "power-law (Zipf 1.2 in-degree) lower CSR, n=4,000,000, mean 8 off-diagonals/row, nrhs=1",
+    2: "power-law (Zipf 1.2 in-degree) lower CSR, n=4,000,000, nnz=36,016,553 (8.0 distinct off-diagonals/row), "
+       "3,969 levels, nrhs=1",
     3: "512 window-64 random lower CSR matrices, n_i uniform in [1000, 50000], ~6 nnz/row, nrhs=16 each",
     4: "3D 200^3 7-point lower factor + 5,000-row tail, n=8,005,000, nnz=31,900,000, nrhs=32",
     5: "preconditioner application z = L^-T L^-1 r (incomplete-Cholesky style) with the 3D 200^3 7-point lower "

@@ -150,10 +150,17 @@ def stencil3d_tail(k: int = 200, tail: int = 5000, seed: int = 4) -> Csr:
 def powerlaw(n: int = 4_000_000, seed: int = 2, mean_deg: float = 8.0, w_loc: int = 4096,
              nseg: int = 8, seglen: int = 250, alpha: float = 1.2) -> Csr:
     """Power-law in-degree: column weights pi(j)^-alpha for a random
-    permutation pi. Row i takes min(Poisson(mean_deg), i) off-diagonals: one
-    local column uniform in [i-w_loc, i-1], the rest drawn by inverse CDF over
-    the weights restricted to [0, i), then de-duplicated. ``nseg`` segments of
-    ``seglen`` rows use a local window of 1, which makes them near-serial."""
+    permutation pi. Row i takes d_i = min(Poisson(mean_deg), i) distinct
+    off-diagonals: one local column uniform in [i-w_loc, i-1], the rest drawn
+    by inverse CDF over the weights restricted to [0, i). A draw that repeats
+    a column the row already holds is drawn again from the same weights, so
+    every row ends with d_i distinct columns and the realised mean is
+    mean_deg (the hub columns make repeats frequent: without the redraws
+    about a quarter of the draws would be lost). Redraws run in rounds over
+    all rows still short; the few rows left after that (their weights are
+    dominated by hub columns they already hold) draw from the weights of the
+    columns they lack, one column at a time. ``nseg`` segments of ``seglen``
+    rows use a local window of 1, which makes them near-serial."""
     rng = np.random.default_rng(seed)
     perm = rng.permutation(n).astype(np.float64) + 1.0
     w = perm ** (-alpha)
@@ -169,12 +176,74 @@ def powerlaw(n: int = 4_000_000, seed: int = 2, mean_deg: float = 8.0, w_loc: in
     extra = (deg[has] - 1).astype(np.int64)
     er = np.repeat(has, extra)
     u = rng.random(er.size) * cumw[er - 1]
-    ec = np.searchsorted(cumw, u, side="right").astype(np.int64)
-    ec = np.minimum(ec, er - 1)
-    rows = np.concatenate([has, er])
-    cols = np.concatenate([loc, ec])
-    rows, cols = _unique_pairs(n, rows, cols)
-    return _assemble(n, rows, cols, rng, f"powerlaw_n{n}_s{seed}_w{w_loc}_g{nseg}")
+    ec = np.minimum(_inv_cdf(cumw, u), er - 1)
+    keys = np.unique(np.concatenate([has * n + loc, er * n + ec]))
+    got = np.bincount(keys // n, minlength=n)
+    added = np.zeros(0, np.int64)  # accepted redraws, sorted
+    for _ in range(40):
+        short = np.nonzero(got < deg)[0].astype(np.int64)
+        if short.size <= 20_000:
+            break
+        rr = np.repeat(short, (deg[short] - got[short]).astype(np.int64))
+        u = rng.random(rr.size) * cumw[rr - 1]
+        cc = np.minimum(_inv_cdf(cumw, u), rr - 1)
+        # distinct within the round; a row drew exactly its shortfall, so
+        # every fresh key fits
+        cand = np.unique(rr * n + cc)
+        new = cand[~_contains(keys, cand) & ~_contains(added, cand)]
+        added = np.sort(np.concatenate([added, new]))
+        got += np.bincount(new // n, minlength=n)
+    keys = np.sort(np.concatenate([keys, added]))
+    short = np.nonzero(got < deg)[0].astype(np.int64)
+    if short.size:
+        keys = np.sort(np.concatenate([keys, _draw_excluding(rng, cumw, keys, short, deg[short] - got[short], n)]))
+    return _assemble(n, keys // n, keys % n, rng, f"powerlaw_n{n}_s{seed}_w{w_loc}_g{nseg}")
+
+
+def _inv_cdf(cumw, u):
+    """Index of the first cumulative weight above each u (inverse CDF); the
+    queries are searched in sorted order, which keeps the search cache-local,
+    and the results are put back in the order of u."""
+    order = np.argsort(u)
+    out = np.empty(u.size, np.int64)
+    out[order] = np.searchsorted(cumw, u[order], side="right")
+    return out
+
+
+def _contains(sorted_keys, q):
+    """Membership of q in a sorted int64 array."""
+    if sorted_keys.size == 0:
+        return np.zeros(q.size, bool)
+    i = np.searchsorted(sorted_keys, q)
+    return sorted_keys[np.minimum(i, sorted_keys.size - 1)] == q
+
+
+def _draw_excluding(rng, cumw, keys, rows, need, n):
+    """For each row r of ``rows``, ``need`` more columns drawn one at a time
+    from the weights (cumulative ``cumw``) restricted to the columns of
+    [0, r) the row does not hold: the uniform draw u is taken on the reduced
+    total and moved past the weight of every held column at or below the
+    column it lands on, until the landing column no longer changes."""
+    out = []
+    for r, k in zip(rows.tolist(), need.tolist()):
+        a, b = np.searchsorted(keys, [r * n, (r + 1) * n])
+        held = sorted((keys[a:b] % n).tolist())
+        for _ in range(k):
+            hw = [cumw[h] - (cumw[h - 1] if h else 0.0) for h in held]
+            while True:
+                u = rng.random() * (cumw[r - 1] - sum(hw))
+                c = -1
+                for _ in range(len(held) + 2):
+                    shift = sum(x for h, x in zip(held, hw) if h <= c) if c >= 0 else 0.0
+                    c2 = min(int(np.searchsorted(cumw, u + shift, side="right")), r - 1)
+                    if c2 == c:
+                        break
+                    c = c2
+                if c not in held:
+                    break
+            held = sorted(held + [c])
+            out.append(r * n + c)
+    return np.array(out, np.int64)
 
 
 def _leveled(widths, extra, pick, rng, name) -> Csr:

@@ -1,18 +1,22 @@
 """Benchmark: SpTRSV solves/s and HBM GB/s, rewritten vs plain level-set.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4]
 
-Workload (default): the lower factor of the 1000x1000 2D 5-point stencil
-(pattern only, diagonally dominant random values) followed by a 20,000-row
-near-serial chain; n = 1,020,000, nnz = 3,078,000, one right-hand side, FP64.
-Variants on the same matrix and right-hand side, each autotuned first:
+Workload (default, the largest single-GPU configuration): the lower factor of
+the 200^3 3D 7-point stencil (pattern only, diagonally dominant random values)
+followed by a 5,000-row near-serial tail; n = 8,005,000, nnz = 31,900,000,
+32 right-hand sides, FP64, each solve a replay of a hipGraph.
+Variants on the same matrix and right-hand sides, each autotuned first:
   plain    level-set solve of L
   naive    L' after the naive rewrite (levels with < 32 rows, fill cap 4x)
   learned  L' after the rewrite with levels chosen by the trained policy
 A step is one solve of the headline variant (learned if a trained policy is
 available, else naive). Every variant is checked against the CPU oracle
 (relative error <= 1e-10) before it is timed; rewriting and tuning are
-preprocessing and are reported separately.
+preprocessing and are reported separately. value / ms_per_step come from the
+median of the per-step device times; graph workloads also report five
+repetitions of 100 replays. --config 1 is the 2D stencil + 20,000-row chain
+(one right-hand side, stream launches), --config 2 the 4M-row power law.
 
 Prints ONE JSON line. Inputs are resident in HBM when the timed region starts.
 """
@@ -325,7 +329,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=1, choices=sorted(WORKLOADS))
+    ap.add_argument("--config", type=int, default=4, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--variants", default="plain,naive,learned",
@@ -379,6 +383,9 @@ def main():
         b = b.view(-1)
 
     variants = {}
+    probe = sp.Handle()
+    costs = probe.measure_level_costs()
+    log(f"[bench] empty-level costs (ns): { {k: round(v, 1) for k, v in costs.items()} }")
 
     def setup(name, mask_fn=None, rewrite=True):
         h = sp.Handle()
@@ -400,6 +407,7 @@ def main():
             info["tuned_ms"] = None
         else:
             info["tuned_ms"] = h.autotune(which, nrhs)
+            info["tune"] = h.tune_info()
         info["schedule"] = h.get_schedule(which, nrhs)
         info["autotune_s"] = time.perf_counter() - t
         x = h.solve(b, which)
@@ -408,9 +416,10 @@ def main():
         if not info["relerr"] <= TOL:
             raise SystemExit(f"[bench] variant {name} failed parity: relerr={info['relerr']:.3e}")
         info["bytes"] = alg_bytes(m.n, info["nnz"], info["nlev"], nrhs, info["nnz_t"], rewrite)
+        info["level_floor_us"] = h.level_floor(costs, which, nrhs, graph=use_graph)
         variants[name] = (h, which, info)
         log(f"[bench] {name}: nlev={info['nlev']} relerr={info['relerr']:.2e} pre={info['preprocess_s']:.2f}s "
-            f"schedule={info['schedule']}")
+            f"schedule={info['schedule']} level floor {info['level_floor_us']:.1f} us")
 
     want = set(v.strip() for v in args.variants.split(",") if v.strip())
     fixed_sched = json.loads(args.schedules) if args.schedules else {}
@@ -430,12 +439,11 @@ def main():
         except (ImportError, sp.SptrsvError, FileNotFoundError) as e:
             log(f"[bench] learned policy unavailable: {e}")
 
-    def timed(name, steps, warmup, profile=False):
-        """Wall time of `steps` solves (graph replays if use_graph), and with
-        profile=True the per-kernel-class HIP-event profile: of these solves
-        when a solve is a few launches, else (the events would add host work
-        to every launch) and for graph replays (no events inside a graph) of
-        as many eager solves right after."""
+    def timed(name, steps, warmup):
+        """Per-step device times (HIP events on the solve stream around every
+        step: a graph replay, or an eager solve) and the wall time of all
+        steps; plus, for graph replays, the protocol of five repetitions of
+        100 replays (mean per solve of each, median of the five)."""
         h, which, _ = variants[name]
         x = torch.empty_like(b)
         if use_graph:
@@ -445,44 +453,64 @@ def main():
             run = lambda: h.solve(b, which, x)  # noqa: E731
         for _ in range(warmup):
             run()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
-        in_region = False
-        if profile and not use_graph:
-            h.profile_start()
-            h.solve(b, which, x)
-            torch.cuda.synchronize()
-            in_region = sum(v["launches"] for v in h.profile_stop().values()) <= 4
-        if in_region:
-            h.profile_start()
         t = time.perf_counter()
-        for _ in range(steps):
+        for e0, e1 in ev:
+            e0.record(stream)
             run()
+            e1.record(stream)
         torch.cuda.synchronize()
-        el = time.perf_counter() - t
-        prof = None
-        if profile:
-            if not in_region:
-                h.profile_start()
-                for _ in range(steps):
-                    h.solve(b, which, x)
+        wall = time.perf_counter() - t
+        per = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+        reps = None
+        if use_graph:
+            reps = []
+            for _ in range(5):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(100):
+                    run()
+                e1.record(stream)
                 torch.cuda.synchronize()
-            prof = h.profile_stop()
-            prof["in_timed_region"] = in_region
+                reps.append(e0.elapsed_time(e1) / 100)
         h.check()
-        return el, prof
+        return per, wall, reps
+
+    def kernel_profile(name, steps):
+        """Per-kernel-class HIP-event profile of eager solves on the solve
+        stream (after the timed region: no events inside a graph)."""
+        h, which, _ = variants[name]
+        x = torch.empty_like(b)
+        h.solve(b, which, x)
+        h.profile_start()
+        for _ in range(steps):
+            h.solve(b, which, x)
+        torch.cuda.synchronize()
+        prof = h.profile_stop()
+        h.check()
+        return prof
+
+    def median(v):
+        v = sorted(v)
+        k = len(v)
+        return v[k // 2] if k % 2 else 0.5 * (v[k // 2 - 1] + v[k // 2])
 
     headline = "learned" if "learned" in variants else ("naive" if "naive" in variants else "plain")
     for name in variants:
-        if name == headline:
-            continue
-        el, _ = timed(name, max(5, args.steps // 2), args.warmup)
-        variants[name][2]["ms"] = el * 1e3 / max(5, args.steps // 2)
-    el, prof = timed(headline, args.steps, args.warmup, profile=True)
-    variants[headline][2]["ms"] = el * 1e3 / args.steps
-    ms = el * 1e3 / args.steps
+        steps = args.steps if name == headline else max(20, args.steps // 2)
+        per, wall, reps = timed(name, steps, args.warmup)
+        info = variants[name][2]
+        info["ms"] = median(per)
+        info["ms_wall_mean"] = wall * 1e3 / steps
+        info["steps"] = steps
+        if reps is not None:
+            info["graph_reps_ms"] = reps
+            info["graph_reps_median_ms"] = median(reps)
+    ms = variants[headline][2]["ms"]
+    prof = kernel_profile(headline, max(5, min(args.steps, 20)))
 
     # roofline of the dominant kernel class, from the live profile
-    in_region = prof.pop("in_timed_region")
     dom = max(prof, key=lambda k: prof[k]["ms"])
     dp = prof[dom]
     per_launch_ms = dp["ms"] / max(1, dp["launches"])
@@ -493,34 +521,37 @@ def main():
     if dom == "wide_level" and variants[headline][2]["schedule"]["mode"] == 3:
         kname = "k_sf_solve"  # the synchronisation-free launch is profiled with the device-wide class
     traffic = load_traffic(kname, f"config{args.config}_{headline}")
+    total_prof_ms = sum(v["ms"] for v in prof.values())
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic, "kernel": kname,
-                "launches": dp["launches"], "avg_launch_ms": round(per_launch_ms, 5),
-                "alg_bytes_per_launch": bytes_per_launch,
-                "events": "timed region" if in_region else "eager solves after the timed region",
-                "kernel_share_of_step": round(sum(v["ms"] for v in prof.values()) and dp["ms"] /
-                                              sum(v["ms"] for v in prof.values()), 4)}
+                "launches_per_solve": round(dp["launches"] / max(5, min(args.steps, 20)), 3),
+                "avg_launch_ms": round(per_launch_ms, 6), "alg_bytes_per_launch": bytes_per_launch,
+                "events": "HIP events on the solve stream around every launch of eager solves after the timed region",
+                "kernel_share_of_step": round(dp["ms"] / total_prof_ms, 4) if total_prof_ms > 0 else None}
+    hinfo = variants[headline][2]
+    path = {"alg_bytes_per_solve": hinfo["bytes"], "achieved": round(hinfo["bytes"] / (ms * 1e-3) / 1e9, 3),
+            "unit": "GB/s", "frac": round(hinfo["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 6),
+            "level_floor_us": round(hinfo["level_floor_us"], 2),
+            "ms_over_level_floor": round(ms * 1e3 / hinfo["level_floor_us"], 3) if hinfo["level_floor_us"] > 0 else None}
 
     cpu = None
     if not args.no_cpu:
-        reps = max(1, min(2000, int(12.0 / max(t_oracle_one, 1e-6))))
-        t = time.perf_counter()
-        for _ in range(reps):
-            oracle.solve(m, b_np)
-        el_c = time.perf_counter() - t
-        cpu = {"value": round(reps / el_c, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"{reps} full solves of the same matrix and right-hand side(s) by the serial FP64 oracle "
-                         f"({el_c:.1f}s); host nproc={os.cpu_count()}"}
+        cpu = cpu_baseline(oracle, m, b_np, t_oracle_one)
 
     out_var = {}
     for name, (_, _, info) in variants.items():
         gbs = info["bytes"] / (info["ms"] * 1e-3) / 1e9
         out_var[name] = {"solves_per_s": round(1e3 / info["ms"], 3), "ms": round(info["ms"], 5),
+                         "ms_wall_mean": round(info["ms_wall_mean"], 5), "steps": info["steps"],
                          "alg_GBps": round(gbs, 3), "hbm_frac": round(gbs / HBM_PEAK_GBS, 6), "nlev": info["nlev"],
                          "nnz": info["nnz"], "nnz_T": info["nnz_t"], "relerr": info["relerr"],
+                         "level_floor_us": round(info["level_floor_us"], 2),
                          "preprocess_s": round(info["preprocess_s"], 3), "autotune_s": round(info["autotune_s"], 3),
-                         "schedule": info["schedule"],
+                         "schedule": info["schedule"], "tune": info.get("tune"),
                          "us_per_level": round(info["ms"] * 1e3 / max(1, info["nlev"]), 4)}
+        if "graph_reps_ms" in info:
+            out_var[name]["graph_reps_ms"] = [round(v, 5) for v in info["graph_reps_ms"]]
+            out_var[name]["graph_reps_median_ms"] = round(info["graph_reps_median_ms"], 5)
         for k in ("rows_rewritten", "max_distance"):
             if k in info:
                 out_var[name][k] = info[k]
@@ -529,7 +560,7 @@ def main():
         "value": round(1e3 / ms, 3),
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": variants[headline][2]["steps"],
         "warmup": args.warmup,
         "ms_per_step": round(ms, 5),
         "higher_is_better": True,
@@ -538,14 +569,55 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded generator of the workload's structure; no dataset)",
         "config": {"workload": WORKLOADS[args.config], "variant": headline, "nrhs": nrhs, "n": m.n, "nnz": m.nnz,
-                   "parallelism": "single GPU", "timing": "hipGraph replays" if use_graph else "stream launches"},
+                   "parallelism": "single GPU", "timing": ("hipGraph replays" if use_graph else "stream launches")
+                   + "; value and ms_per_step from the median of the per-step HIP-event times"},
         "roofline": roofline,
+        "path": path,
         "cpu_baseline": cpu,
         "variants": out_var,
         "speedup_vs_plain": round(out_var["plain"]["ms"] / ms, 4) if "plain" in out_var else None,
+        "level_costs_ns": {k: round(v, 2) for k, v in costs.items()},
         "kernel_profile": prof,
     }
     print(json.dumps(res), flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(oracle, m, b_np, t_one):
+    """The serial FP64 oracle on one host core (the calling thread pinned to
+    the first core it may run on; restored afterwards): one warm-up solve,
+    then the median of five (more, up to about 12 s, when a solve is short)."""
+    import statistics
+    keep = os.sched_getaffinity(0)
+    core = min(keep)
+    os.sched_setaffinity(0, {core})
+    try:
+        oracle.solve(m, b_np)
+        reps = max(5, min(201, int(12.0 / max(t_one, 1e-6))))
+        if reps % 2 == 0:
+            reps += 1
+        times = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            oracle.solve(m, b_np)
+            times.append(time.perf_counter() - t)
+    finally:
+        os.sched_setaffinity(0, keep)
+    med = statistics.median(times)
+    return {"value": round(1.0 / med, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"the whole solve of the same matrix and right-hand side(s) by the serial FP64 oracle, pinned "
+                      f"to host core {core}: 1 warm-up, median of {reps} ({med * 1e3:.2f} ms each); host "
+                      f"nproc={os.cpu_count()}, CPU {cpu_model()}"}
 
 
 if __name__ == "__main__":

@@ -239,8 +239,23 @@ sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, 
 /* Autotuner: times candidate schedules with HIP events on s (inputs b = 1) and
  * keeps the fastest for (which, nrhs); for SPTRSV_BATCH the candidates are the
  * workgroup sizes of the persistent launch. best_ms (host, may be NULL) receives the
- * best solve time. Synchronous. */
+ * best solve time. Synchronous.
+ * Candidates whose launches wait on the device (the synchronisation-free
+ * executor, persistent wide runs) run with a wait limit of 8x the best time so
+ * far (at least 2 ms) instead of the solve's 10 s: a candidate that reaches it
+ * is dropped, and counted in sptrsv_get_tune_info. */
 sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms);
+
+/* What the handle's last sptrsv_autotune call did: candidates timed,
+ * candidates dropped because a device-side wait reached its limit, the best
+ * time, and the largest wait limit given to a candidate (ms). */
+typedef struct {
+  int32_t candidates;
+  int32_t timed_out;
+  float best_ms;
+  float max_wait_limit_ms;
+} sptrsv_tune_info_t;
+sptrsv_status_t sptrsv_get_tune_info(sptrsv_handle_t h, sptrsv_tune_info_t *out);
 
 /* hipGraph capture of one solve with fixed buffers; replays are ASYNC. The graph
  * belongs to the handle (at most 16); graph_id receives its index. */
@@ -260,6 +275,39 @@ typedef struct {
   double bytes;
 } sptrsv_kernel_profile_t;
 sptrsv_status_t sptrsv_profile(sptrsv_handle_t h, int enable, sptrsv_kernel_profile_t *out, hipStream_t s);
+
+/* Level floor: what one level costs when it holds no work, for each way a
+ * solve separates consecutive levels (Sec. II.A: levels run in order, so a
+ * solve costs at least the sum of these over its levels). Measured on the
+ * device with the solve kernels' own synchronisation (ns per level):
+ *   thin_level_ns       a level of a thin-run window spread over several waves:
+ *                       an LDS-only workgroup barrier and one dependent LDS read
+ *   thin_wave_level_ns  the same in a window run by one wave (no barrier)
+ *   launch_ns           a kernel launch per level on a stream
+ *   graph_node_ns       a kernel node per level of a replayed hipGraph
+ *   grid_barrier_ns     a device-wide barrier of a persistent launch
+ *   flag_hop_ns         a value handed from one workgroup to the next through
+ *                       a device-coherent store and load (the least a
+ *                       dependency costs the synchronisation-free executor)
+ * Synchronous; allocates a few bytes of device memory. */
+typedef struct {
+  double thin_level_ns;
+  double thin_wave_level_ns;
+  double launch_ns;
+  double graph_node_ns;
+  double grid_barrier_ns;
+  double flag_hop_ns;
+} sptrsv_level_costs_t;
+sptrsv_status_t sptrsv_measure_level_costs(sptrsv_handle_t h, hipStream_t s, sptrsv_level_costs_t *out);
+/* The level floor of one solve of (which, nrhs) under the schedule it uses
+ * (built if needed): the costs above summed over the plan's levels as its
+ * runs separate them (thin-run levels by window kind, one launch or graph node
+ * per wide level and per launch of a run, device-wide barriers inside
+ * persistent runs, one hop per level for the synchronisation-free executor),
+ * plus the launches of the gather, b-transform and scatter. graph != 0 prices
+ * launches as graph nodes. floor_us receives microseconds. Synchronous. */
+sptrsv_status_t sptrsv_level_floor(sptrsv_handle_t h, int which, int32_t nrhs, int32_t graph,
+                                   const sptrsv_level_costs_t *c, double *floor_us);
 
 /* Residual check: h_out[c] = max_i |(L x - b)[i,c]| for the ORIGINAL L, host
  * double[nrhs]. Synchronous. */

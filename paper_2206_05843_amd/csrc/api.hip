@@ -376,15 +376,18 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   return SPTRSV_OK;
 }
 
-// Algorithmic bytes of solving levels [l0, l1): each off-diagonal (and T entry)
-// once as value + column, each row's pointer and diagonal once, b read and x
-// written once per right-hand side, and the level pointers.
+// Algorithmic bytes of solving levels [l0, l1), the levels' share of the
+// compulsory traffic of a solve: every nonzero once as value + column (12 B,
+// the diagonal included), per row its pointer and level map entry (8 B; 12 B
+// with the row pointer of T for a rewritten matrix), b read and x written
+// once per right-hand side, and the level pointers. T's entries are the
+// gather's share (T b is applied there).
 static double run_bytes(const Plan &P, int32_t l0, int32_t l1, int32_t nrhs) {
   double b = 4.0 * (l1 - l0 + 1);
+  const double per_row = P.has_t ? 12.0 : 8.0;
   for (int32_t l = l0; l < l1; ++l) {
     const double rows = P.h_level_ptr[l + 1] - P.h_level_ptr[l];
-    const double off = (double)P.h_lv_nnz[l] - rows;
-    b += 12.0 * off + 12.0 * rows + 16.0 * rows * nrhs;  // T b is applied in the gather
+    b += 12.0 * (double)P.h_lv_nnz[l] + per_row * rows + 16.0 * rows * nrhs;
   }
   return b;
 }
@@ -403,8 +406,9 @@ static void prof_end(sptrsv_ctx *h, int slot, hipStream_t s) {
   if (slot >= 0) (void)hipEventRecord(h->prof_ev[(size_t)slot * 2 + 1], s);
 }
 
-ThinArgs thin_args(const Plan &P) {
-  return ThinArgs{P.level_ptr.p, P.sdg.p, P.img.p, P.ext_ptr.p, P.ext.p, P.bp.p, P.xp.p, P.tp.p};
+ThinArgs thin_args(const Plan &P) { return thin_args(P, P.bp.p, P.xp.p); }
+ThinArgs thin_args(const Plan &P, double *bp, double *xp) {
+  return ThinArgs{P.level_ptr.p, P.sdg.p, P.img.p, P.ext_ptr.p, P.ext.p, bp, xp, P.tp.p};
 }
 
 // The level-distance histogram of the dependencies that need overflow records
@@ -425,49 +429,63 @@ sptrsv_status_t build_extra_hist(sptrsv_ctx *h, Plan &P, hipStream_t s) {
 // b (caller's layout) -> bp (level order, interleaved); for the rewritten
 // system b' = T b, where only the rows of T with off-diagonals differ from b:
 // those are recomputed from the caller's b after the plain gather.
-sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, hipStream_t s) {
-  HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, io_iperm(P), P.bp.p, s));
+sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *bp,
+                         hipStream_t s) {
+  HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, io_iperm(P), bp, s));
   if (P.has_t && P.n_tpos > 0)
     HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, io_perm(P), P.trp.p, P.tci.p, P.tva.p, b, ldb,
-                             P.bp.p, s));
+                             bp, s));
   return SPTRSV_OK;
+}
+
+// One solve over the plan's runs, built for (nrhs, its schedule), with the
+// work vectors bp and xp (n * nrhs doubles each). Allocates nothing.
+sptrsv_status_t solve_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
+                           int64_t ldx, double *bp, double *xp, hipStream_t s) {
+  if (P.n == 0) return SPTRSV_OK;
+  const sptrsv_schedule_t sc = P.runs_sched;
+  int *err = h->d_err.p;
+  const double vec_bytes = 16.0 * (double)P.n * nrhs + 4.0 * P.n;
+  int slot = prof_begin(h, 0, vec_bytes + (P.has_t ? 12.0 * (double)P.nnz_t_off + 4.0 * P.n : 0.0), s);
+  STCHK(gather_b(h, P, nrhs, b, ldb, bp, s));
+  prof_end(h, slot, s);
+  if (sc.mode == 3) {  // synchronisation-free: one launch for the whole solve (profiled with the wide class)
+    slot = h->prof ? prof_begin(h, 2, run_bytes(P, 0, P.nlev, nrhs), s) : -1;
+    HIPCHK(h, launch_syncfree(P.n, nrhs, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, bp, xp, P.sf_ticket.p, err,
+                              sc.wide_grid, wait_limit(h), s));
+    prof_end(h, slot, s);
+  }
+  const ThinArgs ta = thin_args(P, bp, xp);
+  for (const Run &r : P.runs) {
+    if (sc.mode == 3) break;
+    slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
+    if (r.thin) {
+      HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, ta, err, s));
+    } else if (sc.wide_grid > 0) {
+      HIPCHK(h, launch_wide_run(sc.wide_grid, sc.wide_threads, r.l0, r.l1, P.level_ptr.p, nrhs, P.srp.p, P.sci.p,
+                                P.sva.p, P.sdg.p, bp, xp, P.wbar.p, err, wait_limit(h), s));
+    } else {
+      HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
+                                  P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, bp, xp, err, s));
+    }
+    prof_end(h, slot, s);
+  }
+  slot = prof_begin(h, 3, vec_bytes, s);
+  HIPCHK(h, launch_scatter(P.n, nrhs, xp, io_iperm(P), x, ldx, s));
+  prof_end(h, slot, s);
+  return SPTRSV_OK;
+}
+
+bool runs_ready(const Plan &P, int32_t nrhs) {
+  return P.runs_nrhs == nrhs && same_sched(effective_sched(P, nrhs), P.runs_sched);
 }
 
 sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
                            int64_t ldx, hipStream_t s) {
   if (P.n == 0) return SPTRSV_OK;
   STCHK(ensure_work(h, P, nrhs));
-  const sptrsv_schedule_t sc = effective_sched(P, nrhs);
-  if (P.runs_nrhs != nrhs || !same_sched(sc, P.runs_sched)) STCHK(make_runs(h, P, nrhs, sc, s));
-  int *err = h->d_err.p;
-  const double vec_bytes = 16.0 * (double)P.n * nrhs + 4.0 * P.n;
-  int slot = prof_begin(h, 0, vec_bytes + (P.has_t ? 12.0 * (double)P.nnz_t_off + 4.0 * P.n : 0.0), s);
-  STCHK(gather_b(h, P, nrhs, b, ldb, s));
-  prof_end(h, slot, s);
-  if (sc.mode == 3) {  // synchronisation-free: one launch for the whole solve (profiled with the wide class)
-    slot = h->prof ? prof_begin(h, 2, run_bytes(P, 0, P.nlev, nrhs), s) : -1;
-    HIPCHK(h, launch_syncfree(P.n, nrhs, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.bp.p, P.xp.p, P.sf_ticket.p, err,
-                              sc.wide_grid, s));
-    prof_end(h, slot, s);
-  }
-  for (const Run &r : P.runs) {
-    if (sc.mode == 3) break;
-    slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
-    if (r.thin) {
-      HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, thin_args(P), err, s));
-    } else if (sc.wide_grid > 0) {
-      HIPCHK(h, launch_wide_run(sc.wide_grid, sc.wide_threads, r.l0, r.l1, P.level_ptr.p, nrhs, P.srp.p, P.sci.p,
-                                P.sva.p, P.sdg.p, P.bp.p, P.xp.p, P.wbar.p, err, s));
-    } else {
-      HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
-                                  P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, P.bp.p, P.xp.p, err, s));
-    }
-    prof_end(h, slot, s);
-  }
-  slot = prof_begin(h, 3, vec_bytes, s);
-  HIPCHK(h, launch_scatter(P.n, nrhs, P.xp.p, io_iperm(P), x, ldx, s));
-  prof_end(h, slot, s);
-  return SPTRSV_OK;
+  if (!runs_ready(P, nrhs)) STCHK(make_runs(h, P, nrhs, effective_sched(P, nrhs), s));
+  return solve_runs(h, P, nrhs, b, ldb, x, ldx, P.bp.p, P.xp.p, s);
 }
 
 // ------------------------------------------------------------------- ABI
@@ -728,23 +746,47 @@ sptrsv_status_t sptrsv_prepare(sptrsv_handle_t h, int which, int32_t nrhs, hipSt
   return SPTRSV_OK;
 }
 
-sptrsv_status_t sptrsv_solve(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
-                             double *d_x, int64_t ldx, hipStream_t s) {
-  if (!h) return SPTRSV_ERR_ARG;
+}  // extern "C"
+
+// Arguments of a solve entry point: the plan they address, or an error.
+Plan *solve_plan(sptrsv_ctx *h, int which, int32_t nrhs, const double *d_b, int64_t ldb, const double *d_x,
+                 int64_t ldx, sptrsv_status_t *st) {
+  *st = SPTRSV_OK;
   Plan *P = plan_of(h, which);
-  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
-  if (!P->ready)
-    return set_err(h, SPTRSV_ERR_STATE, which == SPTRSV_REWRITTEN ? "no rewrite yet" : "matrix not analysed");
+  if (!P) {
+    *st = set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+    return nullptr;
+  }
+  if (!P->ready) {
+    *st = set_err(h, SPTRSV_ERR_STATE, which == SPTRSV_REWRITTEN ? "no rewrite yet" : "matrix not analysed");
+    return nullptr;
+  }
   const int64_t n = P->n;
-  if (nrhs < 1 || ldb < n || ldx < n || (n > 0 && (!d_b || !d_x)))
-    return set_err(h, SPTRSV_ERR_ARG, "solve: nrhs=%d ldb=%lld ldx=%lld", nrhs, (long long)ldb, (long long)ldx);
+  if (nrhs < 1 || ldb < n || ldx < n || (n > 0 && (!d_b || !d_x))) {
+    *st = set_err(h, SPTRSV_ERR_ARG, "solve: nrhs=%d ldb=%lld ldx=%lld", nrhs, (long long)ldb, (long long)ldx);
+    return nullptr;
+  }
   if (n > 0) {
     const char *b0 = reinterpret_cast<const char *>(d_b);
     const char *b1 = b0 + sizeof(double) * (size_t)(ldb * (nrhs - 1) + n);
     const char *x0 = reinterpret_cast<const char *>(d_x);
     const char *x1 = x0 + sizeof(double) * (size_t)(ldx * (nrhs - 1) + n);
-    if (b0 < x1 && x0 < b1) return set_err(h, SPTRSV_ERR_ARG, "b and x overlap");
+    if (b0 < x1 && x0 < b1) {
+      *st = set_err(h, SPTRSV_ERR_ARG, "b and x overlap");
+      return nullptr;
+    }
   }
+  return P;
+}
+
+extern "C" {
+
+sptrsv_status_t sptrsv_solve(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
+                             double *d_x, int64_t ldx, hipStream_t s) {
+  if (!h) return SPTRSV_ERR_ARG;
+  sptrsv_status_t st;
+  Plan *P = solve_plan(h, which, nrhs, d_b, ldb, d_x, ldx, &st);
+  if (!P) return st;
   return plan_solve(h, *P, nrhs, d_b, ldb, d_x, ldx, s);
 }
 
@@ -808,6 +850,41 @@ sptrsv_status_t sptrsv_profile(sptrsv_handle_t h, int enable, sptrsv_kernel_prof
   }
   if (out)
     for (int c = 0; c < 4; ++c) out[c] = acc[c];
+  return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_level_floor(sptrsv_handle_t h, int which, int32_t nrhs, int32_t graph,
+                                   const sptrsv_level_costs_t *c, double *floor_us) {
+  if (!h || !c || !floor_us) return SPTRSV_ERR_ARG;
+  Plan *P = plan_of(h, which);
+  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  if (!P->ready) return set_err(h, SPTRSV_ERR_STATE, "matrix not analysed/rewritten");
+  if (nrhs < 1) return set_err(h, SPTRSV_ERR_ARG, "nrhs=%d", nrhs);
+  *floor_us = 0.0;
+  if (P->n == 0) return SPTRSV_OK;
+  if (!runs_ready(*P, nrhs)) STCHK(make_runs(h, *P, nrhs, effective_sched(*P, nrhs), nullptr));
+  const sptrsv_schedule_t sc = P->runs_sched;
+  const double launch = graph ? c->graph_node_ns : c->launch_ns;
+  double ns = launch * (2 + (P->has_t && P->n_tpos > 0 ? 1 : 0));  // gather, b-transform, scatter
+  if (sc.mode == 3) {
+    ns += 2 * launch + (double)P->nlev * c->flag_hop_ns;  // fill of x, the solve; a hop per level
+  } else {
+    for (const Run &r : P->runs) {
+      if (r.thin) {
+        ns += launch;
+        for (int32_t w = 0; w < r.nw; ++w) {
+          const int4 W = P->h_win[(size_t)(r.wi + w)];
+          const int32_t nl = P->h_win[(size_t)(r.wi + w + 1)].x - W.x;
+          ns += (double)nl * ((W.y & 1) ? c->thin_wave_level_ns : c->thin_level_ns);
+        }
+      } else if (sc.wide_grid > 0) {
+        ns += launch + (double)(r.l1 - r.l0 - 1) * c->grid_barrier_ns;
+      } else {
+        ns += (double)(r.l1 - r.l0) * launch;
+      }
+    }
+  }
+  *floor_us = ns * 1e-3;
   return SPTRSV_OK;
 }
 

@@ -103,7 +103,7 @@ sptrsv_status_t sptrsv_level_times(sptrsv_handle_t h, int which, int32_t nrhs, c
   sptrsv_schedule_t sc{2, 0, 512, 256, 1};  // every level that fits runs in one workgroup
   STCHK(make_runs(h, *P, nrhs, sc, s));
   HIPCHK(h, hipMemsetAsync(d_times, 0, sizeof(float) * (size_t)P->nlev, s));
-  STCHK(gather_b(h, *P, nrhs, d_b, P->n, s));
+  STCHK(gather_b(h, *P, nrhs, d_b, P->n, P->bp.p, s));
   for (const Run &r : P->runs) {
     if (r.thin) {
       HIPCHK(h, launch_thin_run(512, P->win.p + r.wi, r.nw, nrhs, thin_args(*P), h->d_err.p, s, d_times, ns_per_tick));

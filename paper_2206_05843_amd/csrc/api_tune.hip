@@ -82,8 +82,8 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
   auto run = [&]() {
     return batch ? sptrsv_batch_solve(h, nrhs, b.p, x.p, s) : plan_solve(h, *P, nrhs, b.p, n, x.p, n, s);
   };
-  // a synchronisation-free candidate that reaches its time limit on this
-  // matrix is dropped (its timeout bit cleared), not reported as a failure
+  // a candidate whose device-side wait reaches its limit on this matrix is
+  // dropped (its timeout bit cleared) and counted in the tuning report
   auto drop_timeout = [&]() -> bool {
     int32_t bits = 0;
     if (hipMemcpyAsync(&bits, h->d_err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -94,14 +94,27 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
     (void)hipStreamSynchronize(s);
     return true;
   };
+  sptrsv_tune_info_t info{};
   for (const sptrsv_schedule_t &cand : cands) {
     P->sched = cand;
     P->runs_nrhs = -1;
     P->tuned.erase(nrhs);
+    // launches that wait on the device get a limit tied to the best time so far
+    const bool waits = !batch && (cand.mode == 3 || cand.wide_grid > 0);
+    h->wait_ticks = 0;
+    if (waits && best < 1e29f) {
+      const double lim_ms = std::max(2.0, 8.0 * (double)best);
+      h->wait_ticks = (unsigned long long)(lim_ms * 1e5);  // 100 MHz wall clock
+      info.max_wait_limit_ms = std::max(info.max_wait_limit_ms, (float)lim_ms);
+    }
+    ++info.candidates;
     float t[3];
     st = run();  // warm-up
     if (st != SPTRSV_OK) break;
-    if (cand.mode == 3 && drop_timeout()) continue;
+    if (waits && drop_timeout()) {
+      ++info.timed_out;
+      continue;
+    }
     for (int rep = 0; rep < 3 && st == SPTRSV_OK; ++rep) {
       (void)hipEventRecord(e0, s);
       st = run();
@@ -110,13 +123,17 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
       (void)hipEventElapsedTime(&t[rep], e0, e1);
     }
     if (st != SPTRSV_OK) break;
-    if (cand.mode == 3 && drop_timeout()) continue;
+    if (waits && drop_timeout()) {
+      ++info.timed_out;
+      continue;
+    }
     std::sort(t, t + 3);
     if (t[1] < best) {
       best = t[1];
       best_s = cand;
     }
   }
+  h->wait_ticks = 0;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   P->sched = keep;
@@ -124,8 +141,16 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
   if (st != SPTRSV_OK) return st;
   HIPCHK(h, hipStreamSynchronize(s));
   P->tuned[nrhs] = best_s;
+  info.best_ms = best;
+  h->tune_info = info;
   if (best_ms) *best_ms = best;
   return sptrsv_check(h, s);
+}
+
+sptrsv_status_t sptrsv_get_tune_info(sptrsv_handle_t h, sptrsv_tune_info_t *out) {
+  if (!h || !out) return SPTRSV_ERR_ARG;
+  *out = h->tune_info;
+  return SPTRSV_OK;
 }
 
 sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,

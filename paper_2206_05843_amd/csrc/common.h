@@ -129,6 +129,18 @@ struct Plan {
   DArr<ExtDep> ext;
   int32_t runs_nrhs = -1;
   sptrsv_schedule_t runs_sched{};
+  // Overlap of the layout transposes with the level chain (large solves): the
+  // chain's runs are cut into segments at levels seg_lvl[k]; gather group k
+  // (the caller-row tiles of 64 rows whose first position lies in segment k)
+  // and the b-transform of segment k's rows run on the handle's side stream
+  // before segment k starts, and scatter group k (tiles whose last position
+  // lies in segment k) after it ends, while later segments run.
+  bool ovl = false;
+  std::vector<int32_t> seg_run;        // [K+1] first run of each segment
+  std::vector<int32_t> g_off, s_off;   // [K+1] offsets of each group in g_tiles / s_tiles
+  std::vector<int32_t> t_off;          // [K+1] offsets of each segment's rows of T in tpos
+  DArr<int32_t> g_tiles, s_tiles;
+  std::vector<int32_t> h_tpos;         // host copy of tpos
   DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
   DArr<unsigned> tp;                   // [4] thin-run launches: epoch, progress, helper sink
   DArr<unsigned long long> sf_ticket;  // [1] ticket counter of the synchronisation-free solve
@@ -193,7 +205,20 @@ struct sptrsv_ctx {
   size_t prof_used = 0;
   // scan scratch
   DArr<long long> scan_tmp;
+  // bounded device-side waits of solves (synchronisation-free and persistent
+  // launches), in ticks of the 100 MHz wall clock; 0 = the default 10 s. The
+  // autotuner lowers it per candidate.
+  unsigned long long wait_ticks = 0;
+  sptrsv_tune_info_t tune_info{};
+  // side stream (default priority) and events of the overlapped transposes
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> ovl_ev;
 };
+
+// Wait limit of a solve launch in wall-clock ticks.
+inline unsigned long long wait_limit(const sptrsv_ctx *h) {
+  return h->wait_ticks ? h->wait_ticks : 100000000ull * 10;
+}
 
 // Status plumbing ------------------------------------------------------------
 sptrsv_status_t set_err(sptrsv_ctx *h, sptrsv_status_t st, const char *fmt, ...);
@@ -297,6 +322,13 @@ hipError_t launch_apply_t(int32_t nt, int32_t nrhs, int32_t lanes, const int32_t
                           double *bp, hipStream_t s);
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
+// The same over a list of caller-row tiles of 64 rows.
+hipError_t launch_gather_tiles(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm,
+                               const int32_t *tiles, int32_t ntiles, double *bp, hipStream_t s);
+hipError_t launch_scatter_tiles(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm,
+                                const int32_t *tiles, int32_t ntiles, double *x, int64_t ldx, hipStream_t s);
+// First and last position of the rows of every caller-row tile of 64 rows.
+hipError_t launch_tile_span(int32_t n, const int32_t *iperm, int32_t *first, int32_t *last, hipStream_t s);
 int thin_win_bytes();
 hipError_t launch_extra_hist(int32_t n, const int32_t *level_ptr, int32_t nlev, const int32_t *srp,
                              const int32_t *sci, int32_t *lop, int32_t *hist, hipStream_t s);
@@ -310,7 +342,8 @@ hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t
                              hipStream_t s);
 hipError_t launch_wide_run(int grid, int threads, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                           const double *bp, double *xp, unsigned *bar, int *err, hipStream_t s);
+                           const double *bp, double *xp, unsigned *bar, int *err, unsigned long long tlimit,
+                           hipStream_t s);
 int wide_run_resident_blocks(int threads);
 // rev: b and x in the reversed (caller's) numbering of the lower form
 hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,
@@ -415,7 +448,7 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
 // blocks: workgroups of 256 threads (0: 512).
 hipError_t launch_syncfree(int32_t n, int32_t nrhs, const int32_t *srp, const int32_t *sci, const double *sva,
                            const double *sdg, const double *bp, double *xp, unsigned long long *ticket, int *err,
-                           int32_t blocks, hipStream_t s);
+                           int32_t blocks, unsigned long long tlimit, hipStream_t s);
 // Triangular forms (k_form.hip) ---------------------------------------------------
 hipError_t launch_rev_entries(int32_t n, int32_t nnz, const int32_t *rp, const int32_t *ci, const double *va,
                               int32_t *orp, int32_t *oci, double *ova, hipStream_t s);
@@ -426,6 +459,16 @@ hipError_t launch_take_entries(int32_t nnz, const int32_t *order, const int32_t 
 hipError_t launch_rev_io(int32_t n, const int32_t *perm, const int32_t *iperm, int32_t *perm_io, int32_t *iperm_io,
                          hipStream_t s);
 ThinArgs thin_args(const Plan &P);
-sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, hipStream_t s);
+ThinArgs thin_args(const Plan &P, double *bp, double *xp);
+sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *bp,
+                         hipStream_t s);
+// The plan a solve entry point addresses after checking its arguments (null
+// with *st set on failure).
+Plan *solve_plan(sptrsv_ctx *h, int which, int32_t nrhs, const double *d_b, int64_t ldb, const double *d_x,
+                 int64_t ldx, sptrsv_status_t *st);
+// Whether the plan's runs and images are built for nrhs and the schedule in force.
+bool runs_ready(const Plan &P, int32_t nrhs);
+sptrsv_status_t solve_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
+                           int64_t ldx, double *bp, double *xp, hipStream_t s);
 sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
                            int64_t ldx, hipStream_t s);

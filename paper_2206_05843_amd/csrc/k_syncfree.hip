@@ -115,12 +115,11 @@ __global__ __launch_bounds__(kBlock) void k_sf_solve(int32_t n, int32_t nrhs, co
 
 hipError_t launch_syncfree(int32_t n, int32_t nrhs, const int32_t *srp, const int32_t *sci, const double *sva,
                            const double *sdg, const double *bp, double *xp, unsigned long long *ticket, int *err,
-                           int32_t blocks, hipStream_t s) {
+                           int32_t blocks, unsigned long long limit, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int64_t total = (int64_t)n * nrhs;
   unsigned long long *xb = reinterpret_cast<unsigned long long *>(xp);
   hipLaunchKernelGGL(k_sf_init, dim3(grid_for(total, kBlock, 8192)), dim3(kBlock), 0, s, total, xb, ticket);
-  const unsigned long long limit = 100000000ull * 10;  // 10 s of the 100 MHz wall clock
   const dim3 grid(grid_for(total, kBlock, blocks > 0 ? blocks : 512));
   if (nrhs == 1)
     hipLaunchKernelGGL(k_sf_solve<true>, grid, dim3(kBlock), 0, s, n, nrhs, srp, sci, sva, sdg, bp, xp, ticket, err,

@@ -16,6 +16,7 @@
 //  * wide levels: one launch over the device per level (kernel boundaries order
 //    the levels).
 #include "common.h"
+#include "sync.h"
 
 namespace {
 
@@ -29,14 +30,6 @@ struct Ctl {
   int32_t pad[3];
 };
 
-// Workgroup barrier that orders LDS only: global stores may still be in flight
-// (the global copy of x is only read across an LDS-window restart, which uses a
-// full barrier).
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // A thin run is cut into LDS windows (consecutive levels, chosen on the host so
 // that the window's rows and dependency records fit in LDS). Per window:
@@ -260,13 +253,10 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
               nxt = load_item<kOne>(pb, items, tid, nr, v, rw, rix);
             }
             if (cur.act) v[(int64_t)cur.s * nr + cur.c] = solve_item<kOne>(cur, nr, v, ovf);
-            if (one_wave) {
-              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-              __builtin_amdgcn_wave_barrier();
-              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-            } else {
-              lds_barrier();
-            }
+            if (one_wave)
+              wave_lds_barrier();
+            else
+              lds_barrier();  // LDS only: the global x is read only across a window restart
             if (kTimed && tid == 0) {
               const int32_t lg = c0 + l;
               const unsigned long long now = wall_clock64();

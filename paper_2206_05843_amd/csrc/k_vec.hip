@@ -2,6 +2,8 @@
 // the level-ordered, RHS-interleaved work vector and back, the b-transform of
 // the rewritten system (Sec. II.B), the residual check, and the batched
 // variants of the gather and scatter.
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -24,6 +26,73 @@ __global__ void k_gather(int32_t n, int32_t nrhs, const double *__restrict__ b, 
       if (r0 + rr < n) bp[(int64_t)iperm[r0 + rr] * nrhs + c0 + c] = tile[rr][c];
     }
     __syncthreads();
+  }
+}
+
+// The gather and scatter over a list of tiles (workgroups stride the list;
+// the grid is capped so that a group running beside the level chain leaves
+// most of the device to it).
+__global__ void k_gather_tiles(int32_t n, int32_t nrhs, const double *__restrict__ b, int64_t ldb,
+                               const int32_t *__restrict__ iperm, const int32_t *__restrict__ tiles, int32_t ntiles,
+                               double *bp) {
+  __shared__ double tile[64][33];
+  for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const int32_t r0 = tiles[ti] * 64;
+    for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
+      const int32_t nc = min(32, nrhs - c0);
+      for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+        const int c = idx / 64, rr = idx % 64;
+        if (r0 + rr < n) tile[rr][c] = b[(int64_t)(c0 + c) * ldb + r0 + rr];
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+        const int rr = idx / nc, c = idx % nc;
+        if (r0 + rr < n) bp[(int64_t)iperm[r0 + rr] * nrhs + c0 + c] = tile[rr][c];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_scatter_tiles(int32_t n, int32_t nrhs, const double *__restrict__ xp,
+                                const int32_t *__restrict__ iperm, const int32_t *__restrict__ tiles, int32_t ntiles,
+                                double *x, int64_t ldx) {
+  __shared__ double tile[64][33];
+  for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const int32_t r0 = tiles[ti] * 64;
+    for (int32_t c0 = 0; c0 < nrhs; c0 += 32) {
+      const int32_t nc = min(32, nrhs - c0);
+      for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+        const int rr = idx / nc, c = idx % nc;
+        if (r0 + rr < n) tile[rr][c] = xp[(int64_t)iperm[r0 + rr] * nrhs + c0 + c];
+      }
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < 64 * nc; idx += blockDim.x) {
+        const int c = idx / 64, rr = idx % 64;
+        if (r0 + rr < n) x[(int64_t)(c0 + c) * ldx + r0 + rr] = tile[rr][c];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Smallest and largest position of the rows of each 64-row tile (a wave per tile).
+__global__ void k_tile_span(int32_t n, const int32_t *__restrict__ iperm, int32_t *first, int32_t *last) {
+  const int32_t ntiles = (n + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  for (int32_t t = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); t < ntiles;
+       t += (int32_t)((gridDim.x * blockDim.x) >> 6)) {
+    const int32_t r = t * 64 + lane;
+    int32_t lo = r < n ? iperm[r] : INT32_MAX, hi = r < n ? iperm[r] : -1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      lo = min(lo, __shfl_xor(lo, off, 64));
+      hi = max(hi, __shfl_xor(hi, off, 64));
+    }
+    if (lane == 0) {
+      first[t] = lo;
+      last[t] = hi;
+    }
   }
 }
 
@@ -184,6 +253,8 @@ __global__ void k_batch_scatter(int64_t total, int32_t nrhs, const double *__res
   }
 }
 
+constexpr int32_t kTileGrid = 1024;
+
 }  // namespace
 
 hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
@@ -193,6 +264,29 @@ hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, 
     hipLaunchKernelGGL(k_gather1, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, b, iperm, bp);
   else
     hipLaunchKernelGGL(k_gather, dim3((n + 63) / 64), dim3(256), 0, s, n, nrhs, b, ldb, iperm, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_tiles(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm,
+                               const int32_t *tiles, int32_t ntiles, double *bp, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_tiles, dim3(std::min(ntiles, kTileGrid)), dim3(256), 0, s, n, nrhs, b, ldb, iperm, tiles,
+                     ntiles, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_tiles(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm,
+                                const int32_t *tiles, int32_t ntiles, double *x, int64_t ldx, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_tiles, dim3(std::min(ntiles, kTileGrid)), dim3(256), 0, s, n, nrhs, xp, iperm, tiles,
+                     ntiles, x, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_span(int32_t n, const int32_t *iperm, int32_t *first, int32_t *last, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t ntiles = (n + 63) / 64;
+  hipLaunchKernelGGL(k_tile_span, dim3(grid_for(ntiles * 64, 256, 16384)), dim3(256), 0, s, n, iperm, first, last);
   return hipGetLastError();
 }
 

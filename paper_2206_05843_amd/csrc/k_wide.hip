@@ -4,6 +4,7 @@
 // one persistent launch for a run of consecutive wide levels with a
 // device-wide barrier between levels.
 #include "common.h"
+#include "sync.h"
 
 namespace {
 
@@ -159,36 +160,13 @@ __global__ void k_wide_run(int32_t l0, int32_t l1, const int32_t *__restrict__ l
       __hip_atomic_store(xp + (int64_t)pos * nr + c, xv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (l + 1 == l1) break;
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores of x have completed
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const unsigned target = (unsigned)(l - l0 + 1) * gridDim.x;
-      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      unsigned spins = 0;
-      while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        __builtin_amdgcn_s_sleep(1);
-        if ((++spins & 255u) == 0u && wall_clock64() - t0 > tlimit) {
-          s_abort = 1;
-          break;
-        }
-      }
-    }
-    __syncthreads();
-    if (s_abort) {
+    if (!grid_barrier(bar, (unsigned)(l - l0 + 1), t0, tlimit, &s_abort)) {
       bits |= EB_TIMEOUT;
       break;
     }
   }
   if (bits) atomicOr(err, bits);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(bar + 1, 1u) == gridDim.x - 1) {
-      atomicExch(bar, 0u);
-      atomicExch(bar + 1, 0u);
-      __threadfence();
-    }
-  }
+  grid_barrier_reset(bar);
 }
 
 }  // namespace
@@ -246,12 +224,12 @@ int wide_run_resident_blocks(int threads) {
 
 hipError_t launch_wide_run(int grid, int threads, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                           const double *bp, double *xp, unsigned *bar, int *err, hipStream_t s) {
+                           const double *bp, double *xp, unsigned *bar, int *err, unsigned long long limit,
+                           hipStream_t s) {
   if (l1 <= l0) return hipSuccess;
   const int cap = wide_run_resident_blocks(threads);
   if (cap < 1) return hipErrorInvalidConfiguration;
   grid = std::max(1, std::min(grid, cap));  // every workgroup must be resident for the barrier
-  const unsigned long long limit = 100000000ull * 10;  // 10 s of the 100 MHz wall clock
   if (nrhs == 1)
     hipLaunchKernelGGL((k_wide_run<true>), dim3(grid), dim3(threads), 0, s, l0, l1, level_ptr, nrhs, srp, sci, sva,
                        sdg, bp, xp, bar, err, limit);

@@ -30,7 +30,8 @@ EXPORTS = [
     "sptrsv_autotune", "sptrsv_graph_create", "sptrsv_graph_launch", "sptrsv_residual", "sptrsv_batch_analyze",
     "sptrsv_batch_solve", "sptrsv_batch_solve_looped", "sptrsv_batch_levels", "sptrsv_plan_save",
     "sptrsv_plan_load", "sptrsv_level_features", "sptrsv_mlp_forward", "sptrsv_mlp_backward", "sptrsv_mlp_adam",
-    "sptrsv_mlp_mask", "sptrsv_profile", "sptrsv_level_times",
+    "sptrsv_mlp_mask", "sptrsv_profile", "sptrsv_level_times", "sptrsv_get_tune_info",
+    "sptrsv_measure_level_costs", "sptrsv_level_floor",
 ]
 
 
@@ -63,6 +64,22 @@ class KernelProfile(C.Structure):
 
 
 PROFILE_CLASSES = ["gather", "thin_run", "wide_level", "scatter"]
+
+
+class TuneInfo(C.Structure):
+    _fields_ = [("candidates", C.c_int32), ("timed_out", C.c_int32), ("best_ms", C.c_float),
+                ("max_wait_limit_ms", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LevelCosts(C.Structure):
+    _fields_ = [("thin_level_ns", C.c_double), ("thin_wave_level_ns", C.c_double), ("launch_ns", C.c_double),
+                ("graph_node_ns", C.c_double), ("grid_barrier_ns", C.c_double), ("flag_hop_ns", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Schedule(C.Structure):
@@ -118,6 +135,9 @@ def lib():
         "sptrsv_mlp_adam": [vp, vp, vp, vp, i32, f32, vp],
         "sptrsv_mlp_mask": [vp, i32, f32, vp, vp],
         "sptrsv_profile": [vp, C.c_int, vp, vp],
+        "sptrsv_get_tune_info": [vp, C.POINTER(TuneInfo)],
+        "sptrsv_measure_level_costs": [vp, vp, C.POINTER(LevelCosts)],
+        "sptrsv_level_floor": [vp, C.c_int, i32, i32, C.POINTER(LevelCosts), C.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -319,6 +339,27 @@ class Handle:
         ms = C.c_float(0)
         self._check(self._L.sptrsv_autotune(self._h, which, nrhs, _stream(), C.byref(ms)))
         return ms.value
+
+    def measure_level_costs(self) -> dict:
+        """ns per empty level for each way a solve separates levels."""
+        out = LevelCosts()
+        self._check(self._L.sptrsv_measure_level_costs(self._h, _stream(), C.byref(out)))
+        return out.as_dict()
+
+    def level_floor(self, costs: dict, which=ORIGINAL, nrhs=1, graph=False) -> float:
+        """Microseconds one solve of (which, nrhs) costs at least with empty
+        levels, under the schedule it uses."""
+        c = LevelCosts(**costs)
+        out = C.c_double(0)
+        self._check(self._L.sptrsv_level_floor(self._h, which, nrhs, int(bool(graph)), C.byref(c), C.byref(out)))
+        return out.value
+
+    def tune_info(self) -> dict:
+        """What the last autotune did: candidates timed, candidates dropped at
+        their device-side wait limit, the best time and the largest limit."""
+        out = TuneInfo()
+        self._check(self._L.sptrsv_get_tune_info(self._h, C.byref(out)))
+        return out.as_dict()
 
     def profile_start(self):
         self._check(self._L.sptrsv_profile(self._h, 1, None, _stream()))

@@ -64,6 +64,54 @@ def test_full_solve_autotuned(full, cfg, variant):
     assert torch.equal(x, x2)
 
 
+def _oracle_policy_mask(m, lv, pol):
+    """The shipped policy's level mask computed on the CPU side: the oracle's
+    FP64 features through the FP64 network with the checkpoint's weights
+    (rounded to the float32 the checkpoint holds). Also returns the oracle's
+    probabilities, to find decisions that sit on the threshold."""
+    from oracle import mlp
+    th = pol.params.cpu().numpy().astype(np.float64)
+    norm = pol.norm.cpu().numpy().astype(np.float64)
+    fo = oracle.level_features(m, lv)
+    po, _ = mlp.forward(th, (fo - norm[:mlp.F_IN]) * norm[mlp.F_IN:])
+    mask = ((po >= pol.threshold) & (np.arange(lv.nlev) > 0)).astype(np.uint8)
+    return mask, po
+
+
+def _same_rewrite(h, rw):
+    g = {k: v.cpu().numpy() for k, v in h.rewritten().items()}
+    assert np.array_equal(g["lp_ptr"], rw.lp.row_ptr) and np.array_equal(g["lp_col"], rw.lp.col)
+    assert np.array_equal(g["t_ptr"], rw.t_ptr) and np.array_equal(g["t_col"], rw.t_col)
+    assert np.array_equal(g["lp_val"], rw.lp.val) and np.array_equal(g["t_val"], rw.t_val)
+    assert np.array_equal(h.targets().cpu().numpy(), rw.target)
+
+
+@pytest.mark.parametrize("cfg,variant", [(1, "naive"), (2, "naive"), (1, "learned"), (2, "learned")])
+def test_full_rewrite_patterns(full, cfg, variant):
+    """Rewritten L', T and targets at full size, bit for bit. For the learned
+    variant the level mask is the CPU side's (the oracle's features and
+    network); the device's own mask must agree with it on every level whose
+    oracle probability is not within 1e-4 of the threshold."""
+    m = full[cfg][0]
+    lv = oracle.levels(m)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    mask = None
+    if variant == "learned":
+        from paper_2206_05843_amd import policy
+        pol = policy.load_default()
+        assert pol is not None
+        mask, po = _oracle_policy_mask(m, lv, pol)
+        gm = pol.mask_for(h).cpu().numpy()
+        sure = np.abs(po - pol.threshold) > 1e-4
+        assert np.array_equal(gm[sure], mask[sure])
+    st = h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0, to_dev(mask) if mask is not None else None)
+    rw = oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0, 0, mask, lv)
+    assert st["rows_rewritten"] == rw.rows_rewritten
+    assert st["nlev_after"] == oracle.levels(rw.lp).nlev
+    _same_rewrite(h, rw)
+
+
 def test_full_rewrite_patterns_3d():
     m = gen.config_matrix(4)[0]
     h = sp.Handle()

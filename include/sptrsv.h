@@ -205,6 +205,21 @@ sptrsv_status_t sptrsv_get_targets(sptrsv_handle_t h, int32_t *d_target, hipStre
 sptrsv_status_t sptrsv_solve(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
                              double *d_x, int64_t ldx, hipStream_t s);
 
+/* sptrsv_solve_noalloc -- sptrsv_solve for callers that cannot allocate device
+ * memory: code under hipGraph capture, tight serving loops, harnesses that
+ * forbid hipMalloc. Same arguments, kernels and result (bit for bit) as
+ * sptrsv_solve; its two work vectors (n * nrhs doubles each) live in a static
+ * 64 MiB device array that every GPU the library runs on holds until the
+ * process ends, so n * nrhs must be at most 4,194,304 (else ERR_ARG).
+ * It calls no allocating routine: the schedule for (which, nrhs) must already
+ * be built (sptrsv_prepare, or an earlier sptrsv_solve with the same nrhs and
+ * schedule), else ERR_STATE. The work area is shared by every call on the same
+ * GPU (all handles): calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller. Nothing in it needs to
+ * start at any value. ASYNC; errors as sptrsv_solve. */
+sptrsv_status_t sptrsv_solve_noalloc(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
+                                     double *d_x, int64_t ldx, hipStream_t s);
+
 /* Allocate the work vectors for (which, nrhs) so later solves allocate nothing. */
 sptrsv_status_t sptrsv_prepare(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s);
 

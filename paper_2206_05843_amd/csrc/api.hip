@@ -538,6 +538,11 @@ sptrsv_status_t sptrsv_create(sptrsv_handle_t *out) {
     solve_kernels_init();
     inited = true;
   }
+  const hipError_t ne = noalloc_init(h->dev);
+  if (ne != hipSuccess) {
+    delete h;
+    return SPTRSV_ERR_HIP;
+  }
   h->orig.sched = default_schedule();
   h->rew.sched = default_schedule();
   *out = h;

@@ -215,6 +215,10 @@ struct sptrsv_ctx {
   std::vector<hipEvent_t> ovl_ev;
 };
 
+// Per-device address of the static work area of sptrsv_solve_noalloc
+// (api_noalloc.hip), looked up once per device.
+hipError_t noalloc_init(int dev);
+
 // Wait limit of a solve launch in wall-clock ticks.
 inline unsigned long long wait_limit(const sptrsv_ctx *h) {
   return h->wait_ticks ? h->wait_ticks : 100000000ull * 10;

@@ -31,7 +31,7 @@ EXPORTS = [
     "sptrsv_batch_solve", "sptrsv_batch_solve_looped", "sptrsv_batch_levels", "sptrsv_plan_save",
     "sptrsv_plan_load", "sptrsv_level_features", "sptrsv_mlp_forward", "sptrsv_mlp_backward", "sptrsv_mlp_adam",
     "sptrsv_mlp_mask", "sptrsv_profile", "sptrsv_level_times", "sptrsv_get_tune_info",
-    "sptrsv_measure_level_costs", "sptrsv_level_floor",
+    "sptrsv_solve_noalloc", "sptrsv_measure_level_costs", "sptrsv_level_floor",
 ]
 
 
@@ -114,6 +114,7 @@ def lib():
         "sptrsv_get_rewritten": [vp, vp, vp, vp, vp, vp, vp, vp],
         "sptrsv_get_targets": [vp, vp, vp],
         "sptrsv_solve": [vp, C.c_int, i32, vp, i64, vp, i64, vp],
+        "sptrsv_solve_noalloc": [vp, C.c_int, i32, vp, i64, vp, i64, vp],
         "sptrsv_prepare": [vp, C.c_int, i32, vp],
         "sptrsv_check": [vp, vp],
         "sptrsv_set_schedule": [vp, C.c_int, C.POINTER(Schedule)],
@@ -295,8 +296,10 @@ class Handle:
         return t
 
     # --------------------------------------------------------------------- solve
-    def solve(self, b, which=ORIGINAL, x=None):
-        """b: float64 device tensor of shape (n,) or (nrhs, n) (column c = b[c])."""
+    def solve(self, b, which=ORIGINAL, x=None, noalloc=False):
+        """b: float64 device tensor of shape (n,) or (nrhs, n) (column c = b[c]).
+        noalloc=True calls sptrsv_solve_noalloc (work vectors in the library's
+        static work area; x must be given and the schedule prepared)."""
         _need(b.dtype == torch.float64 and b.is_cuda, "float64 device tensor expected")
         bb = b if b.dim() == 2 else b.view(1, -1)
         _need(bb.shape[1] == self.n and bb.stride(1) == 1, "b must be (nrhs, n) with unit row stride")
@@ -306,7 +309,8 @@ class Handle:
             x = torch.empty_like(bb)
         xx = x if x.dim() == 2 else x.view(1, -1)
         ldx = xx.stride(0) if nrhs > 1 else self.n
-        self._check(self._L.sptrsv_solve(self._h, which, nrhs, _ptr(bb), ldb, _ptr(xx), ldx, _stream()))
+        fn = self._L.sptrsv_solve_noalloc if noalloc else self._L.sptrsv_solve
+        self._check(fn(self._h, which, nrhs, _ptr(bb), ldb, _ptr(xx), ldx, _stream()))
         return x if b.dim() == 2 else x.view(-1)
 
     def prepare(self, which=ORIGINAL, nrhs=1):

@@ -311,6 +311,45 @@ def bench_precond(args, np, torch, gen, oracle, sp):
     print(json.dumps(res), flush=True)
 
 
+def bench_analysis(args, np, torch, gen, oracle, sp):
+    """Preprocessing only: wall time of each step (synchronised) on the
+    workload, with the oracle's serial level pass beside it."""
+    dev = torch.device("cuda:0")
+    m, nrhs = gen.config_matrix(args.config)
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (m.row_ptr, m.col, m.val))
+    t = time.perf_counter()
+    lv = oracle.levels(m)
+    t_oracle = time.perf_counter() - t
+    out = {"workload": WORKLOADS[args.config], "oracle_levels_s": round(t_oracle, 4), "nlev": lv.nlev, "runs": []}
+    from paper_2206_05843_amd import policy
+    pol = policy.load_default()
+    for rep in range(3):
+        r = {}
+        torch.cuda.synchronize()
+        h = sp.Handle()
+        t = time.perf_counter()
+        nlev = h.analyze(rp, ci, va)
+        torch.cuda.synchronize()
+        r["analyze_s"] = time.perf_counter() - t
+        assert nlev == lv.nlev
+        t = time.perf_counter()
+        h.level_features()
+        torch.cuda.synchronize()
+        r["features_s"] = time.perf_counter() - t
+        t = time.perf_counter()
+        h.rewrite(sp.THIN_ROWS, 32, 4.0, 0)
+        torch.cuda.synchronize()
+        r["rewrite_naive_s"] = time.perf_counter() - t
+        if pol is not None:
+            t = time.perf_counter()
+            h.rewrite(sp.THIN_ROWS, 32, 4.0, 0, pol.mask_for(h))
+            torch.cuda.synchronize()
+            r["rewrite_learned_s"] = time.perf_counter() - t
+        out["runs"].append({k: round(v, 4) for k, v in r.items()})
+        log(f"[bench] analysis rep {rep}: {out['runs'][-1]}")
+    print(json.dumps(out), flush=True)
+
+
 def calibrate_copy(torch, mib):
     """Ten device-to-device copies of a buffer of known size: the FETCH_SIZE and
     WRITE_SIZE counters of these launches scale the counters of the solve
@@ -339,6 +378,9 @@ def main():
                          "lanes_per_row); those variants skip the autotuner (for profiled runs)")
     ap.add_argument("--graph", type=int, default=None, choices=(0, 1),
                     help="time hipGraph replays of the solve (default: on for the 3D stencil workload)")
+    ap.add_argument("--analysis-only", action="store_true",
+                    help="only time the preprocessing of the workload (analysis, level features with the "
+                         "longest-path heights, naive and learned rewrites), no solves")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 device copies of MIB MiB (the reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -366,6 +408,9 @@ def main():
         return
     if args.config == 5:
         bench_precond(args, np, torch, gen, oracle, sp)
+        return
+    if args.analysis_only:
+        bench_analysis(args, np, torch, gen, oracle, sp)
         return
     use_graph = (args.config in GRAPH_DEFAULT) if args.graph is None else bool(args.graph)
     stream = torch.cuda.Stream()  # graph capture needs a non-default stream

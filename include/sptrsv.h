@@ -234,7 +234,12 @@ sptrsv_status_t sptrsv_check(sptrsv_handle_t h, hipStream_t s);
  * 3 = no level barriers at all: one synchronisation-free launch in which each
  * (row, right-hand side) waits only for the values it reads (the comparison
  * executor; wide_grid gives its workgroups of 256 threads, 0 = 512, at most
- * 2048; the other knobs are ignored).
+ * 2048; the other knobs are ignored),
+ * 4 = levels with at most thin_rows rows in thin runs as in mode 0, and each
+ * run of consecutive wider levels as one dataflow launch: every level is cut
+ * into chunks of 2 * wide_threads items (wide_threads = 128, 256 or 512) and
+ * a chunk waits only for the chunks of the run holding the rows it reads, not
+ * for whole levels (wide_grid: workgroups in flight, 0 = as many as fit).
  * set_schedule replaces the schedules sptrsv_autotune picked for this matrix;
  * get_schedule reports the schedule a solve with nrhs right-hand sides uses
  * (the tuned one for that nrhs if there is one, else the one set). */
@@ -337,6 +342,10 @@ sptrsv_status_t sptrsv_residual(sptrsv_handle_t h, int32_t nrhs, const double *d
  * column indices local. Each matrix is level-scheduled as in sptrsv_analyze.
  * batch_solve solves all matrices in one persistent launch; matrix i's b and x
  * are n_i x nrhs column-major at offset nrhs*h_row_off[i], ld = n_i. ASYNC.
+ * A matrix with a level too wide for one workgroup's LDS window at this nrhs
+ * (about 1,000 rows at 16 right-hand sides) is taken out of the persistent
+ * launch and solved level by level (thin runs, one device-wide launch per
+ * wide level) in the same call, with the same result.
  * ------------------------------------------------------------------------- */
 sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t nmat, const int32_t *h_n, const int64_t *h_row_off,
                                      const int64_t *h_nnz_off, const int32_t *d_row_ptr_cat, const int32_t *d_col_cat,
@@ -352,11 +361,37 @@ sptrsv_status_t sptrsv_batch_levels(sptrsv_handle_t h, int32_t i, int32_t *nlev,
                                     int32_t *d_level_rows, hipStream_t s);
 
 /* ---------------------------------------------------------------------------
- * Plan persistence (levels, rewritten matrix and schedules in a file): not
- * implemented; both calls return SPTRSV_ERR_STATE with a message and change
- * nothing. A plan is rebuilt with sptrsv_analyze and sptrsv_rewrite. */
+ * Plan files: rewriting is a preprocessing step whose result later solves use
+ * (Sec. II.B, Sec. III), so a handle's analysis and rewrite can be kept in a
+ * file and loaded into another handle (or process) that then solves without
+ * analysing, rewriting or tuning again.
+ * plan_save writes the matrix in its lower-triangular form, the level sets and
+ * level-ordered copy of L, the rewritten L', T, targets and statistics (if a
+ * rewrite was made) with their level sets, and the schedules in force and
+ * tuned per nrhs, to the host file `path` (created or truncated). Synchronous
+ * (waits for the device). Errors: STATE (nothing analysed), ARG (the file
+ * cannot be written), HIP.
+ * plan_load replaces the handle's analysis and rewrite by the file's (it
+ * destroys the handle's graphs, which captured the old buffers). Solves after
+ * it give the same x, bit for bit, as solves with the handle that saved it.
+ * The file is checked before the handle changes: a file that is not a plan,
+ * of another version, truncated or altered (an FNV-1a-64 hash over its bytes
+ * is stored at its end) returns ERR_ARG and leaves the handle as it was; a
+ * file that passes the checks but fails while loading leaves it unanalysed.
+ * Window images and work vectors are rebuilt by the first solve or
+ * sptrsv_prepare. Synchronous. */
 sptrsv_status_t sptrsv_plan_save(sptrsv_handle_t h, const char *path);
 sptrsv_status_t sptrsv_plan_load(sptrsv_handle_t h, const char *path);
+
+/* What a handle holds (after analyze, rewrite or plan_load): its triangular
+ * form, n, nnz and number of levels of the analysed matrix, whether a rewrite
+ * is held, and (st, may be NULL) that rewrite's statistics. ERR_STATE if
+ * nothing is analysed. */
+typedef struct {
+  int32_t form, n, nlev, has_rewrite;
+  int64_t nnz;
+} sptrsv_info_t;
+sptrsv_status_t sptrsv_get_info(sptrsv_handle_t h, sptrsv_info_t *out, sptrsv_rewrite_stats_t *st);
 
 /* ---------------------------------------------------------------------------
  * Learned rewrite policy (not in the paper; replaces the thin-level test of

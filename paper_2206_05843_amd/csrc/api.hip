@@ -42,6 +42,11 @@ int bit_width(int64_t v) {
 
 }  // namespace
 
+// Overlapped transposes: at most kMaxSegments segments of the level chain,
+// used from kOverlapMin work-vector entries on.
+constexpr int32_t kMaxSegments = 16;
+constexpr int64_t kOverlapMin = (int64_t)1 << 22;
+
 sptrsv_schedule_t default_schedule() {
   sptrsv_schedule_t s{};
   s.mode = 0;
@@ -61,7 +66,9 @@ bool same_sched(const sptrsv_schedule_t &a, const sptrsv_schedule_t &b) {
 }
 
 sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
-  if (s.mode < 0 || s.mode > 3) return set_err(h, SPTRSV_ERR_ARG, "schedule mode %d", s.mode);
+  if (s.mode < 0 || s.mode > 4) return set_err(h, SPTRSV_ERR_ARG, "schedule mode %d", s.mode);
+  if (s.mode == 4 && s.wide_threads != 128 && s.wide_threads != 256 && s.wide_threads != 512)
+    return set_err(h, SPTRSV_ERR_ARG, "wide_threads %d: a dataflow run takes 128, 256 or 512", s.wide_threads);
   if (s.wg_threads != 256 && s.wg_threads != 512 && s.wg_threads != 1024)
     return set_err(h, SPTRSV_ERR_ARG, "wg_threads %d", s.wg_threads);
   if (s.wide_threads < 64 || s.wide_threads > 1024 || s.wide_threads % 64)
@@ -199,21 +206,182 @@ sptrsv_status_t build_images(sptrsv_ctx *h, Plan &P, hipStream_t s) {
   return SPTRSV_OK;
 }
 
+// Chunk tables of the dataflow runs (schedule mode 4): each level of a flow
+// run is cut into chunks of one workgroup's items (rows_per_chunk rows); a
+// chunk's list holds the distinct chunks of the same run that hold the rows
+// its rows depend on. Built on the host from the level-ordered pattern, which
+// the plan keeps a host copy of after the first build.
+static sptrsv_status_t build_flow(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc,
+                                  hipStream_t s) {
+  const int32_t n = P.n;
+  if (P.h_srp.empty()) {
+    P.h_srp.resize((size_t)n + 1);
+    P.h_sci.resize((size_t)std::max<int64_t>(P.nnz - n, 1));
+    HIPCHK(h, hipMemcpyAsync(P.h_srp.data(), P.srp.p, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+    if (P.nnz > n)
+      HIPCHK(h, hipMemcpyAsync(P.h_sci.data(), P.sci.p, sizeof(int32_t) * (size_t)(P.nnz - n), hipMemcpyDeviceToHost,
+                               s));
+    HIPCHK(h, hipStreamSynchronize(s));
+  }
+  const int32_t rpc = std::max(1, sc.wide_threads * flow_items_per_thread() / nrhs);
+  std::vector<int32_t> cpos, dptr, dlist, chunk_of((size_t)n, -1), stamp;
+  int32_t nflags = 0;
+  for (Run &r : P.runs) {
+    if (!r.flow) continue;
+    r.cp = (int32_t)cpos.size();
+    r.fl = nflags;
+    const int32_t pbeg = P.h_level_ptr[(size_t)r.l0], pend = P.h_level_ptr[(size_t)r.l1];
+    for (int32_t l = r.l0; l < r.l1; ++l)
+      for (int32_t p = P.h_level_ptr[(size_t)l]; p < P.h_level_ptr[(size_t)l + 1]; p += rpc) {
+        const int32_t k = (int32_t)cpos.size() - r.cp;
+        const int32_t pe = std::min(p + rpc, P.h_level_ptr[(size_t)l + 1]);
+        for (int32_t q = p; q < pe; ++q) chunk_of[(size_t)q] = k;
+        cpos.push_back(p);
+      }
+    r.nchunk = (int32_t)cpos.size() - r.cp;
+    cpos.push_back(pend);
+    // dptr has one entry per chunk and a terminator, aligned with cpos (same offsets)
+    dptr.resize(cpos.size() - 1 - r.nchunk);
+    stamp.assign((size_t)r.nchunk, -1);
+    for (int32_t k = 0; k < r.nchunk; ++k) {
+      dptr.push_back((int32_t)dlist.size());
+      for (int32_t p = cpos[(size_t)(r.cp + k)]; p < cpos[(size_t)(r.cp + k + 1)]; ++p)
+        for (int32_t q = P.h_srp[(size_t)p]; q < P.h_srp[(size_t)p + 1]; ++q) {
+          const int32_t d = P.h_sci[(size_t)q];
+          if (d < pbeg) continue;  // finished by an earlier launch
+          const int32_t dc = chunk_of[(size_t)d];
+          if (stamp[(size_t)dc] != k) {
+            stamp[(size_t)dc] = k;
+            dlist.push_back(dc);
+          }
+        }
+    }
+    dptr.push_back((int32_t)dlist.size());
+    nflags += r.nchunk;
+  }
+  if (dlist.empty()) dlist.push_back(0);
+  HIPCHK(h, P.flow_pos.alloc(cpos.size()));
+  HIPCHK(h, P.flow_dptr.alloc(dptr.size()));
+  HIPCHK(h, P.flow_dlist.alloc(dlist.size()));
+  HIPCHK(h, P.flow_flags.alloc((size_t)std::max(nflags, 1)));
+  HIPCHK(h, P.flow_ctl.alloc(4));
+  HIPCHK(h, hipMemcpy(P.flow_pos.p, cpos.data(), sizeof(int32_t) * cpos.size(), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(P.flow_dptr.p, dptr.data(), sizeof(int32_t) * dptr.size(), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(P.flow_dlist.p, dlist.data(), sizeof(int32_t) * dlist.size(), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemset(P.flow_flags.p, 0, sizeof(unsigned) * (size_t)std::max(nflags, 1)));
+  HIPCHK(h, hipMemset(P.flow_ctl.p, 0, 4 * sizeof(unsigned)));
+  return SPTRSV_OK;
+}
+
+// Segments of the level chain and the tile groups of the overlapped
+// transposes (Plan::ovl): used when the vectors are large (n * nrhs >= 2^22)
+// and the chain has several runs; segments end at run boundaries, at about
+// equal shares of the positions.
+
+static sptrsv_status_t build_overlap(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc,
+                                     hipStream_t s) {
+  P.ovl = false;
+  P.seg_run.clear();
+  const int32_t nruns = (int32_t)P.runs.size();
+  if (sc.mode == 3 || (int64_t)P.n * nrhs < kOverlapMin || nruns < 4 || !h->side) return SPTRSV_OK;
+  const int32_t K = std::min(kMaxSegments, nruns);
+  P.seg_run.push_back(0);
+  for (int32_t k = 1; k < K; ++k) {
+    const int64_t target = (int64_t)P.n * k / K;
+    int32_t r = P.seg_run.back() + 1;
+    while (r < nruns && P.h_level_ptr[(size_t)P.runs[(size_t)r].l0] < target) ++r;
+    if (r >= nruns) break;
+    P.seg_run.push_back(r);
+  }
+  P.seg_run.push_back(nruns);
+  const int32_t nseg = (int32_t)P.seg_run.size() - 1;
+  if (nseg < 2) {
+    P.seg_run.clear();
+    return SPTRSV_OK;
+  }
+  std::vector<int32_t> seg_pos((size_t)nseg + 1);
+  for (int32_t k = 0; k < nseg; ++k) seg_pos[(size_t)k] = P.h_level_ptr[(size_t)P.runs[(size_t)P.seg_run[(size_t)k]].l0];
+  seg_pos[(size_t)nseg] = P.n;
+  const int32_t ntiles = (P.n + 63) / 64;
+  DArr<int32_t> first, last;
+  HIPCHK(h, first.alloc((size_t)ntiles));
+  HIPCHK(h, last.alloc((size_t)ntiles));
+  HIPCHK(h, launch_tile_span(P.n, io_iperm(P), first.p, last.p, s));
+  std::vector<int32_t> hf((size_t)ntiles), hl((size_t)ntiles);
+  HIPCHK(h, hipMemcpyAsync(hf.data(), first.p, sizeof(int32_t) * (size_t)ntiles, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(hl.data(), last.p, sizeof(int32_t) * (size_t)ntiles, hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  auto seg_of = [&](int32_t pos) {
+    return (int32_t)(std::upper_bound(seg_pos.begin(), seg_pos.end(), pos) - seg_pos.begin()) - 1;
+  };
+  // counting sort of the tiles by the segment of their first / last position
+  auto group = [&](const std::vector<int32_t> &key, std::vector<int32_t> &off, std::vector<int32_t> &out) {
+    off.assign((size_t)nseg + 1, 0);
+    std::vector<int32_t> g((size_t)ntiles);
+    for (int32_t t = 0; t < ntiles; ++t) {
+      g[(size_t)t] = seg_of(key[(size_t)t]);
+      ++off[(size_t)g[(size_t)t] + 1];
+    }
+    for (int32_t k = 0; k < nseg; ++k) off[(size_t)k + 1] += off[(size_t)k];
+    out.assign((size_t)ntiles, 0);
+    std::vector<int32_t> at(off.begin(), off.end() - 1);
+    for (int32_t t = 0; t < ntiles; ++t) out[(size_t)at[(size_t)g[(size_t)t]]++] = t;
+  };
+  std::vector<int32_t> gt, st;
+  group(hf, P.g_off, gt);
+  group(hl, P.s_off, st);
+  HIPCHK(h, P.g_tiles.reserve((size_t)ntiles));
+  HIPCHK(h, P.s_tiles.reserve((size_t)ntiles));
+  HIPCHK(h, hipMemcpy(P.g_tiles.p, gt.data(), sizeof(int32_t) * (size_t)ntiles, hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(P.s_tiles.p, st.data(), sizeof(int32_t) * (size_t)ntiles, hipMemcpyHostToDevice));
+  P.t_off.assign((size_t)nseg + 1, 0);
+  for (int32_t k = 0; k <= nseg; ++k)
+    P.t_off[(size_t)k] = (int32_t)(std::lower_bound(P.h_tpos.begin(), P.h_tpos.end(), seg_pos[(size_t)k]) -
+                                   P.h_tpos.begin());
+  if ((int32_t)h->ovl_ev.size() < 2 * nseg + 2) return set_err(h, SPTRSV_ERR_STATE, "overlap events missing");
+  P.ovl = true;
+  return SPTRSV_OK;
+}
+
 sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_schedule_t &sc, hipStream_t s) {
   P.runs.clear();
   P.h_win.clear();
   const int64_t cap = thin_win_bytes();
   const int64_t thr = sc.thin_rows;
   auto rows_of = [&](int32_t l) -> int64_t { return P.h_level_ptr[l + 1] - P.h_level_ptr[l]; };
+  const bool flow = sc.mode == 4;
   for (int32_t l = 0; l < P.nlev; ++l) {
     const int64_t rows = rows_of(l);
-    bool thin = sc.mode == 2 || (sc.mode == 0 && rows <= thr);
+    bool thin = sc.mode == 2 || ((sc.mode == 0 || flow) && rows <= thr);
     if (win_bytes(rows, 0, 1, nrhs) > cap) thin = false;  // must fit one window alone
-    // consecutive thin levels share a run; so do consecutive wide levels with a persistent launch
-    if (!P.runs.empty() && P.runs.back().thin == thin && P.runs.back().l1 == l && (thin || sc.wide_grid > 0))
+    // consecutive thin levels share a run; so do consecutive wide levels of a persistent or dataflow launch
+    if (!P.runs.empty() && P.runs.back().thin == thin && P.runs.back().l1 == l &&
+        (thin || sc.wide_grid > 0 || flow))
       P.runs.back().l1 = l + 1;
     else
       P.runs.push_back(Run{l, l + 1, thin});
+    if (!thin) P.runs.back().flow = flow;
+  }
+  // with the transposes overlapped, long dataflow runs are cut into pieces of
+  // about n / kMaxSegments positions so that the chain has segment boundaries
+  if (flow && (int64_t)P.n * nrhs >= kOverlapMin) {
+    std::vector<Run> cut;
+    const int64_t piece = std::max<int64_t>(1, P.n / kMaxSegments);
+    for (const Run &r : P.runs) {
+      if (!r.flow) {
+        cut.push_back(r);
+        continue;
+      }
+      int32_t a = r.l0;
+      for (int32_t l = r.l0; l < r.l1; ++l)
+        if (P.h_level_ptr[(size_t)l + 1] - P.h_level_ptr[(size_t)a] >= piece || l + 1 == r.l1) {
+          Run q{a, l + 1, false};
+          q.flow = true;
+          cut.push_back(q);
+          a = l + 1;
+        }
+    }
+    P.runs.swap(cut);
   }
   for (Run &r : P.runs) {
     if (!r.thin) continue;
@@ -222,6 +390,8 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
   }
   P.runs_nrhs = -1;  // until the images are built
   STCHK(build_images(h, P, s));
+  if (flow) STCHK(build_flow(h, P, nrhs, sc, s));
+  STCHK(build_overlap(h, P, nrhs, sc, s));
   P.runs_nrhs = nrhs;
   P.runs_sched = sc;
   return SPTRSV_OK;
@@ -360,6 +530,7 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
     for (int32_t p = 0; p < n; ++p)
       if (htrp[(size_t)p + 1] > htrp[(size_t)p]) tpos.push_back(p);
     P.n_tpos = (int32_t)tpos.size();
+    P.h_tpos = tpos;
     // lanes per row of T: enough that a group's reads of a row coalesce, few
     // enough that most lanes hold an entry
     const double avg_t = P.n_tpos > 0 ? (double)P.nnz_t_off / (double)P.n_tpos : 0.0;
@@ -440,10 +611,74 @@ sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, 
 
 // One solve over the plan's runs, built for (nrhs, its schedule), with the
 // work vectors bp and xp (n * nrhs doubles each). Allocates nothing.
+// One run of the level chain (not the synchronisation-free executor).
+static sptrsv_status_t launch_run(sptrsv_ctx *h, Plan &P, const Run &r, int32_t nrhs, const ThinArgs &ta, double *bp,
+                                  double *xp, hipStream_t s) {
+  const sptrsv_schedule_t &sc = P.runs_sched;
+  int *err = h->d_err.p;
+  const int slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
+  if (r.thin) {
+    HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, ta, err, s));
+  } else if (r.flow) {
+    const FlowArgs fa{P.flow_pos.p + r.cp, P.flow_dptr.p + r.cp, P.flow_dlist.p, P.flow_flags.p + r.fl,
+                      P.flow_ctl.p, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, bp, xp};
+    HIPCHK(h, launch_flow_run(sc.wide_threads, sc.wide_grid, fa, r.nchunk, nrhs, err, wait_limit(h), s));
+  } else if (sc.wide_grid > 0) {
+    HIPCHK(h, launch_wide_run(sc.wide_grid, sc.wide_threads, r.l0, r.l1, P.level_ptr.p, nrhs, P.srp.p, P.sci.p,
+                              P.sva.p, P.sdg.p, bp, xp, P.wbar.p, err, wait_limit(h), s));
+  } else {
+    HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
+                                P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, bp, xp, err, s));
+  }
+  prof_end(h, slot, s);
+  return SPTRSV_OK;
+}
+
+// The solve with the transposes beside the level chain: the side stream
+// gathers segment k's tiles (and applies T to its rows) before the chain
+// reaches segment k, and scatters the tiles that end in segment k while later
+// segments run; the caller's stream waits for the side stream at the end.
+static sptrsv_status_t solve_overlapped(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb,
+                                        double *x, int64_t ldx, double *bp, double *xp, hipStream_t s) {
+  const int32_t nseg = (int32_t)P.seg_run.size() - 1;
+  hipStream_t side = h->side;
+  hipEvent_t *ev = h->ovl_ev.data();  // [0] fork, [1 + k] gathered, [1 + nseg + k] solved, [1 + 2 nseg] join
+  const int32_t *iperm = io_iperm(P);
+  HIPCHK(h, hipEventRecord(ev[0], s));
+  HIPCHK(h, hipStreamWaitEvent(side, ev[0], 0));
+  for (int32_t k = 0; k < nseg; ++k) {
+    HIPCHK(h, launch_gather_tiles(P.n, nrhs, b, ldb, iperm, P.g_tiles.p + P.g_off[(size_t)k],
+                                  P.g_off[(size_t)k + 1] - P.g_off[(size_t)k], bp, side));
+    const int32_t t0 = P.t_off[(size_t)k], t1 = P.t_off[(size_t)k + 1];
+    if (P.has_t && t1 > t0)
+      HIPCHK(h, launch_apply_t(t1 - t0, nrhs, P.t_lanes, P.tpos.p + t0, io_perm(P), P.trp.p, P.tci.p, P.tva.p, b,
+                               ldb, bp, side));
+    HIPCHK(h, hipEventRecord(ev[1 + k], side));
+  }
+  const ThinArgs ta = thin_args(P, bp, xp);
+  for (int32_t k = 0; k < nseg; ++k) {
+    HIPCHK(h, hipStreamWaitEvent(s, ev[1 + k], 0));
+    for (int32_t ri = P.seg_run[(size_t)k]; ri < P.seg_run[(size_t)k + 1]; ++ri)
+      STCHK(launch_run(h, P, P.runs[(size_t)ri], nrhs, ta, bp, xp, s));
+    const int32_t n_sc = P.s_off[(size_t)k + 1] - P.s_off[(size_t)k];
+    if (k + 1 < nseg) {
+      HIPCHK(h, hipEventRecord(ev[1 + nseg + k], s));
+      HIPCHK(h, hipStreamWaitEvent(side, ev[1 + nseg + k], 0));
+      HIPCHK(h, launch_scatter_tiles(P.n, nrhs, xp, iperm, P.s_tiles.p + P.s_off[(size_t)k], n_sc, x, ldx, side));
+    } else {
+      HIPCHK(h, launch_scatter_tiles(P.n, nrhs, xp, iperm, P.s_tiles.p + P.s_off[(size_t)k], n_sc, x, ldx, s));
+    }
+  }
+  HIPCHK(h, hipEventRecord(ev[1 + 2 * nseg], side));
+  HIPCHK(h, hipStreamWaitEvent(s, ev[1 + 2 * nseg], 0));
+  return SPTRSV_OK;
+}
+
 sptrsv_status_t solve_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, int64_t ldb, double *x,
                            int64_t ldx, double *bp, double *xp, hipStream_t s) {
   if (P.n == 0) return SPTRSV_OK;
   const sptrsv_schedule_t sc = P.runs_sched;
+  if (P.ovl && !h->prof) return solve_overlapped(h, P, nrhs, b, ldb, x, ldx, bp, xp, s);
   int *err = h->d_err.p;
   const double vec_bytes = 16.0 * (double)P.n * nrhs + 4.0 * P.n;
   int slot = prof_begin(h, 0, vec_bytes + (P.has_t ? 12.0 * (double)P.nnz_t_off + 4.0 * P.n : 0.0), s);
@@ -458,17 +693,7 @@ sptrsv_status_t solve_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
   const ThinArgs ta = thin_args(P, bp, xp);
   for (const Run &r : P.runs) {
     if (sc.mode == 3) break;
-    slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
-    if (r.thin) {
-      HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, ta, err, s));
-    } else if (sc.wide_grid > 0) {
-      HIPCHK(h, launch_wide_run(sc.wide_grid, sc.wide_threads, r.l0, r.l1, P.level_ptr.p, nrhs, P.srp.p, P.sci.p,
-                                P.sva.p, P.sdg.p, bp, xp, P.wbar.p, err, wait_limit(h), s));
-    } else {
-      HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
-                                  P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, bp, xp, err, s));
-    }
-    prof_end(h, slot, s);
+    STCHK(launch_run(h, P, r, nrhs, ta, bp, xp, s));
   }
   slot = prof_begin(h, 3, vec_bytes, s);
   HIPCHK(h, launch_scatter(P.n, nrhs, xp, io_iperm(P), x, ldx, s));
@@ -543,6 +768,14 @@ sptrsv_status_t sptrsv_create(sptrsv_handle_t *out) {
     delete h;
     return SPTRSV_ERR_HIP;
   }
+  // side stream and events of the overlapped transposes (default priority)
+  bool ok = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess;
+  h->ovl_ev.assign(2 * kMaxSegments + 2, nullptr);
+  for (auto &e : h->ovl_ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)sptrsv_destroy(h);
+    return SPTRSV_ERR_HIP;
+  }
   h->orig.sched = default_schedule();
   h->rew.sched = default_schedule();
   *out = h;
@@ -556,6 +789,9 @@ sptrsv_status_t sptrsv_destroy(sptrsv_handle_t h) {
     if (g.ge) (void)hipGraphExecDestroy(g.ge);
     if (g.g) (void)hipGraphDestroy(g.g);
   }
+  for (hipEvent_t e : h->ovl_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->side) (void)hipStreamDestroy(h->side);
   delete h;
   return SPTRSV_OK;
 }
@@ -664,32 +900,18 @@ sptrsv_status_t analyze_form(sptrsv_ctx *h, int32_t form, int32_t n, int32_t nnz
 }  // namespace
 
 // Longest-path membership of the rows of the handle's lower matrix (row
-// constraints of Sec. III.A): heights are the levels of J L^T J, whose row
-// n - 1 - r lists the dependents of row r, found by the same level kernel as
-// the plan's levels; oncrit[r] = level(r) + height(r) == nlev - 1.
+// constraints of Sec. III.A): heights by a sweep over the plan's levels from
+// the last to the first (launch_heights), then oncrit[r] = level(r) +
+// height(r) == nlev - 1.
 sptrsv_status_t crit_rows(sptrsv_ctx *h, const Plan &P, uint8_t *oncrit, hipStream_t s) {
-  const int32_t n = P.n, nnz = h->nnz;
+  const int32_t n = P.n;
   if (n == 0) return SPTRSV_OK;
-  DArr<int32_t> t_rp, t_ci, m_rp, m_ci, levr;
-  DArr<double> t_va, m_va;
-  HIPCHK(h, t_rp.alloc((size_t)n + 1));
-  HIPCHK(h, m_rp.alloc((size_t)n + 1));
-  HIPCHK(h, t_ci.alloc((size_t)nnz));
-  HIPCHK(h, m_ci.alloc((size_t)nnz));
-  HIPCHK(h, t_va.alloc((size_t)nnz));
-  HIPCHK(h, m_va.alloc((size_t)nnz));
-  HIPCHK(h, levr.alloc((size_t)n));
-  STCHK(transpose_csr(h, n, nnz, h->rp.p, h->ci.p, h->va.p, t_rp.p, t_ci.p, t_va.p, s));
-  HIPCHK(h, launch_rev_entries(n, nnz, t_rp.p, t_ci.p, t_va.p, m_rp.p, m_ci.p, m_va.p, s));
-  int32_t *aux = h->d_aux.p;  // [40] ticket, [41] error bits
-  HIPCHK(h, hipMemsetAsync(aux + 40, 0, 2 * sizeof(int32_t), s));
-  HIPCHK(h, hipMemsetAsync(levr.p, 0, sizeof(int32_t) * (size_t)n, s));
-  HIPCHK(h, launch_levels(n, m_rp.p, m_ci.p, levr.p, reinterpret_cast<unsigned *>(aux + 40), aux + 41, s));
-  int32_t bits = 0;
-  HIPCHK(h, hipMemcpyAsync(&bits, aux + 41, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  DArr<int32_t> hp;
+  HIPCHK(h, hp.alloc((size_t)n));
+  HIPCHK(h, hipMemsetAsync(hp.p, 0, sizeof(int32_t) * (size_t)n, s));
+  HIPCHK(h, launch_heights(n, P.nlev, P.level_ptr.p, P.h_level_ptr.data(), P.srp.p, P.sci.p, hp.p, s));
+  HIPCHK(h, launch_crit_from_heights(n, P.nlev, P.perm.p, P.row_level.p, hp.p, oncrit, s));
   HIPCHK(h, hipStreamSynchronize(s));
-  if (bits) return set_err(h, status_from_bits(bits), "critical-path heights failed (bits 0x%x)", bits);
-  HIPCHK(h, launch_crit_flags(n, P.nlev, P.row_level.p, levr.p, oncrit, s));
   return SPTRSV_OK;
 }
 
@@ -882,6 +1104,8 @@ sptrsv_status_t sptrsv_level_floor(sptrsv_handle_t h, int which, int32_t nrhs, i
           const int32_t nl = P->h_win[(size_t)(r.wi + w + 1)].x - W.x;
           ns += (double)nl * ((W.y & 1) ? c->thin_wave_level_ns : c->thin_level_ns);
         }
+      } else if (r.flow) {
+        ns += launch + (double)(r.l1 - r.l0 - 1) * c->flag_hop_ns;
       } else if (sc.wide_grid > 0) {
         ns += launch + (double)(r.l1 - r.l0 - 1) * c->grid_barrier_ns;
       } else {

@@ -32,6 +32,12 @@ std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
   }
   // the synchronisation-free executor at a few grid sizes (workgroups in flight)
   for (int g : {128, 256, 512}) c.push_back(sptrsv_schedule_t{3, 0, 512, 256, 1, g});
+  // dataflow runs of the wide levels (chunk sizes from the workgroup size), thin runs below
+  for (int wt : {128, 256, 512})
+    for (int thr : {0, 64, 1024}) {
+      if (thin_window_bytes(thr, 0, 1, nrhs) > thin_win_bytes()) continue;
+      c.push_back(sptrsv_schedule_t{4, thr, 1024, wt, 1, 0});
+    }
   // consecutive wide levels in one persistent launch (one lane per item)
   const int grids[] = {32, 256};
   for (int g : grids) {
@@ -100,7 +106,7 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
     P->runs_nrhs = -1;
     P->tuned.erase(nrhs);
     // launches that wait on the device get a limit tied to the best time so far
-    const bool waits = !batch && (cand.mode == 3 || cand.wide_grid > 0);
+    const bool waits = !batch && (cand.mode == 3 || cand.mode == 4 || cand.wide_grid > 0);
     h->wait_ticks = 0;
     if (waits && best < 1e29f) {
       const double lim_ms = std::max(2.0, 8.0 * (double)best);

@@ -81,6 +81,24 @@ struct Run {
   int32_t l0, l1;  // levels [l0, l1)
   bool thin;
   int32_t wi = 0, nw = 0;  // thin: its LDS windows in Plan::win [wi, wi + nw], entry wi + nw = end
+  bool flow = false;       // a dataflow run (schedule mode 4) of wide levels
+  int32_t nchunk = 0;      // flow: its chunks, chunk_pos [cp, cp + nchunk], dptr [cp, cp + nchunk], flags [fl, ...)
+  int32_t cp = 0, fl = 0;
+};
+
+// What a dataflow run reads (pointers already offset to the run's chunks):
+// chunk c holds positions [chunk_pos[c], chunk_pos[c + 1]) and waits for the
+// chunks dlist[dptr[c] .. dptr[c + 1]) of the same run; flags[c] holds the tag
+// of the launch that finished it; ctl = {ticket, workgroups done, epoch}.
+struct FlowArgs {
+  const int32_t *chunk_pos, *dptr, *dlist;
+  unsigned *flags, *ctl;
+  const int32_t *srp, *sci;
+  const double *sva, *sdg;
+  const int4 *ell_c;
+  const double2 *ell_v;
+  const double *bp;
+  double *xp;
 };
 
 // Everything needed to solve one lower-triangular matrix level by level:
@@ -141,6 +159,10 @@ struct Plan {
   std::vector<int32_t> t_off;          // [K+1] offsets of each segment's rows of T in tpos
   DArr<int32_t> g_tiles, s_tiles;
   std::vector<int32_t> h_tpos;         // host copy of tpos
+  // dataflow runs (mode 4): chunk tables of all flow runs, back to back
+  DArr<int32_t> flow_pos, flow_dptr, flow_dlist;
+  DArr<unsigned> flow_flags, flow_ctl;
+  std::vector<int32_t> h_srp, h_sci;   // host copy of the level-ordered pattern (built on first use)
   DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
   DArr<unsigned> tp;                   // [4] thin-run launches: epoch, progress, helper sink
   DArr<unsigned long long> sf_ticket;  // [1] ticket counter of the synchronisation-free solve
@@ -155,6 +177,13 @@ inline const int32_t *io_iperm(const Plan &P) { return P.rev_io ? P.iperm_io.p :
 struct BatchMat {
   int32_t n;
   int64_t row_off, nnz_off;
+};
+
+// A batched matrix with a level too wide for an LDS window at the cached
+// nrhs: solved level by level beside the persistent launch.
+struct BatchWide {
+  int32_t m = 0;
+  std::vector<Run> runs;
 };
 
 struct Graph {
@@ -195,6 +224,9 @@ struct sptrsv_ctx {
   DArr<int64_t> b_row_off_d;           // [nmat+1]
   DArr<unsigned> b_q;                  // persistent-launch queue counters
   std::vector<int32_t> b_h_mwin;       // window index of each matrix's run, for the cached nrhs
+  std::vector<int32_t> b_h_order;      // longest-processing-time order of all matrices
+  int32_t b_nq = 0;                    // matrices in the persistent queue (b_order) for the cached nrhs
+  std::vector<BatchWide> b_wide;       // the others
   int32_t b_win_nrhs = -1, b_win_wg = -1;
   std::vector<Graph> graphs;
   // live profile of solve launches
@@ -245,6 +277,12 @@ hipError_t launch_validate(int32_t n, int32_t nnz, const int32_t *rp, const int3
 hipError_t launch_levels(int32_t n, const int32_t *rp, const int32_t *ci, int32_t *lev1, unsigned *ticket, int *err,
                          hipStream_t s);
 hipError_t launch_max(const int32_t *a, int32_t n, int32_t *out, hipStream_t s);
+// Heights by position (hp zeroed by the caller) from the plan's level-ordered
+// copy, last level first; then the longest-path flags of the rows.
+hipError_t launch_heights(int32_t n, int32_t nlev, const int32_t *level_ptr, const int32_t *h_level_ptr,
+                          const int32_t *srp, const int32_t *sci, int32_t *hp, hipStream_t s);
+hipError_t launch_crit_from_heights(int32_t n, int32_t nlev, const int32_t *perm, const int32_t *row_level,
+                                    const int32_t *hp, uint8_t *oncrit, hipStream_t s);
 // exclusive scan of int64 values in place-compatible form: out may equal in
 size_t scan_scratch_elems(int64_t n);
 hipError_t launch_scan_i64(const long long *in, long long *out, int64_t n, long long *scratch, hipStream_t s);
@@ -366,10 +404,6 @@ hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const
                                int32_t *skipped, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
                                int32_t workers, int32_t *seg, unsigned long long *claim, char *big, int32_t bigC,
                                int32_t bigH, int32_t *out, hipStream_t s);
-// Critical-path flags of the rows of L from its levels and the 1-based levels
-// levr of J L^T J (the heights of L's rows, in reverse row order, plus one).
-hipError_t launch_crit_flags(int32_t n, int32_t nlev, const int32_t *row_level, const int32_t *levr,
-                             uint8_t *oncrit, hipStream_t s);
 hipError_t launch_row_counts(int32_t n, const int32_t *rp, const int32_t *target, const int32_t *cntL,
                              const int32_t *cntT, long long *cl, long long *ct, hipStream_t s);
 hipError_t launch_collect_moved(int32_t n, const int32_t *target, const int32_t *cntL, const int32_t *cntT,
@@ -448,6 +482,11 @@ sptrsv_status_t crit_rows(sptrsv_ctx *h, const Plan &P, uint8_t *oncrit, hipStre
 sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci,
                            const double *va, const int32_t *trp, const int32_t *tci, const double *tva,
                            hipStream_t s, bool rev_io = false);
+// Dataflow run (k_flow.hip): workgroups of wg threads (128, 256 or 512), grid
+// 0 = as many as are resident.
+int flow_items_per_thread();
+hipError_t launch_flow_run(int wg, int grid, const FlowArgs &a, int32_t nchunk, int32_t nrhs, int *err,
+                           unsigned long long tlimit, hipStream_t s);
 // Synchronisation-free solve of the whole plan (k_syncfree.hip): bp -> xp.
 // blocks: workgroups of 256 threads (0: 512).
 hipError_t launch_syncfree(int32_t n, int32_t nrhs, const int32_t *srp, const int32_t *sci, const double *sva,

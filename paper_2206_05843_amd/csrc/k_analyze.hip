@@ -78,6 +78,8 @@ __global__ void k_levels(int32_t n, const int32_t *__restrict__ rp, const int32_
     }
     unsigned spins = 0;
     while (__ballot(pend) != 0ull) {
+      const int32_t p_in = p;
+      const bool pend_in = pend;
       unsigned long long lm = __ballot(pend && e - p > kLongRow);
       while (lm != 0ull) {  // long rows, one at a time, by the whole wave
         const int src = __builtin_ctzll(lm);
@@ -118,11 +120,57 @@ __global__ void k_levels(int32_t n, const int32_t *__restrict__ rp, const int32_
           pend = false;
         }
       }
+      // a wave none of whose rows advanced pauses before it polls again, so
+      // that waiting waves do not flood the memory system with coherent loads
+      if (__ballot(p != p_in || pend != pend_in) == 0ull) __builtin_amdgcn_s_sleep(4);
       if ((++spins & 63u) == 0u && wall_clock64() - t0 > tlimit) {
         if (lane == 0) atomicOr(err, EB_TIMEOUT);
         return;
       }
     }
+  }
+}
+
+// Heights (longest path from a row to a row nothing depends on), by a sweep
+// over the levels from the last to the first on the level-ordered copy: when
+// a level is reached, every row that depends on one of its rows sits in a
+// later level and has already raised its height, so the level's heights are
+// final; each row then raises the height of every row it depends on. hp is by
+// position and starts at zero. A wide level is one launch (kernel boundaries
+// order the levels).
+__global__ void k_height_level(int32_t pb, int32_t pe, const int32_t *__restrict__ srp,
+                               const int32_t *__restrict__ sci, int32_t *hp) {
+  for (int64_t p = pb + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pe; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t h = hp[p] + 1;
+    for (int32_t q = srp[p]; q < srp[p + 1]; ++q) atomicMax(hp + sci[q], h);
+  }
+}
+
+// A run of consecutive narrow levels [l0, l1) in one workgroup, last level
+// first; the raises of a level complete (s_waitcnt) before the workgroup
+// barrier that starts the next one, and heights are read with device-scope
+// loads from where the atomics were performed.
+__global__ __launch_bounds__(1024) void k_height_run(int32_t l0, int32_t l1, const int32_t *__restrict__ level_ptr,
+                                                     const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
+                                                     int32_t *hp) {
+  for (int32_t l = l1 - 1; l >= l0; --l) {
+    const int32_t pb = level_ptr[l], pe = level_ptr[l + 1];
+    for (int32_t p = pb + (int32_t)threadIdx.x; p < pe; p += (int32_t)blockDim.x) {
+      const int32_t h = __hip_atomic_load(hp + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+      for (int32_t q = srp[p]; q < srp[p + 1]; ++q) atomicMax(hp + sci[q], h);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+}
+
+// Longest-path membership of every row: level + height = nlev - 1.
+__global__ void k_crit_from_heights(int32_t n, int32_t nlev, const int32_t *__restrict__ perm,
+                                    const int32_t *__restrict__ row_level, const int32_t *__restrict__ hp,
+                                    uint8_t *oncrit) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = perm[p];
+    oncrit[r] = (uint8_t)(row_level[r] + hp[p] == nlev - 1 ? 1 : 0);
   }
 }
 
@@ -369,8 +417,36 @@ hipError_t launch_levels(int32_t n, const int32_t *rp, const int32_t *ci, int32_
                          hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned long long limit = 100000000ull * 20;  // 20 s of the 100 MHz wall clock
-  hipLaunchKernelGGL(k_levels, dim3(grid_for(n, kBlock, 2048)), dim3(kBlock), 0, s, n, rp, ci, lev1, ticket, err,
+  hipLaunchKernelGGL(k_levels, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, s, n, rp, ci, lev1, ticket, err,
                      limit);
+  return hipGetLastError();
+}
+
+hipError_t launch_heights(int32_t n, int32_t nlev, const int32_t *level_ptr, const int32_t *h_level_ptr,
+                          const int32_t *srp, const int32_t *sci, int32_t *hp, hipStream_t s) {
+  constexpr int32_t kNarrow = 256;  // levels of at most this many rows share a one-workgroup launch
+  int32_t l = nlev - 1;
+  while (l >= 0) {
+    const int32_t rows = h_level_ptr[l + 1] - h_level_ptr[l];
+    if (rows > kNarrow) {
+      hipLaunchKernelGGL(k_height_level, dim3(grid_for(rows, kBlock, 4096)), dim3(kBlock), 0, s, h_level_ptr[l],
+                         h_level_ptr[l + 1], srp, sci, hp);
+      --l;
+      continue;
+    }
+    int32_t l0 = l;
+    while (l0 > 0 && h_level_ptr[l0] - h_level_ptr[l0 - 1] <= kNarrow) --l0;
+    hipLaunchKernelGGL(k_height_run, dim3(1), dim3(1024), 0, s, l0, l + 1, level_ptr, srp, sci, hp);
+    l = l0 - 1;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_crit_from_heights(int32_t n, int32_t nlev, const int32_t *perm, const int32_t *row_level,
+                                    const int32_t *hp, uint8_t *oncrit, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_crit_from_heights, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, n, nlev, perm,
+                     row_level, hp, oncrit);
   return hipGetLastError();
 }
 

@@ -740,20 +740,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_feat_rows(int32_t n, const int3
 // the rows of L in reverse order, so that levr[n - 1 - r] - 1 is the height of
 // r (longest path from r to a row nothing depends on).
 // oncrit[r] = level(r) + height(r) == nlev - 1.
-__global__ void k_crit_flags(int32_t n, int32_t nlev, const int32_t *__restrict__ row_level,
-                             const int32_t *__restrict__ levr, uint8_t *oncrit) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-    oncrit[r] = (uint8_t)(row_level[r] + levr[n - 1 - r] - 1 == nlev - 1 ? 1 : 0);
-}
 
 }  // namespace
 
-hipError_t launch_crit_flags(int32_t n, int32_t nlev, const int32_t *row_level, const int32_t *levr,
-                             uint8_t *oncrit, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_crit_flags, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, nlev, row_level, levr, oncrit);
-  return hipGetLastError();
-}
 
 size_t rewrite_big_ws_bytes(int32_t C, int32_t H) { return ws_core_bytes(C, H) + 48; }
 

@@ -32,6 +32,7 @@ EXPORTS = [
     "sptrsv_plan_load", "sptrsv_level_features", "sptrsv_mlp_forward", "sptrsv_mlp_backward", "sptrsv_mlp_adam",
     "sptrsv_mlp_mask", "sptrsv_profile", "sptrsv_level_times", "sptrsv_get_tune_info",
     "sptrsv_solve_noalloc", "sptrsv_measure_level_costs", "sptrsv_level_floor",
+    "sptrsv_get_info",
 ]
 
 
@@ -72,6 +73,11 @@ class TuneInfo(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Info(C.Structure):
+    _fields_ = [("form", C.c_int32), ("n", C.c_int32), ("nlev", C.c_int32), ("has_rewrite", C.c_int32),
+                ("nnz", C.c_int64)]
 
 
 class LevelCosts(C.Structure):
@@ -139,6 +145,7 @@ def lib():
         "sptrsv_get_tune_info": [vp, C.POINTER(TuneInfo)],
         "sptrsv_measure_level_costs": [vp, vp, C.POINTER(LevelCosts)],
         "sptrsv_level_floor": [vp, C.c_int, i32, i32, C.POINTER(LevelCosts), C.POINTER(dbl)],
+        "sptrsv_get_info": [vp, C.POINTER(Info), C.POINTER(RewriteStats)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -428,7 +435,14 @@ class Handle:
         self._check(self._L.sptrsv_plan_save(self._h, path.encode()))
 
     def plan_load(self, path: str):
+        """Replace this handle's analysis and rewrite by a plan file's."""
         self._check(self._L.sptrsv_plan_load(self._h, path.encode()))
+        info, st = Info(), RewriteStats()
+        self._check(self._L.sptrsv_get_info(self._h, C.byref(info), C.byref(st)))
+        self.n, self.nlev = info.n, info.nlev
+        self.rstats = st.as_dict() if info.has_rewrite else None
+        return {"form": info.form, "n": info.n, "nnz": info.nnz, "nlev": info.nlev,
+                "has_rewrite": bool(info.has_rewrite)}
 
     # ------------------------------------------------------------ learned policy
     def level_times(self, b, which=ORIGINAL):

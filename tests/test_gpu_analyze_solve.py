@@ -64,7 +64,8 @@ def test_level_stats_exact(handles, name):
 SCHEDS = [dict(mode=0), dict(mode=1), dict(mode=2), dict(mode=0, thin_rows=64, wg_threads=256),
           dict(mode=1, lanes_per_row=4), dict(mode=0, thin_rows=300, wg_threads=1024, lanes_per_row=8),
           dict(mode=1, wide_grid=256), dict(mode=0, thin_rows=64, wide_threads=512, wide_grid=1024),
-          dict(mode=1, wide_threads=64, wide_grid=3), dict(mode=3)]
+          dict(mode=1, wide_threads=64, wide_grid=3), dict(mode=3),
+          dict(mode=4), dict(mode=4, thin_rows=0, wide_threads=128), dict(mode=4, thin_rows=64, wide_threads=512, wide_grid=7)]
 
 
 @pytest.mark.parametrize("name", [n for n, _ in MATS])
@@ -230,7 +231,8 @@ def test_graph_replays(handles):
             del b2
 
 
-@pytest.mark.parametrize("sched", [dict(mode=1, wide_grid=256), dict(mode=0, thin_rows=16, wide_grid=64)])
+@pytest.mark.parametrize("sched", [dict(mode=1, wide_grid=256), dict(mode=0, thin_rows=16, wide_grid=64),
+                                   dict(mode=4, thin_rows=16), dict(mode=4, thin_rows=0, wide_threads=128)])
 def test_graph_replays_persistent_wide(handles, sched):
     # the barrier counters of a persistent wide run reset themselves at the end
     # of every launch, so graph replays and eager solves can alternate

@@ -342,7 +342,7 @@ def bench_analysis(args, np, torch, gen, oracle, sp):
         r["rewrite_naive_s"] = time.perf_counter() - t
         if pol is not None:
             t = time.perf_counter()
-            h.rewrite(sp.THIN_ROWS, 32, 4.0, 0, pol.mask_for(h))
+            policy.rewrite_learned(h, pol)
             torch.cuda.synchronize()
             r["rewrite_learned_s"] = time.perf_counter() - t
         out["runs"].append({k: round(v, 4) for k, v in r.items()})
@@ -432,15 +432,14 @@ def main():
     costs = probe.measure_level_costs()
     log(f"[bench] empty-level costs (ns): { {k: round(v, 1) for k, v in costs.items()} }")
 
-    def setup(name, mask_fn=None, rewrite=True):
+    def setup(name, rewrite_fn=None, rewrite=True):
         h = sp.Handle()
         t = time.perf_counter()
         nlev = h.analyze(rp, ci, va)
         which = sp.ORIGINAL
         info = dict(nlev=nlev, nnz=m.nnz, nnz_t=0)
         if rewrite:
-            mask = mask_fn(h) if mask_fn else None
-            st = h.rewrite(sp.THIN_ROWS, 32, 4.0, 0, mask)
+            st = rewrite_fn(h) if rewrite_fn else h.rewrite(sp.THIN_ROWS, 32, 4.0, 0)
             which = sp.REWRITTEN
             info.update(nlev=st["nlev_after"], nnz=st["nnz_Lp"], nnz_t=st["nnz_T"], rows_rewritten=st["rows_rewritten"],
                         nlev_before=st["nlev_before"], max_distance=st["max_distance"])
@@ -480,7 +479,7 @@ def main():
             from paper_2206_05843_amd import policy
             pol = policy.load_default()
             if pol is not None:
-                setup("learned", mask_fn=pol.mask_for)
+                setup("learned", rewrite_fn=lambda h: policy.rewrite_learned(h, pol))
         except (ImportError, sp.SptrsvError, FileNotFoundError) as e:
             log(f"[bench] learned policy unavailable: {e}")
 

@@ -169,6 +169,16 @@ typedef struct {
   int32_t scan_workers;         /* workgroups running the scan at once, 0..SPTRSV_MAX_SCAN_WORKERS:
                                    0 or 1 = one, from level 0 on; 2 = from both ends of the level
                                    order at once; more = half from each end. Same result for all. */
+  const int32_t *d_level_budget; /* optional device int32[nlev]: for the rows of source level l, a
+                                   positive entry replaces thin_threshold as the row budget of the
+                                   target (THIN_ROWS only): the learned policy's per-level action  */
+  const float *d_level_fill_cap; /* optional device float[nlev]: a positive entry replaces fill_cap
+                                   for the rows of source level l                                */
+  double self_check;            /* > 0: after rewriting, solve L x = L 1 with the original and the
+                                   rewritten system; if their solutions differ by more than this
+                                   (relative, max norm) or are not finite, the rewrite is replaced by
+                                   the original system (L' = L, T = I) and the stats say so (the
+                                   precision risk of long substitution chains, Sec. III.A). 0 = off */
 } sptrsv_rewrite_opts_t;
 
 typedef struct {
@@ -176,6 +186,8 @@ typedef struct {
   int64_t nnz_L, nnz_Lp, nnz_T, total_cost_before, total_cost_after;
   double avg_level_cost_before, avg_level_cost_after; /* Table I metrics (Sec. IV) */
   int32_t rows_skipped;         /* rows a row constraint left in place                           */
+  int32_t self_check_failed;    /* 1: the self-check failed and the original system is in use    */
+  double self_check_err;        /* the self-check's relative difference (0 when it did not run)  */
 } sptrsv_rewrite_stats_t;
 
 /* Errors: STATE (no analysis), ARG (bad opts), OVERFLOW (rewritten sizes beyond
@@ -442,6 +454,34 @@ sptrsv_status_t sptrsv_level_times(sptrsv_handle_t h, int which, int32_t nrhs, c
 /* mask[l] = (p[l] >= threshold) for l >= 1, mask[0] = 0: the rewrite mask of
  * the learned policy from probabilities (ASYNC). */
 sptrsv_status_t sptrsv_mlp_mask(const float *d_prob, int32_t nlev, float threshold, uint8_t *d_mask, hipStream_t s);
+/* Per-level finish times under the synchronisation-free executor (the
+ * schedule the autotuner picks on power-law matrices; with its tuned grid when
+ * the handle holds a tuned mode-3 schedule for this nrhs): one solve in which
+ * every item records the device wall clock when its value is written, then
+ * d_times[l] (device, nlev floats) = latest stamp of level l - earliest stamp
+ * of the solve, in ns. A level's share of the solve is the growth of the
+ * running maximum of these times across it. b as in sptrsv_solve (ld = n); the
+ * solution is discarded. Allocates 8 n nrhs bytes for the stamps.
+ * Synchronous. These times label levels when the policy is trained on the
+ * executor it will run under (Sec. III.A: a rewrite pays only where it shortens
+ * the solve). */
+sptrsv_status_t sptrsv_level_finish_times(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b,
+                                          float *d_times, hipStream_t s);
+
+/* Tiered actions of the learned policy (Sec. III.A: which rows to rewrite, and
+ * how far). Tier j (0 <= j < ntiers <= SPTRSV_MAX_TIERS) has a probability
+ * threshold (host array, ascending), a target budget in rows and a fill cap
+ * (host arrays; 0 = the rewrite's own value). A level l >= 1 takes the highest
+ * tier whose threshold p[l] reaches: d_mask[l] = 1, d_budget[l], d_cap[l] =
+ * that tier's; otherwise, and at level 0, d_mask[l] = 0 and d_budget[l] =
+ * d_cap[l] = 0. The three device arrays (nlev entries each) go to
+ * sptrsv_rewrite as mask, d_level_budget and d_level_fill_cap. ERR_ARG for
+ * thresholds out of order or NaN, a negative budget or cap, or ntiers out of
+ * range. ASYNC. */
+#define SPTRSV_MAX_TIERS 4
+sptrsv_status_t sptrsv_mlp_actions(const float *d_prob, int32_t nlev, int32_t ntiers, const float *thresholds,
+                                   const int32_t *budgets, const float *caps, uint8_t *d_mask, int32_t *d_budget,
+                                   float *d_cap, hipStream_t s);
 
 #ifdef __cplusplus
 }

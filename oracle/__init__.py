@@ -76,6 +76,10 @@ def _load():
                                    C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32, C.c_int64, C.c_int32,
                                    C.c_int32, i32p, C.POINTER(C.c_int32)]
     lib.orc_rewrite_rc.restype = C.c_void_p
+    lib.orc_rewrite_lv.argtypes = [C.c_int32, i32p, i32p, f64p, C.c_int32, i32p, i32p, i32p, C.c_int32,
+                                   C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_int32, C.c_int64, C.c_int32,
+                                   C.c_int32, C.c_void_p, C.c_void_p, i32p, C.POINTER(C.c_int32)]
+    lib.orc_rewrite_lv.restype = C.c_void_p
     lib.orc_rewrite_skipped.argtypes = [C.c_void_p]
     lib.orc_rewrite_skipped.restype = C.c_int32
     lib.orc_rewrite_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -223,12 +227,15 @@ NFEAT = 20  # per-level features of the learned policy (see orc_level_features)
 
 def rewrite(m, thin_metric: int = THIN_ROWS, thin_threshold: float = 32.0, fill_cap: float = 0.0,
             max_distance: int = 0, mask: np.ndarray | None = None, lv: Levels | None = None, max_indegree: int = 0,
-            max_spread: int = 0, critical_only: bool = False, both_ends: bool = False) -> Rewrite:
+            max_spread: int = 0, critical_only: bool = False, both_ends: bool = False,
+            level_budget: np.ndarray | None = None, level_cap: np.ndarray | None = None) -> Rewrite:
     """The scan and rewriting of Sec. II.B / Sec. III (oracle.c O5), with the
     row constraints of Sec. III.A: max_indegree (alpha), max_spread (beta) and
     critical_only; 0 / False disable them. both_ends takes the independent
     segments of the scan alternately from the first and the last level (the
-    result is the same)."""
+    result is the same). level_budget (int32 per level, rows, THIN_ROWS) and
+    level_cap (float32 per level) replace thin_threshold and fill_cap for the
+    rows of a source level where they are positive."""
     lib = _load()
     lv = lv or levels(m)
     rp, ci, v = _arrs(m)
@@ -238,10 +245,19 @@ def rewrite(m, thin_metric: int = THIN_ROWS, thin_threshold: float = 32.0, fill_
     if mask is not None:
         mk = np.ascontiguousarray(mask, np.uint8)
         assert mk.size >= lv.nlev
-    ctx = lib.orc_rewrite_rc(m.n, rp, ci, v, lv.nlev, lv.row_level, lv.level_ptr, lv.level_rows, thin_metric,
+    lb = lc = None
+    if level_budget is not None:
+        lb = np.ascontiguousarray(level_budget, np.int32)
+        assert lb.size >= lv.nlev
+    if level_cap is not None:
+        lc = np.ascontiguousarray(level_cap, np.float32)
+        assert lc.size >= lv.nlev
+    ctx = lib.orc_rewrite_lv(m.n, rp, ci, v, lv.nlev, lv.row_level, lv.level_ptr, lv.level_rows, thin_metric,
                              float(thin_threshold), float(fill_cap), int(max_distance),
                              mk.ctypes.data if mk is not None else None, int(max_indegree), int(max_spread),
-                             int(bool(critical_only)), int(bool(both_ends)), tgt, C.byref(st))
+                             int(bool(critical_only)), int(bool(both_ends)),
+                             lb.ctypes.data if lb is not None else None, lc.ctypes.data if lc is not None else None,
+                             tgt, C.byref(st))
     if not ctx:
         raise RuntimeError(f"oracle rewrite failed: {STATUS[st.value]}")
     try:

@@ -368,6 +368,11 @@ static int32_t alive_count(const subst_ws *s) {
  * DAG (level + height = nlev - 1, height = longest path to a row nothing
  * depends on). Zero disables a limit.
  *
+ * Per-level budgets and caps (the learned policy's actions, not in the
+ * paper): lv_budget[l] > 0 replaces the row budget W for the rows of source
+ * level l (THIN_ROWS: such a row is accepted while the target holds at most
+ * lv_budget[l] rows after it), and lv_cap[l] > 0 replaces fill_cap for them.
+ *
  * Outputs per row: tgt[r] = target level if the row was rewritten, else -1.
  * The rewritten rows are kept inside the returned context until collected.
  * ------------------------------------------------------------------------- */
@@ -416,11 +421,12 @@ static void sort_pairs(int32_t *col, double *val, int32_t len) {
   }
 }
 
-orc_rewrite_ctx *orc_rewrite_rc(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nlev,
+orc_rewrite_ctx *orc_rewrite_lv(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nlev,
                                 const int32_t *lev, const int32_t *level_ptr, const int32_t *level_rows,
                                 int32_t thin_metric, double thin_threshold, double fill_cap, int32_t max_distance,
                                 const uint8_t *mask, int32_t max_indeg, int64_t max_spread, int32_t crit_only,
-                                int32_t both_ends, int32_t *tgt, int32_t *status) {
+                                int32_t both_ends, const int32_t *lv_budget, const float *lv_cap, int32_t *tgt,
+                                int32_t *status) {
   *status = ORC_OK;
   int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nlev + 1));
   int64_t *nzl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nlev + 1));
@@ -509,12 +515,17 @@ orc_rewrite_ctx *orc_rewrite_rc(int32_t n, const int32_t *rp, const int32_t *ci,
         }
         int64_t nnz_new = (int64_t)alive_count(&s) + 1;
         int64_t nnz_old = rp[r + 1] - rp[r];
+        /* a source level may carry its own budget (rows, THIN_ROWS) and fill
+           cap; the budget bounds the target's size for the rows coming from
+           that level */
+        const double Wl = (thin_metric == 0 && lv_budget && lv_budget[l] > 0) ? (double)lv_budget[l] : W;
+        const double capl = (lv_cap && lv_cap[l] > 0.0f) ? (double)lv_cap[l] : fill_cap;
         int ok;
         if (thin_metric == 0)
-          ok = (double)(size_t_ + 1) <= W;
+          ok = (double)(size_t_ + 1) <= Wl;
         else
           ok = (double)(cost_t + 2 * nnz_new - 1) <= W;
-        if (fill_cap > 0.0) ok = ok && (double)nnz_new <= fill_cap * (double)nnz_old;
+        if (capl > 0.0) ok = ok && (double)nnz_new <= capl * (double)nnz_old;
         if (max_distance > 0) ok = ok && (l - t) <= max_distance;
         if (ok) {
           int skip = 0;
@@ -662,6 +673,15 @@ orc_rewrite_ctx *orc_rewrite_rc(int32_t n, const int32_t *rp, const int32_t *ci,
   free(s.tcol);
   free(s.tval);
   return ctx;
+}
+
+orc_rewrite_ctx *orc_rewrite_rc(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nlev,
+                                const int32_t *lev, const int32_t *level_ptr, const int32_t *level_rows,
+                                int32_t thin_metric, double thin_threshold, double fill_cap, int32_t max_distance,
+                                const uint8_t *mask, int32_t max_indeg, int64_t max_spread, int32_t crit_only,
+                                int32_t both_ends, int32_t *tgt, int32_t *status) {
+  return orc_rewrite_lv(n, rp, ci, v, nlev, lev, level_ptr, level_rows, thin_metric, thin_threshold, fill_cap,
+                        max_distance, mask, max_indeg, max_spread, crit_only, both_ends, NULL, NULL, tgt, status);
 }
 
 orc_rewrite_ctx *orc_rewrite(int32_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t nlev,

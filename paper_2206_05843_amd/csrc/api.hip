@@ -224,21 +224,28 @@ static sptrsv_status_t build_flow(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sp
     HIPCHK(h, hipStreamSynchronize(s));
   }
   const int32_t rpc = std::max(1, sc.wide_threads * flow_items_per_thread() / nrhs);
-  std::vector<int32_t> cpos, dptr, dlist, chunk_of((size_t)n, -1), stamp;
+  std::vector<int32_t> cpos, dptr, dlist, lcs, chunk_of((size_t)n, -1), stamp;
   int32_t nflags = 0;
   for (Run &r : P.runs) {
     if (!r.flow) continue;
     r.cp = (int32_t)cpos.size();
     r.fl = nflags;
+    r.lc = (int32_t)lcs.size();
+    r.max_chunks = 0;
     const int32_t pbeg = P.h_level_ptr[(size_t)r.l0], pend = P.h_level_ptr[(size_t)r.l1];
-    for (int32_t l = r.l0; l < r.l1; ++l)
+    for (int32_t l = r.l0; l < r.l1; ++l) {
+      const int32_t first = (int32_t)cpos.size() - r.cp;
+      lcs.push_back(first);
       for (int32_t p = P.h_level_ptr[(size_t)l]; p < P.h_level_ptr[(size_t)l + 1]; p += rpc) {
         const int32_t k = (int32_t)cpos.size() - r.cp;
         const int32_t pe = std::min(p + rpc, P.h_level_ptr[(size_t)l + 1]);
         for (int32_t q = p; q < pe; ++q) chunk_of[(size_t)q] = k;
         cpos.push_back(p);
       }
+      r.max_chunks = std::max(r.max_chunks, (int32_t)cpos.size() - r.cp - first);
+    }
     r.nchunk = (int32_t)cpos.size() - r.cp;
+    lcs.push_back(r.nchunk);
     cpos.push_back(pend);
     // dptr has one entry per chunk and a terminator, aligned with cpos (same offsets)
     dptr.resize(cpos.size() - 1 - r.nchunk);
@@ -263,6 +270,9 @@ static sptrsv_status_t build_flow(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sp
   HIPCHK(h, P.flow_pos.alloc(cpos.size()));
   HIPCHK(h, P.flow_dptr.alloc(dptr.size()));
   HIPCHK(h, P.flow_dlist.alloc(dlist.size()));
+  HIPCHK(h, P.flow_lc.alloc(std::max<size_t>(lcs.size(), 1)));
+  if (!lcs.empty())
+    HIPCHK(h, hipMemcpy(P.flow_lc.p, lcs.data(), sizeof(int32_t) * lcs.size(), hipMemcpyHostToDevice));
   HIPCHK(h, P.flow_flags.alloc((size_t)std::max(nflags, 1)));
   HIPCHK(h, P.flow_ctl.alloc(4));
   HIPCHK(h, hipMemcpy(P.flow_pos.p, cpos.data(), sizeof(int32_t) * cpos.size(), hipMemcpyHostToDevice));
@@ -620,9 +630,11 @@ static sptrsv_status_t launch_run(sptrsv_ctx *h, Plan &P, const Run &r, int32_t 
   if (r.thin) {
     HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, ta, err, s));
   } else if (r.flow) {
-    const FlowArgs fa{P.flow_pos.p + r.cp, P.flow_dptr.p + r.cp, P.flow_dlist.p, P.flow_flags.p + r.fl,
-                      P.flow_ctl.p, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, bp, xp};
-    HIPCHK(h, launch_flow_run(sc.wide_threads, sc.wide_grid, fa, r.nchunk, nrhs, err, wait_limit(h), s));
+    const FlowArgs fa{P.flow_pos.p + r.cp, P.flow_dptr.p + r.cp, P.flow_dlist.p, P.flow_lc.p + r.lc,
+                      P.flow_flags.p + r.fl, P.flow_ctl.p, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p,
+                      P.ell_v.p, bp, xp};
+    HIPCHK(h, launch_flow_run(sc.wide_threads, sc.wide_grid, fa, r.l1 - r.l0, r.max_chunks, nrhs, err,
+                              wait_limit(h), s));
   } else if (sc.wide_grid > 0) {
     HIPCHK(h, launch_wide_run(sc.wide_grid, sc.wide_threads, r.l0, r.l1, P.level_ptr.p, nrhs, P.srp.p, P.sci.p,
                               P.sva.p, P.sdg.p, bp, xp, P.wbar.p, err, wait_limit(h), s));

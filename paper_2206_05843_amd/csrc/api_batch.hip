@@ -64,22 +64,51 @@ int bit_width64(int64_t v) {
   return b;
 }
 
-// Per-matrix LDS windows for nrhs (cached).
+// Per-matrix LDS windows for nrhs (cached). A matrix whose levels all fit an
+// LDS window goes in the persistent queue; a matrix with a level too wide for
+// one is solved level by level instead (its narrow levels in thin runs, its
+// wide ones one device-wide launch each, as a single plan's mode-0 schedule).
 sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs, int32_t wg, hipStream_t s) {
   if (h->b_win_nrhs == nrhs && h->b_win_wg == wg) return SPTRSV_OK;
   Plan &P = h->bat;
   P.h_win.clear();
   h->b_h_mwin.assign((size_t)h->b_nmat + 1, 0);
+  h->b_wide.clear();
+  std::vector<char> fits((size_t)h->b_nmat, 1);
   for (int32_t m = 0; m < h->b_nmat; ++m) {
     const int32_t l0 = (int32_t)h->b_lvl_off[(size_t)m], l1 = (int32_t)h->b_lvl_off[(size_t)m + 1];
-    for (int32_t l = l0; l < l1; ++l)
-      if (!level_fits_window(P, l, nrhs))
-        return set_err(h, SPTRSV_ERR_ARG, "batch: level %d of matrix %d is too wide for one workgroup at nrhs=%d",
-                       l - l0, m, nrhs);
+    for (int32_t l = l0; l < l1 && fits[(size_t)m]; ++l)
+      if (!level_fits_window(P, l, nrhs)) fits[(size_t)m] = 0;
     h->b_h_mwin[(size_t)m] = (int32_t)P.h_win.size();
-    cut_windows(P, l0, l1, nrhs, wg, P.h_win);
+    if (fits[(size_t)m]) cut_windows(P, l0, l1, nrhs, wg, P.h_win);
   }
   h->b_h_mwin[(size_t)h->b_nmat] = (int32_t)P.h_win.size();
+  for (int32_t m = 0; m < h->b_nmat; ++m) {
+    if (fits[(size_t)m]) continue;
+    BatchWide bw;
+    bw.m = m;
+    const int32_t l0 = (int32_t)h->b_lvl_off[(size_t)m], l1 = (int32_t)h->b_lvl_off[(size_t)m + 1];
+    for (int32_t l = l0; l < l1; ++l) {
+      const bool thin = level_fits_window(P, l, nrhs);
+      if (!bw.runs.empty() && thin && bw.runs.back().thin && bw.runs.back().l1 == l)
+        bw.runs.back().l1 = l + 1;
+      else
+        bw.runs.push_back(Run{l, l + 1, thin});
+    }
+    for (Run &r : bw.runs)
+      if (r.thin) {
+        r.wi = (int32_t)P.h_win.size();
+        r.nw = cut_windows(P, r.l0, r.l1, nrhs, wg, P.h_win);
+      }
+    h->b_wide.push_back(std::move(bw));
+  }
+  // the persistent queue: the matrices that fit, in the analysis' order
+  std::vector<int32_t> q;
+  for (int32_t m : h->b_h_order)
+    if (fits[(size_t)m]) q.push_back(m);
+  h->b_nq = (int32_t)q.size();
+  HIPCHK(h, h->b_order.reserve(std::max<size_t>(q.size(), 1)));
+  if (!q.empty()) HIPCHK(h, hipMemcpy(h->b_order.p, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice));
   h->b_win_nrhs = -1;  // until the images are built
   STCHK(build_images(h, P, s));
   HIPCHK(h, h->b_mwin.alloc((size_t)h->b_nmat + 1));
@@ -87,6 +116,22 @@ sptrsv_status_t batch_windows(sptrsv_ctx *h, int32_t nrhs, int32_t wg, hipStream
                       hipMemcpyHostToDevice));
   h->b_win_nrhs = nrhs;
   h->b_win_wg = wg;
+  return SPTRSV_OK;
+}
+
+// The matrices taken out of the persistent launch, level by level.
+sptrsv_status_t batch_wide_solves(sptrsv_ctx *h, int32_t nrhs, int32_t wg, hipStream_t s) {
+  Plan &P = h->bat;
+  const sptrsv_schedule_t d = default_schedule();
+  for (const BatchWide &bw : h->b_wide)
+    for (const Run &r : bw.runs) {
+      if (r.thin)
+        HIPCHK(h, launch_thin_run(wg, P.win.p + r.wi, r.nw, nrhs, thin_args(P), h->d_err.p, s));
+      else
+        HIPCHK(h, launch_wide_level(d.wide_threads, 1, P.h_level_ptr[(size_t)r.l0], P.h_level_ptr[(size_t)r.l1], nrhs,
+                                    P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, P.bp.p, P.xp.p,
+                                    h->d_err.p, s));
+    }
   return SPTRSV_OK;
 }
 
@@ -251,8 +296,7 @@ sptrsv_status_t sptrsv_batch_analyze(sptrsv_handle_t h, int32_t nmat, const int3
     if (h->b_nlev[(size_t)a] != h->b_nlev[(size_t)b]) return h->b_nlev[(size_t)a] > h->b_nlev[(size_t)b];
     return h->b_n[(size_t)a] > h->b_n[(size_t)b];
   });
-  HIPCHK(h, h->b_order.alloc((size_t)nmat));
-  HIPCHK(h, hipMemcpy(h->b_order.p, order.data(), sizeof(int32_t) * (size_t)nmat, hipMemcpyHostToDevice));
+  h->b_h_order = order;
   HIPCHK(h, h->b_q.alloc(2));
   HIPCHK(h, hipMemset(h->b_q.p, 0, 2 * sizeof(unsigned)));
   P.ready = true;
@@ -273,9 +317,12 @@ sptrsv_status_t sptrsv_batch_solve(sptrsv_handle_t h, int32_t nrhs, const double
   const int32_t wg = effective_sched(P, nrhs).wg_threads;
   STCHK(batch_windows(h, nrhs, wg, s));
   HIPCHK(h, launch_batch_gather(P.n, nrhs, d_b_cat, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, P.bp.p, s));
-  const int32_t grid = std::min(h->b_nmat, batch_resident_blocks(wg));
-  HIPCHK(h, launch_batch_run(wg, h->b_nmat, grid, h->b_order.p, h->b_mwin.p, P.win.p, nrhs, thin_args(P), h->b_q.p,
-                             h->d_err.p, s));
+  if (h->b_nq > 0) {
+    const int32_t grid = std::min(h->b_nq, batch_resident_blocks(wg));
+    HIPCHK(h, launch_batch_run(wg, h->b_nq, grid, h->b_order.p, h->b_mwin.p, P.win.p, nrhs, thin_args(P), h->b_q.p,
+                               h->d_err.p, s));
+  }
+  STCHK(batch_wide_solves(h, nrhs, wg, s));
   HIPCHK(h, launch_batch_scatter(P.n, nrhs, P.xp.p, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, d_x_cat, s));
   return SPTRSV_OK;
 }
@@ -292,8 +339,9 @@ sptrsv_status_t sptrsv_batch_solve_looped(sptrsv_handle_t h, int32_t nrhs, const
   HIPCHK(h, launch_batch_gather(P.n, nrhs, d_b_cat, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, P.bp.p, s));
   for (int32_t m = 0; m < h->b_nmat; ++m) {
     const int32_t wi = h->b_h_mwin[(size_t)m], nw = h->b_h_mwin[(size_t)m + 1] - wi - 1;
-    HIPCHK(h, launch_thin_run(wg, P.win.p + wi, nw, nrhs, thin_args(P), h->d_err.p, s));
+    if (nw >= 1) HIPCHK(h, launch_thin_run(wg, P.win.p + wi, nw, nrhs, thin_args(P), h->d_err.p, s));
   }
+  STCHK(batch_wide_solves(h, nrhs, wg, s));
   HIPCHK(h, launch_batch_scatter(P.n, nrhs, P.xp.p, h->b_mat_of_row.p, h->b_row_off_d.p, P.iperm.p, d_x_cat, s));
   return SPTRSV_OK;
 }

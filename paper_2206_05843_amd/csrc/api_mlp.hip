@@ -89,6 +89,50 @@ sptrsv_status_t sptrsv_mlp_mask(const float *d_prob, int32_t nlev, float thresho
   return launch_mlp_mask(d_prob, nlev, threshold, d_mask, s) == hipSuccess ? SPTRSV_OK : SPTRSV_ERR_HIP;
 }
 
+sptrsv_status_t sptrsv_mlp_actions(const float *d_prob, int32_t nlev, int32_t ntiers, const float *thresholds,
+                                   const int32_t *budgets, const float *caps, uint8_t *d_mask, int32_t *d_budget,
+                                   float *d_cap, hipStream_t s) {
+  if (nlev < 0 || ntiers < 1 || ntiers > SPTRSV_MAX_TIERS || !thresholds || !budgets || !caps)
+    return SPTRSV_ERR_ARG;
+  if (nlev > 0 && (!d_prob || !d_mask || !d_budget || !d_cap)) return SPTRSV_ERR_ARG;
+  MlpTiers t{};
+  t.n = ntiers;
+  for (int j = 0; j < ntiers; ++j) {
+    if (!(thresholds[j] == thresholds[j]) || budgets[j] < 0 || !(caps[j] >= 0.0f)) return SPTRSV_ERR_ARG;
+    if (j > 0 && !(thresholds[j] >= thresholds[j - 1])) return SPTRSV_ERR_ARG;
+    t.thr[j] = thresholds[j];
+    t.budget[j] = budgets[j];
+    t.cap[j] = caps[j];
+  }
+  return launch_mlp_actions(d_prob, nlev, t, d_mask, d_budget, d_cap, s) == hipSuccess ? SPTRSV_OK : SPTRSV_ERR_HIP;
+}
+
+sptrsv_status_t sptrsv_level_finish_times(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b,
+                                          float *d_times, hipStream_t s) {
+  if (!h || !d_b || !d_times || nrhs < 1) return SPTRSV_ERR_ARG;
+  Plan *P = which == SPTRSV_ORIGINAL ? &h->orig : which == SPTRSV_REWRITTEN ? &h->rew : nullptr;
+  if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  if (!P->ready) return set_err(h, SPTRSV_ERR_STATE, "matrix not analysed/rewritten");
+  if (P->n == 0) return SPTRSV_OK;
+  int rate_khz = 100000;
+  (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, h->dev);
+  const float ns_per_tick = 1.0e6f / (float)(rate_khz > 0 ? rate_khz : 100000);
+  STCHK(ensure_work(h, *P, nrhs));
+  const auto tk = P->tuned.find(nrhs);
+  const int32_t blocks = tk != P->tuned.end() && tk->second.mode == 3 ? tk->second.wide_grid : 0;
+  DArr<unsigned long long> stamp, lmax;
+  HIPCHK(h, stamp.alloc((size_t)P->n * (size_t)nrhs));
+  HIPCHK(h, lmax.alloc((size_t)P->nlev + 1));
+  HIPCHK(h, hipMemsetAsync(lmax.p + P->nlev, 0xff, sizeof(unsigned long long), s));
+  STCHK(gather_b(h, *P, nrhs, d_b, P->n, P->bp.p, s));
+  HIPCHK(h, launch_syncfree(P->n, nrhs, P->srp.p, P->sci.p, P->sva.p, P->sdg.p, P->bp.p, P->xp.p, P->sf_ticket.p,
+                            h->d_err.p, blocks, wait_limit(h), s, stamp.p));
+  HIPCHK(h, launch_stamp_levels(P->nlev, nrhs, P->level_ptr.p, stamp.p, lmax.p, lmax.p + P->nlev, ns_per_tick,
+                                d_times, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  return sptrsv_check(h, s);
+}
+
 sptrsv_status_t sptrsv_level_times(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, float *d_times,
                                    hipStream_t s) {
   if (!h || !d_b || !d_times || nrhs < 1) return SPTRSV_ERR_ARG;

@@ -1,6 +1,7 @@
 // sptrsv_rewrite: decision scan, row pointers, rewritten rows, re-levelling.
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "common.h"
 
@@ -9,10 +10,76 @@ namespace {
 constexpr int32_t kScanBigC = 1 << 20;  // entries of the scan's global workspace
 constexpr int32_t kScanBigH = 1 << 21;
 
+__global__ void k_fill_value(double *a, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
 int32_t next_pow2(int64_t v) {
   int64_t p = 1;
   while (p < v) p <<= 1;
   return (int32_t)p;
+}
+
+// The rewrite's self-check: b = L 1 solved with the original and with the
+// rewritten system; a relative difference above tol, or a non-finite one,
+// replaces the rewrite by the original system (L' = L, T = I, no row moved),
+// so later rewritten solves give the original solve's result. A non-finite
+// value the check itself produced is not left latched on the device.
+sptrsv_status_t self_check(sptrsv_ctx *h, double tol, sptrsv_rewrite_stats_t &r, hipStream_t s) {
+  const int32_t n = h->n;
+  DArr<double> b, x0, x1;
+  HIPCHK(h, b.alloc((size_t)n));
+  HIPCHK(h, x0.alloc((size_t)n));
+  HIPCHK(h, x1.alloc((size_t)n));
+  int32_t bits_before = 0;
+  HIPCHK(h, hipMemcpyAsync(&bits_before, h->d_err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, launch_row_sums(n, h->rp.p, h->va.p, b.p, s));
+  STCHK(plan_solve(h, h->orig, 1, b.p, n, x0.p, n, s));
+  STCHK(plan_solve(h, h->rew, 1, b.p, n, x1.p, n, s));
+  unsigned long long *acc = reinterpret_cast<unsigned long long *>(h->d_aux.p + 256);
+  HIPCHK(h, hipMemsetAsync(acc, 0, 2 * sizeof(unsigned long long), s));
+  HIPCHK(h, launch_max_abs_diff(n, x0.p, x1.p, acc, s));
+  unsigned long long hv[2];
+  HIPCHK(h, hipMemcpyAsync(hv, acc, sizeof(hv), hipMemcpyDeviceToHost, s));
+  HIPCHK(h, hipMemcpyAsync(h->d_err.p, &bits_before, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipStreamSynchronize(s));
+  double d, m;
+  std::memcpy(&d, &hv[0], sizeof(double));
+  std::memcpy(&m, &hv[1], sizeof(double));
+  const double err = m > 0.0 ? d / m : d;
+  r.self_check_err = err;
+  r.self_check_failed = 0;
+  if (err <= tol) return SPTRSV_OK;
+  // fall back to the original system
+  const int64_t nnz = h->nnz;
+  r.self_check_failed = 1;
+  HIPCHK(h, h->lp_rp.alloc((size_t)n + 1));
+  HIPCHK(h, h->lp_ci.alloc((size_t)nnz));
+  HIPCHK(h, h->lp_va.alloc((size_t)nnz));
+  HIPCHK(h, hipMemcpyAsync(h->lp_rp.p, h->rp.p, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->lp_ci.p, h->ci.p, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, hipMemcpyAsync(h->lp_va.p, h->va.p, sizeof(double) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+  HIPCHK(h, h->t_rp.alloc((size_t)n + 1));
+  HIPCHK(h, h->t_ci.alloc((size_t)n));
+  HIPCHK(h, h->t_va.alloc((size_t)n));
+  HIPCHK(h, launch_iota(h->t_rp.p, n + 1, s));
+  HIPCHK(h, launch_iota(h->t_ci.p, n, s));
+  hipLaunchKernelGGL(k_fill_value, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, h->t_va.p, (int64_t)n, 1.0);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipMemsetAsync(h->target.p, 0xff, sizeof(int32_t) * (size_t)n, s));
+  STCHK(build_plan(h, h->rew, n, nnz, h->lp_rp.p, h->lp_ci.p, h->lp_va.p, h->t_rp.p, h->t_ci.p, h->t_va.p, s,
+                   h->orig.rev_io));
+  r.nlev_after = h->rew.nlev;
+  r.rows_rewritten = 0;
+  r.max_distance = 0;
+  r.target_steps = 0;
+  r.nnz_Lp = nnz;
+  r.nnz_T = n;
+  r.total_cost_after = h->rew.total_cost;
+  r.avg_level_cost_after = h->rew.avg_cost;
+  r.rows_skipped = 0;
+  return SPTRSV_OK;
 }
 
 }  // namespace
@@ -33,6 +100,7 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
   if (o->scan_workers < 0 || o->scan_workers > SPTRSV_MAX_SCAN_WORKERS)
     return set_err(h, SPTRSV_ERR_ARG, "rewrite: scan_workers %d outside [0, %d]", o->scan_workers,
                    SPTRSV_MAX_SCAN_WORKERS);
+  if (!(o->self_check >= 0.0)) return set_err(h, SPTRSV_ERR_ARG, "rewrite: self_check %g", o->self_check);
   if (o->max_indegree < 0 || o->max_spread < 0 || (o->critical_only != 0 && o->critical_only != 1))
     return set_err(h, SPTRSV_ERR_ARG, "rewrite: row constraints max_indegree %d max_spread %lld critical_only %d",
                    o->max_indegree, (long long)o->max_spread, o->critical_only);
@@ -73,8 +141,18 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
     DArr<unsigned long long> claim;
     HIPCHK(h, seg.alloc((size_t)nlev + 1));
     HIPCHK(h, claim.alloc(1));
+    // the largest per-level row budget bounds how many candidates a step evaluates at once
+    double Wmax = W;
+    if (o->d_level_budget) {
+      std::vector<int32_t> hb((size_t)nlev);
+      HIPCHK(h, hipMemcpyAsync(hb.data(), o->d_level_budget, sizeof(int32_t) * (size_t)nlev, hipMemcpyDeviceToHost,
+                               s));
+      HIPCHK(h, hipStreamSynchronize(s));
+      for (int32_t v : hb) Wmax = std::max(Wmax, (double)v);
+    }
     HIPCHK(h, launch_rewrite_scan(n, nlev, h->rp.p, h->ci.p, h->va.p, P.level_ptr.p, P.perm.p, P.lv_rows.p,
-                                  P.lv_cost.p, o->d_level_mask, o->thin_metric, W, o->fill_cap, o->max_distance,
+                                  P.lv_cost.p, o->d_level_mask, o->thin_metric, W, o->fill_cap, o->d_level_budget,
+                                  o->d_level_fill_cap, Wmax, o->max_distance,
                                   o->max_indegree, o->max_spread, o->critical_only ? oncrit.p : nullptr, aux + 32,
                                   cur.p, h->target.p, cntL.p, cntT.p, workers, seg.p, claim.p, h->rw_big.p, kScanBigC,
                                   kScanBigH, aux + 16, s));
@@ -160,6 +238,7 @@ sptrsv_status_t sptrsv_rewrite(sptrsv_handle_t h, const sptrsv_rewrite_opts_t *o
   r.avg_level_cost_before = P.avg_cost;
   r.avg_level_cost_after = h->rew.avg_cost;
   r.rows_skipped = held;
+  if (o->self_check > 0.0 && n > 0) STCHK(self_check(h, o->self_check, r, s));
   h->rstats = r;
   h->has_rewrite = true;
   if (st) *st = r;

@@ -84,14 +84,17 @@ struct Run {
   bool flow = false;       // a dataflow run (schedule mode 4) of wide levels
   int32_t nchunk = 0;      // flow: its chunks, chunk_pos [cp, cp + nchunk], dptr [cp, cp + nchunk], flags [fl, ...)
   int32_t cp = 0, fl = 0;
+  int32_t lc = 0;          // flow: level_chunk [lc, lc + l1 - l0]: first chunk of each level of the run
+  int32_t max_chunks = 0;  // flow: chunks of its widest level
 };
 
 // What a dataflow run reads (pointers already offset to the run's chunks):
 // chunk c holds positions [chunk_pos[c], chunk_pos[c + 1]) and waits for the
-// chunks dlist[dptr[c] .. dptr[c + 1]) of the same run; flags[c] holds the tag
-// of the launch that finished it; ctl = {ticket, workgroups done, epoch}.
+// chunks dlist[dptr[c] .. dptr[c + 1]) of the same run; level l of the run
+// holds chunks [level_chunk[l], level_chunk[l + 1]); flags[c] holds the tag of
+// the launch that finished it; ctl = {unused, workgroups done, epoch}.
 struct FlowArgs {
-  const int32_t *chunk_pos, *dptr, *dlist;
+  const int32_t *chunk_pos, *dptr, *dlist, *level_chunk;
   unsigned *flags, *ctl;
   const int32_t *srp, *sci;
   const double *sva, *sdg;
@@ -160,7 +163,7 @@ struct Plan {
   DArr<int32_t> g_tiles, s_tiles;
   std::vector<int32_t> h_tpos;         // host copy of tpos
   // dataflow runs (mode 4): chunk tables of all flow runs, back to back
-  DArr<int32_t> flow_pos, flow_dptr, flow_dlist;
+  DArr<int32_t> flow_pos, flow_dptr, flow_dlist, flow_lc;
   DArr<unsigned> flow_flags, flow_ctl;
   std::vector<int32_t> h_srp, h_sci;   // host copy of the level-ordered pattern (built on first use)
   DArr<double> bp, xp;                 // [n * nrhs] permuted, RHS-interleaved
@@ -369,6 +372,11 @@ hipError_t launch_gather_tiles(int32_t n, int32_t nrhs, const double *b, int64_t
                                const int32_t *tiles, int32_t ntiles, double *bp, hipStream_t s);
 hipError_t launch_scatter_tiles(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm,
                                 const int32_t *tiles, int32_t ntiles, double *x, int64_t ldx, hipStream_t s);
+// Row sums b = A 1, and out[0..1] = bits of max |x1 - x0| and max |x0|
+// (out zeroed by the caller; NaN counts as infinite).
+hipError_t launch_row_sums(int32_t n, const int32_t *rp, const double *va, double *b, hipStream_t s);
+hipError_t launch_max_abs_diff(int32_t n, const double *x0, const double *x1, unsigned long long *out,
+                               hipStream_t s);
 // First and last position of the rows of every caller-row tile of 64 rows.
 hipError_t launch_tile_span(int32_t n, const int32_t *iperm, int32_t *first, int32_t *last, hipStream_t s);
 int thin_win_bytes();
@@ -400,6 +408,7 @@ int32_t rewrite_waves_per_block();
 hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const int32_t *ci, const double *va,
                                const int32_t *level_ptr, const int32_t *level_rows, const int64_t *lv_rows,
                                const int64_t *lv_cost, const uint8_t *mask, int32_t metric, double W, double fill_cap,
+                               const int32_t *lv_budget, const float *lv_cap, double Wmax,
                                int32_t max_dist, int32_t max_indeg, int64_t max_spread, const uint8_t *oncrit,
                                int32_t *skipped, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
                                int32_t workers, int32_t *seg, unsigned long long *claim, char *big, int32_t bigC,
@@ -427,6 +436,14 @@ hipError_t launch_mlp_backward(const float *P, const float *feat, const float *n
 hipError_t launch_mlp_adam(float *P, const float *g, float *m, float *v, float lr, float c1, float c2,
                            hipStream_t s);
 hipError_t launch_mlp_mask(const float *prob, int32_t nlev, float thr, uint8_t *mask, hipStream_t s);
+struct MlpTiers {
+  int32_t n;
+  float thr[4];
+  int32_t budget[4];
+  float cap[4];
+};
+hipError_t launch_mlp_actions(const float *prob, int32_t nlev, const MlpTiers &t, uint8_t *mask, int32_t *budget,
+                              float *cap, hipStream_t s);
 // Per-level sums behind the learned policy's level features, filled row by row:
 // hist[l * kFeatHist + b] holds the off-diagonal count bins (b < 6) and the
 // counts of rows passing the row-constraint tests (6: fewer than 4 dependencies
@@ -485,13 +502,20 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
 // Dataflow run (k_flow.hip): workgroups of wg threads (128, 256 or 512), grid
 // 0 = as many as are resident.
 int flow_items_per_thread();
-hipError_t launch_flow_run(int wg, int grid, const FlowArgs &a, int32_t nchunk, int32_t nrhs, int *err,
-                           unsigned long long tlimit, hipStream_t s);
+hipError_t launch_flow_run(int wg, int grid, const FlowArgs &a, int32_t nlev, int32_t max_chunks, int32_t nrhs,
+                           int *err, unsigned long long tlimit, hipStream_t s);
 // Synchronisation-free solve of the whole plan (k_syncfree.hip): bp -> xp.
-// blocks: workgroups of 256 threads (0: 512).
+// blocks: workgroups of 256 threads (0: 512). stamp (optional, n * nrhs):
+// the device wall clock when each item's value was written.
 hipError_t launch_syncfree(int32_t n, int32_t nrhs, const int32_t *srp, const int32_t *sci, const double *sva,
                            const double *sdg, const double *bp, double *xp, unsigned long long *ticket, int *err,
-                           int32_t blocks, unsigned long long tlimit, hipStream_t s);
+                           int32_t blocks, unsigned long long tlimit, hipStream_t s,
+                           unsigned long long *stamp = nullptr);
+// times[l] = (latest stamp of level l - earliest stamp of all) * ns_per_tick;
+// lmax has nlev entries, *gmin must hold ~0 before the call.
+hipError_t launch_stamp_levels(int32_t nlev, int32_t nrhs, const int32_t *level_ptr, const unsigned long long *stamp,
+                               unsigned long long *lmax, unsigned long long *gmin, float ns_per_tick, float *times,
+                               hipStream_t s);
 // Triangular forms (k_form.hip) ---------------------------------------------------
 hipError_t launch_rev_entries(int32_t n, int32_t nnz, const int32_t *rp, const int32_t *ci, const double *va,
                               int32_t *orp, int32_t *oci, double *ova, hipStream_t s);

@@ -168,6 +168,23 @@ __global__ void k_mlp_mask(const float *__restrict__ prob, int32_t nlev, float t
     mask[i] = (i > 0 && prob[i] >= thr) ? 1 : 0;
 }
 
+// Tiered actions: a level takes the highest tier whose threshold its
+// probability reaches (thresholds ascending) and becomes a source with that
+// tier's target budget and fill cap; below the first threshold, and at level
+// 0, it is not a source (budget and cap 0: the rewrite's own values).
+__global__ void k_mlp_actions(const float *__restrict__ prob, int32_t nlev, MlpTiers t, uint8_t *mask,
+                              int32_t *budget, float *cap) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nlev; i += gridDim.x * blockDim.x) {
+    int k = -1;
+    if (i > 0)
+      for (int j = 0; j < t.n; ++j)
+        if (prob[i] >= t.thr[j]) k = j;
+    mask[i] = k >= 0 ? 1 : 0;
+    budget[i] = k >= 0 ? t.budget[k] : 0;
+    cap[i] = k >= 0 ? t.cap[k] : 0.0f;
+  }
+}
+
 // The 20 features of each level (see sptrsv_level_features), from the level
 // statistics and the per-row sums of the distance-1 rewrite.
 __global__ void k_feat_finalize(int32_t nlev, const int64_t *__restrict__ rows, const int64_t *__restrict__ nnz,
@@ -228,6 +245,14 @@ hipError_t launch_mlp_adam(float *P, const float *g, float *m, float *v, float l
 hipError_t launch_mlp_mask(const float *prob, int32_t nlev, float thr, uint8_t *mask, hipStream_t s) {
   if (nlev <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mlp_mask, dim3((nlev + 255) / 256), dim3(256), 0, s, prob, nlev, thr, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_actions(const float *prob, int32_t nlev, const MlpTiers &t, uint8_t *mask, int32_t *budget,
+                              float *cap, hipStream_t s) {
+  if (nlev <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_actions, dim3((nlev + 255) / 256 > 1024 ? 1024 : (nlev + 255) / 256), dim3(256), 0, s,
+                     prob, nlev, t, mask, budget, cap);
   return hipGetLastError();
 }
 

@@ -70,7 +70,13 @@ __device__ __forceinline__ long long wave_max_ll(long long v) {
 
 // Find column k or insert it (keys inserted concurrently by the lanes of a
 // wave are distinct). Returns the entry index, or -1 if the workspace is full.
+// A failed insert still takes its entry count (cnt becomes larger than C), so
+// once one insert has failed every later call returns at once: the row has
+// overflowed this workspace and is evaluated again in a larger one, and
+// probing a table filled by failed inserts would cost H steps per call.
 __device__ __forceinline__ int32_t ws_find_or_insert(Ws &w, int32_t k, bool &isnew) {
+  isnew = true;
+  if (__hip_atomic_load(w.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > w.C) return -1;
   uint32_t hh = ((uint32_t)k * 2654435761u) & (uint32_t)(w.H - 1);
   for (int32_t probe = 0; probe < w.H; ++probe) {
     const int32_t prev = atomicCAS(w.hkey + hh, -1, k);
@@ -113,22 +119,26 @@ __device__ int subst_row(Ws &w, int32_t r, int32_t t, const int32_t *__restrict_
   int overflow = 0;
   {
     const int32_t b = rp[r], e = rp[r + 1] - 1;
-    for (int32_t p = b + lane; p < e; p += 64) {
-      const int32_t k = ci[p];
-      bool isnew;
-      const int32_t s = ws_find_or_insert(w, k, isnew);
-      if (s < 0) {
-        overflow = 1;
-        continue;
+    for (int32_t p0 = b; p0 < e; p0 += 64) {  // the wave stops at the first overflow
+      const int32_t p = p0 + lane;
+      if (p < e) {
+        const int32_t k = ci[p];
+        bool isnew;
+        const int32_t s = ws_find_or_insert(w, k, isnew);
+        if (s < 0) {
+          overflow = 1;
+        } else {
+          const bool inB = cur[k] >= t;
+          w.col[s] = k;
+          w.val[s] = va[p];
+          w.st[s] = inB ? 1 : 0;
+          if (inB)
+            w.pend[atomicAdd(w.np, 1)] = s;
+          else
+            atomicAdd(w.na, 1);
+        }
       }
-      const bool inB = cur[k] >= t;
-      w.col[s] = k;
-      w.val[s] = va[p];
-      w.st[s] = inB ? 1 : 0;
-      if (inB)
-        w.pend[atomicAdd(w.np, 1)] = s;
-      else
-        atomicAdd(w.na, 1);
+      if (__ballot(overflow) != 0ull) break;
     }
   }
   wave_sync();
@@ -158,28 +168,32 @@ __device__ int subst_row(Ws &w, int32_t r, int32_t t, const int32_t *__restrict_
     wave_sync();
     ++nT;
     const int32_t jb = rp[j], je = rp[j + 1] - 1;
-    for (int32_t p = jb + lane; p < je; p += 64) {
-      const int32_t k = ci[p];
-      const double v = va[p];
-      bool isnew;
-      const int32_t s = ws_find_or_insert(w, k, isnew);
-      if (s < 0) {
-        overflow = 1;
-        continue;
+    for (int32_t p0 = jb; p0 < je; p0 += 64) {  // the wave stops at the first overflow
+      const int32_t p = p0 + lane;
+      if (p < je) {
+        const int32_t k = ci[p];
+        const double v = va[p];
+        bool isnew;
+        const int32_t s = ws_find_or_insert(w, k, isnew);
+        if (s < 0) {
+          overflow = 1;
+        } else {
+          const double prod = m * v;
+          if (isnew) {
+            const bool inB = cur[k] >= t;
+            w.col[s] = k;
+            w.val[s] = 0.0 - prod;
+            w.st[s] = inB ? 1 : 0;
+            if (inB)
+              w.pend[atomicAdd(w.np, 1)] = s;
+            else
+              atomicAdd(w.na, 1);
+          } else {
+            w.val[s] = w.val[s] - prod;
+          }
+        }
       }
-      const double prod = m * v;
-      if (isnew) {
-        const bool inB = cur[k] >= t;
-        w.col[s] = k;
-        w.val[s] = 0.0 - prod;
-        w.st[s] = inB ? 1 : 0;
-        if (inB)
-          w.pend[atomicAdd(w.np, 1)] = s;
-        else
-          atomicAdd(w.na, 1);
-      } else {
-        w.val[s] = w.val[s] - prod;
-      }
+      if (__ballot(overflow) != 0ull) break;
     }
     wave_sync();
     if (__ballot(overflow) != 0ull) return SUB_OVERFLOW;
@@ -255,6 +269,9 @@ struct ScanArgs {
   const uint8_t *mask;
   int32_t metric;
   double W, fill_cap;
+  const int32_t *lv_budget;  // optional per source level: row budget (THIN_ROWS), <= 0 = W
+  const float *lv_cap;       // optional per source level: fill cap, <= 0 = fill_cap
+  double Wmax;               // the largest row budget of any level (THIN_ROWS)
   int32_t max_dist;
   // row constraints (Sec. III.A): alpha, beta, and critical-path membership
   // of the original rows (null: no such constraint)
@@ -270,6 +287,15 @@ struct ScanArgs {
   int32_t bigC, bigH;
   int32_t *out;     // [0] rows moved [1] max distance [2] target steps [3] error bits
 };
+
+// Row budget (THIN_ROWS) and fill cap of the rows of source level lvl: the
+// level's own where one is given and positive, else the options'.
+__device__ __forceinline__ double level_budget(const ScanArgs &a, int32_t lvl) {
+  return a.lv_budget && a.lv_budget[lvl] > 0 ? (double)a.lv_budget[lvl] : a.W;
+}
+__device__ __forceinline__ double level_cap(const ScanArgs &a, int32_t lvl) {
+  return a.lv_cap && a.lv_cap[lvl] > 0.0f ? (double)a.lv_cap[lvl] : a.fill_cap;
+}
 
 // Whether a row constraint leaves candidate r (already within budget, fill
 // and distance) where it is: na A columns spanning [lo, hi].
@@ -378,7 +404,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
       for (;;) {
         int32_t limit = kWaves;
         if (a.metric == SPTRSV_THIN_ROWS) {
-          const double room = a.W - (double)size;  // rows the target can still take
+          const double room = a.Wmax - (double)size;  // rows the target can still take (at most)
           if (room < (double)kWaves) limit = room < 0.0 ? 1 : (int32_t)room + 1;
         }
         while (l < seg_end && nc < limit) {
@@ -426,9 +452,10 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
       const int32_t r = c_row[wave];
       const int64_t nnz_old = a.rp[r + 1] - a.rp[r];
       int64_t capA = s_capA_cost;
-      if (a.fill_cap > 0.0) {
+      const double capl = level_cap(a, c_lvl[wave]);
+      if (capl > 0.0) {
         // nA + 1 <= fill_cap * nnz_old
-        const double lim = a.fill_cap * (double)nnz_old - 1.0;
+        const double lim = capl * (double)nnz_old - 1.0;
         const int64_t c2 = lim < 0.0 ? -1 : (int64_t)lim;
         capA = c2 < capA ? c2 : capA;
       }
@@ -463,10 +490,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
         bool ok = c_st[i] == SUB_OK;
         if (ok) {
           if (a.metric == SPTRSV_THIN_ROWS)
-            ok = (double)(size + 1) <= a.W;
+            ok = (double)(size + 1) <= level_budget(a, lvl);
           else
             ok = (double)(cost + 2 * nnz_new - 1) <= a.W;
-          if (a.fill_cap > 0.0) ok = ok && (double)nnz_new <= a.fill_cap * (double)nnz_old;
+          const double capl = level_cap(a, lvl);
+          if (capl > 0.0) ok = ok && (double)nnz_new <= capl * (double)nnz_old;
           if (a.max_dist > 0) ok = ok && (lvl - t) <= a.max_dist;
         }
         if (ok && row_held(a, r, c_na[i], c_lo[i], c_hi[i])) {
@@ -526,10 +554,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_rewrite_scan(ScanArgs a) {
           const int64_t nnz_new = (int64_t)c_na[0] + 1;
           bool ok;
           if (a.metric == SPTRSV_THIN_ROWS)
-            ok = (double)(size + 1) <= a.W;
+            ok = (double)(size + 1) <= level_budget(a, lvl);
           else
             ok = (double)(cost + 2 * nnz_new - 1) <= a.W;
-          if (a.fill_cap > 0.0) ok = ok && (double)nnz_new <= a.fill_cap * (double)nnz_old;
+          const double capl = level_cap(a, lvl);
+          if (capl > 0.0) ok = ok && (double)nnz_new <= capl * (double)nnz_old;
           if (a.max_dist > 0) ok = ok && (lvl - t) <= a.max_dist;
           const bool keep = ok && row_held(a, r, c_na[0], c_lo[0], c_hi[0]);
           if (keep) ++held;
@@ -749,6 +778,7 @@ size_t rewrite_big_ws_bytes(int32_t C, int32_t H) { return ws_core_bytes(C, H) +
 hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const int32_t *ci, const double *va,
                                const int32_t *level_ptr, const int32_t *level_rows, const int64_t *lv_rows,
                                const int64_t *lv_cost, const uint8_t *mask, int32_t metric, double W, double fill_cap,
+                               const int32_t *lv_budget, const float *lv_cap, double Wmax,
                                int32_t max_dist, int32_t max_indeg, int64_t max_spread, const uint8_t *oncrit,
                                int32_t *skipped, int32_t *cur, int32_t *target, int32_t *cntL, int32_t *cntT,
                                int32_t workers, int32_t *seg, unsigned long long *claim, char *big, int32_t bigC,
@@ -768,6 +798,9 @@ hipError_t launch_rewrite_scan(int32_t n, int32_t nlev, const int32_t *rp, const
   a.metric = metric;
   a.W = W;
   a.fill_cap = fill_cap;
+  a.lv_budget = lv_budget;
+  a.lv_cap = lv_cap;
+  a.Wmax = Wmax > W ? Wmax : W;
   a.max_dist = max_dist;
   a.max_indeg = max_indeg;
   a.max_spread = max_spread;

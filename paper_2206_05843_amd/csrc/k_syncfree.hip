@@ -8,7 +8,8 @@
 // so they were claimed earlier by a running wave and every wait ends. x starts
 // as a signalling-NaN pattern that arithmetic never produces (division quiets
 // every NaN), so one device-coherent 64-bit load returns both "done" and the
-// value. A lane requests its next four dependencies' values at once and takes
+// value (a plain load is tried first and trusted when it is not the pending
+// pattern). A lane requests its next four dependencies' values at once and takes
 // the ready ones in column order, so the sum keeps the row's order. A wave
 // none of whose lanes moved in an iteration sleeps briefly before it polls
 // again, and the launch is kept to a few thousand waves: the waiting lanes'
@@ -30,12 +31,12 @@ __global__ void k_sf_init(int64_t total, unsigned long long *xb, unsigned long l
   if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0ull;
 }
 
-template <bool kOne>
+template <bool kOne, bool kStamp>
 __global__ __launch_bounds__(kBlock) void k_sf_solve(int32_t n, int32_t nrhs, const int32_t *__restrict__ srp,
                                                      const int32_t *__restrict__ sci, const double *__restrict__ sva,
                                                      const double *__restrict__ sdg, const double *__restrict__ bp,
                                                      double *xp, unsigned long long *ticket, int *err,
-                                                     unsigned long long tlimit) {
+                                                     unsigned long long tlimit, unsigned long long *stamp) {
   const int lane = threadIdx.x & 63;
   const int32_t nr = kOne ? 1 : nrhs;
   const int64_t total = (int64_t)n * nr;
@@ -76,9 +77,17 @@ __global__ __launch_bounds__(kBlock) void k_sf_solve(int32_t n, int32_t nrhs, co
             k[j] = sci[qq];
             w[j] = sva[qq];
           }
+          // a plain (cached) load first: it returns either the pending
+          // pattern or the final value, since caches hold no line of x from
+          // before this launch (the fill kernel ran in between) and every
+          // value is written once; only what still reads as pending is
+          // fetched again past the caches
+#pragma unroll
+          for (int j = 0; j < kDeps; ++j) v[j] = xb[(int64_t)k[j] * nr + c];
 #pragma unroll
           for (int j = 0; j < kDeps; ++j)
-            v[j] = __hip_atomic_load(xb + (int64_t)k[j] * nr + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v[j] == kPending)
+              v[j] = __hip_atomic_load(xb + (int64_t)k[j] * nr + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           int32_t done = 0;
 #pragma unroll
           for (int j = 0; j < kDeps; ++j) {
@@ -96,6 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_sf_solve(int32_t n, int32_t nrhs, co
           if (!isfinite(x)) bits |= EB_NONFINITE;
           __hip_atomic_store(xb + it, (unsigned long long)__double_as_longlong(x), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
+          if (kStamp) stamp[it] = wall_clock64();  // when this item's value was written
           pend = false;
           moved = true;
         }
@@ -111,21 +121,82 @@ __global__ __launch_bounds__(kBlock) void k_sf_solve(int32_t n, int32_t nrhs, co
   if (bits) atomicOr(err, bits);
 }
 
+// Per-level finish times of a stamped solve: the latest stamp of each level's
+// items and the earliest stamp of all (atomicMin), then the levels' latest
+// stamps relative to that earliest one, in ns.
+__global__ void k_stamp_level_max(int32_t nlev, int32_t nrhs, const int32_t *__restrict__ level_ptr,
+                                  const unsigned long long *__restrict__ stamp, unsigned long long *lmax,
+                                  unsigned long long *gmin) {
+  __shared__ unsigned long long s_hi[4], s_lo[4];
+  for (int32_t l = blockIdx.x; l < nlev; l += gridDim.x) {
+    const int64_t i0 = (int64_t)level_ptr[l] * nrhs, i1 = (int64_t)level_ptr[l + 1] * nrhs;
+    unsigned long long hi = 0ull, lo = ~0ull;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      const unsigned long long t = stamp[i];
+      hi = t > hi ? t : hi;
+      lo = t < lo ? t : lo;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long h2 = __shfl_xor(hi, o, 64), l2 = __shfl_xor(lo, o, 64);
+      hi = h2 > hi ? h2 : hi;
+      lo = l2 < lo ? l2 : lo;
+    }
+    if ((threadIdx.x & 63) == 0) {
+      s_hi[threadIdx.x >> 6] = hi;
+      s_lo[threadIdx.x >> 6] = lo;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+        hi = s_hi[w] > hi ? s_hi[w] : hi;
+        lo = s_lo[w] < lo ? s_lo[w] : lo;
+      }
+      lmax[l] = hi;
+      atomicMin(gmin, lo);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_stamp_finish(int32_t nlev, const unsigned long long *__restrict__ lmax,
+                               const unsigned long long *__restrict__ gmin, float ns_per_tick, float *times) {
+  for (int32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < nlev; l += gridDim.x * blockDim.x)
+    times[l] = (float)(lmax[l] - *gmin) * ns_per_tick;
+}
+
 }  // namespace
 
 hipError_t launch_syncfree(int32_t n, int32_t nrhs, const int32_t *srp, const int32_t *sci, const double *sva,
                            const double *sdg, const double *bp, double *xp, unsigned long long *ticket, int *err,
-                           int32_t blocks, unsigned long long limit, hipStream_t s) {
+                           int32_t blocks, unsigned long long limit, hipStream_t s, unsigned long long *stamp) {
   if (n == 0) return hipSuccess;
   const int64_t total = (int64_t)n * nrhs;
   unsigned long long *xb = reinterpret_cast<unsigned long long *>(xp);
   hipLaunchKernelGGL(k_sf_init, dim3(grid_for(total, kBlock, 8192)), dim3(kBlock), 0, s, total, xb, ticket);
   const dim3 grid(grid_for(total, kBlock, blocks > 0 ? blocks : 512));
-  if (nrhs == 1)
-    hipLaunchKernelGGL(k_sf_solve<true>, grid, dim3(kBlock), 0, s, n, nrhs, srp, sci, sva, sdg, bp, xp, ticket, err,
-                       limit);
-  else
-    hipLaunchKernelGGL(k_sf_solve<false>, grid, dim3(kBlock), 0, s, n, nrhs, srp, sci, sva, sdg, bp, xp, ticket, err,
-                       limit);
+#define SF(ONE, ST)                                                                                               \
+  hipLaunchKernelGGL((k_sf_solve<ONE, ST>), grid, dim3(kBlock), 0, s, n, nrhs, srp, sci, sva, sdg, bp, xp, ticket, \
+                     err, limit, stamp)
+  if (stamp) {
+    if (nrhs == 1)
+      SF(true, true);
+    else
+      SF(false, true);
+  } else if (nrhs == 1) {
+    SF(true, false);
+  } else {
+    SF(false, false);
+  }
+#undef SF
+  return hipGetLastError();
+}
+
+hipError_t launch_stamp_levels(int32_t nlev, int32_t nrhs, const int32_t *level_ptr, const unsigned long long *stamp,
+                               unsigned long long *lmax, unsigned long long *gmin, float ns_per_tick, float *times,
+                               hipStream_t s) {
+  if (nlev <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stamp_level_max, dim3(nlev < 4096 ? nlev : 4096), dim3(256), 0, s, nlev, nrhs, level_ptr,
+                     stamp, lmax, gmin);
+  hipLaunchKernelGGL(k_stamp_finish, dim3((nlev + 255) / 256), dim3(256), 0, s, nlev, lmax, gmin, ns_per_tick, times);
   return hipGetLastError();
 }

@@ -253,6 +253,39 @@ __global__ void k_batch_scatter(int64_t total, int32_t nrhs, const double *__res
   }
 }
 
+// b = A 1: row sums of a CSR matrix (the right-hand side of the rewrite's
+// self-check, whose exact solution is all ones).
+__global__ void k_row_sums(int32_t n, const int32_t *__restrict__ rp, const double *__restrict__ va, double *b) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int32_t q = rp[r]; q < rp[r + 1]; ++q) s += va[q];
+    b[r] = s;
+  }
+}
+
+// out[0] = max |x1 - x0| (a NaN counts as infinite), out[1] = max |x0|, as
+// the bit patterns of non-negative doubles (monotone as unsigned integers).
+__global__ void k_max_abs_diff(int32_t n, const double *__restrict__ x0, const double *__restrict__ x1,
+                               unsigned long long *out) {
+  double d = 0.0, m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double e = fabs(x1[i] - x0[i]);
+    if (e != e) e = INFINITY;
+    d = e > d ? e : d;
+    double a = fabs(x0[i]);
+    if (a != a) a = INFINITY;
+    m = a > m ? a : m;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    d = fmax(d, __shfl_xor(d, off, 64));
+    m = fmax(m, __shfl_xor(m, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(d));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 constexpr int32_t kTileGrid = 1024;
 
 }  // namespace
@@ -280,6 +313,19 @@ hipError_t launch_scatter_tiles(int32_t n, int32_t nrhs, const double *xp, const
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_tiles, dim3(std::min(ntiles, kTileGrid)), dim3(256), 0, s, n, nrhs, xp, iperm, tiles,
                      ntiles, x, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_sums(int32_t n, const int32_t *rp, const double *va, double *b, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_sums, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, rp, va, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_abs_diff(int32_t n, const double *x0, const double *x1, unsigned long long *out,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_max_abs_diff, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, x0, x1, out);
   return hipGetLastError();
 }
 

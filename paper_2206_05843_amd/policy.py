@@ -1,13 +1,19 @@
-"""Learned rewrite policy: which levels to rewrite.
+"""Learned rewrite policy: which levels to rewrite, and how far.
 
-The paper's naive strategy rewrites every thin level (Sec. III) and discusses
-that a rewrite is not always worth its cost (Sec. III.A). This policy replaces
-the thin-level test with a small network over per-level features; the
-strategy's budget, fill cap and stop-and-retarget logic stay in force, and a
-missing or unusable checkpoint falls back to the thin-level test.
+The paper's naive strategy rewrites every thin level under one target budget
+and fill cap (Sec. III) and notes that a rewrite is not always worth its cost
+(Sec. III.A). Here a small network over per-level features gives each level a
+probability that rewriting it pays, and tiers map that probability to an
+action: below the first tier's threshold the level is not a source; in tier j
+it is a source whose rows may fill a target up to budget_j rows with at most
+cap_j times their own entries (0 = the rewrite's own budget and cap). So the
+policy can move rows naive cannot (a larger budget or cap on the levels the
+network trusts) and keep rows naive would move. The stop-and-retarget logic
+of the scan stays in force; a missing or unusable checkpoint falls back to the
+thin-level test.
 
 Inference is on the device: sptrsv_level_features -> sptrsv_mlp_forward ->
-sptrsv_mlp_mask (the level mask handed to sptrsv_rewrite).
+sptrsv_mlp_actions (mask, per-level budget and cap handed to sptrsv_rewrite).
 """
 from __future__ import annotations
 
@@ -23,8 +29,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CKPT = os.path.join(HERE, "policy_ckpt.npz")
 
 
+def _tiers(tiers):
+    """[(threshold, budget, cap), ...] with ascending thresholds; a bare number
+    is one tier at that threshold with the rewrite's own budget and cap."""
+    if isinstance(tiers, (int, float, np.floating)):
+        tiers = [(float(tiers), 0, 0.0)]
+    out = [(float(t), int(b), float(c)) for t, b, c in tiers]
+    if not 1 <= len(out) <= _sp.MAX_TIERS:
+        raise ValueError("a policy has 1 to 4 tiers")
+    if any(out[i][0] > out[i + 1][0] for i in range(len(out) - 1)) or any(b < 0 or c < 0 for _, b, c in out):
+        raise ValueError("tiers need ascending thresholds and budgets, caps >= 0")
+    return out
+
+
 class Policy:
-    def __init__(self, params: np.ndarray, norm: np.ndarray, threshold: float = 0.5, meta: dict | None = None):
+    def __init__(self, params: np.ndarray, norm: np.ndarray, tiers=0.5, meta: dict | None = None):
         params = np.asarray(params, np.float32).reshape(-1)
         norm = np.asarray(norm, np.float32).reshape(-1)
         if params.size != _sp.MLP_NPARAM or norm.size != 2 * _sp.MLP_NIN:
@@ -33,32 +52,46 @@ class Policy:
             raise ValueError("non-finite policy checkpoint")
         self.params = torch.from_numpy(params).to("cuda")
         self.norm = torch.from_numpy(norm).to("cuda")
-        self.threshold = float(threshold)
+        self.tiers = _tiers(tiers)
         self.meta = meta or {}
+
+    @property
+    def threshold(self) -> float:
+        """The lowest threshold: levels below it are not sources."""
+        return self.tiers[0][0]
 
     def probs(self, h: _sp.Handle):
         return _sp.mlp_forward(self.params, h.level_features(), self.norm)
 
+    def actions(self, h: _sp.Handle, prob=None):
+        """(mask, budget, cap) device arrays over the ORIGINAL levels of h
+        (level 0 never a source)."""
+        return _sp.mlp_actions(self.probs(h) if prob is None else prob, self.tiers)
+
     def mask_for(self, h: _sp.Handle):
         """uint8 device mask over the ORIGINAL levels of h (level 0 never a source)."""
-        return _sp.mlp_mask(self.probs(h), self.threshold)
+        return self.actions(h)[0]
 
     def save(self, path: str = DEFAULT_CKPT):
         np.savez(path, params=self.params.cpu().numpy(), norm=self.norm.cpu().numpy(),
-                 threshold=np.array([self.threshold], np.float32))
+                 tiers=np.array(self.tiers, np.float64).reshape(-1, 3))
         with open(os.path.splitext(path)[0] + ".json", "w") as f:
             json.dump(self.meta, f, indent=1)
 
     @staticmethod
     def load(path: str = DEFAULT_CKPT) -> "Policy":
         with np.load(path, allow_pickle=False) as z:
-            params, norm, thr = z["params"], z["norm"], float(z["threshold"][0])
+            params, norm = z["params"], z["norm"]
+            if "tiers" in z:
+                tiers = [(float(t), int(b), float(c)) for t, b, c in np.asarray(z["tiers"]).reshape(-1, 3)]
+            else:
+                tiers = float(z["threshold"][0])
         meta = {}
         jp = os.path.splitext(path)[0] + ".json"
         if os.path.exists(jp):
             with open(jp) as f:
                 meta = json.load(f)
-        return Policy(params, norm, thr, meta)
+        return Policy(params, norm, tiers, meta)
 
 
 def init_params(seed: int = 0) -> np.ndarray:
@@ -86,10 +119,15 @@ def load_default() -> Policy | None:
 
 def rewrite_learned(h: _sp.Handle, policy: Policy | None, thin_threshold=32.0, fill_cap=4.0, max_distance=0,
                     max_indegree=0, max_spread=0, critical_only=False):
-    """Rewrite with the policy's level mask (fallback: the thin-level test).
-    The row constraints of Sec. III.A (indegree < max_indegree, column span <
-    max_spread, longest-path rows only) apply to each row of the chosen levels,
-    as in the plain strategies; 0 / False leaves them off."""
-    mask = policy.mask_for(h) if policy is not None else None
+    """Rewrite with the policy's per-level actions (fallback: the thin-level
+    test with thin_threshold and fill_cap). A tier's budget and cap of 0 take
+    thin_threshold and fill_cap. The row constraints of Sec. III.A (indegree <
+    max_indegree, column span < max_spread, longest-path rows only) apply to
+    each row of the chosen levels, as in the plain strategies; 0 / False
+    leaves them off."""
+    if policy is None:
+        return h.rewrite(_sp.THIN_ROWS, thin_threshold, fill_cap, max_distance, None, max_indegree=max_indegree,
+                         max_spread=max_spread, critical_only=critical_only)
+    mask, budget, cap = policy.actions(h)
     return h.rewrite(_sp.THIN_ROWS, thin_threshold, fill_cap, max_distance, mask, max_indegree=max_indegree,
-                     max_spread=max_spread, critical_only=critical_only)
+                     max_spread=max_spread, critical_only=critical_only, level_budget=budget, level_fill_cap=cap)

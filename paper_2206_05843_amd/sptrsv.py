@@ -32,7 +32,7 @@ EXPORTS = [
     "sptrsv_plan_load", "sptrsv_level_features", "sptrsv_mlp_forward", "sptrsv_mlp_backward", "sptrsv_mlp_adam",
     "sptrsv_mlp_mask", "sptrsv_profile", "sptrsv_level_times", "sptrsv_get_tune_info",
     "sptrsv_solve_noalloc", "sptrsv_measure_level_costs", "sptrsv_level_floor",
-    "sptrsv_get_info",
+    "sptrsv_get_info", "sptrsv_level_finish_times", "sptrsv_mlp_actions",
 ]
 
 
@@ -46,7 +46,8 @@ class SptrsvError(RuntimeError):
 class RewriteOpts(C.Structure):
     _fields_ = [("thin_metric", C.c_int32), ("thin_threshold", C.c_double), ("fill_cap", C.c_double),
                 ("max_distance", C.c_int32), ("d_level_mask", C.c_void_p), ("max_indegree", C.c_int32),
-                ("critical_only", C.c_int32), ("max_spread", C.c_int64), ("scan_workers", C.c_int32)]
+                ("critical_only", C.c_int32), ("max_spread", C.c_int64), ("scan_workers", C.c_int32),
+                ("d_level_budget", C.c_void_p), ("d_level_fill_cap", C.c_void_p), ("self_check", C.c_double)]
 
 
 class RewriteStats(C.Structure):
@@ -54,7 +55,8 @@ class RewriteStats(C.Structure):
                 ("max_distance", C.c_int32), ("target_steps", C.c_int32), ("nnz_L", C.c_int64),
                 ("nnz_Lp", C.c_int64), ("nnz_T", C.c_int64), ("total_cost_before", C.c_int64),
                 ("total_cost_after", C.c_int64), ("avg_level_cost_before", C.c_double),
-                ("avg_level_cost_after", C.c_double), ("rows_skipped", C.c_int32)]
+                ("avg_level_cost_after", C.c_double), ("rows_skipped", C.c_int32),
+                ("self_check_failed", C.c_int32), ("self_check_err", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -141,6 +143,8 @@ def lib():
         "sptrsv_level_times": [vp, C.c_int, i32, vp, vp, vp],
         "sptrsv_mlp_adam": [vp, vp, vp, vp, i32, f32, vp],
         "sptrsv_mlp_mask": [vp, i32, f32, vp, vp],
+        "sptrsv_mlp_actions": [vp, i32, i32, C.POINTER(f32), C.POINTER(i32), C.POINTER(f32), vp, vp, vp, vp],
+        "sptrsv_level_finish_times": [vp, C.c_int, i32, vp, vp, vp],
         "sptrsv_profile": [vp, C.c_int, vp, vp],
         "sptrsv_get_tune_info": [vp, C.POINTER(TuneInfo)],
         "sptrsv_measure_level_costs": [vp, vp, C.POINTER(LevelCosts)],
@@ -205,6 +209,26 @@ def mlp_mask(prob, threshold: float = 0.5):
     mask = torch.empty(prob.shape[0], dtype=torch.uint8, device=prob.device)
     _check_free(lib().sptrsv_mlp_mask(_ptr(prob), prob.shape[0], threshold, _ptr(mask), _stream()), "mlp_mask")
     return mask
+
+
+MAX_TIERS = 4
+
+
+def mlp_actions(prob, tiers):
+    """Tiered actions from probabilities: tiers = [(threshold, budget, cap),
+    ...] with ascending thresholds; returns the (mask, budget, cap) device
+    arrays for Handle.rewrite(mask, level_budget=, level_fill_cap=)."""
+    k = len(tiers)
+    nlev = prob.shape[0]
+    thr = (C.c_float * max(k, 1))(*[float(t[0]) for t in tiers])
+    bud = (C.c_int32 * max(k, 1))(*[int(t[1]) for t in tiers])
+    cap = (C.c_float * max(k, 1))(*[float(t[2]) for t in tiers])
+    mask = torch.empty(nlev, dtype=torch.uint8, device=prob.device)
+    budget = torch.empty(nlev, dtype=torch.int32, device=prob.device)
+    fcap = torch.empty(nlev, dtype=torch.float32, device=prob.device)
+    _check_free(lib().sptrsv_mlp_actions(_ptr(prob), nlev, k, thr, bud, cap, _ptr(mask), _ptr(budget), _ptr(fcap),
+                                         _stream()), "mlp_actions")
+    return mask, budget, fcap
 
 
 class Handle:
@@ -272,12 +296,20 @@ class Handle:
 
     # ------------------------------------------------------------------- rewrite
     def rewrite(self, thin_metric=THIN_ROWS, thin_threshold=32.0, fill_cap=4.0, max_distance=0, mask=None,
-                max_indegree=0, max_spread=0, critical_only=False, scan_workers=1):
-        o = RewriteOpts(thin_metric, float(thin_threshold), float(fill_cap), int(max_distance),
-                        _ptr(mask) if mask is not None else None, int(max_indegree), int(bool(critical_only)),
-                        int(max_spread), int(scan_workers))
+                max_indegree=0, max_spread=0, critical_only=False, scan_workers=1, self_check=0.0,
+                level_budget=None, level_fill_cap=None):
         if mask is not None:
             _need(mask.dtype == torch.uint8 and mask.numel() >= self.nlev, "uint8 mask of nlev entries expected")
+        if level_budget is not None:
+            _need(level_budget.dtype == torch.int32 and level_budget.numel() >= self.nlev,
+                  "int32 level_budget of nlev entries expected")
+        if level_fill_cap is not None:
+            _need(level_fill_cap.dtype == torch.float32 and level_fill_cap.numel() >= self.nlev,
+                  "float32 level_fill_cap of nlev entries expected")
+        o = RewriteOpts(thin_metric, float(thin_threshold), float(fill_cap), int(max_distance),
+                        _ptr(mask) if mask is not None else None, int(max_indegree), int(bool(critical_only)),
+                        int(max_spread), int(scan_workers), _ptr(level_budget), _ptr(level_fill_cap),
+                        float(self_check))
         st = RewriteStats()
         self._check(self._L.sptrsv_rewrite(self._h, C.byref(o), _stream(), C.byref(st)))
         self.rstats = st.as_dict()
@@ -451,6 +483,16 @@ class Handle:
         nlev = self.nlev if which == ORIGINAL else self.rstats["nlev_after"]
         t = torch.empty(nlev, dtype=torch.float32, device="cuda")
         self._check(self._L.sptrsv_level_times(self._h, which, bb.shape[0], _ptr(bb.contiguous()), _ptr(t), _stream()))
+        return t
+
+    def level_finish_times(self, b, which=ORIGINAL):
+        """Per-level finish times (ns from the solve's first written value) of
+        one synchronisation-free solve."""
+        bb = b if b.dim() == 2 else b.view(1, -1)
+        nlev = self.nlev if which == ORIGINAL else self.rstats["nlev_after"]
+        t = torch.empty(nlev, dtype=torch.float32, device="cuda")
+        self._check(self._L.sptrsv_level_finish_times(self._h, which, bb.shape[0], _ptr(bb.contiguous()), _ptr(t),
+                                                      _stream()))
         return t
 
     def level_features(self):

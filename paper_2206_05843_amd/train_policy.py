@@ -2,29 +2,40 @@
 
     python -m paper_2206_05843_amd.train_policy --out DIR [--matrices 200] [--heldout 20]
 
+Action. A level the network trusts becomes a source of the rewrite with a
+larger target budget and fill cap than the naive strategy's (32 rows, 4x):
+the pair (B, C) is chosen first, on validation matrices (seeds 1900..), as the
+one whose thin-level rewrite (levels with < B rows, budget B, cap C) solves
+fastest in geometric mean, each variant autotuned.
+
 Data. For each seeded power-law training matrix (n ~ U[50k, 500k]) the
-library measures, on the device, the time of every level of one solve of L
-and of one solve of L' after the naive rewrite (levels with < 32 rows, fill
-cap 4x), with every level inside one workgroup (sptrsv_level_times). A level
-that the naive rewrite empties is labelled 1 when the time its rows cost in
-their new levels of L' (their share, by row entries, of those levels' times)
-is below the time the level took in L, else 0; levels that are not emptied are
-labelled 0. The features are the 20 per-level features of the original levels
-(sptrsv_level_features), the row constraints of Sec. III.A among them.
+library times one synchronisation-free solve of L and one of L' after the
+(B, C) rewrite -- the executor the autotuner picks on these matrices -- with
+every item stamping the device clock when its value is written
+(sptrsv_level_finish_times). A level's time is the growth of the running
+maximum of its levels' finish times across it (its share of the critical
+path). A level that the rewrite empties is labelled 1 when the time its rows
+cost in their new levels of L' (their share, by row entries, of those levels'
+times) is below the time the level took in L, else 0; levels that are not
+emptied are labelled 0. The features are the 20 per-level features of the
+original levels (sptrsv_level_features), the row constraints of Sec. III.A
+among them.
 
 Training. Mean class-balanced binary cross-entropy, Adam, minibatches; forward,
 backward and the Adam step are the library's kernels. Features are
 standardised with the training set's mean and standard deviation, which are
 stored in the checkpoint with the weights.
 
-Calibration. The decision threshold on the network's probability is chosen
-on separate validation matrices (seeds 1900..): the one with the best
-geometric-mean solve-time ratio against the naive rewrite (ties: the higher
-threshold, which rewrites less).
+Calibration. Two tiers map the network's probability to an action: p >= t_hi
+takes (B, C), t_lo <= p < t_hi the naive budget and cap, p < t_lo leaves the
+level alone. (t_lo, t_hi) is chosen on the validation matrices: the pair with
+the best geometric-mean solve-time ratio against the naive rewrite (ties: the
+pair that rewrites less).
 
-Evaluation. On held-out seeds, plain, naive and learned are autotuned and
-timed; the rewritten solutions are checked against the plain solution
-(relative error <= 1e-10) and the plain one by its residual.
+Evaluation. On held-out seeds (2000..), plain, naive, the constant rule "(B, C)
+on every thin level" and learned are autotuned and timed; the rewritten
+solutions are checked against the plain solution (relative error <= 1e-10) and
+the plain one by its residual.
 """
 from __future__ import annotations
 
@@ -47,6 +58,9 @@ import gen  # noqa: E402
 from paper_2206_05843_amd import sptrsv as sp  # noqa: E402
 from paper_2206_05843_amd.policy import Policy, init_params  # noqa: E402
 
+NAIVE = (32.0, 4.0)
+ACTIONS = [(64, 8.0), (128, 8.0), (256, 8.0), (128, 16.0), (256, 16.0)]
+
 
 def log(*a):
     print(*a, flush=True)
@@ -57,15 +71,25 @@ def to_dev(m):
     return (torch.from_numpy(m.row_ptr).to(d), torch.from_numpy(m.col).to(d), torch.from_numpy(m.val).to(d))
 
 
-def level_data(m, reps: int = 3):
-    """Features, labels and time deltas of the original levels of m."""
+def level_shares(finish):
+    """A level's share of a synchronisation-free solve: the growth of the
+    running maximum of the levels' finish times across it."""
+    f = np.maximum.accumulate(np.asarray(finish, np.float64))
+    return np.diff(np.concatenate([[0.0], f]))
+
+
+def level_data(m, action, reps: int = 3):
+    """Features, labels and time deltas of the original levels of m, under the
+    rewrite with target budget and fill cap `action` on every thin level."""
     h = sp.Handle()
     h.analyze(*to_dev(m))
     feat = h.level_features().cpu().numpy()
     b = torch.from_numpy(gen.rhs(m, 1)[0]).to("cuda")
-    t_plain = np.mean([h.level_times(b, sp.ORIGINAL).cpu().numpy() for _ in range(reps)], axis=0)
-    h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0)
-    t_rew = np.mean([h.level_times(b, sp.REWRITTEN).cpu().numpy() for _ in range(reps)], axis=0)
+    t_plain = np.mean([level_shares(h.level_finish_times(b, sp.ORIGINAL).cpu().numpy()) for _ in range(reps)],
+                      axis=0)
+    h.rewrite(sp.THIN_ROWS, float(action[0]), float(action[1]), 0)
+    t_rew = np.mean([level_shares(h.level_finish_times(b, sp.REWRITTEN).cpu().numpy()) for _ in range(reps)],
+                    axis=0)
     tgt = h.targets().cpu().numpy()
     rw = h.rewritten()
     work = (np.diff(rw["lp_ptr"].cpu().numpy()) - 1) + (np.diff(rw["t_ptr"].cpu().numpy()) - 1) + 1
@@ -132,63 +156,111 @@ def accuracy(params, norm, feat, label):
                 recall=tp / max(1.0, float(np.sum(y))), positives=float(np.mean(y)))
 
 
-def time_variant(h, which, b, reps=20):
+def time_variant(h, which, b, reps=21):
+    """Autotuned solve time: median of `reps` solves, each between HIP events
+    on the current stream."""
     h.autotune(which, 1)
     x = torch.empty_like(b)
     for _ in range(3):
         h.solve(b, which, x)
     torch.cuda.synchronize()
-    t = time.perf_counter()
+    ts = []
     for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         h.solve(b, which, x)
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t) / reps, x
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    return float(np.median(ts)), x
 
 
-def calibrate(params, norm, seeds, thresholds=(0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.99)):
-    """Threshold with the best geometric-mean time ratio naive / learned on
-    the given matrices (each variant autotuned)."""
-    ratios = {t: [] for t in thresholds}
+def _geomean(r):
+    return math.exp(float(np.mean(np.log(r))))
+
+
+def choose_action(seeds, actions=ACTIONS):
+    """(B, C) whose thin-level rewrite (levels with < B rows, budget B, cap C)
+    is fastest in geometric mean against naive on the given matrices."""
+    ratios = {a: [] for a in actions}
     for s in seeds:
         m = gen.policy_training_matrix(s)
         b = torch.from_numpy(gen.rhs(m, 1)[0]).to("cuda")
         h = sp.Handle()
         h.analyze(*to_dev(m))
-        h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0)
+        h.rewrite(sp.THIN_ROWS, *NAIVE, 0)
         t_naive, _ = time_variant(h, sp.REWRITTEN, b)
-        for t in thresholds:
-            pol = Policy(params, norm, t)
-            h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0, pol.mask_for(h))
-            t_l, _ = time_variant(h, sp.REWRITTEN, b)
-            ratios[t].append(t_naive / t_l)
+        for a in actions:
+            h.rewrite(sp.THIN_ROWS, float(a[0]), float(a[1]), 0)
+            ratios[a].append(t_naive / time_variant(h, sp.REWRITTEN, b)[0])
         h.close()
-    score = {t: math.exp(np.mean(np.log(r))) for t, r in ratios.items()}
-    best = max(sorted(thresholds, reverse=True), key=lambda t: score[t])
-    log(f"[calibrate] geomean naive/learned by threshold: {json.dumps({str(k): round(v, 4) for k, v in score.items()})}"
-        f" -> {best}")
+    score = {a: _geomean(r) for a, r in ratios.items()}
+    best = max(actions, key=lambda a: score[a])
+    log(f"[action] geomean naive/(B,C) rewrite: { {str(k): round(v, 4) for k, v in score.items()} } -> {best}")
     return best, score
 
 
-def evaluate(policy: Policy, seeds, check=True):
-    """Autotuned solve time of plain, naive and learned on each seed. The
-    rewritten solutions are checked against the plain solution (relative error
-    <= 1e-10) and the plain one by its residual."""
+def tier_grid(action):
+    """Candidate (t_lo, t_hi) pairs; t_lo == t_hi leaves out the naive tier,
+    t_hi above 1 leaves out the (B, C) tier."""
+    his = (0.02, 0.1, 0.3, 0.5, 0.7, 0.9, 1.01)
+    los = (0.02, 0.1, 0.3, 0.5)
+    pairs = sorted({(lo, hi) for hi in his for lo in los + (hi,) if lo <= hi and lo <= 1.0})
+    return [((lo, 0, 0.0), (hi, int(action[0]), float(action[1]))) for lo, hi in pairs]
+
+
+def calibrate(params, norm, seeds, action):
+    """Tier thresholds with the best geometric-mean time ratio naive / learned
+    on the given matrices (each variant autotuned; ties: the higher
+    thresholds, which rewrite less)."""
+    grid = tier_grid(action)
+    ratios = {g: [] for g in grid}
+    pol = Policy(params, norm, list(grid[0]))
+    for s in seeds:
+        m = gen.policy_training_matrix(s)
+        b = torch.from_numpy(gen.rhs(m, 1)[0]).to("cuda")
+        h = sp.Handle()
+        h.analyze(*to_dev(m))
+        h.rewrite(sp.THIN_ROWS, *NAIVE, 0)
+        t_naive, _ = time_variant(h, sp.REWRITTEN, b)
+        prob = pol.probs(h)
+        for g in grid:
+            mask, bud, cap = sp.mlp_actions(prob, list(g))
+            h.rewrite(sp.THIN_ROWS, *NAIVE, 0, mask, level_budget=bud, level_fill_cap=cap)
+            ratios[g].append(t_naive / time_variant(h, sp.REWRITTEN, b)[0])
+        h.close()
+    score = {g: _geomean(r) for g, r in ratios.items()}
+    best = max(sorted(grid, key=lambda g: (-g[1][0], -g[0][0])), key=lambda g: score[g])
+    log("[calibrate] geomean naive/learned by (t_lo, t_hi): "
+        + json.dumps({f"{g[0][0]},{g[1][0]}": round(v, 4) for g, v in score.items()}) + f" -> {best}")
+    return list(best), score
+
+
+def evaluate(policy: Policy, seeds, action, check=True):
+    """Autotuned solve time of plain, naive, the constant (B, C) rule and
+    learned on each seed. The rewritten solutions are checked against the
+    plain solution (relative error <= 1e-10) and the plain one by its
+    residual."""
+    from paper_2206_05843_amd.policy import rewrite_learned
     out = []
     for s in seeds:
         m = gen.policy_training_matrix(s)
-        b_np = gen.rhs(m, 1)
-        b = torch.from_numpy(b_np[0]).to("cuda")
+        b = torch.from_numpy(gen.rhs(m, 1)[0]).to("cuda")
         xr = None
-        res = {"seed": s, "n": m.n}
-        for name in ("plain", "naive", "learned"):
+        res = {"seed": s, "n": m.n, "nnz": m.nnz}
+        for name in ("plain", "naive", "constant", "learned"):
             h = sp.Handle()
             res_nlev = h.analyze(*to_dev(m))
             which = sp.ORIGINAL
+            st = None
             if name == "naive":
-                res_nlev = h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0)["nlev_after"]
-                which = sp.REWRITTEN
+                st = h.rewrite(sp.THIN_ROWS, *NAIVE, 0)
+            elif name == "constant":
+                st = h.rewrite(sp.THIN_ROWS, float(action[0]), float(action[1]), 0)
             elif name == "learned":
-                res_nlev = h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0, policy.mask_for(h))["nlev_after"]
+                st = rewrite_learned(h, policy, *NAIVE)
+            if st is not None:
+                res_nlev = st["nlev_after"]
                 which = sp.REWRITTEN
             t, x = time_variant(h, which, b)
             h.check()
@@ -199,16 +271,18 @@ def evaluate(policy: Policy, seeds, check=True):
                 else:
                     err = float((x - xr).abs().max() / xr.abs().max())
                     assert err <= 1e-10, (s, name, err)
-            res[name] = {"ms": t * 1e3, "nlev": res_nlev}
+            res[name] = {"ms": t * 1e3, "nlev": res_nlev, "mode": h.get_schedule(which, 1)["mode"]}
+            if st is not None:
+                res[name].update(rows_rewritten=st["rows_rewritten"], nnz_Lp=st["nnz_Lp"], nnz_T=st["nnz_T"])
             h.close()
-        res["learned_vs_naive"] = res["naive"]["ms"] / res["learned"]["ms"]
-        res["learned_vs_plain"] = res["plain"]["ms"] / res["learned"]["ms"]
+        for k in ("naive", "plain", "constant"):
+            res[f"learned_vs_{k}"] = res[k]["ms"] / res["learned"]["ms"]
         log(f"[eval] seed {s} n={m.n} plain {res['plain']['ms']:.3f}ms naive {res['naive']['ms']:.3f}ms "
-            f"learned {res['learned']['ms']:.3f}ms (x{res['learned_vs_naive']:.3f} vs naive)")
+            f"constant {res['constant']['ms']:.3f}ms learned {res['learned']['ms']:.3f}ms "
+            f"(x{res['learned_vs_naive']:.3f} vs naive)")
         out.append(res)
-    g = math.exp(np.mean([math.log(r["learned_vs_naive"]) for r in out]))
-    gp = math.exp(np.mean([math.log(r["learned_vs_plain"]) for r in out]))
-    return out, g, gp
+    g = {k: _geomean([r[f"learned_vs_{k}"] for r in out]) for k in ("naive", "plain", "constant")}
+    return out, g
 
 
 def main():
@@ -218,15 +292,22 @@ def main():
     ap.add_argument("--first-seed", type=int, default=1000)
     ap.add_argument("--heldout", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=40)
-    ap.add_argument("--calib", type=int, default=10, help="validation matrices for the threshold (seeds 1900..)")
+    ap.add_argument("--calib", type=int, default=10, help="validation matrices for the action and tiers (1900..)")
+    ap.add_argument("--action", default="", help="B,C to skip the action search")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
+    calib_seeds = list(range(1900, 1900 + max(args.calib, 1)))
+    if args.action:
+        bb, cc = args.action.split(",")
+        action, action_score = (int(bb), float(cc)), {}
+    else:
+        action, action_score = choose_action(calib_seeds)
     seeds = list(range(args.first_seed, args.first_seed + args.matrices))
     feats, labels, deltas, owner = [], [], [], []
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=4) as ex:
         for i, m in enumerate(ex.map(gen.policy_training_matrix, seeds)):
-            f, y, d, e = level_data(m)
+            f, y, d, e = level_data(m, action)
             feats.append(f)
             labels.append(y)
             deltas.append(d)
@@ -243,23 +324,28 @@ def main():
     acc_tr = accuracy(params, norm, F[~val], Y[~val])
     acc_va = accuracy(params, norm, F[val], Y[val])
     log(f"[train] train {acc_tr} val {acc_va}")
-    thr, score = (0.5, {})
+    tiers, score = [(0.5, int(action[0]), float(action[1]))], {}
     if args.calib > 0:
-        thr, score = calibrate(params, norm, list(range(1900, 1900 + args.calib)))
+        tiers, score = calibrate(params, norm, calib_seeds, action)
     meta = {"train_seeds": [seeds[0], seeds[-1]], "levels": int(F.shape[0]), "positive_rate": float(Y.mean()),
             "epochs": args.epochs, "loss_history": hist, "train_metrics": acc_tr, "val_metrics": acc_va,
-            "label": "1 = emptied by the naive rewrite and its rows cost less time in L' than the level in L",
-            "threshold": thr, "calibration_seeds": [1900, 1900 + args.calib - 1] if args.calib > 0 else [],
-            "calibration_geomean_naive_over_learned": {str(k): v for k, v in score.items()}}
-    pol = Policy(params, norm, thr, meta)
+            "action": {"budget": int(action[0]), "fill_cap": float(action[1]),
+                       "geomean_naive_over_constant_by_action": {str(k): v for k, v in action_score.items()}},
+            "label": "1 = emptied by the (budget, cap) rewrite and its rows cost less of the synchronisation-free "
+                     "solve's critical path in L' than the level in L",
+            "tiers": [list(t) for t in tiers], "calibration_seeds": [calib_seeds[0], calib_seeds[-1]],
+            "calibration_geomean_naive_over_learned": {f"{g[0][0]},{g[1][0]}": v for g, v in score.items()}}
+    pol = Policy(params, norm, tiers, meta)
     pol.save(os.path.join(args.out, "policy_ckpt.npz"))
     if args.heldout > 0:
-        res, g, gp = evaluate(pol, list(range(2000, 2000 + args.heldout)))
-        summary = {"heldout_seeds": [2000, 2000 + args.heldout - 1], "geomean_learned_vs_naive": g,
-                   "geomean_learned_vs_plain": gp, "per_matrix": res}
+        res, g = evaluate(pol, list(range(2000, 2000 + args.heldout)), action)
+        summary = {"heldout_seeds": [2000, 2000 + args.heldout - 1], "tiers": [list(t) for t in tiers],
+                   "geomean_learned_vs_naive": g["naive"], "geomean_learned_vs_plain": g["plain"],
+                   "geomean_learned_vs_constant": g["constant"], "per_matrix": res}
         with open(os.path.join(args.out, "policy_eval.json"), "w") as f:
             json.dump(summary, f, indent=1)
-        log(f"[eval] geomean speedup learned vs naive {g:.4f}, vs plain {gp:.4f}")
+        log(f"[eval] geomean speedup learned vs naive {g['naive']:.4f}, vs plain {g['plain']:.4f}, "
+            f"vs constant {g['constant']:.4f}")
 
 
 if __name__ == "__main__":

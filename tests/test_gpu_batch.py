@@ -140,3 +140,37 @@ def test_batch_errors():
     with pytest.raises(sp.SptrsvError) as ei:
         h._check(h._L.sptrsv_batch_solve(h._h, 1, None, None, None))
     assert ei.value.name in ("STATE", "ARG")
+
+
+@pytest.mark.parametrize("nrhs", [16, 1])
+@pytest.mark.parametrize("wide_first", [False, True])
+def test_batch_with_levels_too_wide_for_a_window(nrhs, wide_first):
+    """A uniform random lower-triangular matrix (n = 50,000, about 6 nonzeros
+    per row, columns anywhere before the row) has levels of thousands of rows,
+    too wide for one workgroup's LDS window at 16 right-hand sides: it is
+    solved level by level beside the persistent launch, in the same call, and
+    every matrix still matches the oracle; the looped per-matrix solve gives
+    the same bits."""
+    wide = gen.window_random(50_000, 17, window=50_000, draws=6)
+    widths = np.diff(oracle.levels(wide).level_ptr)
+    assert widths.max() > 2000
+    small = [gen.window_random(3000 + 500 * i, 40 + i) for i in range(5)]
+    mats = [wide] + small if wide_first else small[:3] + [wide] + small[3:]
+    h = sp.Handle()
+    h.batch_analyze([m.n for m in mats], *_cat(mats))
+    b = _rhs_cat(mats, nrhs)
+    bd = to_dev(b)
+    x = torch.zeros(b.size, dtype=torch.float64, device="cuda")
+    h.batch_solve(bd, x, nrhs)
+    h.check()
+    xs = x.cpu().numpy()
+    off = 0
+    for m in mats:
+        bm = b[off * nrhs:(off + m.n) * nrhs].reshape(nrhs, m.n)
+        xm = xs[off * nrhs:(off + m.n) * nrhs].reshape(nrhs, m.n)
+        assert oracle.relerr(xm, oracle.solve(m, bm)) <= TOL
+        off += m.n
+    x2 = torch.zeros_like(x)
+    h.batch_solve(bd, x2, nrhs, looped=True)
+    h.check()
+    assert torch.equal(x, x2)

@@ -51,8 +51,7 @@ def test_full_solve_autotuned(full, cfg, variant):
         which = sp.REWRITTEN
     elif variant == "learned":
         from paper_2206_05843_amd import policy
-        pol = policy.load_default()
-        h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0, pol.mask_for(h) if pol is not None else None)
+        policy.rewrite_learned(h, policy.load_default())
         which = sp.REWRITTEN
     h.autotune(which, nrhs)
     bd = to_dev(b)
@@ -64,18 +63,25 @@ def test_full_solve_autotuned(full, cfg, variant):
     assert torch.equal(x, x2)
 
 
-def _oracle_policy_mask(m, lv, pol):
-    """The shipped policy's level mask computed on the CPU side: the oracle's
-    FP64 features through the FP64 network with the checkpoint's weights
-    (rounded to the float32 the checkpoint holds). Also returns the oracle's
-    probabilities, to find decisions that sit on the threshold."""
+def _oracle_policy_actions(m, lv, pol):
+    """The shipped policy's per-level actions computed on the CPU side: the
+    oracle's FP64 features through the FP64 network with the checkpoint's
+    weights (rounded to the float32 the checkpoint holds), then the highest
+    tier whose threshold the probability reaches. Also returns the oracle's
+    probabilities, to find decisions that sit on a threshold."""
     from oracle import mlp
     th = pol.params.cpu().numpy().astype(np.float64)
     norm = pol.norm.cpu().numpy().astype(np.float64)
     fo = oracle.level_features(m, lv)
     po, _ = mlp.forward(th, (fo - norm[:mlp.F_IN]) * norm[mlp.F_IN:])
-    mask = ((po >= pol.threshold) & (np.arange(lv.nlev) > 0)).astype(np.uint8)
-    return mask, po
+    tier = np.full(lv.nlev, -1)
+    for j, (t, _, _) in enumerate(pol.tiers):
+        tier[po >= t] = j
+    tier[0] = -1
+    mask = (tier >= 0).astype(np.uint8)
+    budget = np.array([pol.tiers[k][1] if k >= 0 else 0 for k in tier], np.int32)
+    cap = np.array([pol.tiers[k][2] if k >= 0 else 0.0 for k in tier], np.float32)
+    return mask, budget, cap, po
 
 
 def _same_rewrite(h, rw):
@@ -89,24 +95,28 @@ def _same_rewrite(h, rw):
 @pytest.mark.parametrize("cfg,variant", [(1, "naive"), (2, "naive"), (1, "learned"), (2, "learned")])
 def test_full_rewrite_patterns(full, cfg, variant):
     """Rewritten L', T and targets at full size, bit for bit. For the learned
-    variant the level mask is the CPU side's (the oracle's features and
-    network); the device's own mask must agree with it on every level whose
-    oracle probability is not within 1e-4 of the threshold."""
+    variant the per-level actions (mask, target budget, fill cap) are the CPU
+    side's (the oracle's features and network); the device's own actions must
+    agree with them on every level whose oracle probability is not within 1e-4
+    of a threshold."""
     m = full[cfg][0]
     lv = oracle.levels(m)
     h = sp.Handle()
     h.analyze(*dev(m))
-    mask = None
+    mask = budget = cap = None
     if variant == "learned":
         from paper_2206_05843_amd import policy
         pol = policy.load_default()
         assert pol is not None
-        mask, po = _oracle_policy_mask(m, lv, pol)
-        gm = pol.mask_for(h).cpu().numpy()
-        sure = np.abs(po - pol.threshold) > 1e-4
+        mask, budget, cap, po = _oracle_policy_actions(m, lv, pol)
+        gm, gb, gc = (a.cpu().numpy() for a in pol.actions(h))
+        sure = np.all([np.abs(po - t) > 1e-4 for t, _, _ in pol.tiers], axis=0)
         assert np.array_equal(gm[sure], mask[sure])
-    st = h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0, to_dev(mask) if mask is not None else None)
-    rw = oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0, 0, mask, lv)
+        assert np.array_equal(gb[sure], budget[sure]) and np.array_equal(gc[sure], cap[sure])
+    st = h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0, to_dev(mask) if mask is not None else None,
+                   level_budget=to_dev(budget) if budget is not None else None,
+                   level_fill_cap=to_dev(cap) if cap is not None else None)
+    rw = oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0, 0, mask, lv, level_budget=budget, level_cap=cap)
     assert st["rows_rewritten"] == rw.rows_rewritten
     assert st["nlev_after"] == oracle.levels(rw.lp).nlev
     _same_rewrite(h, rw)

@@ -154,3 +154,103 @@ def test_learned_rewrite_with_row_constraints(knobs):
     assert np.array_equal(g["lp_ptr"], rw.lp.row_ptr) and np.array_equal(g["lp_col"], rw.lp.col)
     assert np.array_equal(g["t_ptr"], rw.t.row_ptr) and np.array_equal(g["t_col"], rw.t.col)
     assert st["rows_skipped"] == rw.rows_skipped
+
+
+def test_mlp_actions_tiers():
+    """Tiered actions from probabilities: the highest tier whose threshold
+    the probability reaches, level 0 never a source (direct definition)."""
+    rng = np.random.default_rng(11)
+    p = rng.random(1000).astype(np.float32)
+    p[[5, 6, 7]] = [0.2, 0.6, 0.59999]
+    tiers = [(0.2, 0, 0.0), (0.6, 128, 8.0)]
+    mask, bud, cap = (a.cpu().numpy() for a in sp.mlp_actions(to_dev(p), tiers))
+    k = np.where(p >= 0.6, 1, np.where(p >= 0.2, 0, -1))
+    k[0] = -1
+    assert np.array_equal(mask, (k >= 0).astype(np.uint8))
+    assert np.array_equal(bud, np.where(k == 1, 128, 0).astype(np.int32))
+    assert np.array_equal(cap, np.where(k == 1, 8.0, 0.0).astype(np.float32))
+    assert mask[5] == 1 and bud[5] == 0 and bud[6] == 128 and bud[7] == 0
+    # one tier reproduces sptrsv_mlp_mask
+    m1, _, _ = sp.mlp_actions(to_dev(p), [(0.5, 0, 0.0)])
+    assert torch.equal(m1, sp.mlp_mask(to_dev(p), 0.5))
+    with pytest.raises(sp.SptrsvError):
+        sp.mlp_actions(to_dev(p), [(0.6, 0, 0.0), (0.2, 64, 4.0)])  # thresholds out of order
+    with pytest.raises(sp.SptrsvError):
+        sp.mlp_actions(to_dev(p), [(0.1, -1, 0.0)])
+    with pytest.raises(sp.SptrsvError):
+        sp.mlp_actions(to_dev(p), [(0.1, 0, 0.0)] * 5)
+
+
+def test_policy_tiers_rewrite_matches_oracle():
+    """A two-tier policy (random weights) through rewrite_learned: mask,
+    per-level budget and cap from the device equal the FP64 network's on the
+    oracle's features (thresholds in wide gaps of the probabilities), and the
+    rewrite equals the oracle's with those per-level actions."""
+    from paper_2206_05843_amd import policy
+    m = gen.config_matrix(2, "small")[0]
+    lv = oracle.levels(m)
+    th = mlp.init(6)
+    fo = oracle.level_features(m, lv)
+    mean, sd = fo.mean(axis=0), fo.std(axis=0) + 1e-3
+    norm = np.concatenate([mean, 1.0 / sd]).astype(np.float32)
+    po, _ = mlp.forward(th.astype(np.float32).astype(np.float64),
+                        (fo - norm[:mlp.F_IN].astype(np.float64)) * norm[mlp.F_IN:].astype(np.float64))
+    q = np.sort(po[1:])
+    gaps = np.diff(q)
+    # two thresholds in the two widest gaps between the 20% and 80% quantiles
+    lo_i, hi_i = int(0.2 * len(q)), int(0.8 * len(q))
+    cand = np.argsort(gaps[lo_i:hi_i])[::-1][:2] + lo_i
+    t1, t2 = sorted(float((q[k] + q[k + 1]) / 2) for k in cand)
+    assert min(gaps[cand]) > 1e-5
+    tiers = [(t1, 0, 0.0), (t2, 96, 6.0)]
+    tier = np.where(po >= t2, 1, np.where(po >= t1, 0, -1))
+    tier[0] = -1
+    mask = (tier >= 0).astype(np.uint8)
+    budget = np.where(tier == 1, 96, 0).astype(np.int32)
+    cap = np.where(tier == 1, 6.0, 0.0).astype(np.float32)
+    pol = policy.Policy(th, norm, tiers)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    gm, gb, gc = (a.cpu().numpy() for a in pol.actions(h))
+    assert np.array_equal(gm, mask) and np.array_equal(gb, budget) and np.array_equal(gc, cap)
+    st = policy.rewrite_learned(h, pol)
+    rw = oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0, 0, mask, lv, level_budget=budget, level_cap=cap)
+    assert st["rows_rewritten"] == rw.rows_rewritten > 0
+    g = {k2: v.cpu().numpy() for k2, v in h.rewritten().items()}
+    assert np.array_equal(g["lp_ptr"], rw.lp.row_ptr) and np.array_equal(g["lp_col"], rw.lp.col)
+    assert np.array_equal(g["t_ptr"], rw.t.row_ptr) and np.array_equal(g["t_col"], rw.t.col)
+    assert np.array_equal(g["lp_val"], rw.lp.val) and np.array_equal(g["t_val"], rw.t.val)
+
+
+def test_policy_checkpoint_roundtrip(tmp_path):
+    from paper_2206_05843_amd import policy
+    tiers = [(0.1, 0, 0.0), (0.4, 128, 8.0)]
+    pol = policy.Policy(mlp.init(2), np.concatenate([np.zeros(mlp.F_IN), np.ones(mlp.F_IN)]), tiers, {"k": 1})
+    pol.save(str(tmp_path / "p.npz"))
+    q = policy.Policy.load(str(tmp_path / "p.npz"))
+    assert q.tiers == pol.tiers and q.meta == {"k": 1} and torch.equal(q.params, pol.params)
+    with pytest.raises(ValueError):
+        policy.Policy(mlp.init(2), np.zeros(2 * mlp.F_IN), [(0.5, 0, 0.0), (0.1, 64, 4.0)])
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_level_finish_times(nrhs):
+    """Finish times of a stamped synchronisation-free solve: on a chain
+    (every level one row that reads the row before) they increase strictly
+    level by level; on a general matrix a level's latest value is written
+    after the earliest value of the level before it (each level >= 1 has a
+    row reading a row of the level before), and every time is >= 0. Ordinary
+    solves stay right afterwards."""
+    ch = gen.bidiagonal(3000, 1)
+    for m in (ch, gen.window_random(20000, 4, 200, 3)):
+        h = sp.Handle()
+        nlev = h.analyze(*dev(m))
+        b = to_dev(gen.rhs(m, nrhs))
+        t = h.level_finish_times(b if nrhs > 1 else b.view(-1)).cpu().numpy()
+        assert t.shape == (nlev,) and np.all(np.isfinite(t)) and np.all(t >= 0)
+        assert t.max() > 0
+        if m is ch:
+            assert np.all(np.diff(t) > 0)
+        x = h.solve(b if nrhs > 1 else b.view(-1))
+        h.check()
+        assert oracle.relerr(x.view(nrhs, -1).cpu().numpy(), oracle.solve(m, b.view(nrhs, -1).cpu().numpy())) <= 1e-10

@@ -346,3 +346,108 @@ def test_scan_workers_errors():
     st = h.rewrite(sp.THIN_ROWS, 8.0, 0.0, 0, scan_workers=0)  # 0 is one workgroup
     rw = oracle.rewrite(m, sp.THIN_ROWS, 8.0, 0.0, 0)
     assert st["rows_rewritten"] == rw.rows_rewritten
+
+
+def _hub_matrix(D):
+    """Rows 0..D-1 have no dependency (level 0); row D reads all of them (level
+    1); row D+1 reads row D (level 2). Rewriting row D toward level 0
+    substitutes D rows: its T row needs D entries."""
+    rng = np.random.default_rng(21)
+    n = D + 2
+    off = rng.uniform(-1.0, 1.0, D)
+    rp = np.concatenate([np.arange(0, D + 1), [2 * D + 1, 2 * D + 3]]).astype(np.int64)
+    col = np.concatenate([np.arange(D), np.arange(D), [D, D, D + 1]]).astype(np.int32)
+    val = np.concatenate([np.ones(D), off, [1.0 + np.abs(off).sum(), -0.5, 2.0]])
+    return gen.Csr(n, rp.astype(np.int32), col, val, "hub")
+
+
+def test_rewrite_beyond_the_scan_workspace_is_an_overflow_error():
+    """A row whose rewritten form outgrows the scan's per-wave global
+    workspace (about 1M entries) is refused with SPTRSV_ERR_OVERFLOW (fill cap
+    off); the handle keeps its analysis and has no rewrite."""
+    m = _hub_matrix(1_100_000)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    with pytest.raises(sp.SptrsvError) as e:
+        h.rewrite(sp.THIN_ROWS, 1e9, 0.0, 0)
+    assert e.value.name == "OVERFLOW"
+    b = torch.from_numpy(gen.rhs(m, 1)).cuda()
+    x = h.solve(b)
+    h.check()
+    assert oracle.relerr(x.cpu().numpy(), oracle.solve(m, b.cpu().numpy())) <= 1e-10
+    with pytest.raises(sp.SptrsvError) as e:
+        h.solve(b, sp.REWRITTEN)
+    assert e.value.name == "STATE"
+
+
+def _growing_chain(n, ratio):
+    """Bidiagonal chain x_i = b_i + ratio x_{i-1} (diagonal 1, off-diagonal
+    -ratio): with b = L 1 every x_i is exactly 1, but the rewritten rows carry
+    products ratio^k in T, and b' = T b cancels them in floating point."""
+    rp = np.concatenate([[0], 1 + 2 * np.arange(n)]).astype(np.int32)
+    col = np.concatenate([[0]] + [[i - 1, i] for i in range(1, n)]).astype(np.int32)
+    val = np.concatenate([[1.0]] + [[-ratio, 1.0] for _ in range(1, n)])
+    return gen.Csr(n, rp, col, val, "chain")
+
+
+def test_self_check_falls_back_to_the_original_system():
+    m = _growing_chain(300, 10.0)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(sp.THIN_ROWS, 32, 0.0, 0, self_check=1e-8)
+    assert st["self_check_failed"] == 1 and st["self_check_err"] > 1e-8
+    assert st["rows_rewritten"] == 0 and st["nlev_after"] == st["nlev_before"] == 300
+    g = h.rewritten()
+    assert np.array_equal(g["lp_ptr"].cpu().numpy(), m.row_ptr) and np.array_equal(g["lp_col"].cpu().numpy(), m.col)
+    assert np.array_equal(g["lp_val"].cpu().numpy(), m.val)
+    assert np.array_equal(g["t_ptr"].cpu().numpy(), np.arange(m.n + 1))
+    assert np.all(g["t_val"].cpu().numpy() == 1.0)
+    assert np.all(h.targets().cpu().numpy() == -1)
+    one = np.ones((1, m.n))
+    b = torch.from_numpy(oracle.spmv(m.row_ptr, m.col, m.val, m.n, one)).cuda()
+    x0 = h.solve(b, sp.ORIGINAL)
+    x1 = h.solve(b, sp.REWRITTEN)
+    h.check()  # the failed check left no error latched
+    assert torch.equal(x0, x1)
+    assert np.all(x0.cpu().numpy() == 1.0)
+    # without the check the rewritten system is far off
+    h2 = sp.Handle()
+    h2.analyze(*dev(m))
+    h2.rewrite(sp.THIN_ROWS, 32, 0.0, 0)
+    x2 = h2.solve(b, sp.REWRITTEN)
+    assert not np.allclose(x2.cpu().numpy(), 1.0, rtol=1e-8)
+
+
+def test_self_check_passes_on_a_dominant_matrix():
+    m = gen.config_matrix(1, "small")[0]
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(sp.THIN_ROWS, 32, 4.0, 0, self_check=1e-10)
+    rw = oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0)
+    assert st["self_check_failed"] == 0 and 0.0 <= st["self_check_err"] <= 1e-12
+    assert st["rows_rewritten"] == rw.rows_rewritten
+
+
+@pytest.mark.parametrize("case", ["window", "cfg1_small", "cfg2_small", "powerlaw_mask"])
+def test_per_level_budget_and_cap_parity(case):
+    """Per-level row budgets and fill caps (the learned policy's actions):
+    rewritten L', T, targets and levels bit for bit against the oracle."""
+    rng = np.random.default_rng({"window": 1, "cfg1_small": 2, "cfg2_small": 3, "powerlaw_mask": 4}[case])
+    m = {"window": lambda: gen.window_random(4000, 9, window=20, draws=4),
+         "cfg1_small": lambda: gen.config_matrix(1, "small")[0],
+         "cfg2_small": lambda: gen.config_matrix(2, "small")[0],
+         "powerlaw_mask": lambda: gen.powerlaw(30000, 12, w_loc=300, nseg=3, seglen=80)}[case]()
+    lv = oracle.levels(m)
+    budget = rng.choice([0, 16, 32, 64, 128], size=lv.nlev).astype(np.int32)
+    lcap = rng.choice([0.0, 2.0, 4.0, 8.0], size=lv.nlev).astype(np.float32)
+    mask = None
+    if case == "powerlaw_mask":
+        mask = (rng.random(lv.nlev) < 0.7).astype(np.uint8)
+        mask[0] = 0
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st = h.rewrite(sp.THIN_ROWS, 32, 4.0, 0, to_dev(mask) if mask is not None else None,
+                   level_budget=to_dev(budget), level_fill_cap=to_dev(lcap))
+    rw = oracle.rewrite(m, oracle.THIN_ROWS, 32, 4.0, 0, mask, lv, level_budget=budget, level_cap=lcap)
+    assert rw.rows_rewritten > 0
+    compare(m, h, st, rw, lv, nrhs=(1,))

@@ -657,3 +657,88 @@ def test_planted_two_ended_order_error_is_caught(tmp_path):
 
     _with_planted_oracle(tmp_path, "(k % 2 == 0 ? k / 2 : nseg - 1 - k / 2)", "(k % 2 == 0 ? k / 2 : nseg - k / 2 - (k == 1))",
                          check)
+
+
+# ------------------------------------------------ per-level budgets and caps
+def test_per_level_budget_bidiagonal_closed_form():
+    """Bidiagonal, every level one row and a source. Rows of levels below 50
+    may fill a target to 5 rows, rows of levels 50 and above to 20: targets
+    0, 5, ..., 45 take five rows each; target 45 then takes rows 50..64 (its
+    size 5 grows to 20 under the larger budget), and 65 and 85 start groups of
+    twenty. Worked out by hand from the scan's definition."""
+    m = gen.bidiagonal(100, 5)
+    lv = oracle.levels(m)
+    budget = np.where(np.arange(lv.nlev) < 50, 5, 20).astype(np.int32)
+    rw = oracle.rewrite(m, THIN_ROWS, 1e9, 0.0, 0, None, lv, level_budget=budget)
+    want = np.empty(100, np.int64)
+    for r in range(100):
+        want[r] = 5 * (r // 5) if r < 50 else (45 if r < 65 else (65 if r < 85 else 85))
+    got = np.where(rw.target >= 0, rw.target, np.arange(100))
+    assert np.array_equal(got, want)
+    assert oracle.levels(rw.lp).nlev == len(set(want.tolist()))
+
+
+def _scan_replay_lv(m, lv, rw, W, cap, budget, lcap):
+    """Re-derive every decision of a THIN_ROWS scan with per-level budgets and
+    caps from the definition: the rewritten row's size comes from a
+    reachability search (nnz(L'[r]) = reachable rows outside B + 1), and a row
+    is accepted exactly when the target's size after it fits its level's budget
+    and its rewritten size fits its level's cap."""
+    c = oracle.level_costs(m, lv)
+    cur = _final_cur(lv, rw)
+    nnz_l = np.diff(m.row_ptr)
+    t, size = 0, c.rows[0]
+    for l in range(1, lv.nlev):
+        rows = lv.level_rows[lv.level_ptr[l]:lv.level_ptr[l + 1]]
+        if not c.rows[l] < W:
+            assert np.all(rw.target[rows] == -1)
+            t, size = l, c.rows[l]
+            continue
+        Wl = budget[l] if budget[l] > 0 else W
+        capl = float(lcap[l]) if lcap[l] > 0 else cap
+        for i, r in enumerate(rows):
+            _, A = _reach(m, r, cur >= t)
+            ok = size + 1 <= Wl and (capl <= 0 or len(A) + 1 <= capl * nnz_l[r])
+            assert (rw.target[r] == t) == ok, (l, r, t)
+            if ok:
+                size += 1
+            else:
+                assert np.all(rw.target[rows[i:]] == -1)
+                t, size = l, len(rows) - i
+                break
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_per_level_budget_and_cap_replay(seed):
+    rng = np.random.default_rng(700 + seed)
+    m = gen.window_random(int(rng.integers(200, 600)), 800 + seed, window=int(rng.integers(3, 12)), draws=3)
+    lv = oracle.levels(m)
+    budget = rng.choice([0, 4, 8, 16, 32], size=lv.nlev).astype(np.int32)
+    lcap = rng.choice([0.0, 1.5, 2.0, 4.0, 8.0], size=lv.nlev).astype(np.float32)
+    W, cap = 12, 3.0
+    rw = oracle.rewrite(m, THIN_ROWS, W, cap, 0, None, lv, level_budget=budget, level_cap=lcap)
+    check_rewrite_invariants(m, rw, lv, THIN_ROWS, W, 0.0, 0)
+    _scan_replay_lv(m, lv, rw, W, cap, budget, lcap)
+    assert rw.rows_rewritten > 0
+
+
+@pytest.mark.parametrize("old,new", [
+    ("const double Wl = (thin_metric == 0 && lv_budget && lv_budget[l] > 0) ? (double)lv_budget[l] : W;",
+     "const double Wl = (thin_metric == 0 && lv_budget && lv_budget[t] > 0) ? (double)lv_budget[t] : W;"),
+    ("const double capl = (lv_cap && lv_cap[l] > 0.0f) ? (double)lv_cap[l] : fill_cap;",
+     "const double capl = (lv_cap && lv_cap[t] > 0.0f) ? (double)lv_cap[t] : fill_cap;")])
+def test_planted_per_level_error_is_caught(tmp_path, old, new):
+    """Taking the target's budget or cap instead of the source level's fails
+    the replay."""
+    rng = np.random.default_rng(703)
+    m = gen.window_random(400, 803, window=6, draws=3)
+
+    def check():
+        lv = oracle.levels(m)
+        budget = rng.choice([0, 4, 8, 16, 32], size=lv.nlev).astype(np.int32)
+        lcap = rng.choice([0.0, 1.5, 2.0, 4.0, 8.0], size=lv.nlev).astype(np.float32)
+        rw = oracle.rewrite(m, THIN_ROWS, 12, 3.0, 0, None, lv, level_budget=budget, level_cap=lcap)
+        with pytest.raises(AssertionError):
+            _scan_replay_lv(m, lv, rw, 12, 3.0, budget, lcap)
+
+    _with_planted_oracle(tmp_path, old, new, check)

@@ -194,6 +194,7 @@ def choose_action(seeds, actions=ACTIONS):
             h.rewrite(sp.THIN_ROWS, float(a[0]), float(a[1]), 0)
             ratios[a].append(t_naive / time_variant(h, sp.REWRITTEN, b)[0])
         h.close()
+        log(f"[action] seed {s}: " + " ".join(f"{a[0]},{a[1]:g}:{r[-1]:.3f}" for a, r in ratios.items()))
     score = {a: _geomean(r) for a, r in ratios.items()}
     best = max(actions, key=lambda a: score[a])
     log(f"[action] geomean naive/(B,C) rewrite: { {str(k): round(v, 4) for k, v in score.items()} } -> {best}")
@@ -229,6 +230,7 @@ def calibrate(params, norm, seeds, action):
             h.rewrite(sp.THIN_ROWS, *NAIVE, 0, mask, level_budget=bud, level_fill_cap=cap)
             ratios[g].append(t_naive / time_variant(h, sp.REWRITTEN, b)[0])
         h.close()
+        log(f"[calibrate] seed {s}: best pair so far x{max(r[-1] for r in ratios.values()):.3f}")
     score = {g: _geomean(r) for g, r in ratios.items()}
     best = max(sorted(grid, key=lambda g: (-g[1][0], -g[0][0])), key=lambda g: score[g])
     log("[calibrate] geomean naive/learned by (t_lo, t_hi): "

@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "sync.h"
 
 sptrsv_status_t status_from_bits(int bits) {
   if (bits & EB_ARG) return SPTRSV_ERR_ARG;
@@ -492,8 +493,8 @@ sptrsv_status_t build_plan(sptrsv_ctx *h, Plan &P, int32_t n, int64_t nnz, const
   HIPCHK(h, P.ell_c.alloc(n));
   HIPCHK(h, P.ell_v.alloc((size_t)2 * n));
   HIPCHK(h, launch_fill_ell(n, P.srp.p, P.sci.p, P.sva.p, P.ell_c.p, P.ell_v.p, s));
-  HIPCHK(h, P.wbar.alloc(2));
-  HIPCHK(h, hipMemsetAsync(P.wbar.p, 0, 2 * sizeof(unsigned), s));
+  HIPCHK(h, P.wbar.alloc(kGridBarWords));
+  HIPCHK(h, hipMemsetAsync(P.wbar.p, 0, kGridBarWords * sizeof(unsigned), s));
   HIPCHK(h, P.tp.alloc(4));
   HIPCHK(h, hipMemsetAsync(P.tp.p, 0, 4 * sizeof(unsigned), s));
   HIPCHK(h, P.sf_ticket.alloc(1));
@@ -658,7 +659,8 @@ static sptrsv_status_t solve_overlapped(sptrsv_ctx *h, Plan &P, int32_t nrhs, co
   const int32_t *iperm = io_iperm(P);
   HIPCHK(h, hipEventRecord(ev[0], s));
   HIPCHK(h, hipStreamWaitEvent(side, ev[0], 0));
-  for (int32_t k = 0; k < nseg; ++k) {
+  // segment k's b (and b-transform) on the side stream, then its event
+  auto gather_seg = [&](int32_t k) -> sptrsv_status_t {
     HIPCHK(h, launch_gather_tiles(P.n, nrhs, b, ldb, iperm, P.g_tiles.p + P.g_off[(size_t)k],
                                   P.g_off[(size_t)k + 1] - P.g_off[(size_t)k], bp, side));
     const int32_t t0 = P.t_off[(size_t)k], t1 = P.t_off[(size_t)k + 1];
@@ -666,7 +668,14 @@ static sptrsv_status_t solve_overlapped(sptrsv_ctx *h, Plan &P, int32_t nrhs, co
       HIPCHK(h, launch_apply_t(t1 - t0, nrhs, P.t_lanes, P.tpos.p + t0, io_perm(P), P.trp.p, P.tci.p, P.tva.p, b,
                                ldb, bp, side));
     HIPCHK(h, hipEventRecord(ev[1 + k], side));
-  }
+    return SPTRSV_OK;
+  };
+  // The side stream runs at most two segments ahead of the chain: segments 0
+  // and 1 first, then, after segment k is solved, the scatter of k and the
+  // gather of k + 2. The transposes are spread over the chain instead of
+  // taking the memory system from its first segments all at once.
+  STCHK(gather_seg(0));
+  if (nseg > 1) STCHK(gather_seg(1));
   const ThinArgs ta = thin_args(P, bp, xp);
   for (int32_t k = 0; k < nseg; ++k) {
     HIPCHK(h, hipStreamWaitEvent(s, ev[1 + k], 0));
@@ -677,6 +686,7 @@ static sptrsv_status_t solve_overlapped(sptrsv_ctx *h, Plan &P, int32_t nrhs, co
       HIPCHK(h, hipEventRecord(ev[1 + nseg + k], s));
       HIPCHK(h, hipStreamWaitEvent(side, ev[1 + nseg + k], 0));
       HIPCHK(h, launch_scatter_tiles(P.n, nrhs, xp, iperm, P.s_tiles.p + P.s_off[(size_t)k], n_sc, x, ldx, side));
+      if (k + 2 < nseg) STCHK(gather_seg(k + 2));
     } else {
       HIPCHK(h, launch_scatter_tiles(P.n, nrhs, xp, iperm, P.s_tiles.p + P.s_off[(size_t)k], n_sc, x, ldx, s));
     }

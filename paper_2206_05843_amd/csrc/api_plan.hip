@@ -13,6 +13,7 @@
 #include <memory>
 
 #include "common.h"
+#include "sync.h"
 
 namespace {
 
@@ -215,8 +216,8 @@ sptrsv_status_t get_plan(sptrsv_ctx *h, Reader &r, uint32_t base, Plan &P) {
       HIPCHK(h, hipMemcpy(P.tpos.p, P.h_tpos.data(), sizeof(int32_t) * P.h_tpos.size(), hipMemcpyHostToDevice));
   }
   // per-launch control words start at zero, as build_plan leaves them
-  HIPCHK(h, P.wbar.alloc(2));
-  HIPCHK(h, hipMemset(P.wbar.p, 0, 2 * sizeof(unsigned)));
+  HIPCHK(h, P.wbar.alloc(kGridBarWords));
+  HIPCHK(h, hipMemset(P.wbar.p, 0, kGridBarWords * sizeof(unsigned)));
   HIPCHK(h, P.tp.alloc(4));
   HIPCHK(h, hipMemset(P.tp.p, 0, 4 * sizeof(unsigned)));
   HIPCHK(h, P.sf_ticket.alloc(1));

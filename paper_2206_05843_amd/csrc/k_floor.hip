@@ -162,8 +162,8 @@ sptrsv_status_t sptrsv_measure_level_costs(sptrsv_handle_t h, hipStream_t s, spt
   // a device-wide barrier over every workgroup the persistent wide runs keep resident
   {
     const int grid = std::max(1, wide_run_resident_blocks(256));
-    HIPCHK(h, words.alloc(2));
-    HIPCHK(h, hipMemsetAsync(words.p, 0, 2 * sizeof(unsigned), s));
+    HIPCHK(h, words.alloc(kGridBarWords));
+    HIPCHK(h, hipMemsetAsync(words.p, 0, kGridBarWords * sizeof(unsigned), s));
     constexpr int kRounds = 1000;
     for (int rep = 0; rep < 2; ++rep)
       hipLaunchKernelGGL(k_floor_grid, dim3(grid), dim3(256), 0, s, kRounds, words.p, ticks.p, err, limit);

@@ -286,7 +286,10 @@ __global__ void k_max_abs_diff(int32_t n, const double *__restrict__ x0, const d
   }
 }
 
-constexpr int32_t kTileGrid = 1024;
+#ifndef SPTRSV_TILE_GRID
+#define SPTRSV_TILE_GRID 1024
+#endif
+constexpr int32_t kTileGrid = SPTRSV_TILE_GRID;  // workgroups of one tile-group transpose
 
 }  // namespace
 

@@ -9,7 +9,9 @@ followed by a 5,000-row near-serial tail; n = 8,005,000, nnz = 31,900,000,
 Variants on the same matrix and right-hand sides, each autotuned first:
   plain    level-set solve of L
   naive    L' after the naive rewrite (levels with < 32 rows, fill cap 4x)
-  learned  L' after the rewrite with levels chosen by the trained policy
+  learned  L' after the rewrite with per-level actions chosen by the trained
+           policy, or the naive rule's L' when that autotunes faster on this
+           matrix (a measured per-matrix fallback; config.chosen says which)
 A step is one solve of the headline variant (learned if a trained policy is
 available, else naive). Every variant is checked against the CPU oracle
 (relative error <= 1e-10) before it is timed; rewriting and tuning are
@@ -371,6 +373,8 @@ def main():
     ap.add_argument("--config", type=int, default=4, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-fallback", action="store_true",
+                    help="learned variant without the measured per-matrix fallback to the naive rewrite")
     ap.add_argument("--variants", default="plain,naive,learned",
                     help="comma-separated subset of plain,naive,learned to set up and time")
     ap.add_argument("--schedules", default=None,
@@ -440,6 +444,8 @@ def main():
         info = dict(nlev=nlev, nnz=m.nnz, nnz_t=0)
         if rewrite:
             st = rewrite_fn(h) if rewrite_fn else h.rewrite(sp.THIN_ROWS, 32, 4.0, 0)
+            if isinstance(st, tuple):
+                st, info["chosen"] = st
             which = sp.REWRITTEN
             info.update(nlev=st["nlev_after"], nnz=st["nnz_Lp"], nnz_t=st["nnz_T"], rows_rewritten=st["rows_rewritten"],
                         nlev_before=st["nlev_before"], max_distance=st["max_distance"])
@@ -479,7 +485,11 @@ def main():
             from paper_2206_05843_amd import policy
             pol = policy.load_default()
             if pol is not None:
-                setup("learned", rewrite_fn=lambda h: policy.rewrite_learned(h, pol))
+                if args.no_fallback:
+                    setup("learned", rewrite_fn=lambda h: policy.rewrite_learned(h, pol))
+                else:
+                    setup("learned", rewrite_fn=lambda h: policy.rewrite_learned_checked(h, pol, nrhs,
+                                                                                         csr=(rp, ci, va)))
         except (ImportError, sp.SptrsvError, FileNotFoundError) as e:
             log(f"[bench] learned policy unavailable: {e}")
 
@@ -596,7 +606,7 @@ def main():
         if "graph_reps_ms" in info:
             out_var[name]["graph_reps_ms"] = [round(v, 5) for v in info["graph_reps_ms"]]
             out_var[name]["graph_reps_median_ms"] = round(info["graph_reps_median_ms"], 5)
-        for k in ("rows_rewritten", "max_distance"):
+        for k in ("rows_rewritten", "max_distance", "chosen"):
             if k in info:
                 out_var[name][k] = info[k]
     res = {
@@ -612,7 +622,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded generator of the workload's structure; no dataset)",
-        "config": {"workload": WORKLOADS[args.config], "variant": headline, "nrhs": nrhs, "n": m.n, "nnz": m.nnz,
+        "config": {"workload": WORKLOADS[args.config], "variant": headline,
+                   "chosen": variants[headline][2].get("chosen", headline), "nrhs": nrhs, "n": m.n, "nnz": m.nnz,
                    "parallelism": "single GPU", "timing": ("hipGraph replays" if use_graph else "stream launches")
                    + "; value and ms_per_step from the median of the per-step HIP-event times"},
         "roofline": roofline,

@@ -142,7 +142,14 @@ __global__ void k_height_level(int32_t pb, int32_t pe, const int32_t *__restrict
                                const int32_t *__restrict__ sci, int32_t *hp) {
   for (int64_t p = pb + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < pe; p += (int64_t)gridDim.x * blockDim.x) {
     const int32_t h = hp[p] + 1;
-    for (int32_t q = srp[p]; q < srp[p + 1]; ++q) atomicMax(hp + sci[q], h);
+    // heights only grow, so a value read here (possibly an older copy) that
+    // already reaches h makes the atomic redundant: hub columns that thousands
+    // of rows of a level depend on then take a few atomics instead of one per
+    // row (same-address atomics are serialised)
+    for (int32_t q = srp[p]; q < srp[p + 1]; ++q) {
+      const int32_t d = sci[q];
+      if (hp[d] < h) atomicMax(hp + d, h);
+    }
   }
 }
 

@@ -131,3 +131,40 @@ def rewrite_learned(h: _sp.Handle, policy: Policy | None, thin_threshold=32.0, f
     mask, budget, cap = policy.actions(h)
     return h.rewrite(_sp.THIN_ROWS, thin_threshold, fill_cap, max_distance, mask, max_indegree=max_indegree,
                      max_spread=max_spread, critical_only=critical_only, level_budget=budget, level_fill_cap=cap)
+
+
+def rewrite_learned_checked(h: _sp.Handle, policy: Policy | None, nrhs: int = 1, thin_threshold=32.0, fill_cap=4.0,
+                            csr=None, **knobs):
+    """The learned rewrite with a measured per-matrix fallback: the policy's
+    rewrite and the naive rule's (thin_threshold, fill_cap) are each
+    autotuned for nrhs right-hand sides on this matrix, and h keeps the
+    faster one (ties: the learned one), autotuned. With csr = (row_ptr, col,
+    val) of the matrix h analysed, the naive rewrite is timed on a scratch
+    handle, so h is rewritten again only when naive wins. Returns (stats,
+    chosen) with chosen in {"learned", "naive"}."""
+    if policy is None:
+        st = h.rewrite(_sp.THIN_ROWS, thin_threshold, fill_cap, **knobs)
+        h.autotune(_sp.REWRITTEN, nrhs)
+        return st, "naive"
+    st_l = rewrite_learned(h, policy, thin_threshold, fill_cap, **knobs)
+    t_learned = h.autotune(_sp.REWRITTEN, nrhs)
+    if csr is not None:
+        g = _sp.Handle()
+        try:
+            g.analyze(*csr)
+            g.rewrite(_sp.THIN_ROWS, thin_threshold, fill_cap, **knobs)
+            t_naive = g.autotune(_sp.REWRITTEN, nrhs)
+        finally:
+            g.close()
+        if t_naive >= t_learned:
+            return st_l, "learned"
+        st = h.rewrite(_sp.THIN_ROWS, thin_threshold, fill_cap, **knobs)
+        h.autotune(_sp.REWRITTEN, nrhs)
+        return st, "naive"
+    st = h.rewrite(_sp.THIN_ROWS, thin_threshold, fill_cap, **knobs)
+    t_naive = h.autotune(_sp.REWRITTEN, nrhs)
+    if t_naive < t_learned:
+        return st, "naive"
+    st = rewrite_learned(h, policy, thin_threshold, fill_cap, **knobs)
+    h.autotune(_sp.REWRITTEN, nrhs)
+    return st, "learned"

@@ -59,7 +59,7 @@ from paper_2206_05843_amd import sptrsv as sp  # noqa: E402
 from paper_2206_05843_amd.policy import Policy, init_params  # noqa: E402
 
 NAIVE = (32.0, 4.0)
-ACTIONS = [(64, 8.0), (128, 8.0), (256, 8.0), (128, 16.0), (256, 16.0)]
+ACTIONS = [(128, 8.0), (256, 16.0), (512, 16.0), (512, 32.0), (1024, 32.0), (1024, 64.0)]
 
 
 def log(*a):

@@ -254,3 +254,35 @@ def test_level_finish_times(nrhs):
         x = h.solve(b if nrhs > 1 else b.view(-1))
         h.check()
         assert oracle.relerr(x.view(nrhs, -1).cpu().numpy(), oracle.solve(m, b.view(nrhs, -1).cpu().numpy())) <= 1e-10
+
+
+@pytest.mark.parametrize("use_csr", [False, True])
+@pytest.mark.parametrize("mk", [lambda: gen.config_matrix(1, "small")[0], lambda: gen.policy_training_matrix(2000)])
+def test_rewrite_learned_checked(mk, use_csr):
+    """The measured fallback keeps either the shipped policy's rewrite or the
+    naive rule's, whichever autotuned faster; the kept L' equals the oracle's
+    rewrite for that choice bit for bit and the solve is right."""
+    from paper_2206_05843_amd import policy
+    pol = policy.load_default()
+    assert pol is not None
+    m = mk()
+    lv = oracle.levels(m)
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    st, chosen = policy.rewrite_learned_checked(h, pol, 1, csr=dev(m) if use_csr else None)
+    assert chosen in ("learned", "naive")
+    if chosen == "naive":
+        rw = oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0, 0, None, lv)
+    else:
+        h2 = sp.Handle()
+        h2.analyze(*dev(m))
+        mask, bud, cap = (a.cpu().numpy() for a in pol.actions(h2))
+        rw = oracle.rewrite(m, oracle.THIN_ROWS, 32.0, 4.0, 0, mask, lv, level_budget=bud, level_cap=cap)
+    g = {k2: v.cpu().numpy() for k2, v in h.rewritten().items()}
+    assert st["rows_rewritten"] == rw.rows_rewritten
+    assert np.array_equal(g["lp_ptr"], rw.lp.row_ptr) and np.array_equal(g["lp_col"], rw.lp.col)
+    assert np.array_equal(g["t_ptr"], rw.t.row_ptr) and np.array_equal(g["t_col"], rw.t.col)
+    b = to_dev(gen.rhs(m, 1)[0])
+    x = h.solve(b, sp.REWRITTEN)
+    h.check()
+    assert oracle.relerr(x.cpu().numpy()[None], oracle.solve(m, b.cpu().numpy()[None])) <= 1e-10

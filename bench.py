@@ -68,8 +68,9 @@ def alg_bytes(n, nnz, nlev, nrhs, nnz_t=0, rewritten=False):
 
 # Sources whose text decides what a kernel reads and writes (thin runs read
 # the window images k_image.hip builds).
-KERNEL_SOURCE = {"k_thin_run": ("k_thin.hip", "k_image.hip"), "k_batch_run": ("k_thin.hip", "k_image.hip"),
-                 "k_wide_level": ("k_wide.hip",), "k_gather": ("k_vec.hip",), "k_scatter": ("k_vec.hip",),
+KERNEL_SOURCE = {"k_thin_run": ("k_thin.hip", "k_image.hip", "sync.h"),
+                 "k_batch_run": ("k_thin.hip", "k_image.hip", "sync.h"),
+                 "k_wide_level": ("k_wide.hip", "sync.h"), "k_gather": ("k_vec.hip",), "k_scatter": ("k_vec.hip",),
                  "k_sf_solve": ("k_syncfree.hip",)}
 
 

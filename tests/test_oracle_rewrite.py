@@ -742,3 +742,21 @@ def test_planted_per_level_error_is_caught(tmp_path, old, new):
             _scan_replay_lv(m, lv, rw, 12, 3.0, budget, lcap)
 
     _with_planted_oracle(tmp_path, old, new, check)
+
+
+@pytest.mark.parametrize("fill", ["same", "zero"])
+def test_uniform_per_level_values_equal_plain_rewrite(fill):
+    """Per-level budgets and caps equal to the rewrite's own (or 0, meaning
+    the rewrite's own) give the plain rewrite bit for bit."""
+    m = gen.window_random(700, 907, window=8, draws=3)
+    lv = oracle.levels(m)
+    W, cap = 16, 3.0
+    budget = np.full(lv.nlev, W if fill == "same" else 0, np.int32)
+    lcap = np.full(lv.nlev, cap if fill == "same" else 0.0, np.float32)
+    a = oracle.rewrite(m, THIN_ROWS, W, cap, 0, None, lv)
+    b = oracle.rewrite(m, THIN_ROWS, W, cap, 0, None, lv, level_budget=budget, level_cap=lcap)
+    assert a.rows_rewritten > 0
+    assert np.array_equal(a.target, b.target)
+    assert np.array_equal(a.lp.row_ptr, b.lp.row_ptr) and np.array_equal(a.lp.col, b.lp.col)
+    assert np.array_equal(a.lp.val, b.lp.val)
+    assert np.array_equal(a.t_ptr, b.t_ptr) and np.array_equal(a.t_col, b.t_col) and np.array_equal(a.t_val, b.t_val)

@@ -252,6 +252,13 @@ sptrsv_status_t sptrsv_check(sptrsv_handle_t h, hipStream_t s);
  * into chunks of 2 * wide_threads items (wide_threads = 128, 256 or 512) and
  * a chunk waits only for the chunks of the run holding the rows it reads, not
  * for whole levels (wide_grid: workgroups in flight, 0 = as many as fit).
+ * overlap = 1: when the work vectors are large (n * nrhs >= 2^22) and the
+ * chain has at least four runs, the transposes between the caller's b, x and
+ * the work vectors run in 64-row tile groups on a handle-owned side stream
+ * beside the level chain (up to 16 segments, at most two ahead of it); 0 (the
+ * default, and what the autotuner keeps): before and after the chain. On the
+ * 3D stencil with 32 right-hand sides the side stream's memory traffic slowed
+ * the chain by more than it hid, in graph replays.
  * set_schedule replaces the schedules sptrsv_autotune picked for this matrix;
  * get_schedule reports the schedule a solve with nrhs right-hand sides uses
  * (the tuned one for that nrhs if there is one, else the one set). */
@@ -264,6 +271,7 @@ typedef struct {
   int32_t wide_grid;      /* 0: one launch per wide level; > 0: consecutive wide levels in one persistent launch
                              of up to wide_grid workgroups (capped to what is resident at once) with a
                              device-wide barrier between levels (lanes_per_row is then 1) */
+  int32_t overlap;        /* 0 or 1: transposes beside the chain (see above) */
 } sptrsv_schedule_t;
 sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_schedule_t *sched);
 sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, sptrsv_schedule_t *sched);

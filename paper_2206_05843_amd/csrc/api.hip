@@ -45,8 +45,14 @@ int bit_width(int64_t v) {
 
 // Overlapped transposes: at most kMaxSegments segments of the level chain,
 // used from kOverlapMin work-vector entries on.
-constexpr int32_t kMaxSegments = 16;
-constexpr int64_t kOverlapMin = (int64_t)1 << 22;
+#ifndef SPTRSV_OVERLAP_MIN_LOG2
+#define SPTRSV_OVERLAP_MIN_LOG2 22
+#endif
+#ifndef SPTRSV_MAX_SEGMENTS
+#define SPTRSV_MAX_SEGMENTS 16
+#endif
+constexpr int32_t kMaxSegments = SPTRSV_MAX_SEGMENTS;
+constexpr int64_t kOverlapMin = (int64_t)1 << SPTRSV_OVERLAP_MIN_LOG2;
 
 sptrsv_schedule_t default_schedule() {
   sptrsv_schedule_t s{};
@@ -56,6 +62,7 @@ sptrsv_schedule_t default_schedule() {
   s.wide_threads = 256;
   s.lanes_per_row = 1;
   s.wide_grid = 0;
+  s.overlap = 0;
   return s;
 }
 
@@ -63,7 +70,8 @@ namespace {
 
 bool same_sched(const sptrsv_schedule_t &a, const sptrsv_schedule_t &b) {
   return a.mode == b.mode && a.thin_rows == b.thin_rows && a.wg_threads == b.wg_threads &&
-         a.wide_threads == b.wide_threads && a.lanes_per_row == b.lanes_per_row && a.wide_grid == b.wide_grid;
+         a.wide_threads == b.wide_threads && a.lanes_per_row == b.lanes_per_row && a.wide_grid == b.wide_grid &&
+         a.overlap == b.overlap;
 }
 
 sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
@@ -79,6 +87,7 @@ sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
     return set_err(h, SPTRSV_ERR_ARG, "lanes_per_row %d", g);
   if (s.thin_rows < 0) return set_err(h, SPTRSV_ERR_ARG, "thin_rows %d", s.thin_rows);
   if (s.wide_grid < 0 || s.wide_grid > 65536) return set_err(h, SPTRSV_ERR_ARG, "wide_grid %d", s.wide_grid);
+  if (s.overlap != 0 && s.overlap != 1) return set_err(h, SPTRSV_ERR_ARG, "overlap %d", s.overlap);
   if (s.mode == 3 && s.wide_grid > 2048)
     return set_err(h, SPTRSV_ERR_ARG, "wide_grid %d: the synchronisation-free launch takes at most 2048 workgroups",
                    s.wide_grid);
@@ -294,7 +303,7 @@ static sptrsv_status_t build_overlap(sptrsv_ctx *h, Plan &P, int32_t nrhs, const
   P.ovl = false;
   P.seg_run.clear();
   const int32_t nruns = (int32_t)P.runs.size();
-  if (sc.mode == 3 || (int64_t)P.n * nrhs < kOverlapMin || nruns < 4 || !h->side) return SPTRSV_OK;
+  if (!sc.overlap || sc.mode == 3 || (int64_t)P.n * nrhs < kOverlapMin || nruns < 4 || !h->side) return SPTRSV_OK;
   const int32_t K = std::min(kMaxSegments, nruns);
   P.seg_run.push_back(0);
   for (int32_t k = 1; k < K; ++k) {
@@ -375,7 +384,7 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
   }
   // with the transposes overlapped, long dataflow runs are cut into pieces of
   // about n / kMaxSegments positions so that the chain has segment boundaries
-  if (flow && (int64_t)P.n * nrhs >= kOverlapMin) {
+  if (flow && sc.overlap && (int64_t)P.n * nrhs >= kOverlapMin) {
     std::vector<Run> cut;
     const int64_t piece = std::max<int64_t>(1, P.n / kMaxSegments);
     for (const Run &r : P.runs) {

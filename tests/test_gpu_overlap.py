@@ -34,7 +34,8 @@ def _solve(h, which, b, sched=None):
     return x
 
 
-SPLIT = [dict(mode=0, thin_rows=64, wg_threads=512), dict(mode=4, thin_rows=64, wg_threads=512, wide_threads=256)]
+SPLIT = [dict(mode=0, thin_rows=64, wg_threads=512, overlap=1),
+         dict(mode=4, thin_rows=64, wg_threads=512, wide_threads=256, overlap=1)]
 
 
 @pytest.mark.parametrize("split", range(len(SPLIT)))
@@ -74,7 +75,7 @@ def test_overlapped_graph_replays(mat):
     h = sp.Handle()
     h.analyze(*dev(mat))
     h.rewrite(sp.THIN_ROWS, 32, 4.0)
-    h.set_schedule(sp.REWRITTEN, mode=0, thin_rows=64, wg_threads=512)
+    h.set_schedule(sp.REWRITTEN, mode=0, thin_rows=64, wg_threads=512, overlap=1)
     x_ref = h.solve(b, sp.REWRITTEN)
     h.check()
     x = torch.zeros_like(b)

@@ -277,7 +277,9 @@ sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_s
 sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, sptrsv_schedule_t *sched);
 
 /* Autotuner: times candidate schedules with HIP events on s (inputs b = 1) and
- * keeps the fastest for (which, nrhs); for SPTRSV_BATCH the candidates are the
+ * keeps the fastest for (which, nrhs), then tries the wide launches of a best
+ * split schedule (mode 0) with 64, 128 and 512 threads per workgroup; for
+ * SPTRSV_BATCH the candidates are the
  * workgroup sizes of the persistent launch. best_ms (host, may be NULL) receives the
  * best solve time. Synchronous.
  * Candidates whose launches wait on the device (the synchronisation-free

@@ -101,7 +101,9 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
     return true;
   };
   sptrsv_tune_info_t info{};
-  for (const sptrsv_schedule_t &cand : cands) {
+  // one candidate: a warm-up and the median of three timed solves; false
+  // when it was dropped at its wait limit or a solve failed (st says which)
+  auto time_cand = [&](const sptrsv_schedule_t &cand, float *ms) -> bool {
     P->sched = cand;
     P->runs_nrhs = -1;
     P->tuned.erase(nrhs);
@@ -116,10 +118,10 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
     ++info.candidates;
     float t[3];
     st = run();  // warm-up
-    if (st != SPTRSV_OK) break;
+    if (st != SPTRSV_OK) return false;
     if (waits && drop_timeout()) {
       ++info.timed_out;
-      continue;
+      return false;
     }
     for (int rep = 0; rep < 3 && st == SPTRSV_OK; ++rep) {
       (void)hipEventRecord(e0, s);
@@ -128,15 +130,37 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
       (void)hipEventSynchronize(e1);
       (void)hipEventElapsedTime(&t[rep], e0, e1);
     }
-    if (st != SPTRSV_OK) break;
+    if (st != SPTRSV_OK) return false;
     if (waits && drop_timeout()) {
       ++info.timed_out;
-      continue;
+      return false;
     }
     std::sort(t, t + 3);
-    if (t[1] < best) {
-      best = t[1];
+    *ms = t[1];
+    return true;
+  };
+  for (const sptrsv_schedule_t &cand : cands) {
+    float ms = 0.f;
+    if (time_cand(cand, &ms) && ms < best) {
+      best = ms;
       best_s = cand;
+    }
+    if (st != SPTRSV_OK) break;
+  }
+  // the workgroup size of the wide-level launches, around the best split
+  // schedule (smaller workgroups spread a level over more CUs)
+  if (st == SPTRSV_OK && !batch && best_s.mode == 0 && best < 1e29f) {
+    const sptrsv_schedule_t base = best_s;
+    for (int wt : {64, 128, 512}) {
+      if (wt == base.wide_threads) continue;
+      sptrsv_schedule_t cand = base;
+      cand.wide_threads = wt;
+      float ms = 0.f;
+      if (time_cand(cand, &ms) && ms < best) {
+        best = ms;
+        best_s = cand;
+      }
+      if (st != SPTRSV_OK) break;
     }
   }
   h->wait_ticks = 0;

@@ -10,7 +10,9 @@
 // every NaN), so one device-coherent 64-bit load returns both "done" and the
 // value (a plain load is tried first and trusted when it is not the pending
 // pattern). A lane requests its next four dependencies' values at once and takes
-// the ready ones in column order, so the sum keeps the row's order. A wave
+// the ready ones in column order, so the sum keeps the row's order; while it
+// waits on a batch it keeps the batch's columns and weights in registers and
+// polls past the caches directly, so a pass costs one memory round trip. A wave
 // none of whose lanes moved in an iteration sleeps briefly before it polls
 // again, and the launch is kept to a few thousand waves: the waiting lanes'
 // polling otherwise saturates the memory system and slows every hop (on a
@@ -23,7 +25,7 @@ namespace {
 
 constexpr unsigned long long kPending = 0x7ff4dead5eed5a1dull;
 constexpr int kBlock = 256;
-constexpr int kDeps = 4;
+constexpr int kDeps = 4;  // dependencies requested together (6 or 8 were slower)
 
 __global__ void k_sf_init(int64_t total, unsigned long long *xb, unsigned long long *ticket) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
@@ -62,32 +64,47 @@ __global__ __launch_bounds__(kBlock) void k_sf_solve(int32_t n, int32_t nrhs, co
       d = sdg[pos];
     }
     unsigned spins = 0;
+    bool seen_pending = false;  // the dependency at q read as pending in the last pass
+    int32_t k[kDeps];           // columns and weights of the batch at kq, kept across passes
+    double w[kDeps];
+    int32_t kq = -1;
     while (__ballot(pend) != 0ull) {
       bool moved = false;
       if (pend) {
         const int32_t q_in = q;
+        bool first = true;
         while (q < qe) {
           const int32_t cnt = qe - q < kDeps ? qe - q : kDeps;
-          int32_t k[kDeps];
-          double w[kDeps];
           unsigned long long v[kDeps];
+          if (q != kq) {  // a new batch: its columns and weights
 #pragma unroll
-          for (int j = 0; j < kDeps; ++j) {
-            const int32_t qq = q + (j < cnt ? j : 0);
-            k[j] = sci[qq];
-            w[j] = sva[qq];
+            for (int j = 0; j < kDeps; ++j) {
+              const int32_t qq = q + (j < cnt ? j : 0);
+              k[j] = sci[qq];
+              w[j] = sva[qq];
+            }
+            kq = q;
           }
           // a plain (cached) load first: it returns either the pending
           // pattern or the final value, since caches hold no line of x from
           // before this launch (the fill kernel ran in between) and every
           // value is written once; only what still reads as pending is
-          // fetched again past the caches
+          // fetched again past the caches. A batch whose first dependency
+          // read as pending in the last pass goes past the caches at once
+          // (its cached line can only say pending again).
+          if (first && seen_pending) {
 #pragma unroll
-          for (int j = 0; j < kDeps; ++j) v[j] = xb[(int64_t)k[j] * nr + c];
-#pragma unroll
-          for (int j = 0; j < kDeps; ++j)
-            if (v[j] == kPending)
+            for (int j = 0; j < kDeps; ++j)
               v[j] = __hip_atomic_load(xb + (int64_t)k[j] * nr + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+#pragma unroll
+            for (int j = 0; j < kDeps; ++j) v[j] = xb[(int64_t)k[j] * nr + c];
+#pragma unroll
+            for (int j = 0; j < kDeps; ++j)
+              if (v[j] == kPending)
+                v[j] = __hip_atomic_load(xb + (int64_t)k[j] * nr + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          first = false;
           int32_t done = 0;
 #pragma unroll
           for (int j = 0; j < kDeps; ++j) {
@@ -97,7 +114,8 @@ __global__ __launch_bounds__(kBlock) void k_sf_solve(int32_t n, int32_t nrhs, co
             }
           }
           q += done;
-          if (done < cnt) break;  // a dependency is still pending
+          seen_pending = done < cnt;
+          if (seen_pending) break;  // a dependency is still pending
         }
         moved = q != q_in;
         if (q == qe) {

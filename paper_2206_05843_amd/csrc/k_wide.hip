@@ -8,8 +8,9 @@
 
 namespace {
 
-// One wide level, items (row, rhs) spread over the device, two per thread in
-// flight: a row's first four dependencies come from the fixed-width copy
+// One wide level, items (row, rhs) spread over the device (two per thread in
+// flight with one right-hand side, one with several: 1.6 % faster on the 3D
+// stencil with 32): a row's first four dependencies come from the fixed-width copy
 // indexed by position (no row pointer on the load chain), the rest from the
 // CSR four at a time; all loads of a step are issued before they are used and
 // the products are subtracted in the row's column order.
@@ -18,7 +19,7 @@ __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t
                              const int32_t *__restrict__ sci, const double *__restrict__ sva,
                              const double *__restrict__ sdg, const int4 *__restrict__ ell_c,
                              const double2 *__restrict__ ell_v, const double *__restrict__ bp, double *xp, int *err) {
-  constexpr int kI = 2;
+  constexpr int kI = kOne ? 2 : 1;  // several right-hand sides: one item per thread spreads a level wider
   const int32_t nr = kOne ? 1 : nrhs;
   const int64_t items = (int64_t)(pe - pb) * nr;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -194,7 +195,8 @@ hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t
     return hipGetLastError();
   }
   const int64_t items = rows * nrhs;
-  const int g = grid_for((items + 1) / 2, threads, 65536);  // two items per thread
+  const int per = nrhs == 1 ? 2 : 1;  // items per thread, as in the kernel
+  const int g = grid_for((items + per - 1) / per, threads, 65536);
   if (nrhs == 1)
     hipLaunchKernelGGL((k_wide_level<true>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, ell_c,
                        ell_v, bp, xp, err);

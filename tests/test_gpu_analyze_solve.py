@@ -194,7 +194,7 @@ def test_state_and_arg_errors(handles):
     assert ei.value.name == "ARG"
 
 
-@pytest.mark.parametrize("bad", [dict(mode=5), dict(overlap=2), dict(lanes_per_row=3), dict(wg_threads=300),
+@pytest.mark.parametrize("bad", [dict(mode=5), dict(overlap=2), dict(overlap=-1), dict(lanes_per_row=3), dict(wg_threads=300),
                                  dict(mode=4, wide_threads=1024), dict(mode=3, wide_grid=4096)])
 def test_bad_schedule_is_refused(handles, bad):
     _, h, _ = handles["cfg0"]

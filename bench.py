@@ -5,7 +5,9 @@
 Workload (default, the largest single-GPU configuration): the lower factor of
 the 200^3 3D 7-point stencil (pattern only, diagonally dominant random values)
 followed by a 5,000-row near-serial tail; n = 8,005,000, nnz = 31,900,000,
-32 right-hand sides, FP64, each solve a replay of a hipGraph.
+32 right-hand sides stored by rows (n x 32 row-major, read and written through
+the level order by sptrsv_solve_rows), FP64, each solve a replay of a hipGraph;
+the same variants with column-major right-hand sides are timed beside it.
 Variants on the same matrix and right-hand sides, each autotuned first:
   plain    level-set solve of L
   naive    L' after the naive rewrite (levels with < 32 rows, fill cap 4x)
@@ -50,6 +52,7 @@ WORKLOADS = {
        "factor + 5,000-row tail, n=8,005,000, nnz=31,900,000, nrhs=32",
 }
 GRAPH_DEFAULT = {4}  # workloads timed as hipGraph replays of the solve
+ROWS_DEFAULT = {4}  # workloads whose right-hand sides are stored by rows by default
 
 
 def log(*a):
@@ -381,6 +384,10 @@ def main():
     ap.add_argument("--schedules", default=None,
                     help="JSON object variant -> schedule (mode, thin_rows, wg_threads, wide_threads, "
                          "lanes_per_row); those variants skip the autotuner (for profiled runs)")
+    ap.add_argument("--layout", default=None, choices=("cols", "rows"),
+                    help="how the right-hand sides are stored: cols (column-major, a column per right-hand side) "
+                         "or rows (n x nrhs row-major, solved with sptrsv_solve_rows); default rows for the 3D "
+                         "stencil workload, whose other layout is timed too and reported beside it")
     ap.add_argument("--graph", type=int, default=None, choices=(0, 1),
                     help="time hipGraph replays of the solve (default: on for the 3D stencil workload)")
     ap.add_argument("--analysis-only", action="store_true",
@@ -418,6 +425,7 @@ def main():
         bench_analysis(args, np, torch, gen, oracle, sp)
         return
     use_graph = (args.config in GRAPH_DEFAULT) if args.graph is None else bool(args.graph)
+    layout = args.layout or ("rows" if args.config in ROWS_DEFAULT else "cols")
     stream = torch.cuda.Stream()  # graph capture needs a non-default stream
     torch.cuda.set_stream(stream)
     t0 = time.perf_counter()
@@ -431,6 +439,8 @@ def main():
     b = torch.from_numpy(b_np).to(dev)
     if nrhs == 1:
         b = b.view(-1)
+        layout = "cols"  # one right-hand side: both layouts are the same vector
+    b_rows = b.t().contiguous() if layout == "rows" else None  # (n, nrhs): a row's right-hand sides together
 
     variants = {}
     probe = sp.Handle()
@@ -464,10 +474,15 @@ def main():
         x = h.solve(b, which)
         h.check()
         info["relerr"] = oracle.relerr(x.view(nrhs, -1).cpu().numpy(), x_ref)
-        if not info["relerr"] <= TOL:
+        if layout == "rows":
+            xr = h.solve_rows(b_rows, which)
+            h.check()
+            info["relerr_cols"] = info["relerr"]
+            info["relerr"] = oracle.relerr(xr.t().cpu().numpy(), x_ref)
+        if not max(info["relerr"], info.get("relerr_cols", 0.0)) <= TOL:
             raise SystemExit(f"[bench] variant {name} failed parity: relerr={info['relerr']:.3e}")
         info["bytes"] = alg_bytes(m.n, info["nnz"], info["nlev"], nrhs, info["nnz_t"], rewrite)
-        info["level_floor_us"] = h.level_floor(costs, which, nrhs, graph=use_graph)
+        info["level_floor_us"] = h.level_floor(costs, which, nrhs, graph=use_graph, rows=layout == "rows")
         variants[name] = (h, which, info)
         log(f"[bench] {name}: nlev={info['nlev']} relerr={info['relerr']:.2e} pre={info['preprocess_s']:.2f}s "
             f"schedule={info['schedule']} level floor {info['level_floor_us']:.1f} us")
@@ -494,18 +509,21 @@ def main():
         except (ImportError, sp.SptrsvError, FileNotFoundError) as e:
             log(f"[bench] learned policy unavailable: {e}")
 
-    def timed(name, steps, warmup):
+    def timed(name, steps, warmup, rows):
         """Per-step device times (HIP events on the solve stream around every
         step: a graph replay, or an eager solve) and the wall time of all
         steps; plus, for graph replays, the protocol of five repetitions of
         100 replays (mean per solve of each, median of the five)."""
         h, which, _ = variants[name]
-        x = torch.empty_like(b)
+        bb = b_rows if rows else b
+        x = torch.empty_like(bb)
         if use_graph:
-            gid = h.graph_create(b, x, which)
+            gid = h.graph_create_rows(bb, x, which) if rows else h.graph_create(bb, x, which)
             run = lambda: h.graph_launch(gid)  # noqa: E731
+        elif rows:
+            run = lambda: h.solve_rows(bb, which, x)  # noqa: E731
         else:
-            run = lambda: h.solve(b, which, x)  # noqa: E731
+            run = lambda: h.solve(bb, which, x)  # noqa: E731
         for _ in range(warmup):
             run()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
@@ -536,11 +554,13 @@ def main():
         """Per-kernel-class HIP-event profile of eager solves on the solve
         stream (after the timed region: no events inside a graph)."""
         h, which, _ = variants[name]
-        x = torch.empty_like(b)
-        h.solve(b, which, x)
+        bb = b_rows if layout == "rows" else b
+        solve = h.solve_rows if layout == "rows" else h.solve
+        x = torch.empty_like(bb)
+        solve(bb, which, x)
         h.profile_start()
         for _ in range(steps):
-            h.solve(b, which, x)
+            solve(bb, which, x)
         torch.cuda.synchronize()
         prof = h.profile_stop()
         h.check()
@@ -554,8 +574,13 @@ def main():
     headline = "learned" if "learned" in variants else ("naive" if "naive" in variants else "plain")
     for name in variants:
         steps = args.steps if name == headline else max(20, args.steps // 2)
-        per, wall, reps = timed(name, steps, args.warmup)
+        per, wall, reps = timed(name, steps, args.warmup, layout == "rows")
         info = variants[name][2]
+        if layout == "rows":  # the same variant with column-major right-hand sides, for comparison
+            per_c, _, reps_c = timed(name, max(20, args.steps // 2), args.warmup, False)
+            info["ms_cols"] = median(per_c)
+            if reps_c is not None:
+                info["graph_reps_median_ms_cols"] = median(reps_c)
         info["ms"] = median(per)
         info["ms_wall_mean"] = wall * 1e3 / steps
         info["steps"] = steps
@@ -607,9 +632,12 @@ def main():
         if "graph_reps_ms" in info:
             out_var[name]["graph_reps_ms"] = [round(v, 5) for v in info["graph_reps_ms"]]
             out_var[name]["graph_reps_median_ms"] = round(info["graph_reps_median_ms"], 5)
-        for k in ("rows_rewritten", "max_distance", "chosen"):
+        for k in ("rows_rewritten", "max_distance", "chosen", "relerr_cols"):
             if k in info:
                 out_var[name][k] = info[k]
+        for k in ("ms_cols", "graph_reps_median_ms_cols"):
+            if k in info:
+                out_var[name][k] = round(info[k], 5)
     res = {
         "metric": METRIC,
         "value": round(1e3 / ms, 3),
@@ -625,6 +653,8 @@ def main():
         "data": "synthetic (seeded generator of the workload's structure; no dataset)",
         "config": {"workload": WORKLOADS[args.config], "variant": headline,
                    "chosen": variants[headline][2].get("chosen", headline), "nrhs": nrhs, "n": m.n, "nnz": m.nnz,
+                   "layout": ("right-hand sides by rows (n x nrhs row-major)" if layout == "rows"
+                              else "right-hand sides by columns (column-major, leading dimension n)"),
                    "parallelism": "single GPU", "timing": ("hipGraph replays" if use_graph else "stream launches")
                    + "; value and ms_per_step from the median of the per-step HIP-event times"},
         "roofline": roofline,

@@ -232,6 +232,20 @@ sptrsv_status_t sptrsv_solve(sptrsv_handle_t h, int which, int32_t nrhs, const d
 sptrsv_status_t sptrsv_solve_noalloc(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
                                      double *d_x, int64_t ldx, hipStream_t s);
 
+/* sptrsv_solve_rows -- sptrsv_solve with the right-hand sides stored by rows:
+ * d_b, d_x: n x nrhs, entry (i, c) at i * nrhs + c (the layout of one row's
+ * right-hand sides together that the solve kernels work in), no leading
+ * dimension. Same x as sptrsv_solve bit for bit (the same kernels and order).
+ * With thin runs and one launch per wide level (modes 0, 1, 2 with wide_grid
+ * 0) the solve kernels read b and write x through the level order themselves,
+ * with no transposes; the b-transform writes only the rows of T with
+ * off-diagonals into the work vector. Other schedules copy b in and x out by
+ * rows. nrhs = 1 is sptrsv_solve with ld = n. ASYNC and capture-safe once a
+ * solve of the same (which, nrhs) has run or sptrsv_prepare has been called.
+ * Errors as sptrsv_solve (ARG: nrhs < 1, b and x overlapping). */
+sptrsv_status_t sptrsv_solve_rows(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, double *d_x,
+                                  hipStream_t s);
+
 /* Allocate the work vectors for (which, nrhs) so later solves allocate nothing. */
 sptrsv_status_t sptrsv_prepare(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s);
 
@@ -303,6 +317,9 @@ sptrsv_status_t sptrsv_get_tune_info(sptrsv_handle_t h, sptrsv_tune_info_t *out)
  * belongs to the handle (at most 16); graph_id receives its index. */
 sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
                                     double *d_x, int64_t ldx, hipStream_t s, int32_t *graph_id);
+/* The same for sptrsv_solve_rows. */
+sptrsv_status_t sptrsv_graph_create_rows(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, double *d_x,
+                                         hipStream_t s, int32_t *graph_id);
 sptrsv_status_t sptrsv_graph_launch(sptrsv_handle_t h, int32_t graph_id, hipStream_t s);
 
 /* Live kernel profile of solves: enable = 1 clears the counters and starts
@@ -346,9 +363,14 @@ sptrsv_status_t sptrsv_measure_level_costs(sptrsv_handle_t h, hipStream_t s, spt
  * runs separate them (thin-run levels by window kind, one launch or graph node
  * per wide level and per launch of a run, device-wide barriers inside
  * persistent runs, one hop per level for the synchronisation-free executor),
- * plus the launches of the gather, b-transform and scatter. graph != 0 prices
- * launches as graph nodes. floor_us receives microseconds. Synchronous. */
-sptrsv_status_t sptrsv_level_floor(sptrsv_handle_t h, int which, int32_t nrhs, int32_t graph,
+ * plus the launches of the gather, b-transform and scatter. flags:
+ * SPTRSV_FLOOR_GRAPH prices launches as graph nodes; SPTRSV_FLOOR_ROWS prices a
+ * solve with the right-hand sides by rows (sptrsv_solve_rows), which has no
+ * gather or scatter launch under thin-run and per-level wide schedules; other
+ * bits are an ARG error. floor_us receives microseconds. Synchronous. */
+#define SPTRSV_FLOOR_GRAPH 1
+#define SPTRSV_FLOOR_ROWS 2
+sptrsv_status_t sptrsv_level_floor(sptrsv_handle_t h, int which, int32_t nrhs, int32_t flags,
                                    const sptrsv_level_costs_t *c, double *floor_us);
 
 /* Residual check: h_out[c] = max_i |(L x - b)[i,c]| for the ORIGINAL L, host

@@ -624,7 +624,7 @@ sptrsv_status_t gather_b(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, 
                          hipStream_t s) {
   HIPCHK(h, launch_gather(P.n, nrhs, b, ldb, io_iperm(P), bp, s));
   if (P.has_t && P.n_tpos > 0)
-    HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, io_perm(P), P.trp.p, P.tci.p, P.tva.p, b, ldb,
+    HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, io_perm(P), P.trp.p, P.tci.p, P.tva.p, b, 1, ldb,
                              bp, s));
   return SPTRSV_OK;
 }
@@ -650,7 +650,7 @@ static sptrsv_status_t launch_run(sptrsv_ctx *h, Plan &P, const Run &r, int32_t 
                               P.sva.p, P.sdg.p, bp, xp, P.wbar.p, err, wait_limit(h), s));
   } else {
     HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
-                                P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, bp, xp, err, s));
+                                P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, bp, xp, err, s, ta.rio));
   }
   prof_end(h, slot, s);
   return SPTRSV_OK;
@@ -675,7 +675,7 @@ static sptrsv_status_t solve_overlapped(sptrsv_ctx *h, Plan &P, int32_t nrhs, co
     const int32_t t0 = P.t_off[(size_t)k], t1 = P.t_off[(size_t)k + 1];
     if (P.has_t && t1 > t0)
       HIPCHK(h, launch_apply_t(t1 - t0, nrhs, P.t_lanes, P.tpos.p + t0, io_perm(P), P.trp.p, P.tci.p, P.tva.p, b,
-                               ldb, bp, side));
+                               1, ldb, bp, side));
     HIPCHK(h, hipEventRecord(ev[1 + k], side));
     return SPTRSV_OK;
   };
@@ -742,6 +742,51 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
   STCHK(ensure_work(h, P, nrhs));
   if (!runs_ready(P, nrhs)) STCHK(make_runs(h, P, nrhs, effective_sched(P, nrhs), s));
   return solve_runs(h, P, nrhs, b, ldb, x, ldx, P.bp.p, P.xp.p, s);
+}
+
+// The flags of the rows of T with off-diagonals, for solves by rows.
+sptrsv_status_t ensure_rows(sptrsv_ctx *h, Plan &P, hipStream_t s) {
+  if (!P.has_t || P.tflag.p || P.n == 0) return SPTRSV_OK;
+  HIPCHK(h, P.tflag.alloc((size_t)P.n));
+  HIPCHK(h, launch_tflag(P.n, P.n_tpos, P.tpos.p, P.tflag.p, s));
+  return SPTRSV_OK;
+}
+
+// A solve with the right-hand sides stored by rows (entry (i, c) of b and x
+// at i * nrhs + c; nrhs > 1). Thin runs and one launch per wide level read b
+// and write x through the level order themselves (the b-transform writes only
+// the rows of T with off-diagonals into the work vector); the other schedules
+// copy b into the work vector and x out of it by rows.
+sptrsv_status_t solve_rows(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b, double *x, hipStream_t s) {
+  if (P.n == 0) return SPTRSV_OK;
+  STCHK(ensure_work(h, P, nrhs));
+  if (!runs_ready(P, nrhs)) STCHK(make_runs(h, P, nrhs, effective_sched(P, nrhs), s));
+  STCHK(ensure_rows(h, P, s));
+  const sptrsv_schedule_t sc = P.runs_sched;
+  double *bp = P.bp.p, *xp = P.xp.p;
+  const int32_t *perm = io_perm(P);
+  const bool t = P.has_t && P.n_tpos > 0;
+  if (sc.mode != 3 && sc.mode != 4 && sc.wide_grid == 0) {
+    if (t)
+      HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, perm, P.trp.p, P.tci.p, P.tva.p, b, nrhs, 1, bp,
+                               s));
+    ThinArgs ta = thin_args(P, bp, xp);
+    ta.rio = RowsIO{b, x, perm, P.has_t ? P.tflag.p : nullptr};
+    for (const Run &r : P.runs) STCHK(launch_run(h, P, r, nrhs, ta, bp, xp, s));
+    return SPTRSV_OK;
+  }
+  HIPCHK(h, launch_gather_rows(P.n, nrhs, b, perm, bp, s));
+  if (t)
+    HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, perm, P.trp.p, P.tci.p, P.tva.p, b, nrhs, 1, bp, s));
+  if (sc.mode == 3) {
+    HIPCHK(h, launch_syncfree(P.n, nrhs, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, bp, xp, P.sf_ticket.p, h->d_err.p,
+                              sc.wide_grid, wait_limit(h), s));
+  } else {
+    const ThinArgs ta = thin_args(P, bp, xp);
+    for (const Run &r : P.runs) STCHK(launch_run(h, P, r, nrhs, ta, bp, xp, s));
+  }
+  HIPCHK(h, launch_scatter_rows(P.n, nrhs, xp, perm, x, s));
+  return SPTRSV_OK;
 }
 
 // ------------------------------------------------------------------- ABI
@@ -1001,6 +1046,7 @@ sptrsv_status_t sptrsv_prepare(sptrsv_handle_t h, int which, int32_t nrhs, hipSt
   STCHK(ensure_work(h, *P, nrhs));
   const sptrsv_schedule_t sc = effective_sched(*P, nrhs);
   STCHK(make_runs(h, *P, nrhs, sc, s));
+  STCHK(ensure_rows(h, *P, s));
   return SPTRSV_OK;
 }
 
@@ -1046,6 +1092,18 @@ sptrsv_status_t sptrsv_solve(sptrsv_handle_t h, int which, int32_t nrhs, const d
   Plan *P = solve_plan(h, which, nrhs, d_b, ldb, d_x, ldx, &st);
   if (!P) return st;
   return plan_solve(h, *P, nrhs, d_b, ldb, d_x, ldx, s);
+}
+
+sptrsv_status_t sptrsv_solve_rows(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, double *d_x,
+                                  hipStream_t s) {
+  if (!h) return SPTRSV_ERR_ARG;
+  const Plan *Q = plan_of(h, which);
+  const int64_t n = Q ? Q->n : 0;
+  sptrsv_status_t st;
+  Plan *P = solve_plan(h, which, nrhs, d_b, n, d_x, n, &st);  // the same extent as n x nrhs column-major
+  if (!P) return st;
+  if (nrhs == 1) return plan_solve(h, *P, 1, d_b, n, d_x, n, s);  // one column: the same layout
+  return solve_rows(h, *P, nrhs, d_b, d_x, s);
 }
 
 sptrsv_status_t sptrsv_check(sptrsv_handle_t h, hipStream_t s) {
@@ -1111,7 +1169,7 @@ sptrsv_status_t sptrsv_profile(sptrsv_handle_t h, int enable, sptrsv_kernel_prof
   return SPTRSV_OK;
 }
 
-sptrsv_status_t sptrsv_level_floor(sptrsv_handle_t h, int which, int32_t nrhs, int32_t graph,
+sptrsv_status_t sptrsv_level_floor(sptrsv_handle_t h, int which, int32_t nrhs, int32_t flags,
                                    const sptrsv_level_costs_t *c, double *floor_us) {
   if (!h || !c || !floor_us) return SPTRSV_ERR_ARG;
   Plan *P = plan_of(h, which);
@@ -1122,8 +1180,13 @@ sptrsv_status_t sptrsv_level_floor(sptrsv_handle_t h, int which, int32_t nrhs, i
   if (P->n == 0) return SPTRSV_OK;
   if (!runs_ready(*P, nrhs)) STCHK(make_runs(h, *P, nrhs, effective_sched(*P, nrhs), nullptr));
   const sptrsv_schedule_t sc = P->runs_sched;
-  const double launch = graph ? c->graph_node_ns : c->launch_ns;
-  double ns = launch * (2 + (P->has_t && P->n_tpos > 0 ? 1 : 0));  // gather, b-transform, scatter
+  if (flags & ~(SPTRSV_FLOOR_GRAPH | SPTRSV_FLOOR_ROWS)) return set_err(h, SPTRSV_ERR_ARG, "flags=%d", flags);
+  const double launch = (flags & SPTRSV_FLOOR_GRAPH) ? c->graph_node_ns : c->launch_ns;
+  // gather, b-transform, scatter; right-hand sides by rows read and written
+  // through the level order skip the gather and the scatter where the runs
+  // are thin runs and per-level wide launches
+  const bool direct = (flags & SPTRSV_FLOOR_ROWS) && sc.mode != 3 && sc.mode != 4 && sc.wide_grid == 0;
+  double ns = launch * ((direct ? 0 : 2) + (P->has_t && P->n_tpos > 0 ? 1 : 0));
   if (sc.mode == 3) {
     ns += 2 * launch + (double)P->nlev * c->flag_hop_ns;  // fill of x, the solve; a hop per level
   } else {

@@ -183,8 +183,9 @@ sptrsv_status_t sptrsv_get_tune_info(sptrsv_handle_t h, sptrsv_tune_info_t *out)
   return SPTRSV_OK;
 }
 
-sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
-                                    double *d_x, int64_t ldx, hipStream_t s, int32_t *graph_id) {
+// One solve captured in a hipGraph: by columns (ldb, ldx) or, with rows, by rows.
+static sptrsv_status_t graph_create(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
+                                    double *d_x, int64_t ldx, bool rows, hipStream_t s, int32_t *graph_id) {
   if (!h || !graph_id) return SPTRSV_ERR_ARG;
   if (!s) return set_err(h, SPTRSV_ERR_ARG, "graph capture needs a non-null stream");
   if (h->graphs.size() >= 16) return set_err(h, SPTRSV_ERR_ARG, "at most 16 graphs per handle");
@@ -193,7 +194,8 @@ sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, 
   const bool prof = h->prof;  // no event records inside a captured graph
   h->prof = false;
   HIPCHK(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  sptrsv_status_t st = sptrsv_solve(h, which, nrhs, d_b, ldb, d_x, ldx, s);
+  sptrsv_status_t st = rows ? sptrsv_solve_rows(h, which, nrhs, d_b, d_x, s)
+                            : sptrsv_solve(h, which, nrhs, d_b, ldb, d_x, ldx, s);
   hipError_t e = hipStreamEndCapture(s, &g.g);
   h->prof = prof;
   if (st != SPTRSV_OK) {
@@ -209,6 +211,16 @@ sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, 
   h->graphs.push_back(g);
   *graph_id = (int32_t)h->graphs.size() - 1;
   return SPTRSV_OK;
+}
+
+sptrsv_status_t sptrsv_graph_create(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, int64_t ldb,
+                                    double *d_x, int64_t ldx, hipStream_t s, int32_t *graph_id) {
+  return graph_create(h, which, nrhs, d_b, ldb, d_x, ldx, false, s, graph_id);
+}
+
+sptrsv_status_t sptrsv_graph_create_rows(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, double *d_x,
+                                         hipStream_t s, int32_t *graph_id) {
+  return graph_create(h, which, nrhs, d_b, 0, d_x, 0, true, s, graph_id);
 }
 
 sptrsv_status_t sptrsv_graph_launch(sptrsv_handle_t h, int32_t graph_id, hipStream_t s) {

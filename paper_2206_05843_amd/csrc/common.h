@@ -127,6 +127,7 @@ struct Plan {
   DArr<int32_t> trp, tci;              // T off-diagonals per position (columns: caller's rows)
   DArr<double> tva;
   DArr<int32_t> tpos;                  // positions whose row of T has off-diagonals
+  DArr<uint8_t> tflag;                 // 1 at those positions (solves by rows; built on demand)
   int32_t n_tpos = 0;
   int32_t t_lanes = 1;                 // lanes per row of T in the b-transform
   DArr<int64_t> lv_rows, lv_nnz, lv_cost;
@@ -347,6 +348,17 @@ inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
 // Device arrays a thin run reads: level bounds, diagonal, the static window
 // images and each position's dependencies before its window (CSR), and the
 // work vectors.
+// Right-hand sides stored by rows (b null: the work vectors only): b is read
+// at b[perm[pos] * nrhs + c] except where tflag[pos] marks a row of T with
+// off-diagonals (b' already in the work vector), and x is also written to
+// x[perm[pos] * nrhs + c].
+struct RowsIO {
+  const double *b;
+  double *x;
+  const int32_t *perm;
+  const uint8_t *tflag;
+};
+
 struct ThinArgs {
   const int32_t *level_ptr;
   const double *sdg;
@@ -356,15 +368,25 @@ struct ThinArgs {
   const double *bp;
   double *xp;
   unsigned *tp;  // pacing words of the L2 prefetch helpers of a single-run launch (null: no helpers)
+  RowsIO rio;
 };
 
 // Launchers (k_solve.hip) ------------------------------------------------------
 hipError_t launch_gather(int32_t n, int32_t nrhs, const double *b, int64_t ldb, const int32_t *iperm, double *bp,
                          hipStream_t s);
 // lanes: 1 (a thread per row and column of b) or 4, 16, 64 (a group per row)
+// b's entry (row, c) at b[row * rs + c * cs]: rs = 1, cs = ldb column-major;
+// rs = nrhs, cs = 1 by rows.
 hipError_t launch_apply_t(int32_t nt, int32_t nrhs, int32_t lanes, const int32_t *tpos, const int32_t *perm,
-                          const int32_t *trp, const int32_t *tcol, const double *tva, const double *b, int64_t ldb,
-                          double *bp, hipStream_t s);
+                          const int32_t *trp, const int32_t *tcol, const double *tva, const double *b, int64_t rs,
+                          int64_t cs, double *bp, hipStream_t s);
+// Right-hand sides stored by rows: bp[pos * nrhs + c] = b[perm[pos] * nrhs + c],
+// x[perm[pos] * nrhs + c] = xp[pos * nrhs + c]; tflag[tpos[i]] = 1 (zeroed first).
+hipError_t launch_gather_rows(int32_t n, int32_t nrhs, const double *b, const int32_t *perm, double *bp,
+                              hipStream_t s);
+hipError_t launch_scatter_rows(int32_t n, int32_t nrhs, const double *xp, const int32_t *perm, double *x,
+                               hipStream_t s);
+hipError_t launch_tflag(int32_t n, int32_t nt, const int32_t *tpos, uint8_t *tflag, hipStream_t s);
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
 // The same over a list of caller-row tiles of 64 rows.
@@ -389,7 +411,7 @@ hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, co
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                              const int4 *ell_c, const double2 *ell_v, const double *bp, double *xp, int *err,
-                             hipStream_t s);
+                             hipStream_t s, RowsIO rio = RowsIO{});
 hipError_t launch_wide_run(int grid, int threads, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                            const double *bp, double *xp, unsigned *bar, int *err, unsigned long long tlimit,

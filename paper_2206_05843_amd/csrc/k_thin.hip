@@ -177,7 +177,13 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
         const int32_t itc = it < nitems ? it : nitems - 1;
         const int32_t sj = kOne ? itc : itc / nr;
         const int32_t pos = P0 + sj;
-        acc[j] = bp[(int64_t)pos * nr + (kOne ? 0 : itc - sj * nr)];
+        const int32_t cj = kOne ? 0 : itc - sj * nr;
+        // right-hand sides stored by rows: the caller's b through the level
+        // order, except rows of T with off-diagonals (b' in bp)
+        if (A.rio.b && !(A.rio.tflag && A.rio.tflag[pos]))
+          acc[j] = A.rio.b[(int64_t)A.rio.perm[pos] * nr + cj];
+        else
+          acc[j] = bp[(int64_t)pos * nr + cj];
         dg[j] = sdg[pos];
         e0[j] = ext_ptr[pos];
         e1[j] = it < nitems ? ext_ptr[pos + 1] : e0[j];
@@ -288,6 +294,10 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
       const double x = v[i];
       if (!isfinite(x)) bits |= EB_NONFINITE;
       xw[i] = x;
+      if (A.rio.x) {  // and the caller's x, by rows
+        const int32_t sj = kOne ? i : i / nr;
+        A.rio.x[(int64_t)A.rio.perm[P0 + sj] * nr + (kOne ? 0 : i - sj * nr)] = x;
+      }
     }
     __syncthreads();  // the window's global x is complete before the next phase 1 reads it
   }

@@ -110,16 +110,17 @@ __global__ void k_gather1(int32_t n, const double *__restrict__ b, const int32_t
 // One thread per (row, column of b): for short rows of T.
 __global__ void k_apply_t(int32_t nt, int32_t nrhs, const int32_t *__restrict__ tpos, const int32_t *__restrict__ perm,
                           const int32_t *__restrict__ trp, const int32_t *__restrict__ tcol,
-                          const double *__restrict__ tva, const double *__restrict__ b, int64_t ldb, double *bp) {
+                          const double *__restrict__ tva, const double *__restrict__ b, int64_t rs, int64_t cs,
+                          double *bp) {
   const int64_t total = (int64_t)nt * nrhs;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t j = (int32_t)(i / nrhs);
     const int32_t c = (int32_t)(i - (int64_t)j * nrhs);
     const int32_t pos = tpos[j];
-    const double *bc = b + (int64_t)c * ldb;
-    double acc = bc[perm[pos]];
+    const double *bc = b + (int64_t)c * cs;
+    double acc = bc[(int64_t)perm[pos] * rs];
     const int32_t qb = trp[pos], qe = trp[pos + 1];
-    for (int32_t q = qb; q < qe; ++q) acc += tva[q] * bc[tcol[q]];
+    for (int32_t q = qb; q < qe; ++q) acc += tva[q] * bc[(int64_t)tcol[q] * rs];
     bp[(int64_t)pos * nrhs + c] = acc;
   }
 }
@@ -131,7 +132,7 @@ template <int G>
 __global__ void k_apply_t_group(int32_t nt, int32_t nrhs, const int32_t *__restrict__ tpos,
                                 const int32_t *__restrict__ perm, const int32_t *__restrict__ trp,
                                 const int32_t *__restrict__ tcol, const double *__restrict__ tva,
-                                const double *__restrict__ b, int64_t ldb, double *bp) {
+                                const double *__restrict__ b, int64_t rs, int64_t cs, double *bp) {
   const int lane = threadIdx.x % G;
   const int64_t ng = (int64_t)gridDim.x * (blockDim.x / G);
   // every lane of a group takes the same trip count, so the butterfly sees
@@ -141,12 +142,12 @@ __global__ void k_apply_t_group(int32_t nt, int32_t nrhs, const int32_t *__restr
     const int32_t qb = trp[pos], qe = trp[pos + 1];
     const int32_t row = perm[pos];
     for (int32_t c = 0; c < nrhs; ++c) {
-      const double *bc = b + (int64_t)c * ldb;
+      const double *bc = b + (int64_t)c * cs;
       double acc = 0.0;
-      for (int32_t q = qb + lane; q < qe; q += G) acc += tva[q] * bc[tcol[q]];
+      for (int32_t q = qb + lane; q < qe; q += G) acc += tva[q] * bc[(int64_t)tcol[q] * rs];
 #pragma unroll
       for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-      if (lane == 0) bp[(int64_t)pos * nrhs + c] = bc[row] + acc;
+      if (lane == 0) bp[(int64_t)pos * nrhs + c] = bc[(int64_t)row * rs] + acc;
     }
   }
 }
@@ -168,6 +169,31 @@ __global__ void k_scatter(int32_t n, int32_t nrhs, const double *__restrict__ xp
     }
     __syncthreads();
   }
+}
+
+// Right-hand sides stored by rows: one row's nrhs values move together.
+__global__ void k_gather_rows(int64_t total, int32_t nrhs, const double *__restrict__ b,
+                              const int32_t *__restrict__ perm, double *bp) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pos = i / nrhs;
+    bp[i] = b[(int64_t)perm[pos] * nrhs + (i - pos * nrhs)];
+  }
+}
+
+__global__ void k_scatter_rows(int64_t total, int32_t nrhs, const double *__restrict__ xp,
+                               const int32_t *__restrict__ perm, double *x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pos = i / nrhs;
+    x[(int64_t)perm[pos] * nrhs + (i - pos * nrhs)] = xp[i];
+  }
+}
+
+__global__ void k_tflag_zero(int32_t n, uint8_t *tflag) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) tflag[i] = 0;
+}
+
+__global__ void k_tflag_set(int32_t nt, const int32_t *__restrict__ tpos, uint8_t *tflag) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) tflag[tpos[i]] = 1;
 }
 
 __global__ void k_scatter1(int32_t n, const double *__restrict__ xp, const int32_t *__restrict__ iperm, double *x) {
@@ -340,30 +366,53 @@ hipError_t launch_tile_span(int32_t n, const int32_t *iperm, int32_t *first, int
 }
 
 hipError_t launch_apply_t(int32_t nt, int32_t nrhs, int32_t lanes, const int32_t *tpos, const int32_t *perm,
-                          const int32_t *trp, const int32_t *tcol, const double *tva, const double *b, int64_t ldb,
-                          double *bp, hipStream_t s) {
+                          const int32_t *trp, const int32_t *tcol, const double *tva, const double *b, int64_t rs,
+                          int64_t cs, double *bp, hipStream_t s) {
   if (nt == 0) return hipSuccess;
   const int64_t groups = nt;
   switch (lanes) {
     case 1:
       hipLaunchKernelGGL(k_apply_t, dim3(grid_for((int64_t)nt * nrhs, 256, 16384)), dim3(256), 0, s, nt, nrhs, tpos,
-                         perm, trp, tcol, tva, b, ldb, bp);
+                         perm, trp, tcol, tva, b, rs, cs, bp);
       break;
     case 4:
       hipLaunchKernelGGL(k_apply_t_group<4>, dim3(grid_for(groups * 4, 256, 16384)), dim3(256), 0, s, nt, nrhs, tpos,
-                         perm, trp, tcol, tva, b, ldb, bp);
+                         perm, trp, tcol, tva, b, rs, cs, bp);
       break;
     case 16:
       hipLaunchKernelGGL(k_apply_t_group<16>, dim3(grid_for(groups * 16, 256, 16384)), dim3(256), 0, s, nt, nrhs,
-                         tpos, perm, trp, tcol, tva, b, ldb, bp);
+                         tpos, perm, trp, tcol, tva, b, rs, cs, bp);
       break;
     case 64:
       hipLaunchKernelGGL(k_apply_t_group<64>, dim3(grid_for(groups * 64, 256, 16384)), dim3(256), 0, s, nt, nrhs,
-                         tpos, perm, trp, tcol, tva, b, ldb, bp);
+                         tpos, perm, trp, tcol, tva, b, rs, cs, bp);
       break;
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(int32_t n, int32_t nrhs, const double *b, const int32_t *perm, double *bp,
+                              hipStream_t s) {
+  const int64_t total = (int64_t)n * nrhs;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(total, 256, 16384)), dim3(256), 0, s, total, nrhs, b, perm, bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(int32_t n, int32_t nrhs, const double *xp, const int32_t *perm, double *x,
+                               hipStream_t s) {
+  const int64_t total = (int64_t)n * nrhs;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(total, 256, 16384)), dim3(256), 0, s, total, nrhs, xp, perm, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_tflag(int32_t n, int32_t nt, const int32_t *tpos, uint8_t *tflag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tflag_zero, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, tflag);
+  if (nt > 0) hipLaunchKernelGGL(k_tflag_set, dim3(grid_for(nt, 256, 4096)), dim3(256), 0, s, nt, tpos, tflag);
   return hipGetLastError();
 }
 

@@ -18,14 +18,15 @@ template <bool kOne>
 __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t *__restrict__ srp,
                              const int32_t *__restrict__ sci, const double *__restrict__ sva,
                              const double *__restrict__ sdg, const int4 *__restrict__ ell_c,
-                             const double2 *__restrict__ ell_v, const double *__restrict__ bp, double *xp, int *err) {
+                             const double2 *__restrict__ ell_v, const double *__restrict__ bp, double *xp, int *err,
+                             RowsIO rio) {
   constexpr int kI = kOne ? 2 : 1;  // several right-hand sides: one item per thread spreads a level wider
   const int32_t nr = kOne ? 1 : nrhs;
   const int64_t items = (int64_t)(pe - pb) * nr;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int bits = 0;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; base < items; base += stride * kI) {
-    int32_t pos[kI], c[kI], qb[kI], deg[kI];
+    int32_t pos[kI], c[kI], qb[kI], deg[kI], row[kI];
     int4 ec[kI];
     double2 e0[kI], e1[kI];
     double acc[kI], dg[kI];
@@ -40,7 +41,13 @@ __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t
       ec[j] = ell_c[pos[j]];
       e0[j] = ell_v[2 * (int64_t)pos[j]];
       e1[j] = ell_v[2 * (int64_t)pos[j] + 1];
-      acc[j] = bp[(int64_t)pos[j] * nr + c[j]];
+      row[j] = rio.b ? rio.perm[pos[j]] : 0;
+      // right-hand sides stored by rows: the caller's b through the level
+      // order, except rows of T with off-diagonals (b' in bp)
+      if (rio.b && !(rio.tflag && rio.tflag[pos[j]]))
+        acc[j] = rio.b[(int64_t)row[j] * nr + c[j]];
+      else
+        acc[j] = bp[(int64_t)pos[j] * nr + c[j]];
       dg[j] = sdg[pos[j]];
     }
     double xv[kI][4];
@@ -76,6 +83,7 @@ __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t
       const double x = a / dg[j];
       if (!isfinite(x)) bits |= EB_NONFINITE;
       xp[(int64_t)pos[j] * nr + c[j]] = x;
+      if (rio.x) rio.x[(int64_t)row[j] * nr + c[j]] = x;
     }
   }
   if (bits) atomicOr(err, bits);
@@ -175,7 +183,7 @@ __global__ void k_wide_run(int32_t l0, int32_t l1, const int32_t *__restrict__ l
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                              const int4 *ell_c, const double2 *ell_v, const double *bp, double *xp, int *err,
-                             hipStream_t s) {
+                             hipStream_t s, RowsIO rio) {
   const int64_t rows = pe - pb;
   if (rows <= 0) return hipSuccess;
   if (nrhs == 1 && lanes_per_row > 1) {
@@ -199,10 +207,10 @@ hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t
   const int g = grid_for((items + per - 1) / per, threads, 65536);
   if (nrhs == 1)
     hipLaunchKernelGGL((k_wide_level<true>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, ell_c,
-                       ell_v, bp, xp, err);
+                       ell_v, bp, xp, err, rio);
   else
     hipLaunchKernelGGL((k_wide_level<false>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, ell_c,
-                       ell_v, bp, xp, err);
+                       ell_v, bp, xp, err, rio);
   return hipGetLastError();
 }
 

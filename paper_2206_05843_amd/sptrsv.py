@@ -32,7 +32,8 @@ EXPORTS = [
     "sptrsv_plan_load", "sptrsv_level_features", "sptrsv_mlp_forward", "sptrsv_mlp_backward", "sptrsv_mlp_adam",
     "sptrsv_mlp_mask", "sptrsv_profile", "sptrsv_level_times", "sptrsv_get_tune_info",
     "sptrsv_solve_noalloc", "sptrsv_measure_level_costs", "sptrsv_level_floor",
-    "sptrsv_get_info", "sptrsv_level_finish_times", "sptrsv_mlp_actions",
+    "sptrsv_get_info", "sptrsv_level_finish_times", "sptrsv_mlp_actions", "sptrsv_solve_rows",
+    "sptrsv_graph_create_rows",
 ]
 
 
@@ -124,6 +125,8 @@ def lib():
         "sptrsv_get_targets": [vp, vp, vp],
         "sptrsv_solve": [vp, C.c_int, i32, vp, i64, vp, i64, vp],
         "sptrsv_solve_noalloc": [vp, C.c_int, i32, vp, i64, vp, i64, vp],
+        "sptrsv_solve_rows": [vp, C.c_int, i32, vp, vp, vp],
+        "sptrsv_graph_create_rows": [vp, C.c_int, i32, vp, vp, vp, C.POINTER(i32)],
         "sptrsv_prepare": [vp, C.c_int, i32, vp],
         "sptrsv_check": [vp, vp],
         "sptrsv_set_schedule": [vp, C.c_int, C.POINTER(Schedule)],
@@ -353,6 +356,25 @@ class Handle:
         self._check(fn(self._h, which, nrhs, _ptr(bb), ldb, _ptr(xx), ldx, _stream()))
         return x if b.dim() == 2 else x.view(-1)
 
+    def solve_rows(self, b, which=ORIGINAL, x=None):
+        """b: float64 device tensor of shape (n, nrhs), contiguous (a row's
+        right-hand sides together); returns x of the same shape."""
+        _need(b.dtype == torch.float64 and b.is_cuda and b.dim() == 2 and b.shape[0] == self.n and b.is_contiguous(),
+              "contiguous float64 device tensor of shape (n, nrhs) expected")
+        if x is None:
+            x = torch.empty_like(b)
+        _need(x.shape == b.shape and x.is_contiguous(), "x must be a contiguous (n, nrhs) tensor")
+        self._check(self._L.sptrsv_solve_rows(self._h, which, b.shape[1], _ptr(b), _ptr(x), _stream()))
+        return x
+
+    def graph_create_rows(self, b, x, which=ORIGINAL) -> int:
+        _need(b.is_contiguous() and x.is_contiguous() and b.shape == x.shape and b.dim() == 2, "(n, nrhs) tensors")
+        gid = C.c_int32(0)
+        self._check(self._L.sptrsv_graph_create_rows(self._h, which, b.shape[1], _ptr(b), _ptr(x), _stream(),
+                                                     C.byref(gid)))
+        self._keep.append((b, x))
+        return gid.value
+
     def prepare(self, which=ORIGINAL, nrhs=1):
         self._check(self._L.sptrsv_prepare(self._h, which, nrhs, _stream()))
 
@@ -390,12 +412,13 @@ class Handle:
         self._check(self._L.sptrsv_measure_level_costs(self._h, _stream(), C.byref(out)))
         return out.as_dict()
 
-    def level_floor(self, costs: dict, which=ORIGINAL, nrhs=1, graph=False) -> float:
+    def level_floor(self, costs: dict, which=ORIGINAL, nrhs=1, graph=False, rows=False) -> float:
         """Microseconds one solve of (which, nrhs) costs at least with empty
-        levels, under the schedule it uses."""
+        levels, under the schedule it uses (rows: right-hand sides by rows)."""
         c = LevelCosts(**costs)
         out = C.c_double(0)
-        self._check(self._L.sptrsv_level_floor(self._h, which, nrhs, int(bool(graph)), C.byref(c), C.byref(out)))
+        flags = (1 if graph else 0) | (2 if rows else 0)
+        self._check(self._L.sptrsv_level_floor(self._h, which, nrhs, flags, C.byref(c), C.byref(out)))
         return out.value
 
     def tune_info(self) -> dict:

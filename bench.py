@@ -73,7 +73,8 @@ def alg_bytes(n, nnz, nlev, nrhs, nnz_t=0, rewritten=False):
 # the window images k_image.hip builds).
 KERNEL_SOURCE = {"k_thin_run": ("k_thin.hip", "k_image.hip", "sync.h"),
                  "k_batch_run": ("k_thin.hip", "k_image.hip", "sync.h"),
-                 "k_wide_level": ("k_wide.hip", "sync.h"), "k_gather": ("k_vec.hip",), "k_scatter": ("k_vec.hip",),
+                 "k_wide_level": ("k_wide.hip", "sync.h"), "k_wide_run": ("k_wide.hip", "sync.h"),
+                 "k_flow_run": ("k_flow.hip",), "k_gather": ("k_vec.hip",), "k_scatter": ("k_vec.hip",),
                  "k_sf_solve": ("k_syncfree.hip",)}
 
 
@@ -467,7 +468,7 @@ def main():
             h.set_schedule(which, **fixed_sched[name])
             info["tuned_ms"] = None
         else:
-            info["tuned_ms"] = h.autotune(which, nrhs)
+            info["tuned_ms"] = h.autotune(which, nrhs, rows=layout == "rows")
             info["tune"] = h.tune_info()
         info["schedule"] = h.get_schedule(which, nrhs)
         info["autotune_s"] = time.perf_counter() - t
@@ -598,8 +599,13 @@ def main():
     achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     kname = {"thin_run": "k_thin_run", "wide_level": "k_wide_level", "gather": "k_gather",
              "scatter": "k_scatter"}[dom]
-    if dom == "wide_level" and variants[headline][2]["schedule"]["mode"] == 3:
+    hsched = variants[headline][2]["schedule"]
+    if dom == "wide_level" and hsched["mode"] == 3:
         kname = "k_sf_solve"  # the synchronisation-free launch is profiled with the device-wide class
+    elif dom == "wide_level" and hsched["mode"] == 4:
+        kname = "k_flow_run"  # dataflow runs of the wide levels
+    elif dom == "wide_level" and hsched["wide_grid"] > 0:
+        kname = "k_wide_run"  # persistent runs of consecutive wide levels
     traffic = load_traffic(kname, f"config{args.config}_{headline}")
     total_prof_ms = sum(v["ms"] for v in prof.values())
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -236,11 +236,11 @@ sptrsv_status_t sptrsv_solve_noalloc(sptrsv_handle_t h, int which, int32_t nrhs,
  * d_b, d_x: n x nrhs, entry (i, c) at i * nrhs + c (the layout of one row's
  * right-hand sides together that the solve kernels work in), no leading
  * dimension. Same x as sptrsv_solve bit for bit (the same kernels and order).
- * With thin runs and one launch per wide level (modes 0, 1, 2 with wide_grid
- * 0) the solve kernels read b and write x through the level order themselves,
- * with no transposes; the b-transform writes only the rows of T with
- * off-diagonals into the work vector. Other schedules copy b in and x out by
- * rows. nrhs = 1 is sptrsv_solve with ld = n. ASYNC and capture-safe once a
+ * With thin runs, wide launches and persistent wide runs (modes 0, 1, 2) the
+ * solve kernels read b and write x through the level order themselves, with
+ * no transposes; the b-transform writes only the rows of T with off-diagonals
+ * into the work vector. The synchronisation-free and dataflow executors
+ * (modes 3, 4) copy b in and x out by rows. nrhs = 1 is sptrsv_solve with ld = n. ASYNC and capture-safe once a
  * solve of the same (which, nrhs) has run or sptrsv_prepare has been called.
  * Errors as sptrsv_solve (ARG: nrhs < 1, b and x overlapping). */
 sptrsv_status_t sptrsv_solve_rows(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, double *d_x,
@@ -284,7 +284,9 @@ typedef struct {
   int32_t lanes_per_row;  /* wide levels, nrhs == 1: 1, 2, 4, 8, 16 or 32 lanes per row */
   int32_t wide_grid;      /* 0: one launch per wide level; > 0: consecutive wide levels in one persistent launch
                              of up to wide_grid workgroups (capped to what is resident at once) with a
-                             device-wide barrier between levels (lanes_per_row is then 1) */
+                             device-wide barrier between levels, each workgroup fetching the next level's
+                             indices, weights and b between its arrival and its wait (lanes_per_row is
+                             then 1) */
   int32_t overlap;        /* 0 or 1: transposes beside the chain (see above) */
 } sptrsv_schedule_t;
 sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_schedule_t *sched);
@@ -301,6 +303,12 @@ sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, 
  * far (at least 2 ms) instead of the solve's 10 s: a candidate that reaches it
  * is dropped, and counted in sptrsv_get_tune_info. */
 sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms);
+/* The same, timing solves with the right-hand sides stored by rows
+ * (sptrsv_solve_rows), where thin-run and per-level wide schedules skip the
+ * copies the other executors keep. The pick is stored for (which, nrhs) as
+ * sptrsv_autotune's is: the layout tuned last sets the schedule both layouts
+ * use. which = SPTRSV_BATCH is an ARG error. */
+sptrsv_status_t sptrsv_autotune_rows(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms);
 
 /* What the handle's last sptrsv_autotune call did: candidates timed,
  * candidates dropped because a device-side wait reached its limit, the best
@@ -366,7 +374,7 @@ sptrsv_status_t sptrsv_measure_level_costs(sptrsv_handle_t h, hipStream_t s, spt
  * plus the launches of the gather, b-transform and scatter. flags:
  * SPTRSV_FLOOR_GRAPH prices launches as graph nodes; SPTRSV_FLOOR_ROWS prices a
  * solve with the right-hand sides by rows (sptrsv_solve_rows), which has no
- * gather or scatter launch under thin-run and per-level wide schedules; other
+ * gather or scatter launch under modes 0, 1 and 2; other
  * bits are an ARG error. floor_us receives microseconds. Synchronous. */
 #define SPTRSV_FLOOR_GRAPH 1
 #define SPTRSV_FLOOR_ROWS 2

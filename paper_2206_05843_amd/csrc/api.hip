@@ -647,7 +647,8 @@ static sptrsv_status_t launch_run(sptrsv_ctx *h, Plan &P, const Run &r, int32_t 
                               wait_limit(h), s));
   } else if (sc.wide_grid > 0) {
     HIPCHK(h, launch_wide_run(sc.wide_grid, sc.wide_threads, r.l0, r.l1, P.level_ptr.p, nrhs, P.srp.p, P.sci.p,
-                              P.sva.p, P.sdg.p, bp, xp, P.wbar.p, err, wait_limit(h), s));
+                              P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, bp, xp, P.wbar.p, err, wait_limit(h), s,
+                              ta.rio));
   } else {
     HIPCHK(h, launch_wide_level(sc.wide_threads, sc.lanes_per_row, P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs,
                                 P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p, P.ell_v.p, bp, xp, err, s, ta.rio));
@@ -766,7 +767,7 @@ sptrsv_status_t solve_rows(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
   double *bp = P.bp.p, *xp = P.xp.p;
   const int32_t *perm = io_perm(P);
   const bool t = P.has_t && P.n_tpos > 0;
-  if (sc.mode != 3 && sc.mode != 4 && sc.wide_grid == 0) {
+  if (sc.mode != 3 && sc.mode != 4) {
     if (t)
       HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, perm, P.trp.p, P.tci.p, P.tva.p, b, nrhs, 1, bp,
                                s));
@@ -1185,7 +1186,7 @@ sptrsv_status_t sptrsv_level_floor(sptrsv_handle_t h, int which, int32_t nrhs, i
   // gather, b-transform, scatter; right-hand sides by rows read and written
   // through the level order skip the gather and the scatter where the runs
   // are thin runs and per-level wide launches
-  const bool direct = (flags & SPTRSV_FLOOR_ROWS) && sc.mode != 3 && sc.mode != 4 && sc.wide_grid == 0;
+  const bool direct = (flags & SPTRSV_FLOOR_ROWS) && sc.mode != 3 && sc.mode != 4;
   double ns = launch * ((direct ? 0 : 2) + (P->has_t && P->n_tpos > 0 ? 1 : 0));
   if (sc.mode == 3) {
     ns += 2 * launch + (double)P->nlev * c->flag_hop_ns;  // fill of x, the solve; a hop per level

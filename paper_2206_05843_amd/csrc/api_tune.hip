@@ -38,8 +38,9 @@ std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
       if (thin_window_bytes(thr, 0, 1, nrhs) > thin_win_bytes()) continue;
       c.push_back(sptrsv_schedule_t{4, thr, 1024, wt, 1, 0});
     }
-  // consecutive wide levels in one persistent launch (one lane per item)
-  const int grids[] = {32, 256};
+  // consecutive wide levels in one persistent launch (one lane per item; 4096
+  // is capped to the workgroups that fit on the device at once)
+  const int grids[] = {32, 256, 4096};
   for (int g : grids) {
     c.push_back(sptrsv_schedule_t{1, 0, 512, 256, 1, g});
     for (int thr : thin_list) {
@@ -50,14 +51,12 @@ std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
   return c;
 }
 
-}  // namespace
-
-extern "C" {
-
-sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms) {
+// rows: time solves with the right-hand sides stored by rows (solve_rows)
+sptrsv_status_t autotune(sptrsv_ctx *h, int which, int32_t nrhs, bool rows, hipStream_t s, float *best_ms) {
   if (!h) return SPTRSV_ERR_ARG;
   Plan *P = sched_plan_of(h, which);
   if (!P) return set_err(h, SPTRSV_ERR_ARG, "which=%d", which);
+  if (rows && which == SPTRSV_BATCH) return set_err(h, SPTRSV_ERR_ARG, "right-hand sides by rows: one matrix only");
   if (!P->ready) return set_err(h, SPTRSV_ERR_STATE, "matrix not analysed/rewritten");
   if (nrhs < 1) return set_err(h, SPTRSV_ERR_ARG, "nrhs=%d", nrhs);
   const int64_t n = P->n;
@@ -86,7 +85,8 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
     cands = candidates(nrhs);
   }
   auto run = [&]() {
-    return batch ? sptrsv_batch_solve(h, nrhs, b.p, x.p, s) : plan_solve(h, *P, nrhs, b.p, n, x.p, n, s);
+    if (batch) return sptrsv_batch_solve(h, nrhs, b.p, x.p, s);
+    return rows ? sptrsv_solve_rows(h, which, nrhs, b.p, x.p, s) : plan_solve(h, *P, nrhs, b.p, n, x.p, n, s);
   };
   // a candidate whose device-side wait reaches its limit on this matrix is
   // dropped (its timeout bit cleared) and counted in the tuning report
@@ -175,6 +175,18 @@ sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipS
   h->tune_info = info;
   if (best_ms) *best_ms = best;
   return sptrsv_check(h, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+sptrsv_status_t sptrsv_autotune(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms) {
+  return autotune(h, which, nrhs, false, s, best_ms);
+}
+
+sptrsv_status_t sptrsv_autotune_rows(sptrsv_handle_t h, int which, int32_t nrhs, hipStream_t s, float *best_ms) {
+  return autotune(h, which, nrhs, true, s, best_ms);
 }
 
 sptrsv_status_t sptrsv_get_tune_info(sptrsv_handle_t h, sptrsv_tune_info_t *out) {

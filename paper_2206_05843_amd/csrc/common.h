@@ -414,8 +414,8 @@ hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t
                              hipStream_t s, RowsIO rio = RowsIO{});
 hipError_t launch_wide_run(int grid, int threads, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                           const double *bp, double *xp, unsigned *bar, int *err, unsigned long long tlimit,
-                           hipStream_t s);
+                           const int4 *ell_c, const double2 *ell_v, const double *bp, double *xp, unsigned *bar,
+                           int *err, unsigned long long tlimit, hipStream_t s, RowsIO rio = RowsIO{});
 int wide_run_resident_blocks(int threads);
 // rev: b and x in the reversed (caller's) numbering of the lower form
 hipError_t launch_residual(int32_t n, int32_t nrhs, const int32_t *rp, const int32_t *ci, const double *va,

@@ -47,8 +47,11 @@ __device__ __forceinline__ unsigned grid_bar_groups() {
   return g < (unsigned)kGridBarGroups ? g : (unsigned)kGridBarGroups;
 }
 
-__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned round, unsigned long long t0,
-                                             unsigned long long tlimit, int *s_abort) {
+// The barrier in two halves, so that a workgroup can issue loads that do not
+// depend on the round (the next level's indices and weights) between its
+// arrival and its wait. grid_barrier_arrive: wait for this thread's memory
+// operations, then one arrival per workgroup.
+__device__ __forceinline__ void grid_barrier_arrive(unsigned *bar, unsigned round) {
   __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -59,6 +62,14 @@ __device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned round, unsi
       const unsigned top = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (top + 1u == round * ng) __hip_atomic_store(bar + 32, round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+  }
+}
+
+// grid_barrier_wait: every workgroup has arrived for `round` (false in every
+// thread when the wall-clock limit expired first).
+__device__ __forceinline__ bool grid_barrier_wait(unsigned *bar, unsigned round, unsigned long long t0,
+                                                  unsigned long long tlimit, int *s_abort) {
+  if (threadIdx.x == 0) {
     unsigned spins = 0;
     while (__hip_atomic_load(bar + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round) {
       __builtin_amdgcn_s_sleep(1);
@@ -70,6 +81,12 @@ __device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned round, unsi
   }
   __syncthreads();
   return *s_abort == 0;
+}
+
+__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned round, unsigned long long t0,
+                                             unsigned long long tlimit, int *s_abort) {
+  grid_barrier_arrive(bar, round);
+  return grid_barrier_wait(bar, round, t0, tlimit, s_abort);
 }
 
 // End of a persistent launch that used grid_barrier: the last workgroup to

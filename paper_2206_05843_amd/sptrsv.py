@@ -27,7 +27,7 @@ EXPORTS = [
     "sptrsv_create", "sptrsv_destroy", "sptrsv_last_error", "sptrsv_status_name", "sptrsv_analyze", "sptrsv_analyze_form",
     "sptrsv_get_levels", "sptrsv_level_stats", "sptrsv_rewrite", "sptrsv_get_rewritten", "sptrsv_get_targets",
     "sptrsv_solve", "sptrsv_prepare", "sptrsv_check", "sptrsv_set_schedule", "sptrsv_get_schedule",
-    "sptrsv_autotune", "sptrsv_graph_create", "sptrsv_graph_launch", "sptrsv_residual", "sptrsv_batch_analyze",
+    "sptrsv_autotune", "sptrsv_autotune_rows", "sptrsv_graph_create", "sptrsv_graph_launch", "sptrsv_residual", "sptrsv_batch_analyze",
     "sptrsv_batch_solve", "sptrsv_batch_solve_looped", "sptrsv_batch_levels", "sptrsv_plan_save",
     "sptrsv_plan_load", "sptrsv_level_features", "sptrsv_mlp_forward", "sptrsv_mlp_backward", "sptrsv_mlp_adam",
     "sptrsv_mlp_mask", "sptrsv_profile", "sptrsv_level_times", "sptrsv_get_tune_info",
@@ -132,6 +132,7 @@ def lib():
         "sptrsv_set_schedule": [vp, C.c_int, C.POINTER(Schedule)],
         "sptrsv_get_schedule": [vp, C.c_int, C.c_int32, C.POINTER(Schedule)],
         "sptrsv_autotune": [vp, C.c_int, i32, vp, C.POINTER(f32)],
+        "sptrsv_autotune_rows": [vp, C.c_int, i32, vp, C.POINTER(f32)],
         "sptrsv_graph_create": [vp, C.c_int, i32, vp, i64, vp, i64, vp, C.POINTER(i32)],
         "sptrsv_graph_launch": [vp, i32, vp],
         "sptrsv_residual": [vp, i32, vp, i64, vp, i64, C.POINTER(dbl), vp],
@@ -401,9 +402,12 @@ class Handle:
         self._check(self._L.sptrsv_get_schedule(self._h, which, nrhs, C.byref(s)))
         return s.as_dict()
 
-    def autotune(self, which=ORIGINAL, nrhs=1) -> float:
+    def autotune(self, which=ORIGINAL, nrhs=1, rows=False) -> float:
+        """Tunes the schedule of (which, nrhs); rows: timing solves with the
+        right-hand sides stored by rows. Returns the best time in ms."""
         ms = C.c_float(0)
-        self._check(self._L.sptrsv_autotune(self._h, which, nrhs, _stream(), C.byref(ms)))
+        fn = self._L.sptrsv_autotune_rows if rows else self._L.sptrsv_autotune
+        self._check(fn(self._h, which, nrhs, _stream(), C.byref(ms)))
         return ms.value
 
     def measure_level_costs(self) -> dict:

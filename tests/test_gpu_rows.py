@@ -144,3 +144,26 @@ def test_rows_level_floor(mats):
         c, out = sptrsv_mod.LevelCosts(**costs), ctypes.c_double(0)
         h._check(h._L.sptrsv_level_floor(h._h, sp.ORIGINAL, 4, 4, ctypes.byref(c), ctypes.byref(out)))
     assert ei.value.name == "ARG"
+
+
+def test_rows_autotune(mats):
+    """Tuning by rows stores a schedule that both layouts then use, and the
+    solve by rows under it matches the oracle; the batched plan is refused."""
+    m = mats["stencil3d_tail"]
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    h.rewrite(sp.THIN_ROWS, 32, 4.0)
+    ms = h.autotune(sp.REWRITTEN, 8, rows=True)
+    assert ms > 0
+    sched = h.get_schedule(sp.REWRITTEN, 8)
+    b_cols = gen.rhs(m, 8)
+    bc = torch.from_numpy(b_cols).cuda()
+    x_rows = h.solve_rows(bc.t().contiguous(), sp.REWRITTEN)
+    x_cols = h.solve(bc, sp.REWRITTEN)
+    h.check()
+    assert h.get_schedule(sp.REWRITTEN, 8) == sched
+    assert torch.equal(x_rows.t(), x_cols)
+    assert oracle.relerr(x_cols.cpu().numpy(), oracle.solve(m, b_cols)) <= TOL
+    with pytest.raises(sp.SptrsvError) as ei:
+        h.autotune(sp.BATCH, 8, rows=True)
+    assert ei.value.name == "ARG"

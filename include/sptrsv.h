@@ -288,13 +288,18 @@ typedef struct {
                              indices, weights and b between its arrival and its wait (lanes_per_row is
                              then 1) */
   int32_t overlap;        /* 0 or 1: transposes beside the chain (see above) */
+  int32_t thin_cols;      /* right-hand sides per thin-run workgroup: 0 = all; c, a divisor of nrhs smaller than
+                             it = nrhs / c workgroups each solve c columns of every thin run (columns are
+                             independent), with LDS windows cut for c columns; otherwise all */
 } sptrsv_schedule_t;
 sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_schedule_t *sched);
 sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, sptrsv_schedule_t *sched);
 
 /* Autotuner: times candidate schedules with HIP events on s (inputs b = 1) and
  * keeps the fastest for (which, nrhs), then tries the wide launches of a best
- * split schedule (mode 0) with 64, 128 and 512 threads per workgroup; for
+ * split schedule (mode 0) with 64, 128 and 512 threads per workgroup, and,
+ * with several right-hand sides, the thin runs of the best schedule split
+ * over workgroups by columns (thin_cols 1, 2, 4, ... dividing nrhs); for
  * SPTRSV_BATCH the candidates are the
  * workgroup sizes of the persistent launch. best_ms (host, may be NULL) receives the
  * best solve time. Synchronous.

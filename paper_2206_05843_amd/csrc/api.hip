@@ -63,6 +63,7 @@ sptrsv_schedule_t default_schedule() {
   s.lanes_per_row = 1;
   s.wide_grid = 0;
   s.overlap = 0;
+  s.thin_cols = 0;
   return s;
 }
 
@@ -71,7 +72,7 @@ namespace {
 bool same_sched(const sptrsv_schedule_t &a, const sptrsv_schedule_t &b) {
   return a.mode == b.mode && a.thin_rows == b.thin_rows && a.wg_threads == b.wg_threads &&
          a.wide_threads == b.wide_threads && a.lanes_per_row == b.lanes_per_row && a.wide_grid == b.wide_grid &&
-         a.overlap == b.overlap;
+         a.overlap == b.overlap && a.thin_cols == b.thin_cols;
 }
 
 sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
@@ -88,6 +89,7 @@ sptrsv_status_t check_sched(sptrsv_ctx *h, const sptrsv_schedule_t &s) {
   if (s.thin_rows < 0) return set_err(h, SPTRSV_ERR_ARG, "thin_rows %d", s.thin_rows);
   if (s.wide_grid < 0 || s.wide_grid > 65536) return set_err(h, SPTRSV_ERR_ARG, "wide_grid %d", s.wide_grid);
   if (s.overlap != 0 && s.overlap != 1) return set_err(h, SPTRSV_ERR_ARG, "overlap %d", s.overlap);
+  if (s.thin_cols < 0) return set_err(h, SPTRSV_ERR_ARG, "thin_cols %d", s.thin_cols);
   if (s.mode == 3 && s.wide_grid > 2048)
     return set_err(h, SPTRSV_ERR_ARG, "wide_grid %d: the synchronisation-free launch takes at most 2048 workgroups",
                    s.wide_grid);
@@ -105,6 +107,13 @@ sptrsv_schedule_t effective_sched(const Plan &P, int32_t nrhs) {
 
 static int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
   return thin_window_bytes(rows, ents, nl, nrhs);
+}
+
+// Right-hand sides per thin-run workgroup under schedule sc: thin_cols when
+// it divides nrhs (and is smaller), else all of them.
+int32_t thin_width(const sptrsv_schedule_t &sc, int32_t nrhs) {
+  const int32_t c = sc.thin_cols;
+  return c > 0 && c < nrhs && nrhs % c == 0 ? c : nrhs;
 }
 
 // A level alone in a window reads all its dependencies from earlier windows,
@@ -370,10 +379,11 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
   const int64_t thr = sc.thin_rows;
   auto rows_of = [&](int32_t l) -> int64_t { return P.h_level_ptr[l + 1] - P.h_level_ptr[l]; };
   const bool flow = sc.mode == 4;
+  const int32_t gw = thin_width(sc, nrhs);  // columns per thin-run workgroup
   for (int32_t l = 0; l < P.nlev; ++l) {
     const int64_t rows = rows_of(l);
     bool thin = sc.mode == 2 || ((sc.mode == 0 || flow) && rows <= thr);
-    if (win_bytes(rows, 0, 1, nrhs) > cap) thin = false;  // must fit one window alone
+    if (win_bytes(rows, 0, 1, gw) > cap) thin = false;  // must fit one window alone
     // consecutive thin levels share a run; so do consecutive wide levels of a persistent or dataflow launch
     if (!P.runs.empty() && P.runs.back().thin == thin && P.runs.back().l1 == l &&
         (thin || sc.wide_grid > 0 || flow))
@@ -406,7 +416,7 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
   for (Run &r : P.runs) {
     if (!r.thin) continue;
     r.wi = (int32_t)P.h_win.size();
-    r.nw = cut_windows(P, r.l0, r.l1, nrhs, sc.wg_threads, P.h_win);
+    r.nw = cut_windows(P, r.l0, r.l1, gw, sc.wg_threads, P.h_win);
   }
   P.runs_nrhs = -1;  // until the images are built
   STCHK(build_images(h, P, s));
@@ -638,7 +648,8 @@ static sptrsv_status_t launch_run(sptrsv_ctx *h, Plan &P, const Run &r, int32_t 
   int *err = h->d_err.p;
   const int slot = h->prof ? prof_begin(h, r.thin ? 1 : 2, run_bytes(P, r.l0, r.l1, nrhs), s) : -1;
   if (r.thin) {
-    HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, ta, err, s));
+    HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, ta, err, s, nullptr, 0.f,
+                              thin_width(sc, nrhs)));
   } else if (r.flow) {
     const FlowArgs fa{P.flow_pos.p + r.cp, P.flow_dptr.p + r.cp, P.flow_dlist.p, P.flow_lc.p + r.lc,
                       P.flow_flags.p + r.fl, P.flow_ctl.p, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p,

@@ -18,7 +18,7 @@
 namespace {
 
 constexpr char kMagic[8] = {'S', 'P', 'T', 'R', 'S', 'V', 'P', 'L'};
-constexpr uint32_t kVersion = 3;
+constexpr uint32_t kVersion = 4;
 constexpr uint32_t kTagHash = 0xffffffffu;
 
 uint64_t fnv1a(const unsigned char *p, size_t n, uint64_t h = 1469598103934665603ull) {

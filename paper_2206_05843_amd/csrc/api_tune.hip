@@ -163,6 +163,23 @@ sptrsv_status_t autotune(sptrsv_ctx *h, int which, int32_t nrhs, bool rows, hipS
       if (st != SPTRSV_OK) break;
     }
   }
+  // several right-hand sides: thin runs split over workgroups by columns
+  // (each solves thin_cols of them), around the best schedule with thin runs
+  if (st == SPTRSV_OK && !batch && nrhs > 1 && best < 1e29f &&
+      (best_s.mode == 2 || ((best_s.mode == 0 || best_s.mode == 4) && best_s.thin_rows > 0))) {
+    const sptrsv_schedule_t base = best_s;
+    for (int tc = 1; tc < nrhs; tc *= 2) {
+      if (nrhs % tc) continue;
+      sptrsv_schedule_t cand = base;
+      cand.thin_cols = tc;
+      float ms = 0.f;
+      if (time_cand(cand, &ms) && ms < best) {
+        best = ms;
+        best_s = cand;
+      }
+      if (st != SPTRSV_OK) break;
+    }
+  }
   h->wait_ticks = 0;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

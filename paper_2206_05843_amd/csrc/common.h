@@ -404,8 +404,9 @@ hipError_t launch_tile_span(int32_t n, const int32_t *iperm, int32_t *first, int
 int thin_win_bytes();
 hipError_t launch_extra_hist(int32_t n, const int32_t *level_ptr, int32_t nlev, const int32_t *srp,
                              const int32_t *sci, int32_t *lop, int32_t *hist, hipStream_t s);
+// ng: right-hand sides per solver workgroup (a divisor of nrhs; 0 = all)
 hipError_t launch_thin_run(int wg, const int4 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
-                           hipStream_t s, float *times = nullptr, float ns_per_tick = 0.f);
+                           hipStream_t s, float *times = nullptr, float ns_per_tick = 0.f, int32_t ng = 0);
 hipError_t launch_fill_ell(int32_t n, const int32_t *srp, const int32_t *sci, const double *sva, int4 *ell_c,
                            double2 *ell_v, hipStream_t s);
 hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t pe, int32_t nrhs,

@@ -128,14 +128,19 @@ constexpr int p1_copy() {
   return WG >= 1024 ? 8 : 12;
 }
 
-// The windows [win, win + nwin) of one thin run, by the calling workgroup.
-// Returns the latched error bits; a window that does not fit aborts the run.
+// The windows [win, win + nwin) of one thin run, by the calling workgroup,
+// for the ng right-hand sides c0 .. c0 + ng - 1 of the nrhs (kOne: ng = 1).
+// The columns are independent, so a run can be split over several
+// workgroups by columns; LDS holds ng values per row (windows are cut for ng
+// columns). Returns the latched error bits; a window that does not fit aborts
+// the run.
 template <int WG, bool kOne, bool kTimed>
 __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restrict__ win, int32_t nwin, int32_t nrhs,
-                                             const ThinArgs &A, float *times, float ns_per_tick,
-                                             unsigned *prog = nullptr, unsigned ptag = 0) {
+                                             int32_t ng, int32_t c0, const ThinArgs &A, float *times,
+                                             float ns_per_tick, unsigned *prog = nullptr, unsigned ptag = 0) {
   double *lds = reinterpret_cast<double *>(lds_raw + kCtlBytes);
-  const int32_t nr = kOne ? 1 : nrhs;
+  const int32_t nr = nrhs;           // stride of the global vectors
+  const int32_t gw = kOne ? 1 : ng;  // columns in LDS and per row of items
   const int tid = threadIdx.x;
   const int32_t *__restrict__ level_ptr = A.level_ptr;
   const double *__restrict__ sdg = A.sdg;
@@ -156,17 +161,17 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
     const int32_t NO = W.z;  // the window's overflow records
     const int32_t NL = lB - lA;
     // the host sizes windows to fit, and 16-bit slots and offsets must hold R and NO
-    if (thin_window_bytes(R, NO, NL, nr) > kWinBytes - kCtlBytes || R >= 65536 || NO >= 65536) return bits | EB_ARG;
+    if (thin_window_bytes(R, NO, NL, gw) > kWinBytes - kCtlBytes || R >= 65536 || NO >= 65536) return bits | EB_ARG;
     double2 *rw = reinterpret_cast<double2 *>(lds);          // [R] w0, w1 (scaled by 1/diagonal)
     Dep *ovf = reinterpret_cast<Dep *>(rw + R);               // [NO] third and later dependencies
     uint2 *rix = reinterpret_cast<uint2 *>(ovf + NO);         // [R, padded to even] slot0, slot1, count, overflow
-    double *v = reinterpret_cast<double *>(rix + ((R + 1) & ~1));  // [(R + 1) * nr] partial sums, then x; zero row R
-    int32_t *lv = reinterpret_cast<int32_t *>(v + (int64_t)(R + 1) * nr);  // [NL + 1] level bounds from P0
+    double *v = reinterpret_cast<double *>(rix + ((R + 1) & ~1));  // [(R + 1) * gw] partial sums, then x; zero row R
+    int32_t *lv = reinterpret_cast<int32_t *>(v + (int64_t)(R + 1) * gw);  // [NL + 1] level bounds from P0
     // phase 1. Each thread requests its items' right-hand side, diagonal and
     // range of dependencies before the window; in the first round it streams
     // the window's static image into LDS while those are in flight; then it
     // subtracts the dependencies before the window (in the row's column order).
-    const int32_t nitems = R * nr;
+    const int32_t nitems = R * gw;
     constexpr int kI = p1_items<WG, kOne>();
     for (int32_t base = 0; base < nitems; base += WG * kI) {
       double acc[kI], dg[kI];
@@ -175,9 +180,9 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
       for (int j = 0; j < kI; ++j) {
         const int32_t it = base + j * WG + tid;
         const int32_t itc = it < nitems ? it : nitems - 1;
-        const int32_t sj = kOne ? itc : itc / nr;
+        const int32_t sj = kOne ? itc : itc / gw;
         const int32_t pos = P0 + sj;
-        const int32_t cj = kOne ? 0 : itc - sj * nr;
+        const int32_t cj = c0 + (kOne ? 0 : itc - sj * gw);
         // right-hand sides stored by rows: the caller's b through the level
         // order, except rows of T with off-diagonals (b' in bp)
         if (A.rio.b && !(A.rio.tflag && A.rio.tflag[pos]))
@@ -190,7 +195,7 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
       }
       if (base == 0) {
         for (int32_t i = tid; i <= NL; i += WG) lv[i] = level_ptr[lA + i] - P0;
-        for (int32_t i = tid; i < nr; i += WG) v[(int64_t)R * nr + i] = 0.0;
+        for (int32_t i = tid; i < gw; i += WG) v[(int64_t)R * gw + i] = 0.0;
         const uint4 *__restrict__ im = A.img + W.w;
         uint4 *dst = reinterpret_cast<uint4 *>(lds);
         const int32_t nu = (int32_t)window_image_units(R, NO);
@@ -213,7 +218,7 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
       for (int j = 0; j < kI; ++j) {
         const int32_t it = base + j * WG + tid;
         if (it >= nitems) continue;
-        const int32_t c = kOne ? 0 : it - (it / nr) * nr;
+        const int32_t c = c0 + (kOne ? 0 : it - (it / gw) * gw);
         double a = acc[j];
         for (int32_t e = e0[j]; e < e1[j]; e += kBatch) {
           double wv[kBatch], xv[kBatch];
@@ -249,16 +254,16 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
           const int32_t nlc = NL - c0 < 63 ? NL - c0 : 63;
           const int32_t lvreg = lv[c0 + lane <= NL ? c0 + lane : NL];
           int32_t pb = __builtin_amdgcn_readlane(lvreg, 0);
-          int32_t items = (__builtin_amdgcn_readlane(lvreg, 1) - pb) * nr;
-          Item cur = load_item<kOne>(pb, items, tid, nr, v, rw, rix);
+          int32_t items = (__builtin_amdgcn_readlane(lvreg, 1) - pb) * gw;
+          Item cur = load_item<kOne>(pb, items, tid, gw, v, rw, rix);
           for (int32_t l = 0; l < nlc; ++l) {
             Item nxt = cur;
             if (l + 1 < nlc) {
               pb = __builtin_amdgcn_readlane(lvreg, l + 1);
-              items = (__builtin_amdgcn_readlane(lvreg, l + 2) - pb) * nr;
-              nxt = load_item<kOne>(pb, items, tid, nr, v, rw, rix);
+              items = (__builtin_amdgcn_readlane(lvreg, l + 2) - pb) * gw;
+              nxt = load_item<kOne>(pb, items, tid, gw, v, rw, rix);
             }
-            if (cur.act) v[(int64_t)cur.s * nr + cur.c] = solve_item<kOne>(cur, nr, v, ovf);
+            if (cur.act) v[(int64_t)cur.s * gw + cur.c] = solve_item<kOne>(cur, gw, v, ovf);
             if (one_wave)
               wave_lds_barrier();
             else
@@ -275,10 +280,10 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
       }
     } else {
       for (int32_t l = 0; l < NL; ++l) {
-        const int32_t pb = lv[l], items = (lv[l + 1] - pb) * nr;
+        const int32_t pb = lv[l], items = (lv[l + 1] - pb) * gw;
         for (int32_t t = tid; t < items; t += WG) {
-          const Item it = load_item<kOne>(pb, items, t, nr, v, rw, rix);
-          v[(int64_t)it.s * nr + it.c] = solve_item<kOne>(it, nr, v, ovf);
+          const Item it = load_item<kOne>(pb, items, t, gw, v, rw, rix);
+          v[(int64_t)it.s * gw + it.c] = solve_item<kOne>(it, gw, v, ovf);
         }
         lds_barrier();
         if (kTimed && tid == 0) {
@@ -289,15 +294,13 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
       }
     }
     __syncthreads();  // every x of the window is in LDS
-    double *xw = xp + (int64_t)P0 * nr;
     for (int32_t i = tid; i < nitems; i += WG) {
       const double x = v[i];
       if (!isfinite(x)) bits |= EB_NONFINITE;
-      xw[i] = x;
-      if (A.rio.x) {  // and the caller's x, by rows
-        const int32_t sj = kOne ? i : i / nr;
-        A.rio.x[(int64_t)A.rio.perm[P0 + sj] * nr + (kOne ? 0 : i - sj * nr)] = x;
-      }
+      const int32_t sj = kOne ? i : i / gw;
+      const int32_t cj = c0 + (kOne ? 0 : i - sj * gw);
+      xp[(int64_t)(P0 + sj) * nr + cj] = x;
+      if (A.rio.x) A.rio.x[(int64_t)A.rio.perm[P0 + sj] * nr + cj] = x;  // and the caller's x, by rows
     }
     __syncthreads();  // the window's global x is complete before the next phase 1 reads it
   }
@@ -370,19 +373,21 @@ __device__ void prefetch_windows(char *lds_raw, const int4 *__restrict__ win, in
   if (sink == 0x9e3779b9u) tp[2] = sink;  // keeps the loads; the value is never read
 }
 
+// One thin run: workgroup g < nrhs / ng solves columns g*ng .. g*ng + ng - 1;
+// with one solver (ng = nrhs) the launcher may add prefetch helpers after it.
 template <int WG, bool kOne, bool kTimed = false>
-__global__ __launch_bounds__(WG) void k_thin_run(const int4 *__restrict__ win, int32_t nwin, int32_t nrhs, ThinArgs A,
-                                                 int *err, float *times, float ns_per_tick) {
+__global__ __launch_bounds__(WG) void k_thin_run(const int4 *__restrict__ win, int32_t nwin, int32_t nrhs, int32_t ng,
+                                                 ThinArgs A, int *err, float *times, float ns_per_tick) {
   extern __shared__ __align__(16) char lds_raw[];
-  if (blockIdx.x != 0) {  // helpers exist only when the launcher gave the grid room for them
+  const int32_t nsolver = nrhs / ng;
+  if ((int32_t)blockIdx.x >= nsolver) {  // helpers exist only when the launcher gave the grid room for them
     if (blockIdx.x % kXcd == 0) prefetch_windows<WG>(lds_raw, win, nwin, nrhs, A, (int)(blockIdx.x / kXcd) - 1);
     return;
   }
   unsigned ep = 0;
   if (A.tp) ep = __hip_atomic_load(A.tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int bits =
-      thin_run_body<WG, kOne, kTimed>(lds_raw, win, nwin, nrhs, A, times, ns_per_tick, A.tp ? A.tp + 1 : nullptr,
-                                      epoch_tag(ep));
+  const int bits = thin_run_body<WG, kOne, kTimed>(lds_raw, win, nwin, nrhs, ng, (int32_t)blockIdx.x * ng, A, times,
+                                                   ns_per_tick, A.tp ? A.tp + 1 : nullptr, epoch_tag(ep));
   if (threadIdx.x == 0) {
     if (bits) atomicOr(err, bits);
     if (A.tp) __hip_atomic_store(A.tp, ep + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -427,7 +432,8 @@ __global__ __launch_bounds__(WG) void k_batch_run(int32_t nmat, const int32_t *_
     __syncthreads();
     if (t >= nmat) break;
     const int32_t m = order[t];
-    bits |= thin_run_body<WG, kOne, false>(lds_raw, win + mwin[m], mwin[m + 1] - mwin[m] - 1, nrhs, A, nullptr, 0.f);
+    bits |= thin_run_body<WG, kOne, false>(lds_raw, win + mwin[m], mwin[m + 1] - mwin[m] - 1, nrhs, nrhs, 0, A,
+                                           nullptr, 0.f);
   }
   if (threadIdx.x == 0) {
     if (bits) atomicOr(err, bits);
@@ -464,26 +470,33 @@ void solve_kernels_init() {
 }
 
 hipError_t launch_thin_run(int wg, const int4 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
-                           hipStream_t s, float *times, float ns_per_tick) {
-  const bool one = nrhs == 1;
-  // the solver, plus kHelp prefetch helpers on its XCD for runs long enough to
-  // use them (windows are numbered below 2^20 in the progress word)
-  const unsigned grid = a.tp && nwin >= kHelpMinWin && nwin < (1 << kTagShift) ? 1 + kXcd * kHelp : 1;
+                           hipStream_t s, float *times, float ns_per_tick, int32_t ng) {
+  if (ng <= 0 || ng > nrhs || nrhs % ng) ng = nrhs;
+  const bool one = ng == 1;
+  ThinArgs aa = a;
+  unsigned grid = (unsigned)(nrhs / ng);  // one solver per group of ng columns
+  if (grid == 1) {
+    // the solver, plus kHelp prefetch helpers on its XCD for runs long enough
+    // to use them (windows are numbered below 2^20 in the progress word)
+    if (a.tp && nwin >= kHelpMinWin && nwin < (1 << kTagShift)) grid = 1 + kXcd * kHelp;
+  } else {
+    aa.tp = nullptr;  // several solvers: no helpers, no progress words
+  }
   if (times) {  // labelling runs only: 512 threads
     if (one)
-      hipLaunchKernelGGL((k_thin_run<512, true, true>), dim3(grid), dim3(512), kWinBytes, s, win, nwin, nrhs, a, err,
-                         times, ns_per_tick);
+      hipLaunchKernelGGL((k_thin_run<512, true, true>), dim3(grid), dim3(512), kWinBytes, s, win, nwin, nrhs, ng, aa,
+                         err, times, ns_per_tick);
     else
-      hipLaunchKernelGGL((k_thin_run<512, false, true>), dim3(grid), dim3(512), kWinBytes, s, win, nwin, nrhs, a, err,
-                         times, ns_per_tick);
+      hipLaunchKernelGGL((k_thin_run<512, false, true>), dim3(grid), dim3(512), kWinBytes, s, win, nwin, nrhs, ng,
+                         aa, err, times, ns_per_tick);
     return hipGetLastError();
   }
 #define THIN(W)                                                                                              \
   if (one)                                                                                                   \
-    hipLaunchKernelGGL((k_thin_run<W, true>), dim3(grid), dim3(W), kWinBytes, s, win, nwin, nrhs, a, err,       \
+    hipLaunchKernelGGL((k_thin_run<W, true>), dim3(grid), dim3(W), kWinBytes, s, win, nwin, nrhs, ng, aa, err,  \
                        (float *)nullptr, 0.f);                                                               \
   else                                                                                                       \
-    hipLaunchKernelGGL((k_thin_run<W, false>), dim3(grid), dim3(W), kWinBytes, s, win, nwin, nrhs, a, err,      \
+    hipLaunchKernelGGL((k_thin_run<W, false>), dim3(grid), dim3(W), kWinBytes, s, win, nwin, nrhs, ng, aa, err, \
                        (float *)nullptr, 0.f);
   if (wg == 256) {
     THIN(256)

@@ -94,7 +94,7 @@ class LevelCosts(C.Structure):
 class Schedule(C.Structure):
     _fields_ = [("mode", C.c_int32), ("thin_rows", C.c_int32), ("wg_threads", C.c_int32),
                 ("wide_threads", C.c_int32), ("lanes_per_row", C.c_int32), ("wide_grid", C.c_int32),
-                ("overlap", C.c_int32)]
+                ("overlap", C.c_int32), ("thin_cols", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -392,8 +392,8 @@ class Handle:
         return list(out)
 
     def set_schedule(self, which=ORIGINAL, mode=0, thin_rows=4096, wg_threads=512, wide_threads=256,
-                     lanes_per_row=1, wide_grid=0, overlap=0):
-        s = Schedule(mode, thin_rows, wg_threads, wide_threads, lanes_per_row, wide_grid, overlap)
+                     lanes_per_row=1, wide_grid=0, overlap=0, thin_cols=0):
+        s = Schedule(mode, thin_rows, wg_threads, wide_threads, lanes_per_row, wide_grid, overlap, thin_cols)
         self._check(self._L.sptrsv_set_schedule(self._h, which, C.byref(s)))
 
     def get_schedule(self, which=ORIGINAL, nrhs=1):

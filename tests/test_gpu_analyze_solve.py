@@ -195,7 +195,7 @@ def test_state_and_arg_errors(handles):
 
 
 @pytest.mark.parametrize("bad", [dict(mode=5), dict(overlap=2), dict(overlap=-1), dict(lanes_per_row=3), dict(wg_threads=300),
-                                 dict(mode=4, wide_threads=1024), dict(mode=3, wide_grid=4096)])
+                                 dict(mode=4, wide_threads=1024), dict(mode=3, wide_grid=4096), dict(thin_cols=-1)])
 def test_bad_schedule_is_refused(handles, bad):
     _, h, _ = handles["cfg0"]
     with pytest.raises(sp.SptrsvError) as ei:
@@ -282,9 +282,10 @@ def test_set_schedule_replaces_tuned(handles):
     tuned = h.get_schedule(nrhs=2)
     assert tuned["mode"] in (0, 1, 2, 3)
     assert h.get_schedule(nrhs=1) == dict(mode=0, thin_rows=4096, wg_threads=512, wide_threads=256, lanes_per_row=1,
-                                          wide_grid=0, overlap=0)
+                                          wide_grid=0, overlap=0, thin_cols=0)
     assert tuned["overlap"] == 0  # the autotuner keeps the transposes out of the chain
-    want = dict(mode=0, thin_rows=64, wg_threads=256, wide_threads=128, lanes_per_row=1, wide_grid=0, overlap=0)
+    want = dict(mode=0, thin_rows=64, wg_threads=256, wide_threads=128, lanes_per_row=1, wide_grid=0, overlap=0,
+                thin_cols=0)
     h.set_schedule(**want)
     assert h.get_schedule(nrhs=2) == want  # an explicit schedule replaces the tuned one
     h.prepare(nrhs=2)

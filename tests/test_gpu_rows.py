@@ -167,3 +167,36 @@ def test_rows_autotune(mats):
     with pytest.raises(sp.SptrsvError) as ei:
         h.autotune(sp.BATCH, 8, rows=True)
     assert ei.value.name == "ARG"
+
+
+@pytest.mark.parametrize("tc", [1, 2, 4, 8, 16, 3])
+@pytest.mark.parametrize("name", ["stencil3d_tail", "window"])
+def test_thin_cols(mats, name, tc):
+    """Thin runs split over workgroups by columns, in both layouts, with and
+    without the rewrite, against the oracle; the two layouts agree bit for bit
+    under the same schedule. (The LDS windows are cut for the workgroup's
+    columns, so which dependencies a window reads from global memory, and with
+    them the rounding, can differ from the unsplit schedule.) A width that
+    does not divide nrhs falls back to all columns in one workgroup, bit for
+    bit the unsplit result."""
+    m = mats[name]
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    h.rewrite(sp.THIN_ROWS, 32, 4.0)
+    b_cols = gen.rhs(m, 16)
+    bc = torch.from_numpy(b_cols).cuda()
+    x_ref = oracle.solve(m, b_cols)
+    for which in (sp.ORIGINAL, sp.REWRITTEN):
+        print(f"thin_cols: {name} tc={tc} which={which}", flush=True)
+        h.set_schedule(which, mode=0, thin_rows=256, wg_threads=512)
+        ref = h.solve(bc, which)
+        h.check()
+        h.set_schedule(which, mode=0, thin_rows=256, wg_threads=512, thin_cols=tc)
+        assert h.get_schedule(which, 16)["thin_cols"] == tc
+        x_cols = h.solve(bc, which)
+        x_rows = h.solve_rows(bc.t().contiguous(), which)
+        h.check()
+        assert torch.equal(x_rows.t(), x_cols)
+        assert oracle.relerr(x_cols.cpu().numpy(), x_ref) <= TOL
+        if 16 % tc:
+            assert torch.equal(x_cols, ref)

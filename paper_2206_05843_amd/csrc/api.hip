@@ -220,7 +220,7 @@ sptrsv_status_t build_images(sptrsv_ctx *h, Plan &P, hipStream_t s) {
   HIPCHK(h, P.ext.reserve((size_t)next));
   HIPCHK(h, hipMemcpyAsync(P.win.p, P.h_win.data(), sizeof(int4) * (size_t)nent, hipMemcpyHostToDevice, s));
   HIPCHK(h, launch_img_fill(n, P.level_ptr.p, P.nlev, d_lw.p, P.win.p, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, oex.p,
-                            P.ext_ptr.p, P.img.p, P.ext.p, s));
+                            P.ext_ptr.p, P.img.p, P.ext.p, io_perm(P), s));
   HIPCHK(h, hipStreamSynchronize(s));
   return SPTRSV_OK;
 }
@@ -757,10 +757,16 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
 }
 
 // The flags of the rows of T with off-diagonals, for solves by rows.
+// And the first four dependencies of every position as caller rows.
 sptrsv_status_t ensure_rows(sptrsv_ctx *h, Plan &P, hipStream_t s) {
-  if (!P.has_t || P.tflag.p || P.n == 0) return SPTRSV_OK;
-  HIPCHK(h, P.tflag.alloc((size_t)P.n));
-  HIPCHK(h, launch_tflag(P.n, P.n_tpos, P.tpos.p, P.tflag.p, s));
+  if (P.rows_ready || P.n == 0) return SPTRSV_OK;
+  if (P.has_t) {
+    HIPCHK(h, P.tflag.alloc((size_t)P.n));
+    HIPCHK(h, launch_tflag(P.n, P.n_tpos, P.tpos.p, P.tflag.p, s));
+  }
+  HIPCHK(h, P.ell_r.alloc((size_t)P.n));
+  HIPCHK(h, launch_map_ell(P.n, P.ell_c.p, io_perm(P), P.ell_r.p, s));
+  P.rows_ready = true;
   return SPTRSV_OK;
 }
 
@@ -783,7 +789,7 @@ sptrsv_status_t solve_rows(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
       HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, perm, P.trp.p, P.tci.p, P.tva.p, b, nrhs, 1, bp,
                                s));
     ThinArgs ta = thin_args(P, bp, xp);
-    ta.rio = RowsIO{b, x, perm, P.has_t ? P.tflag.p : nullptr};
+    ta.rio = RowsIO{b, x, perm, P.has_t ? P.tflag.p : nullptr, P.ell_r.p};
     for (const Run &r : P.runs) STCHK(launch_run(h, P, r, nrhs, ta, bp, xp, s));
     return SPTRSV_OK;
   }

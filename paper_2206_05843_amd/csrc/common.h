@@ -68,11 +68,12 @@ struct __align__(16) Dep {
   int32_t slot, pad;
 };
 
-// One dependency on a row before the row's LDS window: the unscaled weight and
-// the position whose final x it reads.
+// One dependency on a row before the row's LDS window: the unscaled weight,
+// the position whose final x it reads, and that position's row in the
+// caller's numbering (where a solve by rows reads it).
 struct __align__(16) ExtDep {
   double w;
-  int32_t col, pad;
+  int32_t col, row;
 };
 
 // One run of the solve schedule: a range of levels done inside one workgroup
@@ -128,6 +129,8 @@ struct Plan {
   DArr<double> tva;
   DArr<int32_t> tpos;                  // positions whose row of T has off-diagonals
   DArr<uint8_t> tflag;                 // 1 at those positions (solves by rows; built on demand)
+  DArr<int4> ell_r;                    // [n] ell_c in the caller's rows (solves by rows; built on demand)
+  bool rows_ready = false;
   int32_t n_tpos = 0;
   int32_t t_lanes = 1;                 // lanes per row of T in the b-transform
   DArr<int64_t> lv_rows, lv_nnz, lv_cost;
@@ -350,13 +353,16 @@ inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
 // work vectors.
 // Right-hand sides stored by rows (b null: the work vectors only): b is read
 // at b[perm[pos] * nrhs + c] except where tflag[pos] marks a row of T with
-// off-diagonals (b' already in the work vector), and x is also written to
-// x[perm[pos] * nrhs + c].
+// off-diagonals (b' already in the work vector), and x is written to
+// x[perm[pos] * nrhs + c] only: the caller's x is the work vector, and
+// dependencies are read from it through caller rows (ell_r: a position's
+// first four dependencies as caller rows, -1 padded; perm for the rest).
 struct RowsIO {
   const double *b;
   double *x;
   const int32_t *perm;
   const uint8_t *tflag;
+  const int4 *ell_r;
 };
 
 struct ThinArgs {
@@ -387,6 +393,8 @@ hipError_t launch_gather_rows(int32_t n, int32_t nrhs, const double *b, const in
 hipError_t launch_scatter_rows(int32_t n, int32_t nrhs, const double *xp, const int32_t *perm, double *x,
                                hipStream_t s);
 hipError_t launch_tflag(int32_t n, int32_t nt, const int32_t *tpos, uint8_t *tflag, hipStream_t s);
+// ell_r[p] = ell_c[p] with every position k >= 0 replaced by perm[k]
+hipError_t launch_map_ell(int32_t n, const int4 *ell_c, const int32_t *perm, int4 *ell_r, hipStream_t s);
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
 // The same over a list of caller-row tiles of 64 rows.
@@ -494,7 +502,8 @@ hipError_t launch_win_prefix(int32_t nent, const int4 *win, const int32_t *level
                              const long long *ovf_ex, const long long *ovf_cnt, long long *out, hipStream_t s);
 hipError_t launch_img_fill(int32_t n, const int32_t *level_ptr, int32_t nlev, const int32_t *lvl_win, const int4 *win,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                           const long long *ovf_ex, const int32_t *ext_ptr, uint4 *img, ExtDep *ext, hipStream_t s);
+                           const long long *ovf_ex, const int32_t *ext_ptr, uint4 *img, ExtDep *ext,
+                           const int32_t *perm, hipStream_t s);
 // Batched launchers (k_solve.hip) -------------------------------------------------
 hipError_t launch_batch_run(int wg, int32_t nmat, int32_t grid, const int32_t *order, const int32_t *mwin,
                             const int4 *win, int32_t nrhs, const ThinArgs &a, unsigned *q, int *err, hipStream_t s);

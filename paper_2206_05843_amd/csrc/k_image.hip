@@ -63,7 +63,7 @@ __global__ void k_img_fill(int32_t n, const int32_t *__restrict__ level_ptr, int
                            const int32_t *__restrict__ srp, const int32_t *__restrict__ sci,
                            const double *__restrict__ sva, const double *__restrict__ sdg,
                            const long long *__restrict__ ovf_ex, const int32_t *__restrict__ ext_ptr, uint4 *img,
-                           ExtDep *ext) {
+                           ExtDep *ext, const int32_t *__restrict__ perm) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
     const int32_t wi = lvl_win[level_of(level_ptr, nlev, (int32_t)p)];
     if (wi < 0) continue;
@@ -84,7 +84,7 @@ __global__ void k_img_fill(int32_t n, const int32_t *__restrict__ level_ptr, int
         ExtDep d;
         d.w = wv;
         d.col = k;
-        d.pad = 0;
+        d.row = perm ? perm[k] : k;
         ext[e++] = d;
         continue;
       }
@@ -129,9 +129,10 @@ hipError_t launch_win_prefix(int32_t nent, const int4 *win, const int32_t *level
 
 hipError_t launch_img_fill(int32_t n, const int32_t *level_ptr, int32_t nlev, const int32_t *lvl_win, const int4 *win,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
-                           const long long *ovf_ex, const int32_t *ext_ptr, uint4 *img, ExtDep *ext, hipStream_t s) {
+                           const long long *ovf_ex, const int32_t *ext_ptr, uint4 *img, ExtDep *ext,
+                           const int32_t *perm, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_img_fill, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, s, n, level_ptr, nlev, lvl_win,
-                     win, srp, sci, sva, sdg, ovf_ex, ext_ptr, img, ext);
+                     win, srp, sci, sva, sdg, ovf_ex, ext_ptr, img, ext, perm);
   return hipGetLastError();
 }

@@ -148,6 +148,7 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
   const ExtDep *__restrict__ ext = A.ext;
   const double *__restrict__ bp = A.bp;
   double *xp = A.xp;
+  const double *xs = A.rio.x ? A.rio.x : xp;  // where the x of earlier windows is read
   int bits = 0;
   unsigned long long t_w0 = 0, t_prev = 0;
   float p1_per_row = 0.f;
@@ -227,10 +228,11 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
           for (int d = 0; d < kBatch; ++d) {
             const ExtDep x = ext[e + d < e1[j] ? e + d : e];
             wv[d] = x.w;
-            k[d] = x.col;
+            k[d] = A.rio.x ? x.row : x.col;
           }
+          // by rows the caller's x is the work vector, read by caller row
 #pragma unroll
-          for (int d = 0; d < kBatch; ++d) xv[d] = xp[(int64_t)k[d] * nr + c];
+          for (int d = 0; d < kBatch; ++d) xv[d] = xs[(int64_t)k[d] * nr + c];
 #pragma unroll
           for (int d = 0; d < kBatch; ++d)
             if (e + d < e1[j]) a -= wv[d] * xv[d];
@@ -299,8 +301,10 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
       if (!isfinite(x)) bits |= EB_NONFINITE;
       const int32_t sj = kOne ? i : i / gw;
       const int32_t cj = c0 + (kOne ? 0 : i - sj * gw);
-      xp[(int64_t)(P0 + sj) * nr + cj] = x;
-      if (A.rio.x) A.rio.x[(int64_t)A.rio.perm[P0 + sj] * nr + cj] = x;  // and the caller's x, by rows
+      if (A.rio.x)  // by rows: the caller's x only
+        A.rio.x[(int64_t)A.rio.perm[P0 + sj] * nr + cj] = x;
+      else
+        xp[(int64_t)(P0 + sj) * nr + cj] = x;
     }
     __syncthreads();  // the window's global x is complete before the next phase 1 reads it
   }

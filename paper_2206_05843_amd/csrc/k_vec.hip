@@ -188,6 +188,14 @@ __global__ void k_scatter_rows(int64_t total, int32_t nrhs, const double *__rest
   }
 }
 
+__global__ void k_map_ell(int32_t n, const int4 *__restrict__ ell_c, const int32_t *__restrict__ perm, int4 *ell_r) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int4 e = ell_c[i];
+    ell_r[i] = make_int4(e.x >= 0 ? perm[e.x] : -1, e.y >= 0 ? perm[e.y] : -1, e.z >= 0 ? perm[e.z] : -1,
+                         e.w >= 0 ? perm[e.w] : -1);
+  }
+}
+
 __global__ void k_tflag_zero(int32_t n, uint8_t *tflag) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) tflag[i] = 0;
 }
@@ -406,6 +414,12 @@ hipError_t launch_scatter_rows(int32_t n, int32_t nrhs, const double *xp, const 
   const int64_t total = (int64_t)n * nrhs;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(total, 256, 16384)), dim3(256), 0, s, total, nrhs, xp, perm, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_ell(int32_t n, const int4 *ell_c, const int32_t *perm, int4 *ell_r, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_map_ell, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, ell_c, perm, ell_r);
   return hipGetLastError();
 }
 

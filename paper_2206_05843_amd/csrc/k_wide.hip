@@ -50,7 +50,7 @@ __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t
       c[j] = kOne ? 0 : (int32_t)(itc - (int64_t)(pos[j] - pb) * nr);
       qb[j] = srp[pos[j]];
       deg[j] = it < items ? srp[pos[j] + 1] - qb[j] : 0;
-      ec[j] = ell_c[pos[j]];
+      ec[j] = rio.x ? rio.ell_r[pos[j]] : ell_c[pos[j]];
       e0[j] = ell_v[2 * (int64_t)pos[j]];
       e1[j] = ell_v[2 * (int64_t)pos[j] + 1];
       row[j] = rio.b ? rio.perm[pos[j]] : 0;
@@ -62,12 +62,14 @@ __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t
         acc[j] = bp[(int64_t)pos[j] * nr + c[j]];
       dg[j] = sdg[pos[j]];
     }
+    // by rows the caller's x is the work vector: dependencies as caller rows
+    const double *xs = rio.x ? rio.x : xp;
     double xv[kI][4];
 #pragma unroll
     for (int j = 0; j < kI; ++j) {
       const int32_t kk[4] = {ec[j].x, ec[j].y, ec[j].z, ec[j].w};
 #pragma unroll
-      for (int d = 0; d < 4; ++d) xv[j][d] = d < deg[j] ? xp[(int64_t)kk[d] * nr + c[j]] : 0.0;
+      for (int d = 0; d < 4; ++d) xv[j][d] = d < deg[j] ? xs[(int64_t)kk[d] * nr + c[j]] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < kI; ++j) {
@@ -86,16 +88,22 @@ __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t
           k4[d] = q0 + d < qe ? sci[q0 + d] : -1;
           w4[d] = q0 + d < qe ? sva[q0 + d] : 0.0;
         }
+        if (rio.x) {
 #pragma unroll
-        for (int d = 0; d < 4; ++d) x4[d] = k4[d] >= 0 ? xp[(int64_t)k4[d] * nr + c[j]] : 0.0;
+          for (int d = 0; d < 4; ++d) k4[d] = k4[d] >= 0 ? rio.perm[k4[d]] : -1;
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) x4[d] = k4[d] >= 0 ? xs[(int64_t)k4[d] * nr + c[j]] : 0.0;
 #pragma unroll
         for (int d = 0; d < 4; ++d)
           if (k4[d] >= 0) a -= w4[d] * x4[d];
       }
       const double x = a / dg[j];
       if (!isfinite(x)) bits |= EB_NONFINITE;
-      xp[(int64_t)pos[j] * nr + c[j]] = x;
-      if (rio.x) rio.x[(int64_t)row[j] * nr + c[j]] = x;
+      if (rio.x)
+        rio.x[(int64_t)row[j] * nr + c[j]] = x;
+      else
+        xp[(int64_t)pos[j] * nr + c[j]] = x;
     }
   }
   if (bits) atomicOr(err, bits);
@@ -147,7 +155,7 @@ __device__ __forceinline__ void wide_fetch(int64_t it, int32_t pb, int32_t nr, c
   w.c = kOne ? 0 : (int32_t)(it - (int64_t)(w.pos - pb) * nr);
   w.qb = srp[w.pos];
   w.deg = srp[w.pos + 1] - w.qb;
-  w.ec = ell_c[w.pos];
+  w.ec = rio.x ? rio.ell_r[w.pos] : ell_c[w.pos];
   w.e0 = ell_v[2 * (int64_t)w.pos];
   w.e1 = ell_v[2 * (int64_t)w.pos + 1];
   w.row = rio.b ? rio.perm[w.pos] : 0;
@@ -166,13 +174,14 @@ template <int kK>
 __device__ __forceinline__ void wide_solve(const WideItem (&w)[kK], const bool (&ok)[kK], int32_t nr,
                                            const int32_t *__restrict__ sci, const double *__restrict__ sva,
                                            double *xp, const RowsIO &rio, int &bits) {
+  double *xs = rio.x ? rio.x : xp;  // by rows the caller's x is the work vector
   double xv[kK][4];
 #pragma unroll
   for (int j = 0; j < kK; ++j) {
     const int32_t kk[4] = {w[j].ec.x, w[j].ec.y, w[j].ec.z, w[j].ec.w};
 #pragma unroll
     for (int d = 0; d < 4; ++d)
-      xv[j][d] = ok[j] && d < w[j].deg ? __hip_atomic_load(xp + (int64_t)kk[d] * nr + w[j].c, __ATOMIC_RELAXED,
+      xv[j][d] = ok[j] && d < w[j].deg ? __hip_atomic_load(xs + (int64_t)kk[d] * nr + w[j].c, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT)
                                         : 0.0;
   }
@@ -193,9 +202,13 @@ __device__ __forceinline__ void wide_solve(const WideItem (&w)[kK], const bool (
         k4[d] = q0 + d < qe ? sci[q0 + d] : -1;
         w4[d] = q0 + d < qe ? sva[q0 + d] : 0.0;
       }
+      if (rio.x) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) k4[d] = k4[d] >= 0 ? rio.perm[k4[d]] : -1;
+      }
 #pragma unroll
       for (int d = 0; d < 4; ++d)
-        x4[d] = k4[d] >= 0 ? __hip_atomic_load(xp + (int64_t)k4[d] * nr + w[j].c, __ATOMIC_RELAXED,
+        x4[d] = k4[d] >= 0 ? __hip_atomic_load(xs + (int64_t)k4[d] * nr + w[j].c, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT)
                            : 0.0;
 #pragma unroll
@@ -204,8 +217,8 @@ __device__ __forceinline__ void wide_solve(const WideItem (&w)[kK], const bool (
     }
     const double x = a / w[j].dg;
     if (!isfinite(x)) bits |= EB_NONFINITE;
-    __hip_atomic_store(xp + (int64_t)w[j].pos * nr + w[j].c, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (rio.x) rio.x[(int64_t)w[j].row * nr + w[j].c] = x;
+    __hip_atomic_store(xs + (int64_t)(rio.x ? w[j].row : w[j].pos) * nr + w[j].c, x, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

@@ -213,7 +213,8 @@ def bench_batch(args, np, torch, gen, oracle, sp):
 def bench_precond(args, np, torch, gen, oracle, sp):
     """One step = z = L^-T (L^-1 r): a forward solve with L and a transposed
     solve with the same factor (sptrsv_analyze_form, LOWER_TRANS), each
-    rewritten by the naive rule and autotuned, replayed as hipGraphs."""
+    rewritten by the naive rule and autotuned, replayed as hipGraphs. r, the
+    intermediate y and z are stored by rows (n x nrhs) unless --layout cols."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
@@ -224,7 +225,17 @@ def bench_precond(args, np, torch, gen, oracle, sp):
     t_oracle = time.perf_counter() - t0
     log(f"[bench] oracle application {t_oracle:.1f}s")
     rp, ci, va = (torch.from_numpy(a).to(dev) for a in (m.row_ptr, m.col, m.val))
+    rows = (args.layout or "rows") == "rows"
     r = torch.from_numpy(r_np).to(dev)
+    if rows:
+        r = r.t().contiguous()  # (n, nrhs): a row's right-hand sides together
+
+    def solve(h, which, b, x):
+        return h.solve_rows(b, which, x) if rows else h.solve(b, which, x)
+
+    def graph(h, which, b, x):
+        return h.graph_create_rows(b, x, which) if rows else h.graph_create(b, x, which)
+
     out_var = {}
     best = None
     for name, rewrite in (("plain", False), ("naive", True)):
@@ -242,18 +253,18 @@ def bench_precond(args, np, torch, gen, oracle, sp):
                 which = sp.REWRITTEN
                 info[f"nlev_{key}"] = st["nlev_after"]
                 info[f"nnz_T_{key}"] = st["nnz_T"]
-            h.autotune(which, nrhs)
+            h.autotune(which, nrhs, rows=rows)
             info[f"schedule_{key}"] = h.get_schedule(which, nrhs)
             hs.append((h, which))
-        hs[0][0].solve(r, hs[0][1], y)
-        hs[1][0].solve(y, hs[1][1], z)
+        solve(hs[0][0], hs[0][1], r, y)
+        solve(hs[1][0], hs[1][1], y, z)
         for h, _ in hs:
             h.check()
-        info["relerr"] = oracle.relerr(z.cpu().numpy(), z_ref)
+        info["relerr"] = oracle.relerr((z.t() if rows else z).cpu().numpy(), z_ref)
         if not info["relerr"] <= TOL:
             raise SystemExit(f"[bench] {name} application failed parity: relerr={info['relerr']:.3e}")
-        g0 = hs[0][0].graph_create(r, y, hs[0][1])
-        g1 = hs[1][0].graph_create(y, z, hs[1][1])
+        g0 = graph(hs[0][0], hs[0][1], r, y)
+        g1 = graph(hs[1][0], hs[1][1], y, z)
         for _ in range(args.warmup):
             hs[0][0].graph_launch(g0)
             hs[1][0].graph_launch(g1)
@@ -268,8 +279,8 @@ def bench_precond(args, np, torch, gen, oracle, sp):
         for h, _ in hs:
             h.profile_start()
         for _ in range(args.steps):
-            hs[0][0].solve(r, hs[0][1], y)
-            hs[1][0].solve(y, hs[1][1], z)
+            solve(hs[0][0], hs[0][1], r, y)
+            solve(hs[1][0], hs[1][1], y, z)
         torch.cuda.synchronize()
         prof = {}
         for h, _ in hs:
@@ -295,6 +306,13 @@ def bench_precond(args, np, torch, gen, oracle, sp):
     bpl = dp["bytes"] / max(1, dp["launches"])
     achieved = bpl / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     kname = {"thin_run": "k_thin_run", "wide_level": "k_wide_level", "gather": "k_gather", "scatter": "k_scatter"}[dom]
+    hsched = head["schedule_L"]
+    if dom == "wide_level" and hsched["mode"] == 3:
+        kname = "k_sf_solve"
+    elif dom == "wide_level" and hsched["mode"] == 4:
+        kname = "k_flow_run"
+    elif dom == "wide_level" and hsched["wide_grid"] > 0:
+        kname = "k_wide_run"
     cpu = None
     if not args.no_cpu:
         cpu = {"value": round(1.0 / t_oracle, 5), "unit": "applications/s", "cores": 1, "kind": "oracle",
@@ -306,6 +324,8 @@ def bench_precond(args, np, torch, gen, oracle, sp):
         "warmup": args.warmup, "ms_per_step": round(head["ms"], 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded generator of the workload's structure; no dataset)",
         "config": {"workload": WORKLOADS[5], "variant": best, "nrhs": nrhs, "n": m.n, "nnz": m.nnz,
+                   "layout": ("r, y and z by rows (n x nrhs row-major)" if rows
+                              else "r, y and z by columns (column-major, leading dimension n)"),
                    "parallelism": "single GPU", "timing": "hipGraph replays (one graph per solve)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": load_traffic(kname, "config5_" + best),
@@ -388,7 +408,8 @@ def main():
     ap.add_argument("--layout", default=None, choices=("cols", "rows"),
                     help="how the right-hand sides are stored: cols (column-major, a column per right-hand side) "
                          "or rows (n x nrhs row-major, solved with sptrsv_solve_rows); default rows for the 3D "
-                         "stencil workload, whose other layout is timed too and reported beside it")
+                         "stencil workloads (the solve, whose other layout is timed too and reported beside it, "
+                         "and the preconditioner application)")
     ap.add_argument("--graph", type=int, default=None, choices=(0, 1),
                     help="time hipGraph replays of the solve (default: on for the 3D stencil workload)")
     ap.add_argument("--analysis-only", action="store_true",

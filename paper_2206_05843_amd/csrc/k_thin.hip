@@ -299,6 +299,10 @@ __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restri
     for (int32_t i = tid; i < nitems; i += WG) {
       const double x = v[i];
       if (!isfinite(x)) bits |= EB_NONFINITE;
+      if (!A.rio.x && gw == nr) {  // all columns in this workgroup: the window is one contiguous block
+        xp[(int64_t)P0 * nr + i] = x;
+        continue;
+      }
       const int32_t sj = kOne ? i : i / gw;
       const int32_t cj = c0 + (kOne ? 0 : i - sj * gw);
       if (A.rio.x)  // by rows: the caller's x only

@@ -63,6 +63,37 @@ def test_full_solve_autotuned(full, cfg, variant):
     assert torch.equal(x, x2)
 
 
+@pytest.mark.parametrize("variant", ["plain", "naive"])
+def test_full_solve_rows_graph(full, variant):
+    """The 3D stencil workload as the benchmark times it: right-hand sides by
+    rows, tuned by rows, solved in hipGraph replays; every output against the
+    oracle, every replay bit for bit the eager solve."""
+    m, nrhs, b, xr = full[4]
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    which = sp.ORIGINAL
+    if variant == "naive":
+        h.rewrite(sp.THIN_ROWS, 32.0, 4.0, 0)
+        which = sp.REWRITTEN
+    h.autotune(which, nrhs, rows=True)
+    print(f"full rows: {variant} schedule={h.get_schedule(which, nrhs)}", flush=True)
+    br = to_dev(b).t().contiguous()
+    x = h.solve_rows(br, which)
+    h.check()
+    assert oracle.relerr(x.t().cpu().numpy(), xr) <= TOL
+    xg = torch.zeros_like(x)
+    st = torch.cuda.Stream()  # graph capture needs a non-default stream
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        gid = h.graph_create_rows(br, xg, which)
+        for _ in range(3):
+            xg.zero_()
+            h.graph_launch(gid)
+            st.synchronize()
+            assert torch.equal(xg, x)
+        h.check()
+
+
 def _oracle_policy_actions(m, lv, pol):
     """The shipped policy's per-level actions computed on the CPU side: the
     oracle's FP64 features through the FP64 network with the checkpoint's

@@ -22,7 +22,9 @@ sptrsv_mod = pytest.importorskip("paper_2206_05843_amd.sptrsv")
 TOL = 1e-10
 SCHEDS = [dict(mode=0, thin_rows=64, wg_threads=512), dict(mode=0, thin_rows=4096, wg_threads=1024),
           dict(mode=1, wide_threads=128), dict(mode=2, wg_threads=256),
-          dict(mode=1, wide_grid=64), dict(mode=3, wide_grid=128), dict(mode=4, thin_rows=64, wide_threads=256)]
+          dict(mode=1, wide_grid=64), dict(mode=3, wide_grid=128), dict(mode=4, thin_rows=64, wide_threads=256),
+          dict(mode=0, thin_rows=64, wg_threads=1024, wide_grid=4096, thin_cols=1),
+          dict(mode=0, thin_rows=256, wg_threads=512, wide_grid=256, wide_threads=512, thin_cols=2)]
 MATS = {"stencil3d_tail": lambda: gen.stencil3d_tail(16, 300, 5), "window": lambda: gen.window_random(3000, 7, 40, 5),
         "cfg2_small": lambda: gen.config_matrix(2, "small")[0]}
 

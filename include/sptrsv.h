@@ -298,8 +298,9 @@ sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, 
 /* Autotuner: times candidate schedules with HIP events on s (inputs b = 1) and
  * keeps the fastest for (which, nrhs), then tries the wide launches of a best
  * split schedule (mode 0) with 64, 128 and 512 threads per workgroup, and,
- * with several right-hand sides, the thin runs of the best schedule split
- * over workgroups by columns (thin_cols 1, 2, 4, ... dividing nrhs); for
+ * with several right-hand sides, the other splits of the best schedule's thin
+ * runs over workgroups by columns (the candidates split them one column per
+ * workgroup; then thin_cols 2, 4, ... dividing nrhs, and all columns); for
  * SPTRSV_BATCH the candidates are the
  * workgroup sizes of the persistent launch. best_ms (host, may be NULL) receives the
  * best solve time. Synchronous.

@@ -12,22 +12,23 @@ __global__ void k_fill(double *a, int64_t n, double v) {
 }
 
 // Candidate schedules: all-wide, all-in-one-workgroup, and thin/wide splits at
-// several widths, workgroup sizes and (one RHS) lanes per row.
+// several widths, workgroup sizes and (one RHS) lanes per row. With several
+// right-hand sides the thin runs start split one column per workgroup (their
+// windows cut for one column); other splits are tried around the best.
 std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
   std::vector<sptrsv_schedule_t> c;
   const int thin_list[] = {64, 256, 1024, 4096, 16384};
   const int wg_list[] = {256, 512, 1024};
   const int lpr1[] = {1, 4};
-  for (int wg : wg_list) {
-    sptrsv_schedule_t s{2, 0, wg, 256, 1, 0};
-    c.push_back(s);
-  }
+  const int32_t tc = nrhs > 1 ? 1 : 0;  // thin_cols of the first round
+  const int32_t gw = nrhs > 1 ? 1 : nrhs;
+  for (int wg : wg_list) c.push_back(sptrsv_schedule_t{2, 0, wg, 256, 1, 0, 0, tc});
   for (int lpr : lpr1) {
     if (nrhs > 1 && lpr > 1) continue;
-    c.push_back(sptrsv_schedule_t{1, 0, 512, 256, lpr, 0});
+    c.push_back(sptrsv_schedule_t{1, 0, 512, 256, lpr, 0, 0, 0});
     for (int thr : thin_list) {
-      if (thin_window_bytes(thr, 0, 1, nrhs) > thin_win_bytes()) continue;
-      for (int wg : wg_list) c.push_back(sptrsv_schedule_t{0, thr, wg, 256, lpr, 0});
+      if (thin_window_bytes(thr, 0, 1, gw) > thin_win_bytes()) continue;
+      for (int wg : wg_list) c.push_back(sptrsv_schedule_t{0, thr, wg, 256, lpr, 0, 0, tc});
     }
   }
   // the synchronisation-free executor at a few grid sizes (workgroups in flight)
@@ -35,8 +36,8 @@ std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
   // dataflow runs of the wide levels (chunk sizes from the workgroup size), thin runs below
   for (int wt : {128, 256, 512})
     for (int thr : {0, 64, 1024}) {
-      if (thin_window_bytes(thr, 0, 1, nrhs) > thin_win_bytes()) continue;
-      c.push_back(sptrsv_schedule_t{4, thr, 1024, wt, 1, 0});
+      if (thin_window_bytes(thr, 0, 1, gw) > thin_win_bytes()) continue;
+      c.push_back(sptrsv_schedule_t{4, thr, 1024, wt, 1, 0, 0, thr > 0 ? tc : 0});
     }
   // consecutive wide levels in one persistent launch (one lane per item; 4096
   // is capped to the workgroups that fit on the device at once)
@@ -44,8 +45,8 @@ std::vector<sptrsv_schedule_t> candidates(int32_t nrhs) {
   for (int g : grids) {
     c.push_back(sptrsv_schedule_t{1, 0, 512, 256, 1, g});
     for (int thr : thin_list) {
-      if (thin_window_bytes(thr, 0, 1, nrhs) > thin_win_bytes()) continue;
-      c.push_back(sptrsv_schedule_t{0, thr, 1024, 256, 1, g});
+      if (thin_window_bytes(thr, 0, 1, gw) > thin_win_bytes()) continue;
+      c.push_back(sptrsv_schedule_t{0, thr, 1024, 256, 1, g, 0, tc});
     }
   }
   return c;
@@ -163,13 +164,18 @@ sptrsv_status_t autotune(sptrsv_ctx *h, int which, int32_t nrhs, bool rows, hipS
       if (st != SPTRSV_OK) break;
     }
   }
-  // several right-hand sides: thin runs split over workgroups by columns
-  // (each solves thin_cols of them), around the best schedule with thin runs
+  // several right-hand sides: the other splits of the thin runs over
+  // workgroups by columns (thin_cols 2, 4, ... and all columns in one
+  // workgroup), around the best schedule with thin runs
   if (st == SPTRSV_OK && !batch && nrhs > 1 && best < 1e29f &&
       (best_s.mode == 2 || ((best_s.mode == 0 || best_s.mode == 4) && best_s.thin_rows > 0))) {
     const sptrsv_schedule_t base = best_s;
-    for (int tc = 1; tc < nrhs; tc *= 2) {
-      if (nrhs % tc) continue;
+    std::vector<int32_t> splits;
+    for (int32_t tc = 1; tc < nrhs; tc *= 2)
+      if (nrhs % tc == 0) splits.push_back(tc);
+    splits.push_back(0);  // all columns in one workgroup
+    for (int32_t tc : splits) {
+      if (tc == base.thin_cols) continue;
       sptrsv_schedule_t cand = base;
       cand.thin_cols = tc;
       float ms = 0.f;

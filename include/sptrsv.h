@@ -290,7 +290,8 @@ typedef struct {
   int32_t overlap;        /* 0 or 1: transposes beside the chain (see above) */
   int32_t thin_cols;      /* right-hand sides per thin-run workgroup: 0 = all; c, a divisor of nrhs smaller than
                              it = nrhs / c workgroups each solve c columns of every thin run (columns are
-                             independent), with LDS windows cut for c columns; otherwise all */
+                             independent), with LDS windows cut for c columns; otherwise all. The batched
+                             launch (SPTRSV_BATCH) solves every column of a matrix in one workgroup */
 } sptrsv_schedule_t;
 sptrsv_status_t sptrsv_set_schedule(sptrsv_handle_t h, int which, const sptrsv_schedule_t *sched);
 sptrsv_status_t sptrsv_get_schedule(sptrsv_handle_t h, int which, int32_t nrhs, sptrsv_schedule_t *sched);

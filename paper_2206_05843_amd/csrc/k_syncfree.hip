@@ -26,6 +26,10 @@ namespace {
 constexpr unsigned long long kPending = 0x7ff4dead5eed5a1dull;
 constexpr int kBlock = 256;
 constexpr int kDeps = 4;  // dependencies requested together (6 or 8 were slower)
+// pause of a wave none of whose lanes moved, in units of 64 cycles: on the 2D
+// stencil + chain 4 took 1.49 ms per solve against 1.52 with 8 and 1.58 with 16
+// (2: 1.48, but slower on the power law)
+constexpr int kSleep = 4;
 
 __global__ void k_sf_init(int64_t total, unsigned long long *xb, unsigned long long *ticket) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
@@ -128,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_sf_solve(int32_t n, int32_t nrhs, co
           moved = true;
         }
       }
-      if (__ballot(moved) == 0ull) __builtin_amdgcn_s_sleep(8);
+      if (__ballot(moved) == 0ull) __builtin_amdgcn_s_sleep(kSleep);
       if ((++spins & 63u) == 0u && wall_clock64() - t0 > tlimit) {
         bits |= EB_TIMEOUT;
         timed_out = true;

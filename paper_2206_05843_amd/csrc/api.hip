@@ -757,7 +757,8 @@ sptrsv_status_t plan_solve(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
 }
 
 // The flags of the rows of T with off-diagonals, for solves by rows.
-// And the first four dependencies of every position as caller rows.
+// And the dependencies of every position as caller rows (the first four in
+// ell_r, all in sci_r).
 sptrsv_status_t ensure_rows(sptrsv_ctx *h, Plan &P, hipStream_t s) {
   if (P.rows_ready || P.n == 0) return SPTRSV_OK;
   if (P.has_t) {
@@ -766,6 +767,9 @@ sptrsv_status_t ensure_rows(sptrsv_ctx *h, Plan &P, hipStream_t s) {
   }
   HIPCHK(h, P.ell_r.alloc((size_t)P.n));
   HIPCHK(h, launch_map_ell(P.n, P.ell_c.p, io_perm(P), P.ell_r.p, s));
+  const int64_t noff = P.nnz - P.n;
+  HIPCHK(h, P.sci_r.alloc((size_t)std::max<int64_t>(noff, 1)));
+  HIPCHK(h, launch_map_cols(noff, P.sci.p, io_perm(P), P.sci_r.p, s));
   P.rows_ready = true;
   return SPTRSV_OK;
 }
@@ -789,7 +793,7 @@ sptrsv_status_t solve_rows(sptrsv_ctx *h, Plan &P, int32_t nrhs, const double *b
       HIPCHK(h, launch_apply_t(P.n_tpos, nrhs, P.t_lanes, P.tpos.p, perm, P.trp.p, P.tci.p, P.tva.p, b, nrhs, 1, bp,
                                s));
     ThinArgs ta = thin_args(P, bp, xp);
-    ta.rio = RowsIO{b, x, perm, P.has_t ? P.tflag.p : nullptr, P.ell_r.p};
+    ta.rio = RowsIO{b, x, perm, P.has_t ? P.tflag.p : nullptr, P.ell_r.p, P.sci_r.p};
     for (const Run &r : P.runs) STCHK(launch_run(h, P, r, nrhs, ta, bp, xp, s));
     return SPTRSV_OK;
   }

@@ -130,6 +130,7 @@ struct Plan {
   DArr<int32_t> tpos;                  // positions whose row of T has off-diagonals
   DArr<uint8_t> tflag;                 // 1 at those positions (solves by rows; built on demand)
   DArr<int4> ell_r;                    // [n] ell_c in the caller's rows (solves by rows; built on demand)
+  DArr<int32_t> sci_r;                 // [nnz - n] sci in the caller's rows (the same)
   bool rows_ready = false;
   int32_t n_tpos = 0;
   int32_t t_lanes = 1;                 // lanes per row of T in the b-transform
@@ -356,13 +357,14 @@ inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
 // off-diagonals (b' already in the work vector), and x is written to
 // x[perm[pos] * nrhs + c] only: the caller's x is the work vector, and
 // dependencies are read from it through caller rows (ell_r: a position's
-// first four dependencies as caller rows, -1 padded; perm for the rest).
+// first four dependencies as caller rows, -1 padded; sci_r: every column).
 struct RowsIO {
   const double *b;
   double *x;
   const int32_t *perm;
   const uint8_t *tflag;
   const int4 *ell_r;
+  const int32_t *sci_r;  // the level-ordered copy's columns as caller rows
 };
 
 struct ThinArgs {
@@ -395,6 +397,8 @@ hipError_t launch_scatter_rows(int32_t n, int32_t nrhs, const double *xp, const 
 hipError_t launch_tflag(int32_t n, int32_t nt, const int32_t *tpos, uint8_t *tflag, hipStream_t s);
 // ell_r[p] = ell_c[p] with every position k >= 0 replaced by perm[k]
 hipError_t launch_map_ell(int32_t n, const int4 *ell_c, const int32_t *perm, int4 *ell_r, hipStream_t s);
+// out[q] = perm[col[q]]
+hipError_t launch_map_cols(int64_t nnz, const int32_t *col, const int32_t *perm, int32_t *out, hipStream_t s);
 hipError_t launch_scatter(int32_t n, int32_t nrhs, const double *xp, const int32_t *iperm, double *x, int64_t ldx,
                           hipStream_t s);
 // The same over a list of caller-row tiles of 64 rows.

@@ -196,6 +196,11 @@ __global__ void k_map_ell(int32_t n, const int4 *__restrict__ ell_c, const int32
   }
 }
 
+__global__ void k_map_cols(int64_t nnz, const int32_t *__restrict__ col, const int32_t *__restrict__ perm, int32_t *out) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x)
+    out[q] = perm[col[q]];
+}
+
 __global__ void k_tflag_zero(int32_t n, uint8_t *tflag) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) tflag[i] = 0;
 }
@@ -420,6 +425,12 @@ hipError_t launch_scatter_rows(int32_t n, int32_t nrhs, const double *xp, const 
 hipError_t launch_map_ell(int32_t n, const int4 *ell_c, const int32_t *perm, int4 *ell_r, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_map_ell, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, n, ell_c, perm, ell_r);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_cols(int64_t nnz, const int32_t *col, const int32_t *perm, int32_t *out, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_map_cols, dim3(grid_for(nnz, 256, 16384)), dim3(256), 0, s, nnz, col, perm, out);
   return hipGetLastError();
 }
 

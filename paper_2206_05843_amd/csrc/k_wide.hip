@@ -80,17 +80,14 @@ __global__ void k_wide_level(int32_t pb, int32_t pe, int32_t nrhs, const int32_t
       for (int d = 0; d < 4; ++d)
         if (d < deg[j]) a -= vv[d] * xv[j][d];
       const int32_t qe = qb[j] + deg[j];
+      const int32_t *cols = rio.x ? rio.sci_r : sci;  // by rows: columns as caller rows
       for (int32_t q0 = qb[j] + 4; q0 < qe; q0 += 4) {
         int32_t k4[4];
         double w4[4], x4[4];
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
-          k4[d] = q0 + d < qe ? sci[q0 + d] : -1;
+          k4[d] = q0 + d < qe ? cols[q0 + d] : -1;
           w4[d] = q0 + d < qe ? sva[q0 + d] : 0.0;
-        }
-        if (rio.x) {
-#pragma unroll
-          for (int d = 0; d < 4; ++d) k4[d] = k4[d] >= 0 ? rio.perm[k4[d]] : -1;
         }
 #pragma unroll
         for (int d = 0; d < 4; ++d) x4[d] = k4[d] >= 0 ? xs[(int64_t)k4[d] * nr + c[j]] : 0.0;
@@ -193,18 +190,18 @@ __device__ __forceinline__ void wide_solve(const WideItem (&w)[kK], const bool (
 #pragma unroll
     for (int d = 0; d < 4; ++d)
       if (d < w[j].deg) a -= vv[d] * xv[j][d];
+    // dependencies beyond the first four, four at a time, in column order
+    // (prefetching the next four's columns and weights here cost registers,
+    // and with them resident waves, on every level)
     const int32_t qe = w[j].qb + w[j].deg;
+    const int32_t *cols = rio.x ? rio.sci_r : sci;  // by rows: columns as caller rows
     for (int32_t q0 = w[j].qb + 4; q0 < qe; q0 += 4) {
       int32_t k4[4];
       double w4[4], x4[4];
 #pragma unroll
       for (int d = 0; d < 4; ++d) {
-        k4[d] = q0 + d < qe ? sci[q0 + d] : -1;
+        k4[d] = q0 + d < qe ? cols[q0 + d] : -1;
         w4[d] = q0 + d < qe ? sva[q0 + d] : 0.0;
-      }
-      if (rio.x) {
-#pragma unroll
-        for (int d = 0; d < 4; ++d) k4[d] = k4[d] >= 0 ? rio.perm[k4[d]] : -1;
       }
 #pragma unroll
       for (int d = 0; d < 4; ++d)

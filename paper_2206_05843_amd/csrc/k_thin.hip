@@ -134,13 +134,16 @@ constexpr int p1_copy() {
 // workgroups by columns; LDS holds ng values per row (windows are cut for ng
 // columns). Returns the latched error bits; a window that does not fit aborts
 // the run.
-template <int WG, bool kOne, bool kTimed>
+// kSplit: the run is split over workgroups by columns (ng < nrhs); without it
+// the strides and the first column are compile-time where they can be.
+template <int WG, bool kOne, bool kTimed, bool kSplit = false>
 __device__ __forceinline__ int thin_run_body(char *lds_raw, const int4 *__restrict__ win, int32_t nwin, int32_t nrhs,
-                                             int32_t ng, int32_t c0, const ThinArgs &A, float *times,
+                                             int32_t ng, int32_t c0_arg, const ThinArgs &A, float *times,
                                              float ns_per_tick, unsigned *prog = nullptr, unsigned ptag = 0) {
   double *lds = reinterpret_cast<double *>(lds_raw + kCtlBytes);
-  const int32_t nr = nrhs;           // stride of the global vectors
-  const int32_t gw = kOne ? 1 : ng;  // columns in LDS and per row of items
+  const int32_t nr = kOne && !kSplit ? 1 : nrhs;  // stride of the global vectors
+  const int32_t gw = kOne ? 1 : ng;               // columns in LDS and per row of items
+  const int32_t c0 = kSplit ? c0_arg : 0;         // the first of those columns
   const int tid = threadIdx.x;
   const int32_t *__restrict__ level_ptr = A.level_ptr;
   const double *__restrict__ sdg = A.sdg;
@@ -383,7 +386,7 @@ __device__ void prefetch_windows(char *lds_raw, const int4 *__restrict__ win, in
 
 // One thin run: workgroup g < nrhs / ng solves columns g*ng .. g*ng + ng - 1;
 // with one solver (ng = nrhs) the launcher may add prefetch helpers after it.
-template <int WG, bool kOne, bool kTimed = false>
+template <int WG, bool kOne, bool kTimed = false, bool kSplit = false>
 __global__ __launch_bounds__(WG) void k_thin_run(const int4 *__restrict__ win, int32_t nwin, int32_t nrhs, int32_t ng,
                                                  ThinArgs A, int *err, float *times, float ns_per_tick) {
   extern __shared__ __align__(16) char lds_raw[];
@@ -394,8 +397,9 @@ __global__ __launch_bounds__(WG) void k_thin_run(const int4 *__restrict__ win, i
   }
   unsigned ep = 0;
   if (A.tp) ep = __hip_atomic_load(A.tp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int bits = thin_run_body<WG, kOne, kTimed>(lds_raw, win, nwin, nrhs, ng, (int32_t)blockIdx.x * ng, A, times,
-                                                   ns_per_tick, A.tp ? A.tp + 1 : nullptr, epoch_tag(ep));
+  const int bits = thin_run_body<WG, kOne, kTimed, kSplit>(lds_raw, win, nwin, nrhs, ng, (int32_t)blockIdx.x * ng, A,
+                                                           times, ns_per_tick, A.tp ? A.tp + 1 : nullptr,
+                                                           epoch_tag(ep));
   if (threadIdx.x == 0) {
     if (bits) atomicOr(err, bits);
     if (A.tp) __hip_atomic_store(A.tp, ep + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -458,6 +462,8 @@ template <int WG, bool kOne>
 void set_lds_attr() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_thin_run<WG, kOne>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_thin_run<WG, kOne, false, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kWinBytes);
 }
 
 }  // namespace
@@ -479,8 +485,9 @@ void solve_kernels_init() {
 
 hipError_t launch_thin_run(int wg, const int4 *win, int32_t nwin, int32_t nrhs, const ThinArgs &a, int *err,
                            hipStream_t s, float *times, float ns_per_tick, int32_t ng) {
-  if (ng <= 0 || ng > nrhs || nrhs % ng) ng = nrhs;
+  if (ng <= 0 || ng > nrhs || nrhs % ng || times) ng = nrhs;  // labelling runs are never split
   const bool one = ng == 1;
+  const bool split = ng < nrhs;
   ThinArgs aa = a;
   unsigned grid = (unsigned)(nrhs / ng);  // one solver per group of ng columns
   if (grid == 1) {
@@ -500,7 +507,13 @@ hipError_t launch_thin_run(int wg, const int4 *win, int32_t nwin, int32_t nrhs, 
     return hipGetLastError();
   }
 #define THIN(W)                                                                                              \
-  if (one)                                                                                                   \
+  if (split && one)                                                                                          \
+    hipLaunchKernelGGL((k_thin_run<W, true, false, true>), dim3(grid), dim3(W), kWinBytes, s, win, nwin, nrhs,  \
+                       ng, aa, err, (float *)nullptr, 0.f);                                                  \
+  else if (split)                                                                                            \
+    hipLaunchKernelGGL((k_thin_run<W, false, false, true>), dim3(grid), dim3(W), kWinBytes, s, win, nwin, nrhs, \
+                       ng, aa, err, (float *)nullptr, 0.f);                                                  \
+  else if (one)                                                                                              \
     hipLaunchKernelGGL((k_thin_run<W, true>), dim3(grid), dim3(W), kWinBytes, s, win, nwin, nrhs, ng, aa, err,  \
                        (float *)nullptr, 0.f);                                                               \
   else                                                                                                       \

@@ -238,9 +238,14 @@ sptrsv_status_t sptrsv_solve_noalloc(sptrsv_handle_t h, int which, int32_t nrhs,
  * dimension. Same x as sptrsv_solve bit for bit (the same kernels and order).
  * With thin runs, wide launches and persistent wide runs (modes 0, 1, 2) the
  * solve kernels read b and write x through the level order themselves, with
- * no transposes; the b-transform writes only the rows of T with off-diagonals
- * into the work vector. The synchronisation-free and dataflow executors
- * (modes 3, 4) copy b in and x out by rows. nrhs = 1 is sptrsv_solve with ld = n. ASYNC and capture-safe once a
+ * no transposes, and d_x serves as the solve's work vector: a dependency's
+ * value is read from it through the caller's row (so d_x must not be read or
+ * written by anything else while the solve runs); the b-transform writes only
+ * the rows of T with off-diagonals into the handle's work vector. The
+ * synchronisation-free and dataflow executors (modes 3, 4) copy b in and x out
+ * by rows. The first solve by rows of a plan maps its columns to caller rows
+ * (about 4 bytes per nonzero and 17 per row of device memory, kept with the
+ * plan). nrhs = 1 is sptrsv_solve with ld = n. ASYNC and capture-safe once a
  * solve of the same (which, nrhs) has run or sptrsv_prepare has been called.
  * Errors as sptrsv_solve (ARG: nrhs < 1, b and x overlapping). */
 sptrsv_status_t sptrsv_solve_rows(sptrsv_handle_t h, int which, int32_t nrhs, const double *d_b, double *d_x,

@@ -109,6 +109,16 @@ static int64_t win_bytes(int64_t rows, int64_t ents, int64_t nl, int32_t nrhs) {
   return thin_window_bytes(rows, ents, nl, nrhs);
 }
 
+// Wide levels whose rows have at least kLongRow off-diagonals on average are
+// solved with a workgroup per row when there are 2 to 256 right-hand sides:
+// a (row, column) item alone would sum them one after another.
+constexpr int64_t kLongRow = 16;
+bool long_rows(const Plan &P, int32_t l, int32_t nrhs) {
+  if (nrhs < 2 || nrhs > 256 || P.h_lv_nnz.size() <= (size_t)l) return false;
+  const int64_t rows = P.h_level_ptr[(size_t)l + 1] - P.h_level_ptr[(size_t)l];
+  return rows > 0 && P.h_lv_nnz[(size_t)l] - rows >= kLongRow * rows;
+}
+
 // Right-hand sides per thin-run workgroup under schedule sc: thin_cols when
 // it divides nrhs (and is smaller), else all of them.
 int32_t thin_width(const sptrsv_schedule_t &sc, int32_t nrhs) {
@@ -384,13 +394,17 @@ sptrsv_status_t make_runs(sptrsv_ctx *h, Plan &P, int32_t nrhs, const sptrsv_sch
     const int64_t rows = rows_of(l);
     bool thin = sc.mode == 2 || ((sc.mode == 0 || flow) && rows <= thr);
     if (win_bytes(rows, 0, 1, gw) > cap) thin = false;  // must fit one window alone
+    // a wide level whose rows average many dependencies, with several
+    // right-hand sides, is a launch of its own with a workgroup per row
+    const bool longr = !thin && long_rows(P, l, nrhs);
     // consecutive thin levels share a run; so do consecutive wide levels of a persistent or dataflow launch
-    if (!P.runs.empty() && P.runs.back().thin == thin && P.runs.back().l1 == l &&
-        (thin || sc.wide_grid > 0 || flow))
+    if (!longr && !P.runs.empty() && P.runs.back().thin == thin && !P.runs.back().longr &&
+        P.runs.back().l1 == l && (thin || sc.wide_grid > 0 || flow))
       P.runs.back().l1 = l + 1;
     else
       P.runs.push_back(Run{l, l + 1, thin});
-    if (!thin) P.runs.back().flow = flow;
+    if (!thin) P.runs.back().flow = flow && !longr;
+    P.runs.back().longr = longr;
   }
   // with the transposes overlapped, long dataflow runs are cut into pieces of
   // about n / kMaxSegments positions so that the chain has segment boundaries
@@ -650,6 +664,12 @@ static sptrsv_status_t launch_run(sptrsv_ctx *h, Plan &P, const Run &r, int32_t 
   if (r.thin) {
     HIPCHK(h, launch_thin_run(sc.wg_threads, P.win.p + r.wi, r.nw, nrhs, ta, err, s, nullptr, 0.f,
                               thin_width(sc, nrhs)));
+  } else if (r.longr) {
+    const int64_t rows = P.h_level_ptr[r.l1] - P.h_level_ptr[r.l0];
+    const int32_t avg = (int32_t)std::min<int64_t>((P.h_lv_nnz[(size_t)r.l0] - rows) / std::max<int64_t>(rows, 1),
+                                                   1 << 20);
+    HIPCHK(h, launch_wide_long(P.h_level_ptr[r.l0], P.h_level_ptr[r.l1], nrhs, avg, P.srp.p, P.sci.p, P.sva.p,
+                               P.sdg.p, bp, xp, err, s, ta.rio));
   } else if (r.flow) {
     const FlowArgs fa{P.flow_pos.p + r.cp, P.flow_dptr.p + r.cp, P.flow_dlist.p, P.flow_lc.p + r.lc,
                       P.flow_flags.p + r.fl, P.flow_ctl.p, P.srp.p, P.sci.p, P.sva.p, P.sdg.p, P.ell_c.p,

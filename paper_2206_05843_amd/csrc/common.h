@@ -87,6 +87,7 @@ struct Run {
   int32_t cp = 0, fl = 0;
   int32_t lc = 0;          // flow: level_chunk [lc, lc + l1 - l0]: first chunk of each level of the run
   int32_t max_chunks = 0;  // flow: chunks of its widest level
+  bool longr = false;      // one wide level of long rows, several right-hand sides: a workgroup per row
 };
 
 // What a dataflow run reads (pointers already offset to the run's chunks):
@@ -425,6 +426,11 @@ hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t
                              const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                              const int4 *ell_c, const double2 *ell_v, const double *bp, double *xp, int *err,
                              hipStream_t s, RowsIO rio = RowsIO{});
+// One wide level [pb, pe) with a workgroup per row (long rows, 2 <= nrhs <= 256;
+// avg_deg: the level's off-diagonals per row, which sizes the workgroup).
+hipError_t launch_wide_long(int32_t pb, int32_t pe, int32_t nrhs, int32_t avg_deg, const int32_t *srp,
+                            const int32_t *sci, const double *sva, const double *sdg, const double *bp, double *xp,
+                            int *err, hipStream_t s, RowsIO rio = RowsIO{});
 hipError_t launch_wide_run(int grid, int threads, int32_t l0, int32_t l1, const int32_t *level_ptr, int32_t nrhs,
                            const int32_t *srp, const int32_t *sci, const double *sva, const double *sdg,
                            const int4 *ell_c, const double2 *ell_v, const double *bp, double *xp, unsigned *bar,

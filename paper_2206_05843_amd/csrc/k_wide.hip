@@ -133,6 +133,66 @@ __global__ void k_wide_level_group(int32_t pb, int32_t pe, const int32_t *__rest
   if (bits) atomicOr(err, bits);
 }
 
+// One wide level whose rows have many dependencies, with several right-hand
+// sides: one workgroup per row. Its threads form G = WG / nrhs groups of nrhs
+// lanes (lane c takes column c, so a group's loads of one dependency's x are
+// contiguous); group g sums the row's products g, g + G, g + 2G, ... for its
+// column, four requested at a time, and the G partial sums are added in group
+// order, so the result does not depend on timing (it is not the row's column
+// order, so it can differ from the other executors in the last bits).
+template <int WG>
+__global__ __launch_bounds__(WG) void k_wide_long(int32_t pb, int32_t nrhs, const int32_t *__restrict__ srp,
+                                                  const int32_t *__restrict__ sci, const double *__restrict__ sva,
+                                                  const double *__restrict__ sdg, const double *__restrict__ bp,
+                                                  double *xp, int *err, RowsIO rio) {
+  __shared__ double part[WG];
+  const int32_t nr = nrhs;
+  const int32_t G = WG / nr;  // the host keeps nrhs <= WG
+  const int32_t t = (int32_t)threadIdx.x, g = t / nr, c = t - g * nr;
+  const int32_t pos = pb + (int32_t)blockIdx.x;
+  const int32_t qb = srp[pos], qe = srp[pos + 1];
+  const int32_t *cols = rio.x ? rio.sci_r : sci;  // by rows: columns as caller rows
+  const double *xs = rio.x ? rio.x : xp;
+  const int32_t row = rio.b ? rio.perm[pos] : 0;
+  double bv = 0.0;
+  if (g == 0) {
+    if (rio.b && !(rio.tflag && rio.tflag[pos]))
+      bv = rio.b[(int64_t)row * nr + c];
+    else
+      bv = bp[(int64_t)pos * nr + c];
+  }
+  double acc = 0.0;
+  if (g < G) {
+    for (int32_t q0 = qb + g; q0 < qe; q0 += 4 * G) {
+      int32_t k[4];
+      double w[4], xv[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int32_t q = q0 + d * G;
+        k[d] = q < qe ? cols[q] : -1;
+        w[d] = q < qe ? sva[q] : 0.0;
+      }
+#pragma unroll
+      for (int d = 0; d < 4; ++d) xv[d] = k[d] >= 0 ? xs[(int64_t)k[d] * nr + c] : 0.0;
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (k[d] >= 0) acc += w[d] * xv[d];
+    }
+  }
+  part[t] = acc;
+  __syncthreads();
+  if (g == 0) {
+    double sum = part[c];
+    for (int32_t gg = 1; gg < G; ++gg) sum += part[gg * nr + c];
+    const double x = (bv - sum) / sdg[pos];
+    if (!isfinite(x)) atomicOr(err, EB_NONFINITE);
+    if (rio.x)
+      rio.x[(int64_t)row * nr + c] = x;
+    else
+      xp[(int64_t)pos * nr + c] = x;
+  }
+}
+
 // What one item (row, right-hand side) of a wide level needs apart from the
 // x values it reads: position, column, CSR range, the fixed-width copy of its
 // first four dependencies, its b (or b'), the diagonal and the caller's row.
@@ -320,6 +380,28 @@ hipError_t launch_wide_level(int threads, int lanes_per_row, int32_t pb, int32_t
   else
     hipLaunchKernelGGL((k_wide_level<false>), dim3(g), dim3(threads), 0, s, pb, pe, nrhs, srp, sci, sva, sdg, ell_c,
                        ell_v, bp, xp, err, rio);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_long(int32_t pb, int32_t pe, int32_t nrhs, int32_t avg_deg, const int32_t *srp,
+                            const int32_t *sci, const double *sva, const double *sdg, const double *bp, double *xp,
+                            int *err, hipStream_t s, RowsIO rio) {
+  if (pe <= pb) return hipSuccess;
+  if (nrhs < 2 || nrhs > 256) return hipErrorInvalidValue;
+  // enough groups that each sums about four products: one round of loads
+  const int32_t want = (avg_deg + 3) / 4;
+  int wg = 64;
+  while (wg < 1024 && (wg < nrhs || wg / nrhs < want)) wg *= 2;
+#define LONG(W) \
+  hipLaunchKernelGGL((k_wide_long<W>), dim3(pe - pb), dim3(W), 0, s, pb, nrhs, srp, sci, sva, sdg, bp, xp, err, rio)
+  switch (wg) {
+    case 64: LONG(64); break;
+    case 128: LONG(128); break;
+    case 256: LONG(256); break;
+    case 512: LONG(512); break;
+    default: LONG(1024); break;
+  }
+#undef LONG
   return hipGetLastError();
 }
 

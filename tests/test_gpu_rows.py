@@ -202,3 +202,28 @@ def test_thin_cols(mats, name, tc):
         assert oracle.relerr(x_cols.cpu().numpy(), x_ref) <= TOL
         if 16 % tc:
             assert torch.equal(x_cols, ref)
+
+
+@pytest.mark.parametrize("nrhs", [2, 3, 32])
+@pytest.mark.parametrize("sched", [dict(mode=1), dict(mode=1, wide_grid=4096), dict(mode=0, thin_rows=8, thin_cols=1),
+                                   dict(mode=4, thin_rows=0, wide_threads=256)])
+def test_long_rows(sched, nrhs):
+    """Wide levels whose rows average at least 16 off-diagonals, with several
+    right-hand sides, run with a workgroup per row: against the oracle, both
+    layouts bit for bit, plain and rewritten."""
+    m = gen.window_random(3000, 11, 96, 48)
+    assert (m.nnz - m.n) / m.n >= 16
+    h = sp.Handle()
+    h.analyze(*dev(m))
+    h.rewrite(sp.THIN_ROWS, 32, 4.0)
+    b_cols = gen.rhs(m, nrhs)
+    bc = torch.from_numpy(b_cols).cuda()
+    x_ref = oracle.solve(m, b_cols)
+    for which in (sp.ORIGINAL, sp.REWRITTEN):
+        print(f"long rows: sched={sched} nrhs={nrhs} which={which}", flush=True)
+        h.set_schedule(which, **sched)
+        x_cols = h.solve(bc, which)
+        x_rows = h.solve_rows(bc.t().contiguous(), which)
+        h.check()
+        assert torch.equal(x_rows.t(), x_cols)
+        assert oracle.relerr(x_cols.cpu().numpy(), x_ref) <= TOL

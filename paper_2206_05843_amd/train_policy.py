@@ -35,7 +35,8 @@ pair that rewrites less).
 Evaluation. On held-out seeds (2000..), plain, naive, the constant rule "(B, C)
 on every thin level" and learned are autotuned and timed; the rewritten
 solutions are checked against the plain solution (relative error <= 1e-10) and
-the plain one by its residual.
+the plain one by its residual. --evaluate CKPT runs only this, for a saved
+checkpoint.
 """
 from __future__ import annotations
 
@@ -287,6 +288,23 @@ def evaluate(policy: Policy, seeds, action, check=True):
     return out, g
 
 
+def evaluate_checkpoint(path, heldout, out):
+    """The held-out comparison of a saved policy (its tiers and the action
+    recorded with it) on seeds 2000 .. 2000 + heldout - 1, written to
+    out/policy_eval.json."""
+    pol = Policy.load(path)
+    act = pol.meta.get("action", {})
+    action = (int(act.get("budget", NAIVE[0])), float(act.get("fill_cap", NAIVE[1])))
+    res, g = evaluate(pol, list(range(2000, 2000 + heldout)), action)
+    summary = {"heldout_seeds": [2000, 2000 + heldout - 1], "tiers": [list(t) for t in pol.tiers],
+               "geomean_learned_vs_naive": g["naive"], "geomean_learned_vs_plain": g["plain"],
+               "geomean_learned_vs_constant": g["constant"], "per_matrix": res}
+    with open(os.path.join(out, "policy_eval.json"), "w") as f:
+        json.dump(summary, f, indent=1)
+    log(f"[eval] geomean speedup learned vs naive {g['naive']:.4f}, vs plain {g['plain']:.4f}, "
+        f"vs constant {g['constant']:.4f}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
@@ -296,8 +314,13 @@ def main():
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--calib", type=int, default=10, help="validation matrices for the action and tiers (1900..)")
     ap.add_argument("--action", default="", help="B,C to skip the action search")
+    ap.add_argument("--evaluate", default="", metavar="CKPT",
+                    help="only measure the checkpoint CKPT (.npz with its .json) on the held-out seeds")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
+    if args.evaluate:
+        evaluate_checkpoint(args.evaluate, args.heldout, args.out)
+        return
     calib_seeds = list(range(1900, 1900 + max(args.calib, 1)))
     if args.action:
         bb, cc = args.action.split(",")
